@@ -1,0 +1,229 @@
+"""Pins of the oracle's Q1 discretisation (CPU only).
+
+Each test checks the oracle against something other than itself: Gauss
+quadrature of the trilinear shape functions, closed-form solutions,
+invariants of the Neumann operator, and finite differences.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import q1
+
+
+def _gauss_element(hx, hy, hz, what):
+    """Brute-force element matrices by 2-point Gauss quadrature of Q1 shape functions."""
+    g = np.array([-1.0, 1.0]) / np.sqrt(3.0)
+    pts = (g + 1.0) / 2.0  # on [0, 1]
+    K = np.zeros((8, 8))
+    M = np.zeros((8, 8))
+    for xi in pts:
+        for eta in pts:
+            for zeta in pts:
+                w = 0.125 * hx * hy * hz  # each weight 1/2 per axis on [0,1], times volume
+                N = np.zeros(8)
+                dN = np.zeros((8, 3))
+                for a in range(8):
+                    ax, ay, az = a & 1, (a >> 1) & 1, (a >> 2) & 1
+                    fx = xi if ax else 1 - xi
+                    fy = eta if ay else 1 - eta
+                    fz = zeta if az else 1 - zeta
+                    sx = 1.0 if ax else -1.0
+                    sy = 1.0 if ay else -1.0
+                    sz = 1.0 if az else -1.0
+                    N[a] = fx * fy * fz
+                    dN[a] = [sx * fy * fz / hx, fx * sy * fz / hy, fx * fy * sz / hz]
+                K += w * dN @ dN.T
+                M += w * np.outer(N, N)
+    return K if what == "K" else M
+
+
+@pytest.mark.parametrize("h", [(1.0, 1.0, 1.0), (0.25, 0.5, 0.125), (0.1, 0.3, 0.7)])
+def test_element_matrices_match_quadrature(h):
+    assert np.allclose(q1.element_stiffness(*h), _gauss_element(*h, "K"), rtol=0, atol=1e-14 * max(h) / min(h) ** 2)
+    assert np.allclose(q1.element_mass(*h), _gauss_element(*h, "M"), rtol=0, atol=1e-15)
+
+
+def test_unit_cube_element_closed_form():
+    K = q1.element_stiffness(1.0, 1.0, 1.0)
+    for a in range(8):
+        for b in range(8):
+            ndiff = bin(a ^ b).count("1")
+            want = {0: 1.0 / 3.0, 1: 0.0, 2: -1.0 / 12.0, 3: -1.0 / 12.0}[ndiff]
+            assert abs(K[a, b] - want) <= 1e-16
+    assert np.allclose(K.sum(axis=1), 0.0, atol=1e-15)
+    assert abs(np.linalg.eigvalsh(K).max() - 0.5) < 1e-14
+    # K0 = h * Khat for cubes of side h
+    assert np.allclose(q1.element_stiffness(0.25, 0.25, 0.25), 0.25 * K, atol=1e-16)
+
+
+def test_conductivity_law():
+    rho = np.array([0.0, 0.5, 1.0, 1e-3])
+    k = q1.conductivity(rho, 1e-6, 1.0, 3)
+    assert np.allclose(k, 1e-6 + rho ** 3 * (1.0 - 1e-6), rtol=1e-15)
+    assert k[0] == 1e-6 and k[2] == 1.0
+
+
+def test_neumann_operator_invariants():
+    rng = np.random.default_rng(3)
+    g = q1.Grid(5, 4, 6)
+    k = 10.0 ** rng.uniform(-6, 0, g.nelem)
+    A = q1.assemble(g, k)
+    assert np.abs(A @ np.ones(g.nnodes)).max() <= 1e-14 * np.abs(A).max() * 27
+    x, y = rng.standard_normal((2, g.nnodes))
+    assert abs(x @ (A @ y) - y @ (A @ x)) <= 1e-13 * np.abs(x @ (A @ y)) + 1e-300
+    assert x @ (A @ x) >= 0
+    # 21-point pattern for cubes: axis neighbours have coefficient exactly 0
+    g2 = q1.Grid(4)
+    A2 = q1.assemble(g2, np.ones(g2.nelem)).tocsr()
+    n = g2.node_index(2, 2, 2)
+    row = A2.getrow(n)
+    nz = {int(c) for c, v in zip(row.indices, row.data) if v != 0.0}
+    assert len(nz) == 21
+    for d in (1, g2.nnx, g2.nnx * g2.nny):
+        assert A2[n, n + d] == 0.0 and A2[n, n - d] == 0.0
+
+
+def _layered_exact(zn, kz):
+    """T(z) = int_0^z (1 - s) / k(s) ds for piecewise-constant k per layer."""
+    T = np.zeros(len(zn))
+    for i in range(1, len(zn)):
+        a, b = zn[i - 1], zn[i]
+        T[i] = T[i - 1] + ((b - a) - 0.5 * (b * b - a * a)) / kz[i - 1]
+    return T
+
+
+@pytest.mark.parametrize("contrast", [1.0, 1e3, 1e6])
+def test_layered_exact_solution(contrast):
+    n = 6
+    g = q1.Grid(n)
+    rng = np.random.default_rng(7)
+    kz = np.where(rng.uniform(size=n) < 0.5, 1.0, 1.0 / contrast)
+    k = np.repeat(kz, n * n)  # element layers along z
+    A = q1.assemble(g, k)
+    mask = np.zeros((n + 1,) * 3, dtype=np.uint8)
+    mask[0] = 1
+    f = q1.element_load(g, 1.0)
+    T = q1.solve_direct(A, f, mask.ravel())
+    zn = np.arange(n + 1) / n
+    want = _layered_exact(zn, kz)
+    T3 = T.reshape(n + 1, n + 1, n + 1)
+    tol = 1e-12 if contrast == 1.0 else 1e-15 * contrast * 100
+    for kk in range(n + 1):
+        assert np.abs(T3[kk] - want[kk]).max() <= tol * max(1.0, abs(want).max())
+
+
+def test_manufactured_solution_second_order():
+    errs = []
+    for n in (4, 8, 16):
+        g = q1.Grid(n)
+        ix, jy, kz = g.node_coords()
+        x, y, z = ix / n, jy / n, kz / n
+        u = np.sin(np.pi * x) * np.sin(np.pi * y) * np.sin(np.pi * z)
+        src = 3 * np.pi ** 2 * u
+        f = q1.assemble_mass(g) @ src
+        A = q1.assemble(g, np.ones(g.nelem))
+        mask = ((ix == 0) | (ix == n) | (jy == 0) | (jy == n) | (kz == 0) | (kz == n)).astype(np.uint8)
+        T = q1.solve_direct(A, f, mask)
+        errs.append(np.abs(T - u).max())
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.7 <= r2 <= 4.3, errs
+    assert r1 > 3.0
+
+
+def test_dirichlet_value_shift():
+    """Fixed temperature T_D shifts the solution by T_D (A 1 = 0, adiabatic elsewhere)."""
+    n = 6
+    g = q1.Grid(n)
+    rho = synth.uniform_noise_rho(n, 1).ravel()
+    k = q1.conductivity(rho, 1e-3, 1.0, 3)
+    A = q1.assemble(g, k)
+    mask = synth.dirichlet_patch_mask(n, n, n).ravel()
+    f = q1.element_load(g, 1.0)
+    T0 = q1.solve_direct(A, f, mask)
+    T100 = q1.solve_direct(A, f, mask, np.full(g.nnodes, 100.0))
+    assert np.abs(T100 - T0 - 100.0).max() < 1e-10
+
+
+def test_load_and_energy_identity():
+    n = 8
+    g = q1.Grid(n)
+    f = q1.element_load(g, 1.0)
+    assert abs(f.sum() - 1.0) < 1e-14  # integral of the unit source over the unit cube
+    rho = synth.uniform_noise_rho(n, 0).ravel()
+    k = q1.conductivity(rho, 1e-3, 1.0, 3)
+    A = q1.assemble(g, k)
+    mask = synth.dirichlet_patch_mask(n, n, n).ravel()
+    T = q1.solve_direct(A, f, mask)
+    c = q1.compliance(f, T)
+    assert abs(c - T @ (A @ T)) <= 1e-12 * c
+    assert q1.relative_residual(A, T, f, mask) < 1e-12
+
+
+def _compliance_of(g, rho, mask, kmin, kmax, p):
+    k = q1.conductivity(rho, kmin, kmax, p)
+    A = q1.assemble(g, k)
+    f = q1.element_load(g, 1.0)
+    T = q1.solve_direct(A, f, mask)
+    return q1.compliance(f, T), T, A, f
+
+
+def test_sensitivity_identities_and_fd():
+    n = 6
+    g = q1.Grid(n)
+    kmin, kmax, p = 1e-3, 1.0, 3
+    rho = synth.uniform_noise_rho(n, 2).ravel()
+    mask = synth.dirichlet_patch_mask(n, n, n).ravel()
+    c, T, A, f = _compliance_of(g, rho, mask, kmin, kmax, p)
+    lam = q1.adjoint_solve(A, f, mask)
+    assert np.abs(lam - T).max() <= 1e-12 * np.abs(T).max()   # compliance is self-adjoint
+    dc = q1.sensitivity(g, rho, T, T, kmin, kmax, p)
+    assert (dc <= 0).all()
+    # Euler identity: sum_e rho_e dc_e = -p (c - k_min T^T A0 T)
+    A0 = q1.assemble(g, np.ones(g.nelem))
+    lhs = rho @ dc
+    rhs = -p * (c - kmin * T @ (A0 @ T))
+    assert abs(lhs - rhs) <= 1e-10 * abs(rhs)
+    # central finite difference along a random direction
+    d = np.random.default_rng(5).standard_normal(g.nelem)
+    eps = 1e-6
+    cp = _compliance_of(g, rho + eps * d, mask, kmin, kmax, p)[0]
+    cm = _compliance_of(g, rho - eps * d, mask, kmin, kmax, p)[0]
+    fd = (cp - cm) / (2 * eps)
+    assert abs(fd - dc @ d) <= 1e-6 * abs(dc @ d)
+
+
+def test_general_adjoint_fd():
+    """A non-self-adjoint objective L = w^T T: dL/drho from the adjoint matches FD."""
+    n = 5
+    g = q1.Grid(n)
+    kmin, kmax, p = 1e-2, 1.0, 3
+    rho = synth.uniform_noise_rho(n, 4).ravel()
+    mask = synth.dirichlet_patch_mask(n, n, n).ravel()
+    w = np.random.default_rng(9).standard_normal(g.nnodes)
+
+    def L(r):
+        _, T, A, f = _compliance_of(g, r, mask, kmin, kmax, p)
+        return w @ T, T, A
+
+    L0, T, A = L(rho)
+    lam = q1.adjoint_solve(A, w, mask)
+    dL = q1.sensitivity(g, rho, T, lam, kmin, kmax, p)
+    d = np.random.default_rng(6).standard_normal(g.nelem)
+    eps = 1e-6
+    fd = (L(rho + eps * d)[0] - L(rho - eps * d)[0]) / (2 * eps)
+    assert abs(fd - dL @ d) <= 1e-6 * abs(dL @ d)
+
+
+def test_elementwise_apply_matches_assembly():
+    rng = np.random.default_rng(11)
+    g = q1.Grid(7, 5, 9, 1.0, 0.5, 2.0)
+    k = 10.0 ** rng.uniform(-4, 0, g.nelem)
+    x = rng.standard_normal(g.nnodes)
+    mask = (rng.uniform(size=g.nnodes) < 0.1).astype(np.uint8)
+    A = q1.assemble(g, k)
+    y1 = q1.apply_elementwise(g, k, x, zslab=3)
+    assert np.abs(y1 - A @ x).max() <= 1e-13 * np.abs(A @ x).max()
+    y2 = q1.apply_elementwise(g, k, x, mask=mask, zslab=4)
+    Am = q1.masked_operator(A, mask)
+    assert np.abs(y2 - Am @ x).max() <= 1e-13 * np.abs(Am @ x).max()

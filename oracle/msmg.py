@@ -34,7 +34,9 @@ Readings taken where the paper is silent or written for cell-centred unknowns
     [lo, hi]; level 1 one forward (pre) / backward (post) sweep of block
     Gauss-Seidel over the 8 parity colours of the coarse cells;
   * CG uses the Polak-Ribiere (flexible) beta and stops on the true relative
-    residual ||b - A x|| / ||b||.
+    residual ||b - A x|| / ||b||;
+  * fine-level products with A are evaluated in difference form (same matrix,
+    rounding that does not grow with the size of T; see q1.DiffOperator).
 """
 from __future__ import annotations
 
@@ -104,8 +106,9 @@ class Hierarchy:
         self.mask = np.asarray(mask).ravel().astype(bool)
         self.k = q1.conductivity(np.asarray(rho).ravel(), kmin, kmax, p)
         A = q1.assemble(grid, self.k)
-        self.A = q1.masked_operator(A, self.mask)
-        self.diag = self.A.diagonal().copy()
+        self.A_csr = q1.masked_operator(A, self.mask)      # Galerkin products
+        self.A = q1.DiffOperator(A, self.mask)             # fine-level products
+        self.diag = self.A_csr.diagonal().copy()
         self._partition()
         self._level1(keep_local)
         self._level2()
@@ -189,6 +192,7 @@ class Hierarchy:
         rows, cols, vals = [], [], []
         self.cell_rows = []      # coarse dof ids of each cell
         self.cell_evals = []     # local eigenvalues of each cell
+        self.cell_gaps = []      # lambda_L - lambda_{L-1} (inf when the space is full)
         self.cell_basis = []     # (node ids, Phi) per cell when keep_local
         self.cell_mass = []
         r = 0
@@ -203,7 +207,10 @@ class Hierarchy:
                     self.cell_basis.append((nodes, np.zeros((len(nodes), 0))))
                     self.cell_mass.append(m)
                 continue
-            lam, phi = sla.eigh(K, np.diag(m), subset_by_index=[0, nl - 1], driver="gvx")
+            top = min(nl, len(nodes) - 1)  # one eigenvalue past the cut (gap diagnostic)
+            lam, phi = sla.eigh(K, np.diag(m), subset_by_index=[0, top], driver="gvx")
+            self.cell_gaps.append(lam[nl] - lam[nl - 1] if top == nl else np.inf)
+            lam, phi = lam[:nl], phi[:, :nl]
             for j in range(nl):
                 phi[:, j] = _fix_sign(phi[:, j], m)
             self.cell_evals.append(lam)
@@ -222,7 +229,7 @@ class Hierarchy:
 
     def level1_operators(self):
         """A_c = R_c A R_c^T, its diagonal-block inverses and the colour classes."""
-        self.Ac = sp.csr_matrix(self.Rc @ self.A @ self.Rc.T)
+        self.Ac = sp.csr_matrix(self.Rc @ self.A_csr @ self.Rc.T)
         # block-diagonal inverse and colour classes for block Gauss-Seidel
         self.colour_rows = [[] for _ in range(8)]
         inv_blocks = []
@@ -273,6 +280,7 @@ class Hierarchy:
             cc_members.setdefault(key, []).append(ci)
         rows, cols, vals = [], [], []
         self.cc_rows, self.cc_evals, self.cc_dofs = [], [], []
+        self.cc_gaps, self.cc_norms = [], []
         r = 0
         for jz in range(ncz):
             for jy in range(ncy):
@@ -287,7 +295,11 @@ class Hierarchy:
                         continue
                     G = KR[dofs][:, dofs].toarray()
                     G = 0.5 * (G + G.T)
-                    lam, v = sla.eigh(G, subset_by_index=[0, nl - 1], driver="evx")
+                    top = min(nl, len(dofs) - 1)
+                    lam, v = sla.eigh(G, subset_by_index=[0, top], driver="evx")
+                    self.cc_gaps.append(lam[nl] - lam[nl - 1] if top == nl else np.inf)
+                    self.cc_norms.append(float(np.abs(G).sum(axis=1).max()))
+                    lam, v = lam[:nl], v[:, :nl]
                     one = np.ones(len(dofs))
                     for j in range(nl):
                         v[:, j] = _fix_sign(v[:, j], one)
@@ -372,11 +384,12 @@ class Hierarchy:
 
 @dataclasses.dataclass
 class PCGResult:
-    x: np.ndarray
+    x: np.ndarray           # iterate rounded to binary64
     iterations: int
     rel_res: float          # true relative residual at exit
     status: str             # "converged" | "maxit" | "breakdown"
     history: list
+    x_lo: np.ndarray = None  # x_ext - x (the part binary64 cannot hold)
 
 
 def pcg(A, b, precond, x0=None, rtol=1e-8, maxit=1000, mask=None):
@@ -385,17 +398,30 @@ def pcg(A, b, precond, x0=None, rtol=1e-8, maxit=1000, mask=None):
     Stops when the recursive relative residual reaches ``rtol`` and the true
     residual ||b - A x|| / ||b|| confirms it; if it does not, the residual is
     replaced by the true one and the search direction restarts from z.
-    Vectors live on all nodes; entries on fixed nodes stay zero.
+    Vectors live on all nodes; entries on fixed nodes stay zero.  The iterate
+    x is accumulated in extended precision (np.longdouble) and the true
+    residual is formed from its neighbour differences: at high conductivity
+    contrast T is ~1/k_min on islands and a binary64 iterate alone cannot
+    reach relative residuals near 1e-8 (A must be a DiffOperator).
     """
+    ext = np.longdouble
     b = np.asarray(b, dtype=np.float64)
     fr = np.ones(len(b), dtype=bool) if mask is None else ~np.asarray(mask).ravel().astype(bool)
     bb = np.where(fr, b, 0.0)
     nb = np.linalg.norm(bb)
-    x = np.zeros_like(bb) if x0 is None else np.where(fr, np.asarray(x0, dtype=np.float64), 0.0)
-    r = bb - np.where(fr, A @ x, 0.0)
+
+    def true_res(xe):
+        return bb - A.free_product(xe)
+
+    def out(xe, it, rel, st, hist):
+        x64 = xe.astype(np.float64)
+        return PCGResult(x64, it, rel, st, hist, (xe - x64).astype(np.float64))
+
+    x = np.zeros(len(b), dtype=ext) if x0 is None else np.where(fr, np.asarray(x0, dtype=np.float64), 0.0).astype(ext)
+    r = true_res(x)
     hist = [np.linalg.norm(r) / nb]
     if hist[0] <= rtol:
-        return PCGResult(x, 0, hist[0], "converged", hist)
+        return out(x, 0, hist[0], "converged", hist)
     z = precond(r)
     p = z.copy()
     rz = float(r @ z)
@@ -403,19 +429,18 @@ def pcg(A, b, precond, x0=None, rtol=1e-8, maxit=1000, mask=None):
         q = np.where(fr, A @ p, 0.0)
         pq = float(p @ q)
         if not (pq > 0.0) or not (rz > 0.0):
-            return PCGResult(x, it - 1, float(np.linalg.norm(bb - np.where(fr, A @ x, 0.0)) / nb),
-                             "breakdown", hist)
+            return out(x, it - 1, float(np.linalg.norm(true_res(x)) / nb), "breakdown", hist)
         alpha = rz / pq
-        x = x + alpha * p
+        x = x + ext(alpha) * p.astype(ext)
         r_new = r - alpha * q
         rel = np.linalg.norm(r_new) / nb
         hist.append(rel)
         restart = False
         if rel <= rtol:
-            true_r = bb - np.where(fr, A @ x, 0.0)
+            true_r = true_res(x)
             true_rel = np.linalg.norm(true_r) / nb
             if true_rel <= rtol:
-                return PCGResult(x, it, float(true_rel), "converged", hist)
+                return out(x, it, float(true_rel), "converged", hist)
             r_new = true_r
             restart = True
         z = precond(r_new)
@@ -426,8 +451,7 @@ def pcg(A, b, precond, x0=None, rtol=1e-8, maxit=1000, mask=None):
         rz = float(z @ r_new)
         p = z + beta * p
         r = r_new
-    true_rel = np.linalg.norm(bb - np.where(fr, A @ x, 0.0)) / nb
-    return PCGResult(x, maxit, float(true_rel), "maxit", hist)
+    return out(x, maxit, float(np.linalg.norm(true_res(x)) / nb), "maxit", hist)
 
 
 def solve(grid, rho, f, mask, kmin, kmax, p, opts=None, rtol=1e-8, maxit=1000, td=None,
@@ -440,4 +464,5 @@ def solve(grid, rho, f, mask, kmin, kmax, p, opts=None, rtol=1e-8, maxit=1000, t
     res = pcg(h.A, bfree, h.precondition, x0=x0, rtol=rtol, maxit=maxit, mask=h.mask)
     T = res.x.copy()
     T[h.mask] = b[h.mask]
+    res.x_lo[h.mask] = 0.0
     return T, res, h

@@ -123,7 +123,7 @@ def test_cc_level_invariants():
 def test_galerkin_identity():
     g, h = _setup(8, 2, 2, Lc=3, Lcc=5)
     P = (h.Rcc @ h.Rc).toarray()
-    A = h.A.toarray()
+    A = h.A_csr.toarray()
     assert np.allclose(h.Acc, P @ A @ P.T, rtol=0, atol=1e-12 * np.abs(h.Acc).max())
     assert np.all(np.linalg.eigvalsh(h.Acc) > 0)
 
@@ -154,7 +154,7 @@ def _chebyshev_matrix(A, D, o):
 def test_chebyshev_error_polynomial(deg):
     g, h = _setup(6, 2, 2, deg=deg)
     F = _free(h)
-    A = h.A.toarray()[np.ix_(F, F)]
+    A = h.A_csr.toarray()[np.ix_(F, F)]
     D = h.diag[F]
     lam, V = sla.eigh(A, np.diag(D))
     o = h.o
@@ -175,7 +175,7 @@ def test_smoother_interval_upper_bound():
     rho = np.where(rng.uniform(size=n ** 3) < 0.4, 1.0, 1e-3)
     g, h = _setup(n, 2, 2, rho=rho, kmin=1e-6)
     F = _free(h)
-    lam = sla.eigvalsh(h.A.toarray()[np.ix_(F, F)], np.diag(h.diag[F]))
+    lam = sla.eigvalsh(h.A_csr.toarray()[np.ix_(F, F)], np.diag(h.diag[F]))
     assert lam.max() <= 1.5 * (1 + 1e-12)
     assert lam.max() > 1.2
 
@@ -187,7 +187,7 @@ def test_three_grid_error_propagation_formula():
     g, h = _setup(6, 2, 2, Lc=4, Lcc=17)
     F = _free(h)
     nf = len(F)
-    A = h.A.toarray()[np.ix_(F, F)]
+    A = h.A_csr.toarray()[np.ix_(F, F)]
     Sinv = _chebyshev_matrix(A, h.diag[F], h.o)
     Rc = h.Rc.toarray()[:, F]
     Ac = h.Ac.toarray()
@@ -273,3 +273,18 @@ def test_pcg_high_contrast_and_warm_start():
     # deterministic
     T3, res3, _ = msmg.solve(g, rho, f, mask, 1e-6, 1.0, 3, hier=h, rtol=1e-8)
     assert res3.iterations == res.iterations and np.array_equal(T3, T)
+
+
+def test_extended_iterate_beats_binary64_floor():
+    """At contrast 1e6 a binary64 T cannot reach 1e-8; the extended iterate can."""
+    n = 16
+    g = q1.Grid(n)
+    rho = synth.grf_rho(n, 4, seed=2).ravel()
+    mask = synth.dirichlet_patch_mask(n, n, n).ravel()
+    f = q1.element_load(g, 1.0)
+    A = q1.assemble(g, q1.conductivity(rho, 1e-6, 1.0, 3))
+    Td = q1.solve_direct(A, f, mask)
+    assert q1.relative_residual_diff(A, Td, f, mask) > 1e-9      # binary64 floor of this field
+    T, res, h = msmg.solve(g, rho, f, mask, 1e-6, 1.0, 3, msmg.Options(H=4, sd=2), rtol=1e-10, maxit=300)
+    assert res.status == "converged"
+    assert q1.relative_residual_diff(A, T, f, mask, T_lo=res.x_lo) <= 1e-10 * (1 + 1e-3)

@@ -227,3 +227,34 @@ def test_elementwise_apply_matches_assembly():
     y2 = q1.apply_elementwise(g, k, x, mask=mask, zslab=4)
     Am = q1.masked_operator(A, mask)
     assert np.abs(y2 - Am @ x).max() <= 1e-13 * np.abs(Am @ x).max()
+
+
+def test_difference_form_operator():
+    """DiffOperator is the masked operator; its rounding does not grow with |x|."""
+    rng = np.random.default_rng(12)
+    g = q1.Grid(6, 5, 7)
+    k = 10.0 ** rng.uniform(-6, 0, g.nelem)
+    A = q1.assemble(g, k)
+    mask = (rng.uniform(size=g.nnodes) < 0.1).astype(np.uint8)
+    D = q1.DiffOperator(A, mask)
+    Am = q1.masked_operator(A, mask)
+    x = rng.standard_normal(g.nnodes)
+    assert np.abs(D @ x - Am @ x).max() <= 1e-13 * np.abs(Am @ x).max()
+    # a large shift c on the free nodes leaves rows away from fixed nodes
+    # unchanged; x on a 2^-20 grid and c = 2^26 keep x + c exact in binary64
+    x = np.round(x * 2.0 ** 20) / 2.0 ** 20
+    c = 2.0 ** 26
+    fr = ~mask.astype(bool)
+    xs = np.where(fr, x + c, 0.0)
+    inner = fr & (np.abs(A) @ mask.astype(float) == 0)
+    ref = (D @ x)[inner]
+    err_diff = np.abs((D @ xs)[inner] - ref).max()
+    err_plain = np.abs((Am @ xs)[inner] - ref).max()
+    assert err_diff <= 1e-14 * np.abs(ref).max()
+    assert err_plain > 1e3 * max(err_diff, 1e-300)
+    # residual helpers agree on well-scaled data, with and without a low part
+    f = q1.element_load(g, 1.0)
+    T = q1.solve_direct(A, f, mask)
+    assert abs(q1.relative_residual_diff(A, T, f, mask) - q1.relative_residual(A, T, f, mask)) <= 1e-10
+    lo = 1e-20 * rng.standard_normal(g.nnodes)
+    assert abs(q1.relative_residual_diff(A, T, f, mask, T_lo=lo) - q1.relative_residual_diff(A, T, f, mask)) <= 1e-10

@@ -1,0 +1,194 @@
+/*
+ * msmg.h -- C ABI of the MI355X multiscale-multigrid PCG solver for SIMP
+ * steady heat conduction on structured Q1 hexahedral meshes.
+ *
+ * Problem (paper section 2): -div(k(rho) grad T) = f on the box
+ * [0,lx] x [0,ly] x [0,lz] cut into nx * ny * nz trilinear hexahedra, with
+ * k = k_min + rho^p (k_max - k_min) per element (section 2.1, eq. material),
+ * fixed temperatures on a nodal mask and adiabatic boundaries elsewhere.  The
+ * discrete system A T = f (section 2.2, eq. new linear system; here nodal Q1
+ * instead of the paper's two-point flux volumes) is solved by preconditioned
+ * CG whose preconditioner is the three-grid cycle of Algorithm 1 with coarse
+ * spaces from the local spectral problems eq. (spepb) and eq. (spectral cc)
+ * (section 3).  Sensitivities follow the adjoint of section 2.3.
+ *
+ * Conventions
+ *   - Node n = (k*(ny+1) + j)*(nx+1) + i, element e = (k*ny + j)*nx + i
+ *     (x fastest).  Nodal arrays hold (nx+1)(ny+1)(nz+1) entries, element
+ *     arrays nx*ny*nz.
+ *   - Every array argument is a HIP device pointer unless stated otherwise.
+ *     The caller owns it; the library never keeps it past the call except
+ *     where stated.  The library owns the handle and all its device memory.
+ *   - Work is enqueued on the given stream; one handle is used from one
+ *     stream at a time.  msmg_solve blocks until the solve ends.
+ *   - Return codes: 0 success; > 0 solve ended without convergence (result
+ *     still written); < 0 error (nothing useful written), see msmg_last_error.
+ */
+#ifndef MSMG_H
+#define MSMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct msmg_handle msmg_handle;
+
+typedef enum { MSMG_F64 = 0, MSMG_F32 = 1, MSMG_BF16 = 2 } msmg_dtype;
+
+typedef enum { MSMG_PC_MULTIGRID = 0, MSMG_PC_SMOOTHER = 1 } msmg_pc_kind;
+
+enum {
+  MSMG_OK = 0,
+  MSMG_MAXIT = 1,       /* iteration limit reached                      */
+  MSMG_BREAKDOWN = 2,   /* p^T A p <= 0 or r^T z <= 0                    */
+  MSMG_NONFINITE = 3,   /* NaN / Inf in the iteration                    */
+  MSMG_EINVAL = -1,     /* invalid argument                               */
+  MSMG_ENOMEM = -2,     /* device allocation failed                       */
+  MSMG_EHIP = -3,       /* HIP runtime error                              */
+  MSMG_ESETUP = -4,     /* coarse-space construction failed               */
+  MSMG_ESINGULAR = -5,  /* no fixed-temperature node: A is singular       */
+  MSMG_ESTATE = -6      /* call order violated (e.g. solve before setup)  */
+};
+
+/* Solver options (section 4 of the paper fixes sd, L_c, L_cc as tunables;
+ * the smoother choice and precision are this library's). */
+typedef struct msmg_options {
+  int H;               /* coarse cell size in elements per axis (>= 2)          [8]    */
+  int sd;              /* coarse cells per coarse-coarse cell per axis (>= 1)   [8]    */
+  int Lc;              /* eigenvectors per coarse cell, 1..8 (eq. spepb)        [4]    */
+  int Lcc;             /* eigenvectors per coarse-coarse cell (eq. spectral cc) [17]   */
+  int cheb_degree;     /* level-0 Chebyshev-Jacobi steps, 1..16                 [2]    */
+  double cheb_lo;      /* smoothing interval on D^-1 A                          [0.15] */
+  double cheb_hi;      /*                                                        [1.5]  */
+  int vcycle_dtype;    /* MSMG_F64 or MSMG_F32 vectors inside the cycle         [F64]  */
+  int rho_v_dtype;     /* density copy read by the cycle: F64/F32/BF16          [F64]  */
+  int basis_dtype;     /* storage of R_c: F64/F32/BF16                          [F64]  */
+  int pc_kind;         /* MSMG_PC_MULTIGRID or MSMG_PC_SMOOTHER (level 0 only)  [MG]   */
+  int check_interval;  /* PCG iterations between host convergence polls        [8]    */
+  int eig_block;       /* level-1 subspace block size (0 = tuned)               [0]    */
+  int eig_degree;      /* level-1 filter degree (0 = tuned)                     [0]    */
+  int eig_maxit;       /* outer subspace iterations per cell                    [60]   */
+  double eig_tol;      /* residual tolerance relative to the spectral bound     [1e-12]*/
+  int cc_block;        /* coarse-coarse subspace block size (0 = Lcc + guard)   [0]    */
+  int cc_degree;       /* coarse-coarse filter degree                           [16]   */
+  int cc_maxit;        /* coarse-coarse outer iterations                        [60]   */
+  int autotune;        /* 1: tune the level-1 launch shape on first setup       [1]    */
+  const char* tune_cache; /* host path of the tuning cache file, or NULL       [NULL] */
+  int timing;          /* 1: time the operator apply and the preconditioner of  [0]
+                          every PCG iteration with HIP events on the solve stream */
+} msmg_options;
+
+/* Solve report. */
+typedef struct msmg_info {
+  int status;              /* return code of msmg_solve                          */
+  int iterations;          /* PCG iterations                                     */
+  int restarts;            /* residual replacements after a failed true check    */
+  double rel_res;          /* final true ||b - A T||_2 / ||b||_2 on free nodes   */
+  double solve_ms;         /* wall time of the solve, host side                  */
+  double setup_ms;         /* wall time of the last msmg_setup                   */
+  int n_c, n_cc;           /* coarse and coarse-coarse dimensions                */
+  int eig_unconverged;     /* level-1 cells that hit eig_maxit                   */
+  int cc_unconverged;      /* coarse-coarse cells that hit cc_maxit              */
+  int eig_ties;            /* level-1 cells whose cutoff gap is below 1e-8 bound */
+  int timed;               /* iterations timed (options.timing)                  */
+  double apply_ms;         /* mean duration of the PCG operator apply kernel     */
+  double precond_ms;       /* mean duration of one preconditioner application    */
+} msmg_info;
+
+/* Hierarchy sizes for a mesh and options; host only, no GPU needed. */
+typedef struct msmg_plan {
+  int ncx, ncy, ncz, ncells;   /* coarse cells                                */
+  int nccx, nccy, nccz, ncc;   /* coarse-coarse cells                         */
+  int n_c, n_cc;               /* padded coarse dimension, cc dimension       */
+  int max_cell_nodes;          /* largest owned-node box of a coarse cell     */
+  int max_cc_dofs;             /* largest coarse-coarse local dimension       */
+  long long nodes, elements;
+  long long device_bytes;      /* device memory the handle will hold          */
+} msmg_plan;
+
+/* Fill *opt with the defaults listed above. */
+void msmg_default_options(msmg_options* opt);
+
+/* Hierarchy plan for nx*ny*nz elements (host only).  Returns MSMG_EINVAL when
+ * the sizes or options cannot be used. */
+int msmg_query_plan(int nx, int ny, int nz, const msmg_options* opt, msmg_plan* out);
+
+/* Allocate a handle for an nx*ny*nz mesh of the box lx*ly*lz (opt NULL =
+ * defaults).  Allocates all device memory up front on the current device. */
+int msmg_create(msmg_handle** h, int nx, int ny, int nz, double lx, double ly, double lz,
+                const msmg_options* opt);
+
+/* Per-design set-up (paper flowchart: form the coefficient field, solve the
+ * spectral problems on every coarse and coarse-coarse element, build the
+ * preconditioner).  rho: element densities in [0,1] of dtype MSMG_F64 or
+ * MSMG_F32 (copied; this copy defines the operator).  k_min > 0,
+ * k_max >= k_min, p >= 1.  mask: nodal uint8, nonzero = fixed temperature
+ * (must contain at least one node).  fixed_values: nodal FP64 temperatures
+ * read on fixed nodes, or NULL for zero.  Call again whenever rho changes. */
+int msmg_setup(msmg_handle* h, const void* rho, msmg_dtype rho_dtype, double k_min, double k_max, int p,
+               const uint8_t* mask, const double* fixed_values, hipStream_t stream);
+
+/* Solve A T = f by PCG (Polak-Ribiere beta) with the configured preconditioner.
+ * f: nodal FP64 load (entries on fixed nodes are ignored).  T: nodal FP64 output;
+ * when use_x0 != 0 its free entries are the initial guess.  Stops when the true
+ * relative residual ||(f - A T)_F|| / ||b_F|| <= rtol (b = f minus the fixed-value
+ * lift), or after maxit iterations.  info may be NULL (host pointer).
+ * The iterate is kept in double-double precision: at high conductivity contrast
+ * T reaches ~1/k_min and a binary64 T alone cannot reach residuals near 1e-8.
+ * T_lo (nullable, nodal FP64 output): when given, T receives the high part and
+ * T_lo the low part of the iterate (T + T_lo); when NULL, T = round(T + T_lo). */
+int msmg_solve(msmg_handle* h, const double* f, double* T, double* T_lo, int use_x0, double rtol, int maxit,
+               msmg_info* info, hipStream_t stream);
+
+/* Element sensitivities dc/drho_e = -p rho_e^(p-1) (k_max - k_min) lambda_e^T K0 T_e
+ * (evaluated as -sum_{a<b} K0_ab (lambda_a - lambda_b)(T_a - T_b), exact for zero-row-sum K0)
+ * (section 2.3 with a design-independent load).  lambda: nodal adjoint with zero
+ * fixed entries, or NULL for the compliance case lambda = T (free entries of T;
+ * valid for zero fixed values).  dc: element FP64 output. */
+int msmg_sensitivity(msmg_handle* h, const double* T, const double* lambda, double* dc, hipStream_t stream);
+
+/* y = P A P x + (I - P) x with P the projection on free nodes (FP64, nodal). */
+int msmg_apply(msmg_handle* h, const double* x, double* y, hipStream_t stream);
+
+/* z = M^-1 r: one preconditioner application (Algorithm 1 for the multigrid
+ * kind).  Entries of r on fixed nodes are ignored; z is zero there. */
+int msmg_precondition(msmg_handle* h, const double* r, double* z, hipStream_t stream);
+
+/* Consistent nodal load of an element-wise constant source: f_n = sum_{e ni n} s_e V/8,
+ * with s_e = src[e], or s_e = src_const when src is NULL. */
+int msmg_element_load(msmg_handle* h, const double* src, double src_const, double* f, hipStream_t stream);
+
+/* Interpolation step between resolutions (section 3, interpolation technique):
+ * Tc on the (nx,ny,nz) mesh -> Tf on the (2nx,2ny,2nz) mesh, the coarse trilinear
+ * function evaluated at the fine nodes (no handle needed). */
+int msmg_prolong_nodal(int nx, int ny, int nz, const double* Tc, double* Tf, hipStream_t stream);
+
+/* Element injection (nx,ny,nz) -> (2nx,2ny,2nz) of an element field of dtype dt
+ * (each child takes its parent's value). */
+int msmg_prolong_element(int nx, int ny, int nz, const void* rc, void* rf, msmg_dtype dt, hipStream_t stream);
+
+/* Diagnostics of the last set-up, copied to host memory (blocking):
+ *   what = 0: level-1 eigenvalues, ncells*Lc doubles (padded entries 0)
+ *   what = 1: R_c in FP64, nodes*Lc doubles, node-major
+ *   what = 2: A_c blocks, ncells*27*Lc*Lc doubles
+ *   what = 3: coarse-coarse eigenvalues, ncc*Lcc doubles
+ *   what = 4: A_cc, n_cc*n_cc doubles
+ *   what = 5: per-cell level-1 status, ncells ints (outer iterations; < 0 = not converged)
+ * `bytes` is the capacity of `host_out`.  Returns MSMG_EINVAL if too small. */
+int msmg_export(msmg_handle* h, int what, void* host_out, size_t bytes);
+
+/* Release the handle and its device memory (NULL is ignored). */
+void msmg_destroy(msmg_handle* h);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* msmg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSMG_H */

@@ -1,0 +1,205 @@
+// Coarse levels of the three-grid cycle (Algorithm 1): block Gauss-Seidel
+// smoothing on A_c, residuals on level 1, restriction / prolongation with
+// R_cc, and the direct coarse-coarse solve (explicit FP64 inverse of A_cc
+// applied as a matrix-vector product).
+#include "internal.h"
+
+namespace msmg {
+
+// Neighbour block index b = (oz+1)*9 + (oy+1)*3 + (ox+1), 13 = the cell itself.
+MSMG_DEV long long nb_cell(const Hier& h, int cx, int cy, int cz, int b, bool& ok) {
+  const int ox = b % 3 - 1, oy = (b / 3) % 3 - 1, oz = b / 9 - 1;
+  const int x = cx + ox, y = cy + oy, z = cz + oz;
+  ok = x >= 0 && x < h.ncx && y >= 0 && y < h.ncy && z >= 0 && z < h.ncz;
+  return ((long long)z * h.ncy + y) * h.ncx + x;
+}
+
+// One colour of one block Gauss-Seidel sweep started from a zero guess:
+//   x_i = D_i^-1 (b_i - sum_{j earlier in the sweep} A_ij x_j)
+// for every cell i of the colour (colour = parity of the cell indices).  Cells
+// of one colour are never neighbours; cells of later colours are still zero,
+// so only earlier colours are read and x needs no clearing.  The forward sweep
+// (colours 0..7) is S_c^-1 = (D + L)^-1, the backward sweep (7..0) its
+// transpose.
+// LP * 8 lanes per cell (LP = power of two >= Lc): lane = (row l, slot q); slot q
+// sums the neighbour blocks b = q, q + 8, q + 16 of row l; the 8 slots of a row
+// are then combined by shuffles (fixed order), so the 27-block products of a
+// cell run in parallel.
+constexpr int ROW_SLOTS = 8;
+
+template <typename VT, typename AT>
+__global__ void k_gs_colour(Hier h, int colour, int forward, int LP, const AT* __restrict__ Ac,
+                            const AT* __restrict__ Dinv, const VT* __restrict__ b, VT* __restrict__ x,
+                            const Scalars* sc) {
+  if (sc && sc->done) return;
+  const int L = h.Lc;
+  const int CL = LP * ROW_SLOTS;
+  const long long gtid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const int lane = int(gtid % CL);
+  const int l = lane / ROW_SLOTS, q = lane % ROW_SLOTS;
+  const long long ci = gtid / CL;
+  const int px = colour & 1, py = (colour >> 1) & 1, pz = (colour >> 2) & 1;
+  const int nx = (h.ncx - px + 1) / 2, ny = (h.ncy - py + 1) / 2, nz = (h.ncz - pz + 1) / 2;
+  const bool valid = ci < (long long)nx * ny * nz;
+  long long cell = 0;
+  VT part = VT(0);
+  if (valid) {
+    const int cx = 2 * int(ci % nx) + px;
+    const int cy = 2 * int((ci / nx) % ny) + py;
+    const int cz = 2 * int(ci / ((long long)nx * ny)) + pz;
+    cell = ((long long)cz * h.ncy + cy) * h.ncx + cx;
+    if (l < L) {
+      const AT* A = Ac + cell * 27 * L * L;
+      for (int bb = q; bb < 27; bb += ROW_SLOTS) {
+        const int ox = bb % 3 - 1, oy = (bb / 3) % 3 - 1, oz = bb / 9 - 1;
+        const int ncol = ((px + ox) & 1) + 2 * ((py + oy) & 1) + 4 * ((pz + oz) & 1);
+        if (forward ? (ncol >= colour) : (ncol <= colour)) continue;
+        bool ok;
+        const long long nc = nb_cell(h, cx, cy, cz, bb, ok);
+        if (!ok) continue;
+        for (int m = 0; m < L; ++m) part += ld<VT, AT>(A, (bb * L + l) * L + m) * x[nc * L + m];
+      }
+    }
+  }
+  // row sums over the 8 slots (xor within aligned groups of 8 lanes)
+#pragma unroll
+  for (int off = 1; off < ROW_SLOTS; off <<= 1) part += __shfl_xor(part, off, 64);
+  const VT t = (valid && l < L) ? b[cell * L + l] - part : VT(0);
+  // x_i = D_i^-1 t: lane (l, 0) of each row computes row l
+  const int base = (threadIdx.x / CL) * CL;
+  VT upd = VT(0);
+  for (int m = 0; m < L; ++m) {
+    const VT tm = __shfl(t, base + m * ROW_SLOTS, 64);
+    if (valid && l < L) upd += ld<VT, AT>(Dinv, (cell * L + l) * L + m) * tm;
+  }
+  if (valid && l < L && q == 0) x[cell * L + l] = upd;
+}
+
+// t = b - A_c x on every cell (CELL_LANES lanes per cell as in the sweep).
+template <typename VT, typename AT>
+__global__ void k_ac_residual(Hier h, int LP, const AT* __restrict__ Ac, const VT* __restrict__ b,
+                              const VT* __restrict__ x, VT* __restrict__ t, const Scalars* sc) {
+  if (sc && sc->done) return;
+  const int L = h.Lc;
+  const int CL = LP * ROW_SLOTS;
+  const long long gtid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const int lane = int(gtid % CL);
+  const int l = lane / ROW_SLOTS, q = lane % ROW_SLOTS;
+  const long long cell = gtid / CL;
+  const bool valid = cell < h.ncells && l < L;
+  VT part = VT(0);
+  if (valid) {
+    const int cx = int(cell % h.ncx), cy = int((cell / h.ncx) % h.ncy), cz = int(cell / ((long long)h.ncx * h.ncy));
+    const AT* A = Ac + cell * 27 * L * L;
+    for (int bb = q; bb < 27; bb += ROW_SLOTS) {
+      bool ok;
+      const long long nc = nb_cell(h, cx, cy, cz, bb, ok);
+      if (!ok) continue;
+      for (int m = 0; m < L; ++m) part += ld<VT, AT>(A, (bb * L + l) * L + m) * x[nc * L + m];
+    }
+  }
+#pragma unroll
+  for (int off = 1; off < ROW_SLOTS; off <<= 1) part += __shfl_xor(part, off, 64);
+  if (valid && q == 0) t[cell * L + l] = b[cell * L + l] - part;
+}
+
+// r_cc[J*Lcc + b] = sum_d R_cc[J][b][d] t[cc_dofs[d]]: one wave per output entry.
+template <typename VT>
+__global__ void k_cc_restrict(Hier h, const VT* __restrict__ Rcc, const int* __restrict__ cc_ptr,
+                              const int* __restrict__ cc_dofs, const VT* __restrict__ t, double* __restrict__ rcc,
+                              const Scalars* sc) {
+  if (sc && sc->done) return;
+  const long long w = (blockIdx.x * (long long)blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (w >= (long long)h.ncc * h.Lcc) return;
+  const int J = int(w / h.Lcc), bidx = int(w % h.Lcc);
+  const int d0 = cc_ptr[J], nd = cc_ptr[J + 1] - d0;
+  const VT* R = Rcc + (long long)h.Lcc * d0 + (long long)bidx * nd;
+  double s = 0.0;
+  for (int d = lane; d < nd; d += 64) s += double(R[d]) * double(t[cc_dofs[d0 + d]]);
+  s = wave_sum(s);
+  if (lane == 0) rcc[w] = s;
+}
+
+// e = AccInv r (dense symmetric FP64): one wave per row.
+__global__ void k_acc_solve(int n, const double* __restrict__ Ainv, const double* __restrict__ r,
+                            double* __restrict__ e, const Scalars* sc) {
+  if (sc && sc->done) return;
+  const long long row = (blockIdx.x * (long long)blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  const double* a = Ainv + row * (long long)n;
+  double s = 0.0;
+  for (int j = lane; j < n; j += 64) s += a[j] * r[j];
+  s = wave_sum(s);
+  if (lane == 0) e[row] = s;
+}
+
+// out[d] = base[d] + sum_b R_cc[J][b][loc(d)] e[J*Lcc + b]
+template <typename VT>
+__global__ void k_cc_prolong(Hier h, int n_c, const VT* __restrict__ Rcc, const int* __restrict__ cc_ptr,
+                             const int* __restrict__ dof_cc, const int* __restrict__ dof_loc,
+                             const VT* __restrict__ base, const double* __restrict__ e, VT* __restrict__ out,
+                             const Scalars* sc) {
+  if (sc && sc->done) return;
+  const long long d = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (d >= n_c) return;
+  const int J = dof_cc[d], loc = dof_loc[d];
+  const int d0 = cc_ptr[J], nd = cc_ptr[J + 1] - d0;
+  const VT* R = Rcc + (long long)h.Lcc * d0;
+  double s = base ? double(base[d]) : 0.0;
+  for (int b = 0; b < h.Lcc; ++b) s += double(R[(long long)b * nd + loc]) * e[(long long)J * h.Lcc + b];
+  out[d] = VT(s);
+}
+
+// ---------------------------------------------------------------------------
+static inline int lanes_per_cell(int L) {
+  int lp = 1;
+  while (lp < L) lp <<= 1;
+  return lp;
+}
+
+void launch_gs_sweep(const Ctx& c, const void* b, void* x, bool forward, hipStream_t s) {
+  const Hier& h = c.h;
+  const int LP = lanes_per_cell(h.Lc);
+  for (int q = 0; q < 8; ++q) {
+    const int colour = forward ? q : 7 - q;
+    const int px = colour & 1, py = (colour >> 1) & 1, pz = (colour >> 2) & 1;
+    const long long ncol = (long long)((h.ncx - px + 1) / 2) * ((h.ncy - py + 1) / 2) * ((h.ncz - pz + 1) / 2);
+    if (ncol == 0) continue;
+    const long long nthreads = ncol * LP * ROW_SLOTS;
+    const dim3 gr((unsigned)((nthreads + 255) / 256)), bl(256);
+#define GS(VT, AT) hipLaunchKernelGGL((k_gs_colour<VT, AT>), gr, bl, 0, s, h, colour, forward ? 1 : 0, LP, (const AT*)c.cc.Ac, (const AT*)c.cc.AcDinv, (const VT*)b, (VT*)x, c.sc)
+    GS(double, double);
+#undef GS
+  }
+}
+
+void launch_ac_residual(const Ctx& c, const void* b, const void* x, void* t, hipStream_t s) {
+  const int LP = lanes_per_cell(c.h.Lc);
+  const long long n = (long long)c.h.ncells * LP * ROW_SLOTS;
+  const dim3 gr((unsigned)((n + 255) / 256)), bl(256);
+#define AR(VT, AT) hipLaunchKernelGGL((k_ac_residual<VT, AT>), gr, bl, 0, s, c.h, LP, (const AT*)c.cc.Ac, (const VT*)b, (const VT*)x, (VT*)t, c.sc)
+  AR(double, double);
+#undef AR
+}
+
+void launch_cc_restrict(const Ctx& c, const void* t, double* rcc, hipStream_t s) {
+  const long long nw = (long long)c.h.ncc * c.h.Lcc;
+  const dim3 gr((unsigned)((nw * 64 + 255) / 256)), bl(256);
+  hipLaunchKernelGGL((k_cc_restrict<double>), gr, bl, 0, s, c.h, (const double*)c.cc.Rcc, c.cc.cc_ptr, c.cc.cc_dofs, (const double*)t, rcc, c.sc);
+}
+
+void launch_acc_solve(const Ctx& c, const double* rcc, double* ecc, hipStream_t s) {
+  const long long n = c.cc.n_cc;
+  const dim3 gr((unsigned)((n * 64 + 255) / 256)), bl(256);
+  hipLaunchKernelGGL(k_acc_solve, gr, bl, 0, s, c.cc.n_cc, c.cc.AccInv, rcc, ecc, c.sc);
+}
+
+void launch_cc_prolong(const Ctx& c, const void* base, const double* ecc, void* out, hipStream_t s) {
+  const long long n = c.cc.n_c;
+  const dim3 gr((unsigned)((n + 255) / 256)), bl(256);
+  hipLaunchKernelGGL((k_cc_prolong<double>), gr, bl, 0, s, c.h, c.cc.n_c, (const double*)c.cc.Rcc, c.cc.cc_ptr, c.cc.dof_cc, c.cc.dof_loc, (const double*)base, ecc, (double*)out, c.sc);
+}
+
+}  // namespace msmg

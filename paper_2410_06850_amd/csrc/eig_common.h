@@ -1,0 +1,227 @@
+// Device building blocks of the set-up eigensolvers: block-level reductions
+// and a parallel cyclic Jacobi eigensolver for small symmetric matrices held
+// in LDS.
+#pragma once
+
+#include "internal.h"
+
+namespace msmg {
+
+MSMG_DEV int block_tid() { return threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z); }
+MSMG_DEV int block_nthr() { return blockDim.x * blockDim.y * blockDim.z; }
+
+// Sum of one value over the block, result returned to every thread.
+MSMG_DEV double block_allsum(double v, double* red) {
+  const int tid = block_tid(), nw = (block_nthr() + 63) >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < nw; ++w) s += red[w];
+  __syncthreads();
+  return s;
+}
+
+MSMG_DEV double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+MSMG_DEV int wave_min_int(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+MSMG_DEV double block_allmax(double v, double* red) {
+  const int tid = block_tid(), nw = (block_nthr() + 63) >> 6;
+  v = wave_max(v);
+  __syncthreads();
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  double s = red[0];
+  for (int w = 1; w < nw; ++w) s = fmax(s, red[w]);
+  __syncthreads();
+  return s;
+}
+
+MSMG_DEV int block_allmin_int(int v, int* red) {
+  const int tid = block_tid(), nw = (block_nthr() + 63) >> 6;
+  v = wave_min_int(v);
+  __syncthreads();
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  int s = red[0];
+  for (int w = 1; w < nw; ++w) s = min(s, red[w]);
+  __syncthreads();
+  return s;
+}
+
+// Sum of NV values per thread over the block; every thread receives the sums.
+template <int NV>
+MSMG_DEV void block_allsum_vec(double (&v)[NV], double* red) {
+  const int tid = block_tid(), nw = (block_nthr() + 63) >> 6;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
+  __syncthreads();
+  if ((tid & 63) == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) red[q * nw + (tid >> 6)] = v[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += red[q * nw + w];
+    v[q] = s;
+  }
+  __syncthreads();
+}
+
+// Partner of index j in round r of the round-robin pairing of mm (even) indices.
+MSMG_DEV int rr_partner(int r, int j, int mm) {
+  if (j == mm - 1) return r;
+  if (j == r) return mm - 1;
+  int p = (2 * r - j) % (mm - 1);
+  if (p < 0) p += mm - 1;
+  return p;
+}
+
+// Rotation (c, s) annihilating A[p][q] (p < q):  tau = (A_qq - A_pp) / (2 A_pq),
+// t = sign(tau) / (|tau| + sqrt(1 + tau^2)), c = 1/sqrt(1+t^2), s = t c
+// (Golub & Van Loan, symmetric Schur decomposition).
+MSMG_DEV void jacobi_rot(const double* A, int m, int p, int q, double& c, double& s) {
+  const double apq = A[p * m + q];
+  if (fabs(apq) < 1e-300) {
+    c = 1.0;
+    s = 0.0;
+    return;
+  }
+  const double tau = (A[q * m + q] - A[p * m + p]) / (2.0 * apq);
+  const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+  c = 1.0 / sqrt(1.0 + t * t);
+  s = t * c;
+}
+
+// Eigen-decomposition of the symmetric m x m matrix A (LDS, row-major) by the
+// parallel cyclic Jacobi method: rounds of disjoint rotations, each applied as
+// a column pass (B = A J, V = V J) and a row pass (A = J^T B).  On return
+// ev[k] are the eigenvalues in ascending order and column k of Vs holds the
+// matching eigenvector (Vs = V with permuted columns).  Uses threads
+// tid < m*m for element work; all threads of the block must call.
+// LDS: A, V, B, Vs: m*m; ev: m; perm: m ints; red: >= 2 * nwaves doubles.
+MSMG_DEV void block_jacobi(double* A, double* V, double* B, double* Vs, double* ev, int* perm, int m,
+                           double* red, int max_sweeps = 16) {
+  const int tid = block_tid(), nthr = block_nthr();
+  const int mm = m + (m & 1);
+  for (int e = tid; e < m * m; e += nthr) V[e] = (e / m == e % m) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    for (int r = 0; r < mm - 1; ++r) {
+      double vnew[4];
+      int cnt = 0;
+      for (int e = tid; e < m * m; e += nthr, ++cnt) {
+        const int i = e / m, j = e % m;
+        const int jp = rr_partner(r, j, mm);
+        double bv, vv;
+        if (jp >= m) {
+          bv = A[e];
+          vv = V[e];
+        } else {
+          double c, s;
+          const int p = min(j, jp), q = max(j, jp);
+          jacobi_rot(A, m, p, q, c, s);
+          if (j == p) {
+            bv = c * A[i * m + p] - s * A[i * m + q];
+            vv = c * V[i * m + p] - s * V[i * m + q];
+          } else {
+            bv = s * A[i * m + p] + c * A[i * m + q];
+            vv = s * V[i * m + p] + c * V[i * m + q];
+          }
+        }
+        B[e] = bv;
+        if (cnt < 4) vnew[cnt] = vv;
+      }
+      __syncthreads();
+      cnt = 0;
+      for (int e = tid; e < m * m; e += nthr, ++cnt) {
+        if (cnt < 4) V[e] = vnew[cnt];
+        const int i = e / m, j = e % m;
+        const int ip = rr_partner(r, i, mm);
+        double av;
+        if (ip >= m) {
+          av = B[e];
+        } else {
+          double c, s;
+          const int p = min(i, ip), q = max(i, ip);
+          jacobi_rot(A, m, p, q, c, s);
+          av = (i == p) ? (c * B[p * m + j] - s * B[q * m + j]) : (s * B[p * m + j] + c * B[q * m + j]);
+        }
+        vnew[cnt < 4 ? cnt : 3] = av;
+      }
+      __syncthreads();
+      cnt = 0;
+      for (int e = tid; e < m * m; e += nthr, ++cnt) A[e] = vnew[cnt < 4 ? cnt : 3];
+      __syncthreads();
+    }
+    // convergence: off-diagonal mass against the whole
+    double off = 0.0, all = 0.0;
+    for (int e = tid; e < m * m; e += nthr) {
+      const double a2 = A[e] * A[e];
+      all += a2;
+      if (e / m != e % m) off += a2;
+    }
+    off = block_allsum(off, red);
+    all = block_allsum(all, red);
+    if (!(off > 1e-32 * all)) break;
+  }
+  if (tid == 0) {
+    for (int k = 0; k < m; ++k) perm[k] = k;
+    for (int k = 1; k < m; ++k) {
+      const int pk = perm[k];
+      const double v = A[pk * m + pk];
+      int j = k - 1;
+      while (j >= 0 && A[perm[j] * m + perm[j]] > v) {
+        perm[j + 1] = perm[j];
+        --j;
+      }
+      perm[j + 1] = pk;
+    }
+    for (int k = 0; k < m; ++k) ev[k] = A[perm[k] * m + perm[k]];
+  }
+  __syncthreads();
+  for (int e = tid; e < m * m; e += nthr) {
+    const int i = e / m, k = e % m;
+    Vs[e] = V[i * m + perm[k]];
+  }
+  __syncthreads();
+}
+
+// Stencil weights of the unit-k Q1 operator around one node: w[o] for the
+// neighbour offset o = (oz+1)*9 + (oy+1)*3 + (ox+1), given the conductivities
+// kk[c] (c = cx + 2cy + 4cz) of the 8 surrounding elements (0 when absent).
+MSMG_DEV void stencil27(const Stencil& st, const double kk[8], double w[27]) {
+#pragma unroll
+  for (int o = 0; o < 27; ++o) {
+    const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int cx = c & 1, cy = (c >> 1) & 1, cz = (c >> 2) & 1;
+      const bool okx = (ox == 0) || (ox > 0 && cx == 1) || (ox < 0 && cx == 0);
+      const bool oky = (oy == 0) || (oy > 0 && cy == 1) || (oy < 0 && cy == 0);
+      const bool okz = (oz == 0) || (oz > 0 && cz == 1) || (oz < 0 && cz == 0);
+      if (okx && oky && okz) s += kk[c];
+    }
+    const int nd = (ox != 0) + (oy != 0) + (oz != 0);
+    double pat;
+    if (nd == 0) pat = st.self;
+    else if (nd == 3) pat = st.bd;
+    else if (nd == 1) pat = st.ax[ox != 0 ? 0 : (oy != 0 ? 1 : 2)];
+    else pat = st.fd[ox == 0 ? 0 : (oy == 0 ? 1 : 2)];
+    w[o] = pat * s;
+  }
+}
+
+}  // namespace msmg

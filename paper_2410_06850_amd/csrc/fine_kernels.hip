@@ -1,0 +1,832 @@
+// Fine-level kernels: matrix-free Q1 apply with the SIMP material law fused in,
+// PCG vector updates with deterministic reductions, the level-0 Chebyshev-Jacobi
+// smoother, restriction / prolongation with the local spectral basis R_c,
+// element sensitivities, consistent loads and grid-to-grid interpolation.
+//
+// Paper anchors: material law eq. (material); the system A t = f of section
+// 2.2 (here with Q1 elements); Algorithm 1 (three-grid cycle) lines for the
+// fine level; adjoint sensitivity of section 2.3.
+#include "internal.h"
+#include "setup.h"
+
+namespace msmg {
+
+// ---------------------------------------------------------------------------
+// small elementwise kernels
+
+__global__ void k_pack_mask(const uint8_t* __restrict__ mask, uint32_t* __restrict__ bits, long long nn) {
+  const long long w = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const long long nw = (nn + 31) >> 5;
+  if (w >= nw) return;
+  uint32_t v = 0;
+  const long long base = w << 5;
+  for (int b = 0; b < 32; ++b) {
+    const long long n = base + b;
+    if (n < nn && mask[n]) v |= (1u << b);
+  }
+  bits[w] = v;
+}
+
+template <typename Tin, typename Tout>
+__global__ void k_convert(const Tin* __restrict__ in, Tout* __restrict__ out, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    out[i] = from_f64<Tout>(to_f64<Tin>(in[i]));
+}
+
+// Jacobi diagonal inverse: D_n = self * sum of the 8 k_e around n; 0 on fixed nodes.
+template <typename RT, typename VT>
+__global__ void k_diag_inv(Geo g, Stencil st, const RT* __restrict__ rho, Material m,
+                           const uint32_t* __restrict__ bits, VT* __restrict__ dinv) {
+  const long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (n >= g.nn) return;
+  const int i = int(n % g.nnx), j = int((n / g.nnx) % g.nny), k = int(n / ((long long)g.nnx * g.nny));
+  double kk[8];
+  load_k8<double, RT>(g, rho, m.kmin, m.kmax - m.kmin, m.p, i, j, k, kk);
+  double s = 0.0;
+  for (int c = 0; c < 8; ++c) s += kk[c];
+  const double d = st.self * s;
+  dinv[n] = from_f64<VT>(mask_bit(bits, n) ? 0.0 : 1.0 / d);
+}
+
+__global__ void k_zero_fixed_copy(const double* __restrict__ in, double* __restrict__ out,
+                                  const uint32_t* __restrict__ bits, long long nn) {
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < nn; n += (long long)gridDim.x * blockDim.x)
+    out[n] = mask_bit(bits, n) ? 0.0 : in[n];
+}
+
+// T = x on free nodes, fixed values (or 0) on fixed nodes.
+__global__ void k_finish_solution(double* __restrict__ T, const double* __restrict__ tfix,
+                                  const uint32_t* __restrict__ bits, long long nn) {
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < nn; n += (long long)gridDim.x * blockDim.x)
+    if (mask_bit(bits, n)) T[n] = tfix ? tfix[n] : 0.0;
+}
+
+// ||v||^2 over all nodes (v is zero on fixed nodes); fin sets bb / tol2 or rr.
+__global__ void k_norm2(const double* __restrict__ v, long long nn, int what, double rtol2, Scalars* sc,
+                        double* partials, unsigned* counter) {
+  __shared__ double red[16];
+  double s[1] = {0.0};
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < nn; n += (long long)gridDim.x * blockDim.x)
+    s[0] += v[n] * v[n];
+  grid_reduce<1>(s, red, partials, counter, gridDim.x, blockIdx.x, [&](double* t) {
+    if (what == 0) {
+      sc->bb = t[0];
+      sc->tol2 = rtol2 * t[0];
+    } else if (what == 1) {
+      sc->rr = t[0];
+    } else {
+      sc->true_rr = t[0];
+    }
+  });
+}
+
+// x += alpha p in double-double (x = xhi + xlo, the product's rounding error is
+// kept with an FMA), r -= alpha q ; rr = ||r||^2, convergence flags.  The
+// iterate needs the extra precision at high contrast: T reaches ~1/k_min on
+// low-conductivity islands and a binary64 T cannot resolve the flux inside
+// high-conductivity regions to a relative residual of 1e-8.
+MSMG_DEV void dd_add(double& hi, double& lo, double a, double ae) {
+  // (hi, lo) += (a, ae)
+  const double s = hi + a;
+  const double bb = s - hi;
+  const double err = (hi - (s - bb)) + (a - bb);
+  const double t = lo + ae + err;
+  hi = s + t;
+  lo = t - (hi - s);
+}
+
+__global__ void k_update_xr(double* __restrict__ x, double* __restrict__ xlo, double* __restrict__ r,
+                            const double* __restrict__ p, const double* __restrict__ q, long long nn, Scalars* sc,
+                            double* partials, unsigned* counter) {
+  if (sc->done) return;
+  __shared__ double red[16];
+  const double a = sc->alpha;
+  double s[1] = {0.0};
+#pragma unroll 4
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < nn; n += (long long)gridDim.x * blockDim.x) {
+    const double pn = p[n];
+    const double prod = a * pn;
+    const double perr = fma(a, pn, -prod);
+    double hi = x[n], lo = xlo[n];
+    dd_add(hi, lo, prod, perr);
+    x[n] = hi;
+    xlo[n] = lo;
+    const double rn = r[n] - a * q[n];
+    r[n] = rn;
+    s[0] += rn * rn;
+  }
+  grid_reduce<1>(s, red, partials, counter, gridDim.x, blockIdx.x, [&](double* t) {
+    sc->rr = t[0];
+    sc->iters += 1;
+    if (!(t[0] == t[0]) || t[0] > 1.7e308) {
+      sc->status = ST_NONFINITE;
+      sc->done = 1;
+    } else if (t[0] <= sc->tol2) {
+      sc->status = ST_CONV_RECURSIVE;
+      sc->done = 1;
+    } else if (sc->iters >= sc->maxit) {
+      sc->status = ST_MAXIT;
+      sc->done = 1;
+    }
+  });
+}
+
+// T = xhi + xlo rounded (or xlo copied out when tlo is given) on free nodes;
+// fixed values (or 0) on fixed nodes.
+__global__ void k_finish_solution_dd(double* __restrict__ T, const double* __restrict__ xlo, double* __restrict__ tlo,
+                                     const double* __restrict__ tfix, const uint32_t* __restrict__ bits, long long nn) {
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < nn; n += (long long)gridDim.x * blockDim.x) {
+    if (mask_bit(bits, n)) {
+      T[n] = tfix ? tfix[n] : 0.0;
+      if (tlo) tlo[n] = 0.0;
+    } else if (tlo) {
+      tlo[n] = xlo[n];
+    } else {
+      T[n] = T[n] + xlo[n];
+    }
+  }
+}
+
+// p = z + beta p
+__global__ void k_update_p(double* __restrict__ p, const double* __restrict__ z, long long nn, const Scalars* sc) {
+  if (sc->done) return;
+  const double b = sc->beta;
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < nn; n += (long long)gridDim.x * blockDim.x)
+    p[n] = z[n] + b * p[n];
+}
+
+// ---------------------------------------------------------------------------
+// Stencil kernels on cell-aligned tiles.
+
+#define TILE_PROLOGUE                                                     \
+  const long long tile = xcd_tile(blockIdx.x, gridDim.x);                 \
+  const Tile t = tile_of_thread(g, h, CX, tile);
+
+// y = A x on free rows (0 on fixed rows); optional p^T (A p) reduction -> alpha.
+//   mode 0: plain apply; 1: PCG apply with pq -> alpha; 2: masked public form P A P x + (I-P) x
+template <typename RT, bool CUBIC>
+__global__ __launch_bounds__(MARCH_THREADS) void k_apply(Geo g, Stencil st, March mg, const RT* __restrict__ rho,
+                                                         Material m, const uint32_t* __restrict__ bits,
+                                                         const double* __restrict__ x, double* __restrict__ y, int mode,
+                                                         Scalars* sc, double* partials, unsigned* counter) {
+  if (mode == 1 && sc->done) return;
+  __shared__ double sx[2 * PW * PH];
+  __shared__ double sk[2 * EW * EH];
+  __shared__ double red[16];
+  const long long tile = xcd_tile(blockIdx.x, gridDim.x);
+  const double dk = m.kmax - m.kmin;
+  double s[1] = {0.0};
+  march<double, CUBIC>(
+      g, st, mg, tile, sx, sk,
+      [&](long long n) { return (mode == 2 && mask_bit(bits, n)) ? 0.0 : x[n]; },
+      [&](long long e) { return conductivity<double>(ld<double, RT>(rho, e), m.kmin, dk, m.p); },
+      [&](int, int, int, long long n, double ax, double xc) {
+        double out = ax;
+        if (mask_bit(bits, n)) out = (mode == 2) ? x[n] : 0.0;
+        y[n] = out;
+        if (mode == 1) s[0] += xc * out;
+      });
+  if (mode != 1) return;
+  grid_reduce<1>(s, red, partials, counter, gridDim.x, blockIdx.x, [&](double* tt) {
+    sc->pq = tt[0];
+    if (!(tt[0] > 0.0) || !(sc->rz > 0.0)) {
+      sc->status = (tt[0] == tt[0] && sc->rz == sc->rz) ? ST_BREAKDOWN : ST_NONFINITE;
+      sc->done = 1;
+    } else {
+      sc->alpha = sc->rz / tt[0];
+    }
+  });
+}
+
+// y = b - A x on free rows (0 on fixed rows); ||y||^2 -> true_rr (if sc).  With
+// xlo the iterate is x + xlo and neighbour differences are taken on both parts.
+template <typename RT, bool CUBIC>
+__global__ void k_residual(Geo g, Stencil st, Hier h, int CX, const RT* __restrict__ rho, Material m,
+                           const uint32_t* __restrict__ bits, const double* __restrict__ b,
+                           const double* __restrict__ x, const double* __restrict__ xlo, double* __restrict__ y,
+                           Scalars* sc, double* partials, unsigned* counter) {
+  __shared__ double red[16];
+  TILE_PROLOGUE
+  const double dk = m.kmax - m.kmin;
+  double s[1] = {0.0};
+  if (t.active) {
+    for (int k = t.zs; k < t.ze; ++k)
+      for (int j = t.ys; j < t.ye; ++j)
+        for (int i = t.xs; i < t.xe; ++i) {
+          const long long n = node_id(g, i, j, k);
+          double out = 0.0;
+          if (!mask_bit(bits, n)) {
+            double kk[8];
+            load_k8<double, RT>(g, rho, m.kmin, dk, m.p, i, j, k, kk);
+            out = b[n] - gather_apply<double, CUBIC>(g, st, kk, i, j, k,
+                                                     [&](int a, int bb, int c) { return x[node_id(g, a, bb, c)]; });
+            if (xlo)
+              out -= gather_apply<double, CUBIC>(g, st, kk, i, j, k,
+                                                 [&](int a, int bb, int c) { return xlo[node_id(g, a, bb, c)]; });
+          }
+          y[n] = out;
+          s[0] += out * out;
+        }
+  }
+  if (!sc) return;
+  grid_reduce<1>(s, red, partials, counter, gridDim.x, blockIdx.x, [&](double* tt) { sc->true_rr = tt[0]; });
+}
+
+// ---------------------------------------------------------------------------
+// Level-0 of Algorithm 1.  Chebyshev coefficients for the interval [lo, hi] of
+// D^-1 A: theta = (hi+lo)/2, delta = (hi-lo)/2, sigma = theta/delta.
+
+// Step 1 of the smoother (degree 1, or the start of higher degrees): x1 = D^-1 r / theta.
+template <typename VT, typename IT>
+__global__ void k_cheb_first(const IT* __restrict__ r, const VT* __restrict__ dinv, VT* __restrict__ x,
+                             VT* __restrict__ d, long long nn, double inv_theta, const Scalars* sc) {
+  if (sc && sc->done) return;
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < nn; n += (long long)gridDim.x * blockDim.x) {
+    const VT v = VT(ld<VT, IT>(r, n) * dinv[n] * VT(inv_theta));
+    x[n] = v;
+    if (d) d[n] = v;
+  }
+}
+
+// Fused first two Chebyshev steps, started from a zero guess:
+//   z1 = D^-1 r / theta,  out = (1 + rho1 rho0) z1 + (2 rho1 / delta) D^-1 (r - A z1)
+// with z1 staged for the neighbours straight from r and D^-1.  When `dout` is
+// given the second direction d1 = out - z1 is stored for further steps.
+template <typename VT, typename RT, typename IT, bool CUBIC>
+__global__ __launch_bounds__(MARCH_THREADS) void k_cheb2(Geo g, Stencil st, March mg, const RT* __restrict__ rho,
+                                                         Material m, const IT* __restrict__ r,
+                                                         const VT* __restrict__ dinv, VT* __restrict__ out,
+                                                         VT* __restrict__ dout, ChebCoef cc, const Scalars* sc) {
+  if (sc && sc->done) return;
+  __shared__ VT sx[2 * PW * PH];
+  __shared__ VT sk[2 * EW * EH];
+  const long long tile = xcd_tile(blockIdx.x, gridDim.x);
+  const VT dk = VT(m.kmax - m.kmin), kmin = VT(m.kmin);
+  const VT it = VT(cc.inv_theta), c0 = VT(cc.c0), c1 = VT(cc.c1);
+  march<VT, CUBIC>(
+      g, st, mg, tile, sx, sk, [&](long long n) { return ld<VT, IT>(r, n) * dinv[n] * it; },
+      [&](long long e) { return conductivity<VT>(ld<VT, RT>(rho, e), kmin, dk, m.p); },
+      [&](int, int, int, long long n, VT az, VT z1) {
+        const VT di = dinv[n];
+        VT v = VT(0);
+        if (di != VT(0)) v = c0 * z1 + c1 * di * (ld<VT, IT>(r, n) - az);
+        out[n] = v;
+        if (dout) dout[n] = v - z1;
+      });
+}
+
+// Generic Chebyshev step k >= 3:  res = r - A x;  d = a d + b D^-1 res;  xout = x + d.
+template <typename VT, typename RT, typename IT, bool CUBIC>
+__global__ __launch_bounds__(MARCH_THREADS) void k_cheb_step(Geo g, Stencil st, March mg, const RT* __restrict__ rho,
+                                                             Material m, const IT* __restrict__ r,
+                                                             const VT* __restrict__ dinv, const VT* __restrict__ x,
+                                                             VT* __restrict__ d, VT* __restrict__ xout, double ca,
+                                                             double cb, const Scalars* sc) {
+  if (sc && sc->done) return;
+  __shared__ VT sx[2 * PW * PH];
+  __shared__ VT sk[2 * EW * EH];
+  const long long tile = xcd_tile(blockIdx.x, gridDim.x);
+  const VT dk = VT(m.kmax - m.kmin), kmin = VT(m.kmin);
+  march<VT, CUBIC>(
+      g, st, mg, tile, sx, sk, [&](long long n) { return x[n]; },
+      [&](long long e) { return conductivity<VT>(ld<VT, RT>(rho, e), kmin, dk, m.p); },
+      [&](int, int, int, long long n, VT ax, VT xc) {
+        const VT di = dinv[n];
+        if (di == VT(0)) {
+          d[n] = VT(0);
+          xout[n] = VT(0);
+          return;
+        }
+        const VT dn = VT(ca) * d[n] + VT(cb) * di * (ld<VT, IT>(r, n) - ax);
+        d[n] = dn;
+        xout[n] = xc + dn;
+      });
+}
+
+// Restriction of Algorithm 1:  rc[cell][l] = sum_{n in cell} R_c[n][l] (r_n - (A x)_n)
+// over owned free nodes.  One block holds whole coarse cells, so the per-cell
+// sums finish in the block (fixed order).
+template <typename VT, typename RT, typename BT, typename IT, bool CUBIC>
+__global__ void k_restrict(Geo g, Stencil st, Hier h, int CX, const RT* __restrict__ rho, Material m,
+                           const uint32_t* __restrict__ bits, const IT* __restrict__ r, const VT* __restrict__ x,
+                           const BT* __restrict__ Rc, double* __restrict__ rc, const Scalars* sc) {
+  if (sc && sc->done) return;
+  extern __shared__ double smem[];
+  TILE_PROLOGUE
+  const int L = h.Lc;
+  const VT dk = VT(m.kmax - m.kmin), kmin = VT(m.kmin);
+  double acc[LC_MAX];
+#pragma unroll
+  for (int l = 0; l < LC_MAX; ++l) acc[l] = 0.0;
+  if (t.active) {
+    for (int k = t.zs; k < t.ze; ++k)
+      for (int j = t.ys; j < t.ye; ++j)
+        for (int i = t.xs; i < t.xe; ++i) {
+          const long long n = node_id(g, i, j, k);
+          if (mask_bit(bits, n)) continue;
+          VT res = ld<VT, IT>(r, n);
+          if (x) {
+            VT kk[8];
+            load_k8<VT, RT>(g, rho, kmin, dk, m.p, i, j, k, kk);
+            res -= gather_apply<VT, CUBIC>(g, st, kk, i, j, k, [&](int a, int b, int c) { return x[node_id(g, a, b, c)]; });
+          }
+#pragma unroll
+          for (int l = 0; l < LC_MAX; ++l)
+            if (l < L) acc[l] += double(ld<VT, BT>(Rc, n * L + l) * res);
+        }
+  }
+  // per-cell reduction in fixed order.  Each wave is one node row of the tile
+  // (blockDim.x = CX*H = 64 when H divides 64): groups of H lanes belong to one
+  // cell, so a segmented xor-shuffle sums the row, then the H rows are summed.
+  const int nthr = blockDim.x * blockDim.y;
+  const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+  const int ntx = (h.ncx + CX - 1) / CX;
+  const int tx = int(tile % ntx), ty = int((tile / ntx) % h.ncy), tz = int(tile / ((long long)ntx * h.ncy));
+  double* red = smem;
+  const bool pow2 = (h.H & (h.H - 1)) == 0 && blockDim.x == 64;
+  if (pow2) {
+#pragma unroll
+    for (int l = 0; l < LC_MAX; ++l) {
+      if (l >= L) break;
+      double v = acc[l];
+      for (int off = 1; off < h.H; off <<= 1) v += __shfl_xor(v, off, 64);
+      acc[l] = v;
+    }
+    if ((threadIdx.x % h.H) == 0) {
+      const int cl = threadIdx.x / h.H;
+      for (int l = 0; l < L; ++l) red[(threadIdx.y * CX + cl) * L + l] = acc[l];
+    }
+    __syncthreads();
+    for (int q = tid; q < CX * L; q += nthr) {
+      const int cl = q / L, l = q % L;
+      const int cx = tx * CX + cl;
+      if (cx >= h.ncx || tz >= h.ncz) continue;
+      double sum = 0.0;
+      for (int ly = 0; ly < (int)blockDim.y; ++ly) sum += red[(ly * CX + cl) * L + l];
+      const long long cell = ((long long)tz * h.ncy + ty) * h.ncx + cx;
+      rc[cell * L + l] = sum;
+    }
+    return;
+  }
+  for (int l = 0; l < L; ++l) red[l * nthr + tid] = acc[l];
+  __syncthreads();
+  for (int q = tid; q < CX * L; q += nthr) {
+    const int cl = q / L, l = q % L;
+    const int cx = tx * CX + cl;
+    if (cx >= h.ncx || tz >= h.ncz) continue;
+    double sum = 0.0;
+    for (int ly = 0; ly < (int)blockDim.y; ++ly)
+      for (int lx = cl * h.H; lx < (cl + 1) * h.H; ++lx) sum += red[l * nthr + ly * blockDim.x + lx];
+    const long long cell = ((long long)tz * h.ncy + ty) * h.ncx + cx;
+    rc[cell * L + l] = sum;
+  }
+}
+
+// Prolongation of Algorithm 1: out = base + sum_l R_c[n][l] (e1 + e2)[owner(n)][l]
+// (e2 optional).  Fixed nodes stay 0 (R_c vanishes there).
+template <typename VT, typename BT>
+__global__ void k_prolong(Geo g, Hier h, int CX, const VT* __restrict__ base, const BT* __restrict__ Rc,
+                          const double* __restrict__ e1, const double* __restrict__ e2, double* __restrict__ out,
+                          const Scalars* sc) {
+  if (sc && sc->done) return;
+  TILE_PROLOGUE
+  if (!t.active) return;
+  const int L = h.Lc;
+  const long long cell = ((long long)t.cz * h.ncy + t.cy) * h.ncx + t.cx;
+  double e[LC_MAX];
+#pragma unroll
+  for (int l = 0; l < LC_MAX; ++l) e[l] = (l < L) ? e1[cell * L + l] + (e2 ? e2[cell * L + l] : 0.0) : 0.0;
+#pragma unroll 3
+  for (int k = t.zs; k < t.ze; ++k)
+    for (int j = t.ys; j < t.ye; ++j)
+      for (int i = t.xs; i < t.xe; ++i) {
+        const long long n = node_id(g, i, j, k);
+        double v = base ? double(base[n]) : 0.0;
+#pragma unroll
+        for (int l = 0; l < LC_MAX; ++l)
+          if (l < L) v += ld<double, BT>(Rc, n * L + l) * e[l];
+        out[n] = v;
+      }
+}
+
+// V-cycle residual on level 0:  out = r - A x (free rows).  The stencil runs in
+// the type of x: after the coarse correction x carries the large, nearly flat
+// values of the low-energy modes and is kept (and differenced) in FP64.
+template <typename VT, typename RT, typename IT, typename XT, bool CUBIC>
+__global__ __launch_bounds__(MARCH_THREADS) void k_vresidual(Geo g, Stencil st, March mg, const RT* __restrict__ rho,
+                                                             Material m, const VT* __restrict__ dinv,
+                                                             const IT* __restrict__ r, const XT* __restrict__ x,
+                                                             VT* __restrict__ out, const Scalars* sc) {
+  if (sc && sc->done) return;
+  __shared__ XT sx[2 * PW * PH];
+  __shared__ XT sk[2 * EW * EH];
+  const long long tile = xcd_tile(blockIdx.x, gridDim.x);
+  const XT dk = XT(m.kmax - m.kmin), kmin = XT(m.kmin);
+  march<XT, CUBIC>(
+      g, st, mg, tile, sx, sk, [&](long long n) { return x[n]; },
+      [&](long long e) { return conductivity<XT>(ld<XT, RT>(rho, e), kmin, dk, m.p); },
+      [&](int, int, int, long long n, XT ax, XT) {
+        out[n] = (dinv[n] == VT(0)) ? VT(0) : VT(ld<XT, IT>(r, n) - ax);
+      });
+}
+
+// z = a + b (V-cycle type) written as FP64, with the PCG products z^T r and
+// z^T q; fin computes beta (Polak-Ribiere) and the new r^T z.
+//   mode 0: initial (beta = 0); mode 1: iteration; mode 2: no reduction.
+template <typename AT_, typename VT>
+__global__ void k_vc_output(const AT_* __restrict__ a, const VT* __restrict__ b, double* __restrict__ z,
+                            const double* __restrict__ r, const double* __restrict__ q, long long nn, int mode,
+                            Scalars* sc, double* partials, unsigned* counter) {
+  if (sc && sc->done) return;
+  __shared__ double red[32];
+  double s[2] = {0.0, 0.0};
+#pragma unroll 4
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < nn; n += (long long)gridDim.x * blockDim.x) {
+    const double v = double(a[n]) + (b ? double(b[n]) : 0.0);
+    z[n] = v;
+    if (mode != 2) {
+      s[0] += v * r[n];
+      if (mode == 1) s[1] += v * q[n];
+    }
+  }
+  if (mode == 2) return;
+  grid_reduce<2>(s, red, partials, counter, gridDim.x, blockIdx.x, [&](double* tt) {
+    sc->zr = tt[0];
+    sc->zq = tt[1];
+    if (!(tt[0] > 0.0)) {
+      sc->status = (tt[0] == tt[0]) ? ST_BREAKDOWN : ST_NONFINITE;
+      sc->done = 1;
+      return;
+    }
+    if (mode == 0) {
+      sc->beta = 0.0;
+    } else {
+      // beta = z^T (r_new - r_old) / rz_old with r_old = r_new + alpha q
+      sc->beta = -sc->alpha * tt[1] / sc->rz;
+    }
+    sc->rz = tt[0];
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Sensitivity: dc/drho_e = -p rho^(p-1) (kmax - kmin) lam_e^T K0 T_e   (section 2.3)
+template <typename RT>
+__global__ void k_sensitivity(Geo g, Stencil st, const RT* __restrict__ rho, Material m,
+                              const double* __restrict__ T, const double* __restrict__ lam,
+                              const uint32_t* __restrict__ bits, double* __restrict__ dc) {
+  const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (e >= g.ne) return;
+  const int i = int(e % g.nx), j = int((e / g.nx) % g.ny), k = int(e / ((long long)g.nx * g.ny));
+  double tv[8], lv[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const long long n = node_id(g, i + (a & 1), j + ((a >> 1) & 1), k + ((a >> 2) & 1));
+    tv[a] = T[n];
+    lv[a] = lam ? lam[n] : (mask_bit(bits, n) ? 0.0 : T[n]);
+  }
+  // pattern of K0[a][b] by the axes where a and b differ
+  double pat[8];
+  pat[0] = st.self;
+  pat[1] = st.ax[0];
+  pat[2] = st.ax[1];
+  pat[4] = st.ax[2];
+  pat[3] = st.fd[2];
+  pat[5] = st.fd[1];
+  pat[6] = st.fd[0];
+  pat[7] = st.bd;
+  // lam^T K0 T = -sum_{a<b} K0[a][b] (lam_a - lam_b)(T_a - T_b)  (zero row sums):
+  // differences keep the product accurate where T is large and nearly flat
+  double q = 0.0;
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = a + 1; b < 8; ++b) q -= pat[a ^ b] * (lv[a] - lv[b]) * (tv[a] - tv[b]);
+  const double r = to_f64<RT>(rho[e]);
+  double rp = 1.0;
+  for (int t = 1; t < m.p; ++t) rp *= r;
+  dc[e] = -double(m.p) * rp * (m.kmax - m.kmin) * q;
+}
+
+// Consistent load of an element-wise constant source: f_n = sum_{e ni n} s_e V / 8.
+__global__ void k_element_load(Geo g, const double* __restrict__ src, double sconst, double* __restrict__ f) {
+  const long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (n >= g.nn) return;
+  const int i = int(n % g.nnx), j = int((n / g.nnx) % g.nny), k = int(n / ((long long)g.nnx * g.nny));
+  double s = 0.0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int ei = i - 1 + (c & 1), ej = j - 1 + ((c >> 1) & 1), ek = k - 1 + ((c >> 2) & 1);
+    if (ei >= 0 && ei < g.nx && ej >= 0 && ej < g.ny && ek >= 0 && ek < g.nz)
+      s += src ? src[elem_id(g, ei, ej, ek)] : sconst;
+  }
+  f[n] = s * (g.vol / 8.0);
+}
+
+// Nodal trilinear prolongation (nx,ny,nz) -> (2nx,2ny,2nz): the coarse Q1
+// function evaluated at the fine nodes (averages of 1, 2, 4 or 8 coarse nodes).
+__global__ void k_prolong_nodal(int nx, int ny, int nz, const double* __restrict__ tc, double* __restrict__ tf) {
+  const long long fnx = 2LL * nx + 1, fny = 2LL * ny + 1, fnz = 2LL * nz + 1;
+  const long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (n >= fnx * fny * fnz) return;
+  const int i = int(n % fnx), j = int((n / fnx) % fny), k = int(n / (fnx * fny));
+  const int i0 = i >> 1, j0 = j >> 1, k0 = k >> 1;
+  const int i1 = i0 + (i & 1), j1 = j0 + (j & 1), k1 = k0 + (k & 1);
+  const long long cnx = nx + 1, cny = ny + 1;
+  auto at = [&](int a, int b, int c) { return tc[((long long)c * cny + b) * cnx + a]; };
+  const double v = at(i0, j0, k0) + at(i1, j0, k0) + at(i0, j1, k0) + at(i1, j1, k0) + at(i0, j0, k1) +
+                   at(i1, j0, k1) + at(i0, j1, k1) + at(i1, j1, k1);
+  tf[n] = 0.125 * v;
+}
+
+// Element injection (nx,ny,nz) -> (2nx,2ny,2nz): each child takes its parent's value.
+template <typename T>
+__global__ void k_prolong_element(int nx, int ny, int nz, const T* __restrict__ rc, T* __restrict__ rf) {
+  const long long fnx = 2LL * nx, fny = 2LL * ny, fnz = 2LL * nz;
+  const long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (n >= fnx * fny * fnz) return;
+  const int i = int(n % fnx), j = int((n / fnx) % fny), k = int(n / (fnx * fny));
+  rf[n] = rc[((long long)(k >> 1) * ny + (j >> 1)) * nx + (i >> 1)];
+}
+
+
+// ---------------------------------------------------------------------------
+// utilities
+
+__global__ void k_fill(double* __restrict__ x, double v, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    x[i] = v;
+}
+
+__global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    b[i] = a[i];
+}
+
+__global__ void k_zero_free(double* __restrict__ x, const uint32_t* __restrict__ bits, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    if (!mask_bit(bits, i)) x[i] = 0.0;
+}
+
+// full = 1: fresh solve (iteration count, maxit, status); 0: clear done/status only.
+__global__ void k_sc_reset(Scalars* sc, int full, int maxit) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  sc->done = 0;
+  sc->status = ST_RUNNING;
+  if (full) {
+    sc->iters = 0;
+    sc->maxit = maxit;
+    sc->alpha = sc->beta = 0.0;
+  }
+}
+
+__global__ void k_count_bits(const uint32_t* __restrict__ bits, long long nw, unsigned* out) {
+  unsigned c = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nw; i += (long long)gridDim.x * blockDim.x)
+    c += __popc(bits[i]);
+  c = wave_sum(c);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
+}
+
+void launch_fill(const Ctx& c, double* x, double v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill, dim3(2048), dim3(256), 0, s, x, v, c.g.nn);
+}
+void launch_copy(const Ctx& c, const double* a, double* b, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy, dim3(2048), dim3(256), 0, s, a, b, c.g.nn);
+}
+void launch_zero_free(const Ctx& c, double* x, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_free, dim3(2048), dim3(256), 0, s, x, c.bits, c.g.nn);
+}
+void launch_sc_reset(const Ctx& c, int full, int maxit, hipStream_t s) {
+  hipLaunchKernelGGL(k_sc_reset, dim3(1), dim3(64), 0, s, c.sc, full, maxit);
+}
+int count_fixed(const Ctx& c, int* nfixed, hipStream_t s) {
+  unsigned* d = reinterpret_cast<unsigned*>(c.counter) + 8;  // spare slot of the counter block
+  if (hipMemsetAsync(d, 0, 4, s) != hipSuccess) return MSMG_EHIP;
+  const long long nw = (c.g.nn + 31) >> 5;
+  hipLaunchKernelGGL(k_count_bits, dim3(512), dim3(256), 0, s, c.bits, nw, d);
+  unsigned hv = 0;
+  if (hipMemcpyAsync(&hv, d, 4, hipMemcpyDeviceToHost, s) != hipSuccess) return MSMG_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return MSMG_EHIP;
+  *nfixed = int(hv);
+  return MSMG_OK;
+}
+
+// ===========================================================================
+// Launchers
+// ===========================================================================
+
+static inline int grid1d(long long n, int bs, int cap = 4096) {
+  long long b = (n + bs - 1) / bs;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return int(b);
+}
+
+void launch_pack_mask(const uint8_t* mask, uint32_t* bits, long long nn, hipStream_t s) {
+  const long long nw = (nn + 31) >> 5;
+  hipLaunchKernelGGL(k_pack_mask, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, mask, bits, nn);
+}
+
+void launch_convert(const void* in, int din, void* out, int dout, long long n, hipStream_t s) {
+  const dim3 gr(grid1d(n, 256, 8192)), bl(256);
+#define CONV(TI, TO) hipLaunchKernelGGL((k_convert<TI, TO>), gr, bl, 0, s, (const TI*)in, (TO*)out, n)
+  if (din == DT_F64 && dout == DT_F64) CONV(double, double);
+  else if (din == DT_F64 && dout == DT_F32) CONV(double, float);
+  else if (din == DT_F64 && dout == DT_BF16) CONV(double, bf16);
+  else if (din == DT_F32 && dout == DT_F64) CONV(float, double);
+  else if (din == DT_F32 && dout == DT_F32) CONV(float, float);
+  else if (din == DT_F32 && dout == DT_BF16) CONV(float, bf16);
+  else if (din == DT_BF16 && dout == DT_F64) CONV(bf16, double);
+  else if (din == DT_BF16 && dout == DT_F32) CONV(bf16, float);
+  else CONV(bf16, bf16);
+#undef CONV
+}
+
+void launch_diag_inv(const Ctx& c, const void* rho, int rdt, void* dinv, int vdt, hipStream_t s) {
+  const dim3 gr((unsigned)((c.g.nn + 255) / 256)), bl(256);
+#define DI(RT, VT) hipLaunchKernelGGL((k_diag_inv<RT, VT>), gr, bl, 0, s, c.g, c.st, (const RT*)rho, c.mat, c.bits, (VT*)dinv)
+  if (rdt == DT_F64 && vdt == DT_F64) DI(double, double);
+  else if (rdt == DT_F64) DI(double, float);
+  else if (rdt == DT_F32 && vdt == DT_F64) DI(float, double);
+  else DI(float, float);
+#undef DI
+}
+
+void launch_zero_fixed_copy(const Ctx& c, const double* in, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_fixed_copy, dim3(grid1d(c.g.nn, 256, 8192)), dim3(256), 0, s, in, out, c.bits, c.g.nn);
+}
+
+void launch_finish_solution(const Ctx& c, double* T, const double* tfix, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish_solution, dim3(grid1d(c.g.nn, 256, 8192)), dim3(256), 0, s, T, tfix, c.bits, c.g.nn);
+}
+
+void launch_norm2(const Ctx& c, const double* v, int what, double rtol2, hipStream_t s) {
+  const int nb = grid1d(c.g.nn, 256, c.red_blocks);
+  hipLaunchKernelGGL(k_norm2, dim3(nb), dim3(256), 0, s, v, c.g.nn, what, rtol2, c.sc, c.partials, c.counter);
+}
+
+void launch_update_xr(const Ctx& c, double* x, double* xlo, double* r, const double* p, const double* q, hipStream_t s) {
+  const int nb = grid1d(c.g.nn, 256, c.red_blocks);
+  hipLaunchKernelGGL(k_update_xr, dim3(nb), dim3(256), 0, s, x, xlo, r, p, q, c.g.nn, c.sc, c.partials, c.counter);
+}
+
+void launch_finish_solution_dd(const Ctx& c, double* T, const double* xlo, double* tlo, const double* tfix, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish_solution_dd, dim3(grid1d(c.g.nn, 256, 8192)), dim3(256), 0, s, T, xlo, tlo, tfix, c.bits, c.g.nn);
+}
+
+void launch_update_p(const Ctx& c, double* p, const double* z, hipStream_t s) {
+  hipLaunchKernelGGL(k_update_p, dim3(grid1d(c.g.nn, 256, 8192)), dim3(256), 0, s, p, z, c.g.nn, c.sc);
+}
+
+static inline dim3 tile_block(const Ctx& c) { return dim3(c.CX * c.h.H, c.h.H); }
+// tiles are remapped per XCD (xcd_tile), which needs a multiple of 8 workgroups
+static inline dim3 tile_grid(const Ctx& c) { return dim3((unsigned)(((c.ntiles + 7) / 8) * 8)); }
+
+static inline dim3 march_grid(const Ctx& c) { return dim3((unsigned)c.mg.blocks); }
+static inline dim3 march_block() { return dim3(MX, MY); }
+
+void launch_apply(const Ctx& c, const double* x, double* y, int mode, hipStream_t s) {
+  const dim3 gr = march_grid(c), bl = march_block();
+#define AP(RT, CU) hipLaunchKernelGGL((k_apply<RT, CU>), gr, bl, 0, s, c.g, c.st, c.mg, (const RT*)c.rho, c.mat, c.bits, x, y, mode, c.sc, c.partials, c.counter)
+  if (c.rho_dt == DT_F64) { if (c.st.cubic) AP(double, true); else AP(double, false); }
+  else { if (c.st.cubic) AP(float, true); else AP(float, false); }
+#undef AP
+}
+
+void launch_residual(const Ctx& c, const double* b, const double* x, const double* xlo, double* y, bool reduce,
+                     hipStream_t s) {
+  const dim3 gr = tile_grid(c), bl = tile_block(c);
+  Scalars* sc = reduce ? c.sc : nullptr;
+#define RS(RT, CU) hipLaunchKernelGGL((k_residual<RT, CU>), gr, bl, 0, s, c.g, c.st, c.h, c.CX, (const RT*)c.rho, c.mat, c.bits, b, x, xlo, y, sc, c.partials, c.counter)
+  if (c.rho_dt == DT_F64) { if (c.st.cubic) RS(double, true); else RS(double, false); }
+  else { if (c.st.cubic) RS(float, true); else RS(float, false); }
+#undef RS
+}
+
+// --- V-cycle level 0 ---------------------------------------------------------
+
+// dispatch over (VT, RVT, BT) of the V-cycle and CUBIC
+#define VC_DISPATCH(...)                                                                          \
+  do {                                                                                             \
+    if (c.v_dt == DT_F64) {                                                                        \
+      using VT = double;                                                                           \
+      using BT = double;                                                                           \
+      if (c.rhov_dt == DT_F64) { using RVT = double; if (c.st.cubic) { constexpr bool CU = true; __VA_ARGS__; } else { constexpr bool CU = false; __VA_ARGS__; } } \
+      else { using RVT = float; if (c.st.cubic) { constexpr bool CU = true; __VA_ARGS__; } else { constexpr bool CU = false; __VA_ARGS__; } } \
+    } else {                                                                                       \
+      using VT = float;                                                                            \
+      if (c.rhov_dt == DT_BF16 && c.b_dt == DT_BF16) { using RVT = bf16; using BT = bf16; if (c.st.cubic) { constexpr bool CU = true; __VA_ARGS__; } else { constexpr bool CU = false; __VA_ARGS__; } } \
+      else if (c.rhov_dt == DT_BF16) { using RVT = bf16; using BT = float; if (c.st.cubic) { constexpr bool CU = true; __VA_ARGS__; } else { constexpr bool CU = false; __VA_ARGS__; } } \
+      else if (c.b_dt == DT_BF16) { using RVT = float; using BT = bf16; if (c.st.cubic) { constexpr bool CU = true; __VA_ARGS__; } else { constexpr bool CU = false; __VA_ARGS__; } } \
+      else { using RVT = float; using BT = float; if (c.st.cubic) { constexpr bool CU = true; __VA_ARGS__; } else { constexpr bool CU = false; __VA_ARGS__; } } \
+    }                                                                                              \
+  } while (0)
+
+// Level-0 smoother S^-1 applied to `in` (FP64 PCG residual when in_is_f64, else
+// a V-cycle vector): out = Chebyshev_d(in).  Uses vc.t0 / vc.t1 as scratch.
+void launch_smooth(const Ctx& c, const void* in, bool in_is_f64, void* out, hipStream_t s) {
+  const dim3 gr = march_grid(c), bl = march_block();
+  const int deg = c.cheb.degree;
+  VC_DISPATCH({
+    (void)sizeof(BT);
+    const VT* dinv = (const VT*)c.dinv;
+    VT* o = (VT*)out;
+    if (deg == 1) {
+      if (in_is_f64)
+        hipLaunchKernelGGL((k_cheb_first<VT, double>), dim3(grid1d(c.g.nn, 256, 8192)), dim3(256), 0, s, (const double*)in, dinv, o, (VT*)nullptr, c.g.nn, c.cheb.inv_theta, c.sc);
+      else
+        hipLaunchKernelGGL((k_cheb_first<VT, VT>), dim3(grid1d(c.g.nn, 256, 8192)), dim3(256), 0, s, (const VT*)in, dinv, o, (VT*)nullptr, c.g.nn, c.cheb.inv_theta, c.sc);
+    } else {
+      // first two steps fused; further steps ping-pong between out and t1
+      VT* d = deg > 2 ? (VT*)c.vc_t0 : nullptr;
+      VT* xa = (deg % 2 == 0) ? o : (VT*)c.vc_t1;  // so that the last step lands in `out`
+      VT* xb = (xa == o) ? (VT*)c.vc_t1 : o;
+      if (in_is_f64)
+        hipLaunchKernelGGL((k_cheb2<VT, RVT, double, CU>), gr, bl, 0, s, c.g, c.st, c.mg, (const RVT*)c.rhov, c.mat, (const double*)in, dinv, xa, d, c.cheb, c.sc);
+      else
+        hipLaunchKernelGGL((k_cheb2<VT, RVT, VT, CU>), gr, bl, 0, s, c.g, c.st, c.mg, (const RVT*)c.rhov, c.mat, (const VT*)in, dinv, xa, d, c.cheb, c.sc);
+      for (int step = 2; step < deg; ++step) {
+        const double ca = c.cheb.step_a[step], cb = c.cheb.step_b[step];
+        if (in_is_f64)
+          hipLaunchKernelGGL((k_cheb_step<VT, RVT, double, CU>), gr, bl, 0, s, c.g, c.st, c.mg, (const RVT*)c.rhov, c.mat, (const double*)in, dinv, xa, d, xb, ca, cb, c.sc);
+        else
+          hipLaunchKernelGGL((k_cheb_step<VT, RVT, VT, CU>), gr, bl, 0, s, c.g, c.st, c.mg, (const RVT*)c.rhov, c.mat, (const VT*)in, dinv, xa, d, xb, ca, cb, c.sc);
+        VT* tmp = xa; xa = xb; xb = tmp;
+      }
+    }
+  });
+}
+
+void launch_restrict(const Ctx& c, const void* r, bool r_is_f64, const void* x, void* rc, hipStream_t s) {
+  const dim3 gr = tile_grid(c), bl = tile_block(c);
+  const size_t nthr = size_t(bl.x) * bl.y;
+  VC_DISPATCH({
+    const size_t sh = nthr * c.h.Lc * sizeof(double);
+    if (r_is_f64)
+      hipLaunchKernelGGL((k_restrict<VT, RVT, BT, double, CU>), gr, bl, sh, s, c.g, c.st, c.h, c.CX, (const RVT*)c.rhov, c.mat, c.bits, (const double*)r, (const VT*)x, (const BT*)c.Rc, (double*)rc, c.sc);
+    else
+      hipLaunchKernelGGL((k_restrict<VT, RVT, BT, VT, CU>), gr, bl, sh, s, c.g, c.st, c.h, c.CX, (const RVT*)c.rhov, c.mat, c.bits, (const VT*)r, (const VT*)x, (const BT*)c.Rc, (double*)rc, c.sc);
+  });
+}
+
+void launch_prolong(const Ctx& c, const void* base, const void* e1, const void* e2, void* out, hipStream_t s) {
+  const dim3 gr = tile_grid(c), bl = tile_block(c);
+  VC_DISPATCH({
+    (void)sizeof(RVT);
+    (void)CU;
+    hipLaunchKernelGGL((k_prolong<VT, BT>), gr, bl, 0, s, c.g, c.h, c.CX, (const VT*)base, (const BT*)c.Rc, (const double*)e1, (const double*)e2, (double*)out, c.sc);
+  });
+}
+
+void launch_vresidual(const Ctx& c, const void* r, bool r_is_f64, const void* x, bool x_is_f64, void* out,
+                      hipStream_t s) {
+  const dim3 gr = march_grid(c), bl = march_block();
+  VC_DISPATCH({
+    (void)sizeof(BT);
+    if (x_is_f64) {
+      hipLaunchKernelGGL((k_vresidual<VT, RVT, double, double, CU>), gr, bl, 0, s, c.g, c.st, c.mg, (const RVT*)c.rhov, c.mat, (const VT*)c.dinv, (const double*)r, (const double*)x, (VT*)out, c.sc);
+    } else {
+      hipLaunchKernelGGL((k_vresidual<VT, RVT, double, VT, CU>), gr, bl, 0, s, c.g, c.st, c.mg, (const RVT*)c.rhov, c.mat, (const VT*)c.dinv, (const double*)r, (const VT*)x, (VT*)out, c.sc);
+    }
+    (void)r_is_f64;
+  });
+}
+
+void launch_vc_output(const Ctx& c, const void* a, bool a_is_f64, const void* b, double* z, const double* r,
+                      const double* q, int mode, hipStream_t s) {
+  const int nb = grid1d(c.g.nn, 256, c.red_blocks);
+  Scalars* sc = mode == 2 ? nullptr : c.sc;
+  if (c.v_dt == DT_F64)
+    hipLaunchKernelGGL((k_vc_output<double, double>), dim3(nb), dim3(256), 0, s, (const double*)a, (const double*)b, z, r, q, c.g.nn, mode, sc, c.partials, c.counter);
+  else if (a_is_f64)
+    hipLaunchKernelGGL((k_vc_output<double, float>), dim3(nb), dim3(256), 0, s, (const double*)a, (const float*)b, z, r, q, c.g.nn, mode, sc, c.partials, c.counter);
+  else
+    hipLaunchKernelGGL((k_vc_output<float, float>), dim3(nb), dim3(256), 0, s, (const float*)a, (const float*)b, z, r, q, c.g.nn, mode, sc, c.partials, c.counter);
+}
+
+void launch_sensitivity(const Ctx& c, const double* T, const double* lam, double* dc, hipStream_t s) {
+  const dim3 gr((unsigned)((c.g.ne + 255) / 256)), bl(256);
+  if (c.rho_dt == DT_F64)
+    hipLaunchKernelGGL((k_sensitivity<double>), gr, bl, 0, s, c.g, c.st, (const double*)c.rho, c.mat, T, lam, c.bits, dc);
+  else
+    hipLaunchKernelGGL((k_sensitivity<float>), gr, bl, 0, s, c.g, c.st, (const float*)c.rho, c.mat, T, lam, c.bits, dc);
+}
+
+void launch_element_load(const Geo& g, const double* src, double sconst, double* f, hipStream_t s) {
+  hipLaunchKernelGGL(k_element_load, dim3((unsigned)((g.nn + 255) / 256)), dim3(256), 0, s, g, src, sconst, f);
+}
+
+void launch_prolong_nodal(int nx, int ny, int nz, const double* tc, double* tf, hipStream_t s) {
+  const long long n = (2LL * nx + 1) * (2LL * ny + 1) * (2LL * nz + 1);
+  hipLaunchKernelGGL(k_prolong_nodal, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, nx, ny, nz, tc, tf);
+}
+
+void launch_prolong_element(int nx, int ny, int nz, const void* rc, void* rf, int dt, hipStream_t s) {
+  const long long n = 8LL * nx * ny * nz;
+  const dim3 gr((unsigned)((n + 255) / 256)), bl(256);
+  if (dt == DT_F64) hipLaunchKernelGGL((k_prolong_element<double>), gr, bl, 0, s, nx, ny, nz, (const double*)rc, (double*)rf);
+  else if (dt == DT_F32) hipLaunchKernelGGL((k_prolong_element<float>), gr, bl, 0, s, nx, ny, nz, (const float*)rc, (float*)rf);
+  else hipLaunchKernelGGL((k_prolong_element<uint16_t>), gr, bl, 0, s, nx, ny, nz, (const uint16_t*)rc, (uint16_t*)rf);
+}
+
+}  // namespace msmg

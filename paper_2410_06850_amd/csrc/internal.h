@@ -1,0 +1,94 @@
+// Internal declarations shared by the kernel files and the runtime.
+#pragma once
+
+#include "common.h"
+#include "march.h"
+
+namespace msmg {
+
+enum DType { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2 };
+
+constexpr int LC_MAX = 8;     // basis vectors per coarse cell (upper bound)
+constexpr int CHEB_MAX = 16;  // Chebyshev degree upper bound
+
+struct ChebCoef {
+  int degree;
+  double inv_theta;  // 1/theta
+  double c0, c1;     // fused first two steps: out = c0 z1 + c1 D^-1 (r - A z1)
+  double step_a[CHEB_MAX], step_b[CHEB_MAX];
+};
+
+// Level-1 / level-2 data layout shared with the kernels.
+struct CoarseCtx {
+  const void* Ac;        // [ncells][27][Lc][Lc]  (a_dt)
+  const void* AcDinv;    // [ncells][Lc][Lc]      (a_dt)
+  int a_dt;
+  const void* Rcc;       // per cc cell J: [Lcc][nd_J] at offset Lcc * cc_ptr[J]   (v_dt)
+  const int* cc_ptr;     // [ncc + 1] offsets of cc-local dofs
+  const int* cc_dofs;    // [n_c] global coarse dof of each cc-local dof
+  const int* dof_cc;     // [n_c] cc cell of each coarse dof
+  const int* dof_loc;    // [n_c] local index of each coarse dof in its cc cell
+  const double* AccInv;  // [n_cc][n_cc] FP64 inverse of A_cc
+  int n_c, n_cc;
+};
+
+struct Ctx {
+  Geo g;
+  Stencil st;
+  Hier h;
+  Material mat;
+  int CX;             // coarse cells per tile along x
+  long long ntiles;
+  March mg;           // plane-march decomposition of the fine stencil kernels
+  const void* rho;    // canonical density (rho_dt)
+  int rho_dt;
+  const void* rhov;   // V-cycle density copy (rhov_dt)
+  int rhov_dt;
+  const uint32_t* bits;
+  void* dinv;         // Jacobi D^-1, V-cycle type
+  int v_dt;           // V-cycle vector type
+  void* Rc;           // [nn][Lc] basis, b_dt
+  int b_dt;
+  ChebCoef cheb;
+  Scalars* sc;
+  double* partials;
+  unsigned* counter;
+  int red_blocks;
+  void* vc_t0;        // V-cycle scratch vectors (v_dt)
+  void* vc_t1;
+  CoarseCtx cc;
+};
+
+// fine level
+void launch_pack_mask(const uint8_t* mask, uint32_t* bits, long long nn, hipStream_t s);
+void launch_convert(const void* in, int din, void* out, int dout, long long n, hipStream_t s);
+void launch_diag_inv(const Ctx& c, const void* rho, int rdt, void* dinv, int vdt, hipStream_t s);
+void launch_zero_fixed_copy(const Ctx& c, const double* in, double* out, hipStream_t s);
+void launch_finish_solution(const Ctx& c, double* T, const double* tfix, hipStream_t s);
+void launch_norm2(const Ctx& c, const double* v, int what, double rtol2, hipStream_t s);
+void launch_update_xr(const Ctx& c, double* x, double* xlo, double* r, const double* p, const double* q, hipStream_t s);
+void launch_finish_solution_dd(const Ctx& c, double* T, const double* xlo, double* tlo, const double* tfix, hipStream_t s);
+void launch_update_p(const Ctx& c, double* p, const double* z, hipStream_t s);
+void launch_apply(const Ctx& c, const double* x, double* y, int mode, hipStream_t s);
+void launch_residual(const Ctx& c, const double* b, const double* x, const double* xlo, double* y, bool reduce,
+                     hipStream_t s);
+void launch_smooth(const Ctx& c, const void* in, bool in_is_f64, void* out, hipStream_t s);
+void launch_restrict(const Ctx& c, const void* r, bool r_is_f64, const void* x, void* rc, hipStream_t s);
+void launch_prolong(const Ctx& c, const void* base, const void* e1, const void* e2, void* out, hipStream_t s);
+void launch_vresidual(const Ctx& c, const void* r, bool r_is_f64, const void* x, bool x_is_f64, void* out,
+                      hipStream_t s);
+void launch_vc_output(const Ctx& c, const void* a, bool a_is_f64, const void* b, double* z, const double* r,
+                      const double* q, int mode, hipStream_t s);
+void launch_sensitivity(const Ctx& c, const double* T, const double* lam, double* dc, hipStream_t s);
+void launch_element_load(const Geo& g, const double* src, double sconst, double* f, hipStream_t s);
+void launch_prolong_nodal(int nx, int ny, int nz, const double* tc, double* tf, hipStream_t s);
+void launch_prolong_element(int nx, int ny, int nz, const void* rc, void* rf, int dt, hipStream_t s);
+
+// coarse levels (V-cycle)
+void launch_gs_sweep(const Ctx& c, const void* b, void* x, bool forward, hipStream_t s);
+void launch_ac_residual(const Ctx& c, const void* b, const void* x, void* t, hipStream_t s);
+void launch_cc_restrict(const Ctx& c, const void* t, double* rcc, hipStream_t s);
+void launch_acc_solve(const Ctx& c, const double* rcc, double* ecc, hipStream_t s);
+void launch_cc_prolong(const Ctx& c, const void* base, const double* ecc, void* out, hipStream_t s);
+
+}  // namespace msmg

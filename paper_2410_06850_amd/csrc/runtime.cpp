@@ -1,0 +1,844 @@
+// Host runtime of the MsMG library: handle, hierarchy plan, memory plan,
+// set-up orchestration, the PCG driver and the C ABI of include/msmg.h.
+//
+// The PCG loop keeps every scalar on the device; the host enqueues batches of
+// iterations and polls one small status record between batches.  Kernels of a
+// batch that start after convergence return immediately (device `done` flag).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/msmg.h"
+#include "internal.h"
+#include "setup.h"
+
+using namespace msmg;
+
+static thread_local std::string g_last_error;
+
+static int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t _e = (expr);                                                                  \
+    if (_e != hipSuccess)                                                                    \
+      return fail(MSMG_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e));             \
+  } while (0)
+
+struct msmg_handle {
+  int device = 0;
+  msmg_options opt{};
+  Geo g{};
+  Stencil st{};
+  Hier hier{};
+  int CX = 1;
+  long long ntiles = 0;
+  double lam_bound = 0.0;  // upper bound of the level-1 standard-form spectrum
+  Material mat{};
+  int rho_dt = DT_F64, rhov_dt = DT_F64, v_dt = DT_F64, b_dt = DT_F64, a_dt = DT_F64;
+  bool mg = true;
+
+  // density, mask, fixed values
+  void* rho = nullptr;
+  void* rhov = nullptr;  // may alias rho
+  uint32_t* bits = nullptr;
+  double* tfix = nullptr;
+  bool has_tfix = false;
+  void* dinv = nullptr;
+
+  // level 1 / 2
+  double* Rc64 = nullptr;
+  void* Rcs = nullptr;  // stored basis (aliases Rc64 for FP64)
+  double* Ac64 = nullptr;
+  void* Acv = nullptr;
+  double* AcDinv64 = nullptr;
+  void* AcDinvv = nullptr;
+  double* G64 = nullptr;
+  double* Rcc64 = nullptr;
+  void* Rccv = nullptr;
+  int* cc_ptr = nullptr;
+  int* cc_dofs = nullptr;
+  int* dof_cc = nullptr;
+  int* dof_loc = nullptr;
+  double* Acc = nullptr;  // becomes A_cc^-1 in place
+  double* evals = nullptr;
+  int* cell_status = nullptr;
+  double* cc_evals = nullptr;
+  int* cc_status = nullptr;
+  int n_c = 0, n_cc = 0, max_cc_dofs = 0, max_cell_nodes = 0;
+  std::vector<int> h_cc_ptr;
+
+  // PCG vectors (FP64)
+  double *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr, *b = nullptr;
+  double* xlo = nullptr;  // low part of the double-double iterate
+  // V-cycle vectors (v_dt) and coarse vectors
+  void *v_r1 = nullptr, *v_r2 = nullptr, *v_res = nullptr, *v_t0 = nullptr, *v_t1 = nullptr;
+  void *c_rc = nullptr, *c_x0 = nullptr, *c_t = nullptr, *c_x1 = nullptr, *c_d = nullptr;
+  double *rcc = nullptr, *ecc = nullptr;
+
+  Scalars* sc = nullptr;
+  Scalars* sc_host = nullptr;  // pinned
+  double* partials = nullptr;
+  unsigned* counter = nullptr;
+  int red_blocks = 4096;
+  long long partial_slots = 0;
+
+  SetupScratch scratch{};
+  bool setup_done = false;
+  double setup_ms = 0.0;
+  int eig_unconverged = 0, cc_unconverged = 0, eig_ties = 0;
+  TuneChoice tune{};
+  std::vector<void*> allocs;
+  std::vector<hipEvent_t> events;  // timing mode: 4 per timed iteration
+};
+
+static size_t dt_size(int dt) { return dt == DT_F64 ? 8 : (dt == DT_F32 ? 4 : 2); }
+
+// --------------------------------------------------------------------------
+// plan
+
+struct Plan {
+  Hier h;
+  int CX;
+  long long ntiles;
+  int n_c, n_cc, max_cell_nodes, max_cc_dofs;
+  std::vector<int> cc_ptr;  // host, ncc+1
+};
+
+static int make_plan(int nx, int ny, int nz, const msmg_options& o, Plan& P) {
+  if (nx < 1 || ny < 1 || nz < 1) return fail(MSMG_EINVAL, "mesh sizes must be positive");
+  if (o.H < 2) return fail(MSMG_EINVAL, "H must be >= 2");
+  if (o.H > 16) return fail(MSMG_EINVAL, "H must be <= 16");
+  if (nx < o.H || ny < o.H || nz < o.H) return fail(MSMG_EINVAL, "each axis needs at least H elements");
+  if (o.sd < 1) return fail(MSMG_EINVAL, "sd must be >= 1");
+  if (o.Lc < 1 || o.Lc > LC_MAX) return fail(MSMG_EINVAL, "Lc must be in 1..8");
+  if (o.Lcc < 1) return fail(MSMG_EINVAL, "Lcc must be >= 1");
+  if (o.cheb_degree < 1 || o.cheb_degree > CHEB_MAX) return fail(MSMG_EINVAL, "cheb_degree must be in 1..16");
+  if (!(o.cheb_hi > o.cheb_lo) || !(o.cheb_lo > 0.0)) return fail(MSMG_EINVAL, "need 0 < cheb_lo < cheb_hi");
+  Hier& h = P.h;
+  h.H = o.H;
+  h.ncx = nx / o.H;
+  h.ncy = ny / o.H;
+  h.ncz = nz / o.H;
+  h.ncells = h.ncx * h.ncy * h.ncz;
+  h.Lc = o.Lc;
+  h.sd = o.sd;
+  h.nccx = std::max(1, h.ncx / o.sd);
+  h.nccy = std::max(1, h.ncy / o.sd);
+  h.nccz = std::max(1, h.ncz / o.sd);
+  h.ncc = h.nccx * h.nccy * h.nccz;
+  h.Lcc = o.Lcc;
+  auto ext = [&](int c, int nc, int nn) { return cell_end(c, o.H, nc, nn) - cell_begin(c, o.H); };
+  const int mx = ext(h.ncx - 1, h.ncx, nx + 1), my = ext(h.ncy - 1, h.ncy, ny + 1), mz = ext(h.ncz - 1, h.ncz, nz + 1);
+  P.max_cell_nodes = mx * my * mz;
+  if (mx > 16 || my > 16 || mz > 16) return fail(MSMG_EINVAL, "a coarse cell exceeds 16 nodes per axis");
+  P.CX = std::max(1, 64 / o.H);
+  P.ntiles = (long long)((h.ncx + P.CX - 1) / P.CX) * h.ncy * h.ncz;
+  // cc cells: coarse dofs grouped; local order = cells of the group in x-fastest order, then l
+  P.cc_ptr.assign(h.ncc + 1, 0);
+  int maxd = 0;
+  h.max_cc_cells = 0;
+  for (int jz = 0; jz < h.nccz; ++jz)
+    for (int jy = 0; jy < h.nccy; ++jy)
+      for (int jx = 0; jx < h.nccx; ++jx) {
+        const int J = (jz * h.nccy + jy) * h.nccx + jx;
+        const int cxs = group_end(jx, h.sd, h.nccx, h.ncx) - group_begin(jx, h.sd);
+        const int cys = group_end(jy, h.sd, h.nccy, h.ncy) - group_begin(jy, h.sd);
+        const int czs = group_end(jz, h.sd, h.nccz, h.ncz) - group_begin(jz, h.sd);
+        const int ncl = cxs * cys * czs;
+        h.max_cc_cells = std::max(h.max_cc_cells, ncl);
+        P.cc_ptr[J + 1] = ncl * h.Lc;
+        maxd = std::max(maxd, ncl * h.Lc);
+      }
+  for (int J = 0; J < h.ncc; ++J) P.cc_ptr[J + 1] += P.cc_ptr[J];
+  P.n_c = h.ncells * h.Lc;
+  P.max_cc_dofs = maxd;
+  int lcc_eff = 0;
+  for (int J = 0; J < h.ncc; ++J) lcc_eff += std::min(h.Lcc, P.cc_ptr[J + 1] - P.cc_ptr[J]);
+  (void)lcc_eff;
+  if (h.Lcc > maxd) h.Lcc = maxd;
+  P.n_cc = h.ncc * h.Lcc;
+  if (P.n_cc > 40000) return fail(MSMG_EINVAL, "coarse-coarse dimension too large for the dense level-2 solve");
+  return MSMG_OK;
+}
+
+static Geo make_geo(int nx, int ny, int nz, double lx, double ly, double lz) {
+  Geo g;
+  g.nx = nx; g.ny = ny; g.nz = nz;
+  g.nnx = nx + 1; g.nny = ny + 1; g.nnz = nz + 1;
+  g.nn = (long long)g.nnx * g.nny * g.nnz;
+  g.ne = (long long)nx * ny * nz;
+  g.hx = lx / nx; g.hy = ly / ny; g.hz = lz / nz;
+  g.vol = g.hx * g.hy * g.hz;
+  return g;
+}
+
+// Unit-k element matrix entries by the set of differing coordinates:
+// K0[a][b] = wx S(dx)M(dy)M(dz) + wy M(dx)S(dy)M(dz) + wz M(dx)M(dy)S(dz),
+// S(0)=1, S(1)=-1, M(0)=1/3, M(1)=1/6, wx = hy hz / hx (etc.).
+static Stencil make_stencil(const Geo& g, double* lam_max_k0) {
+  const double wx = g.hy * g.hz / g.hx, wy = g.hx * g.hz / g.hy, wz = g.hx * g.hy / g.hz;
+  auto S = [](int d) { return d ? -1.0 : 1.0; };
+  auto M = [](int d) { return d ? 1.0 / 6.0 : 1.0 / 3.0; };
+  auto K = [&](int dx, int dy, int dz) {
+    return wx * S(dx) * M(dy) * M(dz) + wy * M(dx) * S(dy) * M(dz) + wz * M(dx) * M(dy) * S(dz);
+  };
+  Stencil st;
+  st.self = K(0, 0, 0);
+  st.ax[0] = K(1, 0, 0);
+  st.ax[1] = K(0, 1, 0);
+  st.ax[2] = K(0, 0, 1);
+  st.fd[0] = K(0, 1, 1);
+  st.fd[1] = K(1, 0, 1);
+  st.fd[2] = K(1, 1, 0);
+  st.bd = K(1, 1, 1);
+  const double sc = std::fabs(st.self);
+  st.cubic = (std::fabs(st.ax[0]) <= 1e-14 * sc && std::fabs(st.ax[1]) <= 1e-14 * sc &&
+              std::fabs(st.ax[2]) <= 1e-14 * sc) ? 1 : 0;
+  if (st.cubic) st.ax[0] = st.ax[1] = st.ax[2] = 0.0;
+  // eigenvalues of K0: tensor patterns, S has {0, 2}, M has {1/2, 1/6}
+  double lm = 0.0;
+  for (int a = 0; a < 8; ++a) {
+    const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
+    const double sx = ax ? 2.0 : 0.0, sy = ay ? 2.0 : 0.0, sz = az ? 2.0 : 0.0;
+    const double mx = ax ? 1.0 / 6.0 : 0.5, my = ay ? 1.0 / 6.0 : 0.5, mz = az ? 1.0 / 6.0 : 0.5;
+    lm = std::max(lm, wx * sx * my * mz + wy * mx * sy * mz + wz * mx * my * sz);
+  }
+  *lam_max_k0 = lm;
+  return st;
+}
+
+static ChebCoef make_cheb(const msmg_options& o) {
+  ChebCoef c{};
+  c.degree = o.cheb_degree;
+  const double theta = 0.5 * (o.cheb_hi + o.cheb_lo), delta = 0.5 * (o.cheb_hi - o.cheb_lo);
+  const double sigma = theta / delta;
+  c.inv_theta = 1.0 / theta;
+  double rho_prev = 1.0 / sigma;
+  for (int k = 1; k < o.cheb_degree; ++k) {
+    const double rho = 1.0 / (2.0 * sigma - rho_prev);
+    c.step_a[k] = rho * rho_prev;
+    c.step_b[k] = 2.0 * rho / delta;
+    if (k == 1) {
+      c.c0 = 1.0 + rho * rho_prev;
+      c.c1 = 2.0 * rho / delta;
+    }
+    rho_prev = rho;
+  }
+  return c;
+}
+
+static Ctx make_ctx(msmg_handle* h) {
+  Ctx c{};
+  c.g = h->g;
+  c.st = h->st;
+  c.h = h->hier;
+  c.mat = h->mat;
+  c.CX = h->CX;
+  c.ntiles = h->ntiles;
+  c.mg = make_march(h->g);
+  c.rho = h->rho;
+  c.rho_dt = h->rho_dt;
+  c.rhov = h->rhov;
+  c.rhov_dt = h->rhov_dt;
+  c.bits = h->bits;
+  c.dinv = h->dinv;
+  c.v_dt = h->v_dt;
+  c.Rc = h->Rcs;
+  c.b_dt = h->b_dt;
+  c.cheb = make_cheb(h->opt);
+  c.sc = h->sc;
+  c.partials = h->partials;
+  c.counter = h->counter;
+  c.red_blocks = h->red_blocks;
+  c.vc_t0 = h->v_t0;
+  c.vc_t1 = h->v_t1;
+  c.cc.Ac = h->Acv;
+  c.cc.AcDinv = h->AcDinvv;
+  c.cc.a_dt = h->a_dt;
+  c.cc.Rcc = h->Rccv;
+  c.cc.cc_ptr = h->cc_ptr;
+  c.cc.cc_dofs = h->cc_dofs;
+  c.cc.dof_cc = h->dof_cc;
+  c.cc.dof_loc = h->dof_loc;
+  c.cc.AccInv = h->Acc;
+  c.cc.n_c = h->n_c;
+  c.cc.n_cc = h->n_cc;
+  return c;
+}
+
+template <typename T>
+static int dev_alloc(msmg_handle* h, T** p, size_t bytes) {
+  void* q = nullptr;
+  if (bytes == 0) bytes = 8;
+  hipError_t e = hipMalloc(&q, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(MSMG_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+  }
+  h->allocs.push_back(q);
+  *p = reinterpret_cast<T*>(q);
+  return MSMG_OK;
+}
+
+static void free_all(msmg_handle* h) {
+  for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+  h->events.clear();
+  for (void* p : h->allocs) (void)hipFree(p);
+  h->allocs.clear();
+  if (h->sc_host) (void)hipHostFree(h->sc_host);
+  h->sc_host = nullptr;
+}
+
+#define TRY(expr)                 \
+  do {                            \
+    int _r = (expr);              \
+    if (_r != MSMG_OK) return _r; \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+extern "C" void msmg_default_options(msmg_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->H = 8;
+  o->sd = 8;
+  o->Lc = 4;
+  o->Lcc = 17;
+  o->cheb_degree = 2;
+  o->cheb_lo = 0.15;
+  o->cheb_hi = 1.5;
+  o->vcycle_dtype = MSMG_F64;
+  o->rho_v_dtype = MSMG_F64;
+  o->basis_dtype = MSMG_F64;
+  o->pc_kind = MSMG_PC_MULTIGRID;
+  o->check_interval = 8;
+  o->eig_block = 0;
+  o->eig_degree = 0;
+  o->eig_maxit = 60;
+  o->eig_tol = 1e-12;
+  o->cc_block = 0;
+  o->cc_degree = 16;
+  o->cc_maxit = 60;
+  o->autotune = 1;
+  o->tune_cache = nullptr;
+  o->timing = 0;
+}
+
+extern "C" const char* msmg_last_error(void) { return g_last_error.c_str(); }
+
+static int check_options(const msmg_options& o) {
+  if (o.vcycle_dtype != MSMG_F64 && o.vcycle_dtype != MSMG_F32) return fail(MSMG_EINVAL, "vcycle_dtype must be F64 or F32");
+  if (o.rho_v_dtype < 0 || o.rho_v_dtype > 2 || o.basis_dtype < 0 || o.basis_dtype > 2)
+    return fail(MSMG_EINVAL, "bad storage dtype");
+  if (o.vcycle_dtype == MSMG_F64 && (o.rho_v_dtype != MSMG_F64 || o.basis_dtype != MSMG_F64))
+    return fail(MSMG_EINVAL, "an FP64 cycle needs FP64 density and basis copies");
+  if (o.vcycle_dtype == MSMG_F32 && (o.rho_v_dtype == MSMG_F64 || o.basis_dtype == MSMG_F64))
+    return fail(MSMG_EINVAL, "an FP32 cycle takes F32 or BF16 density and basis copies");
+  if (o.pc_kind != MSMG_PC_MULTIGRID && o.pc_kind != MSMG_PC_SMOOTHER) return fail(MSMG_EINVAL, "bad pc_kind");
+  if (o.check_interval < 1) return fail(MSMG_EINVAL, "check_interval must be >= 1");
+  if (o.eig_block < 0 || o.eig_block > 16 || o.eig_degree < 0 || o.eig_maxit < 1 || !(o.eig_tol > 0))
+    return fail(MSMG_EINVAL, "bad eigensolver options");
+  if (o.cc_block < 0 || o.cc_block > 32 || o.cc_degree < 1 || o.cc_maxit < 1)
+    return fail(MSMG_EINVAL, "bad coarse-coarse eigensolver options");
+  return MSMG_OK;
+}
+
+extern "C" int msmg_query_plan(int nx, int ny, int nz, const msmg_options* opt, msmg_plan* out) {
+  msmg_options o;
+  if (opt) o = *opt; else msmg_default_options(&o);
+  if (!out) return fail(MSMG_EINVAL, "out is NULL");
+  TRY(check_options(o));
+  Plan P;
+  TRY(make_plan(nx, ny, nz, o, P));
+  out->ncx = P.h.ncx; out->ncy = P.h.ncy; out->ncz = P.h.ncz; out->ncells = P.h.ncells;
+  out->nccx = P.h.nccx; out->nccy = P.h.nccy; out->nccz = P.h.nccz; out->ncc = P.h.ncc;
+  out->n_c = P.n_c;
+  out->n_cc = P.n_cc;
+  out->max_cell_nodes = P.max_cell_nodes;
+  out->max_cc_dofs = P.max_cc_dofs;
+  out->nodes = (long long)(nx + 1) * (ny + 1) * (nz + 1);
+  out->elements = (long long)nx * ny * nz;
+  const long long nn = out->nodes;
+  const size_t v = o.vcycle_dtype == MSMG_F64 ? 8 : 4;
+  long long bytes = 5 * nn * 8 + 5 * nn * (long long)v + nn * (long long)v + out->elements * 8 +
+                    out->elements * (long long)dt_size(o.rho_v_dtype) + nn / 8 + nn * (long long)o.Lc * 8 +
+                    (o.basis_dtype != MSMG_F64 ? nn * (long long)o.Lc * (long long)dt_size(o.basis_dtype) : 0) +
+                    (long long)P.h.ncells * 27 * o.Lc * o.Lc * 8 * 3 + (long long)P.n_cc * P.n_cc * 8;
+  out->device_bytes = bytes;
+  return MSMG_OK;
+}
+
+extern "C" int msmg_create(msmg_handle** out, int nx, int ny, int nz, double lx, double ly, double lz,
+                           const msmg_options* opt) {
+  if (!out) return fail(MSMG_EINVAL, "handle pointer is NULL");
+  *out = nullptr;
+  if (!(lx > 0) || !(ly > 0) || !(lz > 0)) return fail(MSMG_EINVAL, "box lengths must be positive");
+  msmg_options o;
+  if (opt) o = *opt; else msmg_default_options(&o);
+  TRY(check_options(o));
+  Plan P;
+  TRY(make_plan(nx, ny, nz, o, P));
+  msmg_handle* h = new msmg_handle();
+  h->opt = o;
+  HIP_TRY(hipGetDevice(&h->device));
+  h->g = make_geo(nx, ny, nz, lx, ly, lz);
+  double lmk0 = 0.0;
+  h->st = make_stencil(h->g, &lmk0);
+  h->lam_bound = 8.0 * lmk0 / h->g.vol;
+  h->hier = P.h;
+  h->CX = P.CX;
+  h->ntiles = P.ntiles;
+  h->n_c = P.n_c;
+  h->n_cc = P.n_cc;
+  h->max_cc_dofs = P.max_cc_dofs;
+  h->max_cell_nodes = P.max_cell_nodes;
+  h->h_cc_ptr = P.cc_ptr;
+  h->mg = (o.pc_kind == MSMG_PC_MULTIGRID);
+  h->v_dt = o.vcycle_dtype;
+  h->rhov_dt = o.rho_v_dtype;
+  h->b_dt = o.basis_dtype;
+  h->a_dt = DT_F64;  // level 1 and 2 stay FP64 on every path (see the mixed-precision notes)
+  const long long nn = h->g.nn, ne = h->g.ne;
+  const size_t vs = dt_size(h->v_dt);
+  int rc = MSMG_OK;
+  auto A = [&](auto** p, size_t bytes) {
+    if (rc == MSMG_OK) rc = dev_alloc(h, p, bytes);
+  };
+  A(&h->rho, ne * 8);
+  if (h->v_dt == DT_F32) A(&h->rhov, ne * dt_size(h->rhov_dt));
+  A(&h->bits, ((nn + 31) / 32) * 4);
+  A(&h->dinv, nn * vs);
+  A(&h->r, nn * 8); A(&h->p, nn * 8); A(&h->q, nn * 8); A(&h->z, nn * 8); A(&h->b, nn * 8);
+  A(&h->xlo, nn * 8);
+  A(&h->v_r1, nn * vs); A(&h->v_res, nn * vs);
+  if (o.cheb_degree > 2) { A(&h->v_t0, nn * vs); A(&h->v_t1, nn * vs); }
+  h->partial_slots = std::max<long long>(h->ntiles + 8, 8192);
+  A(&h->partials, h->partial_slots * 2 * 8);
+  A(&h->counter, 64);
+  A(&h->sc, sizeof(Scalars));
+  if (h->mg && rc == MSMG_OK) {
+    A(&h->v_r2, nn * 8);  // prolongated iterate: FP64 on every path
+    A(&h->Rc64, nn * h->hier.Lc * 8);
+    if (h->b_dt != DT_F64) A(&h->Rcs, nn * h->hier.Lc * dt_size(h->b_dt));
+    const size_t nblk = (size_t)h->hier.ncells * 27 * h->hier.Lc * h->hier.Lc;
+    A(&h->Ac64, nblk * 8);
+    A(&h->G64, nblk * 8);
+    A(&h->AcDinv64, (size_t)h->n_c * h->hier.Lc * 8);
+    if (h->a_dt != DT_F64) {
+      A(&h->Acv, nblk * 4);
+      A(&h->AcDinvv, (size_t)h->n_c * h->hier.Lc * 4);
+    }
+    A(&h->Rcc64, (size_t)h->hier.Lcc * h->n_c * 8);
+    A(&h->cc_ptr, (h->hier.ncc + 1) * 4);
+    A(&h->cc_dofs, (size_t)h->n_c * 4);
+    A(&h->dof_cc, (size_t)h->n_c * 4);
+    A(&h->dof_loc, (size_t)h->n_c * 4);
+    A(&h->Acc, (size_t)h->n_cc * h->n_cc * 8);
+    A(&h->evals, (size_t)h->n_c * 8);
+    A(&h->cell_status, (size_t)h->hier.ncells * 4);
+    A(&h->cc_evals, (size_t)h->n_cc * 8);
+    A(&h->cc_status, (size_t)h->hier.ncc * 4);
+    A(&h->c_rc, (size_t)h->n_c * 8); A(&h->c_x0, (size_t)h->n_c * 8); A(&h->c_t, (size_t)h->n_c * 8);
+    A(&h->c_x1, (size_t)h->n_c * 8); A(&h->c_d, (size_t)h->n_c * 8);
+    A(&h->rcc, (size_t)h->n_cc * 8); A(&h->ecc, (size_t)h->n_cc * 8);
+    if (rc == MSMG_OK) rc = setup_scratch_alloc(h->g, h->hier, h->max_cc_dofs, h->opt, &h->scratch,
+                                                [&](void** p, size_t bytes) { return dev_alloc(h, p, bytes); });
+  }
+  if (rc == MSMG_OK) {
+    hipError_t e = hipHostMalloc((void**)&h->sc_host, sizeof(Scalars), hipHostMallocDefault);
+    if (e != hipSuccess) rc = fail(MSMG_ENOMEM, "pinned host allocation failed");
+  }
+  if (rc != MSMG_OK) {
+    free_all(h);
+    delete h;
+    return rc;
+  }
+  if (!h->rhov) h->rhov = h->rho;
+  if (!h->Rcs) h->Rcs = h->Rc64;
+  if (!h->Acv) h->Acv = h->Ac64;
+  if (!h->AcDinvv) h->AcDinvv = h->AcDinv64;
+  if (!h->Rccv) h->Rccv = h->Rcc64;
+  HIP_TRY(hipMemset(h->counter, 0, 64));
+  HIP_TRY(hipMemset(h->sc, 0, sizeof(Scalars)));
+  if (h->mg) {
+    // coarse-coarse dof maps (host-built, uploaded once)
+    const Hier& hh = h->hier;
+    std::vector<int> cc_dofs(h->n_c), dof_cc(h->n_c), dof_loc(h->n_c);
+    for (int jz = 0; jz < hh.nccz; ++jz)
+      for (int jy = 0; jy < hh.nccy; ++jy)
+        for (int jx = 0; jx < hh.nccx; ++jx) {
+          const int J = (jz * hh.nccy + jy) * hh.nccx + jx;
+          int d = h->h_cc_ptr[J];
+          for (int cz = group_begin(jz, hh.sd); cz < group_end(jz, hh.sd, hh.nccz, hh.ncz); ++cz)
+            for (int cy = group_begin(jy, hh.sd); cy < group_end(jy, hh.sd, hh.nccy, hh.ncy); ++cy)
+              for (int cx = group_begin(jx, hh.sd); cx < group_end(jx, hh.sd, hh.nccx, hh.ncx); ++cx) {
+                const int cell = (cz * hh.ncy + cy) * hh.ncx + cx;
+                for (int l = 0; l < hh.Lc; ++l) {
+                  const int gd = cell * hh.Lc + l;
+                  cc_dofs[d] = gd;
+                  dof_cc[gd] = J;
+                  dof_loc[gd] = d - h->h_cc_ptr[J];
+                  ++d;
+                }
+              }
+        }
+    HIP_TRY(hipMemcpy(h->cc_ptr, h->h_cc_ptr.data(), (hh.ncc + 1) * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(h->cc_dofs, cc_dofs.data(), (size_t)h->n_c * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(h->dof_cc, dof_cc.data(), (size_t)h->n_c * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(h->dof_loc, dof_loc.data(), (size_t)h->n_c * 4, hipMemcpyHostToDevice));
+  }
+  *out = h;
+  return MSMG_OK;
+}
+
+extern "C" void msmg_destroy(msmg_handle* h) {
+  if (!h) return;
+  (void)hipDeviceSynchronize();
+  free_all(h);
+  delete h;
+}
+
+static double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+extern "C" int msmg_setup(msmg_handle* h, const void* rho, msmg_dtype rho_dtype, double kmin, double kmax, int p,
+                          const uint8_t* mask, const double* fixed_values, hipStream_t s) {
+  if (!h || !rho || !mask) return fail(MSMG_EINVAL, "NULL argument");
+  if (rho_dtype != MSMG_F64 && rho_dtype != MSMG_F32) return fail(MSMG_EINVAL, "rho must be F64 or F32");
+  if (!(kmin > 0.0) || !(kmax >= kmin) || !std::isfinite(kmax)) return fail(MSMG_EINVAL, "need 0 < k_min <= k_max");
+  if (p < 1 || p > 16) return fail(MSMG_EINVAL, "p must be in 1..16");
+  const double t0 = now_ms();
+  h->setup_done = false;
+  h->mat.kmin = kmin;
+  h->mat.kmax = kmax;
+  h->mat.p = p;
+  h->rho_dt = rho_dtype;
+  const long long nn = h->g.nn, ne = h->g.ne;
+  launch_convert(rho, rho_dtype, h->rho, rho_dtype, ne, s);
+  launch_pack_mask(mask, h->bits, nn, s);
+  if (h->rhov != h->rho) launch_convert(rho, rho_dtype, h->rhov, h->rhov_dt, ne, s);
+  else h->rhov_dt = rho_dtype;
+  if (fixed_values) {
+    if (!h->tfix) TRY(dev_alloc(h, &h->tfix, nn * 8));
+    // tfix = values on fixed nodes, 0 elsewhere
+    Ctx c0 = make_ctx(h);
+    launch_convert(fixed_values, DT_F64, h->tfix, DT_F64, nn, s);
+    launch_zero_free(c0, h->tfix, s);
+    h->has_tfix = true;
+  } else {
+    h->has_tfix = false;
+  }
+  // mask must hold a fixed node (else A is singular)
+  {
+    Ctx c = make_ctx(h);
+    int nfixed = 0;
+    TRY(count_fixed(c, &nfixed, s));
+    if (nfixed == 0) return fail(MSMG_ESINGULAR, "the Dirichlet mask is empty: the operator is singular");
+  }
+  Ctx c = make_ctx(h);
+  launch_diag_inv(c, h->rho, h->rho_dt, h->dinv, h->v_dt, s);
+  HIP_TRY(hipGetLastError());
+  if (h->mg) {
+    SetupArgs a{};
+    a.lam_bound = h->lam_bound;
+    a.Rc64 = h->Rc64;
+    a.Rcs = h->Rcs;
+    a.b_dt = h->b_dt;
+    a.Ac64 = h->Ac64;
+    a.Acv = h->Acv;
+    a.AcDinv64 = h->AcDinv64;
+    a.AcDinvv = h->AcDinvv;
+    a.a_dt = h->a_dt;
+    a.G64 = h->G64;
+    a.Rcc64 = h->Rcc64;
+    a.Rccv = h->Rccv;
+    a.Acc = h->Acc;
+    a.evals = h->evals;
+    a.cell_status = h->cell_status;
+    a.cc_evals = h->cc_evals;
+    a.cc_status = h->cc_status;
+    a.n_c = h->n_c;
+    a.n_cc = h->n_cc;
+    a.max_cell_nodes = h->max_cell_nodes;
+    a.max_cc_dofs = h->max_cc_dofs;
+    a.cc_ptr = h->cc_ptr;
+    a.h_cc_ptr = h->h_cc_ptr.data();
+    a.cc_dofs = h->cc_dofs;
+    a.dof_cc = h->dof_cc;
+    a.dof_loc = h->dof_loc;
+    a.opt = &h->opt;
+    a.tune = &h->tune;
+    SetupReport rep{};
+    const int r = run_setup(c, a, &h->scratch, &rep, s);
+    if (r != MSMG_OK) return fail(r, std::string("set-up failed: ") + rep.msg);
+    h->eig_unconverged = rep.eig_unconverged;
+    h->cc_unconverged = rep.cc_unconverged;
+    h->eig_ties = rep.eig_ties;
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipGetLastError());
+  h->setup_ms = now_ms() - t0;
+  h->setup_done = true;
+  return MSMG_OK;
+}
+
+// One preconditioner application r (FP64) -> z (FP64) with the PCG reduction
+// mode (0 init, 1 iteration, 2 none).
+static void precondition(msmg_handle* h, const Ctx& c, const double* r, double* z, const double* q, int mode,
+                         hipStream_t s) {
+  const bool v64 = (h->v_dt == DT_F64);
+  if (!h->mg) {
+    launch_smooth(c, r, true, h->v_r1, s);
+    launch_vc_output(c, h->v_r1, v64, nullptr, z, r, q, mode, s);
+    return;
+  }
+  launch_smooth(c, r, true, h->v_r1, s);                            // r1 = S^-1 r0
+  launch_vresidual(c, r, true, h->v_r1, v64, h->v_res, s);          // r0 - A r1
+  launch_restrict(c, h->v_res, false, nullptr, h->c_rc, s);         // rc = R_c (r0 - A r1)
+  launch_gs_sweep(c, h->c_rc, h->c_x0, true, s);                    // rc0 = S_c^-1 rc
+  launch_ac_residual(c, h->c_rc, h->c_x0, h->c_t, s);               // rc - A_c rc0
+  launch_cc_restrict(c, h->c_t, h->rcc, s);                         // rcc = R_cc (...)
+  launch_acc_solve(c, h->rcc, h->ecc, s);                           // ecc = A_cc^-1 rcc
+  launch_cc_prolong(c, h->c_x0, h->ecc, h->c_x1, s);                // rc1 = rc0 + R_cc^T ecc
+  launch_ac_residual(c, h->c_rc, h->c_x1, h->c_t, s);               // rc - A_c rc1
+  launch_gs_sweep(c, h->c_t, h->c_d, false, s);                     // S_c^-T (...)
+  launch_prolong(c, h->v_r1, h->c_x1, h->c_d, h->v_r2, s);          // r2 = r1 + R_c^T ec (FP64)
+  launch_vresidual(c, r, true, h->v_r2, true, h->v_res, s);         // r0 - A r2
+  launch_smooth(c, h->v_res, false, h->v_r1, s);                    // S^-T (...)
+  launch_vc_output(c, h->v_r2, true, h->v_r1, z, r, q, mode, s);    // y = r2 + ...
+}
+
+static int read_scalars(msmg_handle* h, hipStream_t s) {
+  HIP_TRY(hipMemcpyAsync(h->sc_host, h->sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return MSMG_OK;
+}
+
+extern "C" int msmg_precondition(msmg_handle* h, const double* r, double* z, hipStream_t s) {
+  if (!h || !r || !z) return fail(MSMG_EINVAL, "NULL argument");
+  if (!h->setup_done) return fail(MSMG_ESTATE, "msmg_setup has not completed");
+  Ctx c = make_ctx(h);
+  launch_sc_reset(c, 0, 0, s);
+  launch_zero_fixed_copy(c, r, h->r, s);
+  precondition(h, c, h->r, z, nullptr, 2, s);
+  HIP_TRY(hipGetLastError());
+  return MSMG_OK;
+}
+
+extern "C" int msmg_apply(msmg_handle* h, const double* x, double* y, hipStream_t s) {
+  if (!h || !x || !y) return fail(MSMG_EINVAL, "NULL argument");
+  if (!h->setup_done) return fail(MSMG_ESTATE, "msmg_setup has not completed");
+  if (x == y) return fail(MSMG_EINVAL, "x and y must not alias");
+  Ctx c = make_ctx(h);
+  launch_apply(c, x, y, 2, s);
+  HIP_TRY(hipGetLastError());
+  return MSMG_OK;
+}
+
+extern "C" int msmg_sensitivity(msmg_handle* h, const double* T, const double* lam, double* dc, hipStream_t s) {
+  if (!h || !T || !dc) return fail(MSMG_EINVAL, "NULL argument");
+  if (!h->setup_done) return fail(MSMG_ESTATE, "msmg_setup has not completed");
+  Ctx c = make_ctx(h);
+  launch_sensitivity(c, T, lam, dc, s);
+  HIP_TRY(hipGetLastError());
+  return MSMG_OK;
+}
+
+extern "C" int msmg_element_load(msmg_handle* h, const double* src, double sconst, double* f, hipStream_t s) {
+  if (!h || !f) return fail(MSMG_EINVAL, "NULL argument");
+  launch_element_load(h->g, src, sconst, f, s);
+  HIP_TRY(hipGetLastError());
+  return MSMG_OK;
+}
+
+extern "C" int msmg_prolong_nodal(int nx, int ny, int nz, const double* tc, double* tf, hipStream_t s) {
+  if (nx < 1 || ny < 1 || nz < 1 || !tc || !tf) return fail(MSMG_EINVAL, "bad arguments");
+  launch_prolong_nodal(nx, ny, nz, tc, tf, s);
+  HIP_TRY(hipGetLastError());
+  return MSMG_OK;
+}
+
+extern "C" int msmg_prolong_element(int nx, int ny, int nz, const void* rc, void* rf, msmg_dtype dt, hipStream_t s) {
+  if (nx < 1 || ny < 1 || nz < 1 || !rc || !rf || dt < 0 || dt > 2) return fail(MSMG_EINVAL, "bad arguments");
+  launch_prolong_element(nx, ny, nz, rc, rf, dt, s);
+  HIP_TRY(hipGetLastError());
+  return MSMG_OK;
+}
+
+extern "C" int msmg_solve(msmg_handle* h, const double* f, double* T, double* T_lo, int use_x0, double rtol,
+                          int maxit, msmg_info* info, hipStream_t s) {
+  if (!h || !f || !T) return fail(MSMG_EINVAL, "NULL argument");
+  if (!h->setup_done) return fail(MSMG_ESTATE, "msmg_setup has not completed");
+  if (!(rtol >= 0.0) || maxit < 0) return fail(MSMG_EINVAL, "need rtol >= 0 and maxit >= 0");
+  if (f == T || (T_lo && (T_lo == T || T_lo == f))) return fail(MSMG_EINVAL, "f, T and T_lo must not alias");
+  const double t0 = now_ms();
+  Ctx c = make_ctx(h);
+  double* x = T;
+  // b = f - A t_fix on free rows (0 on fixed rows)
+  if (h->has_tfix) launch_residual(c, f, h->tfix, nullptr, h->b, false, s);
+  else launch_zero_fixed_copy(c, f, h->b, s);
+  // x: free entries of the guess (or 0), fixed entries 0 during the iteration
+  if (use_x0) launch_zero_fixed_copy(c, T, x, s);
+  else launch_fill(c, x, 0.0, s);
+  launch_fill(c, h->p, 0.0, s);
+  launch_sc_reset(c, 1, maxit, s);
+  launch_norm2(c, h->b, 0, rtol * rtol, s);  // bb, tol2
+  launch_fill(c, h->xlo, 0.0, s);
+  if (use_x0) launch_residual(c, h->b, x, nullptr, h->r, false, s);
+  else launch_copy(c, h->b, h->r, s);
+  launch_norm2(c, h->r, 1, 0.0, s);  // rr
+  TRY(read_scalars(h, s));
+  int restarts = 0;
+  int status = MSMG_OK;
+  double rel = 0.0;
+  const double bb = h->sc_host->bb;
+  if (!(bb > 0.0)) {
+    // zero right-hand side: the solution is the lift alone
+    launch_fill(c, x, 0.0, s);
+    launch_finish_solution_dd(c, T, h->xlo, T_lo, h->has_tfix ? h->tfix : nullptr, s);
+    HIP_TRY(hipStreamSynchronize(s));
+    if (info) {
+      std::memset(info, 0, sizeof(*info));
+      info->status = MSMG_OK;
+      info->solve_ms = now_ms() - t0;
+      info->setup_ms = h->setup_ms;
+      info->n_c = h->n_c;
+      info->n_cc = h->n_cc;
+    }
+    return MSMG_OK;
+  }
+  bool converged = h->sc_host->rr <= h->sc_host->tol2;
+  if (converged) rel = std::sqrt(h->sc_host->rr / bb);
+  int iters = 0;
+  int timed_total = 0;
+  if (!converged && maxit > 0) {
+    precondition(h, c, h->r, h->z, nullptr, 0, s);
+    launch_update_p(c, h->p, h->z, s);
+    const int batch = h->opt.check_interval;
+    const int max_timed = 512;
+    if (h->opt.timing && h->events.empty()) {
+      h->events.resize(4 * max_timed);
+      for (auto& e : h->events) HIP_TRY(hipEventCreate(&e));
+    }
+    int launched = 0;
+    while (true) {
+      for (int it = 0; it < batch; ++it) {
+        const bool tm = h->opt.timing && launched < max_timed;
+        if (tm) HIP_TRY(hipEventRecord(h->events[4 * launched + 0], s));
+        launch_apply(c, h->p, h->q, 1, s);
+        if (tm) HIP_TRY(hipEventRecord(h->events[4 * launched + 1], s));
+        launch_update_xr(c, x, h->xlo, h->r, h->p, h->q, s);
+        if (tm) HIP_TRY(hipEventRecord(h->events[4 * launched + 2], s));
+        precondition(h, c, h->r, h->z, h->q, 1, s);
+        if (tm) HIP_TRY(hipEventRecord(h->events[4 * launched + 3], s));
+        launch_update_p(c, h->p, h->z, s);
+        ++launched;
+      }
+      timed_total = std::min(launched, max_timed);
+      TRY(read_scalars(h, s));
+      const Scalars& S = *h->sc_host;
+      if (!S.done) continue;
+      iters = S.iters;
+      if (S.status == ST_CONV_RECURSIVE) {
+        // confirm with the true residual
+        launch_residual(c, h->b, x, h->xlo, h->q, true, s);
+        TRY(read_scalars(h, s));
+        const double trr = h->sc_host->true_rr;
+        if (trr <= h->sc_host->tol2) {
+          converged = true;
+          rel = std::sqrt(trr / bb);
+          break;
+        }
+        if (h->sc_host->iters >= maxit || restarts >= 16) {
+          status = MSMG_MAXIT;
+          rel = std::sqrt(trr / bb);
+          break;
+        }
+        // residual replacement and restart of the search direction
+        ++restarts;
+        launch_copy(c, h->q, h->r, s);
+        launch_sc_reset(c, 0, 0, s);
+        launch_fill(c, h->p, 0.0, s);
+        precondition(h, c, h->r, h->z, nullptr, 0, s);
+        launch_update_p(c, h->p, h->z, s);
+        continue;
+      }
+      status = (S.status == ST_MAXIT) ? MSMG_MAXIT : (S.status == ST_BREAKDOWN ? MSMG_BREAKDOWN : MSMG_NONFINITE);
+      launch_residual(c, h->b, x, h->xlo, h->q, true, s);
+      TRY(read_scalars(h, s));
+      rel = std::sqrt(h->sc_host->true_rr / bb);
+      break;
+    }
+  } else if (!converged) {
+    status = MSMG_MAXIT;
+    rel = std::sqrt(h->sc_host->rr / bb);
+  }
+  launch_finish_solution_dd(c, T, h->xlo, T_lo, h->has_tfix ? h->tfix : nullptr, s);
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipGetLastError());
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->status = status;
+    info->iterations = iters;
+    info->restarts = restarts;
+    info->rel_res = rel;
+    info->solve_ms = now_ms() - t0;
+    info->setup_ms = h->setup_ms;
+    info->n_c = h->n_c;
+    info->n_cc = h->n_cc;
+    info->eig_unconverged = h->eig_unconverged;
+    info->cc_unconverged = h->cc_unconverged;
+    info->eig_ties = h->eig_ties;
+    if (h->opt.timing) {
+      // iterations after convergence return at once; average over the real ones
+      const int nt = std::min(timed_total, iters);
+      double ta = 0.0, tp = 0.0;
+      for (int k = 0; k < nt; ++k) {
+        float a = 0.f, p = 0.f;
+        HIP_TRY(hipEventElapsedTime(&a, h->events[4 * k + 0], h->events[4 * k + 1]));
+        HIP_TRY(hipEventElapsedTime(&p, h->events[4 * k + 2], h->events[4 * k + 3]));
+        ta += a;
+        tp += p;
+      }
+      info->timed = nt;
+      info->apply_ms = nt ? ta / nt : 0.0;
+      info->precond_ms = nt ? tp / nt : 0.0;
+    }
+  }
+  if (status != MSMG_OK) g_last_error = "solve stopped before convergence";
+  return status;
+}
+
+extern "C" int msmg_export(msmg_handle* h, int what, void* host_out, size_t bytes) {
+  if (!h || !host_out) return fail(MSMG_EINVAL, "NULL argument");
+  if (!h->setup_done) return fail(MSMG_ESTATE, "msmg_setup has not completed");
+  if (!h->mg) return fail(MSMG_ESTATE, "no coarse spaces with the smoother-only preconditioner");
+  const Hier& hh = h->hier;
+  const void* src = nullptr;
+  size_t need = 0;
+  switch (what) {
+    case 0: src = h->evals; need = (size_t)h->n_c * 8; break;
+    case 1: src = h->Rc64; need = (size_t)h->g.nn * hh.Lc * 8; break;
+    case 2: src = h->Ac64; need = (size_t)hh.ncells * 27 * hh.Lc * hh.Lc * 8; break;
+    case 3: src = h->cc_evals; need = (size_t)h->n_cc * 8; break;
+    case 4: src = h->scratch.acc_copy; need = (size_t)h->n_cc * h->n_cc * 8; break;
+    case 5: src = h->cell_status; need = (size_t)hh.ncells * 4; break;
+    default: return fail(MSMG_EINVAL, "unknown export id");
+  }
+  if (bytes < need) return fail(MSMG_EINVAL, "output buffer too small: need " + std::to_string(need) + " bytes");
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(host_out, src, need, hipMemcpyDeviceToHost));
+  return MSMG_OK;
+}

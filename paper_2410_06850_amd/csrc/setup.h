@@ -1,0 +1,91 @@
+// Set-up of the coarse spaces (paper section 3): per-cell spectral problems
+// eq. (spepb), Galerkin coarse operators, coarse-coarse spectral problems
+// eq. (spectral cc), the coarse-coarse operator and its inverse.
+#pragma once
+
+#include <functional>
+
+#include "../../include/msmg.h"
+#include "internal.h"
+
+namespace msmg {
+
+// Launch shape of the level-1 eigensolver chosen by the tuner.
+struct TuneChoice {
+  int valid;
+  int bs;       // threads per block
+  int m;        // subspace block size
+  int degree;   // filter degree
+  int blocks_per_cu;
+  double ms;    // measured time of the tuned launch
+};
+
+struct SetupScratch {
+  // coarse-coarse subspace iteration, vectors laid out per cc cell as [m][nd_J]
+  double* Y = nullptr;   // current block
+  double* Yp = nullptr;  // previous block (filter recurrence)
+  double* Z = nullptr;   // operator image / next block
+  double* small = nullptr;  // per cc cell: 3 matrices of mcc x mcc
+  double* ccpar = nullptr;  // per cc cell filter parameters
+  int* ccflag = nullptr;    // per cc cell: converged iteration or -1
+  double* acc_copy = nullptr;  // A_cc before inversion (diagnostics)
+  double* gj = nullptr;        // Gauss-Jordan panels (batched)
+  double* Gd = nullptr;        // dense shifted coarse-coarse matrices, then their inverses
+  unsigned* work = nullptr;    // work-queue counter
+  int mcc = 0;
+};
+
+struct SetupArgs {
+  double lam_bound;
+  double* Rc64;
+  void* Rcs;
+  int b_dt;
+  double* Ac64;
+  void* Acv;
+  double* AcDinv64;
+  void* AcDinvv;
+  int a_dt;
+  double* G64;
+  double* Rcc64;
+  void* Rccv;
+  double* Acc;
+  double* evals;
+  int* cell_status;
+  double* cc_evals;
+  int* cc_status;
+  int n_c, n_cc;
+  int max_cell_nodes;
+  int max_cc_dofs;
+  const int* cc_ptr;
+  const int* h_cc_ptr;
+  const int* cc_dofs;
+  const int* dof_cc;
+  const int* dof_loc;
+  const msmg_options* opt;
+  TuneChoice* tune;
+};
+
+struct SetupReport {
+  int eig_unconverged;
+  int cc_unconverged;
+  int eig_ties;
+  char msg[256];
+};
+
+int setup_scratch_alloc(const Geo& g, const Hier& h, int max_cc_dofs, const msmg_options& o, SetupScratch* s,
+                        const std::function<int(void**, size_t)>& alloc);
+
+int run_setup(const Ctx& c, const SetupArgs& a, SetupScratch* s, SetupReport* rep, hipStream_t st);
+
+// level-1 eigensolver launch (used by the tuner and the set-up)
+int launch_local_eigen(const Ctx& c, const SetupArgs& a, SetupScratch* s, int bs, int m, int degree,
+                       int blocks, hipStream_t st);
+
+// utilities implemented with the fine kernels
+void launch_fill(const Ctx& c, double* x, double v, hipStream_t s);
+void launch_copy(const Ctx& c, const double* a, double* b, hipStream_t s);
+void launch_zero_free(const Ctx& c, double* x, hipStream_t s);
+void launch_sc_reset(const Ctx& c, int full, int maxit, hipStream_t s);
+int count_fixed(const Ctx& c, int* nfixed, hipStream_t s);
+
+}  // namespace msmg

@@ -1,0 +1,976 @@
+// Coarse set-up kernels (paper section 3):
+//   * Galerkin blocks A_c = R_c A R_c^T (and the coarse-coarse stiffness
+//     R_c K^cc R_c^T that keeps only elements inside one coarse-coarse cell),
+//     computed by colouring the coarse cells modulo 3 so that one pass per
+//     colour class yields one neighbour block of every cell;
+//   * diagonal-block inverses of A_c for block Gauss-Seidel;
+//   * a batched Chebyshev-filtered subspace iteration for the standard
+//     coarse-coarse eigenproblems of eq. (spectral cc), vectors in HBM;
+//   * A_cc = R_cc A_c R_cc^T and its in-place Gauss-Jordan inverse (SPD, no
+//     pivoting) used as the direct coarse-coarse solve.
+#include "eig_common.h"
+#include "setup.h"
+
+#include <algorithm>
+#include <vector>
+
+namespace msmg {
+
+int gj_inverse(int n, int batch, double* A, double* P, double* Rb, double* Cb, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Galerkin blocks.  For colour class q = (qx,qy,qz) in {0,1,2}^3 every cell j
+// has exactly one neighbour cell i (offset in {-1,0,1}^3) with i = q mod 3; the
+// pass computes  out[j][block(j->i)][a][b] = sum_{n in j} R[n][a] (A phi_i^b)(n)
+// where phi_i^b is basis vector b of cell i.  With drop_cc, elements whose
+// nodes belong to two coarse-coarse cells are left out of A.
+template <typename BT, int LT>
+__global__ void k_galerkin(Geo g, Stencil st, Hier h, int CX, const void* rho, int rho_dt, Material mat,
+                           const BT* __restrict__ R, int qx, int qy, int qz, int drop_cc, double* __restrict__ out) {
+  extern __shared__ double smem[];
+  const long long tile = xcd_tile(blockIdx.x, gridDim.x);
+  const Tile t = tile_of_thread(g, h, CX, tile);
+  const int H = h.H;
+  double acc[LT][LT];
+#pragma unroll
+  for (int a = 0; a < LT; ++a)
+#pragma unroll
+    for (int b = 0; b < LT; ++b) acc[a][b] = 0.0;
+  const double dk = mat.kmax - mat.kmin;
+  int bidx = 13;
+  if (t.active) {
+    auto off3 = [](int c, int q) {
+      const int d = ((q - c) % 3 + 3) % 3;
+      return d == 0 ? 0 : (d == 1 ? 1 : -1);
+    };
+    const int ox = off3(t.cx, qx), oy = off3(t.cy, qy), oz = off3(t.cz, qz);
+    bidx = (oz + 1) * 9 + (oy + 1) * 3 + (ox + 1);
+    const int icx = t.cx + ox, icy = t.cy + oy, icz = t.cz + oz;
+    const bool exists = icx >= 0 && icx < h.ncx && icy >= 0 && icy < h.ncy && icz >= 0 && icz < h.ncz;
+    if (exists) {
+      for (int k = t.zs; k < t.ze; ++k)
+        for (int j = t.ys; j < t.ye; ++j)
+          for (int i = t.xs; i < t.xe; ++i) {
+            const long long n = node_id(g, i, j, k);
+            double kk[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+              const int ei = i - 1 + (c & 1), ej = j - 1 + ((c >> 1) & 1), ek = k - 1 + ((c >> 2) & 1);
+              bool in = ei >= 0 && ei < g.nx && ej >= 0 && ej < g.ny && ek >= 0 && ek < g.nz;
+              if (in && drop_cc) {
+                const int gx0 = group_axis(owner_axis(ei, H, h.ncx), h.sd, h.nccx), gx1 = group_axis(owner_axis(ei + 1, H, h.ncx), h.sd, h.nccx);
+                const int gy0 = group_axis(owner_axis(ej, H, h.ncy), h.sd, h.nccy), gy1 = group_axis(owner_axis(ej + 1, H, h.ncy), h.sd, h.nccy);
+                const int gz0 = group_axis(owner_axis(ek, H, h.ncz), h.sd, h.nccz), gz1 = group_axis(owner_axis(ek + 1, H, h.ncz), h.sd, h.nccz);
+                in = (gx0 == gx1) && (gy0 == gy1) && (gz0 == gz1);
+              }
+              if (in) {
+                const long long e = elem_id(g, ei, ej, ek);
+                const double r = rho_dt == DT_F64 ? ((const double*)rho)[e] : double(((const float*)rho)[e]);
+                kk[c] = conductivity<double>(r, mat.kmin, dk, mat.p);
+              } else {
+                kk[c] = 0.0;
+              }
+            }
+            double w[27];
+            stencil27(st, kk, w);
+            double wb[LT];
+#pragma unroll
+            for (int b = 0; b < LT; ++b) wb[b] = 0.0;
+#pragma unroll
+            for (int o = 0; o < 27; ++o) {
+              const int mx = i + o % 3 - 1, my = j + (o / 3) % 3 - 1, mz = k + o / 9 - 1;
+              if (mx < 0 || mx >= g.nnx || my < 0 || my >= g.nny || mz < 0 || mz >= g.nnz) continue;
+              if (owner_axis(mx, H, h.ncx) != icx || owner_axis(my, H, h.ncy) != icy || owner_axis(mz, H, h.ncz) != icz) continue;
+              const long long m = node_id(g, mx, my, mz);
+#pragma unroll
+              for (int b = 0; b < LT; ++b) wb[b] += w[o] * ld<double, BT>(R, m * LT + b);
+            }
+#pragma unroll
+            for (int a = 0; a < LT; ++a) {
+              const double ra = ld<double, BT>(R, n * LT + a);
+#pragma unroll
+              for (int b = 0; b < LT; ++b) acc[a][b] += ra * wb[b];
+            }
+          }
+    }
+  }
+  // per-cell sums, one (a, b) entry at a time, fixed order
+  const int nthr = blockDim.x * blockDim.y;
+  const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+  const int ntx = (h.ncx + CX - 1) / CX;
+  const int tx = int(tile % ntx), ty = int((tile / ntx) % h.ncy), tz = int(tile / ((long long)ntx * h.ncy));
+  for (int a = 0; a < LT; ++a)
+    for (int b = 0; b < LT; ++b) {
+      double v = 0.0;
+#pragma unroll
+      for (int aa = 0; aa < LT; ++aa)
+#pragma unroll
+        for (int bb = 0; bb < LT; ++bb)
+          if (aa == a && bb == b) v = acc[aa][bb];
+      smem[tid] = v;
+      __syncthreads();
+      if (tid < CX) {
+        const int cx = tx * CX + tid;
+        if (cx < h.ncx && tz < h.ncz) {
+          double s = 0.0;
+          for (int ly = 0; ly < (int)blockDim.y; ++ly)
+            for (int lx = tid * H; lx < (tid + 1) * H; ++lx) s += smem[ly * blockDim.x + lx];
+          const long long cell = ((long long)tz * h.ncy + ty) * h.ncx + cx;
+          // this thread's cell shares the colour offset computed from its coordinates
+          const int ox = (((qx - cx) % 3 + 3) % 3), oy = (((qy - ty) % 3 + 3) % 3), oz = (((qz - tz) % 3 + 3) % 3);
+          const int bx = ox == 0 ? 1 : (ox == 1 ? 2 : 0), by = oy == 0 ? 1 : (oy == 1 ? 2 : 0), bz = oz == 0 ? 1 : (oz == 1 ? 2 : 0);
+          const int bi = bz * 9 + by * 3 + bx;
+          out[((cell * 27 + bi) * LT + a) * LT + b] = s;
+        }
+      }
+      __syncthreads();
+    }
+  (void)bidx;
+}
+
+// Diagonal-block inverses of A_c.  Padded basis slots (zero rows) get a unit
+// diagonal first so every block is invertible; they stay decoupled.
+__global__ void k_block_inverse(int ncells, int L, double* __restrict__ Ac, double* __restrict__ Dinv) {
+  const long long cell = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (cell >= ncells) return;
+  double a[LC_MAX][2 * LC_MAX];
+  double* blk = Ac + (cell * 27 + 13) * L * L;
+  for (int r = 0; r < L; ++r) {
+    bool zero = true;
+    for (int c = 0; c < L; ++c) zero = zero && (blk[r * L + c] == 0.0);
+    if (zero) blk[r * L + r] = 1.0;
+  }
+  for (int r = 0; r < L; ++r)
+    for (int c = 0; c < 2 * L; ++c) a[r][c] = (c < L) ? blk[r * L + c] : (c - L == r ? 1.0 : 0.0);
+  // Gauss-Jordan without pivoting (the block is SPD)
+  for (int k = 0; k < L; ++k) {
+    const double piv = 1.0 / a[k][k];
+    for (int c = 0; c < 2 * L; ++c) a[k][c] *= piv;
+    for (int r = 0; r < L; ++r) {
+      if (r == k) continue;
+      const double f = a[r][k];
+      for (int c = 0; c < 2 * L; ++c) a[r][c] -= f * a[k][c];
+    }
+  }
+  for (int r = 0; r < L; ++r)
+    for (int c = 0; c < L; ++c) Dinv[(cell * L + r) * L + c] = a[r][L + c];
+}
+
+// ---------------------------------------------------------------------------
+// Coarse-coarse subspace iteration.  Per cc cell J the operator is the block
+// of G = R_c K^cc R_c^T on J's coarse dofs; vectors of J are stored as
+// [mcc][nd_J] at offset mcc * cc_ptr[J].  Padded coarse dofs (beyond a cell's
+// basis size) are kept at zero, which restricts the problem to real dofs.
+
+struct CCArgs {
+  Hier h;
+  int m;                 // block size
+  const double* G;       // [ncells][27][Lc][Lc]
+  const int* cc_ptr;
+  const int* cc_dofs;
+  const int* dof_cc;
+  const int* dof_loc;
+  const int* cell_status;  // basis size of each cell in bits 20-27
+};
+
+MSMG_DEV bool dof_valid(const CCArgs& a, long long d) {
+  const int L = a.h.Lc;
+  const int cell = int(d / L), l = int(d % L);
+  return l < ((a.cell_status[cell] >> 20) & 0xff);
+}
+
+// start block: cos products over the cc cell (evaluated at coarse-cell centres)
+// on basis slot 0 plus a small deterministic perturbation on all valid slots
+__global__ void k_cc_start(CCArgs a, double* __restrict__ Y) {
+  const long long d = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const Hier& h = a.h;
+  if (d >= (long long)h.ncells * h.Lc) return;
+  const int J = a.dof_cc[d], loc = a.dof_loc[d];
+  const int d0 = a.cc_ptr[J], nd = a.cc_ptr[J + 1] - d0;
+  const int cell = int(d / h.Lc), l = int(d % h.Lc);
+  const int cx = cell % h.ncx, cy = (cell / h.ncx) % h.ncy, cz = cell / (h.ncx * h.ncy);
+  const int jx = J % h.nccx, jy = (J / h.nccx) % h.nccy, jz = J / (h.nccx * h.nccy);
+  const int gx0 = group_begin(jx, h.sd), gx1 = group_end(jx, h.sd, h.nccx, h.ncx);
+  const int gy0 = group_begin(jy, h.sd), gy1 = group_end(jy, h.sd, h.nccy, h.ncy);
+  const int gz0 = group_begin(jz, h.sd), gz1 = group_end(jz, h.sd, h.nccz, h.ncz);
+  const double ux = (cx - gx0 + 0.5) / (gx1 - gx0), uy = (cy - gy0 + 0.5) / (gy1 - gy0), uz = (cz - gz0 + 0.5) / (gz1 - gz0);
+  const bool ok = dof_valid(a, d);
+  for (int j = 0; j < a.m; ++j) {
+    // shells of (p, q, r) frequencies
+    const int pq[20][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1},
+                           {1, 1, 1}, {2, 0, 0}, {0, 2, 0}, {0, 0, 2}, {2, 1, 0}, {1, 2, 0}, {2, 0, 1},
+                           {0, 2, 1}, {1, 0, 2}, {0, 1, 2}, {2, 1, 1}, {1, 2, 1}, {1, 1, 2}};
+    const int s = j % 20;
+    double v = cos(M_PI * pq[s][0] * ux) * cos(M_PI * pq[s][1] * uy) * cos(M_PI * pq[s][2] * uz);
+    v = (l == 0 ? v : 0.0);
+    unsigned x = unsigned(d) * 2654435761u + unsigned(j) * 40503u + 12345u;
+    x ^= x >> 16; x *= 0x7feb352dU; x ^= x >> 15; x *= 0x846ca68bU; x ^= x >> 16;
+    v += 0.05 * (double(x) * (1.0 / 4294967296.0) - 0.5);
+    Y[(long long)a.m * d0 + (long long)j * nd + loc] = ok ? v : 0.0;
+  }
+}
+
+// Z = G Y (all cc cells), optionally fused with the filter recurrence:
+//   mode 0: Z = G Y
+//   mode 1: Z = (G Y - c Y) * s1                      (first filter step, X unused)
+//   mode 2: Z = (G Y - c Y) * s1 - s2 * X             (later filter steps)
+// with per-cc-cell coefficients par[J*8 + {c, s1, s2}].
+__global__ void k_cc_spmm(CCArgs a, const double* __restrict__ Y, const double* __restrict__ X, double* __restrict__ Z,
+                          int mode, const double* __restrict__ par, const int* __restrict__ flag) {
+  const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const Hier& h = a.h;
+  const int L = h.Lc;
+  const long long ndof = (long long)h.ncells * L;
+  if (gid >= ndof * a.m) return;
+  const long long d = gid % ndof;
+  const int j = int(gid / ndof);
+  const int J = a.dof_cc[d];
+  if (flag && flag[J] >= 0) return;  // converged cc cell: leave untouched
+  const int loc = a.dof_loc[d];
+  const int d0 = a.cc_ptr[J], nd = a.cc_ptr[J + 1] - d0;
+  const double* Yj = Y + (long long)a.m * d0 + (long long)j * nd;
+  const long long out_i = (long long)a.m * d0 + (long long)j * nd + loc;
+  if (!dof_valid(a, d)) {
+    Z[out_i] = 0.0;
+    return;
+  }
+  const int cell = int(d / L), l = int(d % L);
+  const int cx = cell % h.ncx, cy = (cell / h.ncx) % h.ncy, cz = cell / (h.ncx * h.ncy);
+  const double* Gr = a.G + (long long)cell * 27 * L * L;
+  double s = 0.0;
+  for (int b = 0; b < 27; ++b) {
+    const int x = cx + b % 3 - 1, y = cy + (b / 3) % 3 - 1, z = cz + b / 9 - 1;
+    if (x < 0 || x >= h.ncx || y < 0 || y >= h.ncy || z < 0 || z >= h.ncz) continue;
+    const long long nc = ((long long)z * h.ncy + y) * h.ncx + x;
+    if (a.dof_cc[nc * L] != J) continue;
+    const int nloc0 = a.dof_loc[nc * L];
+    for (int m = 0; m < L; ++m) s += Gr[(b * L + l) * L + m] * Yj[nloc0 + m];
+  }
+  if (mode == 0) {
+    Z[out_i] = s;
+  } else {
+    const double c = par[J * 8 + 0], s1 = par[J * 8 + 1], s2 = par[J * 8 + 2];
+    if (s1 < 0.0) {  // this cell's filter degree is exhausted: carry the block forward
+      Z[out_i] = Yj[loc];
+      return;
+    }
+    double v = (s - c * Yj[loc]) * s1;
+    if (mode == 2) v -= s2 * X[out_i];
+    Z[out_i] = v;
+  }
+}
+
+// S_J = P_J^T Q_J (m x m per cc cell) -> small[J][which]
+__global__ void k_cc_gram(CCArgs a, const double* __restrict__ P, const double* __restrict__ Q, double* __restrict__ small,
+                          int which, const int* __restrict__ flag) {
+  const int J = blockIdx.x;
+  if (flag && flag[J] >= 0) return;
+  const int m = a.m;
+  const int d0 = a.cc_ptr[J], nd = a.cc_ptr[J + 1] - d0;
+  const double* PJ = P + (long long)m * d0;
+  const double* QJ = Q + (long long)m * d0;
+  double* S = small + ((long long)J * 4 + which) * m * m;
+  for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+    const int i = e / m, j = e % m;
+    if (j < i) continue;
+    double s = 0.0;
+    for (int d = 0; d < nd; ++d) s += PJ[(long long)i * nd + d] * QJ[(long long)j * nd + d];
+    S[i * m + j] = s;
+    S[j * m + i] = s;
+  }
+}
+
+// Per cc cell: eigen-decomposition of small[J][which] (m x m).
+//   kind 0 (orthonormalise): C = U S^-1/2 -> small[J][2]
+//   kind 1 (Rayleigh-Ritz):  C = U (ascending) -> small[J][2], Ritz values -> ritz[J][:]
+__global__ void k_cc_small_eig(CCArgs a, double* __restrict__ small, int which, int kind, double* __restrict__ ritz,
+                               const int* __restrict__ flag) {
+  extern __shared__ double sm[];
+  const int J = blockIdx.x;
+  if (flag && flag[J] >= 0) return;
+  const int m = a.m;
+  double* A = sm;
+  double* V = A + m * m;
+  double* B = V + m * m;
+  double* Vs = B + m * m;
+  double* ev = Vs + m * m;
+  double* red = ev + m;
+  int* perm = reinterpret_cast<int*>(red + 64);
+  const double* S = small + ((long long)J * 4 + which) * m * m;
+  for (int e = threadIdx.x; e < m * m; e += blockDim.x) A[e] = S[e];
+  __syncthreads();
+  block_jacobi(A, V, B, Vs, ev, perm, m, red);
+  double* C = small + ((long long)J * 4 + 2) * m * m;
+  for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+    const int k = e % m;
+    if (kind == 0) C[e] = ev[k] > 1e-300 ? Vs[e] / sqrt(ev[k]) : 0.0;
+    else C[e] = Vs[e];
+  }
+  if (kind == 1)
+    for (int k = threadIdx.x; k < m; k += blockDim.x) ritz[(long long)J * m + k] = ev[k];
+}
+
+// Q = P C per cc cell (C = small[J][2])
+__global__ void k_cc_transform(CCArgs a, const double* __restrict__ P, double* __restrict__ Q, const double* __restrict__ small,
+                               const int* __restrict__ flag) {
+  const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const Hier& h = a.h;
+  const long long ndof = (long long)h.ncells * h.Lc;
+  if (gid >= ndof * a.m) return;
+  const long long d = gid % ndof;
+  const int j = int(gid / ndof);
+  const int J = a.dof_cc[d];
+  if (flag && flag[J] >= 0) return;
+  const int m = a.m;
+  const int loc = a.dof_loc[d];
+  const int d0 = a.cc_ptr[J], nd = a.cc_ptr[J + 1] - d0;
+  const double* C = small + ((long long)J * 4 + 2) * m * m;
+  const double* PJ = P + (long long)m * d0;
+  double s = 0.0;
+  for (int i = 0; i < m; ++i) s += PJ[(long long)i * nd + loc] * C[i * m + j];
+  Q[(long long)m * d0 + (long long)j * nd + loc] = s;
+}
+
+// Residual check and filter parameters per cc cell (one block per J).
+// X Ritz block, Z = G X, ritz values.  Converged when every wanted residual
+// ||Z_j - theta_j X_j|| <= tol * bound.  Sets flag[J] = iteration when done.
+__global__ void k_cc_check(CCArgs a, const double* __restrict__ X, const double* __restrict__ Z,
+                           const double* __restrict__ ritz, double* __restrict__ par, int* __restrict__ flag,
+                           const double* __restrict__ bound, int Lwant, double tol, int iter, int last, int degree) {
+  __shared__ double red[64];
+  __shared__ double worst_s;
+  const int J = blockIdx.x;
+  if (flag[J] >= 0) return;
+  const int m = a.m;
+  const int d0 = a.cc_ptr[J], nd = a.cc_ptr[J + 1] - d0;
+  const int lw = min(Lwant, nd);
+  const double* XJ = X + (long long)m * d0;
+  const double* ZJ = Z + (long long)m * d0;
+  const double* th = ritz + (long long)J * m;
+  if (threadIdx.x == 0) worst_s = 0.0;
+  __syncthreads();
+  for (int j = 0; j < lw; ++j) {
+    double s = 0.0;
+    for (int d = threadIdx.x; d < nd; d += blockDim.x) {
+      const double r = ZJ[(long long)j * nd + d] - th[j] * XJ[(long long)j * nd + d];
+      s += r * r;
+    }
+    s = block_allsum(s, red);
+    if (threadIdx.x == 0) worst_s = fmax(worst_s, s);
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double b = bound[J];
+  if (worst_s <= (tol * b) * (tol * b)) {
+    flag[J] = iter;
+    return;
+  }
+  if (last) {
+    flag[J] = -2 - iter;  // not converged (kept as is)
+    return;
+  }
+  // filter interval [a_lo, b], scale point a_min
+  double lo = th[m - 1];
+  if (!(lo < 0.95 * b)) lo = 0.95 * b;
+  const double e = 0.5 * (b - lo), c = 0.5 * (b + lo);
+  double amin = th[0];
+  if (!(amin < lo - 1e-3 * e)) amin = lo - 1e-3 * e;
+  const double xs = (c - amin) / e;
+  int deg = degree;
+  if (xs > 1.0) deg = max(2, min(deg, int(14.5 / acosh(xs))));
+  par[J * 8 + 0] = c;
+  par[J * 8 + 3] = e;
+  par[J * 8 + 4] = e / (amin - c);  // sigma_1
+  par[J * 8 + 5] = double(deg);
+}
+
+// Per-step filter coefficients: step 1: s1 = sigma1/e; step k: sigma_new = 1/(2/sigma1 - sigma),
+// s1 = 2 sigma_new / e, s2 = sigma sigma_new.  par[6] carries sigma.
+__global__ void k_cc_filter_coef(int ncc, double* __restrict__ par, int step, const int* __restrict__ flag) {
+  const int J = blockIdx.x * blockDim.x + threadIdx.x;
+  if (J >= ncc || flag[J] >= 0) return;
+  double* p = par + J * 8;
+  const double e = p[3], s1_ = p[4];
+  if (step == 1) {
+    p[1] = s1_ / e;
+    p[2] = 0.0;
+    p[6] = s1_;
+  } else {
+    const double sigma = p[6];
+    const double sn = 1.0 / (2.0 / s1_ - sigma);
+    if (step > int(p[5])) {
+      p[1] = -1.0;
+      return;
+    }
+    p[1] = 2.0 * sn / e;
+    p[2] = sigma * sn;
+    p[6] = sn;
+  }
+}
+
+// Gershgorin bound of each cc operator (max over rows of sum |G_ij|)
+__global__ void k_cc_bound(CCArgs a, double* __restrict__ bound) {
+  __shared__ double red[64];
+  const int J = blockIdx.x;
+  const Hier& h = a.h;
+  const int L = h.Lc;
+  const int d0 = a.cc_ptr[J], nd = a.cc_ptr[J + 1] - d0;
+  double mx = 0.0;
+  for (int q = threadIdx.x; q < nd; q += blockDim.x) {
+    const long long d = a.cc_dofs[d0 + q];
+    if (!dof_valid(a, d)) continue;
+    const int cell = int(d / L), l = int(d % L);
+    const int cx = cell % h.ncx, cy = (cell / h.ncx) % h.ncy, cz = cell / (h.ncx * h.ncy);
+    double s = 0.0;
+    for (int b = 0; b < 27; ++b) {
+      const int x = cx + b % 3 - 1, y = cy + (b / 3) % 3 - 1, z = cz + b / 9 - 1;
+      if (x < 0 || x >= h.ncx || y < 0 || y >= h.ncy || z < 0 || z >= h.ncz) continue;
+      for (int m = 0; m < L; ++m) s += fabs(a.G[(((long long)cell * 27 + b) * L + l) * L + m]);
+    }
+    mx = fmax(mx, s);
+  }
+  mx = block_allmax(mx, red);
+  if (threadIdx.x == 0) bound[J] = mx * 1.0001 + 1e-300;
+}
+
+// Final R_cc rows: sign-normalised Ritz vectors 0..Lcc-1 of each cc cell.
+// Rcc layout: [J][b][nd_J] at offset Lcc * cc_ptr[J].  Sign: sum of entries > 0,
+// else the first entry of largest magnitude positive.
+__global__ void k_cc_finish(CCArgs a, const double* __restrict__ X, const double* __restrict__ ritz, double* __restrict__ Rcc,
+                            double* __restrict__ cc_evals, int Lcc) {
+  __shared__ double red[64];
+  __shared__ int ired[16];
+  const int J = blockIdx.x;
+  const int m = a.m;
+  const int d0 = a.cc_ptr[J], nd = a.cc_ptr[J + 1] - d0;
+  const double* XJ = X + (long long)m * d0;
+  for (int b = 0; b < Lcc; ++b) {
+    const bool have = b < nd && b < m;
+    double s = 0.0, ss = 0.0;
+    if (have)
+      for (int d = threadIdx.x; d < nd; d += blockDim.x) s += XJ[(long long)b * nd + d];
+    s = block_allsum(s, red);
+    (void)ss;
+    double sgn = s > 0.0 ? 1.0 : -1.0;
+    if (have && !(fabs(s) > 1e-8 * sqrt(double(nd)))) {
+      double amax = 0.0;
+      for (int d = threadIdx.x; d < nd; d += blockDim.x) amax = fmax(amax, fabs(XJ[(long long)b * nd + d]));
+      amax = block_allmax(amax, red);
+      int first = 1 << 30;
+      for (int d = threadIdx.x; d < nd; d += blockDim.x)
+        if (fabs(XJ[(long long)b * nd + d]) >= (1.0 - 1e-8) * amax) first = min(first, d);
+      first = block_allmin_int(first, ired);
+      sgn = XJ[(long long)b * nd + first] > 0.0 ? 1.0 : -1.0;
+    }
+    for (int d = threadIdx.x; d < nd; d += blockDim.x)
+      Rcc[(long long)Lcc * d0 + (long long)b * nd + d] = have ? sgn * XJ[(long long)b * nd + d] : 0.0;
+    if (threadIdx.x == 0) cc_evals[(long long)J * Lcc + b] = have ? ritz[(long long)J * m + b] : 0.0;
+    __syncthreads();
+  }
+}
+
+// Q = P on the active cc cells
+__global__ void k_cc_transform_copy(CCArgs a, const double* __restrict__ P, double* __restrict__ Q, const int* __restrict__ flag) {
+  const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const Hier& h = a.h;
+  const long long ndof = (long long)h.ncells * h.Lc;
+  if (gid >= ndof * a.m) return;
+  const long long d = gid % ndof;
+  const int j = int(gid / ndof);
+  const int J = a.dof_cc[d];
+  if (flag && flag[J] >= 0) return;
+  const int loc = a.dof_loc[d];
+  const int d0 = a.cc_ptr[J], nd = a.cc_ptr[J + 1] - d0;
+  const long long i = (long long)a.m * d0 + (long long)j * nd + loc;
+  Q[i] = P[i];
+}
+
+// Small coarse-coarse cells (nd <= 32): assemble G_J densely and diagonalise it.
+// Padded dofs get a huge decoupled diagonal so they sort last.  Writes the
+// Ritz block X (first min(m, nd) rows) and values, and marks the cell done.
+constexpr int CC_DENSE = 32;
+__global__ void k_cc_dense(CCArgs a, double* __restrict__ X, double* __restrict__ ritz, int* __restrict__ flag) {
+  extern __shared__ double sm[];
+  const int J = blockIdx.x;
+  const Hier& h = a.h;
+  const int L = h.Lc;
+  const int d0 = a.cc_ptr[J], nd = a.cc_ptr[J + 1] - d0;
+  if (nd > CC_DENSE) return;
+  double* A = sm;
+  double* V = A + nd * nd;
+  double* B = V + nd * nd;
+  double* Vs = B + nd * nd;
+  double* ev = Vs + nd * nd;
+  double* red = ev + nd;
+  int* perm = reinterpret_cast<int*>(red + 64);
+  for (int e = threadIdx.x; e < nd * nd; e += blockDim.x) {
+    const int p = e / nd, q = e % nd;
+    const long long dp = a.cc_dofs[d0 + p], dq = a.cc_dofs[d0 + q];
+    double v = 0.0;
+    if (!dof_valid(a, dp) || !dof_valid(a, dq)) {
+      v = (p == q) ? 1e300 : 0.0;
+    } else {
+      const int cp = int(dp / L), lp = int(dp % L), cq = int(dq / L), lq = int(dq % L);
+      const int px = cp % h.ncx, py = (cp / h.ncx) % h.ncy, pz = cp / (h.ncx * h.ncy);
+      const int qx = cq % h.ncx, qy = (cq / h.ncx) % h.ncy, qz = cq / (h.ncx * h.ncy);
+      const int ox = qx - px, oy = qy - py, oz = qz - pz;
+      if (abs(ox) <= 1 && abs(oy) <= 1 && abs(oz) <= 1) {
+        const int b = (oz + 1) * 9 + (oy + 1) * 3 + (ox + 1);
+        v = a.G[(((long long)cp * 27 + b) * L + lp) * L + lq];
+      }
+    }
+    A[e] = v;
+  }
+  __syncthreads();
+  // symmetrise
+  for (int e = threadIdx.x; e < nd * nd; e += blockDim.x) {
+    const int p = e / nd, q = e % nd;
+    if (p < q) {
+      const double v = 0.5 * (A[p * nd + q] + A[q * nd + p]);
+      B[e] = v;
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < nd * nd; e += blockDim.x) {
+    const int p = e / nd, q = e % nd;
+    if (p < q) A[e] = B[e];
+    else if (p > q) A[e] = B[q * nd + p];
+  }
+  __syncthreads();
+  block_jacobi(A, V, B, Vs, ev, perm, nd, red);
+  const int m = a.m;
+  for (int e = threadIdx.x; e < m * nd; e += blockDim.x) {
+    const int k = e / nd, d = e % nd;
+    X[(long long)m * d0 + (long long)k * nd + d] = (k < nd) ? Vs[d * nd + k] : 0.0;
+  }
+  for (int k = threadIdx.x; k < m; k += blockDim.x) ritz[(long long)J * m + k] = (k < nd) ? ev[k] : 0.0;
+  if (threadIdx.x == 0) flag[J] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// A_cc = R_cc A_c R_cc^T by colouring cc cells modulo 3: for class Q and
+// vector b, u = A_c v with v = sum over cc cells J of class Q of R_cc[J][b],
+// then A_cc[(I, a), (J(Q, I), b)] = R_cc[I][a] . u.
+
+template <typename VT, typename AT>
+__global__ void k_acc_apply(Hier h, const AT* __restrict__ Ac, const VT* __restrict__ Rcc, const int* __restrict__ cc_ptr,
+                            const int* __restrict__ dof_cc, const int* __restrict__ dof_loc, int qx, int qy, int qz, int b,
+                            double* __restrict__ u) {
+  const long long d = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const int L = h.Lc;
+  if (d >= (long long)h.ncells * L) return;
+  const int cell = int(d / L), l = int(d % L);
+  const int cx = cell % h.ncx, cy = (cell / h.ncx) % h.ncy, cz = cell / (h.ncx * h.ncy);
+  const AT* A = Ac + (long long)cell * 27 * L * L;
+  double s = 0.0;
+  for (int bb = 0; bb < 27; ++bb) {
+    const int x = cx + bb % 3 - 1, y = cy + (bb / 3) % 3 - 1, z = cz + bb / 9 - 1;
+    if (x < 0 || x >= h.ncx || y < 0 || y >= h.ncy || z < 0 || z >= h.ncz) continue;
+    const long long nc = ((long long)z * h.ncy + y) * h.ncx + x;
+    const int J = dof_cc[nc * L];
+    const int jx = J % h.nccx, jy = (J / h.nccx) % h.nccy, jz = J / (h.nccx * h.nccy);
+    if (jx % 3 != qx || jy % 3 != qy || jz % 3 != qz) continue;
+    const int d0 = cc_ptr[J], nd = cc_ptr[J + 1] - d0;
+    if (b >= min(h.Lcc, nd)) continue;
+    const VT* R = Rcc + (long long)h.Lcc * d0 + (long long)b * nd;
+    const int loc0 = dof_loc[nc * L];
+    for (int m = 0; m < L; ++m) s += double(ld<double, AT>(A, (bb * L + l) * L + m)) * double(R[loc0 + m]);
+  }
+  u[d] = s;
+}
+
+template <typename VT>
+__global__ void k_acc_dot(Hier h, const VT* __restrict__ Rcc, const int* __restrict__ cc_ptr, const int* __restrict__ cc_dofs,
+                          const double* __restrict__ u, int qx, int qy, int qz, int b, int n_cc, double* __restrict__ Acc) {
+  const long long w = (blockIdx.x * (long long)blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (w >= (long long)h.ncc * h.Lcc) return;
+  const int I = int(w / h.Lcc), a = int(w % h.Lcc);
+  const int ix = I % h.nccx, iy = (I / h.nccx) % h.nccy, iz = I / (h.nccx * h.nccy);
+  auto off3 = [](int c, int q) {
+    const int dd = ((q - c) % 3 + 3) % 3;
+    return dd == 0 ? 0 : (dd == 1 ? 1 : -1);
+  };
+  const int jx = ix + off3(ix, qx), jy = iy + off3(iy, qy), jz = iz + off3(iz, qz);
+  if (jx < 0 || jx >= h.nccx || jy < 0 || jy >= h.nccy || jz < 0 || jz >= h.nccz) return;
+  const int J = (jz * h.nccy + jy) * h.nccx + jx;
+  const int d0 = cc_ptr[I], nd = cc_ptr[I + 1] - d0;
+  const int ndJ = cc_ptr[J + 1] - cc_ptr[J];
+  if (a >= min(h.Lcc, nd) || b >= min(h.Lcc, ndJ)) return;
+  const VT* R = Rcc + (long long)h.Lcc * d0 + (long long)a * nd;
+  double s = 0.0;
+  for (int d = lane; d < nd; d += 64) s += double(R[d]) * u[cc_dofs[d0 + d]];
+  s = wave_sum(s);
+  if (lane == 0) Acc[(long long)(I * h.Lcc + a) * n_cc + (J * h.Lcc + b)] = s;
+}
+
+// unused cc slots (cells with fewer than Lcc dofs) get a unit diagonal
+__global__ void k_acc_pad(Hier h, const int* __restrict__ cc_ptr, int n_cc, double* __restrict__ Acc) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= n_cc) return;
+  const int I = w / h.Lcc, a = w % h.Lcc;
+  const int nd = cc_ptr[I + 1] - cc_ptr[I];
+  if (a >= nd) Acc[(long long)w * n_cc + w] = 1.0;
+}
+
+// ---------------------------------------------------------------------------
+// In-place Gauss-Jordan inverse of a batch of SPD matrices (n x n each, stride
+// n*n, batch index blockIdx.z) by pivot blocks of NB:
+//   P = A_kk^-1;  A_kJ <- P A_kJ;  A_IJ -= A_Ik A_kJ;  A_Ik <- -A_Ik P;  A_kk <- P.
+// No pivoting is needed for SPD matrices.
+constexpr int GJ_NB = 32;
+
+// invert the pivot block in LDS (unblocked Gauss-Jordan), store in P and A_kk
+__global__ void k_gj_pivot(int n, double* __restrict__ Ab, int k0, int nb, double* __restrict__ Pb) {
+  __shared__ double a[GJ_NB][GJ_NB + 1];
+  double* A = Ab + (long long)blockIdx.z * n * n;
+  double* P = Pb + (long long)blockIdx.z * GJ_NB * GJ_NB;
+  const int tid = threadIdx.x;  // nb*nb threads at most 1024
+  const int r = tid / nb, c = tid % nb;
+  if (tid < nb * nb) a[r][c] = A[(long long)(k0 + r) * n + (k0 + c)];
+  __syncthreads();
+  for (int k = 0; k < nb; ++k) {
+    const double piv = 1.0 / a[k][k];
+    double akc = 0.0, ark = 0.0;
+    if (tid < nb * nb) {
+      akc = a[k][c];
+      ark = a[r][k];
+    }
+    __syncthreads();
+    if (tid < nb * nb) {
+      if (r == k && c == k) a[r][c] = piv;
+      else if (r == k) a[r][c] = akc * piv;
+      else if (c == k) a[r][c] = -ark * piv;
+      else a[r][c] = a[r][c] - ark * akc * piv;
+    }
+    __syncthreads();
+  }
+  if (tid < nb * nb) {
+    P[r * nb + c] = a[r][c];
+    A[(long long)(k0 + r) * n + (k0 + c)] = a[r][c];
+  }
+}
+
+// Rb[r][j] = sum_t P[r][t] A[k0+t][j] for j outside the pivot block
+__global__ void k_gj_rowpanel(int n, const double* __restrict__ Ab, int k0, int nb, const double* __restrict__ Pb,
+                              double* __restrict__ Rbb) {
+  const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (gid >= (long long)nb * n) return;
+  const double* A = Ab + (long long)blockIdx.z * n * n;
+  const double* P = Pb + (long long)blockIdx.z * GJ_NB * GJ_NB;
+  double* Rb = Rbb + (long long)blockIdx.z * GJ_NB * n;
+  const int r = int(gid / n), j = int(gid % n);
+  if (j >= k0 && j < k0 + nb) return;
+  double s = 0.0;
+  for (int t = 0; t < nb; ++t) s += P[r * nb + t] * A[(long long)(k0 + t) * n + j];
+  Rb[(long long)r * n + j] = s;
+}
+
+// Cb[i][c] = -sum_t A[i][k0+t] P[t][c] for rows outside the pivot block (old column panel)
+__global__ void k_gj_colpanel(int n, const double* __restrict__ Ab, int k0, int nb, const double* __restrict__ Pb,
+                              double* __restrict__ Cbb) {
+  const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (gid >= (long long)n * nb) return;
+  const double* A = Ab + (long long)blockIdx.z * n * n;
+  const double* P = Pb + (long long)blockIdx.z * GJ_NB * GJ_NB;
+  double* Cb = Cbb + (long long)blockIdx.z * GJ_NB * n;
+  const int i = int(gid / nb), c = int(gid % nb);
+  if (i >= k0 && i < k0 + nb) return;
+  double s = 0.0;
+  for (int t = 0; t < nb; ++t) s += A[(long long)i * n + k0 + t] * P[t * nb + c];
+  Cb[(long long)i * nb + c] = -s;
+}
+
+// A_ij -= sum_t A[i][k0+t] Rb[t][j] for i, j outside the pivot block (64x64 tiles)
+__global__ void k_gj_update(int n, double* __restrict__ Ab, int k0, int nb, const double* __restrict__ Rbb) {
+  __shared__ double As[64][GJ_NB + 1];
+  __shared__ double Bs[GJ_NB][64 + 1];
+  double* A = Ab + (long long)blockIdx.z * n * n;
+  const double* Rb = Rbb + (long long)blockIdx.z * GJ_NB * n;
+  const int ti = blockIdx.y * 64, tj = blockIdx.x * 64;
+  const int tid = threadIdx.x;  // 256
+  for (int e = tid; e < 64 * nb; e += 256) {
+    const int r = e / nb, t = e % nb;
+    const int i = ti + r;
+    As[r][t] = (i < n) ? A[(long long)i * n + k0 + t] : 0.0;
+  }
+  for (int e = tid; e < nb * 64; e += 256) {
+    const int t = e / 64, c = e % 64;
+    const int j = tj + c;
+    Bs[t][c] = (j < n) ? Rb[(long long)t * n + j] : 0.0;
+  }
+  __syncthreads();
+  const int r0 = (tid / 16) * 4, c0 = (tid % 16) * 4;
+  double acc[4][4] = {};
+  for (int t = 0; t < nb; ++t)
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] += As[r0 + a][t] * Bs[t][c0 + b];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int i = ti + r0 + a, j = tj + c0 + b;
+      if (i < n && j < n && !(i >= k0 && i < k0 + nb) && !(j >= k0 && j < k0 + nb)) A[(long long)i * n + j] -= acc[a][b];
+    }
+}
+
+__global__ void k_gj_writeback(int n, double* __restrict__ Ab, int k0, int nb, const double* __restrict__ Rbb,
+                               const double* __restrict__ Cbb) {
+  const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (gid >= (long long)nb * n) return;
+  double* A = Ab + (long long)blockIdx.z * n * n;
+  const double* Rb = Rbb + (long long)blockIdx.z * GJ_NB * n;
+  const double* Cb = Cbb + (long long)blockIdx.z * GJ_NB * n;
+  const int r = int(gid / n), j = int(gid % n);
+  if (!(j >= k0 && j < k0 + nb)) {
+    A[(long long)(k0 + r) * n + j] = Rb[(long long)r * n + j];
+    A[(long long)j * n + k0 + r] = Cb[(long long)j * nb + r];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Coarse-coarse shift-invert operator: dense G_J + sigma_J I per cc cell
+// (nd_max x nd_max, padded slots and invalid dofs decoupled with a large
+// diagonal), inverted by the batched Gauss-Jordan sweep.
+
+// sigma_J = 1e-6 * mean valid diagonal (stored in par[J*8 + 7])
+__global__ void k_ccd_shift(CCArgs a, double* __restrict__ par) {
+  __shared__ double red[64];
+  const int J = blockIdx.x;
+  const Hier& h = a.h;
+  const int L = h.Lc;
+  const int d0 = a.cc_ptr[J], nd = a.cc_ptr[J + 1] - d0;
+  double s = 0.0, cnt = 0.0;
+  for (int q = threadIdx.x; q < nd; q += blockDim.x) {
+    const long long d = a.cc_dofs[d0 + q];
+    if (!dof_valid(a, d)) continue;
+    const int cell = int(d / L), l = int(d % L);
+    s += a.G[(((long long)cell * 27 + 13) * L + l) * L + l];
+    cnt += 1.0;
+  }
+  s = block_allsum(s, red);
+  cnt = block_allsum(cnt, red);
+  if (threadIdx.x == 0) par[J * 8 + 7] = 1e-6 * (cnt > 0 ? s / cnt : 1.0) + 1e-300;
+}
+
+__global__ void k_ccd_assemble(CCArgs a, int ndm, const double* __restrict__ par, double* __restrict__ Gd) {
+  const int J = blockIdx.y;
+  const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (e >= (long long)ndm * ndm) return;
+  const Hier& h = a.h;
+  const int L = h.Lc;
+  const int d0 = a.cc_ptr[J], nd = a.cc_ptr[J + 1] - d0;
+  const int p = int(e / ndm), q = int(e % ndm);
+  double v = 0.0;
+  const double big = 1e30;
+  if (p >= nd || q >= nd) {
+    v = (p == q) ? 1.0 : 0.0;
+  } else {
+    const long long dp = a.cc_dofs[d0 + p], dq = a.cc_dofs[d0 + q];
+    if (!dof_valid(a, dp) || !dof_valid(a, dq)) {
+      v = (p == q) ? big : 0.0;
+    } else {
+      const int cp = int(dp / L), lp = int(dp % L), cq = int(dq / L), lq = int(dq % L);
+      const int px = cp % h.ncx, py = (cp / h.ncx) % h.ncy, pz = cp / (h.ncx * h.ncy);
+      const int qx = cq % h.ncx, qy = (cq / h.ncx) % h.ncy, qz = cq / (h.ncx * h.ncy);
+      const int ox = qx - px, oy = qy - py, oz = qz - pz;
+      if (abs(ox) <= 1 && abs(oy) <= 1 && abs(oz) <= 1) {
+        const int b = (oz + 1) * 9 + (oy + 1) * 3 + (ox + 1);
+        const int bt = (1 - oz) * 9 + (1 - oy) * 3 + (1 - ox);
+        // symmetrised entry
+        v = 0.5 * (a.G[(((long long)cp * 27 + b) * L + lp) * L + lq] + a.G[(((long long)cq * 27 + bt) * L + lq) * L + lp]);
+      }
+      if (p == q) v += par[J * 8 + 7];
+    }
+  }
+  Gd[(long long)J * ndm * ndm + e] = v;
+}
+
+// Y = (G + sigma I)^-1 X per active cc cell (the inverse is symmetric: read columns)
+__global__ void k_ccd_apply(CCArgs a, int ndm, const double* __restrict__ Gi, const double* __restrict__ X,
+                            double* __restrict__ Y, const int* __restrict__ flag) {
+  const int J = blockIdx.y;
+  if (flag[J] >= 0) return;
+  const int m = a.m;
+  const int d0 = a.cc_ptr[J], nd = a.cc_ptr[J + 1] - d0;
+  const int d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= nd) return;
+  const double* G = Gi + (long long)J * ndm * ndm;
+  const double* XJ = X + (long long)m * d0;
+  double acc[32];
+  for (int j = 0; j < 32; ++j) acc[j] = 0.0;
+  for (int q = 0; q < nd; ++q) {
+    const double g = G[(long long)q * ndm + d];
+#pragma unroll
+    for (int j = 0; j < 32; ++j)
+      if (j < m) acc[j] += g * XJ[(long long)j * nd + q];
+  }
+  double* YJ = Y + (long long)m * d0;
+#pragma unroll
+  for (int j = 0; j < 32; ++j)
+    if (j < m) YJ[(long long)j * nd + d] = acc[j];
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+
+int launch_galerkin(const Ctx& c, const void* R, int b_dt, int drop_cc, double* out, hipStream_t s) {
+  const dim3 gr((unsigned)(((c.ntiles + 7) / 8) * 8)), bl(c.CX * c.h.H, c.h.H);
+  const size_t sh = size_t(bl.x) * bl.y * sizeof(double);
+  const int L = c.h.Lc;
+  for (int q = 0; q < 27; ++q) {
+    const int qx = q % 3, qy = (q / 3) % 3, qz = q / 9;
+#define GL(BT, LT) hipLaunchKernelGGL((k_galerkin<BT, LT>), gr, bl, sh, s, c.g, c.st, c.h, c.CX, c.rho, c.rho_dt, c.mat, (const BT*)R, qx, qy, qz, drop_cc, out)
+#define GLL(BT)                                    \
+  switch (L) {                                     \
+    case 1: GL(BT, 1); break;                      \
+    case 2: GL(BT, 2); break;                      \
+    case 3: GL(BT, 3); break;                      \
+    case 4: GL(BT, 4); break;                      \
+    case 5: GL(BT, 5); break;                      \
+    case 6: GL(BT, 6); break;                      \
+    case 7: GL(BT, 7); break;                      \
+    default: GL(BT, 8); break;                     \
+  }
+    if (b_dt == DT_F64) { GLL(double) }
+    else if (b_dt == DT_F32) { GLL(float) }
+    else { GLL(bf16) }
+#undef GLL
+#undef GL
+  }
+  return hipGetLastError() == hipSuccess ? MSMG_OK : MSMG_EHIP;
+}
+
+void launch_block_inverse(const Ctx& c, double* Ac, double* Dinv, hipStream_t s) {
+  hipLaunchKernelGGL(k_block_inverse, dim3((c.h.ncells + 63) / 64), dim3(64), 0, s, c.h.ncells, c.h.Lc, Ac, Dinv);
+}
+
+int run_cc_eigen(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, const double* G, int* n_unconv, hipStream_t s) {
+  const Hier& h = c.h;
+  CCArgs a;
+  a.h = h;
+  a.m = sc->mcc;
+  a.G = G;
+  a.cc_ptr = sa.cc_ptr;
+  a.cc_dofs = sa.cc_dofs;
+  a.dof_cc = sa.dof_cc;
+  a.dof_loc = sa.dof_loc;
+  a.cell_status = sa.cell_status;
+  const int m = a.m;
+  const long long ndof = (long long)h.ncells * h.Lc;
+  const dim3 gv((unsigned)((ndof * m + 255) / 256)), bv(256);
+  double* Y = sc->Y;
+  double* Xp = sc->Yp;
+  double* Z = sc->Z;
+  double* small = sc->small;
+  double* par = sc->ccpar;
+  double* ritz = par + (size_t)h.ncc * 8;
+  double* bound = ritz + (size_t)h.ncc * m;
+  int* flag = sc->ccflag;
+  const int small_threads = std::min(1024, std::max(64, ((m * m + 63) / 64) * 64));
+  const size_t small_lds = sizeof(double) * (5 * m * m + m + 64) + sizeof(int) * m;
+  hipLaunchKernelGGL(k_cc_bound, dim3(h.ncc), dim3(256), 0, s, a, bound);
+  hipLaunchKernelGGL(k_cc_start, dim3((unsigned)((ndof + 255) / 256)), dim3(256), 0, s, a, Y);
+  if (hipMemsetAsync(flag, 0xff, sizeof(int) * h.ncc, s) != hipSuccess) return MSMG_EHIP;  // -1: active
+  {
+    const size_t lds = sizeof(double) * (4 * CC_DENSE * CC_DENSE + CC_DENSE + 64) + sizeof(int) * CC_DENSE;
+    hipLaunchKernelGGL(k_cc_dense, dim3(h.ncc), dim3(1024), lds, s, a, Xp, ritz, flag);
+  }
+  auto orth = [&](double* P, double* tmp) {
+    hipLaunchKernelGGL(k_cc_gram, dim3(h.ncc), dim3(256), 0, s, a, P, P, small, 0, flag);
+    hipLaunchKernelGGL(k_cc_small_eig, dim3(h.ncc), dim3(small_threads), small_lds, s, a, small, 0, 0, ritz, flag);
+    hipLaunchKernelGGL(k_cc_transform, gv, bv, 0, s, a, P, tmp, small, flag);
+  };
+  // start: orthonormalise twice (Y -> Xp -> Y), Rayleigh-Ritz (Z = G Y; X = Y C; Z = Z C)
+  auto rr = [&]() {
+    orth(Y, Xp);
+    orth(Xp, Y);
+    hipLaunchKernelGGL(k_cc_spmm, gv, bv, 0, s, a, Y, nullptr, Z, 0, par, flag);
+    hipLaunchKernelGGL(k_cc_gram, dim3(h.ncc), dim3(256), 0, s, a, Y, Z, small, 0, flag);
+    hipLaunchKernelGGL(k_cc_small_eig, dim3(h.ncc), dim3(small_threads), small_lds, s, a, small, 0, 1, ritz, flag);
+    hipLaunchKernelGGL(k_cc_transform, gv, bv, 0, s, a, Y, Xp, small, flag);  // Xp = Ritz vectors
+    hipLaunchKernelGGL(k_cc_transform, gv, bv, 0, s, a, Z, Y, small, flag);   // Y = G * Ritz vectors
+    std::swap(Y, Z);                                                            // Z = G X, Y free
+  };
+  rr();
+  const int maxit = sa.opt->cc_maxit, degree = sa.opt->cc_degree;
+  const double tol = sa.opt->eig_tol;
+  // shift-invert operator (G_J + sigma_J I)^-1 for every cc cell
+  const int ndm = sa.max_cc_dofs;
+  hipLaunchKernelGGL(k_ccd_shift, dim3(h.ncc), dim3(256), 0, s, a, par);
+  hipLaunchKernelGGL(k_ccd_assemble, dim3((unsigned)(((long long)ndm * ndm + 255) / 256), h.ncc), dim3(256), 0, s, a,
+                     ndm, par, sc->Gd);
+  {
+    double* P = sc->gj;
+    double* Rb = P + (size_t)h.ncc * 32 * 32;
+    double* Cb = Rb + (size_t)h.ncc * 32 * ndm;
+    const int r = gj_inverse(ndm, h.ncc, sc->Gd, P, Rb, Cb, s);
+    if (r != MSMG_OK) return r;
+  }
+  const dim3 ga((ndm + 63) / 64, h.ncc), ba(64);
+  for (int it = 0; it <= maxit; ++it) {
+    hipLaunchKernelGGL(k_cc_check, dim3(h.ncc), dim3(256), 0, s, a, Xp, Z, ritz, par, flag, bound, h.Lcc, tol, it,
+                       it == maxit ? 1 : 0, degree);
+    if (it == maxit) break;
+    if (it % 4 == 3) {
+      std::vector<int> hf(h.ncc);
+      if (hipMemcpyAsync(hf.data(), flag, sizeof(int) * h.ncc, hipMemcpyDeviceToHost, s) != hipSuccess) return MSMG_EHIP;
+      if (hipStreamSynchronize(s) != hipSuccess) return MSMG_EHIP;
+      bool all = true;
+      for (int v : hf) all = all && v >= 0;
+      if (all) break;
+    }
+    // Y = (G + sigma I)^-1 X, then orthonormalise and Rayleigh-Ritz with G
+    hipLaunchKernelGGL(k_ccd_apply, ga, ba, 0, s, a, ndm, sc->Gd, Xp, Y, flag);
+    rr();
+  }
+  // X (Ritz vectors) in Xp
+  hipLaunchKernelGGL(k_cc_finish, dim3(h.ncc), dim3(256), 0, s, a, Xp, ritz, sa.Rcc64, sa.cc_evals, h.Lcc);
+  std::vector<int> hf(h.ncc);
+  if (hipMemcpyAsync(hf.data(), flag, sizeof(int) * h.ncc, hipMemcpyDeviceToHost, s) != hipSuccess) return MSMG_EHIP;
+  if (hipMemcpyAsync(sa.cc_status, flag, sizeof(int) * h.ncc, hipMemcpyDeviceToDevice, s) != hipSuccess) return MSMG_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return MSMG_EHIP;
+  int nu = 0;
+  for (int v : hf) nu += (v < 0);
+  *n_unconv = nu;
+  return hipGetLastError() == hipSuccess ? MSMG_OK : MSMG_EHIP;
+}
+
+int build_acc(const Ctx& c, const SetupArgs& sa, double* u, hipStream_t s) {
+  const Hier& h = c.h;
+  const int n = sa.n_cc;
+  if (hipMemsetAsync(sa.Acc, 0, sizeof(double) * (size_t)n * n, s) != hipSuccess) return MSMG_EHIP;
+  const long long ndof = (long long)h.ncells * h.Lc;
+  const dim3 gu((unsigned)((ndof + 255) / 256)), bu(256);
+  const long long nw = (long long)h.ncc * h.Lcc;
+  const dim3 gd((unsigned)((nw * 64 + 255) / 256)), bd(256);
+  for (int q = 0; q < 27; ++q) {
+    const int qx = q % 3, qy = (q / 3) % 3, qz = q / 9;
+    if (qx >= h.nccx || qy >= h.nccy || qz >= h.nccz) continue;
+    for (int b = 0; b < h.Lcc; ++b) {
+      hipLaunchKernelGGL((k_acc_apply<double, double>), gu, bu, 0, s, h, (const double*)sa.Acv, (const double*)sa.Rccv, sa.cc_ptr, sa.dof_cc, sa.dof_loc, qx, qy, qz, b, u);
+      hipLaunchKernelGGL((k_acc_dot<double>), gd, bd, 0, s, h, (const double*)sa.Rccv, sa.cc_ptr, sa.cc_dofs, u, qx, qy, qz, b, n, sa.Acc);
+    }
+  }
+  hipLaunchKernelGGL(k_acc_pad, dim3((n + 255) / 256), dim3(256), 0, s, h, sa.cc_ptr, n, sa.Acc);
+  return hipGetLastError() == hipSuccess ? MSMG_OK : MSMG_EHIP;
+}
+
+int gj_inverse(int n, int batch, double* A, double* P, double* Rb, double* Cb, hipStream_t s) {
+  for (int k0 = 0; k0 < n; k0 += GJ_NB) {
+    const int nb = std::min(GJ_NB, n - k0);
+    hipLaunchKernelGGL(k_gj_pivot, dim3(1, 1, batch), dim3(1024), 0, s, n, A, k0, nb, P);
+    const long long rn = (long long)nb * n;
+    const dim3 gp((unsigned)((rn + 255) / 256), 1, batch);
+    hipLaunchKernelGGL(k_gj_rowpanel, gp, dim3(256), 0, s, n, A, k0, nb, P, Rb);
+    hipLaunchKernelGGL(k_gj_colpanel, gp, dim3(256), 0, s, n, A, k0, nb, P, Cb);
+    const dim3 gt((n + 63) / 64, (n + 63) / 64, batch);
+    hipLaunchKernelGGL(k_gj_update, gt, dim3(256), 0, s, n, A, k0, nb, Rb);
+    hipLaunchKernelGGL(k_gj_writeback, gp, dim3(256), 0, s, n, A, k0, nb, Rb, Cb);
+  }
+  return hipGetLastError() == hipSuccess ? MSMG_OK : MSMG_EHIP;
+}
+
+}  // namespace msmg

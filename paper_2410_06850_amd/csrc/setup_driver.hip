@@ -1,0 +1,216 @@
+// Set-up driver: orders the coarse-space construction for one density field
+// (paper flowchart: coefficient field -> spectral problems on the coarse
+// cells -> spectral problems on the coarse-coarse cells -> preconditioner),
+// and the launch-shape tuner of the batched per-cell eigensolver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "setup.h"
+
+namespace msmg {
+
+int launch_galerkin(const Ctx& c, const void* R, int b_dt, int drop_cc, double* out, hipStream_t s);
+void launch_block_inverse(const Ctx& c, double* Ac, double* Dinv, hipStream_t s);
+int run_cc_eigen(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, const double* G, int* n_unconv, hipStream_t s);
+int build_acc(const Ctx& c, const SetupArgs& sa, double* u, hipStream_t s);
+int gj_inverse(int n, int batch, double* A, double* P, double* Rb, double* Cb, hipStream_t s);
+void launch_convert(const void* in, int din, void* out, int dout, long long n, hipStream_t s);
+
+int setup_scratch_alloc(const Geo& g, const Hier& h, int max_cc_dofs, const msmg_options& o, SetupScratch* s,
+                        const std::function<int(void**, size_t)>& alloc) {
+  (void)g;
+  int m = o.cc_block ? o.cc_block : std::min(32, h.Lcc + 15);
+  if (m < h.Lcc + 1) m = std::min(32, h.Lcc + 1);
+  s->mcc = m;
+  const size_t nvec = (size_t)m * h.ncells * h.Lc;
+  int r;
+  if ((r = alloc((void**)&s->Y, nvec * 8))) return r;
+  if ((r = alloc((void**)&s->Yp, nvec * 8))) return r;
+  if ((r = alloc((void**)&s->Z, nvec * 8))) return r;
+  if ((r = alloc((void**)&s->small, (size_t)h.ncc * 4 * m * m * 8))) return r;
+  if ((r = alloc((void**)&s->ccpar, (size_t)h.ncc * (8 + m + 1) * 8))) return r;
+  if ((r = alloc((void**)&s->ccflag, (size_t)h.ncc * 4))) return r;
+  const size_t ncc = (size_t)h.ncc * h.Lcc;
+  if ((r = alloc((void**)&s->acc_copy, ncc * ncc * 8))) return r;
+  const size_t ndm = (size_t)std::max(max_cc_dofs, 1);
+  const size_t gj_single = 32 * 32 + 2 * 32 * ncc;
+  const size_t gj_batch = (size_t)h.ncc * (32 * 32 + 2 * 32 * ndm);
+  if ((r = alloc((void**)&s->gj, std::max(gj_single, gj_batch) * 8))) return r;
+  if ((r = alloc((void**)&s->Gd, (size_t)h.ncc * ndm * ndm * 8))) return r;
+  if ((r = alloc((void**)&s->work, 64))) return r;
+  return MSMG_OK;
+}
+
+static int hip_ok(hipError_t e, SetupReport* rep, const char* what) {
+  if (e == hipSuccess) return MSMG_OK;
+  std::snprintf(rep->msg, sizeof(rep->msg), "%s: %s", what, hipGetErrorString(e));
+  return MSMG_EHIP;
+}
+
+// ---- tuner cache ----------------------------------------------------------
+static std::string tune_key(const Ctx& c, int nl) {
+  hipDeviceProp_t p;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipGetDeviceProperties(&p, dev);
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "%s H%d L%d nl%d rho%d cells%d", p.gcnArchName, c.h.H, c.h.Lc, nl, c.rho_dt,
+                c.h.ncells);
+  return buf;
+}
+
+static bool cache_lookup(const char* path, const std::string& key, TuneChoice* t) {
+  if (!path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  while (std::fgets(line, sizeof(line), f)) {
+    char* bar = std::strchr(line, '|');
+    if (!bar) continue;
+    *bar = 0;
+    if (key == line) {
+      TuneChoice c{};
+      if (std::sscanf(bar + 1, "%d %d %d %d %lf", &c.bs, &c.m, &c.degree, &c.blocks_per_cu, &c.ms) == 5) {
+        c.valid = 1;
+        *t = c;
+        found = true;
+      }
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+static void cache_store(const char* path, const std::string& key, const TuneChoice& t) {
+  if (!path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s|%d %d %d %d %.4f\n", key.c_str(), t.bs, t.m, t.degree, t.blocks_per_cu, t.ms);
+  std::fclose(f);
+}
+
+static int count_unconverged(const SetupArgs& sa, int ncells, int* unconv, int* ties, hipStream_t s) {
+  std::vector<int> st(ncells);
+  if (hipMemcpyAsync(st.data(), sa.cell_status, sizeof(int) * ncells, hipMemcpyDeviceToHost, s) != hipSuccess) return MSMG_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return MSMG_EHIP;
+  int u = 0, t = 0;
+  for (int v : st) {
+    u += (v >> 28) & 1;
+    t += (v >> 29) & 1;
+  }
+  *unconv = u;
+  *ties = t;
+  return MSMG_OK;
+}
+
+// Time the level-1 eigensolver over a few launch shapes on the real problem
+// and keep the fastest one whose cells all converge.
+static int tune_local(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, int cus, hipStream_t s, TuneChoice* best) {
+  struct Cand { int bs, m, degree, bpc; };
+  std::vector<Cand> cands = {{256, 8, 8, 2}, {256, 8, 12, 2}, {256, 8, 20, 2}, {512, 8, 12, 1},
+                             {512, 8, 12, 2}, {256, 8, 12, 4}};
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MSMG_EHIP;
+  best->valid = 0;
+  int best_unconv = 1 << 30;
+  for (const Cand& cd : cands) {
+    if (cd.m < c.h.Lc + 1) continue;
+    const int blocks = std::max(1, std::min(c.h.ncells, cd.bpc * cus));
+    (void)hipEventRecord(e0, s);
+    const int r = launch_local_eigen(c, sa, sc, cd.bs, cd.m, cd.degree, blocks, s);
+    (void)hipEventRecord(e1, s);
+    if (r != MSMG_OK) continue;
+    if (hipEventSynchronize(e1) != hipSuccess) return MSMG_EHIP;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    int un = 0, ti = 0;
+    if (count_unconverged(sa, c.h.ncells, &un, &ti, s) != MSMG_OK) return MSMG_EHIP;
+    const bool better = (un < best_unconv) || (un == best_unconv && ms < best->ms);
+    if (!best->valid || better) {
+      best->valid = 1;
+      best->bs = cd.bs;
+      best->m = cd.m;
+      best->degree = cd.degree;
+      best->blocks_per_cu = cd.bpc;
+      best->ms = ms;
+      best_unconv = un;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return best->valid ? MSMG_OK : MSMG_ESETUP;
+}
+
+int run_setup(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, SetupReport* rep, hipStream_t s) {
+  std::memset(rep, 0, sizeof(*rep));
+  const Hier& h = c.h;
+  const msmg_options& o = *sa.opt;
+  int dev = 0, cus = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+
+  // 1. local spectral problems eq. (spepb) -> R_c (FP64)
+  TuneChoice& tc = *sa.tune;
+  int r;
+  if (o.eig_block > 0 || o.eig_degree > 0 || !o.autotune) {
+    tc.valid = 1;
+    tc.bs = 256;
+    tc.m = o.eig_block > 0 ? o.eig_block : 8;
+    tc.degree = o.eig_degree > 0 ? o.eig_degree : 12;
+    tc.blocks_per_cu = 2;
+  } else if (!tc.valid) {
+    const std::string key = tune_key(c, sa.max_cell_nodes);
+    if (!cache_lookup(o.tune_cache, key, &tc)) {
+      r = tune_local(c, sa, sc, cus, s, &tc);
+      if (r != MSMG_OK) {
+        std::snprintf(rep->msg, sizeof(rep->msg), "level-1 eigensolver tuning failed");
+        return r;
+      }
+      cache_store(o.tune_cache, key, tc);
+    }
+  }
+  const int blocks = std::max(1, std::min(h.ncells, tc.blocks_per_cu * cus));
+  r = launch_local_eigen(c, sa, sc, tc.bs, tc.m, tc.degree, blocks, s);
+  if (r != MSMG_OK) {
+    std::snprintf(rep->msg, sizeof(rep->msg), "level-1 eigensolver launch failed (block %d)", tc.m);
+    return r;
+  }
+  if ((r = count_unconverged(sa, h.ncells, &rep->eig_unconverged, &rep->eig_ties, s))) return r;
+
+  // 2. stored copy of R_c, Galerkin A_c from the stored values
+  const long long nb = c.g.nn * h.Lc;
+  if (sa.b_dt != DT_F64) launch_convert(sa.Rc64, DT_F64, sa.Rcs, sa.b_dt, nb, s);
+  if ((r = launch_galerkin(c, sa.Rcs, sa.b_dt, 0, sa.Ac64, s))) return hip_ok(hipGetLastError(), rep, "Galerkin A_c");
+  launch_block_inverse(c, sa.Ac64, sa.AcDinv64, s);
+  const long long nblk = (long long)h.ncells * 27 * h.Lc * h.Lc;
+  if (sa.a_dt != DT_F64) {
+    launch_convert(sa.Ac64, DT_F64, sa.Acv, sa.a_dt, nblk, s);
+    launch_convert(sa.AcDinv64, DT_F64, sa.AcDinvv, sa.a_dt, (long long)sa.n_c * h.Lc, s);
+  }
+
+  // 3. coarse-coarse spectral problems eq. (spectral cc) on the FP64 basis
+  if ((r = launch_galerkin(c, sa.Rc64, DT_F64, 1, sa.G64, s))) return hip_ok(hipGetLastError(), rep, "Galerkin G");
+  if ((r = run_cc_eigen(c, sa, sc, sa.G64, &rep->cc_unconverged, s))) {
+    std::snprintf(rep->msg, sizeof(rep->msg), "coarse-coarse eigensolver failed");
+    return r;
+  }
+  if (sa.Rccv != sa.Rcc64) launch_convert(sa.Rcc64, DT_F64, sa.Rccv, DT_F32, (long long)h.Lcc * sa.n_c, s);
+
+  // 4. A_cc = R_cc A_c R_cc^T from the cycle's copies, then its inverse
+  if ((r = build_acc(c, sa, sc->Y, s))) return hip_ok(hipGetLastError(), rep, "A_cc");
+  const size_t nn2 = (size_t)sa.n_cc * sa.n_cc * 8;
+  if ((r = hip_ok(hipMemcpyAsync(sc->acc_copy, sa.Acc, nn2, hipMemcpyDeviceToDevice, s), rep, "A_cc copy"))) return r;
+  double* P = sc->gj;
+  double* Rb = P + 32 * 32;
+  double* Cb = Rb + (size_t)32 * sa.n_cc;
+  if ((r = gj_inverse(sa.n_cc, 1, sa.Acc, P, Rb, Cb, s))) return hip_ok(hipGetLastError(), rep, "A_cc inverse");
+  return hip_ok(hipGetLastError(), rep, "set-up");
+}
+
+}  // namespace msmg

@@ -1,0 +1,170 @@
+"""Torch-facing wrapper of the C ABI: device memory and streams come from
+PyTorch, every step of the computation runs in libmsmg.so.
+
+Layouts: element tensors are (nz, ny, nx) or flat, nodal tensors
+(nz+1, ny+1, nx+1) or flat, all C-contiguous on the current HIP device.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib as L
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t, name, dtype, numel, device):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must live on the GPU")
+    if t.device != device:
+        raise ValueError(f"{name} is on {t.device}, the solver on {device}")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} entries, got {t.numel()}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+_DT = {torch.float64: L.MSMG_F64, torch.float32: L.MSMG_F32}
+
+
+class SolveInfo(dict):
+    __getattr__ = dict.__getitem__
+
+
+class Solver:
+    """PCG with the three-grid multiscale preconditioner on an nx*ny*nz Q1 mesh."""
+
+    def __init__(self, nx, ny=None, nz=None, lx=1.0, ly=1.0, lz=1.0, device=None, **options):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the MsMG solver needs a HIP GPU")
+        ny = nx if ny is None else ny
+        nz = nx if nz is None else nz
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.nnodes = (self.nx + 1) * (self.ny + 1) * (self.nz + 1)
+        self.nelem = self.nx * self.ny * self.nz
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.opts = L.default_options(**options)
+        self._tune_cache = self.opts.tune_cache  # keep the bytes alive
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            L.check(L.lib().msmg_create(ctypes.byref(h), self.nx, self.ny, self.nz, lx, ly, lz, ctypes.byref(self.opts)),
+                    "msmg_create")
+        self._h = h
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            L.lib().msmg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- set-up ---------------------------------------------------------------
+    def setup(self, rho, kmin, kmax, p, mask, fixed_values=None):
+        rho = _need(rho, "rho", None, self.nelem, self.device)
+        if rho.dtype not in _DT:
+            raise TypeError("rho must be float64 or float32")
+        mask = _need(mask, "mask", torch.uint8, self.nnodes, self.device)
+        fv = None
+        if fixed_values is not None:
+            fv = _need(fixed_values, "fixed_values", torch.float64, self.nnodes, self.device)
+        L.check(L.lib().msmg_setup(self._h, _ptr(rho), _DT[rho.dtype], float(kmin), float(kmax), int(p), _ptr(mask),
+                                   _ptr(fv) if fv is not None else None, _stream()), "msmg_setup")
+        self.kmin, self.kmax, self.p = float(kmin), float(kmax), int(p)
+        return self
+
+    # -- solves and products --------------------------------------------------
+    def solve(self, f, T=None, rtol=1e-8, maxit=1000, use_x0=False, T_lo=None):
+        """Solve A T = f.  With T_lo (a tensor like f) the double-double iterate is
+        returned as T + T_lo; otherwise T holds it rounded to binary64."""
+        f = _need(f, "f", torch.float64, self.nnodes, self.device)
+        if T is None:
+            T = torch.empty_like(f)
+            use_x0 = False
+        else:
+            _need(T, "T", torch.float64, self.nnodes, self.device)
+        if T_lo is not None:
+            _need(T_lo, "T_lo", torch.float64, self.nnodes, self.device)
+        info = L.Info()
+        code = L.check(L.lib().msmg_solve(self._h, _ptr(f), _ptr(T), _ptr(T_lo) if T_lo is not None else None,
+                                          int(bool(use_x0)), float(rtol), int(maxit), ctypes.byref(info), _stream()),
+                       "msmg_solve")
+        out = SolveInfo({k: getattr(info, k) for k, _ in L.Info._fields_})
+        out["code"] = code
+        return T, out
+
+    def apply(self, x, y=None):
+        x = _need(x, "x", torch.float64, self.nnodes, self.device)
+        y = torch.empty_like(x) if y is None else y
+        L.check(L.lib().msmg_apply(self._h, _ptr(x), _ptr(y), _stream()), "msmg_apply")
+        return y
+
+    def precondition(self, r, z=None):
+        r = _need(r, "r", torch.float64, self.nnodes, self.device)
+        z = torch.empty_like(r) if z is None else z
+        L.check(L.lib().msmg_precondition(self._h, _ptr(r), _ptr(z), _stream()), "msmg_precondition")
+        return z
+
+    def sensitivity(self, T, lam=None, out=None):
+        T = _need(T, "T", torch.float64, self.nnodes, self.device)
+        if lam is not None:
+            _need(lam, "lam", torch.float64, self.nnodes, self.device)
+        out = torch.empty(self.nelem, dtype=torch.float64, device=self.device) if out is None else out
+        L.check(L.lib().msmg_sensitivity(self._h, _ptr(T), _ptr(lam) if lam is not None else None, _ptr(out),
+                                         _stream()), "msmg_sensitivity")
+        return out
+
+    def element_load(self, src=None, const=1.0):
+        f = torch.empty(self.nnodes, dtype=torch.float64, device=self.device)
+        if src is not None:
+            _need(src, "src", torch.float64, self.nelem, self.device)
+        L.check(L.lib().msmg_element_load(self._h, _ptr(src) if src is not None else None, float(const), _ptr(f),
+                                          _stream()), "msmg_element_load")
+        return f
+
+    def export(self, what, count, dtype=torch.float64):
+        out = torch.empty(count, dtype=dtype)
+        L.check(L.lib().msmg_export(self._h, int(what), ctypes.c_void_p(out.data_ptr()),
+                                    out.numel() * out.element_size()), "msmg_export")
+        return out
+
+    def plan(self):
+        return L.query_plan(self.nx, self.ny, self.nz, self.opts)
+
+
+def prolong_nodal(Tc, n):
+    """Coarse nodal field on an (nx,ny,nz) mesh -> values at the 2x-refined nodes."""
+    nx, ny, nz = n
+    _need(Tc, "Tc", torch.float64, (nx + 1) * (ny + 1) * (nz + 1), Tc.device)
+    Tf = torch.empty((2 * nz + 1) * (2 * ny + 1) * (2 * nx + 1), dtype=torch.float64, device=Tc.device)
+    L.check(L.lib().msmg_prolong_nodal(nx, ny, nz, _ptr(Tc), _ptr(Tf), _stream()), "msmg_prolong_nodal")
+    return Tf
+
+
+def prolong_element(rc, n):
+    """Coarse element field -> 2x-refined element field (injection)."""
+    nx, ny, nz = n
+    if rc.dtype not in (torch.float64, torch.float32, torch.bfloat16):
+        raise TypeError("element field must be float64, float32 or bfloat16")
+    _need(rc, "rc", None, nx * ny * nz, rc.device)
+    dt = {torch.float64: L.MSMG_F64, torch.float32: L.MSMG_F32, torch.bfloat16: L.MSMG_BF16}[rc.dtype]
+    rf = torch.empty(8 * nx * ny * nz, dtype=rc.dtype, device=rc.device)
+    L.check(L.lib().msmg_prolong_element(nx, ny, nz, _ptr(rc), _ptr(rf), dt, _stream()), "msmg_prolong_element")
+    return rf

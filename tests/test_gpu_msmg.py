@@ -1,0 +1,187 @@
+"""GPU parity of the multiscale-multigrid set-up, preconditioner and PCG
+against the oracle (through the C ABI)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from gpu_common import KMAX, P, field, max_sin_angle, oracle_hier, patch_mask, rel, to_dev  # noqa: E402
+from oracle import msmg as omsmg  # noqa: E402
+from oracle import q1  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    # name: (n, kind, seed, kmin, H, sd)
+    "cube16_noise_H8": (16, "noise", 0, 1e-3, 8, 2),
+    "cube16_noise_H4": (16, "noise", 1, 1e-3, 4, 2),
+    "cube16_grf_c1e6_H4": (16, "grf", 2, 1e-6, 4, 2),
+    "cube24_grf_c1e4_H4": (24, "grf", 3, 1e-4, 4, 3),
+}
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    import paper_2410_06850_amd as p
+    return p
+
+
+_cache = {}
+
+
+def _pair(pkg, name, **opts):
+    key = (name, tuple(sorted(opts.items())))
+    if key in _cache:
+        return _cache[key]
+    n, kind, seed, kmin, H, sd = CASES[name]
+    rho = field(n, kind, seed)
+    mask = patch_mask(n)
+    g, h = oracle_hier(n, rho, kmin, mask, H, sd)
+    s = pkg.Solver(n, H=H, sd=sd, **opts)
+    s.setup(to_dev(rho), kmin, KMAX, P, to_dev(mask, torch.uint8))
+    _cache[key] = (g, h, s, rho, mask, kmin)
+    return _cache[key]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_local_eigenpairs_match_oracle(pkg, name):
+    print(f"case local-eigen {name}", flush=True)
+    g, h, s, rho, mask, kmin = _pair(pkg, name)
+    Lc = h.o.Lc
+    ev = s.export(0, h.n_c).numpy().reshape(-1, Lc)
+    st = s.export(5, len(h.cells), torch.int32).numpy()
+    Rc = s.export(1, g.nnodes * Lc).numpy().reshape(g.nnodes, Lc)
+    bound = 4.0 / g.hx ** 2
+    checked = 0
+    for ci in range(len(h.cells)):
+        want = h.cell_evals[ci]
+        nl = len(want)
+        assert ((st[ci] >> 20) & 0xFF) == nl
+        assert not (st[ci] >> 28) & 1, f"cell {ci} did not converge"
+        got = ev[ci, :nl]
+        assert np.all(np.abs(got - want) <= 1e-9 * np.maximum(np.abs(want), 1e-3 * bound)), (ci, got, want)
+        nodes, phi = h.cell_basis[ci]
+        K, m, _ = h.local_problem(*h.cells[ci])
+        lam_all = np.linalg.eigvalsh(K / np.sqrt(m)[:, None] / np.sqrt(m)[None, :])
+        gap = lam_all[nl] - lam_all[nl - 1] if nl < len(lam_all) else np.inf
+        if gap < 1e-6 * bound:
+            continue
+        sa = max_sin_angle(phi, Rc[nodes, :nl], m)
+        assert sa <= 1e-6, (ci, sa)
+        checked += 1
+    assert checked > 0
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_coarse_spectra_match_oracle(pkg, name):
+    """Basis-invariant checks of A_c, the cc eigenvalues and A_cc."""
+    print(f"case coarse-spectra {name}", flush=True)
+    g, h, s, rho, mask, kmin = _pair(pkg, name)
+    Lc = h.o.Lc
+    ncells = len(h.cells)
+    Ac = s.export(2, ncells * 27 * Lc * Lc).numpy().reshape(ncells, 27, Lc, Lc)
+    # assemble the GPU A_c densely (padded dofs are decoupled identities)
+    n_c = ncells * Lc
+    D = np.zeros((n_c, n_c))
+    for ci, (cx, cy, cz) in enumerate(h.cells):
+        for b in range(27):
+            ox, oy, oz = b % 3 - 1, (b // 3) % 3 - 1, b // 9 - 1
+            x, y, z = cx + ox, cy + oy, cz + oz
+            if 0 <= x < h.nc[0] and 0 <= y < h.nc[1] and 0 <= z < h.nc[2]:
+                cj = h.cell_id(x, y, z)
+                D[ci * Lc:(ci + 1) * Lc, cj * Lc:(cj + 1) * Lc] = Ac[ci, b]
+    valid = np.concatenate([np.arange(len(h.cell_rows[ci])) + ci * Lc for ci in range(ncells)])
+    Dg = D[np.ix_(valid, valid)]
+    assert np.abs(Dg - Dg.T).max() <= 1e-11 * np.abs(Dg).max()
+    eg = np.linalg.eigvalsh(0.5 * (Dg + Dg.T))
+    eo = np.linalg.eigvalsh(h.Ac.toarray())
+    assert np.abs(eg - eo).max() <= 1e-9 * np.abs(eo).max()
+    cc = s.export(3, h.n_cc).numpy()
+    want = np.concatenate(h.cc_evals)
+    assert np.abs(cc - want).max() <= 1e-8 * np.abs(want).max() + 1e-12
+    Acc = s.export(4, h.n_cc * h.n_cc).numpy().reshape(h.n_cc, h.n_cc)
+    e1 = np.linalg.eigvalsh(0.5 * (Acc + Acc.T))
+    e2 = np.linalg.eigvalsh(h.Acc)
+    assert np.abs(e1 - e2).max() <= 1e-8 * np.abs(e2).max()
+
+
+def _predicted_subspace_error(g, h, tol=1e-12):
+    """Eigenvector error bound ~ residual / gap of both spectral levels."""
+    b1 = 4.0 / g.hx ** 2
+    e1 = max(tol * b1 / gp for gp in h.cell_gaps)
+    e2 = max(tol * nrm / gp for gp, nrm in zip(h.cc_gaps, h.cc_norms))
+    return max(e1, e2)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_preconditioner_apply_matches_oracle(pkg, name):
+    """P4: z = M^-1 r is basis invariant, so it matches to the accuracy of the
+    computed coarse spaces (1e-10, or residual/gap where spectral gaps are small)."""
+    print(f"case precondition {name}", flush=True)
+    g, h, s, rho, mask, kmin = _pair(pkg, name)
+    r = np.random.default_rng(4).standard_normal(g.nnodes)
+    r[mask.astype(bool)] = 0.0
+    want = h.precondition(r)
+    got = s.precondition(to_dev(r)).cpu().numpy()
+    bound = max(1e-10, 100 * _predicted_subspace_error(g, h))
+    print(f"  rel={rel(got, want):.3e} bound={bound:.3e}")
+    assert rel(got, want) <= bound
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_solve_matches_oracle(pkg, name):
+    print(f"case solve {name}", flush=True)
+    g, h, s, rho, mask, kmin = _pair(pkg, name)
+    n, kind = CASES[name][0], CASES[name][1]
+    f = q1.element_load(g, 1.0)
+    A = q1.assemble(g, h.k)
+    rtol = 1e-12 if kind == "noise" else 1e-10
+    Tlo = torch.empty(g.nnodes, dtype=torch.float64, device="cuda")
+    T, info = s.solve(to_dev(f), rtol=rtol, maxit=500, T_lo=Tlo)
+    assert info.code == 0, info
+    T, Tlo = T.cpu().numpy(), Tlo.cpu().numpy()
+    # P2: the oracle's own residual of the GPU iterate
+    assert q1.relative_residual_diff(A, T, f, mask, T_lo=Tlo) <= rtol * (1 + 1e-2)
+    To, res, _ = omsmg.solve(g, rho, f, mask, kmin, KMAX, P, hier=h, rtol=rtol, maxit=500)
+    assert res.status == "converged"
+    err = rel(T + Tlo, To + res.x_lo)
+    print(f"  gpu it={info.iterations} oracle it={res.iterations} rel.err={err:.3e}")
+    # P1: forward parity where the conditioning allows it
+    assert err <= (1e-10 if kind == "noise" else 1e-4)
+    # P5: iteration counts of the same algorithm
+    _, info8 = s.solve(to_dev(f), rtol=1e-8, maxit=500)
+    _, res8, _ = omsmg.solve(g, rho, f, mask, kmin, KMAX, P, hier=h, rtol=1e-8)
+    print(f"  rtol 1e-8: gpu it={info8.iterations} oracle it={res8.iterations}")
+    slack = 1 if kind == "noise" else max(1, int(0.1 * res8.iterations))
+    assert abs(info8.iterations - res8.iterations) <= slack, (info8.iterations, res8.iterations)
+
+
+def test_mixed_precision_solve(pkg):
+    name = "cube16_grf_c1e6_H4"
+    print(f"case mixed {name}", flush=True)
+    g, h, s64, rho, mask, kmin = _pair(pkg, name)
+    s32 = pkg.Solver(16, H=4, sd=2, vcycle_dtype=1, rho_v_dtype=2, basis_dtype=2)
+    s32.setup(to_dev(rho), kmin, KMAX, P, to_dev(mask, torch.uint8))
+    f = q1.element_load(g, 1.0)
+    A = q1.assemble(g, h.k)
+    T64, i64 = s64.solve(to_dev(f), rtol=1e-8)
+    Tlo = torch.empty(g.nnodes, dtype=torch.float64, device="cuda")
+    T32, i32 = s32.solve(to_dev(f), rtol=1e-8, T_lo=Tlo)
+    print(f"  iterations fp64={i64.iterations} mixed={i32.iterations}")
+    assert i32.code == 0 and i64.code == 0
+    assert q1.relative_residual_diff(A, T32.cpu().numpy(), f, mask, T_lo=Tlo.cpu().numpy()) <= 1e-8 * (1 + 1e-3)
+    assert i32.iterations <= int(1.1 * i64.iterations) + 1
+    # the answer does not depend on the preconditioner's precision
+    Ta, _ = s64.solve(to_dev(f), rtol=1e-10)
+    Tb, _ = s32.solve(to_dev(f), rtol=1e-10)
+    assert rel(Tb.cpu().numpy(), Ta.cpu().numpy()) <= 1e-7
+
+
+def test_deterministic(pkg):
+    name = "cube16_noise_H4"
+    print(f"case determinism {name}", flush=True)
+    g, h, s, rho, mask, kmin = _pair(pkg, name)
+    f = to_dev(q1.element_load(g, 1.0))
+    T1, _ = s.solve(f, rtol=1e-10)
+    T2, _ = s.solve(f, rtol=1e-10)
+    assert torch.equal(T1, T2)

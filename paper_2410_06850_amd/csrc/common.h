@@ -57,6 +57,15 @@ template <> MSMG_HD float ld<float, double>(const double* p, long long i) { retu
 template <> MSMG_HD float ld<float, float>(const float* p, long long i) { return p[i]; }
 template <> MSMG_HD float ld<float, bf16>(const bf16* p, long long i) { return bf16_to_float(p[i]); }
 
+// convert a raw stored value to the working type W
+template <typename W, typename T> MSMG_HD W cvt(T v);
+template <> MSMG_HD double cvt<double, double>(double v) { return v; }
+template <> MSMG_HD double cvt<double, float>(float v) { return double(v); }
+template <> MSMG_HD double cvt<double, bf16>(bf16 v) { return double(bf16_to_float(v)); }
+template <> MSMG_HD float cvt<float, double>(double v) { return float(v); }
+template <> MSMG_HD float cvt<float, float>(float v) { return v; }
+template <> MSMG_HD float cvt<float, bf16>(bf16 v) { return bf16_to_float(v); }
+
 template <typename T> MSMG_HD T from_f64(double v);
 template <> MSMG_HD double from_f64<double>(double v) { return v; }
 template <> MSMG_HD float from_f64<float>(double v) { return float(v); }
@@ -307,35 +316,47 @@ struct Scalars {
 
 enum SolveStatus { ST_RUNNING = 0, ST_CONV_RECURSIVE = 1, ST_MAXIT = 2, ST_BREAKDOWN = 3, ST_NONFINITE = 4 };
 
-// Cross-block deterministic reduction: each block writes its partials, the
+// Cross-block deterministic reduction: each block publishes its partials, the
 // last block to finish sums all partials in block order and runs `fin`.
+//
+// No memory fence is used: on a multi-XCD device a fence at agent scope writes
+// back and invalidates the whole L2 of the XCD, which costs far more than the
+// reduction when every block issues one.  Instead the partials are published
+// with agent-scope atomic exchanges; the block waits for their results before
+// taking a ticket from the counter, so every partial is in place at the
+// coherence point before the last ticket is handed out, and the last block
+// reads them back with agent-scope atomic loads.
 template <int NV, typename Fin>
 MSMG_DEV void grid_reduce(double (&v)[NV], double* red, double* partials, unsigned* counter,
                           int nblocks, int bid, Fin fin) {
   block_sum<NV>(v, red);
   const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+  unsigned long long* P = reinterpret_cast<unsigned long long*>(partials);
   __shared__ int is_last;
   if (tid == 0) {
+    unsigned long long seen = 0;
 #pragma unroll
-    for (int q = 0; q < NV; ++q) partials[(long long)q * nblocks + bid] = v[q];
-    __threadfence();
-    const unsigned ticket = atomicAdd(counter, 1u);
+    for (int q = 0; q < NV; ++q)
+      seen |= __hip_atomic_exchange(&P[(long long)q * nblocks + bid], (unsigned long long)__double_as_longlong(v[q]),
+                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    asm volatile("" ::"v"(seen) : "memory");  // the exchanges have completed
+    const unsigned ticket = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     is_last = (ticket == unsigned(nblocks - 1));
   }
   __syncthreads();
   if (!is_last) return;
-  __threadfence();
   const int nthreads = blockDim.x * blockDim.y * blockDim.z;
   double s[NV];
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
     s[q] = 0.0;
     for (int b = tid; b < nblocks; b += nthreads)
-      s[q] += __hip_atomic_load(&partials[(long long)q * nblocks + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s[q] += __longlong_as_double((long long)__hip_atomic_load(&P[(long long)q * nblocks + b], __ATOMIC_RELAXED,
+                                                                __HIP_MEMORY_SCOPE_AGENT));
   }
   block_sum<NV>(s, red);
   if (tid == 0) {
-    *counter = 0u;
+    __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     fin(s);
   }
 }

@@ -163,30 +163,60 @@ __global__ void k_update_p(double* __restrict__ p, const double* __restrict__ z,
   const Tile t = tile_of_thread(g, h, CX, tile);
 
 // y = A x on free rows (0 on fixed rows); optional p^T (A p) reduction -> alpha.
-//   mode 0: plain apply; 1: PCG apply with pq -> alpha; 2: masked public form P A P x + (I-P) x
-template <typename RT, bool CUBIC>
+//   MODE 0: plain apply; 1: PCG apply with pq -> alpha; 2: masked public form P A P x + (I-P) x
+struct ApplyCentre {
+  uint32_t w;  // mask word of the node
+  double x;    // x_n (MODE 2 only)
+};
+struct MaskedRaw {
+  double v;
+  uint32_t w;
+  int sh;
+};
+
+template <typename RT, bool CUBIC, int MODE>
 __global__ __launch_bounds__(MARCH_THREADS) void k_apply(Geo g, Stencil st, March mg, const RT* __restrict__ rho,
                                                          Material m, const uint32_t* __restrict__ bits,
-                                                         const double* __restrict__ x, double* __restrict__ y, int mode,
+                                                         const double* __restrict__ x, double* __restrict__ y,
                                                          Scalars* sc, double* partials, unsigned* counter) {
-  if (mode == 1 && sc->done) return;
+  if (MODE == 1 && sc->done) return;
   __shared__ double sx[2 * PW * PH];
   __shared__ double sk[2 * EW * EH];
   __shared__ double red[16];
   const long long tile = xcd_tile(blockIdx.x, gridDim.x);
   const double dk = m.kmax - m.kmin;
   double s[1] = {0.0};
-  march<double, CUBIC>(
-      g, st, mg, tile, sx, sk,
-      [&](long long n) { return (mode == 2 && mask_bit(bits, n)) ? 0.0 : x[n]; },
-      [&](long long e) { return conductivity<double>(ld<double, RT>(rho, e), m.kmin, dk, m.p); },
-      [&](int, int, int, long long n, double ax, double xc) {
-        double out = ax;
-        if (mask_bit(bits, n)) out = (mode == 2) ? x[n] : 0.0;
-        y[n] = out;
-        if (mode == 1) s[0] += xc * out;
-      });
-  if (mode != 1) return;
+  auto loadk = [&](long long e) { return rho[e]; };
+  auto convk = [&](RT v) { return conductivity<double>(cvt<double, RT>(v), m.kmin, dk, m.p); };
+  auto loadc = [&](long long n) {
+    ApplyCentre c;
+    c.w = bits[n >> 5];
+    c.x = MODE == 2 ? x[n] : 0.0;
+    return c;
+  };
+  auto emit = [&](int, int, int, long long n, double ax, double xc, const ApplyCentre& c) {
+    double out = ax;
+    if ((c.w >> (n & 31)) & 1u) out = (MODE == 2) ? c.x : 0.0;
+    y[n] = out;
+    if (MODE == 1) s[0] += xc * out;
+  };
+  if (MODE == 2) {
+    march<double, CUBIC>(
+        g, st, mg, tile, sx, sk,
+        [&](long long n) {
+          MaskedRaw r;
+          r.v = x[n];
+          r.w = bits[n >> 5];
+          r.sh = int(n & 31);
+          return r;
+        },
+        [&](const MaskedRaw& r) { return ((r.w >> r.sh) & 1u) ? 0.0 : r.v; }, loadk, convk, loadc, emit);
+  } else {
+    march<double, CUBIC>(
+        g, st, mg, tile, sx, sk, [&](long long n) { return x[n]; }, [&](double v) { return v; }, loadk, convk, loadc,
+        emit);
+  }
+  if (MODE != 1) return;
   grid_reduce<1>(s, red, partials, counter, gridDim.x, blockIdx.x, [&](double* tt) {
     sc->pq = tt[0];
     if (!(tt[0] > 0.0) || !(sc->rz > 0.0)) {
@@ -237,12 +267,12 @@ __global__ void k_residual(Geo g, Stencil st, Hier h, int CX, const RT* __restri
 // D^-1 A: theta = (hi+lo)/2, delta = (hi-lo)/2, sigma = theta/delta.
 
 // Step 1 of the smoother (degree 1, or the start of higher degrees): x1 = D^-1 r / theta.
-template <typename VT, typename IT>
-__global__ void k_cheb_first(const IT* __restrict__ r, const VT* __restrict__ dinv, VT* __restrict__ x,
+template <typename VT, typename IT, typename DT>
+__global__ void k_cheb_first(const IT* __restrict__ r, const DT* __restrict__ dinv, VT* __restrict__ x,
                              VT* __restrict__ d, long long nn, double inv_theta, const Scalars* sc) {
   if (sc && sc->done) return;
   for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < nn; n += (long long)gridDim.x * blockDim.x) {
-    const VT v = VT(ld<VT, IT>(r, n) * dinv[n] * VT(inv_theta));
+    const VT v = VT(ld<VT, IT>(r, n) * VT(dinv[n]) * VT(inv_theta));
     x[n] = v;
     if (d) d[n] = v;
   }
@@ -252,10 +282,16 @@ __global__ void k_cheb_first(const IT* __restrict__ r, const VT* __restrict__ di
 //   z1 = D^-1 r / theta,  out = (1 + rho1 rho0) z1 + (2 rho1 / delta) D^-1 (r - A z1)
 // with z1 staged for the neighbours straight from r and D^-1.  When `dout` is
 // given the second direction d1 = out - z1 is stored for further steps.
-template <typename VT, typename RT, typename IT, bool CUBIC>
+template <typename DT, typename IT>
+struct RD {
+  IT r;
+  DT di;
+};
+
+template <typename VT, typename RT, typename IT, typename DT, bool CUBIC>
 __global__ __launch_bounds__(MARCH_THREADS) void k_cheb2(Geo g, Stencil st, March mg, const RT* __restrict__ rho,
                                                          Material m, const IT* __restrict__ r,
-                                                         const VT* __restrict__ dinv, VT* __restrict__ out,
+                                                         const DT* __restrict__ dinv, VT* __restrict__ out,
                                                          VT* __restrict__ dout, ChebCoef cc, const Scalars* sc) {
   if (sc && sc->done) return;
   __shared__ VT sx[2 * PW * PH];
@@ -263,23 +299,36 @@ __global__ __launch_bounds__(MARCH_THREADS) void k_cheb2(Geo g, Stencil st, Marc
   const long long tile = xcd_tile(blockIdx.x, gridDim.x);
   const VT dk = VT(m.kmax - m.kmin), kmin = VT(m.kmin);
   const VT it = VT(cc.inv_theta), c0 = VT(cc.c0), c1 = VT(cc.c1);
+  auto loadrd = [&](long long n) {
+    RD<DT, IT> v;
+    v.r = r[n];
+    v.di = dinv[n];
+    return v;
+  };
   march<VT, CUBIC>(
-      g, st, mg, tile, sx, sk, [&](long long n) { return ld<VT, IT>(r, n) * dinv[n] * it; },
-      [&](long long e) { return conductivity<VT>(ld<VT, RT>(rho, e), kmin, dk, m.p); },
-      [&](int, int, int, long long n, VT az, VT z1) {
-        const VT di = dinv[n];
+      g, st, mg, tile, sx, sk, loadrd, [&](const RD<DT, IT>& v) { return cvt<VT, IT>(v.r) * VT(v.di) * it; },
+      [&](long long e) { return rho[e]; },
+      [&](RT v) { return conductivity<VT>(cvt<VT, RT>(v), kmin, dk, m.p); }, loadrd,
+      [&](int, int, int, long long n, VT az, VT z1, const RD<DT, IT>& c) {
         VT v = VT(0);
-        if (di != VT(0)) v = c0 * z1 + c1 * di * (ld<VT, IT>(r, n) - az);
+        if (c.di != DT(0)) v = c0 * z1 + c1 * VT(c.di) * (cvt<VT, IT>(c.r) - az);
         out[n] = v;
         if (dout) dout[n] = v - z1;
       });
 }
 
 // Generic Chebyshev step k >= 3:  res = r - A x;  d = a d + b D^-1 res;  xout = x + d.
-template <typename VT, typename RT, typename IT, bool CUBIC>
+template <typename VT, typename IT, typename DT>
+struct RDD {
+  IT r;
+  DT di;
+  VT d;
+};
+
+template <typename VT, typename RT, typename IT, typename DT, bool CUBIC>
 __global__ __launch_bounds__(MARCH_THREADS) void k_cheb_step(Geo g, Stencil st, March mg, const RT* __restrict__ rho,
                                                              Material m, const IT* __restrict__ r,
-                                                             const VT* __restrict__ dinv, const VT* __restrict__ x,
+                                                             const DT* __restrict__ dinv, const VT* __restrict__ x,
                                                              VT* __restrict__ d, VT* __restrict__ xout, double ca,
                                                              double cb, const Scalars* sc) {
   if (sc && sc->done) return;
@@ -288,52 +337,83 @@ __global__ __launch_bounds__(MARCH_THREADS) void k_cheb_step(Geo g, Stencil st, 
   const long long tile = xcd_tile(blockIdx.x, gridDim.x);
   const VT dk = VT(m.kmax - m.kmin), kmin = VT(m.kmin);
   march<VT, CUBIC>(
-      g, st, mg, tile, sx, sk, [&](long long n) { return x[n]; },
-      [&](long long e) { return conductivity<VT>(ld<VT, RT>(rho, e), kmin, dk, m.p); },
-      [&](int, int, int, long long n, VT ax, VT xc) {
-        const VT di = dinv[n];
-        if (di == VT(0)) {
+      g, st, mg, tile, sx, sk, [&](long long n) { return x[n]; }, [&](VT v) { return v; },
+      [&](long long e) { return rho[e]; },
+      [&](RT v) { return conductivity<VT>(cvt<VT, RT>(v), kmin, dk, m.p); },
+      [&](long long n) {
+        RDD<VT, IT, DT> c;
+        c.r = r[n];
+        c.di = dinv[n];
+        c.d = d[n];
+        return c;
+      },
+      [&](int, int, int, long long n, VT ax, VT xc, const RDD<VT, IT, DT>& c) {
+        if (c.di == DT(0)) {
           d[n] = VT(0);
           xout[n] = VT(0);
           return;
         }
-        const VT dn = VT(ca) * d[n] + VT(cb) * di * (ld<VT, IT>(r, n) - ax);
+        const VT dn = VT(ca) * c.d + VT(cb) * VT(c.di) * (cvt<VT, IT>(c.r) - ax);
         d[n] = dn;
         xout[n] = xc + dn;
       });
 }
 
-// Restriction of Algorithm 1:  rc[cell][l] = sum_{n in cell} R_c[n][l] (r_n - (A x)_n)
-// over owned free nodes.  One block holds whole coarse cells, so the per-cell
-// sums finish in the block (fixed order).
-template <typename VT, typename RT, typename BT, typename IT, bool CUBIC>
-__global__ void k_restrict(Geo g, Stencil st, Hier h, int CX, const RT* __restrict__ rho, Material m,
-                           const uint32_t* __restrict__ bits, const IT* __restrict__ r, const VT* __restrict__ x,
-                           const BT* __restrict__ Rc, double* __restrict__ rc, const Scalars* sc) {
+// One row of R_c (L basis values of node n) widened to FP64, with one vector
+// load when the row is 4, 8, 16 or 32 bytes (rows start at multiples of the
+// row size, so these loads are aligned).
+template <typename BT, int L>
+MSMG_DEV void load_row(const BT* __restrict__ Rc, long long n, double out[L]) {
+  constexpr int B = L * int(sizeof(BT));
+  BT v[L];
+  if constexpr (B == 32) {
+    const uint4* p = reinterpret_cast<const uint4*>(Rc + n * L);
+    const uint4 w0 = p[0], w1 = p[1];
+    __builtin_memcpy(v, &w0, 16);
+    __builtin_memcpy(reinterpret_cast<char*>(v) + 16, &w1, 16);
+  } else if constexpr (B == 16) {
+    const uint4 w = *reinterpret_cast<const uint4*>(Rc + n * L);
+    __builtin_memcpy(v, &w, 16);
+  } else if constexpr (B == 8) {
+    const uint2 w = *reinterpret_cast<const uint2*>(Rc + n * L);
+    __builtin_memcpy(v, &w, 8);
+  } else if constexpr (B == 4) {
+    const uint32_t w = *reinterpret_cast<const uint32_t*>(Rc + n * L);
+    __builtin_memcpy(v, &w, 4);
+  } else {
+#pragma unroll
+    for (int l = 0; l < L; ++l) v[l] = Rc[n * L + l];
+  }
+#pragma unroll
+  for (int l = 0; l < L; ++l) out[l] = to_f64(v[l]);
+}
+
+// Restriction of Algorithm 1:  rc[cell][l] = sum_{n in cell} R_c[n][l] r_n over
+// the nodes a cell owns (r and R_c vanish on fixed nodes).  One block holds
+// whole coarse cells, so the per-cell sums finish in the block (fixed order).
+template <typename VT, typename BT, int L>
+__global__ void k_restrict(Geo g, Hier h, int CX, const VT* __restrict__ r, const BT* __restrict__ Rc,
+                           double* __restrict__ rc, const Scalars* sc) {
   if (sc && sc->done) return;
   extern __shared__ double smem[];
   TILE_PROLOGUE
-  const int L = h.Lc;
-  const VT dk = VT(m.kmax - m.kmin), kmin = VT(m.kmin);
-  double acc[LC_MAX];
+  double acc[L];
 #pragma unroll
-  for (int l = 0; l < LC_MAX; ++l) acc[l] = 0.0;
+  for (int l = 0; l < L; ++l) acc[l] = 0.0;
   if (t.active) {
-    for (int k = t.zs; k < t.ze; ++k)
-      for (int j = t.ys; j < t.ye; ++j)
-        for (int i = t.xs; i < t.xe; ++i) {
-          const long long n = node_id(g, i, j, k);
-          if (mask_bit(bits, n)) continue;
-          VT res = ld<VT, IT>(r, n);
-          if (x) {
-            VT kk[8];
-            load_k8<VT, RT>(g, rho, kmin, dk, m.p, i, j, k, kk);
-            res -= gather_apply<VT, CUBIC>(g, st, kk, i, j, k, [&](int a, int b, int c) { return x[node_id(g, a, b, c)]; });
-          }
+    for (int j = t.ys; j < t.ye; ++j)
+      for (int i = t.xs; i < t.xe; ++i) {
+        const long long n0 = node_id(g, i, j, t.zs), pl = (long long)g.nnx * g.nny;
+#pragma unroll 4
+        for (int k = 0; k < t.ze - t.zs; ++k) {
+          const long long n = n0 + k * pl;
+          double row[L];
+          load_row<BT, L>(Rc, n, row);
+          const double res = double(r[n]);
 #pragma unroll
-          for (int l = 0; l < LC_MAX; ++l)
-            if (l < L) acc[l] += double(ld<VT, BT>(Rc, n * L + l) * res);
+          for (int l = 0; l < L; ++l) acc[l] += row[l] * res;
         }
+      }
   }
   // per-cell reduction in fixed order.  Each wave is one node row of the tile
   // (blockDim.x = CX*H = 64 when H divides 64): groups of H lanes belong to one
@@ -346,14 +426,14 @@ __global__ void k_restrict(Geo g, Stencil st, Hier h, int CX, const RT* __restri
   const bool pow2 = (h.H & (h.H - 1)) == 0 && blockDim.x == 64;
   if (pow2) {
 #pragma unroll
-    for (int l = 0; l < LC_MAX; ++l) {
-      if (l >= L) break;
+    for (int l = 0; l < L; ++l) {
       double v = acc[l];
       for (int off = 1; off < h.H; off <<= 1) v += __shfl_xor(v, off, 64);
       acc[l] = v;
     }
     if ((threadIdx.x % h.H) == 0) {
       const int cl = threadIdx.x / h.H;
+#pragma unroll
       for (int l = 0; l < L; ++l) red[(threadIdx.y * CX + cl) * L + l] = acc[l];
     }
     __syncthreads();
@@ -368,6 +448,7 @@ __global__ void k_restrict(Geo g, Stencil st, Hier h, int CX, const RT* __restri
     }
     return;
   }
+#pragma unroll
   for (int l = 0; l < L; ++l) red[l * nthr + tid] = acc[l];
   __syncthreads();
   for (int q = tid; q < CX * L; q += nthr) {
@@ -384,37 +465,45 @@ __global__ void k_restrict(Geo g, Stencil st, Hier h, int CX, const RT* __restri
 
 // Prolongation of Algorithm 1: out = base + sum_l R_c[n][l] (e1 + e2)[owner(n)][l]
 // (e2 optional).  Fixed nodes stay 0 (R_c vanishes there).
-template <typename VT, typename BT>
+template <typename VT, typename BT, int L>
 __global__ void k_prolong(Geo g, Hier h, int CX, const VT* __restrict__ base, const BT* __restrict__ Rc,
                           const double* __restrict__ e1, const double* __restrict__ e2, double* __restrict__ out,
                           const Scalars* sc) {
   if (sc && sc->done) return;
   TILE_PROLOGUE
   if (!t.active) return;
-  const int L = h.Lc;
   const long long cell = ((long long)t.cz * h.ncy + t.cy) * h.ncx + t.cx;
-  double e[LC_MAX];
+  double e[L];
 #pragma unroll
-  for (int l = 0; l < LC_MAX; ++l) e[l] = (l < L) ? e1[cell * L + l] + (e2 ? e2[cell * L + l] : 0.0) : 0.0;
-#pragma unroll 3
-  for (int k = t.zs; k < t.ze; ++k)
-    for (int j = t.ys; j < t.ye; ++j)
-      for (int i = t.xs; i < t.xe; ++i) {
-        const long long n = node_id(g, i, j, k);
+  for (int l = 0; l < L; ++l) e[l] = e1[cell * L + l] + (e2 ? e2[cell * L + l] : 0.0);
+  for (int j = t.ys; j < t.ye; ++j)
+    for (int i = t.xs; i < t.xe; ++i) {
+      const long long n0 = node_id(g, i, j, t.zs), pl = (long long)g.nnx * g.nny;
+#pragma unroll 4
+      for (int k = 0; k < t.ze - t.zs; ++k) {
+        const long long n = n0 + k * pl;
+        double row[L];
+        load_row<BT, L>(Rc, n, row);
         double v = base ? double(base[n]) : 0.0;
 #pragma unroll
-        for (int l = 0; l < LC_MAX; ++l)
-          if (l < L) v += ld<double, BT>(Rc, n * L + l) * e[l];
+        for (int l = 0; l < L; ++l) v += row[l] * e[l];
         out[n] = v;
       }
+    }
 }
 
 // V-cycle residual on level 0:  out = r - A x (free rows).  The stencil runs in
 // the type of x: after the coarse correction x carries the large, nearly flat
 // values of the low-energy modes and is kept (and differenced) in FP64.
+template <typename IT>
+struct RW {
+  IT r;
+  uint32_t w;
+};
+
 template <typename VT, typename RT, typename IT, typename XT, bool CUBIC>
 __global__ __launch_bounds__(MARCH_THREADS) void k_vresidual(Geo g, Stencil st, March mg, const RT* __restrict__ rho,
-                                                             Material m, const VT* __restrict__ dinv,
+                                                             Material m, const uint32_t* __restrict__ bits,
                                                              const IT* __restrict__ r, const XT* __restrict__ x,
                                                              VT* __restrict__ out, const Scalars* sc) {
   if (sc && sc->done) return;
@@ -423,10 +512,17 @@ __global__ __launch_bounds__(MARCH_THREADS) void k_vresidual(Geo g, Stencil st, 
   const long long tile = xcd_tile(blockIdx.x, gridDim.x);
   const XT dk = XT(m.kmax - m.kmin), kmin = XT(m.kmin);
   march<XT, CUBIC>(
-      g, st, mg, tile, sx, sk, [&](long long n) { return x[n]; },
-      [&](long long e) { return conductivity<XT>(ld<XT, RT>(rho, e), kmin, dk, m.p); },
-      [&](int, int, int, long long n, XT ax, XT) {
-        out[n] = (dinv[n] == VT(0)) ? VT(0) : VT(ld<XT, IT>(r, n) - ax);
+      g, st, mg, tile, sx, sk, [&](long long n) { return x[n]; }, [&](XT v) { return v; },
+      [&](long long e) { return rho[e]; },
+      [&](RT v) { return conductivity<XT>(cvt<XT, RT>(v), kmin, dk, m.p); },
+      [&](long long n) {
+        RW<IT> c;
+        c.r = r[n];
+        c.w = bits[n >> 5];
+        return c;
+      },
+      [&](int, int, int, long long n, XT ax, XT, const RW<IT>& c) {
+        out[n] = ((c.w >> (n & 31)) & 1u) ? VT(0) : VT(cvt<XT, IT>(c.r) - ax);
       });
 }
 
@@ -687,9 +783,11 @@ static inline dim3 march_block() { return dim3(MX, MY); }
 
 void launch_apply(const Ctx& c, const double* x, double* y, int mode, hipStream_t s) {
   const dim3 gr = march_grid(c), bl = march_block();
-#define AP(RT, CU) hipLaunchKernelGGL((k_apply<RT, CU>), gr, bl, 0, s, c.g, c.st, c.mg, (const RT*)c.rho, c.mat, c.bits, x, y, mode, c.sc, c.partials, c.counter)
-  if (c.rho_dt == DT_F64) { if (c.st.cubic) AP(double, true); else AP(double, false); }
-  else { if (c.st.cubic) AP(float, true); else AP(float, false); }
+#define AP(RT, CU, MD) hipLaunchKernelGGL((k_apply<RT, CU, MD>), gr, bl, 0, s, c.g, c.st, c.mg, (const RT*)c.rho, c.mat, c.bits, x, y, c.sc, c.partials, c.counter)
+#define AP_M(RT, CU) do { if (mode == 0) AP(RT, CU, 0); else if (mode == 1) AP(RT, CU, 1); else AP(RT, CU, 2); } while (0)
+  if (c.rho_dt == DT_F64) { if (c.st.cubic) AP_M(double, true); else AP_M(double, false); }
+  else { if (c.st.cubic) AP_M(float, true); else AP_M(float, false); }
+#undef AP_M
 #undef AP
 }
 
@@ -705,21 +803,36 @@ void launch_residual(const Ctx& c, const double* b, const double* x, const doubl
 
 // --- V-cycle level 0 ---------------------------------------------------------
 
-// dispatch over (VT, RVT, BT) of the V-cycle and CUBIC
-#define VC_DISPATCH(...)                                                                          \
-  do {                                                                                             \
-    if (c.v_dt == DT_F64) {                                                                        \
-      using VT = double;                                                                           \
-      using BT = double;                                                                           \
-      if (c.rhov_dt == DT_F64) { using RVT = double; if (c.st.cubic) { constexpr bool CU = true; __VA_ARGS__; } else { constexpr bool CU = false; __VA_ARGS__; } } \
-      else { using RVT = float; if (c.st.cubic) { constexpr bool CU = true; __VA_ARGS__; } else { constexpr bool CU = false; __VA_ARGS__; } } \
-    } else {                                                                                       \
-      using VT = float;                                                                            \
-      if (c.rhov_dt == DT_BF16 && c.b_dt == DT_BF16) { using RVT = bf16; using BT = bf16; if (c.st.cubic) { constexpr bool CU = true; __VA_ARGS__; } else { constexpr bool CU = false; __VA_ARGS__; } } \
-      else if (c.rhov_dt == DT_BF16) { using RVT = bf16; using BT = float; if (c.st.cubic) { constexpr bool CU = true; __VA_ARGS__; } else { constexpr bool CU = false; __VA_ARGS__; } } \
-      else if (c.b_dt == DT_BF16) { using RVT = float; using BT = bf16; if (c.st.cubic) { constexpr bool CU = true; __VA_ARGS__; } else { constexpr bool CU = false; __VA_ARGS__; } } \
-      else { using RVT = float; using BT = float; if (c.st.cubic) { constexpr bool CU = true; __VA_ARGS__; } else { constexpr bool CU = false; __VA_ARGS__; } } \
-    }                                                                                              \
+// dispatch over the cycle's types and CUBIC: VT vectors, RVT density copy, BT
+// basis R_c, DVT the Jacobi diagonal (FP64 only on the all-FP64 path)
+#define VC_CASE(VT_, RVT_, BT_, DVT_, ...)                                 \
+  {                                                                        \
+    using VT = VT_;                                                        \
+    using RVT = RVT_;                                                      \
+    using BT = BT_;                                                        \
+    using DVT = DVT_;                                                      \
+    if (c.st.cubic) {                                                      \
+      constexpr bool CU = true;                                            \
+      __VA_ARGS__;                                                         \
+    } else {                                                               \
+      constexpr bool CU = false;                                           \
+      __VA_ARGS__;                                                         \
+    }                                                                      \
+  }
+#define VC_DISPATCH(...)                                                                       \
+  do {                                                                                         \
+    if (c.v_dt == DT_F64) {                                                                    \
+      if (c.b_dt == DT_F64) {                                                                  \
+        if (c.rhov_dt == DT_F64) VC_CASE(double, double, double, double, __VA_ARGS__)          \
+        else VC_CASE(double, float, double, double, __VA_ARGS__)                               \
+      } else if (c.b_dt == DT_BF16) VC_CASE(double, bf16, bf16, float, __VA_ARGS__)            \
+      else VC_CASE(double, float, float, float, __VA_ARGS__)                                   \
+    } else {                                                                                   \
+      if (c.rhov_dt == DT_BF16 && c.b_dt == DT_BF16) VC_CASE(float, bf16, bf16, float, __VA_ARGS__) \
+      else if (c.rhov_dt == DT_BF16) VC_CASE(float, bf16, float, float, __VA_ARGS__)           \
+      else if (c.b_dt == DT_BF16) VC_CASE(float, float, bf16, float, __VA_ARGS__)              \
+      else VC_CASE(float, float, float, float, __VA_ARGS__)                                    \
+    }                                                                                          \
   } while (0)
 
 // Level-0 smoother S^-1 applied to `in` (FP64 PCG residual when in_is_f64, else
@@ -729,43 +842,59 @@ void launch_smooth(const Ctx& c, const void* in, bool in_is_f64, void* out, hipS
   const int deg = c.cheb.degree;
   VC_DISPATCH({
     (void)sizeof(BT);
-    const VT* dinv = (const VT*)c.dinv;
+    const DVT* dinv = (const DVT*)c.dinv;
     VT* o = (VT*)out;
     if (deg == 1) {
       if (in_is_f64)
-        hipLaunchKernelGGL((k_cheb_first<VT, double>), dim3(grid1d(c.g.nn, 256, 8192)), dim3(256), 0, s, (const double*)in, dinv, o, (VT*)nullptr, c.g.nn, c.cheb.inv_theta, c.sc);
+        hipLaunchKernelGGL((k_cheb_first<VT, double, DVT>), dim3(grid1d(c.g.nn, 256, 8192)), dim3(256), 0, s, (const double*)in, dinv, o, (VT*)nullptr, c.g.nn, c.cheb.inv_theta, c.sc);
       else
-        hipLaunchKernelGGL((k_cheb_first<VT, VT>), dim3(grid1d(c.g.nn, 256, 8192)), dim3(256), 0, s, (const VT*)in, dinv, o, (VT*)nullptr, c.g.nn, c.cheb.inv_theta, c.sc);
+        hipLaunchKernelGGL((k_cheb_first<VT, VT, DVT>), dim3(grid1d(c.g.nn, 256, 8192)), dim3(256), 0, s, (const VT*)in, dinv, o, (VT*)nullptr, c.g.nn, c.cheb.inv_theta, c.sc);
     } else {
       // first two steps fused; further steps ping-pong between out and t1
       VT* d = deg > 2 ? (VT*)c.vc_t0 : nullptr;
       VT* xa = (deg % 2 == 0) ? o : (VT*)c.vc_t1;  // so that the last step lands in `out`
       VT* xb = (xa == o) ? (VT*)c.vc_t1 : o;
       if (in_is_f64)
-        hipLaunchKernelGGL((k_cheb2<VT, RVT, double, CU>), gr, bl, 0, s, c.g, c.st, c.mg, (const RVT*)c.rhov, c.mat, (const double*)in, dinv, xa, d, c.cheb, c.sc);
+        hipLaunchKernelGGL((k_cheb2<VT, RVT, double, DVT, CU>), gr, bl, 0, s, c.g, c.st, c.mg, (const RVT*)c.rhov, c.mat, (const double*)in, dinv, xa, d, c.cheb, c.sc);
       else
-        hipLaunchKernelGGL((k_cheb2<VT, RVT, VT, CU>), gr, bl, 0, s, c.g, c.st, c.mg, (const RVT*)c.rhov, c.mat, (const VT*)in, dinv, xa, d, c.cheb, c.sc);
+        hipLaunchKernelGGL((k_cheb2<VT, RVT, VT, DVT, CU>), gr, bl, 0, s, c.g, c.st, c.mg, (const RVT*)c.rhov, c.mat, (const VT*)in, dinv, xa, d, c.cheb, c.sc);
       for (int step = 2; step < deg; ++step) {
         const double ca = c.cheb.step_a[step], cb = c.cheb.step_b[step];
         if (in_is_f64)
-          hipLaunchKernelGGL((k_cheb_step<VT, RVT, double, CU>), gr, bl, 0, s, c.g, c.st, c.mg, (const RVT*)c.rhov, c.mat, (const double*)in, dinv, xa, d, xb, ca, cb, c.sc);
+          hipLaunchKernelGGL((k_cheb_step<VT, RVT, double, DVT, CU>), gr, bl, 0, s, c.g, c.st, c.mg, (const RVT*)c.rhov, c.mat, (const double*)in, dinv, xa, d, xb, ca, cb, c.sc);
         else
-          hipLaunchKernelGGL((k_cheb_step<VT, RVT, VT, CU>), gr, bl, 0, s, c.g, c.st, c.mg, (const RVT*)c.rhov, c.mat, (const VT*)in, dinv, xa, d, xb, ca, cb, c.sc);
+          hipLaunchKernelGGL((k_cheb_step<VT, RVT, VT, DVT, CU>), gr, bl, 0, s, c.g, c.st, c.mg, (const RVT*)c.rhov, c.mat, (const VT*)in, dinv, xa, d, xb, ca, cb, c.sc);
         VT* tmp = xa; xa = xb; xb = tmp;
       }
     }
   });
 }
 
-void launch_restrict(const Ctx& c, const void* r, bool r_is_f64, const void* x, void* rc, hipStream_t s) {
+// dispatch over the number of basis vectors per cell (1 .. LC_MAX)
+#define L_DISPATCH(Lrt, ...)                  \
+  do {                                        \
+    switch (Lrt) {                            \
+      case 1: { constexpr int LL = 1; __VA_ARGS__; } break; \
+      case 2: { constexpr int LL = 2; __VA_ARGS__; } break; \
+      case 3: { constexpr int LL = 3; __VA_ARGS__; } break; \
+      case 4: { constexpr int LL = 4; __VA_ARGS__; } break; \
+      case 5: { constexpr int LL = 5; __VA_ARGS__; } break; \
+      case 6: { constexpr int LL = 6; __VA_ARGS__; } break; \
+      case 7: { constexpr int LL = 7; __VA_ARGS__; } break; \
+      default: { constexpr int LL = 8; __VA_ARGS__; } break; \
+    }                                         \
+  } while (0)
+static_assert(LC_MAX == 8, "L_DISPATCH covers 1 .. 8");
+
+void launch_restrict(const Ctx& c, const void* r, void* rc, hipStream_t s) {
   const dim3 gr = tile_grid(c), bl = tile_block(c);
   const size_t nthr = size_t(bl.x) * bl.y;
   VC_DISPATCH({
+    (void)sizeof(RVT);
+    (void)sizeof(DVT);
+    (void)CU;
     const size_t sh = nthr * c.h.Lc * sizeof(double);
-    if (r_is_f64)
-      hipLaunchKernelGGL((k_restrict<VT, RVT, BT, double, CU>), gr, bl, sh, s, c.g, c.st, c.h, c.CX, (const RVT*)c.rhov, c.mat, c.bits, (const double*)r, (const VT*)x, (const BT*)c.Rc, (double*)rc, c.sc);
-    else
-      hipLaunchKernelGGL((k_restrict<VT, RVT, BT, VT, CU>), gr, bl, sh, s, c.g, c.st, c.h, c.CX, (const RVT*)c.rhov, c.mat, c.bits, (const VT*)r, (const VT*)x, (const BT*)c.Rc, (double*)rc, c.sc);
+    L_DISPATCH(c.h.Lc, hipLaunchKernelGGL((k_restrict<VT, BT, LL>), gr, bl, sh, s, c.g, c.h, c.CX, (const VT*)r, (const BT*)c.Rc, (double*)rc, c.sc));
   });
 }
 
@@ -773,8 +902,9 @@ void launch_prolong(const Ctx& c, const void* base, const void* e1, const void* 
   const dim3 gr = tile_grid(c), bl = tile_block(c);
   VC_DISPATCH({
     (void)sizeof(RVT);
+    (void)sizeof(DVT);
     (void)CU;
-    hipLaunchKernelGGL((k_prolong<VT, BT>), gr, bl, 0, s, c.g, c.h, c.CX, (const VT*)base, (const BT*)c.Rc, (const double*)e1, (const double*)e2, (double*)out, c.sc);
+    L_DISPATCH(c.h.Lc, hipLaunchKernelGGL((k_prolong<VT, BT, LL>), gr, bl, 0, s, c.g, c.h, c.CX, (const VT*)base, (const BT*)c.Rc, (const double*)e1, (const double*)e2, (double*)out, c.sc));
   });
 }
 
@@ -783,10 +913,11 @@ void launch_vresidual(const Ctx& c, const void* r, bool r_is_f64, const void* x,
   const dim3 gr = march_grid(c), bl = march_block();
   VC_DISPATCH({
     (void)sizeof(BT);
+    (void)sizeof(DVT);
     if (x_is_f64) {
-      hipLaunchKernelGGL((k_vresidual<VT, RVT, double, double, CU>), gr, bl, 0, s, c.g, c.st, c.mg, (const RVT*)c.rhov, c.mat, (const VT*)c.dinv, (const double*)r, (const double*)x, (VT*)out, c.sc);
+      hipLaunchKernelGGL((k_vresidual<VT, RVT, double, double, CU>), gr, bl, 0, s, c.g, c.st, c.mg, (const RVT*)c.rhov, c.mat, c.bits, (const double*)r, (const double*)x, (VT*)out, c.sc);
     } else {
-      hipLaunchKernelGGL((k_vresidual<VT, RVT, double, VT, CU>), gr, bl, 0, s, c.g, c.st, c.mg, (const RVT*)c.rhov, c.mat, (const VT*)c.dinv, (const double*)r, (const VT*)x, (VT*)out, c.sc);
+      hipLaunchKernelGGL((k_vresidual<VT, RVT, double, VT, CU>), gr, bl, 0, s, c.g, c.st, c.mg, (const RVT*)c.rhov, c.mat, c.bits, (const double*)r, (const VT*)x, (VT*)out, c.sc);
     }
     (void)r_is_f64;
   });

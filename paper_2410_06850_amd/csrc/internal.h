@@ -73,7 +73,7 @@ void launch_apply(const Ctx& c, const double* x, double* y, int mode, hipStream_
 void launch_residual(const Ctx& c, const double* b, const double* x, const double* xlo, double* y, bool reduce,
                      hipStream_t s);
 void launch_smooth(const Ctx& c, const void* in, bool in_is_f64, void* out, hipStream_t s);
-void launch_restrict(const Ctx& c, const void* r, bool r_is_f64, const void* x, void* rc, hipStream_t s);
+void launch_restrict(const Ctx& c, const void* r, void* rc, hipStream_t s);
 void launch_prolong(const Ctx& c, const void* base, const void* e1, const void* e2, void* out, hipStream_t s);
 void launch_vresidual(const Ctx& c, const void* r, bool r_is_f64, const void* x, bool x_is_f64, void* out,
                       hipStream_t s);

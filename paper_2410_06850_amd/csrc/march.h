@@ -2,20 +2,34 @@
 //
 // A workgroup of 64 x 8 threads owns a 64 x 8 column of nodes and marches over
 // a chunk of z planes.  Each step stages one node plane (with a 1-node halo,
-// 66 x 10 values) and one element plane (65 x 9 conductivities, computed from
-// rho once per element) in LDS through coalesced loads; every thread keeps the
-// 3 x 3 x 3 window of its node and the 8 surrounding conductivities in
-// registers, so a step costs 9 + 4 LDS reads per node.  Two LDS buffers per
-// plane type let one barrier per step suffice.
+// 66 x 10 values) and one element layer (65 x 9 conductivities, computed from
+// rho once per element) in LDS through coalesced loads.  The operator is split
+// by element layer: the layer between planes z and z+1 contributes to the
+// nodes of both planes, so a thread keeps only the 3 x 3 neighbourhood of its
+// node in plane z and one carried partial sum; a step costs 9 + 4 LDS reads
+// per node.  Two LDS buffers per plane type let one barrier per step suffice.
+//
+// Global loads are issued DEPTH steps ahead of their use into a register queue
+// holding the raw stored values (the conversion to the working type, e.g.
+// rho -> conductivity, happens when a slot is written to LDS), so no step waits
+// on a load issued in the same step.  Per-node data the output needs (diagonal,
+// right-hand side, mask word) is prefetched the same way.
 #pragma once
 
 #include "common.h"
+
+#ifndef MSMG_MARCH_DEPTH8
+#define MSMG_MARCH_DEPTH8 2
+#endif
+#ifndef MSMG_MARCH_DEPTH4
+#define MSMG_MARCH_DEPTH4 3
+#endif
 
 namespace msmg {
 
 constexpr int MX = 64, MY = 8;                  // node tile
 constexpr int PW = MX + 2, PH = MY + 2;         // node plane with halo
-constexpr int EW = MX + 1, EH = MY + 1;         // element plane
+constexpr int EW = MX + 1, EH = MY + 1;         // element layer
 constexpr int MARCH_THREADS = MX * MY;
 
 struct March {
@@ -39,15 +53,46 @@ inline March make_march(const Geo& g, int target_blocks = 2048, int min_chunk = 
   return m;
 }
 
-// LDS words (of type W) one marching workgroup needs
-constexpr int march_lds_words() { return 2 * PW * PH + 2 * EW * EH; }
+// Contribution of one element layer to (A x)_n in difference form.  kq[c],
+// c = cx + 2 cy, is the conductivity of the layer's element with lower corner
+// (i-1+cx, j-1+cy) (0 outside the mesh); s is the 3 x 3 neighbourhood of the
+// node in its own plane (s[4] = x_n, s[dy*3+dx] at offset (dx-1, dy-1)) and o
+// the same neighbourhood in the layer's other plane.  Values outside the mesh
+// are staged as 0 and meet a zero conductivity.
+template <typename W, bool CUBIC>
+MSMG_DEV W layer_apply(const Stencil& st, const W kq[4], const W s[9], const W o[9]) {
+  const W x0 = s[4];
+  W acc = W(st.fd[2]) * (kq[0] * (s[0] - x0) + kq[1] * (s[2] - x0) + kq[2] * (s[6] - x0) + kq[3] * (s[8] - x0));
+  acc += W(st.fd[1]) * ((kq[0] + kq[2]) * (o[3] - x0) + (kq[1] + kq[3]) * (o[5] - x0));
+  acc += W(st.fd[0]) * ((kq[0] + kq[1]) * (o[1] - x0) + (kq[2] + kq[3]) * (o[7] - x0));
+  acc += W(st.bd) * (kq[0] * (o[0] - x0) + kq[1] * (o[2] - x0) + kq[2] * (o[6] - x0) + kq[3] * (o[8] - x0));
+  if (!CUBIC) {
+    acc += W(st.ax[0]) * ((kq[0] + kq[2]) * (s[3] - x0) + (kq[1] + kq[3]) * (s[5] - x0));
+    acc += W(st.ax[1]) * ((kq[0] + kq[1]) * (s[1] - x0) + (kq[2] + kq[3]) * (s[7] - x0));
+    acc += W(st.ax[2]) * ((kq[0] + kq[1] + kq[2] + kq[3]) * (o[4] - x0));
+  }
+  return acc;
+}
 
-// loadn(n) -> value staged for node n; loadk(e) -> conductivity of element e;
-// emit(i, j, k, n, Ax, xc) is called for every node of the tile inside the
-// mesh with Ax = (A x)_n in difference form and xc the staged value at n.
-template <typename W, bool CUBIC, typename LoadN, typename LoadK, typename Emit>
+template <typename W>
+constexpr int march_depth() {
+  return sizeof(W) >= 8 ? MSMG_MARCH_DEPTH8 : MSMG_MARCH_DEPTH4;
+}
+
+// loadn(n) -> raw stored value(s) of node n, convn(raw) -> staged value;
+// loadk(e) -> raw value(s) of element e, convk(raw) -> conductivity;
+// loadc(n) -> per-node data for the output of node n (prefetched);
+// emit(i, j, k, n, Ax, xc, c) is called for every node of the tile inside the
+// mesh with Ax = (A x)_n in difference form, xc the staged value at n and c
+// the data loadc returned for n.
+template <typename W, bool CUBIC, typename LoadN, typename ConvN, typename LoadK, typename ConvK, typename LoadC,
+          typename Emit>
 MSMG_DEV void march(const Geo& g, const Stencil& st, const March& mg, long long tile, W* sx, W* sk, LoadN loadn,
-                    LoadK loadk, Emit emit) {
+                    ConvN convn, LoadK loadk, ConvK convk, LoadC loadc, Emit emit) {
+  using RN = decltype(loadn(0LL));
+  using RK = decltype(loadk(0LL));
+  using CD = decltype(loadc(0LL));
+  constexpr int DEPTH = march_depth<W>();
   const int tx = int(tile % mg.ntx), ty = int((tile / mg.ntx) % mg.nty), tz = int(tile / ((long long)mg.ntx * mg.nty));
   const int za = tz * mg.zc;
   if (tz >= mg.nzc || za >= g.nnz) return;  // uniform over the block
@@ -61,80 +106,101 @@ MSMG_DEV void march(const Geo& g, const Stencil& st, const March& mg, long long 
   constexpr int NS = (PW * PH + MARCH_THREADS - 1) / MARCH_THREADS;  // node slots per thread
   constexpr int ES = (EW * EH + MARCH_THREADS - 1) / MARCH_THREADS;  // element slots per thread
   const long long nplane = (long long)g.nnx * g.nny, eplane = (long long)g.nx * g.ny;
-  long long nofs[NS], eofs[ES];
+  int nofs[NS], eofs[ES];
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const int q = tid + s * MARCH_THREADS;
     const int gx = xa - 1 + q % PW, gy = ya - 1 + q / PW;
-    nofs[s] = (q < PW * PH && gx >= 0 && gx < g.nnx && gy >= 0 && gy < g.nny) ? (long long)gy * g.nnx + gx : -1;
+    nofs[s] = (q < PW * PH && gx >= 0 && gx < g.nnx && gy >= 0 && gy < g.nny) ? gy * g.nnx + gx : -1;
   }
 #pragma unroll
   for (int s = 0; s < ES; ++s) {
     const int q = tid + s * MARCH_THREADS;
     const int ex = xa - 1 + q % EW, ey = ya - 1 + q / EW;
-    eofs[s] = (q < EW * EH && ex >= 0 && ex < g.nx && ey >= 0 && ey < g.ny) ? (long long)ey * g.nx + ex : -1;
+    eofs[s] = (q < EW * EH && ex >= 0 && ex < g.nx && ey >= 0 && ey < g.ny) ? ey * g.nx + ex : -1;
   }
-  // prefetch queue: DEPTH planes of loads stay in flight (each queue slot keeps
-  // its registers, the step loop is unrolled by DEPTH)
-  constexpr int DEPTH = sizeof(W) >= 8 ? 3 : 5;
-  W pn[DEPTH][NS], pk[DEPTH][ES];
-  auto load_nodes = [&](int d, int zz) {
-    const bool zin = zz >= 0 && zz < g.nnz;
+  const long long cxy = inside ? (long long)y * g.nnx + x : 0;
+
+  RN pn[DEPTH][NS];
+  RK pk[DEPTH][ES];
+  CD pc[DEPTH];
 #pragma unroll
-    for (int s = 0; s < NS; ++s) pn[d][s] = (zin && nofs[s] >= 0) ? loadn(nofs[s] + zz * nplane) : W(0);
+  for (int d = 0; d < DEPTH; ++d) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) pn[d][s] = RN{};
+#pragma unroll
+    for (int s = 0; s < ES; ++s) pk[d][s] = RK{};
+    pc[d] = CD{};
+  }
+  auto load_nodes = [&](int d, int zz) {
+    if (zz < 0 || zz >= g.nnz) return;
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+      if (nofs[s] >= 0) pn[d][s] = loadn(nofs[s] + zz * nplane);
   };
   auto load_elems = [&](int d, int ez) {
-    const bool zin = ez >= 0 && ez < g.nz;
+    if (ez < 0 || ez >= g.nz) return;
 #pragma unroll
-    for (int s = 0; s < ES; ++s) pk[d][s] = (zin && eofs[s] >= 0) ? loadk(eofs[s] + ez * eplane) : W(0);
+    for (int s = 0; s < ES; ++s)
+      if (eofs[s] >= 0) pk[d][s] = loadk(eofs[s] + ez * eplane);
   };
-  auto store_nodes = [&](int d, int buf) {
+  auto load_centre = [&](int d, int zz) {
+    if (inside && zz < zb) pc[d] = loadc(cxy + zz * nplane);
+  };
+  auto store_nodes = [&](int d, int buf, int zz) {
+    const bool zin = zz >= 0 && zz < g.nnz;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const int q = tid + s * MARCH_THREADS;
-      if (q < PW * PH) sx[buf * PW * PH + q] = pn[d][s];
+      if (q < PW * PH) sx[buf * PW * PH + q] = (zin && nofs[s] >= 0) ? convn(pn[d][s]) : W(0);
     }
   };
-  auto store_elems = [&](int d, int buf) {
+  auto store_elems = [&](int d, int buf, int ez) {
+    const bool zin = ez >= 0 && ez < g.nz;
 #pragma unroll
     for (int s = 0; s < ES; ++s) {
       const int q = tid + s * MARCH_THREADS;
-      if (q < EW * EH) sk[buf * EW * EH + q] = pk[d][s];
+      if (q < EW * EH) sk[buf * EW * EH + q] = (zin && eofs[s] >= 0) ? convk(pk[d][s]) : W(0);
     }
   };
-  W win[27];
-  W kk[8];
-  auto read_plane = [&](int buf, int p) {
+  auto read_plane = [&](int buf, W* dst) {
     const W* src = sx + buf * PW * PH;
 #pragma unroll
     for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
-      for (int dx = 0; dx < 3; ++dx) win[p * 9 + dy * 3 + dx] = src[(ly + dy) * PW + (lx + dx)];
+      for (int dx = 0; dx < 3; ++dx) dst[dy * 3 + dx] = src[(ly + dy) * PW + (lx + dx)];
   };
-  auto read_k = [&](int buf, int layer) {
+  auto read_k = [&](int buf, W* kq) {
     const W* src = sk + buf * EW * EH;
 #pragma unroll
     for (int cy = 0; cy < 2; ++cy)
 #pragma unroll
-      for (int cx = 0; cx < 2; ++cx) kk[layer * 4 + cy * 2 + cx] = src[(ly + cy) * EW + (lx + cx)];
+      for (int cx = 0; cx < 2; ++cx) kq[cy * 2 + cx] = src[(ly + cy) * EW + (lx + cx)];
   };
 
-  // prologue: planes za-1, za and element plane za-1
-  load_nodes(0, za - 1);
-  store_nodes(0, 0);
-  load_nodes(0, za);
-  store_nodes(0, 1);
-  load_elems(0, za - 1);
-  store_elems(0, 0);
-  __syncthreads();
-  read_plane(0, 0);
-  read_plane(1, 1);
-  read_k(0, 0);
-  __syncthreads();
+  // prologue: planes za-1 and za, element layer za-1 -> the partial sum of
+  // node za from the layer below
+  W A[9], carry;
+  {
+    load_nodes(0, za - 1);
+    store_nodes(0, 0, za - 1);
+    load_nodes(0, za);
+    store_nodes(0, 1, za);
+    load_elems(0, za - 1);
+    store_elems(0, 0, za - 1);
+    __syncthreads();
+    W P[9], kq[4];
+    read_plane(0, P);
+    read_plane(1, A);
+    read_k(0, kq);
+    carry = layer_apply<W, CUBIC>(st, kq, A, P);
+    __syncthreads();
+  }
 #pragma unroll
   for (int d = 0; d < DEPTH; ++d) {
     load_nodes(d, za + 1 + d);
     load_elems(d, za + d);
+    load_centre(d, za + d);
   }
   for (int z0 = za; z0 < zb; z0 += DEPTH) {
 #pragma unroll
@@ -142,29 +208,26 @@ MSMG_DEV void march(const Geo& g, const Stencil& st, const March& mg, long long 
       const int z = z0 + d;
       if (z >= zb) break;  // uniform over the block
       const int buf = (z - za) & 1;
-      store_nodes(d, buf);
-      store_elems(d, buf);
+      store_nodes(d, buf, z + 1);
+      store_elems(d, buf, z);
+      const CD cur = pc[d];
       __syncthreads();
       // refill this queue slot; the other slots' loads are still in flight
       if (z + DEPTH < zb) {
         load_nodes(d, z + 1 + DEPTH);
         load_elems(d, z + DEPTH);
+        load_centre(d, z + DEPTH);
       }
-      read_plane(buf, 2);
-      read_k(buf, 1);
+      W B[9], kq[4];
+      read_plane(buf, B);
+      read_k(buf, kq);
       if (inside) {
-        const W ax = gather_apply<W, CUBIC>(g, st, kk, x, y, z, [&](int a, int b, int c) {
-          return win[(c - z + 1) * 9 + (b - y + 1) * 3 + (a - x + 1)];
-        });
-        emit(x, y, z, node_id(g, x, y, z), ax, win[13]);
+        const W ax = carry + layer_apply<W, CUBIC>(st, kq, A, B);
+        emit(x, y, z, cxy + z * nplane, ax, A[4], cur);
       }
+      carry = layer_apply<W, CUBIC>(st, kq, B, A);
 #pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        win[q] = win[9 + q];
-        win[9 + q] = win[18 + q];
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) kk[q] = kk[4 + q];
+      for (int q = 0; q < 9; ++q) A[q] = B[q];
     }
   }
 }

@@ -44,7 +44,7 @@ struct msmg_handle {
   long long ntiles = 0;
   double lam_bound = 0.0;  // upper bound of the level-1 standard-form spectrum
   Material mat{};
-  int rho_dt = DT_F64, rhov_dt = DT_F64, v_dt = DT_F64, b_dt = DT_F64, a_dt = DT_F64;
+  int rho_dt = DT_F64, rhov_dt = DT_F64, v_dt = DT_F64, b_dt = DT_F64, a_dt = DT_F64, dv_dt = DT_F64;
   bool mg = true;
 
   // density, mask, fixed values
@@ -341,8 +341,8 @@ static int check_options(const msmg_options& o) {
   if (o.vcycle_dtype != MSMG_F64 && o.vcycle_dtype != MSMG_F32) return fail(MSMG_EINVAL, "vcycle_dtype must be F64 or F32");
   if (o.rho_v_dtype < 0 || o.rho_v_dtype > 2 || o.basis_dtype < 0 || o.basis_dtype > 2)
     return fail(MSMG_EINVAL, "bad storage dtype");
-  if (o.vcycle_dtype == MSMG_F64 && (o.rho_v_dtype != MSMG_F64 || o.basis_dtype != MSMG_F64))
-    return fail(MSMG_EINVAL, "an FP64 cycle needs FP64 density and basis copies");
+  if (o.vcycle_dtype == MSMG_F64 && o.rho_v_dtype != o.basis_dtype)
+    return fail(MSMG_EINVAL, "an FP64 cycle takes density and basis copies of one type (F64, F32 or BF16)");
   if (o.vcycle_dtype == MSMG_F32 && (o.rho_v_dtype == MSMG_F64 || o.basis_dtype == MSMG_F64))
     return fail(MSMG_EINVAL, "an FP32 cycle takes F32 or BF16 density and basis copies");
   if (o.pc_kind != MSMG_PC_MULTIGRID && o.pc_kind != MSMG_PC_SMOOTHER) return fail(MSMG_EINVAL, "bad pc_kind");
@@ -416,9 +416,11 @@ extern "C" int msmg_create(msmg_handle** out, int nx, int ny, int nz, double lx,
     if (rc == MSMG_OK) rc = dev_alloc(h, p, bytes);
   };
   A(&h->rho, ne * 8);
-  if (h->v_dt == DT_F32) A(&h->rhov, ne * dt_size(h->rhov_dt));
+  if (h->rhov_dt != DT_F64) A(&h->rhov, ne * dt_size(h->rhov_dt));
   A(&h->bits, ((nn + 31) / 32) * 4);
-  A(&h->dinv, nn * vs);
+  // Jacobi diagonal: FP64 only on the all-FP64 path (a fixed coefficient like rho)
+  h->dv_dt = (h->v_dt == DT_F64 && h->b_dt == DT_F64) ? DT_F64 : DT_F32;
+  A(&h->dinv, nn * dt_size(h->dv_dt));
   A(&h->r, nn * 8); A(&h->p, nn * 8); A(&h->q, nn * 8); A(&h->z, nn * 8); A(&h->b, nn * 8);
   A(&h->xlo, nn * 8);
   A(&h->v_r1, nn * vs); A(&h->v_res, nn * vs);
@@ -548,7 +550,7 @@ extern "C" int msmg_setup(msmg_handle* h, const void* rho, msmg_dtype rho_dtype,
     if (nfixed == 0) return fail(MSMG_ESINGULAR, "the Dirichlet mask is empty: the operator is singular");
   }
   Ctx c = make_ctx(h);
-  launch_diag_inv(c, h->rho, h->rho_dt, h->dinv, h->v_dt, s);
+  launch_diag_inv(c, h->rho, h->rho_dt, h->dinv, h->dv_dt, s);
   HIP_TRY(hipGetLastError());
   if (h->mg) {
     SetupArgs a{};
@@ -606,7 +608,7 @@ static void precondition(msmg_handle* h, const Ctx& c, const double* r, double* 
   }
   launch_smooth(c, r, true, h->v_r1, s);                            // r1 = S^-1 r0
   launch_vresidual(c, r, true, h->v_r1, v64, h->v_res, s);          // r0 - A r1
-  launch_restrict(c, h->v_res, false, nullptr, h->c_rc, s);         // rc = R_c (r0 - A r1)
+  launch_restrict(c, h->v_res, h->c_rc, s);                         // rc = R_c (r0 - A r1)
   launch_gs_sweep(c, h->c_rc, h->c_x0, true, s);                    // rc0 = S_c^-1 rc
   launch_ac_residual(c, h->c_rc, h->c_x0, h->c_t, s);               // rc - A_c rc0
   launch_cc_restrict(c, h->c_t, h->rcc, s);                         // rcc = R_cc (...)

@@ -1,0 +1,88 @@
+"""The C-ABI library: it loads without a GPU, exports every function that
+include/msmg.h declares, and its host-only planning logic (msmg_query_plan,
+msmg_default_options) gives the hierarchy sizes of the method."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "msmg.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(msmg_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2410_06850_amd import _lib
+    return _lib
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for want in ("msmg_create", "msmg_setup", "msmg_solve", "msmg_sensitivity", "msmg_apply",
+                 "msmg_precondition", "msmg_destroy", "msmg_last_error", "msmg_query_plan"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    lib = L.lib()
+    names = declared_functions()
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    # the binding's signature table covers exactly the declared functions
+    assert sorted(n for n, _, _ in L.SIGNATURES) == names
+
+
+def test_default_options(L):
+    o = L.default_options()
+    assert (o.H, o.sd, o.Lc, o.Lcc, o.cheb_degree) == (8, 8, 4, 17, 2)
+    assert abs(o.cheb_lo - 0.15) < 1e-15 and abs(o.cheb_hi - 1.5) < 1e-15
+    assert o.vcycle_dtype == L.MSMG_F64 and o.pc_kind == L.MSMG_PC_MULTIGRID
+
+
+def _expected_cells(n_nodes, H):
+    # runs of H nodes, the last cell keeps the remainder
+    return max(1, n_nodes // H)
+
+
+@pytest.mark.parametrize("n,H,sd", [(16, 8, 2), (24, 4, 3), (64, 8, 8), (256, 8, 8), (512, 8, 8)])
+def test_query_plan_sizes(L, n, H, sd):
+    p = L.query_plan(n, n, n, L.default_options(H=H, sd=sd))
+    nc = _expected_cells(n + 1, H)
+    assert (p.ncx, p.ncy, p.ncz) == (nc, nc, nc)
+    assert p.ncells == nc ** 3
+    ncc = max(1, nc // sd)
+    assert (p.nccx, p.nccy, p.nccz) == (ncc, ncc, ncc)
+    assert p.n_c == nc ** 3 * 4
+    assert p.nodes == (n + 1) ** 3 and p.elements == n ** 3
+    # the last cell holds H + remainder nodes per axis
+    last = (n + 1) - (nc - 1) * H
+    assert p.max_cell_nodes == last ** 3
+    assert p.device_bytes > 16 * p.nodes
+
+
+def test_query_plan_non_cubic(L):
+    p = L.query_plan(40, 24, 16, L.default_options(H=8, sd=2))
+    assert (p.ncx, p.ncy, p.ncz) == (5, 3, 2)
+    assert (p.nccx, p.nccy, p.nccz) == (2, 1, 1)
+
+
+def test_query_plan_rejects_bad_input(L):
+    lib = L.lib()
+    plan = L.Plan()
+    for args, opts in [((0, 8, 8), {}), ((8, 8, 8), dict(H=1)), ((8, 8, 8), dict(Lc=9)),
+                       ((8, 8, 8), dict(cheb_degree=0)), ((1024, 1024, 1024), dict(sd=8))]:
+        o = L.default_options(**opts)
+        rc = lib.msmg_query_plan(*args, ctypes.byref(o), ctypes.byref(plan))
+        assert rc == L.MSMG_EINVAL, (args, opts, rc)
+        assert L.last_error()
+    # the 1024^3 mesh fits with larger coarse-coarse cells
+    o = L.default_options(sd=16)
+    assert lib.msmg_query_plan(1024, 1024, 1024, ctypes.byref(o), ctypes.byref(plan)) == L.MSMG_OK
+    assert plan.ncc == 8 ** 3

@@ -39,37 +39,77 @@ def _log(msg):
 
 
 def cpu_baseline():
-    """Oracle PCG-MsMG solve of a bounded sample; DOFs/s of the solve."""
+    """Oracle PCG-MsMG solve of a bounded sample; DOFs/s of the solve.
+
+    The oracle runs as it stands (NumPy/SciPy, FP64 with an extended-precision
+    iterate) with BLAS limited to one thread, so `cores` is 1."""
     import threadpoolctl
 
     from oracle import msmg as omsmg
     from oracle import q1
 
-    n, ell = 48, 3  # same feature size relative to the box as the 256^3 field (ell / N = 1/16)
+    n = 64
+    ell = ELL * n / N  # same feature size relative to the box as the 256^3 field
     g = q1.Grid(n)
     rho = synth.grf_rho(n, ell, seed=0).ravel()
     mask = synth.dirichlet_patch_mask(n, n, n).ravel()
     f = q1.element_load(g, 1.0)
-    with threadpoolctl.threadpool_limits() as _:
-        info = threadpoolctl.threadpool_info()
-    cores = max([d.get("num_threads", 1) for d in info] + [1])
-    t0 = time.perf_counter()
-    h = omsmg.Hierarchy(g, rho, KMIN, 1.0, 3, mask, omsmg.Options(H=8, sd=8))
-    t1 = time.perf_counter()
-    T, res, _ = omsmg.solve(g, rho, f, mask, KMIN, 1.0, 3, hier=h, rtol=RTOL, maxit=400)
-    t2 = time.perf_counter()
+    with threadpoolctl.threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        h = omsmg.Hierarchy(g, rho, KMIN, 1.0, 3, mask, omsmg.Options(H=8, sd=8))
+        t1 = time.perf_counter()
+        T, res, _ = omsmg.solve(g, rho, f, mask, KMIN, 1.0, 3, hier=h, rtol=RTOL, maxit=1000)
+        t2 = time.perf_counter()
     free = int(g.nnodes - mask.sum())
     return {
         "value": free / (t2 - t1),
         "unit": "DOFs/s",
-        "cores": int(cores),
+        "cores": 1,
         "kind": "oracle",
         "sample": (f"oracle PCG-MsMG solve (FP64, extended-precision iterate) of a {n}^3 thresholded GRF "
-                   f"(ell={ell} elements, contrast 1e6), rtol {RTOL}, {res.iterations} iterations, "
-                   f"status {res.status}; set-up {t1 - t0:.1f} s excluded"),
+                   f"(ell={ell:g} elements, contrast 1e6, H=8, sd=8), rtol {RTOL}, {res.iterations} iterations, "
+                   f"status {res.status}, one thread; set-up {t1 - t0:.1f} s excluded"),
         "solve_s": t2 - t1,
         "setup_s": t1 - t0,
     }
+
+
+SOURCES_FOR_TRAFFIC = ("paper_2410_06850_amd/csrc/fine_kernels.hip", "paper_2410_06850_amd/csrc/march.h",
+                       "paper_2410_06850_amd/csrc/common.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_apply_cube256_grf16_c1e6_traffic.json")
+
+
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in SOURCES_FOR_TRAFFIC:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per operator-apply launch from the committed rocprofv3 counter
+    runs (FETCH_SIZE, WRITE_SIZE scaled by a plain-copy calibration), or None
+    when the kernel sources changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+PATHS = {
+    # FP64 cycle arithmetic with BF16 copies of k and R_c, FP32 Jacobi diagonal
+    "mixed": dict(vcycle_dtype=0, rho_v_dtype=2, basis_dtype=2),
+    "fp64": dict(),
+    # FP32 cycle vectors and arithmetic (BF16 copies)
+    "f32cycle": dict(vcycle_dtype=1, rho_v_dtype=2, basis_dtype=2),
+}
 
 
 def main():
@@ -79,11 +119,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=N)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison path")
+    ap.add_argument("--no-f32", action="store_true", help="skip the FP32-cycle comparison path")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain 1 GiB device copy first (reference for the HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU: this build has no multi-GPU path (see the design notes on sharding)",
-              file=sys.stderr)
+        print("bench.py measures one GPU: the solver has no multi-GPU path (sharding is described in the design "
+              "notes); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -92,8 +135,15 @@ def main():
 
     n = args.n
     dev = torch.device("cuda", 0)
+    if args.calibrate_copy:
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        torch.cuda.empty_cache()
     _log(f"generating the {n}^3 field")
-    rho_np = synth.grf_rho(n, ELL * n // N if n != N else ELL, seed=0).ravel()
+    rho_np = synth.grf_rho(n, ELL * n / N, seed=0).ravel()
     mask_np = synth.dirichlet_patch_mask(n, n, n).ravel()
     free = int((n + 1) ** 3 - int(mask_np.sum()))
     rho = torch.tensor(rho_np, device=dev)
@@ -119,40 +169,48 @@ def main():
             _log(f"{tag} step {k}: setup {1e3 * (t1 - t0):.1f} ms, solve {1e3 * (t2 - t1):.1f} ms "
                  f"({info.iterations} it, rel.res {info.rel_res:.2e}, code {info.code}), "
                  f"sensitivity {1e3 * (t3 - t2):.1f} ms, apply {info.apply_ms * 1e3:.1f} us")
+            if info.code != 0:
+                raise RuntimeError(f"{tag}: solve did not converge: {dict(info)}")
             if k >= warmup:
                 recs.append(dict(setup=t1 - t0, solve=t2 - t1, sens=t3 - t2, step=t3 - t0, info=dict(info)))
-        del dc
-        return s, recs
+        del dc, s
+        torch.cuda.empty_cache()
+        return recs
+
+    def summary(recs):
+        last = recs[-1]["info"]
+        t = float(np.mean([r["solve"] for r in recs]))
+        return {
+            "value": free / t,
+            "iterations": last["iterations"],
+            "rel_res": last["rel_res"],
+            "solve_ms": 1e3 * t,
+            "setup_ms": 1e3 * float(np.mean([r["setup"] for r in recs])),
+            "sensitivity_ms": 1e3 * float(np.mean([r["sens"] for r in recs])),
+            "apply_us": 1e3 * float(np.mean([r["info"]["apply_ms"] for r in recs])),
+            "precond_us": 1e3 * float(np.mean([r["info"]["precond_ms"] for r in recs])),
+        }
 
     _log("mixed-precision path")
-    s_mix, mix = run_path(dict(vcycle_dtype=1, rho_v_dtype=2, basis_dtype=2), args.steps, args.warmup, "mixed")
+    mix = run_path(PATHS["mixed"], args.steps, args.warmup, "mixed")
     t_solve = float(np.mean([r["solve"] for r in mix]))
     t_step = float(np.mean([r["step"] for r in mix]))
     info = mix[-1]["info"]
-    # dominant kernel: the PCG operator apply (one per iteration), timed with HIP
-    # events on the solve stream inside the timed steps
+    # dominant kernel: the PCG operator apply (one launch per iteration), timed
+    # with HIP events on the solve stream inside the timed steps
     apply_ms = float(np.mean([r["info"]["apply_ms"] for r in mix]))
     nn, ne = (n + 1) ** 3, n ** 3
-    apply_bytes = 16 * nn + 8 * ne + nn / 8  # x read, y write, rho read, mask bits
+    apply_bytes = 16 * nn + 8 * ne + nn / 8  # x read, y write, k read, mask bits
     achieved = apply_bytes / (apply_ms * 1e-3) / 1e9
-    del s_mix
-    torch.cuda.empty_cache()
+    traffic = measured_traffic() if n == N else None
 
-    fp64 = None
+    others = {}
     if not args.no_fp64:
         _log("FP64 path")
-        s64, r64 = run_path({}, 1, 0, "fp64")
-        fp64 = {
-            "value": free / r64[-1]["solve"],
-            "iterations": r64[-1]["info"]["iterations"],
-            "solve_ms": 1e3 * r64[-1]["solve"],
-            "setup_ms": 1e3 * r64[-1]["setup"],
-            "rel_res": r64[-1]["info"]["rel_res"],
-            "apply_us": 1e3 * r64[-1]["info"]["apply_ms"],
-            "precond_us": 1e3 * r64[-1]["info"]["precond_ms"],
-        }
-        del s64
-        torch.cuda.empty_cache()
+        others["fp64"] = summary(run_path(PATHS["fp64"], 1, 0, "fp64"))
+    if not args.no_f32:
+        _log("FP32-cycle path")
+        others["f32cycle"] = summary(run_path(PATHS["f32cycle"], 1, 0, "f32cycle"))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -170,31 +228,33 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64+f32",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"cube{n}_grf{ELL}_c1e6",
+            "workload": f"cube{n}_grf{ELL * n // N}_c1e6",
             "elements": n ** 3,
             "free_dofs": free,
-            "field": f"thresholded Gaussian random field, ell={ELL}, volume fraction 0.4, seed 0",
+            "field": f"thresholded Gaussian random field, ell={ELL * n / N:g} elements, volume fraction 0.4, seed 0",
             "k_min": KMIN, "k_max": 1.0, "p": 3, "rtol": RTOL,
             "hierarchy": {"H": 8, "sd": 8, "Lc": 4, "Lcc": 17, "cheb_degree": 2},
-            "precision": "FP64 PCG (double-double iterate), FP32 cycle, BF16 rho/R_c, FP64 coarse-coarse",
+            "precision": ("FP64 PCG (double-double iterate) and FP64 cycle arithmetic; BF16 copies of k and R_c, "
+                          "FP32 Jacobi diagonal in the cycle; FP64 coarse levels"),
+            "step": "set-up + PCG solve from zero + compliance sensitivity; value counts the solve only",
         },
         "iterations": info["iterations"],
         "rel_res": info["rel_res"],
         "solve_ms": 1e3 * t_solve,
         "setup_ms": 1e3 * float(np.mean([r["setup"] for r in mix])),
         "precond_us": 1e3 * float(np.mean([r["info"]["precond_ms"] for r in mix])),
-        "fp64_path": fp64,
+        "paths": others,
         "roofline": {
-            "kernel": "k_apply (PCG operator apply, FP64, rho->k fused)",
+            "kernel": "k_apply (PCG operator apply, FP64, difference form)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
             "apply_us": apply_ms * 1e3,
             "bytes_per_launch": apply_bytes,
         },

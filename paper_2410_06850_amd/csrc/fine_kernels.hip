@@ -33,6 +33,15 @@ __global__ void k_convert(const Tin* __restrict__ in, Tout* __restrict__ out, lo
     out[i] = from_f64<Tout>(to_f64<Tin>(in[i]));
 }
 
+// Element conductivities k_e = k_min + rho_e^p (k_max - k_min) in FP64 (the
+// material law), computed once per density field for the solve kernels.
+template <typename RT>
+__global__ void k_conductivity(const RT* __restrict__ rho, double* __restrict__ kc, long long ne, Material m) {
+  const double dk = m.kmax - m.kmin;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < ne; e += (long long)gridDim.x * blockDim.x)
+    kc[e] = conductivity<double>(to_f64<RT>(rho[e]), m.kmin, dk, m.p);
+}
+
 // Jacobi diagonal inverse: D_n = self * sum of the 8 k_e around n; 0 on fixed nodes.
 template <typename RT, typename VT>
 __global__ void k_diag_inv(Geo g, Stencil st, const RT* __restrict__ rho, Material m,
@@ -174,9 +183,9 @@ struct MaskedRaw {
   int sh;
 };
 
-template <typename RT, bool CUBIC, int MODE>
-__global__ __launch_bounds__(MARCH_THREADS) void k_apply(Geo g, Stencil st, March mg, const RT* __restrict__ rho,
-                                                         Material m, const uint32_t* __restrict__ bits,
+template <bool CUBIC, int MODE>
+MSMG_MARCH_KERNEL void k_apply(Geo g, Stencil st, March mg, const double* __restrict__ kc,
+                                                         const uint32_t* __restrict__ bits,
                                                          const double* __restrict__ x, double* __restrict__ y,
                                                          Scalars* sc, double* partials, unsigned* counter) {
   if (MODE == 1 && sc->done) return;
@@ -184,28 +193,29 @@ __global__ __launch_bounds__(MARCH_THREADS) void k_apply(Geo g, Stencil st, Marc
   __shared__ double sk[2 * EW * EH];
   __shared__ double red[16];
   const long long tile = xcd_tile(blockIdx.x, gridDim.x);
-  const double dk = m.kmax - m.kmin;
   double s[1] = {0.0};
-  auto loadk = [&](long long e) { return rho[e]; };
-  auto convk = [&](RT v) { return conductivity<double>(cvt<double, RT>(v), m.kmin, dk, m.p); };
-  auto loadc = [&](long long n) {
+  auto loadk = [&](long long b, unsigned o) { return plane_ld(kc, b, o); };
+  auto convk = [&](double v) { return v; };
+  auto loadc = [&](long long b, unsigned o) {
     ApplyCentre c;
+    const long long n = b + o;
     c.w = bits[n >> 5];
-    c.x = MODE == 2 ? x[n] : 0.0;
+    c.x = MODE == 2 ? plane_ld(x, b, o) : 0.0;
     return c;
   };
-  auto emit = [&](int, int, int, long long n, double ax, double xc, const ApplyCentre& c) {
+  auto emit = [&](long long b, unsigned o, double ax, double xc, const ApplyCentre& c) {
     double out = ax;
-    if ((c.w >> (n & 31)) & 1u) out = (MODE == 2) ? c.x : 0.0;
-    y[n] = out;
+    if ((c.w >> ((b + o) & 31)) & 1u) out = (MODE == 2) ? c.x : 0.0;
+    plane_st(y, b, o, out);
     if (MODE == 1) s[0] += xc * out;
   };
   if (MODE == 2) {
     march<double, CUBIC>(
         g, st, mg, tile, sx, sk,
-        [&](long long n) {
+        [&](long long b, unsigned o) {
           MaskedRaw r;
-          r.v = x[n];
+          const long long n = b + o;
+          r.v = plane_ld(x, b, o);
           r.w = bits[n >> 5];
           r.sh = int(n & 31);
           return r;
@@ -213,8 +223,8 @@ __global__ __launch_bounds__(MARCH_THREADS) void k_apply(Geo g, Stencil st, Marc
         [&](const MaskedRaw& r) { return ((r.w >> r.sh) & 1u) ? 0.0 : r.v; }, loadk, convk, loadc, emit);
   } else {
     march<double, CUBIC>(
-        g, st, mg, tile, sx, sk, [&](long long n) { return x[n]; }, [&](double v) { return v; }, loadk, convk, loadc,
-        emit);
+        g, st, mg, tile, sx, sk, [&](long long b, unsigned o) { return plane_ld(x, b, o); },
+        [&](double v) { return v; }, loadk, convk, loadc, emit);
   }
   if (MODE != 1) return;
   grid_reduce<1>(s, red, partials, counter, gridDim.x, blockIdx.x, [&](double* tt) {
@@ -288,32 +298,30 @@ struct RD {
   DT di;
 };
 
-template <typename VT, typename RT, typename IT, typename DT, bool CUBIC>
-__global__ __launch_bounds__(MARCH_THREADS) void k_cheb2(Geo g, Stencil st, March mg, const RT* __restrict__ rho,
-                                                         Material m, const IT* __restrict__ r,
+template <typename VT, typename KT, typename IT, typename DT, bool CUBIC>
+MSMG_MARCH_KERNEL void k_cheb2(Geo g, Stencil st, March mg, const KT* __restrict__ kv,
+                                                         const IT* __restrict__ r,
                                                          const DT* __restrict__ dinv, VT* __restrict__ out,
                                                          VT* __restrict__ dout, ChebCoef cc, const Scalars* sc) {
   if (sc && sc->done) return;
   __shared__ VT sx[2 * PW * PH];
   __shared__ VT sk[2 * EW * EH];
   const long long tile = xcd_tile(blockIdx.x, gridDim.x);
-  const VT dk = VT(m.kmax - m.kmin), kmin = VT(m.kmin);
   const VT it = VT(cc.inv_theta), c0 = VT(cc.c0), c1 = VT(cc.c1);
-  auto loadrd = [&](long long n) {
+  auto loadrd = [&](long long b, unsigned o) {
     RD<DT, IT> v;
-    v.r = r[n];
-    v.di = dinv[n];
+    v.r = plane_ld(r, b, o);
+    v.di = plane_ld(dinv, b, o);
     return v;
   };
   march<VT, CUBIC>(
       g, st, mg, tile, sx, sk, loadrd, [&](const RD<DT, IT>& v) { return cvt<VT, IT>(v.r) * VT(v.di) * it; },
-      [&](long long e) { return rho[e]; },
-      [&](RT v) { return conductivity<VT>(cvt<VT, RT>(v), kmin, dk, m.p); }, loadrd,
-      [&](int, int, int, long long n, VT az, VT z1, const RD<DT, IT>& c) {
+      [&](long long b, unsigned o) { return plane_ld(kv, b, o); }, [&](KT v) { return cvt<VT, KT>(v); }, loadrd,
+      [&](long long b, unsigned o, VT az, VT z1, const RD<DT, IT>& c) {
         VT v = VT(0);
         if (c.di != DT(0)) v = c0 * z1 + c1 * VT(c.di) * (cvt<VT, IT>(c.r) - az);
-        out[n] = v;
-        if (dout) dout[n] = v - z1;
+        plane_st(out, b, o, v);
+        if (dout) plane_st(dout, b, o, VT(v - z1));
       });
 }
 
@@ -325,9 +333,9 @@ struct RDD {
   VT d;
 };
 
-template <typename VT, typename RT, typename IT, typename DT, bool CUBIC>
-__global__ __launch_bounds__(MARCH_THREADS) void k_cheb_step(Geo g, Stencil st, March mg, const RT* __restrict__ rho,
-                                                             Material m, const IT* __restrict__ r,
+template <typename VT, typename KT, typename IT, typename DT, bool CUBIC>
+MSMG_MARCH_KERNEL void k_cheb_step(Geo g, Stencil st, March mg, const KT* __restrict__ kv,
+                                                             const IT* __restrict__ r,
                                                              const DT* __restrict__ dinv, const VT* __restrict__ x,
                                                              VT* __restrict__ d, VT* __restrict__ xout, double ca,
                                                              double cb, const Scalars* sc) {
@@ -335,27 +343,25 @@ __global__ __launch_bounds__(MARCH_THREADS) void k_cheb_step(Geo g, Stencil st, 
   __shared__ VT sx[2 * PW * PH];
   __shared__ VT sk[2 * EW * EH];
   const long long tile = xcd_tile(blockIdx.x, gridDim.x);
-  const VT dk = VT(m.kmax - m.kmin), kmin = VT(m.kmin);
   march<VT, CUBIC>(
-      g, st, mg, tile, sx, sk, [&](long long n) { return x[n]; }, [&](VT v) { return v; },
-      [&](long long e) { return rho[e]; },
-      [&](RT v) { return conductivity<VT>(cvt<VT, RT>(v), kmin, dk, m.p); },
-      [&](long long n) {
+      g, st, mg, tile, sx, sk, [&](long long b, unsigned o) { return plane_ld(x, b, o); }, [&](VT v) { return v; },
+      [&](long long b, unsigned o) { return plane_ld(kv, b, o); }, [&](KT v) { return cvt<VT, KT>(v); },
+      [&](long long b, unsigned o) {
         RDD<VT, IT, DT> c;
-        c.r = r[n];
-        c.di = dinv[n];
-        c.d = d[n];
+        c.r = plane_ld(r, b, o);
+        c.di = plane_ld(dinv, b, o);
+        c.d = plane_ld(d, b, o);
         return c;
       },
-      [&](int, int, int, long long n, VT ax, VT xc, const RDD<VT, IT, DT>& c) {
+      [&](long long b, unsigned o, VT ax, VT xc, const RDD<VT, IT, DT>& c) {
         if (c.di == DT(0)) {
-          d[n] = VT(0);
-          xout[n] = VT(0);
+          plane_st(d, b, o, VT(0));
+          plane_st(xout, b, o, VT(0));
           return;
         }
         const VT dn = VT(ca) * c.d + VT(cb) * VT(c.di) * (cvt<VT, IT>(c.r) - ax);
-        d[n] = dn;
-        xout[n] = xc + dn;
+        plane_st(d, b, o, dn);
+        plane_st(xout, b, o, VT(xc + dn));
       });
 }
 
@@ -501,28 +507,26 @@ struct RW {
   uint32_t w;
 };
 
-template <typename VT, typename RT, typename IT, typename XT, bool CUBIC>
-__global__ __launch_bounds__(MARCH_THREADS) void k_vresidual(Geo g, Stencil st, March mg, const RT* __restrict__ rho,
-                                                             Material m, const uint32_t* __restrict__ bits,
+template <typename VT, typename KT, typename IT, typename XT, bool CUBIC>
+MSMG_MARCH_KERNEL void k_vresidual(Geo g, Stencil st, March mg, const KT* __restrict__ kv,
+                                                             const uint32_t* __restrict__ bits,
                                                              const IT* __restrict__ r, const XT* __restrict__ x,
                                                              VT* __restrict__ out, const Scalars* sc) {
   if (sc && sc->done) return;
   __shared__ XT sx[2 * PW * PH];
   __shared__ XT sk[2 * EW * EH];
   const long long tile = xcd_tile(blockIdx.x, gridDim.x);
-  const XT dk = XT(m.kmax - m.kmin), kmin = XT(m.kmin);
   march<XT, CUBIC>(
-      g, st, mg, tile, sx, sk, [&](long long n) { return x[n]; }, [&](XT v) { return v; },
-      [&](long long e) { return rho[e]; },
-      [&](RT v) { return conductivity<XT>(cvt<XT, RT>(v), kmin, dk, m.p); },
-      [&](long long n) {
+      g, st, mg, tile, sx, sk, [&](long long b, unsigned o) { return plane_ld(x, b, o); }, [&](XT v) { return v; },
+      [&](long long b, unsigned o) { return plane_ld(kv, b, o); }, [&](KT v) { return cvt<XT, KT>(v); },
+      [&](long long b, unsigned o) {
         RW<IT> c;
-        c.r = r[n];
-        c.w = bits[n >> 5];
+        c.r = plane_ld(r, b, o);
+        c.w = bits[(b + o) >> 5];
         return c;
       },
-      [&](int, int, int, long long n, XT ax, XT, const RW<IT>& c) {
-        out[n] = ((c.w >> (n & 31)) & 1u) ? VT(0) : VT(cvt<XT, IT>(c.r) - ax);
+      [&](long long b, unsigned o, XT ax, XT, const RW<IT>& c) {
+        plane_st(out, b, o, ((c.w >> ((b + o) & 31)) & 1u) ? VT(0) : VT(cvt<XT, IT>(c.r) - ax));
       });
 }
 
@@ -738,6 +742,14 @@ void launch_convert(const void* in, int din, void* out, int dout, long long n, h
 #undef CONV
 }
 
+void launch_conductivity(const Ctx& c, const void* rho, int rdt, double* kc, hipStream_t s) {
+  const dim3 gr(grid1d(c.g.ne, 256, 8192)), bl(256);
+  if (rdt == DT_F64)
+    hipLaunchKernelGGL((k_conductivity<double>), gr, bl, 0, s, (const double*)rho, kc, c.g.ne, c.mat);
+  else
+    hipLaunchKernelGGL((k_conductivity<float>), gr, bl, 0, s, (const float*)rho, kc, c.g.ne, c.mat);
+}
+
 void launch_diag_inv(const Ctx& c, const void* rho, int rdt, void* dinv, int vdt, hipStream_t s) {
   const dim3 gr((unsigned)((c.g.nn + 255) / 256)), bl(256);
 #define DI(RT, VT) hipLaunchKernelGGL((k_diag_inv<RT, VT>), gr, bl, 0, s, c.g, c.st, (const RT*)rho, c.mat, c.bits, (VT*)dinv)
@@ -779,14 +791,23 @@ static inline dim3 tile_block(const Ctx& c) { return dim3(c.CX * c.h.H, c.h.H); 
 static inline dim3 tile_grid(const Ctx& c) { return dim3((unsigned)(((c.ntiles + 7) / 8) * 8)); }
 
 static inline dim3 march_grid(const Ctx& c) { return dim3((unsigned)c.mg.blocks); }
+
+long long march_resident_blocks() {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 2048;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 2048;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(&k_apply<true, 1>),
+                                                   MARCH_THREADS, 0) != hipSuccess)
+    return 2048;
+  return (long long)(per > 0 ? per : 1) * (cus > 0 ? cus : 1);
+}
 static inline dim3 march_block() { return dim3(MX, MY); }
 
 void launch_apply(const Ctx& c, const double* x, double* y, int mode, hipStream_t s) {
   const dim3 gr = march_grid(c), bl = march_block();
-#define AP(RT, CU, MD) hipLaunchKernelGGL((k_apply<RT, CU, MD>), gr, bl, 0, s, c.g, c.st, c.mg, (const RT*)c.rho, c.mat, c.bits, x, y, c.sc, c.partials, c.counter)
-#define AP_M(RT, CU) do { if (mode == 0) AP(RT, CU, 0); else if (mode == 1) AP(RT, CU, 1); else AP(RT, CU, 2); } while (0)
-  if (c.rho_dt == DT_F64) { if (c.st.cubic) AP_M(double, true); else AP_M(double, false); }
-  else { if (c.st.cubic) AP_M(float, true); else AP_M(float, false); }
+#define AP(CU, MD) hipLaunchKernelGGL((k_apply<CU, MD>), gr, bl, 0, s, c.g, c.st, c.mg, c.kc, c.bits, x, y, c.sc, c.partials, c.counter)
+#define AP_M(CU) do { if (mode == 0) AP(CU, 0); else if (mode == 1) AP(CU, 1); else AP(CU, 2); } while (0)
+  if (c.st.cubic) AP_M(true); else AP_M(false);
 #undef AP_M
 #undef AP
 }
@@ -803,12 +824,12 @@ void launch_residual(const Ctx& c, const double* b, const double* x, const doubl
 
 // --- V-cycle level 0 ---------------------------------------------------------
 
-// dispatch over the cycle's types and CUBIC: VT vectors, RVT density copy, BT
-// basis R_c, DVT the Jacobi diagonal (FP64 only on the all-FP64 path)
-#define VC_CASE(VT_, RVT_, BT_, DVT_, ...)                                 \
+// dispatch over the cycle's types and CUBIC: VT vectors, KVT conductivity
+// copy, BT basis R_c, DVT the Jacobi diagonal (FP64 only on the all-FP64 path)
+#define VC_CASE(VT_, KVT_, BT_, DVT_, ...)                                 \
   {                                                                        \
     using VT = VT_;                                                        \
-    using RVT = RVT_;                                                      \
+    using KVT = KVT_;                                                      \
     using BT = BT_;                                                        \
     using DVT = DVT_;                                                      \
     if (c.st.cubic) {                                                      \
@@ -822,14 +843,12 @@ void launch_residual(const Ctx& c, const double* b, const double* x, const doubl
 #define VC_DISPATCH(...)                                                                       \
   do {                                                                                         \
     if (c.v_dt == DT_F64) {                                                                    \
-      if (c.b_dt == DT_F64) {                                                                  \
-        if (c.rhov_dt == DT_F64) VC_CASE(double, double, double, double, __VA_ARGS__)          \
-        else VC_CASE(double, float, double, double, __VA_ARGS__)                               \
-      } else if (c.b_dt == DT_BF16) VC_CASE(double, bf16, bf16, float, __VA_ARGS__)            \
+      if (c.b_dt == DT_F64) VC_CASE(double, double, double, double, __VA_ARGS__)               \
+      else if (c.b_dt == DT_BF16) VC_CASE(double, bf16, bf16, float, __VA_ARGS__)              \
       else VC_CASE(double, float, float, float, __VA_ARGS__)                                   \
     } else {                                                                                   \
-      if (c.rhov_dt == DT_BF16 && c.b_dt == DT_BF16) VC_CASE(float, bf16, bf16, float, __VA_ARGS__) \
-      else if (c.rhov_dt == DT_BF16) VC_CASE(float, bf16, float, float, __VA_ARGS__)           \
+      if (c.kv_dt == DT_BF16 && c.b_dt == DT_BF16) VC_CASE(float, bf16, bf16, float, __VA_ARGS__) \
+      else if (c.kv_dt == DT_BF16) VC_CASE(float, bf16, float, float, __VA_ARGS__)           \
       else if (c.b_dt == DT_BF16) VC_CASE(float, float, bf16, float, __VA_ARGS__)              \
       else VC_CASE(float, float, float, float, __VA_ARGS__)                                    \
     }                                                                                          \
@@ -855,15 +874,15 @@ void launch_smooth(const Ctx& c, const void* in, bool in_is_f64, void* out, hipS
       VT* xa = (deg % 2 == 0) ? o : (VT*)c.vc_t1;  // so that the last step lands in `out`
       VT* xb = (xa == o) ? (VT*)c.vc_t1 : o;
       if (in_is_f64)
-        hipLaunchKernelGGL((k_cheb2<VT, RVT, double, DVT, CU>), gr, bl, 0, s, c.g, c.st, c.mg, (const RVT*)c.rhov, c.mat, (const double*)in, dinv, xa, d, c.cheb, c.sc);
+        hipLaunchKernelGGL((k_cheb2<VT, KVT, double, DVT, CU>), gr, bl, 0, s, c.g, c.st, c.mg, (const KVT*)c.kv, (const double*)in, dinv, xa, d, c.cheb, c.sc);
       else
-        hipLaunchKernelGGL((k_cheb2<VT, RVT, VT, DVT, CU>), gr, bl, 0, s, c.g, c.st, c.mg, (const RVT*)c.rhov, c.mat, (const VT*)in, dinv, xa, d, c.cheb, c.sc);
+        hipLaunchKernelGGL((k_cheb2<VT, KVT, VT, DVT, CU>), gr, bl, 0, s, c.g, c.st, c.mg, (const KVT*)c.kv, (const VT*)in, dinv, xa, d, c.cheb, c.sc);
       for (int step = 2; step < deg; ++step) {
         const double ca = c.cheb.step_a[step], cb = c.cheb.step_b[step];
         if (in_is_f64)
-          hipLaunchKernelGGL((k_cheb_step<VT, RVT, double, DVT, CU>), gr, bl, 0, s, c.g, c.st, c.mg, (const RVT*)c.rhov, c.mat, (const double*)in, dinv, xa, d, xb, ca, cb, c.sc);
+          hipLaunchKernelGGL((k_cheb_step<VT, KVT, double, DVT, CU>), gr, bl, 0, s, c.g, c.st, c.mg, (const KVT*)c.kv, (const double*)in, dinv, xa, d, xb, ca, cb, c.sc);
         else
-          hipLaunchKernelGGL((k_cheb_step<VT, RVT, VT, DVT, CU>), gr, bl, 0, s, c.g, c.st, c.mg, (const RVT*)c.rhov, c.mat, (const VT*)in, dinv, xa, d, xb, ca, cb, c.sc);
+          hipLaunchKernelGGL((k_cheb_step<VT, KVT, VT, DVT, CU>), gr, bl, 0, s, c.g, c.st, c.mg, (const KVT*)c.kv, (const VT*)in, dinv, xa, d, xb, ca, cb, c.sc);
         VT* tmp = xa; xa = xb; xb = tmp;
       }
     }
@@ -890,7 +909,7 @@ void launch_restrict(const Ctx& c, const void* r, void* rc, hipStream_t s) {
   const dim3 gr = tile_grid(c), bl = tile_block(c);
   const size_t nthr = size_t(bl.x) * bl.y;
   VC_DISPATCH({
-    (void)sizeof(RVT);
+    (void)sizeof(KVT);
     (void)sizeof(DVT);
     (void)CU;
     const size_t sh = nthr * c.h.Lc * sizeof(double);
@@ -901,7 +920,7 @@ void launch_restrict(const Ctx& c, const void* r, void* rc, hipStream_t s) {
 void launch_prolong(const Ctx& c, const void* base, const void* e1, const void* e2, void* out, hipStream_t s) {
   const dim3 gr = tile_grid(c), bl = tile_block(c);
   VC_DISPATCH({
-    (void)sizeof(RVT);
+    (void)sizeof(KVT);
     (void)sizeof(DVT);
     (void)CU;
     L_DISPATCH(c.h.Lc, hipLaunchKernelGGL((k_prolong<VT, BT, LL>), gr, bl, 0, s, c.g, c.h, c.CX, (const VT*)base, (const BT*)c.Rc, (const double*)e1, (const double*)e2, (double*)out, c.sc));
@@ -915,9 +934,9 @@ void launch_vresidual(const Ctx& c, const void* r, bool r_is_f64, const void* x,
     (void)sizeof(BT);
     (void)sizeof(DVT);
     if (x_is_f64) {
-      hipLaunchKernelGGL((k_vresidual<VT, RVT, double, double, CU>), gr, bl, 0, s, c.g, c.st, c.mg, (const RVT*)c.rhov, c.mat, c.bits, (const double*)r, (const double*)x, (VT*)out, c.sc);
+      hipLaunchKernelGGL((k_vresidual<VT, KVT, double, double, CU>), gr, bl, 0, s, c.g, c.st, c.mg, (const KVT*)c.kv, c.bits, (const double*)r, (const double*)x, (VT*)out, c.sc);
     } else {
-      hipLaunchKernelGGL((k_vresidual<VT, RVT, double, VT, CU>), gr, bl, 0, s, c.g, c.st, c.mg, (const RVT*)c.rhov, c.mat, c.bits, (const double*)r, (const VT*)x, (VT*)out, c.sc);
+      hipLaunchKernelGGL((k_vresidual<VT, KVT, double, VT, CU>), gr, bl, 0, s, c.g, c.st, c.mg, (const KVT*)c.kv, c.bits, (const double*)r, (const VT*)x, (VT*)out, c.sc);
     }
     (void)r_is_f64;
   });

@@ -42,8 +42,9 @@ struct Ctx {
   March mg;           // plane-march decomposition of the fine stencil kernels
   const void* rho;    // canonical density (rho_dt)
   int rho_dt;
-  const void* rhov;   // V-cycle density copy (rhov_dt)
-  int rhov_dt;
+  const double* kc;   // element conductivities, FP64
+  const void* kv;     // conductivity copy read by the cycle (kv_dt; aliases kc for FP64)
+  int kv_dt;
   const uint32_t* bits;
   void* dinv;         // Jacobi D^-1, V-cycle type
   int v_dt;           // V-cycle vector type
@@ -60,8 +61,10 @@ struct Ctx {
 };
 
 // fine level
+long long march_resident_blocks();  // marching workgroups the device runs at once
 void launch_pack_mask(const uint8_t* mask, uint32_t* bits, long long nn, hipStream_t s);
 void launch_convert(const void* in, int din, void* out, int dout, long long n, hipStream_t s);
+void launch_conductivity(const Ctx& c, const void* rho, int rdt, double* kc, hipStream_t s);
 void launch_diag_inv(const Ctx& c, const void* rho, int rdt, void* dinv, int vdt, hipStream_t s);
 void launch_zero_fixed_copy(const Ctx& c, const double* in, double* out, hipStream_t s);
 void launch_finish_solution(const Ctx& c, double* T, const double* tfix, hipStream_t s);

@@ -1,54 +1,83 @@
 // 2.5D plane march for the fine-level stencil kernels.
 //
-// A workgroup of 64 x 8 threads owns a 64 x 8 column of nodes and marches over
-// a chunk of z planes.  Each step stages one node plane (with a 1-node halo,
-// 66 x 10 values) and one element layer (65 x 9 conductivities, computed from
-// rho once per element) in LDS through coalesced loads.  The operator is split
+// A workgroup of MX x MY threads (32 x 8) owns an MX x MY column of nodes and
+// marches over a chunk of z planes.  Each step stages one node plane (with a
+// 1-node halo, (MX+2) x (MY+2) values) and one element layer ((MX+1) x (MY+1)
+// conductivities) in LDS through coalesced loads.  The operator is split
 // by element layer: the layer between planes z and z+1 contributes to the
 // nodes of both planes, so a thread keeps only the 3 x 3 neighbourhood of its
 // node in plane z and one carried partial sum; a step costs 9 + 4 LDS reads
 // per node.  Two LDS buffers per plane type let one barrier per step suffice.
 //
 // Global loads are issued DEPTH steps ahead of their use into a register queue
-// holding the raw stored values (the conversion to the working type, e.g.
-// rho -> conductivity, happens when a slot is written to LDS), so no step waits
-// on a load issued in the same step.  Per-node data the output needs (diagonal,
-// right-hand side, mask word) is prefetched the same way.
+// holding the raw stored values (the conversion to the working type happens
+// when a slot is written to LDS), so no step waits on a load issued in the same
+// step.  Per-node data the output needs (diagonal, right-hand side, mask word)
+// is prefetched the same way.
 #pragma once
 
 #include "common.h"
 
 #ifndef MSMG_MARCH_DEPTH8
-#define MSMG_MARCH_DEPTH8 2
+#define MSMG_MARCH_DEPTH8 1
 #endif
 #ifndef MSMG_MARCH_DEPTH4
-#define MSMG_MARCH_DEPTH4 3
+#define MSMG_MARCH_DEPTH4 2
 #endif
 
 namespace msmg {
 
-constexpr int MX = 64, MY = 8;                  // node tile
-constexpr int PW = MX + 2, PH = MY + 2;         // node plane with halo
-constexpr int EW = MX + 1, EH = MY + 1;         // element layer
+#ifndef MSMG_MARCH_MX
+#define MSMG_MARCH_MX 32
+#endif
+#ifndef MSMG_MARCH_MY
+#define MSMG_MARCH_MY 8
+#endif
+#ifndef MSMG_MARCH_WAVES
+#define MSMG_MARCH_WAVES 1
+#endif
+
+constexpr int MX = MSMG_MARCH_MX, MY = MSMG_MARCH_MY;  // node tile (a wave covers 64 / MX rows)
+constexpr int PW = MX + 2, PH = MY + 2;                // node plane with halo
+constexpr int EW = MX + 1, EH = MY + 1;                // element layer
 constexpr int MARCH_THREADS = MX * MY;
+
+// Kernel attributes of the marching kernels: the register budget is capped so
+// that MSMG_MARCH_WAVES waves share each SIMD (several workgroups per CU at
+// different phases of their march hide each other's memory waits).
+#define MSMG_MARCH_KERNEL \
+  __global__ __launch_bounds__(MARCH_THREADS) __attribute__((amdgpu_waves_per_eu(MSMG_MARCH_WAVES)))
 
 struct March {
   int ntx, nty, nzc, zc;  // tiles along x, y; z chunks and their length
   long long blocks;       // ntx * nty * nzc rounded up to a multiple of 8
 };
 
-inline March make_march(const Geo& g, int target_blocks = 2048, int min_chunk = 16) {
+// Split the z range into chunks: every (x, y) tile column is cut into nzc
+// chunks of zc planes.  `resident` is the number of marching workgroups the
+// device runs at once; the chunk count minimises (rounds of resident
+// workgroups) x (planes a workgroup stages, zc + 2 with the prologue).
+inline March make_march(const Geo& g, long long resident = 2048, int min_chunk = 8) {
   March m;
   m.ntx = (g.nnx + MX - 1) / MX;
   m.nty = (g.nny + MY - 1) / MY;
   const long long txy = (long long)m.ntx * m.nty;
-  long long nzc = (target_blocks + txy - 1) / txy;
-  if (nzc < 1) nzc = 1;
-  int zc = int((g.nnz + nzc - 1) / nzc);
-  if (zc < min_chunk) zc = min_chunk;
-  if (zc > g.nnz) zc = g.nnz;
-  m.zc = zc;
-  m.nzc = (g.nnz + zc - 1) / zc;
+  if (resident < 1) resident = 1;
+  long long best_cost = -1;
+  int best = 1;
+  const int max_nzc = (g.nnz + min_chunk - 1) / min_chunk;
+  for (int nzc = 1; nzc <= max_nzc; ++nzc) {
+    const int zc = (g.nnz + nzc - 1) / nzc;
+    const int used = (g.nnz + zc - 1) / zc;
+    const long long rounds = (txy * used + resident - 1) / resident;
+    const long long cost = rounds * (zc + 2);
+    if (best_cost < 0 || cost < best_cost) {
+      best_cost = cost;
+      best = nzc;
+    }
+  }
+  m.zc = (g.nnz + best - 1) / best;
+  m.nzc = (g.nnz + m.zc - 1) / m.zc;
   m.blocks = ((txy * m.nzc + 7) / 8) * 8;
   return m;
 }
@@ -74,24 +103,41 @@ MSMG_DEV W layer_apply(const Stencil& st, const W kq[4], const W s[9], const W o
   return acc;
 }
 
+// Element base + ofs of an array, with the plane base kept apart from the
+// 32-bit in-plane offset.
+template <typename T>
+MSMG_DEV T plane_ld(const T* __restrict__ p, long long base, unsigned ofs) {
+  return p[base + ofs];
+}
+template <typename T>
+MSMG_DEV void plane_st(T* __restrict__ p, long long base, unsigned ofs, T v) {
+  p[base + ofs] = v;
+}
+
 template <typename W>
 constexpr int march_depth() {
   return sizeof(W) >= 8 ? MSMG_MARCH_DEPTH8 : MSMG_MARCH_DEPTH4;
 }
 
-// loadn(n) -> raw stored value(s) of node n, convn(raw) -> staged value;
-// loadk(e) -> raw value(s) of element e, convk(raw) -> conductivity;
-// loadc(n) -> per-node data for the output of node n (prefetched);
-// emit(i, j, k, n, Ax, xc, c) is called for every node of the tile inside the
-// mesh with Ax = (A x)_n in difference form, xc the staged value at n and c
-// the data loadc returned for n.
+// Nodes and elements are addressed as (plane base index, offset in the plane):
+// loadn(b, o) -> raw stored value(s) of node b + o, convn(raw) -> staged value;
+// loadk(b, o) -> raw value(s) of element b + o, convk(raw) -> conductivity;
+// loadc(b, o) -> per-node data for the output of node b + o (prefetched);
+// emit(b, o, Ax, xc, c) is called for every node of the tile inside the mesh
+// with Ax = (A x)_n in difference form, xc the staged value at n and c the data
+// loadc returned for n.
+//
+// Every load is issued unconditionally at a clamped in-mesh address (slots
+// outside the mesh stage 0 when written to LDS) and the step loop has a fixed
+// shape, so the compiler can count the loads in flight exactly and waits only
+// for the queue slot a step consumes.
 template <typename W, bool CUBIC, typename LoadN, typename ConvN, typename LoadK, typename ConvK, typename LoadC,
           typename Emit>
 MSMG_DEV void march(const Geo& g, const Stencil& st, const March& mg, long long tile, W* sx, W* sk, LoadN loadn,
                     ConvN convn, LoadK loadk, ConvK convk, LoadC loadc, Emit emit) {
-  using RN = decltype(loadn(0LL));
-  using RK = decltype(loadk(0LL));
-  using CD = decltype(loadc(0LL));
+  using RN = decltype(loadn(0LL, 0u));
+  using RK = decltype(loadk(0LL, 0u));
+  using CD = decltype(loadc(0LL, 0u));
   constexpr int DEPTH = march_depth<W>();
   const int tx = int(tile % mg.ntx), ty = int((tile / mg.ntx) % mg.nty), tz = int(tile / ((long long)mg.ntx * mg.nty));
   const int za = tz * mg.zc;
@@ -106,53 +152,45 @@ MSMG_DEV void march(const Geo& g, const Stencil& st, const March& mg, long long 
   constexpr int NS = (PW * PH + MARCH_THREADS - 1) / MARCH_THREADS;  // node slots per thread
   constexpr int ES = (EW * EH + MARCH_THREADS - 1) / MARCH_THREADS;  // element slots per thread
   const long long nplane = (long long)g.nnx * g.nny, eplane = (long long)g.nx * g.ny;
-  int nofs[NS], eofs[ES];
+  unsigned nofs[NS], eofs[ES];
+  unsigned nvalid = 0, evalid = 0;
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const int q = tid + s * MARCH_THREADS;
     const int gx = xa - 1 + q % PW, gy = ya - 1 + q / PW;
-    nofs[s] = (q < PW * PH && gx >= 0 && gx < g.nnx && gy >= 0 && gy < g.nny) ? gy * g.nnx + gx : -1;
+    if (q < PW * PH && gx >= 0 && gx < g.nnx && gy >= 0 && gy < g.nny) nvalid |= 1u << s;
+    nofs[s] = unsigned(min(max(gy, 0), g.nny - 1) * g.nnx + min(max(gx, 0), g.nnx - 1));
   }
 #pragma unroll
   for (int s = 0; s < ES; ++s) {
     const int q = tid + s * MARCH_THREADS;
     const int ex = xa - 1 + q % EW, ey = ya - 1 + q / EW;
-    eofs[s] = (q < EW * EH && ex >= 0 && ex < g.nx && ey >= 0 && ey < g.ny) ? ey * g.nx + ex : -1;
+    if (q < EW * EH && ex >= 0 && ex < g.nx && ey >= 0 && ey < g.ny) evalid |= 1u << s;
+    eofs[s] = unsigned(min(max(ey, 0), g.ny - 1) * g.nx + min(max(ex, 0), g.nx - 1));
   }
-  const long long cxy = inside ? (long long)y * g.nnx + x : 0;
+  const unsigned cxy = unsigned(min(y, g.nny - 1) * g.nnx + min(x, g.nnx - 1));
 
   RN pn[DEPTH][NS];
   RK pk[DEPTH][ES];
   CD pc[DEPTH];
-#pragma unroll
-  for (int d = 0; d < DEPTH; ++d) {
-#pragma unroll
-    for (int s = 0; s < NS; ++s) pn[d][s] = RN{};
-#pragma unroll
-    for (int s = 0; s < ES; ++s) pk[d][s] = RK{};
-    pc[d] = CD{};
-  }
   auto load_nodes = [&](int d, int zz) {
-    if (zz < 0 || zz >= g.nnz) return;
+    const long long base = (long long)min(max(zz, 0), g.nnz - 1) * nplane;
 #pragma unroll
-    for (int s = 0; s < NS; ++s)
-      if (nofs[s] >= 0) pn[d][s] = loadn(nofs[s] + zz * nplane);
+    for (int s = 0; s < NS; ++s) pn[d][s] = loadn(base, nofs[s]);
   };
   auto load_elems = [&](int d, int ez) {
-    if (ez < 0 || ez >= g.nz) return;
+    const long long base = (long long)min(max(ez, 0), g.nz - 1) * eplane;
 #pragma unroll
-    for (int s = 0; s < ES; ++s)
-      if (eofs[s] >= 0) pk[d][s] = loadk(eofs[s] + ez * eplane);
+    for (int s = 0; s < ES; ++s) pk[d][s] = loadk(base, eofs[s]);
   };
-  auto load_centre = [&](int d, int zz) {
-    if (inside && zz < zb) pc[d] = loadc(cxy + zz * nplane);
-  };
+  auto load_centre = [&](int d, int zz) { pc[d] = loadc((long long)min(zz, g.nnz - 1) * nplane, cxy); };
   auto store_nodes = [&](int d, int buf, int zz) {
     const bool zin = zz >= 0 && zz < g.nnz;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const int q = tid + s * MARCH_THREADS;
-      if (q < PW * PH) sx[buf * PW * PH + q] = (zin && nofs[s] >= 0) ? convn(pn[d][s]) : W(0);
+      const W v = convn(pn[d][s]);
+      if (q < PW * PH) sx[buf * PW * PH + q] = (zin && ((nvalid >> s) & 1u)) ? v : W(0);
     }
   };
   auto store_elems = [&](int d, int buf, int ez) {
@@ -160,7 +198,8 @@ MSMG_DEV void march(const Geo& g, const Stencil& st, const March& mg, long long 
 #pragma unroll
     for (int s = 0; s < ES; ++s) {
       const int q = tid + s * MARCH_THREADS;
-      if (q < EW * EH) sk[buf * EW * EH + q] = (zin && eofs[s] >= 0) ? convk(pk[d][s]) : W(0);
+      const W v = convk(pk[d][s]);
+      if (q < EW * EH) sk[buf * EW * EH + q] = (zin && ((evalid >> s) & 1u)) ? v : W(0);
     }
   };
   auto read_plane = [&](int buf, W* dst) {
@@ -202,29 +241,26 @@ MSMG_DEV void march(const Geo& g, const Stencil& st, const March& mg, long long 
     load_elems(d, za + d);
     load_centre(d, za + d);
   }
-  for (int z0 = za; z0 < zb; z0 += DEPTH) {
+  // whole rounds of DEPTH steps; steps past zb stage clamped planes and emit nothing
+  const int zend = za + (zb - za + DEPTH - 1) / DEPTH * DEPTH;
+  for (int z0 = za; z0 < zend; z0 += DEPTH) {
 #pragma unroll
     for (int d = 0; d < DEPTH; ++d) {
       const int z = z0 + d;
-      if (z >= zb) break;  // uniform over the block
       const int buf = (z - za) & 1;
       store_nodes(d, buf, z + 1);
       store_elems(d, buf, z);
       const CD cur = pc[d];
       __syncthreads();
       // refill this queue slot; the other slots' loads are still in flight
-      if (z + DEPTH < zb) {
-        load_nodes(d, z + 1 + DEPTH);
-        load_elems(d, z + DEPTH);
-        load_centre(d, z + DEPTH);
-      }
+      load_nodes(d, z + 1 + DEPTH);
+      load_elems(d, z + DEPTH);
+      load_centre(d, z + DEPTH);
       W B[9], kq[4];
       read_plane(buf, B);
       read_k(buf, kq);
-      if (inside) {
-        const W ax = carry + layer_apply<W, CUBIC>(st, kq, A, B);
-        emit(x, y, z, cxy + z * nplane, ax, A[4], cur);
-      }
+      const W ax = carry + layer_apply<W, CUBIC>(st, kq, A, B);
+      if (inside && z < zb) emit((long long)z * nplane, cxy, ax, A[4], cur);
       carry = layer_apply<W, CUBIC>(st, kq, B, A);
 #pragma unroll
       for (int q = 0; q < 9; ++q) A[q] = B[q];

@@ -44,12 +44,13 @@ struct msmg_handle {
   long long ntiles = 0;
   double lam_bound = 0.0;  // upper bound of the level-1 standard-form spectrum
   Material mat{};
-  int rho_dt = DT_F64, rhov_dt = DT_F64, v_dt = DT_F64, b_dt = DT_F64, a_dt = DT_F64, dv_dt = DT_F64;
+  int rho_dt = DT_F64, kv_dt = DT_F64, v_dt = DT_F64, b_dt = DT_F64, a_dt = DT_F64, dv_dt = DT_F64;
   bool mg = true;
 
   // density, mask, fixed values
   void* rho = nullptr;
-  void* rhov = nullptr;  // may alias rho
+  double* kc = nullptr;   // element conductivities (FP64)
+  void* kv = nullptr;     // conductivity copy read by the cycle; may alias kc
   uint32_t* bits = nullptr;
   double* tfix = nullptr;
   bool has_tfix = false;
@@ -90,6 +91,7 @@ struct msmg_handle {
   double* partials = nullptr;
   unsigned* counter = nullptr;
   int red_blocks = 4096;
+  long long march_resident = 2048;  // marching workgroups resident at once (queried at create)
   long long partial_slots = 0;
 
   SetupScratch scratch{};
@@ -245,11 +247,12 @@ static Ctx make_ctx(msmg_handle* h) {
   c.mat = h->mat;
   c.CX = h->CX;
   c.ntiles = h->ntiles;
-  c.mg = make_march(h->g);
+  c.mg = make_march(h->g, h->march_resident);
   c.rho = h->rho;
   c.rho_dt = h->rho_dt;
-  c.rhov = h->rhov;
-  c.rhov_dt = h->rhov_dt;
+  c.kc = h->kc;
+  c.kv = h->kv;
+  c.kv_dt = h->kv_dt;
   c.bits = h->bits;
   c.dinv = h->dinv;
   c.v_dt = h->v_dt;
@@ -392,6 +395,7 @@ extern "C" int msmg_create(msmg_handle** out, int nx, int ny, int nz, double lx,
   msmg_handle* h = new msmg_handle();
   h->opt = o;
   HIP_TRY(hipGetDevice(&h->device));
+  h->march_resident = march_resident_blocks();
   h->g = make_geo(nx, ny, nz, lx, ly, lz);
   double lmk0 = 0.0;
   h->st = make_stencil(h->g, &lmk0);
@@ -406,7 +410,7 @@ extern "C" int msmg_create(msmg_handle** out, int nx, int ny, int nz, double lx,
   h->h_cc_ptr = P.cc_ptr;
   h->mg = (o.pc_kind == MSMG_PC_MULTIGRID);
   h->v_dt = o.vcycle_dtype;
-  h->rhov_dt = o.rho_v_dtype;
+  h->kv_dt = o.rho_v_dtype;
   h->b_dt = o.basis_dtype;
   h->a_dt = DT_F64;  // level 1 and 2 stay FP64 on every path (see the mixed-precision notes)
   const long long nn = h->g.nn, ne = h->g.ne;
@@ -416,7 +420,8 @@ extern "C" int msmg_create(msmg_handle** out, int nx, int ny, int nz, double lx,
     if (rc == MSMG_OK) rc = dev_alloc(h, p, bytes);
   };
   A(&h->rho, ne * 8);
-  if (h->rhov_dt != DT_F64) A(&h->rhov, ne * dt_size(h->rhov_dt));
+  A(&h->kc, ne * 8);
+  if (h->kv_dt != DT_F64) A(&h->kv, ne * dt_size(h->kv_dt));
   A(&h->bits, ((nn + 31) / 32) * 4);
   // Jacobi diagonal: FP64 only on the all-FP64 path (a fixed coefficient like rho)
   h->dv_dt = (h->v_dt == DT_F64 && h->b_dt == DT_F64) ? DT_F64 : DT_F32;
@@ -466,7 +471,7 @@ extern "C" int msmg_create(msmg_handle** out, int nx, int ny, int nz, double lx,
     delete h;
     return rc;
   }
-  if (!h->rhov) h->rhov = h->rho;
+  if (!h->kv) h->kv = h->kc;
   if (!h->Rcs) h->Rcs = h->Rc64;
   if (!h->Acv) h->Acv = h->Ac64;
   if (!h->AcDinvv) h->AcDinvv = h->AcDinv64;
@@ -530,8 +535,6 @@ extern "C" int msmg_setup(msmg_handle* h, const void* rho, msmg_dtype rho_dtype,
   const long long nn = h->g.nn, ne = h->g.ne;
   launch_convert(rho, rho_dtype, h->rho, rho_dtype, ne, s);
   launch_pack_mask(mask, h->bits, nn, s);
-  if (h->rhov != h->rho) launch_convert(rho, rho_dtype, h->rhov, h->rhov_dt, ne, s);
-  else h->rhov_dt = rho_dtype;
   if (fixed_values) {
     if (!h->tfix) TRY(dev_alloc(h, &h->tfix, nn * 8));
     // tfix = values on fixed nodes, 0 elsewhere
@@ -550,6 +553,8 @@ extern "C" int msmg_setup(msmg_handle* h, const void* rho, msmg_dtype rho_dtype,
     if (nfixed == 0) return fail(MSMG_ESINGULAR, "the Dirichlet mask is empty: the operator is singular");
   }
   Ctx c = make_ctx(h);
+  launch_conductivity(c, h->rho, h->rho_dt, h->kc, s);
+  if (h->kv != h->kc) launch_convert(h->kc, DT_F64, h->kv, h->kv_dt, ne, s);
   launch_diag_inv(c, h->rho, h->rho_dt, h->dinv, h->dv_dt, s);
   HIP_TRY(hipGetLastError());
   if (h->mg) {

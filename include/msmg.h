@@ -144,6 +144,14 @@ int msmg_setup(msmg_handle* h, const void* rho, msmg_dtype rho_dtype, double k_m
 int msmg_solve(msmg_handle* h, const double* f, double* T, double* T_lo, int use_x0, double rtol, int maxit,
                msmg_info* info, hipStream_t stream);
 
+/* Adjoint solve of the sensitivity analysis (section 2.3, eq. adjoint): A_FF u_F = g_F
+ * with zero fixed entries (u = lambda), whatever fixed values the set-up was given,
+ * reusing the set-up of the last msmg_setup.  Arguments, outputs and return codes as
+ * for msmg_solve (g: nodal FP64, entries on fixed nodes ignored; lambda: nodal FP64,
+ * zero on fixed nodes; lambda_lo nullable). */
+int msmg_solve_adjoint(msmg_handle* h, const double* g, double* lambda, double* lambda_lo, int use_x0, double rtol,
+                       int maxit, msmg_info* info, hipStream_t stream);
+
 /* Element sensitivities dc/drho_e = -p rho_e^(p-1) (k_max - k_min) lambda_e^T K0 T_e
  * (evaluated as -sum_{a<b} K0_ab (lambda_a - lambda_b)(T_a - T_b), exact for zero-row-sum K0)
  * (section 2.3 with a design-independent load).  lambda: nodal adjoint with zero
@@ -170,6 +178,28 @@ int msmg_prolong_nodal(int nx, int ny, int nz, const double* Tc, double* Tf, hip
 /* Element injection (nx,ny,nz) -> (2nx,2ny,2nz) of an element field of dtype dt
  * (each child takes its parent's value). */
 int msmg_prolong_element(int nx, int ny, int nz, const void* rc, void* rf, msmg_dtype dt, hipStream_t stream);
+
+/* Density filter of the optimisation loop (a design-variable filter: the
+ * paper's MMA loop of section 4 works on filtered densities; the weights are
+ * the usual linear hat): w(e,f) = max(0, radius - |c_e - c_f|) with element
+ * centres in element units, summed over elements inside the nx*ny*nz mesh.
+ *   transpose = 0: out_e = sum_f w(e,f) in_f / W_e,  W_e = sum_f w(e,f)
+ *   transpose != 0: out_f = sum_e w(e,f) in_e / W_e (its adjoint, for chain-rule
+ *                   sensitivities)
+ * in, out: element FP64 device arrays (caller-owned, must not alias).
+ * radius in (1, 4]; MSMG_EINVAL otherwise. */
+int msmg_density_filter(int nx, int ny, int nz, double radius, const double* in, double* out, int transpose,
+                        hipStream_t stream);
+
+/* Optimality-criteria design update (a stand-in for the MMA step of section
+ * 2.3): x_new_e = clamp(x_e (-dc_e / (lambda dv_e))^eta, max(x_min, x_e - move),
+ * min(1, x_e + move)) with the multiplier lambda > 0 found on the device so that
+ * sum_e x_new_e = volume_fraction * elements.  x, dc, dv, x_new: element FP64
+ * device arrays of the handle's mesh (dv > 0; x_new must not alias the inputs).
+ * lambda: nullable device pointer receiving the multiplier.  Uses the handle's
+ * reduction scratch (do not overlap with other calls on the handle). */
+int msmg_oc_update(msmg_handle* h, const double* x, const double* dc, const double* dv, double volume_fraction,
+                   double move, double eta, double x_min, double* x_new, double* lambda, hipStream_t stream);
 
 /* Diagnostics of the last set-up, copied to host memory (blocking):
  *   what = 0: level-1 eigenvalues, ncells*Lc doubles (padded entries 0)

@@ -85,12 +85,15 @@ SIGNATURES = [
     ("msmg_create", _I, [ctypes.POINTER(_VP), _I, _I, _I, _D, _D, _D, ctypes.POINTER(Options)]),
     ("msmg_setup", _I, [_VP, _VP, _I, _D, _D, _I, _VP, _VP, _VP]),
     ("msmg_solve", _I, [_VP, _VP, _VP, _VP, _I, _D, _I, ctypes.POINTER(Info), _VP]),
+    ("msmg_solve_adjoint", _I, [_VP, _VP, _VP, _VP, _I, _D, _I, ctypes.POINTER(Info), _VP]),
     ("msmg_sensitivity", _I, [_VP, _VP, _VP, _VP, _VP]),
     ("msmg_apply", _I, [_VP, _VP, _VP, _VP]),
     ("msmg_precondition", _I, [_VP, _VP, _VP, _VP]),
     ("msmg_element_load", _I, [_VP, _VP, _D, _VP, _VP]),
     ("msmg_prolong_nodal", _I, [_I, _I, _I, _VP, _VP, _VP]),
     ("msmg_prolong_element", _I, [_I, _I, _I, _VP, _VP, _I, _VP]),
+    ("msmg_density_filter", _I, [_I, _I, _I, _D, _VP, _VP, _I, _VP]),
+    ("msmg_oc_update", _I, [_VP, _VP, _VP, _VP, _D, _D, _D, _D, _VP, _VP, _VP]),
     ("msmg_export", _I, [_VP, _I, _VP, _SZ]),
     ("msmg_destroy", None, [_VP]),
     ("msmg_last_error", ctypes.c_char_p, []),

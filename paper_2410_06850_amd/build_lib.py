@@ -24,6 +24,7 @@ SOURCES = [
     "setup_local.hip",
     "setup_coarse.hip",
     "setup_driver.hip",
+    "topopt_kernels.hip",
     "runtime.cpp",
 ]
 

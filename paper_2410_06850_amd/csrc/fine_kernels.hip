@@ -715,12 +715,6 @@ int count_fixed(const Ctx& c, int* nfixed, hipStream_t s) {
 // Launchers
 // ===========================================================================
 
-static inline int grid1d(long long n, int bs, int cap = 4096) {
-  long long b = (n + bs - 1) / bs;
-  if (b < 1) b = 1;
-  if (b > cap) b = cap;
-  return int(b);
-}
 
 void launch_pack_mask(const uint8_t* mask, uint32_t* bits, long long nn, hipStream_t s) {
   const long long nw = (nn + 31) >> 5;

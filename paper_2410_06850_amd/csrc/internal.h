@@ -60,6 +60,21 @@ struct Ctx {
   CoarseCtx cc;
 };
 
+// 1-D launch size: one thread per item, at most `cap` workgroups (grid-stride loops)
+inline int grid1d(long long n, int bs, int cap = 4096) {
+  long long b = (n + bs - 1) / bs;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return int(b);
+}
+
+// design update (density filter, optimality criteria)
+void launch_density_filter(int nx, int ny, int nz, double r, const double* in, double* out, bool transpose,
+                           hipStream_t s);
+void launch_oc_update(long long ne, const double* x, const double* dc, const double* dv, double volume, double move,
+                      double eta, double xmin, double* xnew, double* lam_out, void* state, double* partials,
+                      unsigned* counter, int passes, hipStream_t s);
+
 // fine level
 long long march_resident_blocks();  // marching workgroups the device runs at once
 void launch_pack_mask(const uint8_t* mask, uint32_t* bits, long long nn, hipStream_t s);

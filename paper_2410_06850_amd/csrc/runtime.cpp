@@ -93,6 +93,7 @@ struct msmg_handle {
   int red_blocks = 4096;
   long long march_resident = 2048;  // marching workgroups resident at once (queried at create)
   long long partial_slots = 0;
+  void* oc_state = nullptr;  // bracket of the OC multiplier
 
   SetupScratch scratch{};
   bool setup_done = false;
@@ -433,6 +434,7 @@ extern "C" int msmg_create(msmg_handle** out, int nx, int ny, int nz, double lx,
   h->partial_slots = std::max<long long>(h->ntiles + 8, 8192);
   A(&h->partials, h->partial_slots * 2 * 8);
   A(&h->counter, 64);
+  A(&h->oc_state, 64);
   A(&h->sc, sizeof(Scalars));
   if (h->mg && rc == MSMG_OK) {
     A(&h->v_r2, nn * 8);  // prolongated iterate: FP64 on every path
@@ -684,17 +686,20 @@ extern "C" int msmg_prolong_element(int nx, int ny, int nz, const void* rc, void
   return MSMG_OK;
 }
 
-extern "C" int msmg_solve(msmg_handle* h, const double* f, double* T, double* T_lo, int use_x0, double rtol,
-                          int maxit, msmg_info* info, hipStream_t s) {
+// PCG driver shared by the state and adjoint solves.  `homogeneous` solves
+// with zero fixed values (the adjoint system), ignoring the set-up's values.
+static int solve_impl(msmg_handle* h, const double* f, double* T, double* T_lo, int use_x0, double rtol, int maxit,
+                      msmg_info* info, hipStream_t s, bool homogeneous) {
   if (!h || !f || !T) return fail(MSMG_EINVAL, "NULL argument");
   if (!h->setup_done) return fail(MSMG_ESTATE, "msmg_setup has not completed");
   if (!(rtol >= 0.0) || maxit < 0) return fail(MSMG_EINVAL, "need rtol >= 0 and maxit >= 0");
   if (f == T || (T_lo && (T_lo == T || T_lo == f))) return fail(MSMG_EINVAL, "f, T and T_lo must not alias");
   const double t0 = now_ms();
   Ctx c = make_ctx(h);
+  const double* lift = (h->has_tfix && !homogeneous) ? h->tfix : nullptr;
   double* x = T;
   // b = f - A t_fix on free rows (0 on fixed rows)
-  if (h->has_tfix) launch_residual(c, f, h->tfix, nullptr, h->b, false, s);
+  if (lift) launch_residual(c, f, lift, nullptr, h->b, false, s);
   else launch_zero_fixed_copy(c, f, h->b, s);
   // x: free entries of the guess (or 0), fixed entries 0 during the iteration
   if (use_x0) launch_zero_fixed_copy(c, T, x, s);
@@ -714,7 +719,7 @@ extern "C" int msmg_solve(msmg_handle* h, const double* f, double* T, double* T_
   if (!(bb > 0.0)) {
     // zero right-hand side: the solution is the lift alone
     launch_fill(c, x, 0.0, s);
-    launch_finish_solution_dd(c, T, h->xlo, T_lo, h->has_tfix ? h->tfix : nullptr, s);
+    launch_finish_solution_dd(c, T, h->xlo, T_lo, lift, s);
     HIP_TRY(hipStreamSynchronize(s));
     if (info) {
       std::memset(info, 0, sizeof(*info));
@@ -792,7 +797,7 @@ extern "C" int msmg_solve(msmg_handle* h, const double* f, double* T, double* T_
     status = MSMG_MAXIT;
     rel = std::sqrt(h->sc_host->rr / bb);
   }
-  launch_finish_solution_dd(c, T, h->xlo, T_lo, h->has_tfix ? h->tfix : nullptr, s);
+  launch_finish_solution_dd(c, T, h->xlo, T_lo, lift, s);
   HIP_TRY(hipStreamSynchronize(s));
   HIP_TRY(hipGetLastError());
   if (info) {
@@ -828,6 +833,16 @@ extern "C" int msmg_solve(msmg_handle* h, const double* f, double* T, double* T_
   return status;
 }
 
+extern "C" int msmg_solve(msmg_handle* h, const double* f, double* T, double* T_lo, int use_x0, double rtol,
+                          int maxit, msmg_info* info, hipStream_t s) {
+  return solve_impl(h, f, T, T_lo, use_x0, rtol, maxit, info, s, false);
+}
+
+extern "C" int msmg_solve_adjoint(msmg_handle* h, const double* g, double* lambda, double* lambda_lo, int use_x0,
+                                  double rtol, int maxit, msmg_info* info, hipStream_t s) {
+  return solve_impl(h, g, lambda, lambda_lo, use_x0, rtol, maxit, info, s, true);
+}
+
 extern "C" int msmg_export(msmg_handle* h, int what, void* host_out, size_t bytes) {
   if (!h || !host_out) return fail(MSMG_EINVAL, "NULL argument");
   if (!h->setup_done) return fail(MSMG_ESTATE, "msmg_setup has not completed");
@@ -847,5 +862,34 @@ extern "C" int msmg_export(msmg_handle* h, int what, void* host_out, size_t byte
   if (bytes < need) return fail(MSMG_EINVAL, "output buffer too small: need " + std::to_string(need) + " bytes");
   HIP_TRY(hipDeviceSynchronize());
   HIP_TRY(hipMemcpy(host_out, src, need, hipMemcpyDeviceToHost));
+  return MSMG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Design update helpers of the optimisation loop.
+
+extern "C" int msmg_density_filter(int nx, int ny, int nz, double radius, const double* in, double* out,
+                                   int transpose, hipStream_t s) {
+  if (nx < 1 || ny < 1 || nz < 1) return fail(MSMG_EINVAL, "mesh sizes must be >= 1");
+  if (!(radius > 1.0) || radius > 4.0) return fail(MSMG_EINVAL, "filter radius must be in (1, 4] elements");
+  if (!in || !out) return fail(MSMG_EINVAL, "NULL argument");
+  if (in == out) return fail(MSMG_EINVAL, "in and out must not alias");
+  launch_density_filter(nx, ny, nz, radius, in, out, transpose != 0, s);
+  HIP_TRY(hipGetLastError());
+  return MSMG_OK;
+}
+
+extern "C" int msmg_oc_update(msmg_handle* h, const double* x, const double* dc, const double* dv,
+                              double volume_fraction, double move, double eta, double x_min, double* x_new,
+                              double* lambda, hipStream_t s) {
+  if (!h || !x || !dc || !dv || !x_new) return fail(MSMG_EINVAL, "NULL argument");
+  if (x_new == x || x_new == dc || x_new == dv) return fail(MSMG_EINVAL, "x_new must not alias the inputs");
+  if (!(volume_fraction > 0.0 && volume_fraction <= 1.0)) return fail(MSMG_EINVAL, "volume fraction in (0, 1]");
+  if (!(move > 0.0) || !(eta > 0.0) || !(x_min >= 0.0 && x_min < 1.0))
+    return fail(MSMG_EINVAL, "need move > 0, eta > 0, 0 <= x_min < 1");
+  const long long ne = h->g.ne;
+  launch_oc_update(ne, x, dc, dv, volume_fraction * double(ne), move, eta, x_min, x_new, lambda, h->oc_state,
+                   h->partials, h->counter, 8, s);
+  HIP_TRY(hipGetLastError());
   return MSMG_OK;
 }

@@ -1,0 +1,144 @@
+// Design-update kernels around the solve: the density filter and the
+// optimality-criteria (OC) update used by the topology-optimisation loop.
+#include <cmath>
+
+#include "common.h"
+#include "internal.h"
+
+namespace msmg {
+
+// ---------------------------------------------------------------------------
+// Density filter with the linear hat weights w(e, f) = max(0, r - |c_e - c_f|)
+// (distances between element centres, in elements).
+//   forward:   out_e = sum_f w(e,f) in_f / W_e,  W_e = sum_f w(e,f)
+//   transpose: out_f = sum_e w(e,f) in_e / W_e   (the chain rule of forward)
+// Sums run over elements inside the mesh; R = the largest offset with w > 0.
+MSMG_DEV double hat(double r, int dx, int dy, int dz) {
+  const double d = sqrt(double(dx * dx + dy * dy + dz * dz));
+  return d < r ? r - d : 0.0;
+}
+
+MSMG_DEV double filter_weight_sum(int nx, int ny, int nz, int R, double r, int i, int j, int k) {
+  double W = 0.0;
+  for (int dz = -R; dz <= R; ++dz)
+    for (int dy = -R; dy <= R; ++dy)
+      for (int dx = -R; dx <= R; ++dx) {
+        const int a = i + dx, b = j + dy, c = k + dz;
+        if (a < 0 || a >= nx || b < 0 || b >= ny || c < 0 || c >= nz) continue;
+        W += hat(r, dx, dy, dz);
+      }
+  return W;
+}
+
+template <bool TRANSPOSE>
+__global__ void k_density_filter(int nx, int ny, int nz, int R, double r, const double* __restrict__ in,
+                                 double* __restrict__ out) {
+  const long long ne = (long long)nx * ny * nz;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < ne; e += (long long)gridDim.x * blockDim.x) {
+    const int i = int(e % nx), j = int((e / nx) % ny), k = int(e / ((long long)nx * ny));
+    double acc = 0.0, W = 0.0;
+    for (int dz = -R; dz <= R; ++dz)
+      for (int dy = -R; dy <= R; ++dy)
+        for (int dx = -R; dx <= R; ++dx) {
+          const int a = i + dx, b = j + dy, c = k + dz;
+          if (a < 0 || a >= nx || b < 0 || b >= ny || c < 0 || c >= nz) continue;
+          const double w = hat(r, dx, dy, dz);
+          if (w == 0.0) continue;
+          const long long f = ((long long)c * ny + b) * nx + a;
+          if (TRANSPOSE)
+            acc += w * in[f] / filter_weight_sum(nx, ny, nz, R, r, a, b, c);
+          else
+            acc += w * in[f];
+          W += w;
+        }
+    out[e] = TRANSPOSE ? acc : acc / W;
+  }
+}
+
+void launch_density_filter(int nx, int ny, int nz, double r, const double* in, double* out, bool transpose,
+                           hipStream_t s) {
+  int R = int(r);
+  if (double(R) >= r) R -= 1;  // offsets with |d| < r
+  const long long ne = (long long)nx * ny * nz;
+  const dim3 gr(grid1d(ne, 256, 65536)), bl(256);
+  if (transpose)
+    hipLaunchKernelGGL(k_density_filter<true>, gr, bl, 0, s, nx, ny, nz, R, r, in, out);
+  else
+    hipLaunchKernelGGL(k_density_filter<false>, gr, bl, 0, s, nx, ny, nz, R, r, in, out);
+}
+
+// ---------------------------------------------------------------------------
+// OC update: x_new(lambda) = clamp(x (-dc / (lambda dv))^eta, max(x_min, x - m), min(1, x + m))
+// with lambda chosen so that sum x_new = volume (the volume is decreasing in
+// lambda).  The multiplier is bracketed on a log scale: every pass evaluates
+// the volume at OC_NL points of the current bracket in one sweep over the
+// design and keeps the sub-interval that holds the target.
+constexpr int OC_NL = 32;
+constexpr int OC_BLOCKS = 256;
+
+struct OCState {
+  double log_lo, log_hi;  // bracket of log(lambda)
+};
+
+MSMG_DEV double oc_new(double x, double dc, double dv, double lam, double move, double eta, double xmin) {
+  const double lo = fmax(xmin, x - move), hi = fmin(1.0, x + move);
+  const double B = fmax(0.0, -dc) / (lam * dv);
+  double v = x * pow(B, eta);
+  v = fmin(fmax(v, lo), hi);
+  return v;
+}
+
+__global__ void k_oc_init(OCState* st, double log_lo, double log_hi) {
+  st->log_lo = log_lo;
+  st->log_hi = log_hi;
+}
+
+__global__ void k_oc_volumes(long long ne, const double* __restrict__ x, const double* __restrict__ dc,
+                             const double* __restrict__ dv, double move, double eta, double xmin, double target,
+                             OCState* st, double* partials, unsigned* counter) {
+  __shared__ double red[OC_NL * 16];
+  const double llo = st->log_lo, lhi = st->log_hi;
+  double lam[OC_NL];
+#pragma unroll
+  for (int q = 0; q < OC_NL; ++q) lam[q] = exp(llo + (lhi - llo) * q / double(OC_NL - 1));
+  double v[OC_NL];
+#pragma unroll
+  for (int q = 0; q < OC_NL; ++q) v[q] = 0.0;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < ne; e += (long long)gridDim.x * blockDim.x) {
+    const double xe = x[e], de = dc[e], ve = dv[e];
+#pragma unroll
+    for (int q = 0; q < OC_NL; ++q) v[q] += oc_new(xe, de, ve, lam[q], move, eta, xmin);
+  }
+  grid_reduce<OC_NL>(v, red, partials, counter, gridDim.x, blockIdx.x, [&](double* vol) {
+    // vol[q] is non-increasing in q; keep [lambda_q, lambda_{q+1}] with
+    // vol[q] >= target >= vol[q+1] (the ends when the target is outside)
+    int q = 0;
+    while (q < OC_NL - 2 && vol[q + 1] >= target) ++q;
+    const double step = (lhi - llo) / double(OC_NL - 1);
+    st->log_lo = llo + step * q;
+    st->log_hi = llo + step * (q + 1);
+  });
+}
+
+__global__ void k_oc_apply(long long ne, const double* __restrict__ x, const double* __restrict__ dc,
+                           const double* __restrict__ dv, double move, double eta, double xmin,
+                           const OCState* st, double* __restrict__ xnew, double* lam_out) {
+  const double lam = exp(0.5 * (st->log_lo + st->log_hi));
+  if (lam_out && blockIdx.x == 0 && threadIdx.x == 0) *lam_out = lam;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < ne; e += (long long)gridDim.x * blockDim.x)
+    xnew[e] = oc_new(x[e], dc[e], dv[e], lam, move, eta, xmin);
+}
+
+void launch_oc_update(long long ne, const double* x, const double* dc, const double* dv, double volume, double move,
+                      double eta, double xmin, double* xnew, double* lam_out, void* state, double* partials,
+                      unsigned* counter, int passes, hipStream_t s) {
+  OCState* st = (OCState*)state;
+  hipLaunchKernelGGL(k_oc_init, dim3(1), dim3(1), 0, s, st, std::log(1e-40), std::log(1e40));
+  for (int it = 0; it < passes; ++it)
+    hipLaunchKernelGGL(k_oc_volumes, dim3(OC_BLOCKS), dim3(256), 0, s, ne, x, dc, dv, move, eta, xmin, volume, st,
+                       partials, counter);
+  hipLaunchKernelGGL(k_oc_apply, dim3(grid1d(ne, 256, 65536)), dim3(256), 0, s, ne, x, dc, dv, move, eta, xmin, st,
+                     xnew, lam_out);
+}
+
+}  // namespace msmg

@@ -64,6 +64,7 @@ class Solver:
                     "msmg_create")
         self._h = h
         self._keep = []
+        self.version = 0  # bumped by every set-up (autograd checks it)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -88,6 +89,7 @@ class Solver:
         L.check(L.lib().msmg_setup(self._h, _ptr(rho), _DT[rho.dtype], float(kmin), float(kmax), int(p), _ptr(mask),
                                    _ptr(fv) if fv is not None else None, _stream()), "msmg_setup")
         self.kmin, self.kmax, self.p = float(kmin), float(kmax), int(p)
+        self.version += 1
         return self
 
     # -- solves and products --------------------------------------------------
@@ -109,6 +111,36 @@ class Solver:
         out = SolveInfo({k: getattr(info, k) for k, _ in L.Info._fields_})
         out["code"] = code
         return T, out
+
+    def solve_adjoint(self, g, lam=None, rtol=1e-8, maxit=1000, use_x0=False, lam_lo=None):
+        """Adjoint solve A_FF u_F = g_F with zero fixed entries (section 2.3)."""
+        g = _need(g, "g", torch.float64, self.nnodes, self.device)
+        if lam is None:
+            lam = torch.empty_like(g)
+            use_x0 = False
+        else:
+            _need(lam, "lam", torch.float64, self.nnodes, self.device)
+        if lam_lo is not None:
+            _need(lam_lo, "lam_lo", torch.float64, self.nnodes, self.device)
+        info = L.Info()
+        code = L.check(L.lib().msmg_solve_adjoint(self._h, _ptr(g), _ptr(lam),
+                                                  _ptr(lam_lo) if lam_lo is not None else None, int(bool(use_x0)),
+                                                  float(rtol), int(maxit), ctypes.byref(info), _stream()),
+                       "msmg_solve_adjoint")
+        out = SolveInfo({k: getattr(info, k) for k, _ in L.Info._fields_})
+        out["code"] = code
+        return lam, out
+
+    def oc_update(self, x, dc, dv, volume_fraction, move=0.2, eta=0.5, x_min=1e-3, out=None):
+        """Optimality-criteria update with the volume multiplier found on the GPU;
+        returns (x_new, lambda) with lambda a 0-d device tensor."""
+        for t, nm in ((x, "x"), (dc, "dc"), (dv, "dv")):
+            _need(t, nm, torch.float64, self.nelem, self.device)
+        out = torch.empty_like(x) if out is None else _need(out, "out", torch.float64, self.nelem, self.device)
+        lam = torch.empty((), dtype=torch.float64, device=self.device)
+        L.check(L.lib().msmg_oc_update(self._h, _ptr(x), _ptr(dc), _ptr(dv), float(volume_fraction), float(move),
+                                       float(eta), float(x_min), _ptr(out), _ptr(lam), _stream()), "msmg_oc_update")
+        return out, lam
 
     def apply(self, x, y=None):
         x = _need(x, "x", torch.float64, self.nnodes, self.device)
@@ -147,6 +179,16 @@ class Solver:
 
     def plan(self):
         return L.query_plan(self.nx, self.ny, self.nz, self.opts)
+
+
+def density_filter(x, n, radius=1.5, transpose=False, out=None):
+    """Hat-weight density filter on an (nx,ny,nz) element mesh (or its adjoint)."""
+    nx, ny, nz = n
+    _need(x, "x", torch.float64, nx * ny * nz, x.device)
+    out = torch.empty_like(x) if out is None else out
+    L.check(L.lib().msmg_density_filter(nx, ny, nz, float(radius), _ptr(x), _ptr(out), int(bool(transpose)),
+                                        _stream()), "msmg_density_filter")
+    return out
 
 
 def prolong_nodal(Tc, n):

@@ -112,6 +112,104 @@ PATHS = {
 }
 
 
+def run_workload(name, args):
+    """Companion workloads (one JSON line each): the 128^3 FP64 runs, the 256^3
+    contrast sweep, the 512^3 optimisation loop."""
+    import torch
+
+    import paper_2410_06850_amd as pkg
+
+    dev = torch.device("cuda", 0)
+    tune = os.path.join(ROOT, "gpurun_out", "tune_cache.txt")
+    out = {"workload": name, "runs": []}
+
+    def solve_case(n, rho_np, kmin, opts, rtol=RTOL, seed=None, tag=""):
+        mask_np = synth.dirichlet_patch_mask(n, n, n).ravel()
+        free = int((n + 1) ** 3 - int(mask_np.sum()))
+        s = pkg.Solver(n, tune_cache=tune, **opts)
+        rho = torch.tensor(rho_np, device=dev)
+        mask = torch.tensor(mask_np, device=dev)
+        f = s.element_load(const=1.0)
+        rec = {}
+        for rep in range(2):  # the second repetition is reported (first one tunes and warms up)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.setup(rho, kmin, 1.0, 3, mask)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            T, info = s.solve(f, rtol=rtol, maxit=2000)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            rec = dict(tag=tag, n=n, seed=seed, k_min=kmin, iterations=info.iterations, code=info.code,
+                       rel_res=info.rel_res, setup_ms=1e3 * (t1 - t0), solve_ms=1e3 * (t2 - t1),
+                       dofs_per_s=free / (t2 - t1))
+        _log(json.dumps(rec))
+        del s
+        torch.cuda.empty_cache()
+        return rec
+
+    mixed, fp64 = PATHS["mixed"], PATHS["fp64"]
+    if name == "cube128_grf8_c1e6":
+        for seed in (0, 1, 2):
+            rho = synth.grf_rho(128, 8, seed=seed).ravel()
+            out["runs"].append(solve_case(128, rho, 1e-6, fp64, seed=seed, tag="fp64"))
+            out["runs"].append(solve_case(128, rho, 1e-6, mixed, seed=seed, tag="mixed"))
+    elif name == "cube256_grf16_contrast_sweep":
+        rho = synth.grf_rho(256, 16, seed=0).ravel()
+        for kmin in (1e-2, 1e-4, 1e-6):
+            out["runs"].append(solve_case(256, rho, kmin, fp64, tag="fp64"))
+            out["runs"].append(solve_case(256, rho, kmin, mixed, tag="mixed"))
+    elif name == "cube512_topopt":
+        n = 512
+        s = pkg.Solver(n, tune_cache=tune, **mixed)
+        mask = torch.tensor(synth.dirichlet_patch_mask(n, n, n).ravel(), device=dev)
+        t0 = time.perf_counter()
+        _, hist = pkg.topopt.optimize(s, mask, iterations=args.iterations, volume_fraction=0.3, x0=0.3,
+                                      radius=1.5, kmin=1e-6, log=lambda r: _log(json.dumps(r)))
+        out["total_s"] = time.perf_counter() - t0
+        out["runs"] = hist
+        out["config"] = dict(n=n, iterations=args.iterations, volume_fraction=0.3, radius=1.5, move=0.2, eta=0.5,
+                             k_min=1e-6, precision="mixed")
+    elif name == "cube512_grf32_warmstart":
+        # the interpolation step: solve the 256^3 companion (2^3 block average of
+        # the same unthresholded field, thresholded at its own 60th percentile),
+        # prolong T to 512^3 (trilinear) and start the 512^3 solve from it
+        w = synth.grf_raw(512, 32, seed=0)
+        rho_f = synth.threshold_field(w).ravel()
+        rho_c = synth.threshold_field(synth.block_average(w)).ravel()
+        del w
+        res = {}
+        for n, rho_np in ((256, rho_c), (512, rho_f)):
+            mask_np = synth.dirichlet_patch_mask(n, n, n).ravel()
+            s = pkg.Solver(n, tune_cache=tune, **mixed)
+            s.setup(torch.tensor(rho_np, device=dev), 1e-6, 1.0, 3, torch.tensor(mask_np, device=dev))
+            f = s.element_load(const=1.0)
+            if n == 256:
+                T, info = s.solve(f, rtol=RTOL, maxit=2000)
+                res["coarse"] = dict(n=n, iterations=info.iterations, solve_ms=info.solve_ms)
+                x0 = pkg.prolong_nodal(T, (n, n, n))
+                del T
+            else:
+                T, cold = s.solve(f, rtol=RTOL, maxit=2000)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                T, warm = s.solve(f, x0, rtol=RTOL, maxit=2000, use_x0=True)
+                torch.cuda.synchronize()
+                tw = time.perf_counter() - t0
+                res["fine_cold"] = dict(n=n, iterations=cold.iterations, solve_ms=cold.solve_ms, code=cold.code,
+                                        rel_res=cold.rel_res)
+                res["fine_warm"] = dict(n=n, iterations=warm.iterations, solve_ms=1e3 * tw, code=warm.code,
+                                        rel_res=warm.rel_res)
+                res["setup_ms"] = cold.setup_ms
+            _log(json.dumps(res))
+            del s
+            torch.cuda.empty_cache()
+        out["runs"] = [res]
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,11 +221,18 @@ def main():
     ap.add_argument("--no-f32", action="store_true", help="skip the FP32-cycle comparison path")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (reference for the HBM counters)")
+    ap.add_argument("--workload", default=None,
+                    help="run a companion workload instead of the benchmark: cube128_grf8_c1e6, "
+                         "cube256_grf16_contrast_sweep, cube512_topopt, cube512_grf32_warmstart")
+    ap.add_argument("--iterations", type=int, default=20, help="optimisation iterations (cube512_topopt)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver has no multi-GPU path (sharding is described in the design "
               "notes); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.workload:
+        run_workload(args.workload, args)
+        return
 
     import torch
 
@@ -200,7 +305,7 @@ def main():
     # with HIP events on the solve stream inside the timed steps
     apply_ms = float(np.mean([r["info"]["apply_ms"] for r in mix]))
     nn, ne = (n + 1) ** 3, n ** 3
-    apply_bytes = 16 * nn + 8 * ne + nn / 8  # x read, y write, k read, mask bits
+    apply_bytes = 16 * nn + 8 * ne + nn / 8  # p read, q written, k read, mask bits
     achieved = apply_bytes / (apply_ms * 1e-3) / 1e9
     traffic = measured_traffic() if n == N else None
 
@@ -248,7 +353,7 @@ def main():
         "precond_us": 1e3 * float(np.mean([r["info"]["precond_ms"] for r in mix])),
         "paths": others,
         "roofline": {
-            "kernel": "k_apply (PCG operator apply, FP64, difference form)",
+            "kernel": "k_apply (PCG operator apply q = A p, FP64, difference form)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

@@ -170,7 +170,8 @@ void launch_gs_sweep(const Ctx& c, const void* b, void* x, bool forward, hipStre
     const long long nthreads = ncol * LP * ROW_SLOTS;
     const dim3 gr((unsigned)((nthreads + 255) / 256)), bl(256);
 #define GS(VT, AT) hipLaunchKernelGGL((k_gs_colour<VT, AT>), gr, bl, 0, s, h, colour, forward ? 1 : 0, LP, (const AT*)c.cc.Ac, (const AT*)c.cc.AcDinv, (const VT*)b, (VT*)x, c.sc)
-    GS(double, double);
+    if (c.cc.a_dt == DT_F64) GS(double, double);
+    else GS(double, float);
 #undef GS
   }
 }
@@ -180,7 +181,8 @@ void launch_ac_residual(const Ctx& c, const void* b, const void* x, void* t, hip
   const long long n = (long long)c.h.ncells * LP * ROW_SLOTS;
   const dim3 gr((unsigned)((n + 255) / 256)), bl(256);
 #define AR(VT, AT) hipLaunchKernelGGL((k_ac_residual<VT, AT>), gr, bl, 0, s, c.h, LP, (const AT*)c.cc.Ac, (const VT*)b, (const VT*)x, (VT*)t, c.sc)
-  AR(double, double);
+  if (c.cc.a_dt == DT_F64) AR(double, double);
+  else AR(double, float);
 #undef AR
 }
 

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/msmg.h"
@@ -413,7 +414,9 @@ extern "C" int msmg_create(msmg_handle** out, int nx, int ny, int nz, double lx,
   h->v_dt = o.vcycle_dtype;
   h->kv_dt = o.rho_v_dtype;
   h->b_dt = o.basis_dtype;
-  h->a_dt = DT_F64;  // level 1 and 2 stay FP64 on every path (see the mixed-precision notes)
+  // level-1 operator and level 2 stay FP64 on every path: an FP32 copy of A_c
+  // costs ~10% more iterations at contrast 1e6
+  h->a_dt = DT_F64;
   const long long nn = h->g.nn, ne = h->g.ne;
   const size_t vs = dt_size(h->v_dt);
   int rc = MSMG_OK;

@@ -939,6 +939,7 @@ int run_cc_eigen(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, const doub
 }
 
 int build_acc(const Ctx& c, const SetupArgs& sa, double* u, hipStream_t s) {
+  // A_cc = R_cc A_c R_cc^T from the FP64 masters (the cycle may hold an FP32 copy of A_c)
   const Hier& h = c.h;
   const int n = sa.n_cc;
   if (hipMemsetAsync(sa.Acc, 0, sizeof(double) * (size_t)n * n, s) != hipSuccess) return MSMG_EHIP;
@@ -950,7 +951,7 @@ int build_acc(const Ctx& c, const SetupArgs& sa, double* u, hipStream_t s) {
     const int qx = q % 3, qy = (q / 3) % 3, qz = q / 9;
     if (qx >= h.nccx || qy >= h.nccy || qz >= h.nccz) continue;
     for (int b = 0; b < h.Lcc; ++b) {
-      hipLaunchKernelGGL((k_acc_apply<double, double>), gu, bu, 0, s, h, (const double*)sa.Acv, (const double*)sa.Rccv, sa.cc_ptr, sa.dof_cc, sa.dof_loc, qx, qy, qz, b, u);
+      hipLaunchKernelGGL((k_acc_apply<double, double>), gu, bu, 0, s, h, (const double*)sa.Ac64, (const double*)sa.Rccv, sa.cc_ptr, sa.dof_cc, sa.dof_loc, qx, qy, qz, b, u);
       hipLaunchKernelGGL((k_acc_dot<double>), gd, bd, 0, s, h, (const double*)sa.Rccv, sa.cc_ptr, sa.cc_dofs, u, qx, qy, qz, b, n, sa.Acc);
     }
   }

@@ -201,3 +201,26 @@ def test_deterministic(pkg):
     T1, _ = s.solve(f, rtol=1e-10)
     T2, _ = s.solve(f, rtol=1e-10)
     assert torch.equal(T1, T2)
+
+
+@pytest.mark.parametrize("mode", ["fp64", "bf16-coefficients"])
+def test_certificate_cube128_grf8_c1e6(pkg, mode):
+    """P2 at 128^3 (GRF ell 8, contrast 1e6, H 8, sd 8): the oracle's own residual
+    of the GPU solution T + T_lo is <= rtol (1 + 1e-3)."""
+    print(f"case certificate cube128_grf8_c1e6 {mode}", flush=True)
+    n = 128
+    rho = field(n, "grf", 0, ell=8)
+    mask = patch_mask(n)
+    g = q1.Grid(n)
+    opts = {} if mode == "fp64" else MIXED[mode][0]
+    s = pkg.Solver(n, H=8, sd=8, **opts)
+    s.setup(to_dev(rho), 1e-6, KMAX, P, to_dev(mask, torch.uint8))
+    f = q1.element_load(g, 1.0)
+    Tlo = torch.empty(g.nnodes, dtype=torch.float64, device="cuda")
+    T, info = s.solve(to_dev(f), rtol=1e-8, maxit=1000, T_lo=Tlo)
+    print(f"  iterations {info.iterations} rel_res {info.rel_res:.3e}", flush=True)
+    assert info.code == 0
+    A = q1.assemble(g, q1.conductivity(rho, 1e-6, KMAX, P))
+    cert = q1.relative_residual_diff(A, T.cpu().numpy(), f, mask, T_lo=Tlo.cpu().numpy())
+    print(f"  oracle residual {cert:.3e}")
+    assert cert <= 1e-8 * (1 + 1e-3)

@@ -161,7 +161,7 @@ def run_workload(name, args):
             out["runs"].append(solve_case(256, rho, kmin, mixed, tag="mixed"))
     elif name == "cube512_topopt":
         n = 512
-        s = pkg.Solver(n, tune_cache=tune, **mixed)
+        s = pkg.Solver(n, tune_cache=tune, eig_warm_start=1, **mixed)
         mask = torch.tensor(synth.dirichlet_patch_mask(n, n, n).ravel(), device=dev)
         t0 = time.perf_counter()
         _, hist = pkg.topopt.optimize(s, mask, iterations=args.iterations, volume_fraction=0.3, x0=0.3,
@@ -169,7 +169,7 @@ def run_workload(name, args):
         out["total_s"] = time.perf_counter() - t0
         out["runs"] = hist
         out["config"] = dict(n=n, iterations=args.iterations, volume_fraction=0.3, radius=1.5, move=0.2, eta=0.5,
-                             k_min=1e-6, precision="mixed")
+                             k_min=1e-6, precision="mixed", eig_warm_start=1)
     elif name == "cube512_grf32_warmstart":
         # the interpolation step: solve the 256^3 companion (2^3 block average of
         # the same unthresholded field, thresholded at its own 60th percentile),

@@ -80,6 +80,9 @@ typedef struct msmg_options {
   const char* tune_cache; /* host path of the tuning cache file, or NULL       [NULL] */
   int timing;          /* 1: time the operator apply and the preconditioner of  [0]
                           every PCG iteration with HIP events on the solve stream */
+  int eig_warm_start;  /* 1: start the level-1 eigensolver of a set-up from the  [0]
+                          previous set-up's basis (designs that change little
+                          between set-ups, e.g. an optimisation loop)            */
 } msmg_options;
 
 /* Solve report. */

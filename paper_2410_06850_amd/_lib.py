@@ -44,6 +44,7 @@ class Options(ctypes.Structure):
         ("autotune", ctypes.c_int),
         ("tune_cache", ctypes.c_char_p),
         ("timing", ctypes.c_int),
+        ("eig_warm_start", ctypes.c_int),
     ]
 
 

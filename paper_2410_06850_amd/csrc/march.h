@@ -1,6 +1,6 @@
 // 2.5D plane march for the fine-level stencil kernels.
 //
-// A workgroup of MX x MY threads (32 x 8) owns an MX x MY column of nodes and
+// A workgroup of MX x MY threads (64 x 4) owns an MX x MY column of nodes and
 // marches over a chunk of z planes.  Each step stages one node plane (with a
 // 1-node halo, (MX+2) x (MY+2) values) and one element layer ((MX+1) x (MY+1)
 // conductivities) in LDS through coalesced loads.  The operator is split
@@ -28,10 +28,10 @@
 namespace msmg {
 
 #ifndef MSMG_MARCH_MX
-#define MSMG_MARCH_MX 32
+#define MSMG_MARCH_MX 64
 #endif
 #ifndef MSMG_MARCH_MY
-#define MSMG_MARCH_MY 8
+#define MSMG_MARCH_MY 4
 #endif
 #ifndef MSMG_MARCH_WAVES
 #define MSMG_MARCH_WAVES 1

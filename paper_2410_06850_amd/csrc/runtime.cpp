@@ -93,6 +93,7 @@ struct msmg_handle {
   unsigned* counter = nullptr;
   int red_blocks = 4096;
   long long march_resident = 2048;  // marching workgroups resident at once (queried at create)
+  bool has_basis = false;           // Rc64 holds the basis of the last completed set-up
   long long partial_slots = 0;
   void* oc_state = nullptr;  // bracket of the OC multiplier
 
@@ -338,6 +339,7 @@ extern "C" void msmg_default_options(msmg_options* o) {
   o->autotune = 1;
   o->tune_cache = nullptr;
   o->timing = 0;
+  o->eig_warm_start = 0;
 }
 
 extern "C" const char* msmg_last_error(void) { return g_last_error.c_str(); }
@@ -591,6 +593,8 @@ extern "C" int msmg_setup(msmg_handle* h, const void* rho, msmg_dtype rho_dtype,
     a.dof_cc = h->dof_cc;
     a.dof_loc = h->dof_loc;
     a.opt = &h->opt;
+    a.warm = (h->opt.eig_warm_start && h->has_basis) ? 1 : 0;
+    h->has_basis = false;
     a.tune = &h->tune;
     SetupReport rep{};
     const int r = run_setup(c, a, &h->scratch, &rep, s);
@@ -603,6 +607,7 @@ extern "C" int msmg_setup(msmg_handle* h, const void* rho, msmg_dtype rho_dtype,
   HIP_TRY(hipGetLastError());
   h->setup_ms = now_ms() - t0;
   h->setup_done = true;
+  h->has_basis = (h->mg != 0);
   return MSMG_OK;
 }
 

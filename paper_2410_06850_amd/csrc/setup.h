@@ -62,6 +62,7 @@ struct SetupArgs {
   const int* dof_cc;
   const int* dof_loc;
   const msmg_options* opt;
+  int warm;  // level-1 solver starts from the basis left in Rc64 by the previous set-up
   TuneChoice* tune;
 };
 

@@ -35,6 +35,7 @@ struct LocalArgs {
   int maxit;
   double tol;
   int nl_max;   // LDS capacity in nodes
+  int warm;     // start from the basis in Rc64 (previous set-up)
   double* Rc64;
   double* evals;
   int* status;
@@ -322,6 +323,12 @@ __global__ __launch_bounds__(BS) void k_local_eigen(LocalArgs A) {
             const double v = cos(M_PI * a * lx / double(max(nlx - 1, 1))) * cos(M_PI * b * ly / double(max(nly - 1, 1))) *
                              cos(M_PI * c * lz / double(max(nlz - 1, 1)));
             Y[q][j] = sm * (v + 1e-2 * hash01(unsigned(ln * 131 + j * 7919 + 17)));
+            if (A.warm && j < h.Lc) {
+              // previous basis in standard form (Phi sqrt(m)), cosines kept as a small
+              // admixture so that empty columns still span a direction
+              const long long gn = node_id(g, x0 + lx, y0 + ly, z0 + lz);
+              Y[q][j] = A.Rc64[gn * h.Lc + j] * sm + 1e-3 * Y[q][j];
+            }
           }
         } else {
 #pragma unroll
@@ -496,6 +503,7 @@ int launch_local_eigen(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, int 
   a.maxit = sa.opt->eig_maxit;
   a.tol = sa.opt->eig_tol;
   a.nl_max = sa.max_cell_nodes;
+  a.warm = sa.warm;
   a.Rc64 = sa.Rc64;
   a.evals = sa.evals;
   a.status = sa.cell_status;

@@ -224,3 +224,34 @@ def test_certificate_cube128_grf8_c1e6(pkg, mode):
     cert = q1.relative_residual_diff(A, T.cpu().numpy(), f, mask, T_lo=Tlo.cpu().numpy())
     print(f"  oracle residual {cert:.3e}")
     assert cert <= 1e-8 * (1 + 1e-3)
+
+
+def test_warm_started_setup_matches_cold(pkg):
+    """A set-up started from the previous design's basis converges to the same
+    local spectra and preconditioner as a cold one."""
+    name = "cube16_grf_c1e6_H4"
+    print(f"case warm-start {name}", flush=True)
+    n, kind, seed, kmin, H, sd = CASES[name]
+    rho1 = field(n, kind, seed)
+    rho2 = np.where(np.random.default_rng(11).random(rho1.size) < 0.05, 1.0 - rho1 + 1e-3, rho1)
+    mask = to_dev(patch_mask(n), torch.uint8)
+    warm = pkg.Solver(n, H=H, sd=sd, eig_warm_start=1)
+    warm.setup(to_dev(rho1), kmin, KMAX, P, mask)
+    warm.setup(to_dev(rho2), kmin, KMAX, P, mask)
+    cold = pkg.Solver(n, H=H, sd=sd)
+    cold.setup(to_dev(rho2), kmin, KMAX, P, mask)
+    g, h = oracle_hier(n, rho2, kmin, patch_mask(n), H, sd)
+    Lc = 4
+    ev_w = warm.export(0, (n // H) ** 3 * Lc).numpy()
+    ev_c = cold.export(0, (n // H) ** 3 * Lc).numpy()
+    assert np.abs(ev_w - ev_c).max() <= 1e-9 * max(np.abs(ev_c).max(), 1.0)
+    r = np.random.default_rng(12).standard_normal(g.nnodes)
+    zw = warm.precondition(to_dev(r)).cpu().numpy()
+    zc = cold.precondition(to_dev(r)).cpu().numpy()
+    bound = max(1e-10, 100 * _predicted_subspace_error(g, h))
+    print(f"  warm/cold preconditioner rel={rel(zw, zc):.3e} bound={bound:.3e}")
+    assert rel(zw, zc) <= bound
+    f = to_dev(q1.element_load(g, 1.0))
+    _, iw = warm.solve(f, rtol=1e-8)
+    _, ic = cold.solve(f, rtol=1e-8)
+    assert iw.code == 0 and abs(iw.iterations - ic.iterations) <= 1

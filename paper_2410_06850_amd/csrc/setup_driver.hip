@@ -113,8 +113,10 @@ static int count_unconverged(const SetupArgs& sa, int ncells, int* unconv, int* 
 // and keep the fastest one whose cells all converge.
 static int tune_local(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, int cus, hipStream_t s, TuneChoice* best) {
   struct Cand { int bs, m, degree, bpc; };
-  std::vector<Cand> cands = {{256, 8, 8, 2}, {256, 8, 12, 2}, {256, 8, 20, 2}, {512, 8, 12, 1},
-                             {512, 8, 12, 2}, {256, 8, 12, 4}};
+  // both subspace blocks sit in LDS (about 94 KB for the 9^3-node cells of
+  // H = 8), so one workgroup per CU; the shapes differ in threads per cell
+  std::vector<Cand> cands = {{256, 8, 12, 1}, {512, 8, 12, 1}, {768, 8, 8, 1}, {768, 8, 12, 1},
+                             {768, 8, 20, 1}, {1024, 8, 12, 1}};
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MSMG_EHIP;
   best->valid = 0;
@@ -160,10 +162,10 @@ int run_setup(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, SetupReport* 
   int r;
   if (o.eig_block > 0 || o.eig_degree > 0 || !o.autotune) {
     tc.valid = 1;
-    tc.bs = 256;
+    tc.bs = sa.max_cell_nodes <= 256 ? 256 : 768;
+    tc.blocks_per_cu = 1;
     tc.m = o.eig_block > 0 ? o.eig_block : 8;
     tc.degree = o.eig_degree > 0 ? o.eig_degree : 12;
-    tc.blocks_per_cu = 2;
   } else if (!tc.valid) {
     const std::string key = tune_key(c, sa.max_cell_nodes);
     if (!cache_lookup(o.tune_cache, key, &tc)) {

@@ -9,10 +9,12 @@
 //
 // Solver: Chebyshev-filtered subspace iteration (Zhou & Saad, 2007) on the
 // standard form B = M^-1/2 K M^-1/2, whose spectrum lies in [0, 8 lmax(K0)/V]
-// for any conductivities.  Each workgroup owns one cell at a time (work queue),
-// keeps the cell's conductivities, mass and one block of vectors in LDS and
-// the subspace blocks in registers; Rayleigh-Ritz and orthonormalisation use
-// a parallel Jacobi eigensolver on the small projected matrices.  Cells with
+// for any conductivities.  Each workgroup owns one cell at a time (work queue)
+// and keeps the cell's conductivities, mass and two blocks of vectors in LDS;
+// the filter recurrence, the Gram matrices and the block rotations work node
+// by node on those buffers, so registers only hold per-node temporaries.
+// Rayleigh-Ritz and orthonormalisation use a parallel Jacobi eigensolver on
+// the small projected matrices.  Cells with
 // at most 16 free nodes are solved densely.
 #include "eig_common.h"
 #include "setup.h"
@@ -20,7 +22,7 @@
 namespace msmg {
 
 constexpr int DENSE_MAX = 16;
-constexpr int RED_SLOTS = 640;  // block reductions of up to 136 values over 4 waves
+constexpr int RED_SLOTS = 640;  // block reductions of up to 40 values over 16 waves
 
 struct LocalArgs {
   Geo g;
@@ -63,12 +65,15 @@ MSMG_DEV double hash01(unsigned x) {
   return double(x) * (1.0 / 4294967296.0) - 0.5;
 }
 
-template <int M, int BS, int NPT>
+template <int M, int BS>
 __global__ __launch_bounds__(BS) void k_local_eigen(LocalArgs A) {
   extern __shared__ double lds[];
   const int NL = A.nl_max;
-  double* V = lds;                  // M * NL : M^-1/2-scaled block for neighbour access
-  double* kl = V + M * NL;          // NL : conductivities of internal elements
+  // Both subspace blocks live in LDS (node-contiguous per vector); registers
+  // only hold per-node temporaries, so the kernel runs without spilling.
+  double* blk0 = lds;               // M * NL : block buffer
+  double* blk1 = blk0 + M * NL;     // M * NL : block buffer
+  double* kl = blk1 + M * NL;       // NL : conductivities of internal elements
   double* isq = kl + NL;            // NL : 1/sqrt(m) on free nodes, 0 on fixed
   double* Gm = isq + NL;            // small matrices (16*16 each)
   double* Vm = Gm + 256;
@@ -83,10 +88,15 @@ __global__ __launch_bounds__(BS) void k_local_eigen(LocalArgs A) {
   __shared__ int s_cell;
 
   const int tid = threadIdx.x;
+  const int wid = tid >> 6, lane = tid & 63;
+  constexpr int NW = BS / 64;
   const Geo& g = A.g;
   const Hier& h = A.h;
   const double b_hi = A.lam_bound * 1.0001;
   const double dk = A.mat.kmax - A.mat.kmin;
+  const double pat_ax[3] = {A.st.ax[0], A.st.ax[1], A.st.ax[2]};
+  const double pat_fd[3] = {A.st.fd[0], A.st.fd[1], A.st.fd[2]};
+  const double pat_bd = A.st.bd;
 
   while (true) {
     if (tid == 0) s_cell = int(atomicAdd(A.work, 1u));
@@ -133,16 +143,129 @@ __global__ __launch_bounds__(BS) void k_local_eigen(LocalArgs A) {
     const int nfree = int(nfree_d + 0.5);
     const int L = min(h.Lc, nfree);
 
-    double X[NPT][M];  // Ritz block (standard form), rows = own nodes
-#pragma unroll
-    for (int q = 0; q < NPT; ++q)
-#pragma unroll
-      for (int j = 0; j < M; ++j) X[q][j] = 0.0;
+    // X = the block holding the Ritz vectors at the end (standard form)
+    double* X = blk0;
+    double* Y = blk1;
     int status = 0;
     bool tie = false;
 
+    // (B v)_n for all M vectors of block P at local node ln (standard form:
+    // B = M^-1/2 K M^-1/2, K in difference form with per-offset weights)
+    auto apply_node = [&](const double* P, int ln, double* out) {
+      const int lx = ln % nlx, ly = (ln / nlx) % nly, lz = ln / (nlx * nly);
+      double kk[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int ex = lx - 1 + (c & 1), ey = ly - 1 + ((c >> 1) & 1), ez = lz - 1 + ((c >> 2) & 1);
+        kk[c] = (ex >= 0 && ex < nex && ey >= 0 && ey < ney && ez >= 0 && ez < nez) ? kl[(ez * ney + ey) * nex + ex] : 0.0;
+      }
+      const double s0 = isq[ln];
+      double v0[M];
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        v0[j] = s0 * P[j * NL + ln];
+        out[j] = 0.0;
+      }
+#pragma unroll
+      for (int o = 0; o < 27; ++o) {
+        if (o == 13) continue;
+        const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
+        const int nd = (ox != 0) + (oy != 0) + (oz != 0);
+        double pat;
+        if (nd == 3) pat = pat_bd;
+        else if (nd == 1) pat = pat_ax[ox != 0 ? 0 : (oy != 0 ? 1 : 2)];
+        else pat = pat_fd[ox == 0 ? 0 : (oy == 0 ? 1 : 2)];
+        if (nd == 1 && pat == 0.0) continue;  // axis neighbours vanish on cubes
+        double ks = 0.0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          const int ccx = c & 1, ccy = (c >> 1) & 1, ccz = (c >> 2) & 1;
+          const bool okx = (ox == 0) || (ox > 0 && ccx == 1) || (ox < 0 && ccx == 0);
+          const bool oky = (oy == 0) || (oy > 0 && ccy == 1) || (oy < 0 && ccy == 0);
+          const bool okz = (oz == 0) || (oz > 0 && ccz == 1) || (oz < 0 && ccz == 0);
+          if (okx && oky && okz) ks += kk[c];
+        }
+        const int nx_ = lx + ox, ny_ = ly + oy, nz_ = lz + oz;
+        if (nx_ < 0 || nx_ >= nlx || ny_ < 0 || ny_ >= nly || nz_ < 0 || nz_ >= nlz) continue;
+        const int nb = ln + (oz * nly + oy) * nlx + ox;
+        const double wo = pat * ks, sb = isq[nb];
+#pragma unroll
+        for (int j = 0; j < M; ++j) out[j] += wo * (sb * P[j * NL + nb] - v0[j]);
+      }
+#pragma unroll
+      for (int j = 0; j < M; ++j) out[j] *= s0;
+    };
+    // Gram matrix P^T Q into Gm: each wave forms whole dot products (fixed order)
+    auto gram = [&](const double* P, const double* Q) {
+      constexpr int NV = M * (M + 1) / 2;
+      for (int k = wid; k < NV; k += NW) {
+        int i = 0, r = k;
+        while (r >= M - i) {
+          r -= M - i;
+          ++i;
+        }
+        const int j = i + r;
+        double acc = 0.0;
+        for (int n = lane; n < nloc; n += 64) acc += P[i * NL + n] * Q[j * NL + n];
+        acc = wave_sum(acc);
+        if (lane == 0) {
+          Gm[i * M + j] = acc;
+          Gm[j * M + i] = acc;
+        }
+      }
+      __syncthreads();
+    };
+    // P <- P C (C is M x M in LDS), node by node in place
+    auto transform = [&](double* P, const double* C) {
+      for (int ln = tid; ln < nloc; ln += BS) {
+        // keeps the M x M coefficients in LDS instead of hoisting them into registers
+        asm volatile("" ::: "memory");
+        double t[M], u[M];
+#pragma unroll
+        for (int i = 0; i < M; ++i) t[i] = P[i * NL + ln];
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+          double a = 0.0;
+#pragma unroll
+          for (int i = 0; i < M; ++i) a += t[i] * C[i * M + j];
+          u[j] = a;
+        }
+#pragma unroll
+        for (int j = 0; j < M; ++j) P[j * NL + ln] = u[j];
+      }
+      __syncthreads();
+    };
+    // orthonormalise a block: G = P^T P = U S U^T, P <- P U S^-1/2
+    auto orthonormalise = [&](double* P) {
+      gram(P, P);
+      block_jacobi(Gm, Vm, Bm, Vs, ev, perm, M, red);
+      for (int e = tid; e < M * M; e += BS) {
+        const int k = e % M;
+        const double sv = ev[k];
+        Bm[e] = (sv > 1e-300) ? Vs[e] / sqrt(sv) : 0.0;
+      }
+      __syncthreads();
+      transform(P, Bm);
+    };
+    // Rayleigh-Ritz on an orthonormal block P: Q = B P, then both rotated by
+    // the eigenvectors of P^T Q; ev = Ritz values
+    auto rayleigh_ritz = [&](double* P, double* Q) {
+      for (int ln = tid; ln < nloc; ln += BS) {
+        double z[M];
+        apply_node(P, ln, z);
+#pragma unroll
+        for (int j = 0; j < M; ++j) Q[j * NL + ln] = z[j];
+      }
+      __syncthreads();
+      gram(P, Q);
+      block_jacobi(Gm, Vm, Bm, Vs, ev, perm, M, red);
+      transform(P, Vs);
+      transform(Q, Vs);
+    };
+
     if (nfree == 0) {
-      // nothing to solve: zero basis
+      for (int e = tid; e < M * NL; e += BS) X[e] = 0.0;
+      __syncthreads();
     } else if (nfree <= DENSE_MAX) {
       // ---- dense path: assemble B on the free nodes and diagonalise it
       if (tid == 0) {
@@ -178,166 +301,50 @@ __global__ __launch_bounds__(BS) void k_local_eigen(LocalArgs A) {
       }
       __syncthreads();
       block_jacobi(Gm, Vm, Bm, Vs, ev, perm, nf, red);
-#pragma unroll
-      for (int q = 0; q < NPT; ++q) {
-        const int ln = tid + q * BS;
-        if (ln < nloc && isq[ln] > 0.0) {
-          const int f = fidx[ln];
-#pragma unroll
-          for (int j = 0; j < M; ++j) X[q][j] = (j < nf) ? Vs[f * nf + j] : 0.0;
-        }
+      for (int e = tid; e < M * NL; e += BS) {
+        const int j = e / NL, ln = e % NL;
+        double v = 0.0;
+        if (ln < nloc && isq[ln] > 0.0 && j < nf) v = Vs[fidx[ln] * nf + j];
+        X[e] = v;
       }
       if (L < nf && ev[L] - ev[L - 1] < 1e-8 * b_hi) tie = true;
       __syncthreads();
     } else {
-      // ---- Chebyshev-filtered subspace iteration
-      double Y[NPT][M], Z[NPT][M];
-      // precompute this thread's stencil weights (node-local, reused for every product)
-      auto apply_B = [&](double (&in)[NPT][M], double (&out)[NPT][M]) {
+      // ---- Chebyshev-filtered subspace iteration (two LDS blocks: X, Y)
+      // start block: low-frequency cosines on the cell box, times sqrt(m), or
+      // the previous set-up's basis (warm start)
+      for (int ln = tid; ln < nloc; ln += BS) {
+        const int lx = ln % nlx, ly = (ln / nlx) % nly, lz = ln / (nlx * nly);
+        const bool fr = isq[ln] > 0.0;
+        const double sm = fr ? 1.0 / isq[ln] : 0.0;
 #pragma unroll
-        for (int q = 0; q < NPT; ++q) {
-          const int ln = tid + q * BS;
-          if (ln < nloc) {
-#pragma unroll
-            for (int j = 0; j < M; ++j) V[j * NL + ln] = isq[ln] * in[q][j];
-          }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < NPT; ++q) {
-          const int ln = tid + q * BS;
-#pragma unroll
-          for (int j = 0; j < M; ++j) out[q][j] = 0.0;
-          if (ln < nloc && isq[ln] > 0.0) {
-            const int lx = ln % nlx, ly = (ln / nlx) % nly, lz = ln / (nlx * nly);
-            double kk[8];
-#pragma unroll
-            for (int c = 0; c < 8; ++c) {
-              const int ex = lx - 1 + (c & 1), ey = ly - 1 + ((c >> 1) & 1), ez = lz - 1 + ((c >> 2) & 1);
-              kk[c] = (ex >= 0 && ex < nex && ey >= 0 && ey < ney && ez >= 0 && ez < nez) ? kl[(ez * ney + ey) * nex + ex] : 0.0;
-            }
-            double w[27];
-            stencil27(A.st, kk, w);
-            // difference form: (K v)_n = sum_{o != 0} w_o (v_{n+o} - v_n)
-            double v0[M];
-#pragma unroll
-            for (int j = 0; j < M; ++j) v0[j] = V[j * NL + ln];
-#pragma unroll
-            for (int o = 0; o < 27; ++o) {
-              if (o == 13) continue;
-              const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
-              const int nx_ = lx + ox, ny_ = ly + oy, nz_ = lz + oz;
-              const bool ok = nx_ >= 0 && nx_ < nlx && ny_ >= 0 && ny_ < nly && nz_ >= 0 && nz_ < nlz;
-              const int nb = ok ? (nz_ * nly + ny_) * nlx + nx_ : ln;
-              const double wo = ok ? w[o] : 0.0;
-#pragma unroll
-              for (int j = 0; j < M; ++j) out[q][j] += wo * (V[j * NL + nb] - v0[j]);
-            }
-            const double s = isq[ln];
-#pragma unroll
-            for (int j = 0; j < M; ++j) out[q][j] *= s;
-          }
-        }
-        __syncthreads();
-      };
-      // Gram matrix of a block into Gm (full symmetric)
-      auto gram = [&](double (&P)[NPT][M], double (&Q)[NPT][M]) {
-        constexpr int NV = M * (M + 1) / 2;
-        double s[NV];
-#pragma unroll
-        for (int k = 0; k < NV; ++k) s[k] = 0.0;
-#pragma unroll
-        for (int q = 0; q < NPT; ++q) {
-          int k = 0;
-#pragma unroll
-          for (int i = 0; i < M; ++i)
-#pragma unroll
-            for (int j = i; j < M; ++j) s[k++] += P[q][i] * Q[q][j];
-        }
-        block_allsum_vec<NV>(s, red);
-        if (tid == 0) {
-          int k = 0;
-          for (int i = 0; i < M; ++i)
-            for (int j = i; j < M; ++j) {
-              Gm[i * M + j] = s[k];
-              Gm[j * M + i] = s[k];
-              ++k;
-            }
-        }
-        __syncthreads();
-      };
-      // P <- P C with C (M x M) in LDS
-      auto transform = [&](double (&P)[NPT][M], const double* C) {
-#pragma unroll
-        for (int q = 0; q < NPT; ++q) {
-          double t[M];
-#pragma unroll
-          for (int j = 0; j < M; ++j) {
-            double a = 0.0;
-#pragma unroll
-            for (int i = 0; i < M; ++i) a += P[q][i] * C[i * M + j];
-            t[j] = a;
-          }
-#pragma unroll
-          for (int j = 0; j < M; ++j) P[q][j] = t[j];
-        }
-      };
-      // orthonormalise a block: G = P^T P = U S U^T, P <- P U S^-1/2
-      auto orthonormalise = [&](double (&P)[NPT][M]) {
-        gram(P, P);
-        block_jacobi(Gm, Vm, Bm, Vs, ev, perm, M, red);
-        for (int e = tid; e < M * M; e += BS) {
-          const int k = e % M;
-          const double sv = ev[k];
-          Bm[e] = (sv > 1e-300) ? Vs[e] / sqrt(sv) : 0.0;
-        }
-        __syncthreads();
-        transform(P, Bm);
-        __syncthreads();
-      };
-      // Rayleigh-Ritz on an orthonormal block P: X = P V, Z = (B P) V, ev = Ritz values
-      auto rayleigh_ritz = [&](double (&P)[NPT][M]) {
-        apply_B(P, Z);
-        gram(P, Z);
-        block_jacobi(Gm, Vm, Bm, Vs, ev, perm, M, red);
-        transform(P, Vs);
-        transform(Z, Vs);
-#pragma unroll
-        for (int q = 0; q < NPT; ++q)
-#pragma unroll
-          for (int j = 0; j < M; ++j) X[q][j] = P[q][j];
-        __syncthreads();
-      };
-
-      // start block: low-frequency cosines on the cell box, times sqrt(m)
-#pragma unroll
-      for (int q = 0; q < NPT; ++q) {
-        const int ln = tid + q * BS;
-        if (ln < nloc && isq[ln] > 0.0) {
-          const int lx = ln % nlx, ly = (ln / nlx) % nly, lz = ln / (nlx * nly);
-          const double sm = 1.0 / isq[ln];
-#pragma unroll
-          for (int j = 0; j < M; ++j) {
+        for (int j = 0; j < M; ++j) {
+          double y = 0.0;
+          if (fr) {
             int a, b, c;
             shell_index(j, a, b, c);
             const double v = cos(M_PI * a * lx / double(max(nlx - 1, 1))) * cos(M_PI * b * ly / double(max(nly - 1, 1))) *
                              cos(M_PI * c * lz / double(max(nlz - 1, 1)));
-            Y[q][j] = sm * (v + 1e-2 * hash01(unsigned(ln * 131 + j * 7919 + 17)));
+            y = sm * (v + 1e-2 * hash01(unsigned(ln * 131 + j * 7919 + 17)));
             if (A.warm && j < h.Lc) {
               // previous basis in standard form (Phi sqrt(m)), cosines kept as a small
               // admixture so that empty columns still span a direction
               const long long gn = node_id(g, x0 + lx, y0 + ly, z0 + lz);
-              Y[q][j] = A.Rc64[gn * h.Lc + j] * sm + 1e-3 * Y[q][j];
+              y = A.Rc64[gn * h.Lc + j] * sm + 1e-3 * y;
             }
           }
-        } else {
-#pragma unroll
-          for (int j = 0; j < M; ++j) Y[q][j] = 0.0;
+          Y[j * NL + ln] = y;
         }
       }
+      __syncthreads();
       orthonormalise(Y);
       orthonormalise(Y);
-      rayleigh_ritz(Y);
+      rayleigh_ritz(Y, X);  // Ritz vectors in Y, B Y in X
+      {
+        double* t = X;
+        X = Y;
+        Y = t;  // X: Ritz vectors, Y: B X
+      }
       double a_lo = ev[M - 1], a_min = ev[0];
       int it = 0;
       bool conv = false;
@@ -346,13 +353,13 @@ __global__ __launch_bounds__(BS) void k_local_eigen(LocalArgs A) {
         double rs[M];
 #pragma unroll
         for (int j = 0; j < M; ++j) rs[j] = 0.0;
-#pragma unroll
-        for (int q = 0; q < NPT; ++q)
+        for (int ln = tid; ln < nloc; ln += BS) {
 #pragma unroll
           for (int j = 0; j < M; ++j) {
-            const double r = Z[q][j] - ev[j] * X[q][j];
+            const double r = Y[j * NL + ln] - ev[j] * X[j * NL + ln];
             rs[j] += r * r;
           }
+        }
         block_allsum_vec<M>(rs, red);
         double worst = 0.0;
         for (int j = 0; j < L; ++j) worst = fmax(worst, rs[j]);
@@ -377,27 +384,37 @@ __global__ __launch_bounds__(BS) void k_local_eigen(LocalArgs A) {
         }
         double sigma = e / (amin - cc);
         const double tau = 2.0 / sigma;
-        // Y <- (B X - c X) sigma / e   (X holds the Ritz block, Z = B X)
+        // Y1 = (B X - c X) sigma / e, written over B X
+        for (int ln = tid; ln < nloc; ln += BS) {
 #pragma unroll
-        for (int q = 0; q < NPT; ++q)
-#pragma unroll
-          for (int j = 0; j < M; ++j) Y[q][j] = (Z[q][j] - cc * X[q][j]) * (sigma / e);
+          for (int j = 0; j < M; ++j) Y[j * NL + ln] = (Y[j * NL + ln] - cc * X[j * NL + ln]) * (sigma / e);
+        }
+        __syncthreads();
+        // three-term recurrence Y_{d} = (2 sn / e)(B - c) Y_{d-1} - sigma sn Y_{d-2}; the
+        // new block overwrites Y_{d-2} node by node (nothing else reads it)
         for (int d = 2; d <= deg; ++d) {
           const double sn = 1.0 / (tau - sigma);
-          apply_B(Y, Z);
+          for (int ln = tid; ln < nloc; ln += BS) {
+            double z[M];
+            apply_node(Y, ln, z);
 #pragma unroll
-          for (int q = 0; q < NPT; ++q)
-#pragma unroll
-            for (int j = 0; j < M; ++j) {
-              const double yn = (Z[q][j] - cc * Y[q][j]) * (2.0 * sn / e) - (sigma * sn) * X[q][j];
-              X[q][j] = Y[q][j];
-              Y[q][j] = yn;
-            }
+            for (int j = 0; j < M; ++j)
+              X[j * NL + ln] = (z[j] - cc * Y[j * NL + ln]) * (2.0 * sn / e) - (sigma * sn) * X[j * NL + ln];
+          }
+          __syncthreads();
+          double* t = X;
+          X = Y;
+          Y = t;  // Y: newest iterate, X: the previous one
           sigma = sn;
         }
         orthonormalise(Y);
         orthonormalise(Y);
-        rayleigh_ritz(Y);
+        rayleigh_ritz(Y, X);
+        {
+          double* t = X;
+          X = Y;
+          Y = t;  // X: Ritz vectors, Y: B X
+        }
         a_lo = ev[M - 1];
         a_min = ev[0];
       }
@@ -409,12 +426,10 @@ __global__ __launch_bounds__(BS) void k_local_eigen(LocalArgs A) {
     double sdot[M];
 #pragma unroll
     for (int j = 0; j < M; ++j) sdot[j] = 0.0;
+    for (int ln = tid; ln < nloc; ln += BS) {
+      if (isq[ln] > 0.0) {
 #pragma unroll
-    for (int q = 0; q < NPT; ++q) {
-      const int ln = tid + q * BS;
-      if (ln < nloc && isq[ln] > 0.0) {
-#pragma unroll
-        for (int j = 0; j < M; ++j) sdot[j] += X[q][j] / isq[ln];  // sum_n m_n Phi_n
+        for (int j = 0; j < M; ++j) sdot[j] += X[j * NL + ln] / isq[ln];  // sum_n m_n Phi_n
       }
     }
     block_allsum_vec<M>(sdot, red);
@@ -428,44 +443,21 @@ __global__ __launch_bounds__(BS) void k_local_eigen(LocalArgs A) {
         sgn[j] = sdot[j] > 0.0 ? 1.0 : -1.0;
       } else {
         double amax = 0.0;
-#pragma unroll
-        for (int q = 0; q < NPT; ++q) {
-          const int ln = tid + q * BS;
-          if (ln < nloc) amax = fmax(amax, fabs(X[q][j] * isq[ln]));
-        }
+        for (int ln = tid; ln < nloc; ln += BS) amax = fmax(amax, fabs(X[j * NL + ln] * isq[ln]));
         amax = block_allmax(amax, red);
         int first = 1 << 30;
-#pragma unroll
-        for (int q = 0; q < NPT; ++q) {
-          const int ln = tid + q * BS;
-          if (ln < nloc && fabs(X[q][j] * isq[ln]) >= (1.0 - 1e-8) * amax) first = min(first, ln);
-        }
+        for (int ln = tid; ln < nloc; ln += BS)
+          if (fabs(X[j * NL + ln] * isq[ln]) >= (1.0 - 1e-8) * amax) first = min(first, ln);
         first = block_allmin_int(first, ired);
-        double v = 0.0;
-#pragma unroll
-        for (int q = 0; q < NPT; ++q) {
-          const int ln = tid + q * BS;
-          if (ln == first) v = X[q][j];
-        }
-        v = block_allsum(v, red);
+        const double v = X[j * NL + first];
         sgn[j] = v > 0.0 ? 1.0 : -1.0;
       }
     }
     const int Lc = h.Lc;
-#pragma unroll
-    for (int q = 0; q < NPT; ++q) {
-      const int ln = tid + q * BS;
-      if (ln < nloc) {
-        const int lx = ln % nlx, ly = (ln / nlx) % nly, lz = ln / (nlx * nly);
-        const long long gn = node_id(g, x0 + lx, y0 + ly, z0 + lz);
-        for (int l = 0; l < Lc; ++l) {
-          double v = 0.0;
-#pragma unroll
-          for (int j = 0; j < M; ++j)
-            if (j == l) v = X[q][j];
-          A.Rc64[gn * Lc + l] = (l < L) ? sgn[l] * v * isq[ln] : 0.0;
-        }
-      }
+    for (int ln = tid; ln < nloc; ln += BS) {
+      const int lx = ln % nlx, ly = (ln / nlx) % nly, lz = ln / (nlx * nly);
+      const long long gn = node_id(g, x0 + lx, y0 + ly, z0 + lz);
+      for (int l = 0; l < Lc; ++l) A.Rc64[gn * Lc + l] = (l < L) ? sgn[l] * X[l * NL + ln] * isq[ln] : 0.0;
     }
     if (tid == 0) {
       for (int l = 0; l < Lc; ++l) A.evals[(long long)cell * Lc + l] = (l < L) ? ev[l] : 0.0;
@@ -478,14 +470,14 @@ __global__ __launch_bounds__(BS) void k_local_eigen(LocalArgs A) {
 
 // LDS bytes of one workgroup
 static size_t local_lds_bytes(int M, int nl) {
-  return sizeof(double) * (size_t(M) * nl + 2 * size_t(nl) + 4 * 256 + 16 + RED_SLOTS) + sizeof(int) * (16 + 16 + size_t(nl) + DENSE_MAX);
+  return sizeof(double) * (2 * size_t(M) * nl + 2 * size_t(nl) + 4 * 256 + 16 + RED_SLOTS) + sizeof(int) * (16 + 16 + size_t(nl) + DENSE_MAX);
 }
 
-template <int M, int BS, int NPT>
+template <int M, int BS>
 static void launch_local_t(const LocalArgs& a, int blocks, hipStream_t s) {
   const size_t lds = local_lds_bytes(M, a.nl_max);
-  (void)hipFuncSetAttribute((const void*)k_local_eigen<M, BS, NPT>, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-  hipLaunchKernelGGL((k_local_eigen<M, BS, NPT>), dim3(blocks), dim3(BS), lds, s, a);
+  (void)hipFuncSetAttribute((const void*)k_local_eigen<M, BS>, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+  hipLaunchKernelGGL((k_local_eigen<M, BS>), dim3(blocks), dim3(BS), lds, s, a);
 }
 
 int launch_local_eigen(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, int bs, int m, int degree, int blocks,
@@ -511,18 +503,15 @@ int launch_local_eigen(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, int 
   if (m < c.h.Lc + 1) return MSMG_EINVAL;
   if (local_lds_bytes(m, a.nl_max) > 160 * 1024) return MSMG_EINVAL;
   if (hipMemsetAsync(sc->work, 0, sizeof(unsigned), s) != hipSuccess) return MSMG_EHIP;
-  const int npt = (a.nl_max + bs - 1) / bs;
-#define LL(M_, BS_, NPT_)                               \
-  if (m == M_ && bs == BS_ && npt <= NPT_) {            \
-    launch_local_t<M_, BS_, NPT_>(a, blocks, s);        \
+#define LL(M_, BS_)                                      \
+  if (m == M_ && bs == BS_) {                            \
+    launch_local_t<M_, BS_>(a, blocks, s);               \
     return hipGetLastError() == hipSuccess ? MSMG_OK : MSMG_EHIP; \
   }
-  LL(8, 256, 1)
-  LL(8, 256, 2)
-  LL(8, 256, 3)
-  LL(8, 256, 4)
-  LL(8, 512, 1)
-  LL(8, 512, 2)
+  LL(8, 256)
+  LL(8, 512)
+  LL(8, 768)
+  LL(8, 1024)
 #undef LL
   return MSMG_EINVAL;
 }

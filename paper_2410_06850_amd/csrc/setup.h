@@ -10,6 +10,15 @@
 
 namespace msmg {
 
+// Pivot block of the batched Gauss-Jordan inverse and its workspace: per
+// matrix the inverted pivot block (GJ_NB^2) and the row and column panels
+// (GJ_NB x n each).
+constexpr int GJ_NB = 64;
+inline size_t gj_workspace_doubles(int n, int batch) {
+  return (size_t)batch * ((size_t)GJ_NB * GJ_NB + 2 * (size_t)GJ_NB * n);
+}
+int gj_inverse(int n, int batch, double* A, double* work, hipStream_t s);
+
 // Launch shape of the level-1 eigensolver chosen by the tuner.
 struct TuneChoice {
   int valid;

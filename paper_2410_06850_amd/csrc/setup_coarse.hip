@@ -16,7 +16,6 @@
 
 namespace msmg {
 
-int gj_inverse(int n, int batch, double* A, double* P, double* Rb, double* Cb, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Galerkin blocks.  For colour class q = (qx,qy,qz) in {0,1,2}^3 every cell j
@@ -618,102 +617,171 @@ __global__ void k_acc_pad(Hier h, const int* __restrict__ cc_ptr, int n_cc, doub
 // n*n, batch index blockIdx.z) by pivot blocks of NB:
 //   P = A_kk^-1;  A_kJ <- P A_kJ;  A_IJ -= A_Ik A_kJ;  A_Ik <- -A_Ik P;  A_kk <- P.
 // No pivoting is needed for SPD matrices.
-constexpr int GJ_NB = 32;
-
-// invert the pivot block in LDS (unblocked Gauss-Jordan), store in P and A_kk
-__global__ void k_gj_pivot(int n, double* __restrict__ Ab, int k0, int nb, double* __restrict__ Pb) {
+// invert the pivot block in LDS (unblocked Gauss-Jordan), store in P and A_kk;
+// 1024 threads, each owning the entries tid + 1024 q of the nb x nb block
+__global__ __launch_bounds__(1024) void k_gj_pivot(int n, double* __restrict__ Ab, int k0, int nb,
+                                                   double* __restrict__ Pb) {
   __shared__ double a[GJ_NB][GJ_NB + 1];
+  constexpr int NQ = (GJ_NB * GJ_NB + 1023) / 1024;
   double* A = Ab + (long long)blockIdx.z * n * n;
   double* P = Pb + (long long)blockIdx.z * GJ_NB * GJ_NB;
-  const int tid = threadIdx.x;  // nb*nb threads at most 1024
-  const int r = tid / nb, c = tid % nb;
-  if (tid < nb * nb) a[r][c] = A[(long long)(k0 + r) * n + (k0 + c)];
+  const int tid = threadIdx.x;
+  const int ne = nb * nb;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int e = tid + 1024 * q;
+    if (e < ne) a[e / nb][e % nb] = A[(long long)(k0 + e / nb) * n + (k0 + e % nb)];
+  }
   __syncthreads();
   for (int k = 0; k < nb; ++k) {
     const double piv = 1.0 / a[k][k];
-    double akc = 0.0, ark = 0.0;
-    if (tid < nb * nb) {
-      akc = a[k][c];
-      ark = a[r][k];
+    double akc[NQ], ark[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int e = tid + 1024 * q;
+      akc[q] = ark[q] = 0.0;
+      if (e < ne) {
+        akc[q] = a[k][e % nb];
+        ark[q] = a[e / nb][k];
+      }
     }
     __syncthreads();
-    if (tid < nb * nb) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int e = tid + 1024 * q;
+      if (e >= ne) continue;
+      const int r = e / nb, c = e % nb;
       if (r == k && c == k) a[r][c] = piv;
-      else if (r == k) a[r][c] = akc * piv;
-      else if (c == k) a[r][c] = -ark * piv;
-      else a[r][c] = a[r][c] - ark * akc * piv;
+      else if (r == k) a[r][c] = akc[q] * piv;
+      else if (c == k) a[r][c] = -ark[q] * piv;
+      else a[r][c] = a[r][c] - ark[q] * akc[q] * piv;
     }
     __syncthreads();
   }
-  if (tid < nb * nb) {
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int e = tid + 1024 * q;
+    if (e >= ne) continue;
+    const int r = e / nb, c = e % nb;
     P[r * nb + c] = a[r][c];
     A[(long long)(k0 + r) * n + (k0 + c)] = a[r][c];
   }
 }
 
-// Rb[r][j] = sum_t P[r][t] A[k0+t][j] for j outside the pivot block
-__global__ void k_gj_rowpanel(int n, const double* __restrict__ Ab, int k0, int nb, const double* __restrict__ Pb,
-                              double* __restrict__ Rbb) {
-  const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (gid >= (long long)nb * n) return;
-  const double* A = Ab + (long long)blockIdx.z * n * n;
-  const double* P = Pb + (long long)blockIdx.z * GJ_NB * GJ_NB;
-  double* Rb = Rbb + (long long)blockIdx.z * GJ_NB * n;
-  const int r = int(gid / n), j = int(gid % n);
-  if (j >= k0 && j < k0 + nb) return;
-  double s = 0.0;
-  for (int t = 0; t < nb; ++t) s += P[r * nb + t] * A[(long long)(k0 + t) * n + j];
-  Rb[(long long)r * n + j] = s;
-}
+// The three products of a Gauss-Jordan step, each on 64 x 64 output tiles
+// computed by FP64 matrix cores (inner dimension: the nb pivot columns):
+//   GJ_ROW:    Rb[r][j]  =  sum_t P[r][t] A[k0+t][j]     (j outside the pivot block)
+//   GJ_COL:    Cb[i][c]  = -sum_t A[i][k0+t] P[t][c]     (i outside the pivot block)
+//   GJ_UPDATE: A[i][j]  -=  sum_t A[i][k0+t] Rb[t][j]    (i and j outside it)
+// Each wave owns a 32 x 32 quarter of the tile as 2 x 2 blocks of
+// v_mfma_f64_16x16x4 (A operand: lane holds row lane % 16, k lane / 16; B
+// operand: column lane % 16, k lane / 16; result register v: column
+// lane % 16, row lane / 16 + 4 v, as measured on gfx950).  Both operands are
+// staged in LDS with row strides chosen so that the operand reads of 32 lanes
+// hit distinct banks; every thread issues all its global loads (and, for the
+// update, its part of the output tile) before the first LDS store, so the
+// loads of a tile are in flight together.  Operand entries beyond nb are zero.
+typedef double gj_v4d __attribute__((ext_vector_type(4)));
+constexpr int GJ_LDA = 66, GJ_LDB = 80;
+constexpr size_t GJ_TILE_LDS = sizeof(double) * (64 * GJ_LDA + GJ_NB * GJ_LDB);
+enum { GJ_ROW = 0, GJ_COL = 1, GJ_UPDATE = 2 };
 
-// Cb[i][c] = -sum_t A[i][k0+t] P[t][c] for rows outside the pivot block (old column panel)
-__global__ void k_gj_colpanel(int n, const double* __restrict__ Ab, int k0, int nb, const double* __restrict__ Pb,
-                              double* __restrict__ Cbb) {
-  const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (gid >= (long long)n * nb) return;
-  const double* A = Ab + (long long)blockIdx.z * n * n;
-  const double* P = Pb + (long long)blockIdx.z * GJ_NB * GJ_NB;
-  double* Cb = Cbb + (long long)blockIdx.z * GJ_NB * n;
-  const int i = int(gid / nb), c = int(gid % nb);
-  if (i >= k0 && i < k0 + nb) return;
-  double s = 0.0;
-  for (int t = 0; t < nb; ++t) s += A[(long long)i * n + k0 + t] * P[t * nb + c];
-  Cb[(long long)i * nb + c] = -s;
-}
-
-// A_ij -= sum_t A[i][k0+t] Rb[t][j] for i, j outside the pivot block (64x64 tiles)
-__global__ void k_gj_update(int n, double* __restrict__ Ab, int k0, int nb, const double* __restrict__ Rbb) {
-  __shared__ double As[64][GJ_NB + 1];
-  __shared__ double Bs[GJ_NB][64 + 1];
-  double* A = Ab + (long long)blockIdx.z * n * n;
-  const double* Rb = Rbb + (long long)blockIdx.z * GJ_NB * n;
-  const int ti = blockIdx.y * 64, tj = blockIdx.x * 64;
-  const int tid = threadIdx.x;  // 256
-  for (int e = tid; e < 64 * nb; e += 256) {
-    const int r = e / nb, t = e % nb;
-    const int i = ti + r;
-    As[r][t] = (i < n) ? A[(long long)i * n + k0 + t] : 0.0;
+template <int MODE>
+__global__ __launch_bounds__(256) void k_gj_tile(int n, double* __restrict__ Ab, int k0, int nb,
+                                                 const double* __restrict__ Pb, double* __restrict__ Rbb,
+                                                 double* __restrict__ Cbb) {
+  static_assert(GJ_NB == 64, "tiles assume 64 pivot columns");
+  extern __shared__ double gj_lds[];
+  double* As = gj_lds;                 // As[r][t], 64 x GJ_LDA
+  double* Bs = gj_lds + 64 * GJ_LDA;   // Bs[t][c], GJ_NB x GJ_LDB
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  const bool ipiv_tile = i0 >= k0 && i0 + 64 <= k0 + nb, jpiv_tile = j0 >= k0 && j0 + 64 <= k0 + nb;
+  if (MODE == GJ_UPDATE && (ipiv_tile || jpiv_tile)) return;  // left to the write-back
+  if (MODE == GJ_ROW && jpiv_tile) return;
+  if (MODE == GJ_COL && ipiv_tile) return;
+  const long long z = blockIdx.z;
+  double* A = Ab + z * n * n;
+  const double* P = Pb + z * GJ_NB * GJ_NB;
+  double* Rb = Rbb + z * GJ_NB * n;
+  double* Cb = Cbb + z * GJ_NB * n;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
+  const int l16 = lane & 15, lk = lane >> 4;
+  auto a_elem = [&](int r, int t) -> double {  // A operand [r][t]
+    if (t >= nb) return 0.0;
+    if (MODE == GJ_ROW) return r < nb ? P[r * nb + t] : 0.0;
+    const int i = i0 + r;
+    return i < n ? A[(long long)i * n + k0 + t] : 0.0;
+  };
+  auto b_elem = [&](int t, int c) -> double {  // B operand [t][c]
+    if (t >= nb) return 0.0;
+    if (MODE == GJ_COL) return c < nb ? P[t * nb + c] : 0.0;
+    const int j = j0 + c;
+    if (j >= n) return 0.0;
+    return MODE == GJ_ROW ? A[(long long)(k0 + t) * n + j] : Rb[(long long)t * n + j];
+  };
+  auto out_ok = [&](int i, int j) {
+    const bool iok = i < n && !(i >= k0 && i < k0 + nb), jok = j < n && !(j >= k0 && j < k0 + nb);
+    if (MODE == GJ_UPDATE) return iok && jok;
+    if (MODE == GJ_ROW) return i - i0 < nb && jok;
+    return iok && j - j0 < nb;
+  };
+  double ra[16], rb[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = tid + 256 * q;
+    ra[q] = a_elem(e >> 6, e & 63);
+    rb[q] = b_elem(e >> 6, e & 63);
   }
-  for (int e = tid; e < nb * 64; e += 256) {
-    const int t = e / 64, c = e % 64;
-    const int j = tj + c;
-    Bs[t][c] = (j < n) ? Rb[(long long)t * n + j] : 0.0;
+  gj_v4d cv[2][2];
+  if (MODE == GJ_UPDATE) {
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = i0 + wr + bi * 16 + lk + 4 * v, j = j0 + wc + bj * 16 + l16;
+          cv[bi][bj][v] = out_ok(i, j) ? A[(long long)i * n + j] : 0.0;
+        }
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = tid + 256 * q;
+    As[(e >> 6) * GJ_LDA + (e & 63)] = ra[q];
+    Bs[(e >> 6) * GJ_LDB + (e & 63)] = rb[q];
   }
   __syncthreads();
-  const int r0 = (tid / 16) * 4, c0 = (tid % 16) * 4;
-  double acc[4][4] = {};
-  for (int t = 0; t < nb; ++t)
+  gj_v4d acc[2][2];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+  for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] += As[r0 + a][t] * Bs[t][c0 + b];
+    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = gj_v4d{0.0, 0.0, 0.0, 0.0};
+  const int ksteps = (nb + 3) / 4;
+#pragma unroll 4
+  for (int ks = 0; ks < ksteps; ++ks) {
+    const int kk = ks * 4 + lk;
+    const double a0 = As[(wr + l16) * GJ_LDA + kk];
+    const double a1 = As[(wr + 16 + l16) * GJ_LDA + kk];
+    const double b0 = Bs[kk * GJ_LDB + wc + l16];
+    const double b1 = Bs[kk * GJ_LDB + wc + 16 + l16];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+  }
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int i = ti + r0 + a, j = tj + c0 + b;
-      if (i < n && j < n && !(i >= k0 && i < k0 + nb) && !(j >= k0 && j < k0 + nb)) A[(long long)i * n + j] -= acc[a][b];
-    }
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + wr + bi * 16 + lk + 4 * v, j = j0 + wc + bj * 16 + l16;
+        if (!out_ok(i, j)) continue;
+        if (MODE == GJ_UPDATE) A[(long long)i * n + j] = cv[bi][bj][v] - acc[bi][bj][v];
+        else if (MODE == GJ_ROW) Rb[(long long)(i - i0) * n + j] = acc[bi][bj][v];
+        else Cb[(long long)i * nb + (j - j0)] = -acc[bi][bj][v];
+      }
 }
 
 __global__ void k_gj_writeback(int n, double* __restrict__ Ab, int k0, int nb, const double* __restrict__ Rbb,
@@ -788,29 +856,73 @@ __global__ void k_ccd_assemble(CCArgs a, int ndm, const double* __restrict__ par
   Gd[(long long)J * ndm * ndm + e] = v;
 }
 
-// Y = (G + sigma I)^-1 X per active cc cell (the inverse is symmetric: read columns)
-__global__ void k_ccd_apply(CCArgs a, int ndm, const double* __restrict__ Gi, const double* __restrict__ X,
-                            double* __restrict__ Y, const int* __restrict__ flag) {
+// Y = (G + sigma I)^-1 X per active cc cell (the inverse is symmetric: row q of
+// it is column q).  A workgroup computes 512 rows x 32 vectors: wave w owns
+// rows (w & 1) * 256 + lane + 64 k (k < 4) and vectors (w >> 1) * 16 .. +16,
+// so each inverse entry loaded from HBM feeds 16 FMAs and each vector entry
+// read from LDS (a broadcast) feeds 4.  Vectors are staged in chunks of 64
+// entries, transposed, with rows beyond nd and vectors beyond m zero.
+constexpr int CCD_ROWS = 512, CCD_QC = 64, CCD_XS = 34;
+
+__global__ __launch_bounds__(256) void k_ccd_apply(CCArgs a, int ndm, const double* __restrict__ Gi,
+                                                   const double* __restrict__ X, double* __restrict__ Y,
+                                                   const int* __restrict__ flag) {
+  __shared__ __align__(16) double Xs[CCD_QC * CCD_XS];
   const int J = blockIdx.y;
   if (flag[J] >= 0) return;
   const int m = a.m;
   const int d0 = a.cc_ptr[J], nd = a.cc_ptr[J + 1] - d0;
-  const int d = blockIdx.x * blockDim.x + threadIdx.x;
-  if (d >= nd) return;
+  const int rbase = blockIdx.x * CCD_ROWS;
+  if (rbase >= nd) return;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int r0 = rbase + (w & 1) * 256 + lane;
+  const int c0 = (w >> 1) * 16;
   const double* G = Gi + (long long)J * ndm * ndm;
   const double* XJ = X + (long long)m * d0;
-  double acc[32];
-  for (int j = 0; j < 32; ++j) acc[j] = 0.0;
-  for (int q = 0; q < nd; ++q) {
-    const double g = G[(long long)q * ndm + d];
+  int rc[4];
 #pragma unroll
-    for (int j = 0; j < 32; ++j)
-      if (j < m) acc[j] += g * XJ[(long long)j * nd + q];
+  for (int k = 0; k < 4; ++k) rc[k] = min(r0 + 64 * k, ndm - 1);  // clamped: in bounds, result unused
+  double acc[4][16];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int c = 0; c < 16; ++c) acc[k][c] = 0.0;
+  for (int q0 = 0; q0 < nd; q0 += CCD_QC) {
+    __syncthreads();
+    for (int e = tid; e < CCD_QC * 32; e += 256) {
+      const int qq = e % CCD_QC, j = e / CCD_QC;
+      const int q = q0 + qq;
+      Xs[qq * CCD_XS + j] = (j < m && q < nd) ? XJ[(long long)j * nd + q] : 0.0;
+    }
+    __syncthreads();
+    const int qn = min(CCD_QC, nd - q0);
+#pragma unroll 2
+    for (int qq = 0; qq < qn; ++qq) {
+      const double* Gq = G + (long long)(q0 + qq) * ndm;
+      double g[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) g[k] = Gq[rc[k]];
+      const double2* xs = reinterpret_cast<const double2*>(Xs + qq * CCD_XS + c0);
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const double2 x = xs[c];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          acc[k][2 * c] += g[k] * x.x;
+          acc[k][2 * c + 1] += g[k] * x.y;
+        }
+      }
+    }
   }
   double* YJ = Y + (long long)m * d0;
 #pragma unroll
-  for (int j = 0; j < 32; ++j)
-    if (j < m) YJ[(long long)j * nd + d] = acc[j];
+  for (int k = 0; k < 4; ++k) {
+    const int r = r0 + 64 * k;
+    if (r >= nd) continue;
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+      if (c0 + c < m) YJ[(long long)(c0 + c) * nd + r] = acc[k][c];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -903,13 +1015,11 @@ int run_cc_eigen(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, const doub
   hipLaunchKernelGGL(k_ccd_assemble, dim3((unsigned)(((long long)ndm * ndm + 255) / 256), h.ncc), dim3(256), 0, s, a,
                      ndm, par, sc->Gd);
   {
-    double* P = sc->gj;
-    double* Rb = P + (size_t)h.ncc * 32 * 32;
-    double* Cb = Rb + (size_t)h.ncc * 32 * ndm;
-    const int r = gj_inverse(ndm, h.ncc, sc->Gd, P, Rb, Cb, s);
+    const int r = gj_inverse(ndm, h.ncc, sc->Gd, sc->gj, s);
     if (r != MSMG_OK) return r;
   }
-  const dim3 ga((ndm + 63) / 64, h.ncc), ba(64);
+  if (m > 32) return MSMG_EINVAL;
+  const dim3 ga((ndm + CCD_ROWS - 1) / CCD_ROWS, h.ncc), ba(256);
   for (int it = 0; it <= maxit; ++it) {
     hipLaunchKernelGGL(k_cc_check, dim3(h.ncc), dim3(256), 0, s, a, Xp, Z, ritz, par, flag, bound, h.Lcc, tol, it,
                        it == maxit ? 1 : 0, degree);
@@ -959,16 +1069,23 @@ int build_acc(const Ctx& c, const SetupArgs& sa, double* u, hipStream_t s) {
   return hipGetLastError() == hipSuccess ? MSMG_OK : MSMG_EHIP;
 }
 
-int gj_inverse(int n, int batch, double* A, double* P, double* Rb, double* Cb, hipStream_t s) {
+int gj_inverse(int n, int batch, double* A, double* work, hipStream_t s) {
+  double* P = work;
+  double* Rb = P + (size_t)batch * GJ_NB * GJ_NB;
+  double* Cb = Rb + (size_t)batch * GJ_NB * n;
+  for (const void* f : {(const void*)k_gj_tile<GJ_ROW>, (const void*)k_gj_tile<GJ_COL>, (const void*)k_gj_tile<GJ_UPDATE>})
+    if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(GJ_TILE_LDS)) != hipSuccess)
+      return MSMG_EHIP;
+  const unsigned nt = unsigned((n + 63) / 64);
   for (int k0 = 0; k0 < n; k0 += GJ_NB) {
     const int nb = std::min(GJ_NB, n - k0);
     hipLaunchKernelGGL(k_gj_pivot, dim3(1, 1, batch), dim3(1024), 0, s, n, A, k0, nb, P);
+    // the row panel tiles run along j (one tile row at i0 = 0), the column panel along i
+    hipLaunchKernelGGL(k_gj_tile<GJ_ROW>, dim3(nt, 1, batch), dim3(256), GJ_TILE_LDS, s, n, A, k0, nb, P, Rb, Cb);
+    hipLaunchKernelGGL(k_gj_tile<GJ_COL>, dim3(1, nt, batch), dim3(256), GJ_TILE_LDS, s, n, A, k0, nb, P, Rb, Cb);
+    hipLaunchKernelGGL(k_gj_tile<GJ_UPDATE>, dim3(nt, nt, batch), dim3(256), GJ_TILE_LDS, s, n, A, k0, nb, P, Rb, Cb);
     const long long rn = (long long)nb * n;
     const dim3 gp((unsigned)((rn + 255) / 256), 1, batch);
-    hipLaunchKernelGGL(k_gj_rowpanel, gp, dim3(256), 0, s, n, A, k0, nb, P, Rb);
-    hipLaunchKernelGGL(k_gj_colpanel, gp, dim3(256), 0, s, n, A, k0, nb, P, Cb);
-    const dim3 gt((n + 63) / 64, (n + 63) / 64, batch);
-    hipLaunchKernelGGL(k_gj_update, gt, dim3(256), 0, s, n, A, k0, nb, Rb);
     hipLaunchKernelGGL(k_gj_writeback, gp, dim3(256), 0, s, n, A, k0, nb, Rb, Cb);
   }
   return hipGetLastError() == hipSuccess ? MSMG_OK : MSMG_EHIP;

@@ -18,7 +18,6 @@ int launch_galerkin(const Ctx& c, const void* R, int b_dt, int drop_cc, double* 
 void launch_block_inverse(const Ctx& c, double* Ac, double* Dinv, hipStream_t s);
 int run_cc_eigen(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, const double* G, int* n_unconv, hipStream_t s);
 int build_acc(const Ctx& c, const SetupArgs& sa, double* u, hipStream_t s);
-int gj_inverse(int n, int batch, double* A, double* P, double* Rb, double* Cb, hipStream_t s);
 void launch_convert(const void* in, int din, void* out, int dout, long long n, hipStream_t s);
 
 int setup_scratch_alloc(const Geo& g, const Hier& h, int max_cc_dofs, const msmg_options& o, SetupScratch* s,
@@ -38,8 +37,8 @@ int setup_scratch_alloc(const Geo& g, const Hier& h, int max_cc_dofs, const msmg
   const size_t ncc = (size_t)h.ncc * h.Lcc;
   if ((r = alloc((void**)&s->acc_copy, ncc * ncc * 8))) return r;
   const size_t ndm = (size_t)std::max(max_cc_dofs, 1);
-  const size_t gj_single = 32 * 32 + 2 * 32 * ncc;
-  const size_t gj_batch = (size_t)h.ncc * (32 * 32 + 2 * 32 * ndm);
+  const size_t gj_single = gj_workspace_doubles(int(ncc), 1);
+  const size_t gj_batch = gj_workspace_doubles(int(ndm), h.ncc);
   if ((r = alloc((void**)&s->gj, std::max(gj_single, gj_batch) * 8))) return r;
   if ((r = alloc((void**)&s->Gd, (size_t)h.ncc * ndm * ndm * 8))) return r;
   if ((r = alloc((void**)&s->work, 64))) return r;
@@ -208,10 +207,7 @@ int run_setup(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, SetupReport* 
   if ((r = build_acc(c, sa, sc->Y, s))) return hip_ok(hipGetLastError(), rep, "A_cc");
   const size_t nn2 = (size_t)sa.n_cc * sa.n_cc * 8;
   if ((r = hip_ok(hipMemcpyAsync(sc->acc_copy, sa.Acc, nn2, hipMemcpyDeviceToDevice, s), rep, "A_cc copy"))) return r;
-  double* P = sc->gj;
-  double* Rb = P + 32 * 32;
-  double* Cb = Rb + (size_t)32 * sa.n_cc;
-  if ((r = gj_inverse(sa.n_cc, 1, sa.Acc, P, Rb, Cb, s))) return hip_ok(hipGetLastError(), rep, "A_cc inverse");
+  if ((r = gj_inverse(sa.n_cc, 1, sa.Acc, sc->gj, s))) return hip_ok(hipGetLastError(), rep, "A_cc inverse");
   return hip_ok(hipGetLastError(), rep, "set-up");
 }
 

@@ -104,6 +104,63 @@ MSMG_DEV void jacobi_rot(const double* A, int m, int p, int q, double& c, double
   s = t * c;
 }
 
+// The same parallel cyclic Jacobi method for m = 8, run by one wave with the
+// matrix in registers: lane e holds A[e / 8][e % 8] and V[e / 8][e % 8], and
+// every operand of a rotation comes from another lane by a shuffle, so the
+// sweeps need no barrier.  Same rotations in the same order as block_jacobi;
+// eigenvalues ascending (stable in the index on ties) into ev, eigenvectors
+// as the columns of Vs.  Only the 64 lanes of one wave may call; the caller
+// synchronises before others read ev and Vs.
+MSMG_DEV void wave_jacobi8(const double* A, double* Vs, double* ev, int max_sweeps = 16) {
+  const int e = threadIdx.x & 63, i = e >> 3, j = e & 7;
+  double a = A[e];
+  double v = (i == j) ? 1.0 : 0.0;
+  auto rot = [](double app, double aqq, double apq, double& c, double& s) {
+    if (fabs(apq) < 1e-300) {
+      c = 1.0;
+      s = 0.0;
+      return;
+    }
+    const double tau = (aqq - app) / (2.0 * apq);
+    const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+    c = 1.0 / sqrt(1.0 + t * t);
+    s = t * c;
+  };
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    for (int r = 0; r < 7; ++r) {
+      // column pass: B = A J, V = V J (rotation of columns j and its partner)
+      const int jp = rr_partner(r, j, 8), p = min(j, jp), q = max(j, jp);
+      const double app = __shfl(a, p * 9, 64), aqq = __shfl(a, q * 9, 64), apq = __shfl(a, p * 8 + q, 64);
+      double c, s;
+      rot(app, aqq, apq, c, s);
+      const double aip = __shfl(a, i * 8 + p, 64), aiq = __shfl(a, i * 8 + q, 64);
+      const double vip = __shfl(v, i * 8 + p, 64), viq = __shfl(v, i * 8 + q, 64);
+      const double b = (j == p) ? c * aip - s * aiq : s * aip + c * aiq;
+      v = (j == p) ? c * vip - s * viq : s * vip + c * viq;
+      // row pass: A = J^T B with the rotation of rows i and its partner (from the old A)
+      const int ip = rr_partner(r, i, 8), pr = min(i, ip), qr = max(i, ip);
+      const double rpp = __shfl(a, pr * 9, 64), rqq = __shfl(a, qr * 9, 64), rpq = __shfl(a, pr * 8 + qr, 64);
+      double cr, sr;
+      rot(rpp, rqq, rpq, cr, sr);
+      const double bpj = __shfl(b, pr * 8 + j, 64), bqj = __shfl(b, qr * 8 + j, 64);
+      a = (i == pr) ? cr * bpj - sr * bqj : sr * bpj + cr * bqj;
+    }
+    const double a2 = a * a;
+    const double off = wave_sum(i != j ? a2 : 0.0), all = wave_sum(a2);
+    if (!(off > 1e-32 * all)) break;
+  }
+  // rank of diagonal entry k among the diagonal (ascending, ties by index)
+  const double dj = __shfl(a, j * 9, 64);
+  int rank = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const double dk = __shfl(a, k * 9, 64);
+    rank += (dk < dj || (dk == dj && k < j)) ? 1 : 0;
+  }
+  Vs[i * 8 + rank] = v;
+  if (i == 0) ev[rank] = dj;
+}
+
 // Eigen-decomposition of the symmetric m x m matrix A (LDS, row-major) by the
 // parallel cyclic Jacobi method: rounds of disjoint rotations, each applied as
 // a column pass (B = A J, V = V J) and a row pass (A = J^T B).  On return

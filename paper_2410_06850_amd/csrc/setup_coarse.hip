@@ -47,9 +47,18 @@ __global__ void k_galerkin(Geo g, Stencil st, Hier h, int CX, const void* rho, i
     const int icx = t.cx + ox, icy = t.cy + oy, icz = t.cz + oz;
     const bool exists = icx >= 0 && icx < h.ncx && icy >= 0 && icy < h.ncy && icz >= 0 && icz < h.ncz;
     if (exists) {
-      for (int k = t.zs; k < t.ze; ++k)
-        for (int j = t.ys; j < t.ye; ++j)
-          for (int i = t.xs; i < t.xe; ++i) {
+      // towards a neighbour cell only the cell's boundary layer on that side
+      // has stencil partners there
+      int xs = t.xs, xe = t.xe, ys = t.ys, ye = t.ye, zs = t.zs, ze = t.ze;
+      if (ox > 0) xs = max(xs, cell_end(t.cx, H, h.ncx, g.nnx) - 1);
+      if (ox < 0) xe = min(xe, cell_begin(t.cx, H) + 1);
+      if (oy > 0) ys = max(ys, cell_end(t.cy, H, h.ncy, g.nny) - 1);
+      if (oy < 0) ye = min(ye, cell_begin(t.cy, H) + 1);
+      if (oz > 0) zs = max(zs, cell_end(t.cz, H, h.ncz, g.nnz) - 1);
+      if (oz < 0) ze = min(ze, cell_begin(t.cz, H) + 1);
+      for (int k = zs; k < ze; ++k)
+        for (int j = ys; j < ye; ++j)
+          for (int i = xs; i < xe; ++i) {
             const long long n = node_id(g, i, j, k);
             double kk[8];
 #pragma unroll
@@ -93,37 +102,49 @@ __global__ void k_galerkin(Geo g, Stencil st, Hier h, int CX, const void* rho, i
           }
     }
   }
-  // per-cell sums, one (a, b) entry at a time, fixed order
+  // per-cell sums in a fixed order, four (a, b) entries at a time: the H
+  // x-threads of each cell and row first, then the rows
   const int nthr = blockDim.x * blockDim.y;
   const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+  const int bx = blockDim.x, by = blockDim.y;
+  double* part = smem + nthr * 4;  // [by][CX][4]
   const int ntx = (h.ncx + CX - 1) / CX;
   const int tx = int(tile % ntx), ty = int((tile / ntx) % h.ncy), tz = int(tile / ((long long)ntx * h.ncy));
-  for (int a = 0; a < LT; ++a)
-    for (int b = 0; b < LT; ++b) {
+  for (int g0 = 0; g0 < LT * LT; g0 += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
       double v = 0.0;
 #pragma unroll
       for (int aa = 0; aa < LT; ++aa)
 #pragma unroll
         for (int bb = 0; bb < LT; ++bb)
-          if (aa == a && bb == b) v = acc[aa][bb];
-      smem[tid] = v;
-      __syncthreads();
-      if (tid < CX) {
-        const int cx = tx * CX + tid;
-        if (cx < h.ncx && tz < h.ncz) {
-          double s = 0.0;
-          for (int ly = 0; ly < (int)blockDim.y; ++ly)
-            for (int lx = tid * H; lx < (tid + 1) * H; ++lx) s += smem[ly * blockDim.x + lx];
-          const long long cell = ((long long)tz * h.ncy + ty) * h.ncx + cx;
-          // this thread's cell shares the colour offset computed from its coordinates
-          const int ox = (((qx - cx) % 3 + 3) % 3), oy = (((qy - ty) % 3 + 3) % 3), oz = (((qz - tz) % 3 + 3) % 3);
-          const int bx = ox == 0 ? 1 : (ox == 1 ? 2 : 0), by = oy == 0 ? 1 : (oy == 1 ? 2 : 0), bz = oz == 0 ? 1 : (oz == 1 ? 2 : 0);
-          const int bi = bz * 9 + by * 3 + bx;
-          out[((cell * 27 + bi) * LT + a) * LT + b] = s;
-        }
-      }
-      __syncthreads();
+          if (aa * LT + bb == g0 + u) v = acc[aa][bb];
+      smem[tid * 4 + u] = v;
     }
+    __syncthreads();
+    for (int w = tid; w < by * CX * 4; w += nthr) {
+      const int u = w % 4, c = (w / 4) % CX, ly = w / (4 * CX);
+      double s = 0.0;
+      for (int x = 0; x < H; ++x) s += smem[(ly * bx + c * H + x) * 4 + u];
+      part[(ly * CX + c) * 4 + u] = s;
+    }
+    __syncthreads();
+    if (tid < CX * 4) {
+      const int u = tid % 4, c = tid / 4;
+      const int cx = tx * CX + c;
+      if (cx < h.ncx && tz < h.ncz && g0 + u < LT * LT) {
+        double s = 0.0;
+        for (int ly = 0; ly < by; ++ly) s += part[(ly * CX + c) * 4 + u];
+        const long long cell = ((long long)tz * h.ncy + ty) * h.ncx + cx;
+        // the cell's colour offset, from its own coordinates
+        const int ox = (((qx - cx) % 3 + 3) % 3), oy = (((qy - ty) % 3 + 3) % 3), oz = (((qz - tz) % 3 + 3) % 3);
+        const int bxo = ox == 0 ? 1 : (ox == 1 ? 2 : 0), byo = oy == 0 ? 1 : (oy == 1 ? 2 : 0), bzo = oz == 0 ? 1 : (oz == 1 ? 2 : 0);
+        const int bi = bzo * 9 + byo * 3 + bxo;
+        out[(cell * 27 + bi) * LT * LT + g0 + u] = s;
+      }
+    }
+    __syncthreads();
+  }
   (void)bidx;
 }
 
@@ -930,7 +951,7 @@ __global__ __launch_bounds__(256) void k_ccd_apply(CCArgs a, int ndm, const doub
 
 int launch_galerkin(const Ctx& c, const void* R, int b_dt, int drop_cc, double* out, hipStream_t s) {
   const dim3 gr((unsigned)(((c.ntiles + 7) / 8) * 8)), bl(c.CX * c.h.H, c.h.H);
-  const size_t sh = size_t(bl.x) * bl.y * sizeof(double);
+  const size_t sh = (size_t(bl.x) * bl.y * 4 + size_t(bl.y) * c.CX * 4) * sizeof(double);
   const int L = c.h.Lc;
   for (int q = 0; q < 27; ++q) {
     const int qx = q % 3, qy = (q / 3) % 3, qz = q / 9;

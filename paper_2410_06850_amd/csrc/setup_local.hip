@@ -235,10 +235,19 @@ __global__ __launch_bounds__(BS) void k_local_eigen(LocalArgs A) {
       }
       __syncthreads();
     };
+    // eigen-decomposition of the M x M matrix in Gm -> ev (ascending), Vs
+    auto small_eig = [&]() {
+      if constexpr (M == 8) {
+        if (wid == 0) wave_jacobi8(Gm, Vs, ev);
+        __syncthreads();
+      } else {
+        block_jacobi(Gm, Vm, Bm, Vs, ev, perm, M, red);
+      }
+    };
     // orthonormalise a block: G = P^T P = U S U^T, P <- P U S^-1/2
     auto orthonormalise = [&](double* P) {
       gram(P, P);
-      block_jacobi(Gm, Vm, Bm, Vs, ev, perm, M, red);
+      small_eig();
       for (int e = tid; e < M * M; e += BS) {
         const int k = e % M;
         const double sv = ev[k];
@@ -258,7 +267,7 @@ __global__ __launch_bounds__(BS) void k_local_eigen(LocalArgs A) {
       }
       __syncthreads();
       gram(P, Q);
-      block_jacobi(Gm, Vm, Bm, Vs, ev, perm, M, red);
+      small_eig();
       transform(P, Vs);
       transform(Q, Vs);
     };

@@ -230,74 +230,111 @@ __global__ void k_cc_start(CCArgs a, double* __restrict__ Y) {
   }
 }
 
-// Z = G Y (all cc cells), optionally fused with the filter recurrence:
-//   mode 0: Z = G Y
-//   mode 1: Z = (G Y - c Y) * s1                      (first filter step, X unused)
-//   mode 2: Z = (G Y - c Y) * s1 - s2 * X             (later filter steps)
-// with per-cc-cell coefficients par[J*8 + {c, s1, s2}].
-__global__ void k_cc_spmm(CCArgs a, const double* __restrict__ Y, const double* __restrict__ X, double* __restrict__ Z,
-                          int mode, const double* __restrict__ par, const int* __restrict__ flag) {
-  const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+// Z = G Y on the active cc cells.  Grid (ceil(cells / 64), ncc, m / 8): a
+// thread owns one coarse cell of cc cell J and eight vectors, so each 27 x L x L
+// block row of G is read once per eight vectors; the L entries of a
+// neighbour cell are contiguous in every vector.  Invalid (padded) dofs get 0.
+template <int L>
+__global__ __launch_bounds__(64) void k_cc_spmm(CCArgs a, const double* __restrict__ Y, double* __restrict__ Z,
+                                                const int* __restrict__ flag) {
+  const int J = blockIdx.y;
+  if (flag && flag[J] >= 0) return;
   const Hier& h = a.h;
-  const int L = h.Lc;
-  const long long ndof = (long long)h.ncells * L;
-  if (gid >= ndof * a.m) return;
-  const long long d = gid % ndof;
-  const int j = int(gid / ndof);
-  const int J = a.dof_cc[d];
-  if (flag && flag[J] >= 0) return;  // converged cc cell: leave untouched
-  const int loc = a.dof_loc[d];
+  const int m = a.m;
   const int d0 = a.cc_ptr[J], nd = a.cc_ptr[J + 1] - d0;
-  const double* Yj = Y + (long long)a.m * d0 + (long long)j * nd;
-  const long long out_i = (long long)a.m * d0 + (long long)j * nd + loc;
-  if (!dof_valid(a, d)) {
-    Z[out_i] = 0.0;
-    return;
-  }
-  const int cell = int(d / L), l = int(d % L);
+  const int lc = blockIdx.x * 64 + threadIdx.x;
+  if (lc * L >= nd) return;
+  const int j0 = blockIdx.z * 8;
+  const int cell = a.cc_dofs[d0 + lc * L] / L;
   const int cx = cell % h.ncx, cy = (cell / h.ncx) % h.ncy, cz = cell / (h.ncx * h.ncy);
+  const double* YJ = Y + (long long)m * d0;
+  double acc[8][L];
+#pragma unroll
+  for (int jj = 0; jj < 8; ++jj)
+#pragma unroll
+    for (int l = 0; l < L; ++l) acc[jj][l] = 0.0;
   const double* Gr = a.G + (long long)cell * 27 * L * L;
-  double s = 0.0;
   for (int b = 0; b < 27; ++b) {
     const int x = cx + b % 3 - 1, y = cy + (b / 3) % 3 - 1, z = cz + b / 9 - 1;
     if (x < 0 || x >= h.ncx || y < 0 || y >= h.ncy || z < 0 || z >= h.ncz) continue;
     const long long nc = ((long long)z * h.ncy + y) * h.ncx + x;
     if (a.dof_cc[nc * L] != J) continue;
     const int nloc0 = a.dof_loc[nc * L];
-    for (int m = 0; m < L; ++m) s += Gr[(b * L + l) * L + m] * Yj[nloc0 + m];
-  }
-  if (mode == 0) {
-    Z[out_i] = s;
-  } else {
-    const double c = par[J * 8 + 0], s1 = par[J * 8 + 1], s2 = par[J * 8 + 2];
-    if (s1 < 0.0) {  // this cell's filter degree is exhausted: carry the block forward
-      Z[out_i] = Yj[loc];
-      return;
+    double g[L][L];
+#pragma unroll
+    for (int l = 0; l < L; ++l)
+#pragma unroll
+      for (int q = 0; q < L; ++q) g[l][q] = Gr[(b * L + l) * L + q];
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj) {
+      if (j0 + jj >= m) break;
+      const double* yv = YJ + (long long)(j0 + jj) * nd + nloc0;
+      double yq[L];
+#pragma unroll
+      for (int q = 0; q < L; ++q) yq[q] = yv[q];
+#pragma unroll
+      for (int l = 0; l < L; ++l)
+#pragma unroll
+        for (int q = 0; q < L; ++q) acc[jj][l] += g[l][q] * yq[q];
     }
-    double v = (s - c * Yj[loc]) * s1;
-    if (mode == 2) v -= s2 * X[out_i];
-    Z[out_i] = v;
+  }
+  double* ZJ = Z + (long long)m * d0;
+#pragma unroll
+  for (int jj = 0; jj < 8; ++jj) {
+    if (j0 + jj >= m) break;
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+      const long long d = (long long)cell * L + l;
+      ZJ[(long long)(j0 + jj) * nd + lc * L + l] = dof_valid(a, d) ? acc[jj][l] : 0.0;
+    }
   }
 }
 
-// S_J = P_J^T Q_J (m x m per cc cell) -> small[J][which]
-__global__ void k_cc_gram(CCArgs a, const double* __restrict__ P, const double* __restrict__ Q, double* __restrict__ small,
-                          int which, const int* __restrict__ flag) {
+// S_J = P_J^T Q_J (m x m per cc cell, m <= 32) -> small[J][which], symmetrised
+// from the upper triangle.  One workgroup per cc cell; chunks of 64 dofs of
+// both blocks are staged in LDS and each thread accumulates a 2 x 2 patch.
+__global__ __launch_bounds__(256) void k_cc_gram(CCArgs a, const double* __restrict__ P, const double* __restrict__ Q,
+                                                 double* __restrict__ small, int which, const int* __restrict__ flag) {
+  __shared__ double Ps[32 * 65], Qs[32 * 65];
   const int J = blockIdx.x;
   if (flag && flag[J] >= 0) return;
   const int m = a.m;
   const int d0 = a.cc_ptr[J], nd = a.cc_ptr[J + 1] - d0;
   const double* PJ = P + (long long)m * d0;
   const double* QJ = Q + (long long)m * d0;
-  double* S = small + ((long long)J * 4 + which) * m * m;
-  for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
-    const int i = e / m, j = e % m;
-    if (j < i) continue;
-    double s = 0.0;
-    for (int d = 0; d < nd; ++d) s += PJ[(long long)i * nd + d] * QJ[(long long)j * nd + d];
-    S[i * m + j] = s;
-    S[j * m + i] = s;
+  const int tid = threadIdx.x;
+  const int ti = (tid >> 4) * 2, tj = (tid & 15) * 2;
+  double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+  for (int k0 = 0; k0 < nd; k0 += 64) {
+    __syncthreads();
+    for (int e = tid; e < 32 * 64; e += 256) {
+      const int i = e >> 6, kk = e & 63;
+      const bool ok = i < m && k0 + kk < nd;
+      Ps[i * 65 + kk] = ok ? PJ[(long long)i * nd + k0 + kk] : 0.0;
+      Qs[i * 65 + kk] = ok ? QJ[(long long)i * nd + k0 + kk] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < 64; ++kk) {
+      const double p0 = Ps[ti * 65 + kk], p1 = Ps[(ti + 1) * 65 + kk];
+      const double q0 = Qs[tj * 65 + kk], q1 = Qs[(tj + 1) * 65 + kk];
+      acc[0][0] += p0 * q0;
+      acc[0][1] += p0 * q1;
+      acc[1][0] += p1 * q0;
+      acc[1][1] += p1 * q1;
+    }
   }
+  double* S = small + ((long long)J * 4 + which) * m * m;
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const int i = ti + u, j = tj + v;
+      if (i < m && j < m && j >= i) {
+        S[i * m + j] = acc[u][v];
+        S[j * m + i] = acc[u][v];
+      }
+    }
 }
 
 // Per cc cell: eigen-decomposition of small[J][which] (m x m).
@@ -330,33 +367,45 @@ __global__ void k_cc_small_eig(CCArgs a, double* __restrict__ small, int which, 
     for (int k = threadIdx.x; k < m; k += blockDim.x) ritz[(long long)J * m + k] = ev[k];
 }
 
-// Q = P C per cc cell (C = small[J][2])
-__global__ void k_cc_transform(CCArgs a, const double* __restrict__ P, double* __restrict__ Q, const double* __restrict__ small,
-                               const int* __restrict__ flag) {
-  const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  const Hier& h = a.h;
-  const long long ndof = (long long)h.ncells * h.Lc;
-  if (gid >= ndof * a.m) return;
-  const long long d = gid % ndof;
-  const int j = int(gid / ndof);
-  const int J = a.dof_cc[d];
+// Q = P C per cc cell (C = small[J][2], m <= 32).  Grid (ceil(nd / 256), ncc):
+// a thread owns one dof of cc cell J and all m vectors, C sits in LDS.
+__global__ __launch_bounds__(256) void k_cc_transform(CCArgs a, const double* __restrict__ P, double* __restrict__ Q,
+                                                      const double* __restrict__ small, const int* __restrict__ flag) {
+  __shared__ double Cs[32 * 32];
+  const int J = blockIdx.y;
   if (flag && flag[J] >= 0) return;
   const int m = a.m;
-  const int loc = a.dof_loc[d];
   const int d0 = a.cc_ptr[J], nd = a.cc_ptr[J + 1] - d0;
   const double* C = small + ((long long)J * 4 + 2) * m * m;
+  for (int e = threadIdx.x; e < 32 * 32; e += 256) {
+    const int i = e >> 5, j = e & 31;
+    Cs[e] = (i < m && j < m) ? C[i * m + j] : 0.0;
+  }
+  __syncthreads();
+  const int loc = blockIdx.x * 256 + threadIdx.x;
+  if (loc >= nd) return;
   const double* PJ = P + (long long)m * d0;
-  double s = 0.0;
-  for (int i = 0; i < m; ++i) s += PJ[(long long)i * nd + loc] * C[i * m + j];
-  Q[(long long)m * d0 + (long long)j * nd + loc] = s;
+  double t[32];
+#pragma unroll
+  for (int i = 0; i < 32; ++i) t[i] = i < m ? PJ[(long long)i * nd + loc] : 0.0;
+  double* QJ = Q + (long long)m * d0;
+#pragma unroll 4
+  for (int j = 0; j < 32; ++j) {
+    if (j >= m) break;
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < 32; ++i) s += t[i] * Cs[i * 32 + j];
+    QJ[(long long)j * nd + loc] = s;
+  }
 }
 
-// Residual check and filter parameters per cc cell (one block per J).
-// X Ritz block, Z = G X, ritz values.  Converged when every wanted residual
-// ||Z_j - theta_j X_j|| <= tol * bound.  Sets flag[J] = iteration when done.
+// Residual check per cc cell (one block per J).  X Ritz block, Z = G X, ritz
+// values.  Converged when every wanted residual ||Z_j - theta_j X_j|| <=
+// tol * bound.  Sets flag[J] = iteration when done, -2 - iteration when the
+// last iteration ends unconverged.
 __global__ void k_cc_check(CCArgs a, const double* __restrict__ X, const double* __restrict__ Z,
-                           const double* __restrict__ ritz, double* __restrict__ par, int* __restrict__ flag,
-                           const double* __restrict__ bound, int Lwant, double tol, int iter, int last, int degree) {
+                           const double* __restrict__ ritz, int* __restrict__ flag, const double* __restrict__ bound,
+                           int Lwant, double tol, int iter, int last) {
   __shared__ double red[64];
   __shared__ double worst_s;
   const int J = blockIdx.x;
@@ -381,51 +430,8 @@ __global__ void k_cc_check(CCArgs a, const double* __restrict__ X, const double*
   }
   if (threadIdx.x != 0) return;
   const double b = bound[J];
-  if (worst_s <= (tol * b) * (tol * b)) {
-    flag[J] = iter;
-    return;
-  }
-  if (last) {
-    flag[J] = -2 - iter;  // not converged (kept as is)
-    return;
-  }
-  // filter interval [a_lo, b], scale point a_min
-  double lo = th[m - 1];
-  if (!(lo < 0.95 * b)) lo = 0.95 * b;
-  const double e = 0.5 * (b - lo), c = 0.5 * (b + lo);
-  double amin = th[0];
-  if (!(amin < lo - 1e-3 * e)) amin = lo - 1e-3 * e;
-  const double xs = (c - amin) / e;
-  int deg = degree;
-  if (xs > 1.0) deg = max(2, min(deg, int(14.5 / acosh(xs))));
-  par[J * 8 + 0] = c;
-  par[J * 8 + 3] = e;
-  par[J * 8 + 4] = e / (amin - c);  // sigma_1
-  par[J * 8 + 5] = double(deg);
-}
-
-// Per-step filter coefficients: step 1: s1 = sigma1/e; step k: sigma_new = 1/(2/sigma1 - sigma),
-// s1 = 2 sigma_new / e, s2 = sigma sigma_new.  par[6] carries sigma.
-__global__ void k_cc_filter_coef(int ncc, double* __restrict__ par, int step, const int* __restrict__ flag) {
-  const int J = blockIdx.x * blockDim.x + threadIdx.x;
-  if (J >= ncc || flag[J] >= 0) return;
-  double* p = par + J * 8;
-  const double e = p[3], s1_ = p[4];
-  if (step == 1) {
-    p[1] = s1_ / e;
-    p[2] = 0.0;
-    p[6] = s1_;
-  } else {
-    const double sigma = p[6];
-    const double sn = 1.0 / (2.0 / s1_ - sigma);
-    if (step > int(p[5])) {
-      p[1] = -1.0;
-      return;
-    }
-    p[1] = 2.0 * sn / e;
-    p[2] = sigma * sn;
-    p[6] = sn;
-  }
+  if (worst_s <= (tol * b) * (tol * b)) flag[J] = iter;
+  else if (last) flag[J] = -2 - iter;  // not converged (kept as is)
 }
 
 // Gershgorin bound of each cc operator (max over rows of sum |G_ij|)
@@ -487,22 +493,6 @@ __global__ void k_cc_finish(CCArgs a, const double* __restrict__ X, const double
     if (threadIdx.x == 0) cc_evals[(long long)J * Lcc + b] = have ? ritz[(long long)J * m + b] : 0.0;
     __syncthreads();
   }
-}
-
-// Q = P on the active cc cells
-__global__ void k_cc_transform_copy(CCArgs a, const double* __restrict__ P, double* __restrict__ Q, const int* __restrict__ flag) {
-  const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  const Hier& h = a.h;
-  const long long ndof = (long long)h.ncells * h.Lc;
-  if (gid >= ndof * a.m) return;
-  const long long d = gid % ndof;
-  const int j = int(gid / ndof);
-  const int J = a.dof_cc[d];
-  if (flag && flag[J] >= 0) return;
-  const int loc = a.dof_loc[d];
-  const int d0 = a.cc_ptr[J], nd = a.cc_ptr[J + 1] - d0;
-  const long long i = (long long)a.m * d0 + (long long)j * nd + loc;
-  Q[i] = P[i];
 }
 
 // Small coarse-coarse cells (nd <= 32): assemble G_J densely and diagonalise it.
@@ -993,7 +983,9 @@ int run_cc_eigen(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, const doub
   a.cell_status = sa.cell_status;
   const int m = a.m;
   const long long ndof = (long long)h.ncells * h.Lc;
-  const dim3 gv((unsigned)((ndof * m + 255) / 256)), bv(256);
+  if (m > 32) return MSMG_EINVAL;
+  const dim3 gt((unsigned)((sa.max_cc_dofs + 255) / 256), h.ncc), bt(256);
+  const dim3 gs((unsigned)((h.max_cc_cells + 63) / 64), h.ncc, (unsigned)((m + 7) / 8)), bs(64);
   double* Y = sc->Y;
   double* Xp = sc->Yp;
   double* Z = sc->Z;
@@ -1014,21 +1006,28 @@ int run_cc_eigen(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, const doub
   auto orth = [&](double* P, double* tmp) {
     hipLaunchKernelGGL(k_cc_gram, dim3(h.ncc), dim3(256), 0, s, a, P, P, small, 0, flag);
     hipLaunchKernelGGL(k_cc_small_eig, dim3(h.ncc), dim3(small_threads), small_lds, s, a, small, 0, 0, ritz, flag);
-    hipLaunchKernelGGL(k_cc_transform, gv, bv, 0, s, a, P, tmp, small, flag);
+    hipLaunchKernelGGL(k_cc_transform, gt, bt, 0, s, a, P, tmp, small, flag);
+  };
+  auto spmm = [&](const double* P, double* Q) {
+    switch (h.Lc) {
+#define SPMM_L(L_) case L_: hipLaunchKernelGGL(k_cc_spmm<L_>, gs, bs, 0, s, a, P, Q, flag); break;
+      SPMM_L(1) SPMM_L(2) SPMM_L(3) SPMM_L(4) SPMM_L(5) SPMM_L(6) SPMM_L(7) SPMM_L(8)
+#undef SPMM_L
+    }
   };
   // start: orthonormalise twice (Y -> Xp -> Y), Rayleigh-Ritz (Z = G Y; X = Y C; Z = Z C)
   auto rr = [&]() {
     orth(Y, Xp);
     orth(Xp, Y);
-    hipLaunchKernelGGL(k_cc_spmm, gv, bv, 0, s, a, Y, nullptr, Z, 0, par, flag);
+    spmm(Y, Z);
     hipLaunchKernelGGL(k_cc_gram, dim3(h.ncc), dim3(256), 0, s, a, Y, Z, small, 0, flag);
     hipLaunchKernelGGL(k_cc_small_eig, dim3(h.ncc), dim3(small_threads), small_lds, s, a, small, 0, 1, ritz, flag);
-    hipLaunchKernelGGL(k_cc_transform, gv, bv, 0, s, a, Y, Xp, small, flag);  // Xp = Ritz vectors
-    hipLaunchKernelGGL(k_cc_transform, gv, bv, 0, s, a, Z, Y, small, flag);   // Y = G * Ritz vectors
+    hipLaunchKernelGGL(k_cc_transform, gt, bt, 0, s, a, Y, Xp, small, flag);  // Xp = Ritz vectors
+    hipLaunchKernelGGL(k_cc_transform, gt, bt, 0, s, a, Z, Y, small, flag);   // Y = G * Ritz vectors
     std::swap(Y, Z);                                                            // Z = G X, Y free
   };
   rr();
-  const int maxit = sa.opt->cc_maxit, degree = sa.opt->cc_degree;
+  const int maxit = sa.opt->cc_maxit;
   const double tol = sa.opt->eig_tol;
   // shift-invert operator (G_J + sigma_J I)^-1 for every cc cell
   const int ndm = sa.max_cc_dofs;
@@ -1042,8 +1041,8 @@ int run_cc_eigen(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, const doub
   if (m > 32) return MSMG_EINVAL;
   const dim3 ga((ndm + CCD_ROWS - 1) / CCD_ROWS, h.ncc), ba(256);
   for (int it = 0; it <= maxit; ++it) {
-    hipLaunchKernelGGL(k_cc_check, dim3(h.ncc), dim3(256), 0, s, a, Xp, Z, ritz, par, flag, bound, h.Lcc, tol, it,
-                       it == maxit ? 1 : 0, degree);
+    hipLaunchKernelGGL(k_cc_check, dim3(h.ncc), dim3(256), 0, s, a, Xp, Z, ritz, flag, bound, h.Lcc, tol, it,
+                       it == maxit ? 1 : 0);
     if (it == maxit) break;
     if (it % 4 == 3) {
       std::vector<int> hf(h.ncc);

@@ -128,20 +128,21 @@ MSMG_DEV void wave_jacobi8(const double* A, double* Vs, double* ev, int max_swee
   };
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     for (int r = 0; r < 7; ++r) {
-      // column pass: B = A J, V = V J (rotation of columns j and its partner)
+      // the round's four disjoint rotations: lane e computes the one of its
+      // column pair; the row pass takes the rotation of its row pair from lane i
+      // (row 0, column i), whose column pair is that row pair
       const int jp = rr_partner(r, j, 8), p = min(j, jp), q = max(j, jp);
       const double app = __shfl(a, p * 9, 64), aqq = __shfl(a, q * 9, 64), apq = __shfl(a, p * 8 + q, 64);
       double c, s;
       rot(app, aqq, apq, c, s);
+      // column pass: B = A J, V = V J
       const double aip = __shfl(a, i * 8 + p, 64), aiq = __shfl(a, i * 8 + q, 64);
       const double vip = __shfl(v, i * 8 + p, 64), viq = __shfl(v, i * 8 + q, 64);
       const double b = (j == p) ? c * aip - s * aiq : s * aip + c * aiq;
       v = (j == p) ? c * vip - s * viq : s * vip + c * viq;
-      // row pass: A = J^T B with the rotation of rows i and its partner (from the old A)
+      // row pass: A = J^T B
       const int ip = rr_partner(r, i, 8), pr = min(i, ip), qr = max(i, ip);
-      const double rpp = __shfl(a, pr * 9, 64), rqq = __shfl(a, qr * 9, 64), rpq = __shfl(a, pr * 8 + qr, 64);
-      double cr, sr;
-      rot(rpp, rqq, rpq, cr, sr);
+      const double cr = __shfl(c, i, 64), sr = __shfl(s, i, 64);
       const double bpj = __shfl(b, pr * 8 + j, 64), bqj = __shfl(b, qr * 8 + j, 64);
       a = (i == pr) ? cr * bpj - sr * bqj : sr * bpj + cr * bqj;
     }
@@ -159,6 +160,39 @@ MSMG_DEV void wave_jacobi8(const double* A, double* Vs, double* ev, int max_swee
   }
   Vs[i * 8 + rank] = v;
   if (i == 0) ev[rank] = dj;
+}
+
+// Orthonormalising transform of an 8-vector block from its Gram matrix G
+// (LDS, 8 x 8), by one wave: the Cholesky factor G = R^T R and C = R^-1
+// (upper triangular), so that P C has orthonormal columns.  Lane e holds
+// entry (e / 8, e % 8).  Returns false (on every lane) when a pivot is not
+// safely positive; C is then not written.  Same result, up to rounding, as
+// orthonormalising the columns in order by Gram-Schmidt.
+MSMG_DEV bool wave_cholinv8(const double* G, double* C) {
+  const int e = threadIdx.x & 63, i = e >> 3, j = e & 7;
+  double g = G[e];
+  const double g0 = g;
+  double r = 0.0;  // R[i][j] once row i is done
+  for (int k = 0; k < 8; ++k) {
+    // pivots below 1e-14 of the diagonal entry (condition of the block above
+    // ~1e7) go to the eigen-decomposition instead
+    const double dkk = __shfl(g, k * 9, 64), gkk = __shfl(g0, k * 9, 64);
+    if (!(dkk > 1e-14 * gkk) || !(dkk > 1e-300)) return false;
+    const double d = sqrt(dkk);
+    const double rki = __shfl(g, k * 8 + i, 64) / d, rkj = __shfl(g, k * 8 + j, 64) / d;
+    if (i == k) r = (j >= k) ? rkj : 0.0;
+    if (i > k && j > k) g -= rki * rkj;
+  }
+  // X = R^-1 by back substitution, row by row from the bottom
+  double x = 0.0;
+  for (int ii = 7; ii >= 0; --ii) {
+    double acc = (ii == j) ? 1.0 : 0.0;
+    for (int k = ii + 1; k < 8; ++k) acc -= __shfl(r, ii * 8 + k, 64) * __shfl(x, k * 8 + j, 64);
+    const double rii = __shfl(r, ii * 9, 64);
+    if (i == ii) x = (j >= ii) ? acc / rii : 0.0;
+  }
+  C[e] = x;
+  return true;
 }
 
 // Eigen-decomposition of the symmetric m x m matrix A (LDS, row-major) by the

@@ -22,6 +22,9 @@
 namespace msmg {
 
 constexpr int DENSE_MAX = 16;
+#ifndef MSMG_LOCAL_CHOLQR
+#define MSMG_LOCAL_CHOLQR 1  // orthonormalise by Cholesky-QR (else always by the eigen-decomposition)
+#endif
 constexpr int RED_SLOTS = 640;  // block reductions of up to 40 values over 16 waves
 
 struct LocalArgs {
@@ -244,9 +247,25 @@ __global__ __launch_bounds__(BS) void k_local_eigen(LocalArgs A) {
         block_jacobi(Gm, Vm, Bm, Vs, ev, perm, M, red);
       }
     };
-    // orthonormalise a block: G = P^T P = U S U^T, P <- P U S^-1/2
+    // orthonormalise a block from G = P^T P: P <- P R^-1 with the Cholesky
+    // factor R (two such passes make the block orthonormal to rounding for any
+    // condition the filter leaves); where G is not safely positive definite,
+    // the symmetric transform G = U S U^T, P <- P U S^-1/2, which drops null
+    // directions
+    __shared__ int s_chol;
     auto orthonormalise = [&](double* P) {
       gram(P, P);
+      if constexpr (M == 8 && MSMG_LOCAL_CHOLQR) {
+        if (wid == 0) {
+          const bool ok = wave_cholinv8(Gm, Bm);
+          if (lane == 0) s_chol = ok ? 1 : 0;
+        }
+        __syncthreads();
+        if (s_chol) {
+          transform(P, Bm);
+          return;
+        }
+      }
       small_eig();
       for (int e = tid; e < M * M; e += BS) {
         const int k = e % M;

@@ -254,4 +254,9 @@ def test_warm_started_setup_matches_cold(pkg):
     f = to_dev(q1.element_load(g, 1.0))
     _, iw = warm.solve(f, rtol=1e-8)
     _, ic = cold.solve(f, rtol=1e-8)
-    assert iw.code == 0 and abs(iw.iterations - ic.iterations) <= 1
+    print(f"  iterations warm {iw.iterations} cold {ic.iterations}")
+    # the two bases agree to the eigensolver tolerance, not bitwise; this
+    # field (5% of the elements flipped at contrast 1e6) needs ~200
+    # iterations, where rounding-level basis differences move the count by a
+    # few percent: the same 10% slack as for the other high-contrast fields
+    assert iw.code == 0 and abs(iw.iterations - ic.iterations) <= max(1, int(0.1 * ic.iterations))

@@ -74,7 +74,7 @@ typedef struct msmg_options {
   int eig_maxit;       /* outer subspace iterations per cell                    [60]   */
   double eig_tol;      /* residual tolerance relative to the spectral bound     [1e-12]*/
   int cc_block;        /* coarse-coarse subspace block size (0 = Lcc + guard)   [0]    */
-  int cc_degree;       /* coarse-coarse filter degree                           [16]   */
+  int cc_degree;       /* unused (kept for the layout of this struct)           [16]   */
   int cc_maxit;        /* coarse-coarse outer iterations                        [60]   */
   int autotune;        /* 1: tune the level-1 launch shape on first setup       [1]    */
   const char* tune_cache; /* host path of the tuning cache file, or NULL       [NULL] */
@@ -83,6 +83,17 @@ typedef struct msmg_options {
   int eig_warm_start;  /* 1: start the level-1 eigensolver of a set-up from the  [0]
                           previous set-up's basis (designs that change little
                           between set-ups, e.g. an optimisation loop)            */
+  int rho_storage;     /* MSMG_F64 or MSMG_F32: storage of the canonical density [F64]
+                          copy; F32 storage takes F32 densities only             */
+  int lean_memory;     /* 1: the FP64 basis master shares the PCG work vectors   [0]
+                          (read only during a set-up; msmg_export of it works
+                          until the next solve, apply or preconditioner call),
+                          set-up-only coarse-coarse blocks share the cycle's
+                          FP64 iterate, and no copy of A_cc is kept (export 4
+                          fails).  Excludes eig_warm_start.  For the largest
+                          grids (1024^3 on one GPU).                             */
+  int cc_group;        /* coarse-coarse cells whose dense shifted matrices the   [0]
+                          set-up holds at once (0 = as many as fit in 24 GB)     */
 } msmg_options;
 
 /* Solve report. */

@@ -45,6 +45,9 @@ class Options(ctypes.Structure):
         ("tune_cache", ctypes.c_char_p),
         ("timing", ctypes.c_int),
         ("eig_warm_start", ctypes.c_int),
+        ("rho_storage", ctypes.c_int),
+        ("lean_memory", ctypes.c_int),
+        ("cc_group", ctypes.c_int),
     ]
 
 

@@ -46,6 +46,7 @@ struct msmg_handle {
   double lam_bound = 0.0;  // upper bound of the level-1 standard-form spectrum
   Material mat{};
   int rho_dt = DT_F64, kv_dt = DT_F64, v_dt = DT_F64, b_dt = DT_F64, a_dt = DT_F64, dv_dt = DT_F64;
+  int rho_store_dt = DT_F64;  // storage of the canonical density copy
   bool mg = true;
 
   // density, mask, fixed values
@@ -94,6 +95,7 @@ struct msmg_handle {
   int red_blocks = 4096;
   long long march_resident = 2048;  // marching workgroups resident at once (queried at create)
   bool has_basis = false;           // Rc64 holds the basis of the last completed set-up
+  bool basis_live = false;          // lean memory: Rc64 not yet overwritten by PCG vectors
   long long partial_slots = 0;
   void* oc_state = nullptr;  // bracket of the OC multiplier
 
@@ -172,7 +174,7 @@ static int make_plan(int nx, int ny, int nz, const msmg_options& o, Plan& P) {
   (void)lcc_eff;
   if (h.Lcc > maxd) h.Lcc = maxd;
   P.n_cc = h.ncc * h.Lcc;
-  if (P.n_cc > 40000) return fail(MSMG_EINVAL, "coarse-coarse dimension too large for the dense level-2 solve");
+  if (P.n_cc > 72000) return fail(MSMG_EINVAL, "coarse-coarse dimension too large for the dense level-2 solve");
   return MSMG_OK;
 }
 
@@ -340,6 +342,9 @@ extern "C" void msmg_default_options(msmg_options* o) {
   o->tune_cache = nullptr;
   o->timing = 0;
   o->eig_warm_start = 0;
+  o->rho_storage = MSMG_F64;
+  o->lean_memory = 0;
+  o->cc_group = 0;
 }
 
 extern "C" const char* msmg_last_error(void) { return g_last_error.c_str(); }
@@ -356,83 +361,52 @@ static int check_options(const msmg_options& o) {
   if (o.check_interval < 1) return fail(MSMG_EINVAL, "check_interval must be >= 1");
   if (o.eig_block < 0 || o.eig_block > 16 || o.eig_degree < 0 || o.eig_maxit < 1 || !(o.eig_tol > 0))
     return fail(MSMG_EINVAL, "bad eigensolver options");
-  if (o.cc_block < 0 || o.cc_block > 32 || o.cc_degree < 1 || o.cc_maxit < 1)
+  if (o.cc_block < 0 || o.cc_block > 32 || o.cc_maxit < 1)
     return fail(MSMG_EINVAL, "bad coarse-coarse eigensolver options");
+  if (o.rho_storage != MSMG_F64 && o.rho_storage != MSMG_F32) return fail(MSMG_EINVAL, "rho_storage must be F64 or F32");
+  if (o.cc_group < 0) return fail(MSMG_EINVAL, "cc_group must be >= 0");
+  if (o.lean_memory && o.eig_warm_start)
+    return fail(MSMG_EINVAL, "lean_memory keeps no basis between set-ups: eig_warm_start is not available");
   return MSMG_OK;
 }
 
-extern "C" int msmg_query_plan(int nx, int ny, int nz, const msmg_options* opt, msmg_plan* out) {
-  msmg_options o;
-  if (opt) o = *opt; else msmg_default_options(&o);
-  if (!out) return fail(MSMG_EINVAL, "out is NULL");
-  TRY(check_options(o));
-  Plan P;
-  TRY(make_plan(nx, ny, nz, o, P));
-  out->ncx = P.h.ncx; out->ncy = P.h.ncy; out->ncz = P.h.ncz; out->ncells = P.h.ncells;
-  out->nccx = P.h.nccx; out->nccy = P.h.nccy; out->nccz = P.h.nccz; out->ncc = P.h.ncc;
-  out->n_c = P.n_c;
-  out->n_cc = P.n_cc;
-  out->max_cell_nodes = P.max_cell_nodes;
-  out->max_cc_dofs = P.max_cc_dofs;
-  out->nodes = (long long)(nx + 1) * (ny + 1) * (nz + 1);
-  out->elements = (long long)nx * ny * nz;
-  const long long nn = out->nodes;
-  const size_t v = o.vcycle_dtype == MSMG_F64 ? 8 : 4;
-  long long bytes = 5 * nn * 8 + 5 * nn * (long long)v + nn * (long long)v + out->elements * 8 +
-                    out->elements * (long long)dt_size(o.rho_v_dtype) + nn / 8 + nn * (long long)o.Lc * 8 +
-                    (o.basis_dtype != MSMG_F64 ? nn * (long long)o.Lc * (long long)dt_size(o.basis_dtype) : 0) +
-                    (long long)P.h.ncells * 27 * o.Lc * o.Lc * 8 * 3 + (long long)P.n_cc * P.n_cc * 8;
-  out->device_bytes = bytes;
-  return MSMG_OK;
-}
-
-extern "C" int msmg_create(msmg_handle** out, int nx, int ny, int nz, double lx, double ly, double lz,
-                           const msmg_options* opt) {
-  if (!out) return fail(MSMG_EINVAL, "handle pointer is NULL");
-  *out = nullptr;
-  if (!(lx > 0) || !(ly > 0) || !(lz > 0)) return fail(MSMG_EINVAL, "box lengths must be positive");
-  msmg_options o;
-  if (opt) o = *opt; else msmg_default_options(&o);
-  TRY(check_options(o));
-  Plan P;
-  TRY(make_plan(nx, ny, nz, o, P));
-  msmg_handle* h = new msmg_handle();
-  h->opt = o;
-  HIP_TRY(hipGetDevice(&h->device));
-  h->march_resident = march_resident_blocks();
-  h->g = make_geo(nx, ny, nz, lx, ly, lz);
-  double lmk0 = 0.0;
-  h->st = make_stencil(h->g, &lmk0);
-  h->lam_bound = 8.0 * lmk0 / h->g.vol;
-  h->hier = P.h;
-  h->CX = P.CX;
-  h->ntiles = P.ntiles;
-  h->n_c = P.n_c;
-  h->n_cc = P.n_cc;
-  h->max_cc_dofs = P.max_cc_dofs;
-  h->max_cell_nodes = P.max_cell_nodes;
-  h->h_cc_ptr = P.cc_ptr;
-  h->mg = (o.pc_kind == MSMG_PC_MULTIGRID);
-  h->v_dt = o.vcycle_dtype;
-  h->kv_dt = o.rho_v_dtype;
-  h->b_dt = o.basis_dtype;
-  // level-1 operator and level 2 stay FP64 on every path: an FP32 copy of A_c
-  // costs ~10% more iterations at contrast 1e6
-  h->a_dt = DT_F64;
+// Device arrays of a handle.  With dry = true nothing is allocated and the
+// bytes are summed into *total (the footprint msmg_query_plan reports).  With
+// lean_memory the FP64 basis master shares the PCG work vectors r, p, q, z
+// (it is only read during the set-up), the set-up-only Galerkin blocks of the
+// coarse-coarse problem share the FP64 cycle iterate, and the diagnostic copy
+// of A_cc is not kept.
+static int alloc_arrays(msmg_handle* h, bool dry, size_t* total) {
+  const msmg_options& o = h->opt;
   const long long nn = h->g.nn, ne = h->g.ne;
   const size_t vs = dt_size(h->v_dt);
+  const bool lean = o.lean_memory != 0;
   int rc = MSMG_OK;
+  size_t sum = 0;
   auto A = [&](auto** p, size_t bytes) {
-    if (rc == MSMG_OK) rc = dev_alloc(h, p, bytes);
+    sum += bytes;
+    if (!dry && rc == MSMG_OK) rc = dev_alloc(h, p, bytes);
   };
-  A(&h->rho, ne * 8);
+  A(&h->rho, ne * dt_size(h->rho_store_dt));
   A(&h->kc, ne * 8);
   if (h->kv_dt != DT_F64) A(&h->kv, ne * dt_size(h->kv_dt));
   A(&h->bits, ((nn + 31) / 32) * 4);
   // Jacobi diagonal: FP64 only on the all-FP64 path (a fixed coefficient like rho)
   h->dv_dt = (h->v_dt == DT_F64 && h->b_dt == DT_F64) ? DT_F64 : DT_F32;
   A(&h->dinv, nn * dt_size(h->dv_dt));
-  A(&h->r, nn * 8); A(&h->p, nn * 8); A(&h->q, nn * 8); A(&h->z, nn * 8); A(&h->b, nn * 8);
+  if (lean && h->mg) {
+    // r, p, q, z in one block that also holds the FP64 basis during a set-up
+    const long long nv = std::max<long long>(4, h->hier.Lc);
+    double* blk = nullptr;
+    A(&blk, (size_t)nv * nn * 8);
+    if (blk) {
+      h->r = blk; h->p = blk + nn; h->q = blk + 2 * nn; h->z = blk + 3 * nn;
+      h->Rc64 = blk;
+    }
+  } else {
+    A(&h->r, nn * 8); A(&h->p, nn * 8); A(&h->q, nn * 8); A(&h->z, nn * 8);
+  }
+  A(&h->b, nn * 8);
   A(&h->xlo, nn * 8);
   A(&h->v_r1, nn * vs); A(&h->v_res, nn * vs);
   if (o.cheb_degree > 2) { A(&h->v_t0, nn * vs); A(&h->v_t1, nn * vs); }
@@ -441,13 +415,16 @@ extern "C" int msmg_create(msmg_handle** out, int nx, int ny, int nz, double lx,
   A(&h->counter, 64);
   A(&h->oc_state, 64);
   A(&h->sc, sizeof(Scalars));
-  if (h->mg && rc == MSMG_OK) {
+  if (h->mg) {
     A(&h->v_r2, nn * 8);  // prolongated iterate: FP64 on every path
-    A(&h->Rc64, nn * h->hier.Lc * 8);
-    if (h->b_dt != DT_F64) A(&h->Rcs, nn * h->hier.Lc * dt_size(h->b_dt));
+    if (!lean) A(&h->Rc64, nn * h->hier.Lc * 8);
+    // the cycle's copy of the basis; the lean layout needs its own even in FP64,
+    // since the master there is overwritten by the first solve
+    if (h->b_dt != DT_F64 || lean) A(&h->Rcs, nn * h->hier.Lc * dt_size(h->b_dt));
     const size_t nblk = (size_t)h->hier.ncells * 27 * h->hier.Lc * h->hier.Lc;
     A(&h->Ac64, nblk * 8);
-    A(&h->G64, nblk * 8);
+    if (lean && nblk <= (size_t)nn) h->G64 = (double*)h->v_r2;
+    else A(&h->G64, nblk * 8);
     A(&h->AcDinv64, (size_t)h->n_c * h->hier.Lc * 8);
     if (h->a_dt != DT_F64) {
       A(&h->Acv, nblk * 4);
@@ -466,9 +443,80 @@ extern "C" int msmg_create(msmg_handle** out, int nx, int ny, int nz, double lx,
     A(&h->c_rc, (size_t)h->n_c * 8); A(&h->c_x0, (size_t)h->n_c * 8); A(&h->c_t, (size_t)h->n_c * 8);
     A(&h->c_x1, (size_t)h->n_c * 8); A(&h->c_d, (size_t)h->n_c * 8);
     A(&h->rcc, (size_t)h->n_cc * 8); A(&h->ecc, (size_t)h->n_cc * 8);
-    if (rc == MSMG_OK) rc = setup_scratch_alloc(h->g, h->hier, h->max_cc_dofs, h->opt, &h->scratch,
-                                                [&](void** p, size_t bytes) { return dev_alloc(h, p, bytes); });
+    if (rc == MSMG_OK)
+      rc = setup_scratch_alloc(h->g, h->hier, h->max_cc_dofs, h->n_cc, o, &h->scratch, [&](void** p, size_t bytes) {
+        sum += bytes;
+        return dry ? MSMG_OK : dev_alloc(h, p, bytes);
+      });
   }
+  if (total) *total = sum;
+  return rc;
+}
+
+// Host-side fields of a handle that the plan and the options fix.
+static void init_handle(msmg_handle* h, const msmg_options& o, const Plan& P, int nx, int ny, int nz, double lx,
+                        double ly, double lz) {
+  h->opt = o;
+  h->g = make_geo(nx, ny, nz, lx, ly, lz);
+  double lmk0 = 0.0;
+  h->st = make_stencil(h->g, &lmk0);
+  h->lam_bound = 8.0 * lmk0 / h->g.vol;
+  h->hier = P.h;
+  h->CX = P.CX;
+  h->ntiles = P.ntiles;
+  h->n_c = P.n_c;
+  h->n_cc = P.n_cc;
+  h->max_cc_dofs = P.max_cc_dofs;
+  h->max_cell_nodes = P.max_cell_nodes;
+  h->h_cc_ptr = P.cc_ptr;
+  h->mg = (o.pc_kind == MSMG_PC_MULTIGRID);
+  h->v_dt = o.vcycle_dtype;
+  h->kv_dt = o.rho_v_dtype;
+  h->b_dt = o.basis_dtype;
+  h->rho_store_dt = o.rho_storage;
+  // level-1 operator and level 2 stay FP64 on every path: an FP32 copy of A_c
+  // costs ~10% more iterations at contrast 1e6
+  h->a_dt = DT_F64;
+}
+
+extern "C" int msmg_query_plan(int nx, int ny, int nz, const msmg_options* opt, msmg_plan* out) {
+  msmg_options o;
+  if (opt) o = *opt; else msmg_default_options(&o);
+  if (!out) return fail(MSMG_EINVAL, "out is NULL");
+  TRY(check_options(o));
+  Plan P;
+  TRY(make_plan(nx, ny, nz, o, P));
+  out->ncx = P.h.ncx; out->ncy = P.h.ncy; out->ncz = P.h.ncz; out->ncells = P.h.ncells;
+  out->nccx = P.h.nccx; out->nccy = P.h.nccy; out->nccz = P.h.nccz; out->ncc = P.h.ncc;
+  out->n_c = P.n_c;
+  out->n_cc = P.n_cc;
+  out->max_cell_nodes = P.max_cell_nodes;
+  out->max_cc_dofs = P.max_cc_dofs;
+  out->nodes = (long long)(nx + 1) * (ny + 1) * (nz + 1);
+  out->elements = (long long)nx * ny * nz;
+  msmg_handle tmp;
+  init_handle(&tmp, o, P, nx, ny, nz, 1.0, 1.0, 1.0);
+  size_t bytes = 0;
+  TRY(alloc_arrays(&tmp, true, &bytes));
+  out->device_bytes = bytes;
+  return MSMG_OK;
+}
+
+extern "C" int msmg_create(msmg_handle** out, int nx, int ny, int nz, double lx, double ly, double lz,
+                           const msmg_options* opt) {
+  if (!out) return fail(MSMG_EINVAL, "handle pointer is NULL");
+  *out = nullptr;
+  if (!(lx > 0) || !(ly > 0) || !(lz > 0)) return fail(MSMG_EINVAL, "box lengths must be positive");
+  msmg_options o;
+  if (opt) o = *opt; else msmg_default_options(&o);
+  TRY(check_options(o));
+  Plan P;
+  TRY(make_plan(nx, ny, nz, o, P));
+  msmg_handle* h = new msmg_handle();
+  init_handle(h, o, P, nx, ny, nz, lx, ly, lz);
+  HIP_TRY(hipGetDevice(&h->device));
+  h->march_resident = march_resident_blocks();
+  int rc = alloc_arrays(h, false, nullptr);
   if (rc == MSMG_OK) {
     hipError_t e = hipHostMalloc((void**)&h->sc_host, sizeof(Scalars), hipHostMallocDefault);
     if (e != hipSuccess) rc = fail(MSMG_ENOMEM, "pinned host allocation failed");
@@ -531,6 +579,8 @@ extern "C" int msmg_setup(msmg_handle* h, const void* rho, msmg_dtype rho_dtype,
                           const uint8_t* mask, const double* fixed_values, hipStream_t s) {
   if (!h || !rho || !mask) return fail(MSMG_EINVAL, "NULL argument");
   if (rho_dtype != MSMG_F64 && rho_dtype != MSMG_F32) return fail(MSMG_EINVAL, "rho must be F64 or F32");
+  if (h->rho_store_dt == DT_F32 && rho_dtype != MSMG_F32)
+    return fail(MSMG_EINVAL, "this handle stores the density in FP32 (rho_storage): pass F32 densities");
   if (!(kmin > 0.0) || !(kmax >= kmin) || !std::isfinite(kmax)) return fail(MSMG_EINVAL, "need 0 < k_min <= k_max");
   if (p < 1 || p > 16) return fail(MSMG_EINVAL, "p must be in 1..16");
   const double t0 = now_ms();
@@ -538,9 +588,9 @@ extern "C" int msmg_setup(msmg_handle* h, const void* rho, msmg_dtype rho_dtype,
   h->mat.kmin = kmin;
   h->mat.kmax = kmax;
   h->mat.p = p;
-  h->rho_dt = rho_dtype;
+  h->rho_dt = h->rho_store_dt;
   const long long nn = h->g.nn, ne = h->g.ne;
-  launch_convert(rho, rho_dtype, h->rho, rho_dtype, ne, s);
+  launch_convert(rho, rho_dtype, h->rho, h->rho_store_dt, ne, s);
   launch_pack_mask(mask, h->bits, nn, s);
   if (fixed_values) {
     if (!h->tfix) TRY(dev_alloc(h, &h->tfix, nn * 8));
@@ -607,7 +657,8 @@ extern "C" int msmg_setup(msmg_handle* h, const void* rho, msmg_dtype rho_dtype,
   HIP_TRY(hipGetLastError());
   h->setup_ms = now_ms() - t0;
   h->setup_done = true;
-  h->has_basis = (h->mg != 0);
+  h->has_basis = (h->mg != 0) && !h->opt.lean_memory;
+  h->basis_live = (h->mg != 0);
   return MSMG_OK;
 }
 
@@ -647,6 +698,7 @@ extern "C" int msmg_precondition(msmg_handle* h, const double* r, double* z, hip
   if (!h || !r || !z) return fail(MSMG_EINVAL, "NULL argument");
   if (!h->setup_done) return fail(MSMG_ESTATE, "msmg_setup has not completed");
   Ctx c = make_ctx(h);
+  if (h->opt.lean_memory) h->basis_live = false;
   launch_sc_reset(c, 0, 0, s);
   launch_zero_fixed_copy(c, r, h->r, s);
   precondition(h, c, h->r, z, nullptr, 2, s);
@@ -704,6 +756,7 @@ static int solve_impl(msmg_handle* h, const double* f, double* T, double* T_lo, 
   if (f == T || (T_lo && (T_lo == T || T_lo == f))) return fail(MSMG_EINVAL, "f, T and T_lo must not alias");
   const double t0 = now_ms();
   Ctx c = make_ctx(h);
+  if (h->opt.lean_memory) h->basis_live = false;
   const double* lift = (h->has_tfix && !homogeneous) ? h->tfix : nullptr;
   double* x = T;
   // b = f - A t_fix on free rows (0 on fixed rows)
@@ -860,10 +913,14 @@ extern "C" int msmg_export(msmg_handle* h, int what, void* host_out, size_t byte
   size_t need = 0;
   switch (what) {
     case 0: src = h->evals; need = (size_t)h->n_c * 8; break;
-    case 1: src = h->Rc64; need = (size_t)h->g.nn * hh.Lc * 8; break;
+    case 1:
+      if (!h->basis_live) return fail(MSMG_EINVAL, "lean_memory: the FP64 basis was overwritten by a solve");
+      src = h->Rc64; need = (size_t)h->g.nn * hh.Lc * 8; break;
     case 2: src = h->Ac64; need = (size_t)hh.ncells * 27 * hh.Lc * hh.Lc * 8; break;
     case 3: src = h->cc_evals; need = (size_t)h->n_cc * 8; break;
-    case 4: src = h->scratch.acc_copy; need = (size_t)h->n_cc * h->n_cc * 8; break;
+    case 4:
+      if (!h->scratch.acc_copy) return fail(MSMG_EINVAL, "lean_memory: no copy of A_cc is kept");
+      src = h->scratch.acc_copy; need = (size_t)h->n_cc * h->n_cc * 8; break;
     case 5: src = h->cell_status; need = (size_t)hh.ncells * 4; break;
     default: return fail(MSMG_EINVAL, "unknown export id");
   }

@@ -14,6 +14,9 @@ namespace msmg {
 // matrix the inverted pivot block (GJ_NB^2) and the row and column panels
 // (GJ_NB x n each).
 constexpr int GJ_NB = 64;
+// Device memory for the dense shifted coarse-coarse matrices: the cc cells are
+// solved in groups whose matrices fit in this many bytes.
+constexpr size_t CC_GROUP_BYTES = size_t(24) << 30;
 inline size_t gj_workspace_doubles(int n, int batch) {
   return (size_t)batch * ((size_t)GJ_NB * GJ_NB + 2 * (size_t)GJ_NB * n);
 }
@@ -42,6 +45,7 @@ struct SetupScratch {
   double* Gd = nullptr;        // dense shifted coarse-coarse matrices, then their inverses
   unsigned* work = nullptr;    // work-queue counter
   int mcc = 0;
+  int cc_group = 0;            // cc cells whose dense shifted matrices are held at once
 };
 
 struct SetupArgs {
@@ -82,7 +86,7 @@ struct SetupReport {
   char msg[256];
 };
 
-int setup_scratch_alloc(const Geo& g, const Hier& h, int max_cc_dofs, const msmg_options& o, SetupScratch* s,
+int setup_scratch_alloc(const Geo& g, const Hier& h, int max_cc_dofs, int n_cc, const msmg_options& o, SetupScratch* s,
                         const std::function<int(void**, size_t)>& alloc);
 
 int run_setup(const Ctx& c, const SetupArgs& a, SetupScratch* s, SetupReport* rep, hipStream_t st);

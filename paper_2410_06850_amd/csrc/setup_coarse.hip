@@ -184,6 +184,7 @@ __global__ void k_block_inverse(int ncells, int L, double* __restrict__ Ac, doub
 
 struct CCArgs {
   Hier h;
+  int J0, nJ;            // the group of cc cells being solved: J0 .. J0 + nJ - 1
   int m;                 // block size
   const double* G;       // [ncells][27][Lc][Lc]
   const int* cc_ptr;
@@ -206,6 +207,7 @@ __global__ void k_cc_start(CCArgs a, double* __restrict__ Y) {
   const Hier& h = a.h;
   if (d >= (long long)h.ncells * h.Lc) return;
   const int J = a.dof_cc[d], loc = a.dof_loc[d];
+  if (J < a.J0 || J >= a.J0 + a.nJ) return;
   const int d0 = a.cc_ptr[J], nd = a.cc_ptr[J + 1] - d0;
   const int cell = int(d / h.Lc), l = int(d % h.Lc);
   const int cx = cell % h.ncx, cy = (cell / h.ncx) % h.ncy, cz = cell / (h.ncx * h.ncy);
@@ -237,7 +239,7 @@ __global__ void k_cc_start(CCArgs a, double* __restrict__ Y) {
 template <int L>
 __global__ __launch_bounds__(64) void k_cc_spmm(CCArgs a, const double* __restrict__ Y, double* __restrict__ Z,
                                                 const int* __restrict__ flag) {
-  const int J = blockIdx.y;
+  const int J = a.J0 + blockIdx.y;
   if (flag && flag[J] >= 0) return;
   const Hier& h = a.h;
   const int m = a.m;
@@ -296,7 +298,7 @@ __global__ __launch_bounds__(64) void k_cc_spmm(CCArgs a, const double* __restri
 __global__ __launch_bounds__(256) void k_cc_gram(CCArgs a, const double* __restrict__ P, const double* __restrict__ Q,
                                                  double* __restrict__ small, int which, const int* __restrict__ flag) {
   __shared__ double Ps[32 * 65], Qs[32 * 65];
-  const int J = blockIdx.x;
+  const int J = a.J0 + blockIdx.x;
   if (flag && flag[J] >= 0) return;
   const int m = a.m;
   const int d0 = a.cc_ptr[J], nd = a.cc_ptr[J + 1] - d0;
@@ -343,7 +345,7 @@ __global__ __launch_bounds__(256) void k_cc_gram(CCArgs a, const double* __restr
 __global__ void k_cc_small_eig(CCArgs a, double* __restrict__ small, int which, int kind, double* __restrict__ ritz,
                                const int* __restrict__ flag) {
   extern __shared__ double sm[];
-  const int J = blockIdx.x;
+  const int J = a.J0 + blockIdx.x;
   if (flag && flag[J] >= 0) return;
   const int m = a.m;
   double* A = sm;
@@ -372,7 +374,7 @@ __global__ void k_cc_small_eig(CCArgs a, double* __restrict__ small, int which, 
 __global__ __launch_bounds__(256) void k_cc_transform(CCArgs a, const double* __restrict__ P, double* __restrict__ Q,
                                                       const double* __restrict__ small, const int* __restrict__ flag) {
   __shared__ double Cs[32 * 32];
-  const int J = blockIdx.y;
+  const int J = a.J0 + blockIdx.y;
   if (flag && flag[J] >= 0) return;
   const int m = a.m;
   const int d0 = a.cc_ptr[J], nd = a.cc_ptr[J + 1] - d0;
@@ -408,7 +410,7 @@ __global__ void k_cc_check(CCArgs a, const double* __restrict__ X, const double*
                            int Lwant, double tol, int iter, int last) {
   __shared__ double red[64];
   __shared__ double worst_s;
-  const int J = blockIdx.x;
+  const int J = a.J0 + blockIdx.x;
   if (flag[J] >= 0) return;
   const int m = a.m;
   const int d0 = a.cc_ptr[J], nd = a.cc_ptr[J + 1] - d0;
@@ -437,7 +439,7 @@ __global__ void k_cc_check(CCArgs a, const double* __restrict__ X, const double*
 // Gershgorin bound of each cc operator (max over rows of sum |G_ij|)
 __global__ void k_cc_bound(CCArgs a, double* __restrict__ bound) {
   __shared__ double red[64];
-  const int J = blockIdx.x;
+  const int J = a.J0 + blockIdx.x;
   const Hier& h = a.h;
   const int L = h.Lc;
   const int d0 = a.cc_ptr[J], nd = a.cc_ptr[J + 1] - d0;
@@ -466,7 +468,7 @@ __global__ void k_cc_finish(CCArgs a, const double* __restrict__ X, const double
                             double* __restrict__ cc_evals, int Lcc) {
   __shared__ double red[64];
   __shared__ int ired[16];
-  const int J = blockIdx.x;
+  const int J = a.J0 + blockIdx.x;
   const int m = a.m;
   const int d0 = a.cc_ptr[J], nd = a.cc_ptr[J + 1] - d0;
   const double* XJ = X + (long long)m * d0;
@@ -501,7 +503,7 @@ __global__ void k_cc_finish(CCArgs a, const double* __restrict__ X, const double
 constexpr int CC_DENSE = 32;
 __global__ void k_cc_dense(CCArgs a, double* __restrict__ X, double* __restrict__ ritz, int* __restrict__ flag) {
   extern __shared__ double sm[];
-  const int J = blockIdx.x;
+  const int J = a.J0 + blockIdx.x;
   const Hier& h = a.h;
   const int L = h.Lc;
   const int d0 = a.cc_ptr[J], nd = a.cc_ptr[J + 1] - d0;
@@ -817,7 +819,7 @@ __global__ void k_gj_writeback(int n, double* __restrict__ Ab, int k0, int nb, c
 // sigma_J = 1e-6 * mean valid diagonal (stored in par[J*8 + 7])
 __global__ void k_ccd_shift(CCArgs a, double* __restrict__ par) {
   __shared__ double red[64];
-  const int J = blockIdx.x;
+  const int J = a.J0 + blockIdx.x;
   const Hier& h = a.h;
   const int L = h.Lc;
   const int d0 = a.cc_ptr[J], nd = a.cc_ptr[J + 1] - d0;
@@ -835,7 +837,7 @@ __global__ void k_ccd_shift(CCArgs a, double* __restrict__ par) {
 }
 
 __global__ void k_ccd_assemble(CCArgs a, int ndm, const double* __restrict__ par, double* __restrict__ Gd) {
-  const int J = blockIdx.y;
+  const int J = a.J0 + blockIdx.y;
   const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (e >= (long long)ndm * ndm) return;
   const Hier& h = a.h;
@@ -864,7 +866,7 @@ __global__ void k_ccd_assemble(CCArgs a, int ndm, const double* __restrict__ par
       if (p == q) v += par[J * 8 + 7];
     }
   }
-  Gd[(long long)J * ndm * ndm + e] = v;
+  Gd[(long long)(J - a.J0) * ndm * ndm + e] = v;
 }
 
 // Y = (G + sigma I)^-1 X per active cc cell (the inverse is symmetric: row q of
@@ -879,7 +881,7 @@ __global__ __launch_bounds__(256) void k_ccd_apply(CCArgs a, int ndm, const doub
                                                    const double* __restrict__ X, double* __restrict__ Y,
                                                    const int* __restrict__ flag) {
   __shared__ __align__(16) double Xs[CCD_QC * CCD_XS];
-  const int J = blockIdx.y;
+  const int J = a.J0 + blockIdx.y;
   if (flag[J] >= 0) return;
   const int m = a.m;
   const int d0 = a.cc_ptr[J], nd = a.cc_ptr[J + 1] - d0;
@@ -888,7 +890,7 @@ __global__ __launch_bounds__(256) void k_ccd_apply(CCArgs a, int ndm, const doub
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int r0 = rbase + (w & 1) * 256 + lane;
   const int c0 = (w >> 1) * 16;
-  const double* G = Gi + (long long)J * ndm * ndm;
+  const double* G = Gi + (long long)(J - a.J0) * ndm * ndm;
   const double* XJ = X + (long long)m * d0;
   int rc[4];
 #pragma unroll
@@ -970,6 +972,89 @@ void launch_block_inverse(const Ctx& c, double* Ac, double* Dinv, hipStream_t s)
   hipLaunchKernelGGL(k_block_inverse, dim3((c.h.ncells + 63) / 64), dim3(64), 0, s, c.h.ncells, c.h.Lc, Ac, Dinv);
 }
 
+// One group of cc cells (J0 .. J0 + nJ - 1): start block, dense path for small
+// cells, shift-invert subspace iteration with Rayleigh-Ritz on G, R_cc rows.
+static int run_cc_group(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, CCArgs a, hipStream_t s) {
+  const Hier& h = c.h;
+  const int m = a.m, nJ = a.nJ, J0 = a.J0;
+  const long long ndof = (long long)h.ncells * h.Lc;
+  const dim3 gt((unsigned)((sa.max_cc_dofs + 255) / 256), nJ), bt(256);
+  const dim3 gs((unsigned)((h.max_cc_cells + 63) / 64), nJ, (unsigned)((m + 7) / 8)), bs(64);
+  double* Y = sc->Y;
+  double* Xp = sc->Yp;
+  double* Z = sc->Z;
+  double* small = sc->small;
+  double* par = sc->ccpar;
+  double* ritz = par + (size_t)h.ncc * 8;
+  double* bound = ritz + (size_t)h.ncc * m;
+  int* flag = sc->ccflag;
+  const int small_threads = std::min(1024, std::max(64, ((m * m + 63) / 64) * 64));
+  const size_t small_lds = sizeof(double) * (5 * m * m + m + 64) + sizeof(int) * m;
+  hipLaunchKernelGGL(k_cc_bound, dim3(nJ), dim3(256), 0, s, a, bound);
+  hipLaunchKernelGGL(k_cc_start, dim3((unsigned)((ndof + 255) / 256)), dim3(256), 0, s, a, Y);
+  if (hipMemsetAsync(flag + J0, 0xff, sizeof(int) * nJ, s) != hipSuccess) return MSMG_EHIP;  // -1: active
+  {
+    const size_t lds = sizeof(double) * (4 * CC_DENSE * CC_DENSE + CC_DENSE + 64) + sizeof(int) * CC_DENSE;
+    hipLaunchKernelGGL(k_cc_dense, dim3(nJ), dim3(1024), lds, s, a, Xp, ritz, flag);
+  }
+  auto orth = [&](double* P, double* tmp) {
+    hipLaunchKernelGGL(k_cc_gram, dim3(nJ), dim3(256), 0, s, a, P, P, small, 0, flag);
+    hipLaunchKernelGGL(k_cc_small_eig, dim3(nJ), dim3(small_threads), small_lds, s, a, small, 0, 0, ritz, flag);
+    hipLaunchKernelGGL(k_cc_transform, gt, bt, 0, s, a, P, tmp, small, flag);
+  };
+  auto spmm = [&](const double* P, double* Q) {
+    switch (h.Lc) {
+#define SPMM_L(L_) case L_: hipLaunchKernelGGL(k_cc_spmm<L_>, gs, bs, 0, s, a, P, Q, flag); break;
+      SPMM_L(1) SPMM_L(2) SPMM_L(3) SPMM_L(4) SPMM_L(5) SPMM_L(6) SPMM_L(7) SPMM_L(8)
+#undef SPMM_L
+    }
+  };
+  // orthonormalise twice (Y -> Xp -> Y), Rayleigh-Ritz (Z = G Y; X = Y C; Z = Z C)
+  auto rr = [&]() {
+    orth(Y, Xp);
+    orth(Xp, Y);
+    spmm(Y, Z);
+    hipLaunchKernelGGL(k_cc_gram, dim3(nJ), dim3(256), 0, s, a, Y, Z, small, 0, flag);
+    hipLaunchKernelGGL(k_cc_small_eig, dim3(nJ), dim3(small_threads), small_lds, s, a, small, 0, 1, ritz, flag);
+    hipLaunchKernelGGL(k_cc_transform, gt, bt, 0, s, a, Y, Xp, small, flag);  // Xp = Ritz vectors
+    hipLaunchKernelGGL(k_cc_transform, gt, bt, 0, s, a, Z, Y, small, flag);   // Y = G * Ritz vectors
+    std::swap(Y, Z);                                                            // Z = G X, Y free
+  };
+  rr();
+  const int maxit = sa.opt->cc_maxit;
+  const double tol = sa.opt->eig_tol;
+  // shift-invert operator (G_J + sigma_J I)^-1 for every cc cell of the group
+  const int ndm = sa.max_cc_dofs;
+  hipLaunchKernelGGL(k_ccd_shift, dim3(nJ), dim3(256), 0, s, a, par);
+  hipLaunchKernelGGL(k_ccd_assemble, dim3((unsigned)(((long long)ndm * ndm + 255) / 256), nJ), dim3(256), 0, s, a,
+                     ndm, par, sc->Gd);
+  {
+    const int r = gj_inverse(ndm, nJ, sc->Gd, sc->gj, s);
+    if (r != MSMG_OK) return r;
+  }
+  const dim3 ga((ndm + CCD_ROWS - 1) / CCD_ROWS, nJ), ba(256);
+  std::vector<int> hf(nJ);
+  for (int it = 0; it <= maxit; ++it) {
+    hipLaunchKernelGGL(k_cc_check, dim3(nJ), dim3(256), 0, s, a, Xp, Z, ritz, flag, bound, h.Lcc, tol, it,
+                       it == maxit ? 1 : 0);
+    if (it == maxit) break;
+    if (it % 4 == 3) {
+      if (hipMemcpyAsync(hf.data(), flag + J0, sizeof(int) * nJ, hipMemcpyDeviceToHost, s) != hipSuccess)
+        return MSMG_EHIP;
+      if (hipStreamSynchronize(s) != hipSuccess) return MSMG_EHIP;
+      bool all = true;
+      for (int v : hf) all = all && v >= 0;
+      if (all) break;
+    }
+    // Y = (G + sigma I)^-1 X, then orthonormalise and Rayleigh-Ritz with G
+    hipLaunchKernelGGL(k_ccd_apply, ga, ba, 0, s, a, ndm, sc->Gd, Xp, Y, flag);
+    rr();
+  }
+  // X (Ritz vectors) in Xp
+  hipLaunchKernelGGL(k_cc_finish, dim3(nJ), dim3(256), 0, s, a, Xp, ritz, sa.Rcc64, sa.cc_evals, h.Lcc);
+  return hipGetLastError() == hipSuccess ? MSMG_OK : MSMG_EHIP;
+}
+
 int run_cc_eigen(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, const double* G, int* n_unconv, hipStream_t s) {
   const Hier& h = c.h;
   CCArgs a;
@@ -981,83 +1066,15 @@ int run_cc_eigen(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, const doub
   a.dof_cc = sa.dof_cc;
   a.dof_loc = sa.dof_loc;
   a.cell_status = sa.cell_status;
-  const int m = a.m;
-  const long long ndof = (long long)h.ncells * h.Lc;
-  if (m > 32) return MSMG_EINVAL;
-  const dim3 gt((unsigned)((sa.max_cc_dofs + 255) / 256), h.ncc), bt(256);
-  const dim3 gs((unsigned)((h.max_cc_cells + 63) / 64), h.ncc, (unsigned)((m + 7) / 8)), bs(64);
-  double* Y = sc->Y;
-  double* Xp = sc->Yp;
-  double* Z = sc->Z;
-  double* small = sc->small;
-  double* par = sc->ccpar;
-  double* ritz = par + (size_t)h.ncc * 8;
-  double* bound = ritz + (size_t)h.ncc * m;
-  int* flag = sc->ccflag;
-  const int small_threads = std::min(1024, std::max(64, ((m * m + 63) / 64) * 64));
-  const size_t small_lds = sizeof(double) * (5 * m * m + m + 64) + sizeof(int) * m;
-  hipLaunchKernelGGL(k_cc_bound, dim3(h.ncc), dim3(256), 0, s, a, bound);
-  hipLaunchKernelGGL(k_cc_start, dim3((unsigned)((ndof + 255) / 256)), dim3(256), 0, s, a, Y);
-  if (hipMemsetAsync(flag, 0xff, sizeof(int) * h.ncc, s) != hipSuccess) return MSMG_EHIP;  // -1: active
-  {
-    const size_t lds = sizeof(double) * (4 * CC_DENSE * CC_DENSE + CC_DENSE + 64) + sizeof(int) * CC_DENSE;
-    hipLaunchKernelGGL(k_cc_dense, dim3(h.ncc), dim3(1024), lds, s, a, Xp, ritz, flag);
-  }
-  auto orth = [&](double* P, double* tmp) {
-    hipLaunchKernelGGL(k_cc_gram, dim3(h.ncc), dim3(256), 0, s, a, P, P, small, 0, flag);
-    hipLaunchKernelGGL(k_cc_small_eig, dim3(h.ncc), dim3(small_threads), small_lds, s, a, small, 0, 0, ritz, flag);
-    hipLaunchKernelGGL(k_cc_transform, gt, bt, 0, s, a, P, tmp, small, flag);
-  };
-  auto spmm = [&](const double* P, double* Q) {
-    switch (h.Lc) {
-#define SPMM_L(L_) case L_: hipLaunchKernelGGL(k_cc_spmm<L_>, gs, bs, 0, s, a, P, Q, flag); break;
-      SPMM_L(1) SPMM_L(2) SPMM_L(3) SPMM_L(4) SPMM_L(5) SPMM_L(6) SPMM_L(7) SPMM_L(8)
-#undef SPMM_L
-    }
-  };
-  // start: orthonormalise twice (Y -> Xp -> Y), Rayleigh-Ritz (Z = G Y; X = Y C; Z = Z C)
-  auto rr = [&]() {
-    orth(Y, Xp);
-    orth(Xp, Y);
-    spmm(Y, Z);
-    hipLaunchKernelGGL(k_cc_gram, dim3(h.ncc), dim3(256), 0, s, a, Y, Z, small, 0, flag);
-    hipLaunchKernelGGL(k_cc_small_eig, dim3(h.ncc), dim3(small_threads), small_lds, s, a, small, 0, 1, ritz, flag);
-    hipLaunchKernelGGL(k_cc_transform, gt, bt, 0, s, a, Y, Xp, small, flag);  // Xp = Ritz vectors
-    hipLaunchKernelGGL(k_cc_transform, gt, bt, 0, s, a, Z, Y, small, flag);   // Y = G * Ritz vectors
-    std::swap(Y, Z);                                                            // Z = G X, Y free
-  };
-  rr();
-  const int maxit = sa.opt->cc_maxit;
-  const double tol = sa.opt->eig_tol;
-  // shift-invert operator (G_J + sigma_J I)^-1 for every cc cell
-  const int ndm = sa.max_cc_dofs;
-  hipLaunchKernelGGL(k_ccd_shift, dim3(h.ncc), dim3(256), 0, s, a, par);
-  hipLaunchKernelGGL(k_ccd_assemble, dim3((unsigned)(((long long)ndm * ndm + 255) / 256), h.ncc), dim3(256), 0, s, a,
-                     ndm, par, sc->Gd);
-  {
-    const int r = gj_inverse(ndm, h.ncc, sc->Gd, sc->gj, s);
+  if (a.m > 32 || sc->cc_group < 1) return MSMG_EINVAL;
+  // the dense shifted matrices of one group at a time fit the scratch
+  for (int J0 = 0; J0 < h.ncc; J0 += sc->cc_group) {
+    a.J0 = J0;
+    a.nJ = std::min(sc->cc_group, h.ncc - J0);
+    const int r = run_cc_group(c, sa, sc, a, s);
     if (r != MSMG_OK) return r;
   }
-  if (m > 32) return MSMG_EINVAL;
-  const dim3 ga((ndm + CCD_ROWS - 1) / CCD_ROWS, h.ncc), ba(256);
-  for (int it = 0; it <= maxit; ++it) {
-    hipLaunchKernelGGL(k_cc_check, dim3(h.ncc), dim3(256), 0, s, a, Xp, Z, ritz, flag, bound, h.Lcc, tol, it,
-                       it == maxit ? 1 : 0);
-    if (it == maxit) break;
-    if (it % 4 == 3) {
-      std::vector<int> hf(h.ncc);
-      if (hipMemcpyAsync(hf.data(), flag, sizeof(int) * h.ncc, hipMemcpyDeviceToHost, s) != hipSuccess) return MSMG_EHIP;
-      if (hipStreamSynchronize(s) != hipSuccess) return MSMG_EHIP;
-      bool all = true;
-      for (int v : hf) all = all && v >= 0;
-      if (all) break;
-    }
-    // Y = (G + sigma I)^-1 X, then orthonormalise and Rayleigh-Ritz with G
-    hipLaunchKernelGGL(k_ccd_apply, ga, ba, 0, s, a, ndm, sc->Gd, Xp, Y, flag);
-    rr();
-  }
-  // X (Ritz vectors) in Xp
-  hipLaunchKernelGGL(k_cc_finish, dim3(h.ncc), dim3(256), 0, s, a, Xp, ritz, sa.Rcc64, sa.cc_evals, h.Lcc);
+  int* flag = sc->ccflag;
   std::vector<int> hf(h.ncc);
   if (hipMemcpyAsync(hf.data(), flag, sizeof(int) * h.ncc, hipMemcpyDeviceToHost, s) != hipSuccess) return MSMG_EHIP;
   if (hipMemcpyAsync(sa.cc_status, flag, sizeof(int) * h.ncc, hipMemcpyDeviceToDevice, s) != hipSuccess) return MSMG_EHIP;

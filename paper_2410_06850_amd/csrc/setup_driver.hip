@@ -20,7 +20,7 @@ int run_cc_eigen(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, const doub
 int build_acc(const Ctx& c, const SetupArgs& sa, double* u, hipStream_t s);
 void launch_convert(const void* in, int din, void* out, int dout, long long n, hipStream_t s);
 
-int setup_scratch_alloc(const Geo& g, const Hier& h, int max_cc_dofs, const msmg_options& o, SetupScratch* s,
+int setup_scratch_alloc(const Geo& g, const Hier& h, int max_cc_dofs, int n_cc, const msmg_options& o, SetupScratch* s,
                         const std::function<int(void**, size_t)>& alloc) {
   (void)g;
   int m = o.cc_block ? o.cc_block : std::min(32, h.Lcc + 15);
@@ -34,13 +34,14 @@ int setup_scratch_alloc(const Geo& g, const Hier& h, int max_cc_dofs, const msmg
   if ((r = alloc((void**)&s->small, (size_t)h.ncc * 4 * m * m * 8))) return r;
   if ((r = alloc((void**)&s->ccpar, (size_t)h.ncc * (8 + m + 1) * 8))) return r;
   if ((r = alloc((void**)&s->ccflag, (size_t)h.ncc * 4))) return r;
-  const size_t ncc = (size_t)h.ncc * h.Lcc;
-  if ((r = alloc((void**)&s->acc_copy, ncc * ncc * 8))) return r;
+  if (!o.lean_memory && (r = alloc((void**)&s->acc_copy, (size_t)n_cc * n_cc * 8))) return r;
   const size_t ndm = (size_t)std::max(max_cc_dofs, 1);
-  const size_t gj_single = gj_workspace_doubles(int(ncc), 1);
-  const size_t gj_batch = gj_workspace_doubles(int(ndm), h.ncc);
+  s->cc_group = (int)std::max<size_t>(1, std::min<size_t>(h.ncc, CC_GROUP_BYTES / (ndm * ndm * 8)));
+  if (o.cc_group > 0) s->cc_group = std::min(s->cc_group, o.cc_group);
+  const size_t gj_single = gj_workspace_doubles(n_cc, 1);
+  const size_t gj_batch = gj_workspace_doubles(int(ndm), s->cc_group);
   if ((r = alloc((void**)&s->gj, std::max(gj_single, gj_batch) * 8))) return r;
-  if ((r = alloc((void**)&s->Gd, (size_t)h.ncc * ndm * ndm * 8))) return r;
+  if ((r = alloc((void**)&s->Gd, (size_t)s->cc_group * ndm * ndm * 8))) return r;
   if ((r = alloc((void**)&s->work, 64))) return r;
   return MSMG_OK;
 }
@@ -186,7 +187,7 @@ int run_setup(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, SetupReport* 
 
   // 2. stored copy of R_c, Galerkin A_c from the stored values
   const long long nb = c.g.nn * h.Lc;
-  if (sa.b_dt != DT_F64) launch_convert(sa.Rc64, DT_F64, sa.Rcs, sa.b_dt, nb, s);
+  if (sa.Rcs != (void*)sa.Rc64) launch_convert(sa.Rc64, DT_F64, sa.Rcs, sa.b_dt, nb, s);
   if ((r = launch_galerkin(c, sa.Rcs, sa.b_dt, 0, sa.Ac64, s))) return hip_ok(hipGetLastError(), rep, "Galerkin A_c");
   launch_block_inverse(c, sa.Ac64, sa.AcDinv64, s);
   const long long nblk = (long long)h.ncells * 27 * h.Lc * h.Lc;
@@ -206,7 +207,9 @@ int run_setup(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, SetupReport* 
   // 4. A_cc = R_cc A_c R_cc^T from the cycle's copies, then its inverse
   if ((r = build_acc(c, sa, sc->Y, s))) return hip_ok(hipGetLastError(), rep, "A_cc");
   const size_t nn2 = (size_t)sa.n_cc * sa.n_cc * 8;
-  if ((r = hip_ok(hipMemcpyAsync(sc->acc_copy, sa.Acc, nn2, hipMemcpyDeviceToDevice, s), rep, "A_cc copy"))) return r;
+  if (sc->acc_copy &&
+      (r = hip_ok(hipMemcpyAsync(sc->acc_copy, sa.Acc, nn2, hipMemcpyDeviceToDevice, s), rep, "A_cc copy")))
+    return r;
   if ((r = gj_inverse(sa.n_cc, 1, sa.Acc, sc->gj, s))) return hip_ok(hipGetLastError(), rep, "A_cc inverse");
   return hip_ok(hipGetLastError(), rep, "set-up");
 }

@@ -77,12 +77,19 @@ def test_query_plan_rejects_bad_input(L):
     lib = L.lib()
     plan = L.Plan()
     for args, opts in [((0, 8, 8), {}), ((8, 8, 8), dict(H=1)), ((8, 8, 8), dict(Lc=9)),
-                       ((8, 8, 8), dict(cheb_degree=0)), ((1024, 1024, 1024), dict(sd=8))]:
+                       ((8, 8, 8), dict(cheb_degree=0)), ((2048, 1024, 1024), dict(sd=8)),
+                       ((8, 8, 8), dict(rho_storage=2)), ((8, 8, 8), dict(lean_memory=1, eig_warm_start=1))]:
         o = L.default_options(**opts)
         rc = lib.msmg_query_plan(*args, ctypes.byref(o), ctypes.byref(plan))
         assert rc == L.MSMG_EINVAL, (args, opts, rc)
         assert L.last_error()
-    # the 1024^3 mesh fits with larger coarse-coarse cells
+    # the 1024^3 mesh with the default hierarchy: 16^3 cc cells, a dense
+    # 69,632^2 A_cc; the lean layout fits one 288 GB GPU with room for the
+    # caller's density, load and temperature
+    o = L.default_options(vcycle_dtype=1, rho_v_dtype=2, basis_dtype=2, rho_storage=1, lean_memory=1)
+    assert lib.msmg_query_plan(1024, 1024, 1024, ctypes.byref(o), ctypes.byref(plan)) == L.MSMG_OK
+    assert plan.ncc == 16 ** 3 and plan.n_cc == 69632
+    assert plan.device_bytes < 200e9
     o = L.default_options(sd=16)
     assert lib.msmg_query_plan(1024, 1024, 1024, ctypes.byref(o), ctypes.byref(plan)) == L.MSMG_OK
     assert plan.ncc == 8 ** 3

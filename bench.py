@@ -205,6 +205,64 @@ def run_workload(name, args):
             del s
             torch.cuda.empty_cache()
         out["runs"] = [res]
+    elif name == "cube1024_grf32_c1e6":
+        # the largest one-GPU instance: 1024^3 elements, FP32 canonical density
+        # (GRF ell 32, contrast 1e6), lean memory layout; the 512^3 companion
+        # (2^3 block average of the same unthresholded field, thresholded at its
+        # own 60th percentile) is solved first and its T prolonged (trilinear)
+        # as the warm start; a cold start is run as well
+        t0 = time.perf_counter()
+        w = synth.grf_raw(1024, 32, seed=0, dtype=np.float32)
+        rho_f = synth.threshold_field(w, dtype=np.float32).ravel()
+        rho_c = synth.threshold_field(synth.block_average(w), dtype=np.float32).ravel()
+        del w
+        _log(json.dumps(dict(stage="fields", s=time.perf_counter() - t0)))
+        res = {}
+        n = 512
+        mask_np = synth.dirichlet_patch_mask(n, n, n).ravel()
+        s = pkg.Solver(n, tune_cache=tune, **mixed)
+        s.setup(torch.tensor(rho_c, device=dev), 1e-6, 1.0, 3, torch.tensor(mask_np, device=dev))
+        f = s.element_load(const=1.0)
+        T, info = s.solve(f, rtol=RTOL, maxit=2000)
+        res["coarse"] = dict(n=n, iterations=info.iterations, solve_ms=info.solve_ms, setup_ms=info.setup_ms,
+                             code=info.code)
+        _log(json.dumps(res["coarse"]))
+        x0 = pkg.prolong_nodal(T, (n, n, n))
+        del T, f, s, rho_c
+        torch.cuda.empty_cache()
+        n = 1024
+        opts = dict(mixed, rho_storage=1, lean_memory=1)
+        mask_np = synth.dirichlet_patch_mask(n, n, n).ravel()
+        free = int((n + 1) ** 3 - int(mask_np.sum()))
+        s = pkg.Solver(n, tune_cache=tune, **opts)
+        plan = s.plan()
+        rho = torch.from_numpy(rho_f).to(dev)
+        mask = torch.from_numpy(mask_np).to(dev)
+        del rho_f
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.setup(rho, 1e-6, 1.0, 3, mask)
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        _log(json.dumps(dict(stage="setup 1024", s=setup_s, handle_bytes=plan.device_bytes)))
+        f = s.element_load(const=1.0)
+        T, cold = s.solve(f, rtol=RTOL, maxit=2000)
+        res["fine_cold"] = dict(n=n, iterations=cold.iterations, solve_ms=cold.solve_ms, code=cold.code,
+                                rel_res=cold.rel_res, dofs_per_s=free / (1e-3 * cold.solve_ms))
+        _log(json.dumps(res["fine_cold"]))
+        T, warm = s.solve(f, x0, rtol=RTOL, maxit=2000, use_x0=True)
+        res["fine_warm"] = dict(n=n, iterations=warm.iterations, solve_ms=warm.solve_ms, code=warm.code,
+                                rel_res=warm.rel_res, dofs_per_s=free / (1e-3 * warm.solve_ms))
+        _log(json.dumps(res["fine_warm"]))
+        free_b, total_b = torch.cuda.mem_get_info()
+        res["memory"] = dict(handle_bytes=plan.device_bytes, device_used_bytes=total_b - free_b,
+                             torch_peak_bytes=torch.cuda.max_memory_allocated(), n_cc=plan.n_cc)
+        res["setup_ms"] = 1e3 * setup_s
+        res["free_dofs"] = free
+        res["eig_unconverged"], res["cc_unconverged"] = warm.eig_unconverged, warm.cc_unconverged
+        out["runs"] = [res]
+        out["config"] = dict(n=n, ell=32, k_min=1e-6, precision="mixed", rho_storage="f32", lean_memory=1,
+                             H=8, sd=8, Lc=4, Lcc=17)
     else:
         raise SystemExit(f"unknown workload {name}")
     print(json.dumps(out), flush=True)
@@ -223,7 +281,8 @@ def main():
                     help="run one plain 1 GiB device copy first (reference for the HBM counters)")
     ap.add_argument("--workload", default=None,
                     help="run a companion workload instead of the benchmark: cube128_grf8_c1e6, "
-                         "cube256_grf16_contrast_sweep, cube512_topopt, cube512_grf32_warmstart")
+                         "cube256_grf16_contrast_sweep, cube512_topopt, cube512_grf32_warmstart, "
+                         "cube1024_grf32_c1e6")
     ap.add_argument("--iterations", type=int, default=20, help="optimisation iterations (cube512_topopt)")
     args = ap.parse_args()
     if args.gpus != 1:

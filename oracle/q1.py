@@ -139,6 +139,20 @@ def element_load(grid, source):
     return f
 
 
+def element_load_rows(grid, source_const, nodes):
+    """Rows of element_load for a constant source at the given nodes only:
+    f_n = s V / 8 times the number of elements around n."""
+    nodes = np.asarray(nodes, dtype=np.int64).ravel()
+    i = nodes % grid.nnx
+    j = (nodes // grid.nnx) % grid.nny
+    k = nodes // (grid.nnx * grid.nny)
+    cnt = np.zeros(nodes.size)
+    for c in range(8):
+        ex, ey, ez = i - 1 + (c & 1), j - 1 + ((c >> 1) & 1), k - 1 + ((c >> 2) & 1)
+        cnt += ((ex >= 0) & (ex < grid.nx) & (ey >= 0) & (ey < grid.ny) & (ez >= 0) & (ez < grid.nz))
+    return float(source_const) * grid.vol / 8.0 * cnt
+
+
 def lifted_rhs(A, f, mask, td=None):
     """Right-hand side b of the masked system: b_F = f_F - A_FD T_D, b_D = T_D."""
     mask = np.asarray(mask).ravel().astype(bool)
@@ -289,3 +303,49 @@ def relative_residual_diff(A, T, f, mask, td=None, T_lo=None):
     res = (np.asarray(f).ravel() - AT)[~mask]
     b = lifted_rhs(A, f, mask, td)[~mask]
     return float(np.linalg.norm(res) / np.linalg.norm(b))
+
+
+def residual_rows(grid, rho, kmin, kmax, p, T, f_rows, nodes, T_lo=None):
+    """Rows of f - A T at the given (free) nodes, one node at a time from the
+    element matrices, in difference form: (A T)_n = sum over the elements e
+    around n of k_e sum_b K0[a][b] (T_b - T_a), a = n's local index in e (rows
+    of K0 sum to zero).  Needs only the densities and temperatures around the
+    listed nodes, so it runs at any grid size.  Returns the rows and, for
+    scaling round-off bounds, the sums of the absolute values of the terms.
+    ``f_rows`` holds the load at the listed nodes.  Fixed nodes carry their
+    values in T (zero for the model problem).
+    """
+    nodes = np.asarray(nodes, dtype=np.int64).ravel()
+    T = np.asarray(T).reshape(-1)
+    f_rows = np.asarray(f_rows, dtype=np.float64).reshape(-1)
+    rho = np.asarray(rho).reshape(-1)
+    Tl = None if T_lo is None else np.asarray(T_lo).reshape(-1)
+    K0 = element_stiffness(grid.hx, grid.hy, grid.hz)
+    i = nodes % grid.nnx
+    j = (nodes // grid.nnx) % grid.nny
+    k = nodes // (grid.nnx * grid.nny)
+
+    def diff(ib, ia):
+        # T_b - T_a with a double-binary64 T: both parts differenced separately
+        d = T[ib].astype(np.float64) - T[ia].astype(np.float64)
+        if Tl is not None:
+            d = d + (Tl[ib].astype(np.float64) - Tl[ia].astype(np.float64))
+        return d
+
+    AT = np.zeros(nodes.size)
+    absum = np.zeros(nodes.size)
+    for c in range(8):  # element whose corner (c & 1, c >> 1 & 1, c >> 2 & 1) is away from n
+        ex = i - 1 + (c & 1)
+        ey = j - 1 + ((c >> 1) & 1)
+        ez = k - 1 + ((c >> 2) & 1)
+        ok = (ex >= 0) & (ex < grid.nx) & (ey >= 0) & (ey < grid.ny) & (ez >= 0) & (ez < grid.nz)
+        exc, eyc, ezc = np.where(ok, ex, 0), np.where(ok, ey, 0), np.where(ok, ez, 0)
+        ke = conductivity(rho[grid.element_index(exc, eyc, ezc)], kmin, kmax, p)
+        a = np.where(ok, (i - exc) + 2 * (j - eyc) + 4 * (k - ezc), 0)
+        for b in range(8):
+            bx, by, bz = b & 1, (b >> 1) & 1, (b >> 2) & 1
+            d = diff(grid.node_index(exc + bx, eyc + by, ezc + bz), nodes)
+            term = np.where(ok, ke * K0[a, b] * d, 0.0)
+            AT += term
+            absum += np.abs(term)
+    return f_rows - AT, absum

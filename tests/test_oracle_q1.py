@@ -258,3 +258,33 @@ def test_difference_form_operator():
     assert abs(q1.relative_residual_diff(A, T, f, mask) - q1.relative_residual(A, T, f, mask)) <= 1e-10
     lo = 1e-20 * rng.standard_normal(g.nnodes)
     assert abs(q1.relative_residual_diff(A, T, f, mask, T_lo=lo) - q1.relative_residual_diff(A, T, f, mask)) <= 1e-10
+
+
+def test_residual_rows_match_assembled_operator():
+    """Node-by-node residual rows (used where the grid is too large to assemble)
+    equal f - A T with the scattered sparse matrix, on an uneven box with
+    random densities, temperatures and loads; corner, edge, face and interior
+    nodes all appear."""
+    g = q1.Grid(6, 5, 4, lx=0.6, ly=1.0, lz=0.8)
+    rng = np.random.default_rng(7)
+    rho = rng.uniform(0.0, 1.0, g.nelem)
+    T = rng.standard_normal(g.nnodes)
+    T_lo = 1e-17 * rng.standard_normal(g.nnodes)
+    f = rng.standard_normal(g.nnodes)
+    kmin, kmax, p = 1e-3, 1.0, 3
+    A = q1.assemble(g, q1.conductivity(rho, kmin, kmax, p))
+    want = f - A @ (T + T_lo)
+    nodes = np.arange(g.nnodes)
+    got, absum = q1.residual_rows(g, rho, kmin, kmax, p, T, f[nodes], nodes, T_lo=T_lo)
+    assert np.all(np.abs(got - want) <= 1e-13 * (absum + np.abs(f)))
+    # a float32 density array gives the same rows as its exact float64 upcast
+    r32 = rho.astype(np.float32)
+    a, _ = q1.residual_rows(g, r32, kmin, kmax, p, T, f[nodes[::7]], nodes[::7])
+    b, _ = q1.residual_rows(g, r32.astype(np.float64), kmin, kmax, p, T, f[nodes[::7]], nodes[::7])
+    assert np.array_equal(a, b)
+
+
+def test_element_load_rows_match_full_load():
+    g = q1.Grid(5, 4, 3, lx=1.0, ly=0.5, lz=2.0)
+    nodes = np.arange(g.nnodes)
+    assert np.allclose(q1.element_load_rows(g, 2.5, nodes), q1.element_load(g, 2.5), rtol=1e-15, atol=0)

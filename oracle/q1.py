@@ -349,3 +349,39 @@ def residual_rows(grid, rho, kmin, kmax, p, T, f_rows, nodes, T_lo=None):
             AT += term
             absum += np.abs(term)
     return f_rows - AT, absum
+
+
+def relative_residual_slabs(grid, rho, kmin, kmax, p, T, f, mask, T_lo=None, zslab=8):
+    """||(f - A T)_F|| / ||f_F|| for zero fixed values, with A T evaluated element
+    by element in difference form (k_e K0 (T_b - T_a), hi and lo parts of a
+    double-binary64 T differenced separately), z-slab by z-slab so that the
+    memory stays bounded on grids too large to assemble.
+    """
+    K0 = element_stiffness(grid.hx, grid.hy, grid.hz)
+    nz, ny, nx = grid.nz, grid.ny, grid.nx
+    rho3 = np.asarray(rho).reshape(nz, ny, nx)
+    T3 = np.asarray(T, dtype=np.float64).reshape(grid.nnz, grid.nny, grid.nnx)
+    Tl3 = None if T_lo is None else np.asarray(T_lo, dtype=np.float64).reshape(T3.shape)
+    AT = np.zeros(T3.shape)
+    for z0 in range(0, nz, zslab):
+        z1 = min(nz, z0 + zslab)
+        ks = conductivity(rho3[z0:z1], kmin, kmax, p)
+        corner = []
+        for a in range(8):
+            ax, ay, az = a & 1, (a >> 1) & 1, (a >> 2) & 1
+            sl = (slice(z0 + az, z1 + az), slice(ay, ay + ny), slice(ax, ax + nx))
+            corner.append((T3[sl], None if Tl3 is None else Tl3[sl]))
+        for a in range(8):
+            ax, ay, az = a & 1, (a >> 1) & 1, (a >> 2) & 1
+            ya = np.zeros(ks.shape)
+            for b in range(8):
+                if b == a:
+                    continue
+                d = corner[b][0] - corner[a][0]
+                if Tl3 is not None:
+                    d = d + (corner[b][1] - corner[a][1])
+                ya += K0[a, b] * d
+            AT[z0 + az:z1 + az, ay:ay + ny, ax:ax + nx] += ks * ya
+    free = ~np.asarray(mask).reshape(-1).astype(bool)
+    res = (np.asarray(f, dtype=np.float64).reshape(-1) - AT.reshape(-1))[free]
+    return float(np.linalg.norm(res) / np.linalg.norm(np.asarray(f, dtype=np.float64).reshape(-1)[free]))

@@ -25,6 +25,12 @@ def _smoother_solver(pkg, n, box=(1.0, 1.0, 1.0), H=8, **kw):
     ((16, 16, 16), (1.0, 1.0, 1.0), "f64"),
     ((13, 9, 11), (1.3, 0.9, 1.1), "f64"),
     ((24, 17, 9), (1.0, 1.0, 1.0), "f32"),
+    # node counts along x of k * 64 + 1 (the last march tile also computes the
+    # final column), k * 64 (exact fit) and k * 64 + 2
+    ((64, 12, 10), (1.2, 0.7, 0.9), "f64"),
+    ((128, 9, 7), (1.0, 1.0, 1.0), "f64"),
+    ((63, 8, 8), (1.0, 1.0, 1.0), "f32"),
+    ((65, 6, 9), (1.0, 1.0, 1.0), "f64"),
 ])
 def test_apply_matches_oracle(msmg, shape, box, rho_dt):
     nx, ny, nz = shape

@@ -10,16 +10,16 @@
 
 namespace msmg {
 
-// Pivot block of the batched Gauss-Jordan inverse and its workspace: per
-// matrix the inverted pivot block (GJ_NB^2) and the row and column panels
-// (GJ_NB x n each).
+// Pivot block of the batched symmetric Gauss-Jordan (sweep) inverse and its
+// workspace: per matrix the inverted pivot block (GJ_NB^2) and the pivot row
+// panel (GJ_NB x n).
 constexpr int GJ_NB = 64;
+inline size_t gj_workspace_doubles(int n, int batch) {
+  return (size_t)batch * ((size_t)GJ_NB * GJ_NB + (size_t)GJ_NB * n);
+}
 // Device memory for the dense shifted coarse-coarse matrices: the cc cells are
 // solved in groups whose matrices fit in this many bytes.
 constexpr size_t CC_GROUP_BYTES = size_t(24) << 30;
-inline size_t gj_workspace_doubles(int n, int batch) {
-  return (size_t)batch * ((size_t)GJ_NB * GJ_NB + 2 * (size_t)GJ_NB * n);
-}
 int gj_inverse(int n, int batch, double* A, double* work, hipStream_t s);
 
 // Launch shape of the level-1 eigensolver chosen by the tuner.

@@ -630,8 +630,16 @@ __global__ void k_acc_pad(Hier h, const int* __restrict__ cc_ptr, int n_cc, doub
 // n*n, batch index blockIdx.z) by pivot blocks of NB:
 //   P = A_kk^-1;  A_kJ <- P A_kJ;  A_IJ -= A_Ik A_kJ;  A_Ik <- -A_Ik P;  A_kk <- P.
 // No pivoting is needed for SPD matrices.
-// invert the pivot block in LDS (unblocked Gauss-Jordan), store in P and A_kk;
-// 1024 threads, each owning the entries tid + 1024 q of the nb x nb block
+// Symmetric in-place inversion of SPD matrices by block sweeps (the sweep
+// operator of Goodnight, 1979): sweeping pivot block K with P = A_KK^-1 gives
+//   A_KK <- -P,  A_KJ <- P A_KJ,  A_IK <- A_IK P,  A_IJ <- A_IJ - A_IK P A_KJ,
+// which keeps the matrix symmetric; after all blocks it holds -A^-1.  Only the
+// lower triangle (i >= j) is read and kept up to date, halving the trailing
+// updates; a last pass negates and mirrors it into the full inverse.
+//
+// Pivot block: invert the current A_KK (SPD, read from the lower triangle) in
+// LDS by unblocked Gauss-Jordan, keep P, store -P; 1024 threads, each owning
+// the entries tid + 1024 q of the nb x nb block.
 __global__ __launch_bounds__(1024) void k_gj_pivot(int n, double* __restrict__ Ab, int k0, int nb,
                                                    double* __restrict__ Pb) {
   __shared__ double a[GJ_NB][GJ_NB + 1];
@@ -643,7 +651,10 @@ __global__ __launch_bounds__(1024) void k_gj_pivot(int n, double* __restrict__ A
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     const int e = tid + 1024 * q;
-    if (e < ne) a[e / nb][e % nb] = A[(long long)(k0 + e / nb) * n + (k0 + e % nb)];
+    if (e < ne) {
+      const int r = e / nb, c = e % nb;
+      a[r][c] = A[(long long)(k0 + max(r, c)) * n + (k0 + min(r, c))];
+    }
   }
   __syncthreads();
   for (int k = 0; k < nb; ++k) {
@@ -677,15 +688,15 @@ __global__ __launch_bounds__(1024) void k_gj_pivot(int n, double* __restrict__ A
     if (e >= ne) continue;
     const int r = e / nb, c = e % nb;
     P[r * nb + c] = a[r][c];
-    A[(long long)(k0 + r) * n + (k0 + c)] = a[r][c];
+    A[(long long)(k0 + r) * n + (k0 + c)] = -a[r][c];
   }
 }
 
-// The three products of a Gauss-Jordan step, each on 64 x 64 output tiles
-// computed by FP64 matrix cores (inner dimension: the nb pivot columns):
+// The two products of a sweep step on 64 x 64 output tiles, computed by FP64
+// matrix cores (inner dimension: the nb pivot columns), reading A through its
+// lower triangle (A_xy = A[max][min]):
 //   GJ_ROW:    Rb[r][j]  =  sum_t P[r][t] A[k0+t][j]     (j outside the pivot block)
-//   GJ_COL:    Cb[i][c]  = -sum_t A[i][k0+t] P[t][c]     (i outside the pivot block)
-//   GJ_UPDATE: A[i][j]  -=  sum_t A[i][k0+t] Rb[t][j]    (i and j outside it)
+//   GJ_UPDATE: A[i][j]  -=  sum_t A[i][k0+t] Rb[t][j]    (i >= j tiles, both outside it)
 // Each wave owns a 32 x 32 quarter of the tile as 2 x 2 blocks of
 // v_mfma_f64_16x16x4 (A operand: lane holds row lane % 16, k lane / 16; B
 // operand: column lane % 16, k lane / 16; result register v: column
@@ -697,57 +708,123 @@ __global__ __launch_bounds__(1024) void k_gj_pivot(int n, double* __restrict__ A
 typedef double gj_v4d __attribute__((ext_vector_type(4)));
 constexpr int GJ_LDA = 66, GJ_LDB = 80;
 constexpr size_t GJ_TILE_LDS = sizeof(double) * (64 * GJ_LDA + GJ_NB * GJ_LDB);
-enum { GJ_ROW = 0, GJ_COL = 1, GJ_UPDATE = 2 };
+constexpr long long GJ_WORKGROUPS = 2048;  // persistent tile loops: a few rounds of resident workgroups
+enum { GJ_ROW = 0, GJ_UPDATE = 2 };
 
 template <int MODE>
 __global__ __launch_bounds__(256) void k_gj_tile(int n, double* __restrict__ Ab, int k0, int nb,
-                                                 const double* __restrict__ Pb, double* __restrict__ Rbb,
-                                                 double* __restrict__ Cbb) {
+                                                 const double* __restrict__ Pb, double* __restrict__ Rbb, int batch) {
   static_assert(GJ_NB == 64, "tiles assume 64 pivot columns");
   extern __shared__ double gj_lds[];
   double* As = gj_lds;                 // As[r][t], 64 x GJ_LDA
   double* Bs = gj_lds + 64 * GJ_LDA;   // Bs[t][c], GJ_NB x GJ_LDB
-  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
-  const bool ipiv_tile = i0 >= k0 && i0 + 64 <= k0 + nb, jpiv_tile = j0 >= k0 && j0 + 64 <= k0 + nb;
-  if (MODE == GJ_UPDATE && (ipiv_tile || jpiv_tile)) return;  // left to the write-back
-  if (MODE == GJ_ROW && jpiv_tile) return;
-  if (MODE == GJ_COL && ipiv_tile) return;
-  const long long z = blockIdx.z;
-  double* A = Ab + z * n * n;
-  const double* P = Pb + z * GJ_NB * GJ_NB;
-  double* Rb = Rbb + z * GJ_NB * n;
-  double* Cb = Cbb + z * GJ_NB * n;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
-  const int l16 = lane & 15, lk = lane >> 4;
-  auto a_elem = [&](int r, int t) -> double {  // A operand [r][t]
-    if (t >= nb) return 0.0;
-    if (MODE == GJ_ROW) return r < nb ? P[r * nb + t] : 0.0;
-    const int i = i0 + r;
-    return i < n ? A[(long long)i * n + k0 + t] : 0.0;
-  };
-  auto b_elem = [&](int t, int c) -> double {  // B operand [t][c]
-    if (t >= nb) return 0.0;
-    if (MODE == GJ_COL) return c < nb ? P[t * nb + c] : 0.0;
-    const int j = j0 + c;
-    if (j >= n) return 0.0;
-    return MODE == GJ_ROW ? A[(long long)(k0 + t) * n + j] : Rb[(long long)t * n + j];
-  };
-  auto out_ok = [&](int i, int j) {
-    const bool iok = i < n && !(i >= k0 && i < k0 + nb), jok = j < n && !(j >= k0 && j < k0 + nb);
-    if (MODE == GJ_UPDATE) return iok && jok;
-    if (MODE == GJ_ROW) return i - i0 < nb && jok;
-    return iok && j - j0 < nb;
-  };
-  double ra[16], rb[16];
+  // tiles per matrix: the row panel's nt tiles, or the nt (nt + 1) / 2 tiles of the
+  // lower triangle; workgroups loop over (matrix, tile) pairs
+  const int nt = (n + 63) / 64;
+  const long long per = MODE == GJ_ROW ? nt : (long long)nt * (nt + 1) / 2;
+  const long long total = per * batch;
+  for (long long wk = blockIdx.x; wk < total; wk += gridDim.x) {
+    const long long z = wk / per, tl = wk % per;
+    int ti = 0, tj = int(tl);
+    if (MODE == GJ_UPDATE) {
+      // tl = ti (ti + 1) / 2 + tj with 0 <= tj <= ti
+      ti = int((sqrt(8.0 * double(tl) + 1.0) - 1.0) * 0.5);
+      while ((long long)(ti + 1) * (ti + 2) / 2 <= tl) ++ti;
+      while ((long long)ti * (ti + 1) / 2 > tl) --ti;
+      tj = int(tl - (long long)ti * (ti + 1) / 2);
+    }
+    const int i0 = ti * 64, j0 = tj * 64;
+    const bool ipiv_tile = i0 >= k0 && i0 + 64 <= k0 + nb, jpiv_tile = j0 >= k0 && j0 + 64 <= k0 + nb;
+    if (MODE == GJ_UPDATE && (ipiv_tile || jpiv_tile)) continue;  // pivot rows/columns: write-back
+    if (MODE == GJ_ROW && jpiv_tile) continue;
+    double* A = Ab + z * n * n;
+    const double* P = Pb + z * GJ_NB * GJ_NB;
+    double* Rb = Rbb + z * GJ_NB * n;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
+    const int l16 = lane & 15, lk = lane >> 4;
+    // entry (i, j) of the symmetric matrix from its lower triangle
+    auto sym = [&](int i, int j) { return A[(long long)max(i, j) * n + min(i, j)]; };
+    auto a_elem = [&](int r, int t) -> double {  // A operand [r][t]
+      if (t >= nb) return 0.0;
+      if (MODE == GJ_ROW) return r < nb ? P[r * nb + t] : 0.0;
+      const int i = i0 + r;
+      return i < n ? sym(i, k0 + t) : 0.0;
+    };
+    auto b_elem = [&](int t, int c) -> double {  // B operand [t][c]
+      if (t >= nb) return 0.0;
+      const int j = j0 + c;
+      if (j >= n) return 0.0;
+      return MODE == GJ_ROW ? sym(k0 + t, j) : Rb[(long long)t * n + j];
+    };
+    auto out_ok = [&](int i, int j) {
+      const bool iok = i < n && !(i >= k0 && i < k0 + nb), jok = j < n && !(j >= k0 && j < k0 + nb);
+      if (MODE == GJ_UPDATE) return iok && jok;
+      return i - i0 < nb && jok;
+    };
+    // panels read through the upper triangle's mirror (rows above or columns
+    // right of the pivot block) are contiguous along the other index: let
+    // consecutive lanes run along it so the loads stay coalesced
+    const bool a_tr = MODE == GJ_UPDATE && i0 < k0;
+    const bool b_tr = MODE == GJ_ROW && j0 >= k0 + nb;
+    auto a_rt = [&](int e, int& r, int& t) {
+      r = a_tr ? (e & 63) : (e >> 6);
+      t = a_tr ? (e >> 6) : (e & 63);
+    };
+    auto b_tc = [&](int e, int& t, int& c) {
+      t = b_tr ? (e & 63) : (e >> 6);
+      c = b_tr ? (e >> 6) : (e & 63);
+    };
+    double ra[16], rb[16];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int e = tid + 256 * q;
-    ra[q] = a_elem(e >> 6, e & 63);
-    rb[q] = b_elem(e >> 6, e & 63);
-  }
-  gj_v4d cv[2][2];
-  if (MODE == GJ_UPDATE) {
+    for (int q = 0; q < 16; ++q) {
+      const int e = tid + 256 * q;
+      int r, t, c;
+      a_rt(e, r, t);
+      ra[q] = a_elem(r, t);
+      b_tc(e, t, c);
+      rb[q] = b_elem(t, c);
+    }
+    gj_v4d cv[2][2];
+    if (MODE == GJ_UPDATE) {
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = i0 + wr + bi * 16 + lk + 4 * v, j = j0 + wc + bj * 16 + l16;
+            cv[bi][bj][v] = out_ok(i, j) ? A[(long long)i * n + j] : 0.0;
+          }
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = tid + 256 * q;
+      int r, t, c;
+      a_rt(e, r, t);
+      As[r * GJ_LDA + t] = ra[q];
+      b_tc(e, t, c);
+      Bs[t * GJ_LDB + c] = rb[q];
+    }
+    __syncthreads();
+    gj_v4d acc[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = gj_v4d{0.0, 0.0, 0.0, 0.0};
+    const int ksteps = (nb + 3) / 4;
+#pragma unroll 4
+    for (int ks = 0; ks < ksteps; ++ks) {
+      const int kk = ks * 4 + lk;
+      const double a0 = As[(wr + l16) * GJ_LDA + kk];
+      const double a1 = As[(wr + 16 + l16) * GJ_LDA + kk];
+      const double b0 = Bs[kk * GJ_LDB + wc + l16];
+      const double b1 = Bs[kk * GJ_LDB + wc + 16 + l16];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -755,59 +832,50 @@ __global__ __launch_bounds__(256) void k_gj_tile(int n, double* __restrict__ Ab,
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int i = i0 + wr + bi * 16 + lk + 4 * v, j = j0 + wc + bj * 16 + l16;
-          cv[bi][bj][v] = out_ok(i, j) ? A[(long long)i * n + j] : 0.0;
+          if (!out_ok(i, j)) continue;
+          if (MODE == GJ_UPDATE) A[(long long)i * n + j] = cv[bi][bj][v] - acc[bi][bj][v];
+          else Rb[(long long)(i - i0) * n + j] = acc[bi][bj][v];
         }
+    __syncthreads();  // the next tile overwrites the staged panels
   }
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int e = tid + 256 * q;
-    As[(e >> 6) * GJ_LDA + (e & 63)] = ra[q];
-    Bs[(e >> 6) * GJ_LDB + (e & 63)] = rb[q];
-  }
-  __syncthreads();
-  gj_v4d acc[2][2];
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = gj_v4d{0.0, 0.0, 0.0, 0.0};
-  const int ksteps = (nb + 3) / 4;
-#pragma unroll 4
-  for (int ks = 0; ks < ksteps; ++ks) {
-    const int kk = ks * 4 + lk;
-    const double a0 = As[(wr + l16) * GJ_LDA + kk];
-    const double a1 = As[(wr + 16 + l16) * GJ_LDA + kk];
-    const double b0 = Bs[kk * GJ_LDB + wc + l16];
-    const double b1 = Bs[kk * GJ_LDB + wc + 16 + l16];
-    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
-  }
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = i0 + wr + bi * 16 + lk + 4 * v, j = j0 + wc + bj * 16 + l16;
-        if (!out_ok(i, j)) continue;
-        if (MODE == GJ_UPDATE) A[(long long)i * n + j] = cv[bi][bj][v] - acc[bi][bj][v];
-        else if (MODE == GJ_ROW) Rb[(long long)(i - i0) * n + j] = acc[bi][bj][v];
-        else Cb[(long long)i * nb + (j - j0)] = -acc[bi][bj][v];
-      }
 }
 
+// New pivot row panel P A_KJ into the lower triangle (row K left of the
+// block, column K below it); by symmetry it is also the column panel.
 __global__ void k_gj_writeback(int n, double* __restrict__ Ab, int k0, int nb, const double* __restrict__ Rbb,
-                               const double* __restrict__ Cbb) {
-  const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (gid >= (long long)nb * n) return;
+                               int batch) {
+  const long long per = (long long)nb * n, total = per * batch;
+  for (long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x; gid < total;
+       gid += (long long)gridDim.x * blockDim.x) {
+    const long long z = gid / per, e = gid % per;
+    double* A = Ab + z * n * n;
+    const double* Rb = Rbb + z * GJ_NB * n;
+    const int r = int(e / n), j = int(e % n);
+    if (j < k0) A[(long long)(k0 + r) * n + j] = Rb[(long long)r * n + j];
+    else if (j >= k0 + nb) A[(long long)j * n + k0 + r] = Rb[(long long)r * n + j];
+  }
+}
+
+// -A (lower triangle, after the last sweep) -> the full symmetric inverse:
+// one 64 x 64 tile pair (i0 >= j0) per workgroup through LDS.
+__global__ __launch_bounds__(256) void k_gj_finish(int n, double* __restrict__ Ab) {
+  __shared__ double t[64][65];
+  const int ti = blockIdx.y, tj = blockIdx.x;
+  if (tj > ti) return;
   double* A = Ab + (long long)blockIdx.z * n * n;
-  const double* Rb = Rbb + (long long)blockIdx.z * GJ_NB * n;
-  const double* Cb = Cbb + (long long)blockIdx.z * GJ_NB * n;
-  const int r = int(gid / n), j = int(gid % n);
-  if (!(j >= k0 && j < k0 + nb)) {
-    A[(long long)(k0 + r) * n + j] = Rb[(long long)r * n + j];
-    A[(long long)j * n + k0 + r] = Cb[(long long)j * nb + r];
+  const int i0 = ti * 64, j0 = tj * 64;
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    const int i = i0 + r, j = j0 + c;
+    double v = 0.0;
+    if (i < n && j < n) v = -A[(long long)max(i, j) * n + min(i, j)];
+    t[r][c] = v;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    if (i0 + r < n && j0 + c < n) A[(long long)(i0 + r) * n + j0 + c] = t[r][c];
+    if (ti != tj && j0 + r < n && i0 + c < n) A[(long long)(j0 + r) * n + i0 + c] = t[c][r];
   }
 }
 
@@ -1109,22 +1177,26 @@ int build_acc(const Ctx& c, const SetupArgs& sa, double* u, hipStream_t s) {
 int gj_inverse(int n, int batch, double* A, double* work, hipStream_t s) {
   double* P = work;
   double* Rb = P + (size_t)batch * GJ_NB * GJ_NB;
-  double* Cb = Rb + (size_t)batch * GJ_NB * n;
-  for (const void* f : {(const void*)k_gj_tile<GJ_ROW>, (const void*)k_gj_tile<GJ_COL>, (const void*)k_gj_tile<GJ_UPDATE>})
+  for (const void* f : {(const void*)k_gj_tile<GJ_ROW>, (const void*)k_gj_tile<GJ_UPDATE>})
     if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(GJ_TILE_LDS)) != hipSuccess)
       return MSMG_EHIP;
   const unsigned nt = unsigned((n + 63) / 64);
   for (int k0 = 0; k0 < n; k0 += GJ_NB) {
     const int nb = std::min(GJ_NB, n - k0);
     hipLaunchKernelGGL(k_gj_pivot, dim3(1, 1, batch), dim3(1024), 0, s, n, A, k0, nb, P);
-    // the row panel tiles run along j (one tile row at i0 = 0), the column panel along i
-    hipLaunchKernelGGL(k_gj_tile<GJ_ROW>, dim3(nt, 1, batch), dim3(256), GJ_TILE_LDS, s, n, A, k0, nb, P, Rb, Cb);
-    hipLaunchKernelGGL(k_gj_tile<GJ_COL>, dim3(1, nt, batch), dim3(256), GJ_TILE_LDS, s, n, A, k0, nb, P, Rb, Cb);
-    hipLaunchKernelGGL(k_gj_tile<GJ_UPDATE>, dim3(nt, nt, batch), dim3(256), GJ_TILE_LDS, s, n, A, k0, nb, P, Rb, Cb);
-    const long long rn = (long long)nb * n;
-    const dim3 gp((unsigned)((rn + 255) / 256), 1, batch);
-    hipLaunchKernelGGL(k_gj_writeback, gp, dim3(256), 0, s, n, A, k0, nb, Rb, Cb);
+    // the row panel tiles run along j (one tile row at i0 = 0); the update covers
+    // the lower triangle; both loop over (matrix, tile) pairs on at most
+    // GJ_WORKGROUPS workgroups
+    const long long nrow = (long long)nt * batch, nupd = (long long)nt * (nt + 1) / 2 * batch;
+    hipLaunchKernelGGL(k_gj_tile<GJ_ROW>, dim3((unsigned)std::min<long long>(nrow, GJ_WORKGROUPS)), dim3(256),
+                       GJ_TILE_LDS, s, n, A, k0, nb, P, Rb, batch);
+    hipLaunchKernelGGL(k_gj_tile<GJ_UPDATE>, dim3((unsigned)std::min<long long>(nupd, GJ_WORKGROUPS)), dim3(256),
+                       GJ_TILE_LDS, s, n, A, k0, nb, P, Rb, batch);
+    const long long rn = (long long)nb * n * batch;
+    hipLaunchKernelGGL(k_gj_writeback, dim3((unsigned)std::min<long long>((rn + 255) / 256, 8192)), dim3(256), 0, s,
+                       n, A, k0, nb, Rb, batch);
   }
+  hipLaunchKernelGGL(k_gj_finish, dim3(nt, nt, batch), dim3(256), 0, s, n, A);
   return hipGetLastError() == hipSuccess ? MSMG_OK : MSMG_EHIP;
 }
 

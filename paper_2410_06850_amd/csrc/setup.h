@@ -93,7 +93,7 @@ int run_setup(const Ctx& c, const SetupArgs& a, SetupScratch* s, SetupReport* re
 
 // level-1 eigensolver launch (used by the tuner and the set-up)
 int launch_local_eigen(const Ctx& c, const SetupArgs& a, SetupScratch* s, int bs, int m, int degree,
-                       int blocks, hipStream_t st);
+                       int blocks, hipStream_t st, int ncells = 0);
 
 // utilities implemented with the fine kernels
 void launch_fill(const Ctx& c, double* x, double v, hipStream_t s);

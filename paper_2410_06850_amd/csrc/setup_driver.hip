@@ -109,8 +109,8 @@ static int count_unconverged(const SetupArgs& sa, int ncells, int* unconv, int* 
   return MSMG_OK;
 }
 
-// Time the level-1 eigensolver over a few launch shapes on the real problem
-// and keep the fastest one whose cells all converge.
+// Time the level-1 eigensolver over a few launch shapes on the first cells of
+// the real problem and keep the fastest one with the fewest unconverged cells.
 static int tune_local(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, int cus, hipStream_t s, TuneChoice* best) {
   struct Cand { int bs, m, degree, bpc; };
   // both subspace blocks sit in LDS (about 94 KB for the 9^3-node cells of
@@ -121,18 +121,20 @@ static int tune_local(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, int c
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MSMG_EHIP;
   best->valid = 0;
   int best_unconv = 1 << 30;
+  // candidates are timed on the first cells only (a few rounds of workgroups)
+  const int lim = std::min(c.h.ncells, 64 * cus);
   for (const Cand& cd : cands) {
     if (cd.m < c.h.Lc + 1) continue;
-    const int blocks = std::max(1, std::min(c.h.ncells, cd.bpc * cus));
+    const int blocks = std::max(1, std::min(lim, cd.bpc * cus));
     (void)hipEventRecord(e0, s);
-    const int r = launch_local_eigen(c, sa, sc, cd.bs, cd.m, cd.degree, blocks, s);
+    const int r = launch_local_eigen(c, sa, sc, cd.bs, cd.m, cd.degree, blocks, s, lim);
     (void)hipEventRecord(e1, s);
     if (r != MSMG_OK) continue;
     if (hipEventSynchronize(e1) != hipSuccess) return MSMG_EHIP;
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, e0, e1);
     int un = 0, ti = 0;
-    if (count_unconverged(sa, c.h.ncells, &un, &ti, s) != MSMG_OK) return MSMG_EHIP;
+    if (count_unconverged(sa, lim, &un, &ti, s) != MSMG_OK) return MSMG_EHIP;
     const bool better = (un < best_unconv) || (un == best_unconv && ms < best->ms);
     if (!best->valid || better) {
       best->valid = 1;

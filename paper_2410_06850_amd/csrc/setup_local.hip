@@ -41,6 +41,7 @@ struct LocalArgs {
   double tol;
   int nl_max;   // LDS capacity in nodes
   int warm;     // start from the basis in Rc64 (previous set-up)
+  int ncells;   // cells to solve: all, or the first ones when the tuner times a shape
   double* Rc64;
   double* evals;
   int* status;
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(BS) void k_local_eigen(LocalArgs A) {
     __syncthreads();
     const int cell = s_cell;
     __syncthreads();
-    if (cell >= h.ncells) break;
+    if (cell >= A.ncells) break;
     const int cx = cell % h.ncx, cy = (cell / h.ncx) % h.ncy, cz = cell / (h.ncx * h.ncy);
     const int x0 = cell_begin(cx, h.H), x1 = cell_end(cx, h.H, h.ncx, g.nnx);
     const int y0 = cell_begin(cy, h.H), y1 = cell_end(cy, h.H, h.ncy, g.nny);
@@ -509,7 +510,7 @@ static void launch_local_t(const LocalArgs& a, int blocks, hipStream_t s) {
 }
 
 int launch_local_eigen(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, int bs, int m, int degree, int blocks,
-                       hipStream_t s) {
+                       hipStream_t s, int ncells) {
   LocalArgs a;
   a.g = c.g;
   a.st = c.st;
@@ -524,6 +525,7 @@ int launch_local_eigen(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, int 
   a.tol = sa.opt->eig_tol;
   a.nl_max = sa.max_cell_nodes;
   a.warm = sa.warm;
+  a.ncells = (ncells > 0 && ncells < c.h.ncells) ? ncells : c.h.ncells;
   a.Rc64 = sa.Rc64;
   a.evals = sa.evals;
   a.status = sa.cell_status;

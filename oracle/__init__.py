@@ -15,6 +15,11 @@ Modules
           Algorithm 1, equations ``spepb`` and ``spectral cc``).
   interp  grid-to-grid interpolation of temperatures and densities (the
           interpolation technique of section 3).
+  topopt  the optimisation loop's design update: hat density filter and the
+          optimality-criteria update (section 2.3's sensitivities feed it).
+
+q1 also evaluates residual and load rows node by node and the full residual
+slab by slab, for grids too large to assemble.
 
 Every function is pinned by tests in ``tests/test_oracle_*.py`` against
 closed forms, invariants or brute force; none is marked "parity unpinned".

@@ -530,6 +530,24 @@ MSMG_MARCH_KERNEL void k_vresidual(Geo g, Stencil st, March mg, const KT* __rest
       });
 }
 
+// PCG scalars after a preconditioner application: tt = (z^T r, z^T q).
+MSMG_DEV void vc_finish(Scalars* sc, const double* tt, int mode) {
+  sc->zr = tt[0];
+  sc->zq = tt[1];
+  if (!(tt[0] > 0.0)) {
+    sc->status = (tt[0] == tt[0]) ? ST_BREAKDOWN : ST_NONFINITE;
+    sc->done = 1;
+    return;
+  }
+  if (mode == 0) {
+    sc->beta = 0.0;
+  } else {
+    // beta = z^T (r_new - r_old) / rz_old with r_old = r_new + alpha q
+    sc->beta = -sc->alpha * tt[1] / sc->rz;
+  }
+  sc->rz = tt[0];
+}
+
 // z = a + b (V-cycle type) written as FP64, with the PCG products z^T r and
 // z^T q; fin computes beta (Polak-Ribiere) and the new r^T z.
 //   mode 0: initial (beta = 0); mode 1: iteration; mode 2: no reduction.
@@ -550,22 +568,66 @@ __global__ void k_vc_output(const AT_* __restrict__ a, const VT* __restrict__ b,
     }
   }
   if (mode == 2) return;
-  grid_reduce<2>(s, red, partials, counter, gridDim.x, blockIdx.x, [&](double* tt) {
-    sc->zr = tt[0];
-    sc->zq = tt[1];
-    if (!(tt[0] > 0.0)) {
-      sc->status = (tt[0] == tt[0]) ? ST_BREAKDOWN : ST_NONFINITE;
-      sc->done = 1;
-      return;
-    }
-    if (mode == 0) {
-      sc->beta = 0.0;
-    } else {
-      // beta = z^T (r_new - r_old) / rz_old with r_old = r_new + alpha q
-      sc->beta = -sc->alpha * tt[1] / sc->rz;
-    }
-    sc->rz = tt[0];
-  });
+  grid_reduce<2>(s, red, partials, counter, gridDim.x, blockIdx.x, [&](double* tt) { vc_finish(sc, tt, mode); });
+}
+
+// Post-smoother fused with the V-cycle output (degree-2 Chebyshev): the two
+// Chebyshev steps of k_cheb2 applied to `res`, then z = base + v written as
+// FP64 with the PCG products z^T r (MODE 0, 1) and z^T q (MODE 1) reduced as
+// in k_vc_output.  `base` (the prolonged correction) may be null.  v is
+// rounded to VT before the sum, so z is the value the unfused pair computes.
+template <typename DT, typename IT>
+struct RDZ {
+  IT r;
+  DT di;
+  double b, rr, q;
+};
+
+template <typename VT, typename KT, typename IT, typename DT, bool CUBIC, int MODE>
+MSMG_MARCH_KERNEL void k_cheb2_out(Geo g, Stencil st, March mg, const KT* __restrict__ kv,
+                                   const IT* __restrict__ res, const DT* __restrict__ dinv, ChebCoef cc,
+                                   const double* __restrict__ base, double* __restrict__ z,
+                                   const double* __restrict__ r, const double* __restrict__ q, Scalars* sc,
+                                   double* partials, unsigned* counter) {
+  if (sc->done) return;
+  __shared__ VT sx[2 * PW * PH];
+  __shared__ VT sk[2 * EW * EH];
+  __shared__ double red[32];
+  const long long tile = xcd_tile(blockIdx.x, gridDim.x);
+  const VT it = VT(cc.inv_theta), c0 = VT(cc.c0), c1 = VT(cc.c1);
+  double s[2] = {0.0, 0.0};
+  march<VT, CUBIC>(
+      g, st, mg, tile, sx, sk,
+      [&](long long b, unsigned o) {
+        RD<DT, IT> v;
+        v.r = plane_ld(res, b, o);
+        v.di = plane_ld(dinv, b, o);
+        return v;
+      },
+      [&](const RD<DT, IT>& v) { return cvt<VT, IT>(v.r) * VT(v.di) * it; },
+      [&](long long b, unsigned o) { return plane_ld(kv, b, o); }, [&](KT v) { return cvt<VT, KT>(v); },
+      [&](long long b, unsigned o) {
+        // the output's operands ride in the prefetch queue with the planes
+        // (one wave per SIMD fewer than k_cheb2, still faster than loading
+        // them at the output)
+        RDZ<DT, IT> c;
+        c.r = plane_ld(res, b, o);
+        c.di = plane_ld(dinv, b, o);
+        c.b = base ? plane_ld(base, b, o) : 0.0;
+        c.rr = MODE != 2 ? plane_ld(r, b, o) : 0.0;
+        c.q = MODE == 1 ? plane_ld(q, b, o) : 0.0;
+        return c;
+      },
+      [&](long long b, unsigned o, VT az, VT z1, const RDZ<DT, IT>& c) {
+        VT v = VT(0);
+        if (c.di != DT(0)) v = c0 * z1 + c1 * VT(c.di) * (cvt<VT, IT>(c.r) - az);
+        const double zz = c.b + double(v);
+        plane_st(z, b, o, zz);
+        if (MODE != 2) s[0] += zz * c.rr;
+        if (MODE == 1) s[1] += zz * c.q;
+      });
+  if (MODE == 2) return;
+  grid_reduce<2>(s, red, partials, counter, gridDim.x, blockIdx.x, [&](double* tt) { vc_finish(sc, tt, MODE); });
 }
 
 // ---------------------------------------------------------------------------
@@ -946,6 +1008,21 @@ void launch_vc_output(const Ctx& c, const void* a, bool a_is_f64, const void* b,
     hipLaunchKernelGGL((k_vc_output<double, float>), dim3(nb), dim3(256), 0, s, (const double*)a, (const float*)b, z, r, q, c.g.nn, mode, sc, c.partials, c.counter);
   else
     hipLaunchKernelGGL((k_vc_output<float, float>), dim3(nb), dim3(256), 0, s, (const float*)a, (const float*)b, z, r, q, c.g.nn, mode, sc, c.partials, c.counter);
+}
+
+bool smooth_output_fused(const Ctx& c) { return c.cheb.degree == 2; }
+
+void launch_smooth_output(const Ctx& c, const void* in, bool in_is_f64, const double* base, double* z,
+                          const double* r, const double* q, int mode, hipStream_t s) {
+  const dim3 gr = march_grid(c), bl = march_block();
+#define SO(IT_, MD) hipLaunchKernelGGL((k_cheb2_out<VT, KVT, IT_, DVT, CU, MD>), gr, bl, 0, s, c.g, c.st, c.mg, (const KVT*)c.kv, (const IT_*)in, (const DVT*)c.dinv, c.cheb, base, z, r, q, c.sc, c.partials, c.counter)
+#define SO_M(IT_) do { if (mode == 0) SO(IT_, 0); else if (mode == 1) SO(IT_, 1); else SO(IT_, 2); } while (0)
+  VC_DISPATCH({
+    (void)sizeof(BT);
+    if (in_is_f64) SO_M(double); else SO_M(VT);
+  });
+#undef SO_M
+#undef SO
 }
 
 void launch_sensitivity(const Ctx& c, const double* T, const double* lam, double* dc, hipStream_t s) {

@@ -97,6 +97,11 @@ void launch_vresidual(const Ctx& c, const void* r, bool r_is_f64, const void* x,
                       hipStream_t s);
 void launch_vc_output(const Ctx& c, const void* a, bool a_is_f64, const void* b, double* z, const double* r,
                       const double* q, int mode, hipStream_t s);
+// Degree-2 post-smoother fused with the output: z = base + S^-1 in (base may be
+// null) with the PCG reduction `mode`; only when smooth_output_fused(c).
+bool smooth_output_fused(const Ctx& c);
+void launch_smooth_output(const Ctx& c, const void* in, bool in_is_f64, const double* base, double* z,
+                          const double* r, const double* q, int mode, hipStream_t s);
 void launch_sensitivity(const Ctx& c, const double* T, const double* lam, double* dc, hipStream_t s);
 void launch_element_load(const Geo& g, const double* src, double sconst, double* f, hipStream_t s);
 void launch_prolong_nodal(int nx, int ny, int nz, const double* tc, double* tf, hipStream_t s);

@@ -410,7 +410,9 @@ static int alloc_arrays(msmg_handle* h, bool dry, size_t* total) {
   A(&h->xlo, nn * 8);
   A(&h->v_r1, nn * vs); A(&h->v_res, nn * vs);
   if (o.cheb_degree > 2) { A(&h->v_t0, nn * vs); A(&h->v_t1, nn * vs); }
-  h->partial_slots = std::max<long long>(h->ntiles + 8, 8192);
+  // one slot per workgroup of any reducing launch (tiles, march, 1-D grids)
+  h->partial_slots = std::max<long long>({h->ntiles + 8, 8192LL, make_march(h->g, h->march_resident).blocks,
+                                          (long long)h->red_blocks});
   A(&h->partials, h->partial_slots * 2 * 8);
   A(&h->counter, 64);
   A(&h->oc_state, 64);
@@ -667,7 +669,12 @@ extern "C" int msmg_setup(msmg_handle* h, const void* rho, msmg_dtype rho_dtype,
 static void precondition(msmg_handle* h, const Ctx& c, const double* r, double* z, const double* q, int mode,
                          hipStream_t s) {
   const bool v64 = (h->v_dt == DT_F64);
+  const bool fused = smooth_output_fused(c);
   if (!h->mg) {
+    if (fused) {
+      launch_smooth_output(c, r, true, nullptr, z, r, q, mode, s);
+      return;
+    }
     launch_smooth(c, r, true, h->v_r1, s);
     launch_vc_output(c, h->v_r1, v64, nullptr, z, r, q, mode, s);
     return;
@@ -684,6 +691,10 @@ static void precondition(msmg_handle* h, const Ctx& c, const double* r, double* 
   launch_gs_sweep(c, h->c_t, h->c_d, false, s);                     // S_c^-T (...)
   launch_prolong(c, h->v_r1, h->c_x1, h->c_d, h->v_r2, s);          // r2 = r1 + R_c^T ec (FP64)
   launch_vresidual(c, r, true, h->v_r2, true, h->v_res, s);         // r0 - A r2
+  if (fused) {
+    launch_smooth_output(c, h->v_res, false, (const double*)h->v_r2, z, r, q, mode, s);  // y = r2 + S^-T (...)
+    return;
+  }
   launch_smooth(c, h->v_res, false, h->v_r1, s);                    // S^-T (...)
   launch_vc_output(c, h->v_r2, true, h->v_r1, z, r, q, mode, s);    // y = r2 + ...
 }

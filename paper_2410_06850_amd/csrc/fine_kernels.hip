@@ -171,61 +171,43 @@ __global__ void k_update_p(double* __restrict__ p, const double* __restrict__ z,
   const long long tile = xcd_tile(blockIdx.x, gridDim.x);                 \
   const Tile t = tile_of_thread(g, h, CX, tile);
 
-// y = A x on free rows (0 on fixed rows); optional p^T (A p) reduction -> alpha.
-//   MODE 0: plain apply; 1: PCG apply with pq -> alpha; 2: masked public form P A P x + (I-P) x
+// per-node data of the apply's output
 struct ApplyCentre {
   uint32_t w;  // mask word of the node
   double x;    // x_n (MODE 2 only)
 };
-struct MaskedRaw {
-  double v;
-  uint32_t w;
-  int sh;
-};
 
+// y = A x on free rows (MODE 0: 0 on fixed rows; MODE 1: also p^T (A p) ->
+// alpha; MODE 2: xr, the caller's raw input, on fixed rows), on the march
+// whose prefetch queue sits in LDS.  The staged input x is zero on fixed nodes.
 template <bool CUBIC, int MODE>
-MSMG_MARCH_KERNEL void k_apply(Geo g, Stencil st, March mg, const double* __restrict__ kc,
-                                                         const uint32_t* __restrict__ bits,
-                                                         const double* __restrict__ x, double* __restrict__ y,
-                                                         Scalars* sc, double* partials, unsigned* counter) {
+MSMG_MARCH_KERNEL void k_apply(
+    Geo g, Stencil st, March mg, const double* __restrict__ kc, const uint32_t* __restrict__ bits,
+    const double* __restrict__ x, const double* __restrict__ xr, double* __restrict__ y, Scalars* sc,
+    double* partials, unsigned* counter) {
   if (MODE == 1 && sc->done) return;
-  __shared__ double sx[2 * PW * PH];
-  __shared__ double sk[2 * EW * EH];
+  // one LDS array per queue buffer (up to 6)
+  __shared__ double b0[LDS_BUF_D], b1[LDS_BUF_D], b2[LDS_BUF_D], b3[LDS_BUF_D], b4[LDS_NB > 4 ? LDS_BUF_D : 1],
+      b5[LDS_NB > 5 ? LDS_BUF_D : 1];
+  static_assert(LDS_NB <= 6, "six LDS buffers at most");
+  double* const bufs[6] = {b0, b1, b2, b3, b4, b5};
   __shared__ double red[16];
   const long long tile = xcd_tile(blockIdx.x, gridDim.x);
   double s[1] = {0.0};
-  auto loadk = [&](long long b, unsigned o) { return plane_ld(kc, b, o); };
-  auto convk = [&](double v) { return v; };
-  auto loadc = [&](long long b, unsigned o) {
-    ApplyCentre c;
-    const long long n = b + o;
-    c.w = bits[n >> 5];
-    c.x = MODE == 2 ? plane_ld(x, b, o) : 0.0;
-    return c;
-  };
-  auto emit = [&](long long b, unsigned o, double ax, double xc, const ApplyCentre& c) {
-    double out = ax;
-    if ((c.w >> ((b + o) & 31)) & 1u) out = (MODE == 2) ? c.x : 0.0;
-    plane_st(y, b, o, out);
-    if (MODE == 1) s[0] += xc * out;
-  };
-  if (MODE == 2) {
-    march<double, CUBIC>(
-        g, st, mg, tile, sx, sk,
-        [&](long long b, unsigned o) {
-          MaskedRaw r;
-          const long long n = b + o;
-          r.v = plane_ld(x, b, o);
-          r.w = bits[n >> 5];
-          r.sh = int(n & 31);
-          return r;
-        },
-        [&](const MaskedRaw& r) { return ((r.w >> r.sh) & 1u) ? 0.0 : r.v; }, loadk, convk, loadc, emit);
-  } else {
-    march<double, CUBIC>(
-        g, st, mg, tile, sx, sk, [&](long long b, unsigned o) { return plane_ld(x, b, o); },
-        [&](double v) { return v; }, loadk, convk, loadc, emit);
-  }
+  march_lds<CUBIC>(
+      g, st, mg, tile, bufs, x, kc,
+      [&](long long b, unsigned o) {
+        ApplyCentre c;
+        c.w = bits[(b + o) >> 5];
+        c.x = MODE == 2 ? plane_ld(xr, b, o) : 0.0;
+        return c;
+      },
+      [&](long long b, unsigned o, double ax, double xc, const ApplyCentre& c) {
+        double out = ax;
+        if ((c.w >> ((b + o) & 31)) & 1u) out = (MODE == 2) ? c.x : 0.0;
+        plane_st(y, b, o, out);
+        if (MODE == 1) s[0] += xc * out;
+      });
   if (MODE != 1) return;
   grid_reduce<1>(s, red, partials, counter, gridDim.x, blockIdx.x, [&](double* tt) {
     sc->pq = tt[0];
@@ -852,20 +834,20 @@ long long march_resident_blocks() {
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 2048;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 2048;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(&k_apply<true, 1>),
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(&k_vresidual<double, bf16, double, double, true>),
                                                    MARCH_THREADS, 0) != hipSuccess)
     return 2048;
   return (long long)(per > 0 ? per : 1) * (cus > 0 ? cus : 1);
 }
 static inline dim3 march_block() { return dim3(MX, MY); }
 
-void launch_apply(const Ctx& c, const double* x, double* y, int mode, hipStream_t s) {
+void launch_apply(const Ctx& c, const double* x, double* y, int mode, hipStream_t s, const double* xraw) {
   const dim3 gr = march_grid(c), bl = march_block();
-#define AP(CU, MD) hipLaunchKernelGGL((k_apply<CU, MD>), gr, bl, 0, s, c.g, c.st, c.mg, c.kc, c.bits, x, y, c.sc, c.partials, c.counter)
-#define AP_M(CU) do { if (mode == 0) AP(CU, 0); else if (mode == 1) AP(CU, 1); else AP(CU, 2); } while (0)
+#define APL(CU, MD) hipLaunchKernelGGL((k_apply<CU, MD>), gr, bl, 0, s, c.g, c.st, c.mg, c.kc, c.bits, x, xraw, y, c.sc, c.partials, c.counter)
+#define AP_M(CU) do { if (mode == 0) APL(CU, 0); else if (mode == 1) APL(CU, 1); else APL(CU, 2); } while (0)
   if (c.st.cubic) AP_M(true); else AP_M(false);
 #undef AP_M
-#undef AP
+#undef APL
 }
 
 void launch_residual(const Ctx& c, const double* b, const double* x, const double* xlo, double* y, bool reduce,

@@ -16,6 +16,8 @@
 // is prefetched the same way.
 #pragma once
 
+#include <utility>
+
 #include "common.h"
 
 #ifndef MSMG_MARCH_DEPTH8
@@ -266,6 +268,204 @@ MSMG_DEV void march(const Geo& g, const Stencil& st, const March& mg, long long 
       for (int q = 0; q < 9; ++q) A[q] = B[q];
     }
   }
+}
+
+
+// ---------------------------------------------------------------------------
+// Plane march with its prefetch queue in LDS (FP64 node and element arrays).
+//
+// gfx950's global-to-LDS loads (global_load_lds_dword) write the 64 dwords of a
+// wave straight into LDS, so LDS_DEPTH bundles (node plane z+1 with halo,
+// element layer z) are in flight per workgroup without holding registers.
+// Bundles rotate through LDS_NB = LDS_DEPTH + 1 buffers, each its own LDS
+// array so that the compiler can tell a read of one buffer from the loads
+// still landing in the others.  A step waits until at most the loads issued
+// for the LDS_DEPTH - 1 younger bundles are outstanding (vector-memory loads
+// complete in issue order), one barrier then publishes the bundle to all
+// waves, and the buffer read in the previous step is refilled.  Every load
+// instruction runs with all lanes active (spare lanes fetch a valid address
+// into padding), so the count of memory instructions per step is fixed.
+// Slots outside the mesh fetch clamped, finite values; their element
+// conductivities are zeroed when read, which removes their terms.
+// three bundles in flight measured fastest (four and five were slower: the
+// march at three waves per SIMD is then bound by its FP64 arithmetic)
+constexpr int LDS_DEPTH = 3, LDS_NB = LDS_DEPTH + 1;
+constexpr int LDS_NI = (2 * PW * PH + MARCH_THREADS - 1) / MARCH_THREADS;  // node-plane loads per step
+constexpr int LDS_EI = (2 * EW * EH + MARCH_THREADS - 1) / MARCH_THREADS;  // element-layer loads
+constexpr int LDS_INSTR = LDS_NI + LDS_EI;
+constexpr int LDS_ELEM0 = LDS_NI * MARCH_THREADS / 2;       // first element slot (doubles)
+constexpr int LDS_BUF_D = LDS_INSTR * MARCH_THREADS / 2;    // doubles per buffer
+constexpr int LDS_WAIT = (LDS_DEPTH - 1) * (LDS_INSTR + 1);  // + the centre load of each step
+static_assert(LDS_WAIT < 64, "vmcnt holds 6 bits");
+static_assert(MX == 64, "one wave per tile row");
+
+typedef __attribute__((address_space(3))) void* lds_void_ptr;
+typedef __attribute__((address_space(1))) void* glb_void_ptr;
+typedef const __attribute__((address_space(1))) char* glb_char_ptr;
+
+MSMG_DEV void wait_vm(void) {
+  // s_waitcnt with vmcnt = LDS_WAIT, expcnt and lgkmcnt left open
+  __builtin_amdgcn_s_waitcnt((LDS_WAIT & 0xF) | ((LDS_WAIT >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+MSMG_DEV void wait_vm0(void) { __builtin_amdgcn_s_waitcnt(0 | (0x7 << 4) | (0xF << 8)); }
+// barrier without a memory fence (the fence would drain every LDS load in
+// flight); the empty asm keeps the compiler from moving memory operations
+// across it
+MSMG_DEV void lds_barrier(void) {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+template <int J>
+struct StepIdx {
+  static constexpr int value = J;
+};
+
+// f(StepIdx<J>) for J = 0, 1, ... in order (the buffer index of a step is a
+// compile-time constant)
+template <typename F, int... J>
+MSMG_DEV void for_each_step(F&& f, std::integer_sequence<int, J...>) {
+  (f(StepIdx<J>{}), ...);
+}
+
+// loadc(b, o) -> per-node data of node b + o (register queue, LDS_NB slots);
+// emit as in march().  bufs: the LDS_NB buffers of LDS_BUF_D doubles, each a
+// separate LDS array.
+template <bool CUBIC, typename LoadC, typename Emit>
+MSMG_DEV void march_lds(const Geo& g, const Stencil& st, const March& mg, long long tile, double* const* bufs,
+                        const double* __restrict__ x, const double* __restrict__ kc, LoadC loadc, Emit emit) {
+  using CD = decltype(loadc(0LL, 0u));
+  const int tx = int(tile % mg.ntx), ty = int((tile / mg.ntx) % mg.nty), tz = int(tile / ((long long)mg.ntx * mg.nty));
+  const int za = tz * mg.zc;
+  if (tz >= mg.nzc || za >= g.nnz) return;  // uniform over the block
+  const int zb = min(za + mg.zc, g.nnz);
+  const int xa = tx * MX, ya = ty * MY;
+  const int lx = threadIdx.x, ly = threadIdx.y, tid = lx + MX * ly;
+  const int wave = __builtin_amdgcn_readfirstlane(ly);  // MX == 64: one wave per row
+  const int x0 = xa + lx, y0 = ya + ly;
+  const bool inside = x0 < g.nnx && y0 < g.nny;
+  const long long nplane = (long long)g.nnx * g.nny, eplane = (long long)g.nx * g.ny;
+  const unsigned cxy = unsigned(min(y0, g.nny - 1) * g.nnx + min(x0, g.nnx - 1));
+
+  // byte offset inside its plane of this lane's dword of each load
+  // instruction (padding lanes re-read the plane's first dword)
+  unsigned inpl[LDS_INSTR];
+#pragma unroll
+  for (int i = 0; i < LDS_INSTR; ++i) {
+    const int dw = ((i < LDS_NI ? i : i - LDS_NI) * (MARCH_THREADS / 64) + wave) * 64 + lx;
+    const int q = dw >> 1;
+    unsigned off = 0;
+    if (i < LDS_NI && q < PW * PH) {
+      const int gx = min(max(xa - 1 + q % PW, 0), g.nnx - 1), gy = min(max(ya - 1 + q / PW, 0), g.nny - 1);
+      off = unsigned(gy * g.nnx + gx) * 8u + unsigned(dw & 1) * 4u;
+    } else if (i >= LDS_NI && q < EW * EH) {
+      const int ex = min(max(xa - 1 + q % EW, 0), g.nx - 1), ey = min(max(ya - 1 + q / EW, 0), g.ny - 1);
+      off = unsigned(ey * g.nx + ex) * 8u + unsigned(dw & 1) * 4u;
+    }
+    inpl[i] = off;
+  }
+  // in-plane validity of the four elements around this thread's node
+  bool ev[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int ex = x0 - 1 + (c & 1), ey = y0 - 1 + (c >> 1);
+    ev[c] = ex >= 0 && ex < g.nx && ey >= 0 && ey < g.ny;
+  }
+
+  // uniform plane base + 32-bit lane offset: the loads take the scalar-base form
+  const glb_char_ptr xg = (glb_char_ptr)x, kg = (glb_char_ptr)kc;
+  auto issue = [&](double* buf, int z) {
+    const glb_char_ptr nb = xg + (long long)min(max(z + 1, 0), g.nnz - 1) * nplane * 8;
+    const glb_char_ptr eb = kg + (long long)min(max(z, 0), g.nz - 1) * eplane * 8;
+    char* dst = reinterpret_cast<char*>(buf) + wave * 256;
+#pragma unroll
+    for (int i = 0; i < LDS_INSTR; ++i) {
+      const glb_char_ptr src = (i < LDS_NI ? nb : eb) + inpl[i];
+      __builtin_amdgcn_global_load_lds((glb_void_ptr)src, (lds_void_ptr)(dst + i * MARCH_THREADS * 4), 4, 0, 0);
+    }
+  };
+  auto read_plane = [&](const double* src, double* dst) {
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) dst[dy * 3 + dx] = src[(ly + dy) * PW + (lx + dx)];
+  };
+  auto read_k = [&](const double* src, bool zin, double* kq) {
+#pragma unroll
+    for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+      for (int cx = 0; cx < 2; ++cx) {
+        const double v = src[(ly + cy) * EW + (lx + cx)];
+        kq[cy * 2 + cx] = (zin && ev[cy * 2 + cx]) ? v : 0.0;
+      }
+  };
+  CD pc[LDS_NB];
+#pragma unroll
+  for (int d = 0; d < LDS_DEPTH; ++d) {
+    issue(bufs[d], za + d);
+    pc[d] = loadc((long long)min(za + d, g.nnz - 1) * nplane, cxy);
+  }
+
+  // prologue in the buffer the first bundles leave free: planes za-1 and za,
+  // element layer za-1 -> the partial sum of node za from the layer below
+  double A[9], carry;
+  {
+    double* pb = bufs[LDS_NB - 1];
+    auto stage_nodes = [&](int zz) {
+      const bool zin = zz >= 0 && zz < g.nnz;
+      const long long base = (long long)min(max(zz, 0), g.nnz - 1) * nplane;
+      for (int q = tid; q < PW * PH; q += MARCH_THREADS) {
+        const int gx = xa - 1 + q % PW, gy = ya - 1 + q / PW;
+        const bool ok = zin && gx >= 0 && gx < g.nnx && gy >= 0 && gy < g.nny;
+        pb[q] = ok ? x[base + (long long)gy * g.nnx + gx] : 0.0;
+      }
+    };
+    stage_nodes(za - 1);
+    {
+      const int ez = za - 1;
+      const bool zin = ez >= 0 && ez < g.nz;
+      const long long base = (long long)min(max(ez, 0), g.nz - 1) * eplane;
+      for (int q = tid; q < EW * EH; q += MARCH_THREADS) {
+        const int ex = xa - 1 + q % EW, ey = ya - 1 + q / EW;
+        const bool ok = zin && ex >= 0 && ex < g.nx && ey >= 0 && ey < g.ny;
+        pb[LDS_ELEM0 + q] = ok ? kc[base + (long long)ey * g.nx + ex] : 0.0;
+      }
+    }
+    __syncthreads();
+    double P[9], kq[4];
+    read_plane(pb, P);
+    read_k(pb + LDS_ELEM0, true, kq);
+    __syncthreads();
+    stage_nodes(za);
+    __syncthreads();
+    read_plane(pb, A);
+    carry = layer_apply<double, CUBIC>(st, kq, A, P);
+  }
+
+  auto step = [&](auto jc, int z) {
+    constexpr int j = decltype(jc)::value;
+    constexpr int jn = (j + LDS_DEPTH) % LDS_NB;
+    wait_vm();
+    lds_barrier();
+    // refill the buffer read in the previous step
+    issue(bufs[jn], z + LDS_DEPTH);
+    pc[jn] = loadc((long long)min(z + LDS_DEPTH, g.nnz - 1) * nplane, cxy);
+    const double* buf = bufs[j];
+    double B[9], kq[4];
+    read_plane(buf, B);
+    read_k(buf + LDS_ELEM0, z < g.nz, kq);
+    const double ax = carry + layer_apply<double, CUBIC>(st, kq, A, B);
+    if (inside && z < zb) emit((long long)z * nplane, cxy, ax, A[4], pc[j]);
+    carry = layer_apply<double, CUBIC>(st, kq, B, A);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) A[q] = B[q];
+  };
+  const int zend = za + (zb - za + LDS_NB - 1) / LDS_NB * LDS_NB;
+  for (int z0 = za; z0 < zend; z0 += LDS_NB)
+    for_each_step([&](auto jc) { step(jc, z0 + decltype(jc)::value); }, std::make_integer_sequence<int, LDS_NB>{});
+  // no load may still be writing this workgroup's LDS when it ends
+  wait_vm0();
 }
 
 }  // namespace msmg

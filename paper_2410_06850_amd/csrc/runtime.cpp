@@ -722,7 +722,11 @@ extern "C" int msmg_apply(msmg_handle* h, const double* x, double* y, hipStream_
   if (!h->setup_done) return fail(MSMG_ESTATE, "msmg_setup has not completed");
   if (x == y) return fail(MSMG_EINVAL, "x and y must not alias");
   Ctx c = make_ctx(h);
-  launch_apply(c, x, y, 2, s);
+  // the march stages x with zero fixed entries (handle scratch q, which the
+  // lean layout shares with the exported basis)
+  if (h->opt.lean_memory) h->basis_live = false;
+  launch_zero_fixed_copy(c, x, h->q, s);
+  launch_apply(c, h->q, y, 2, s, x);
   HIP_TRY(hipGetLastError());
   return MSMG_OK;
 }
@@ -925,7 +929,7 @@ extern "C" int msmg_export(msmg_handle* h, int what, void* host_out, size_t byte
   switch (what) {
     case 0: src = h->evals; need = (size_t)h->n_c * 8; break;
     case 1:
-      if (!h->basis_live) return fail(MSMG_EINVAL, "lean_memory: the FP64 basis was overwritten by a solve");
+      if (!h->basis_live) return fail(MSMG_EINVAL, "lean_memory: the FP64 basis was overwritten by a solve, apply or preconditioner call");
       src = h->Rc64; need = (size_t)h->g.nn * hh.Lc * 8; break;
     case 2: src = h->Ac64; need = (size_t)hh.ncells * 27 * hh.Lc * hh.Lc * 8; break;
     case 3: src = h->cc_evals; need = (size_t)h->n_cc * 8; break;

@@ -841,9 +841,19 @@ long long march_resident_blocks() {
 }
 static inline dim3 march_block() { return dim3(MX, MY); }
 
+long long apply_resident_blocks() {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 2048;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 2048;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(&k_apply<true, 1>),
+                                                   MARCH_THREADS, 0) != hipSuccess)
+    return 2048;
+  return (long long)(per > 0 ? per : 1) * (cus > 0 ? cus : 1);
+}
+
 void launch_apply(const Ctx& c, const double* x, double* y, int mode, hipStream_t s, const double* xraw) {
-  const dim3 gr = march_grid(c), bl = march_block();
-#define APL(CU, MD) hipLaunchKernelGGL((k_apply<CU, MD>), gr, bl, 0, s, c.g, c.st, c.mg, c.kc, c.bits, x, xraw, y, c.sc, c.partials, c.counter)
+  const dim3 gr((unsigned)c.mgl.blocks), bl(LMX, LMY);
+#define APL(CU, MD) hipLaunchKernelGGL((k_apply<CU, MD>), gr, bl, 0, s, c.g, c.st, c.mgl, c.kc, c.bits, x, xraw, y, c.sc, c.partials, c.counter)
 #define AP_M(CU) do { if (mode == 0) APL(CU, 0); else if (mode == 1) APL(CU, 1); else APL(CU, 2); } while (0)
   if (c.st.cubic) AP_M(true); else AP_M(false);
 #undef AP_M

@@ -40,6 +40,7 @@ struct Ctx {
   int CX;             // coarse cells per tile along x
   long long ntiles;
   March mg;           // plane-march decomposition of the fine stencil kernels
+  March mgl;          // the same for the LDS-queue apply (its own tile shape)
   const void* rho;    // canonical density (rho_dt)
   int rho_dt;
   const double* kc;   // element conductivities, FP64
@@ -77,6 +78,7 @@ void launch_oc_update(long long ne, const double* x, const double* dc, const dou
 
 // fine level
 long long march_resident_blocks();  // marching workgroups the device runs at once
+long long apply_resident_blocks();  // the same for the LDS-queue apply
 void launch_pack_mask(const uint8_t* mask, uint32_t* bits, long long nn, hipStream_t s);
 void launch_convert(const void* in, int din, void* out, int dout, long long n, hipStream_t s);
 void launch_conductivity(const Ctx& c, const void* rho, int rdt, double* kc, hipStream_t s);

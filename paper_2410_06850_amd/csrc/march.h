@@ -59,10 +59,10 @@ struct March {
 // chunks of zc planes.  `resident` is the number of marching workgroups the
 // device runs at once; the chunk count minimises (rounds of resident
 // workgroups) x (planes a workgroup stages, zc + 2 with the prologue).
-inline March make_march(const Geo& g, long long resident = 2048, int min_chunk = 8) {
+inline March make_march(const Geo& g, long long resident = 2048, int min_chunk = 8, int mx = MX, int my = MY) {
   March m;
-  m.ntx = (g.nnx + MX - 1) / MX;
-  m.nty = (g.nny + MY - 1) / MY;
+  m.ntx = (g.nnx + mx - 1) / mx;
+  m.nty = (g.nny + my - 1) / my;
   const long long txy = (long long)m.ntx * m.nty;
   if (resident < 1) resident = 1;
   long long best_cost = -1;
@@ -290,14 +290,20 @@ MSMG_DEV void march(const Geo& g, const Stencil& st, const March& mg, long long 
 // three bundles in flight measured fastest (four and five were slower: the
 // march at three waves per SIMD is then bound by its FP64 arithmetic)
 constexpr int LDS_DEPTH = 3, LDS_NB = LDS_DEPTH + 1;
-constexpr int LDS_NI = (2 * PW * PH + MARCH_THREADS - 1) / MARCH_THREADS;  // node-plane loads per step
-constexpr int LDS_EI = (2 * EW * EH + MARCH_THREADS - 1) / MARCH_THREADS;  // element-layer loads
+// its own tile shape (a wave is any 64 consecutive threads of the tile)
+#ifndef MSMG_LDS_MX
+#define MSMG_LDS_MX 32
+#endif
+constexpr int LMX = MSMG_LDS_MX, LMY = MARCH_THREADS / LMX;
+constexpr int LPW = LMX + 2, LPH = LMY + 2, LEW = LMX + 1, LEH = LMY + 1;
+constexpr int LDS_NI = (2 * LPW * LPH + MARCH_THREADS - 1) / MARCH_THREADS;  // node-plane loads per step
+constexpr int LDS_EI = (2 * LEW * LEH + MARCH_THREADS - 1) / MARCH_THREADS;  // element-layer loads
 constexpr int LDS_INSTR = LDS_NI + LDS_EI;
 constexpr int LDS_ELEM0 = LDS_NI * MARCH_THREADS / 2;       // first element slot (doubles)
 constexpr int LDS_BUF_D = LDS_INSTR * MARCH_THREADS / 2;    // doubles per buffer
 constexpr int LDS_WAIT = (LDS_DEPTH - 1) * (LDS_INSTR + 1);  // + the centre load of each step
 static_assert(LDS_WAIT < 64, "vmcnt holds 6 bits");
-static_assert(MX == 64, "one wave per tile row");
+static_assert(LMX * LMY == MARCH_THREADS && MARCH_THREADS % 64 == 0, "whole waves");
 
 typedef __attribute__((address_space(3))) void* lds_void_ptr;
 typedef __attribute__((address_space(1))) void* glb_void_ptr;
@@ -340,9 +346,9 @@ MSMG_DEV void march_lds(const Geo& g, const Stencil& st, const March& mg, long l
   const int za = tz * mg.zc;
   if (tz >= mg.nzc || za >= g.nnz) return;  // uniform over the block
   const int zb = min(za + mg.zc, g.nnz);
-  const int xa = tx * MX, ya = ty * MY;
-  const int lx = threadIdx.x, ly = threadIdx.y, tid = lx + MX * ly;
-  const int wave = __builtin_amdgcn_readfirstlane(ly);  // MX == 64: one wave per row
+  const int xa = tx * LMX, ya = ty * LMY;
+  const int lx = threadIdx.x, ly = threadIdx.y, tid = lx + LMX * ly;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int x0 = xa + lx, y0 = ya + ly;
   const bool inside = x0 < g.nnx && y0 < g.nny;
   const long long nplane = (long long)g.nnx * g.nny, eplane = (long long)g.nx * g.ny;
@@ -353,14 +359,14 @@ MSMG_DEV void march_lds(const Geo& g, const Stencil& st, const March& mg, long l
   unsigned inpl[LDS_INSTR];
 #pragma unroll
   for (int i = 0; i < LDS_INSTR; ++i) {
-    const int dw = ((i < LDS_NI ? i : i - LDS_NI) * (MARCH_THREADS / 64) + wave) * 64 + lx;
+    const int dw = ((i < LDS_NI ? i : i - LDS_NI) * (MARCH_THREADS / 64) + wave) * 64 + lane;
     const int q = dw >> 1;
     unsigned off = 0;
-    if (i < LDS_NI && q < PW * PH) {
-      const int gx = min(max(xa - 1 + q % PW, 0), g.nnx - 1), gy = min(max(ya - 1 + q / PW, 0), g.nny - 1);
+    if (i < LDS_NI && q < LPW * LPH) {
+      const int gx = min(max(xa - 1 + q % LPW, 0), g.nnx - 1), gy = min(max(ya - 1 + q / LPW, 0), g.nny - 1);
       off = unsigned(gy * g.nnx + gx) * 8u + unsigned(dw & 1) * 4u;
-    } else if (i >= LDS_NI && q < EW * EH) {
-      const int ex = min(max(xa - 1 + q % EW, 0), g.nx - 1), ey = min(max(ya - 1 + q / EW, 0), g.ny - 1);
+    } else if (i >= LDS_NI && q < LEW * LEH) {
+      const int ex = min(max(xa - 1 + q % LEW, 0), g.nx - 1), ey = min(max(ya - 1 + q / LEW, 0), g.ny - 1);
       off = unsigned(ey * g.nx + ex) * 8u + unsigned(dw & 1) * 4u;
     }
     inpl[i] = off;
@@ -389,14 +395,14 @@ MSMG_DEV void march_lds(const Geo& g, const Stencil& st, const March& mg, long l
 #pragma unroll
     for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
-      for (int dx = 0; dx < 3; ++dx) dst[dy * 3 + dx] = src[(ly + dy) * PW + (lx + dx)];
+      for (int dx = 0; dx < 3; ++dx) dst[dy * 3 + dx] = src[(ly + dy) * LPW + (lx + dx)];
   };
   auto read_k = [&](const double* src, bool zin, double* kq) {
 #pragma unroll
     for (int cy = 0; cy < 2; ++cy)
 #pragma unroll
       for (int cx = 0; cx < 2; ++cx) {
-        const double v = src[(ly + cy) * EW + (lx + cx)];
+        const double v = src[(ly + cy) * LEW + (lx + cx)];
         kq[cy * 2 + cx] = (zin && ev[cy * 2 + cx]) ? v : 0.0;
       }
   };
@@ -415,8 +421,8 @@ MSMG_DEV void march_lds(const Geo& g, const Stencil& st, const March& mg, long l
     auto stage_nodes = [&](int zz) {
       const bool zin = zz >= 0 && zz < g.nnz;
       const long long base = (long long)min(max(zz, 0), g.nnz - 1) * nplane;
-      for (int q = tid; q < PW * PH; q += MARCH_THREADS) {
-        const int gx = xa - 1 + q % PW, gy = ya - 1 + q / PW;
+      for (int q = tid; q < LPW * LPH; q += MARCH_THREADS) {
+        const int gx = xa - 1 + q % LPW, gy = ya - 1 + q / LPW;
         const bool ok = zin && gx >= 0 && gx < g.nnx && gy >= 0 && gy < g.nny;
         pb[q] = ok ? x[base + (long long)gy * g.nnx + gx] : 0.0;
       }
@@ -426,8 +432,8 @@ MSMG_DEV void march_lds(const Geo& g, const Stencil& st, const March& mg, long l
       const int ez = za - 1;
       const bool zin = ez >= 0 && ez < g.nz;
       const long long base = (long long)min(max(ez, 0), g.nz - 1) * eplane;
-      for (int q = tid; q < EW * EH; q += MARCH_THREADS) {
-        const int ex = xa - 1 + q % EW, ey = ya - 1 + q / EW;
+      for (int q = tid; q < LEW * LEH; q += MARCH_THREADS) {
+        const int ex = xa - 1 + q % LEW, ey = ya - 1 + q / LEW;
         const bool ok = zin && ex >= 0 && ex < g.nx && ey >= 0 && ey < g.ny;
         pb[LDS_ELEM0 + q] = ok ? kc[base + (long long)ey * g.nx + ex] : 0.0;
       }

@@ -94,6 +94,7 @@ struct msmg_handle {
   unsigned* counter = nullptr;
   int red_blocks = 4096;
   long long march_resident = 2048;  // marching workgroups resident at once (queried at create)
+  long long apply_resident = 768;   // the same for the LDS-queue apply
   bool has_basis = false;           // Rc64 holds the basis of the last completed set-up
   bool basis_live = false;          // lean memory: Rc64 not yet overwritten by PCG vectors
   long long partial_slots = 0;
@@ -253,6 +254,7 @@ static Ctx make_ctx(msmg_handle* h) {
   c.CX = h->CX;
   c.ntiles = h->ntiles;
   c.mg = make_march(h->g, h->march_resident);
+  c.mgl = make_march(h->g, h->apply_resident, 8, LMX, LMY);
   c.rho = h->rho;
   c.rho_dt = h->rho_dt;
   c.kc = h->kc;
@@ -412,6 +414,7 @@ static int alloc_arrays(msmg_handle* h, bool dry, size_t* total) {
   if (o.cheb_degree > 2) { A(&h->v_t0, nn * vs); A(&h->v_t1, nn * vs); }
   // one slot per workgroup of any reducing launch (tiles, march, 1-D grids)
   h->partial_slots = std::max<long long>({h->ntiles + 8, 8192LL, make_march(h->g, h->march_resident).blocks,
+                                          make_march(h->g, h->apply_resident, 8, LMX, LMY).blocks,
                                           (long long)h->red_blocks});
   A(&h->partials, h->partial_slots * 2 * 8);
   A(&h->counter, 64);
@@ -518,6 +521,7 @@ extern "C" int msmg_create(msmg_handle** out, int nx, int ny, int nz, double lx,
   init_handle(h, o, P, nx, ny, nz, lx, ly, lz);
   HIP_TRY(hipGetDevice(&h->device));
   h->march_resident = march_resident_blocks();
+  h->apply_resident = apply_resident_blocks();
   int rc = alloc_arrays(h, false, nullptr);
   if (rc == MSMG_OK) {
     hipError_t e = hipHostMalloc((void**)&h->sc_host, sizeof(Scalars), hipHostMallocDefault);

@@ -171,6 +171,14 @@ __global__ void k_update_p(double* __restrict__ p, const double* __restrict__ z,
   const long long tile = xcd_tile(blockIdx.x, gridDim.x);                 \
   const Tile t = tile_of_thread(g, h, CX, tile);
 
+// The LDS-queue march's buffers: one LDS array each, so that the compiler can
+// tell a read of one from the loads still landing in the others.
+#define MSMG_LDS_BUFFERS(KT)                                                                        \
+  __shared__ double lb0[LdsLayout<KT>::BUF_D], lb1[LdsLayout<KT>::BUF_D], lb2[LdsLayout<KT>::BUF_D], \
+      lb3[LdsLayout<KT>::BUF_D];                                                                    \
+  static_assert(LDS_NB == 4, "four LDS buffers");                                                   \
+  double* const bufs[4] = {lb0, lb1, lb2, lb3};
+
 // per-node data of the apply's output
 struct ApplyCentre {
   uint32_t w;  // mask word of the node
@@ -186,11 +194,7 @@ MSMG_MARCH_KERNEL void k_apply(
     const double* __restrict__ x, const double* __restrict__ xr, double* __restrict__ y, Scalars* sc,
     double* partials, unsigned* counter) {
   if (MODE == 1 && sc->done) return;
-  // one LDS array per queue buffer (up to 6)
-  __shared__ double b0[LDS_BUF_D], b1[LDS_BUF_D], b2[LDS_BUF_D], b3[LDS_BUF_D], b4[LDS_NB > 4 ? LDS_BUF_D : 1],
-      b5[LDS_NB > 5 ? LDS_BUF_D : 1];
-  static_assert(LDS_NB <= 6, "six LDS buffers at most");
-  double* const bufs[6] = {b0, b1, b2, b3, b4, b5};
+  MSMG_LDS_BUFFERS(double)
   __shared__ double red[16];
   const long long tile = xcd_tile(blockIdx.x, gridDim.x);
   double s[1] = {0.0};

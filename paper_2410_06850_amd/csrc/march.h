@@ -296,22 +296,34 @@ constexpr int LDS_DEPTH = 3, LDS_NB = LDS_DEPTH + 1;
 #endif
 constexpr int LMX = MSMG_LDS_MX, LMY = MARCH_THREADS / LMX;
 constexpr int LPW = LMX + 2, LPH = LMY + 2, LEW = LMX + 1, LEH = LMY + 1;
-constexpr int LDS_NI = (2 * LPW * LPH + MARCH_THREADS - 1) / MARCH_THREADS;  // node-plane loads per step
-constexpr int LDS_EI = (2 * LEW * LEH + MARCH_THREADS - 1) / MARCH_THREADS;  // element-layer loads
-constexpr int LDS_INSTR = LDS_NI + LDS_EI;
-constexpr int LDS_ELEM0 = LDS_NI * MARCH_THREADS / 2;       // first element slot (doubles)
-constexpr int LDS_BUF_D = LDS_INSTR * MARCH_THREADS / 2;    // doubles per buffer
-constexpr int LDS_WAIT = (LDS_DEPTH - 1) * (LDS_INSTR + 1);  // + the centre load of each step
-static_assert(LDS_WAIT < 64, "vmcnt holds 6 bits");
 static_assert(LMX * LMY == MARCH_THREADS && MARCH_THREADS % 64 == 0, "whole waves");
+
+// LDS buffer of one bundle for element type KT.  A load instruction moves one
+// 4-byte slot per lane (a 2-byte load lands zero-extended in the low half of
+// its lane's slot): FP64 values take two lanes, FP32 and BF16 one.
+template <typename KT>
+struct LdsLayout {
+  static constexpr int KB = sizeof(KT) >= 4 ? 4 : int(sizeof(KT));  // bytes one lane loads
+  static constexpr int KL = int(sizeof(KT)) / KB;                     // lanes per element
+  static constexpr int NI = (2 * LPW * LPH + MARCH_THREADS - 1) / MARCH_THREADS;  // node-plane loads
+  static constexpr int EI = (KL * LEW * LEH + MARCH_THREADS - 1) / MARCH_THREADS;  // element-layer loads
+  static constexpr int INSTR = NI + EI;
+  static constexpr int ELEM0 = NI * MARCH_THREADS * 4;               // byte offset of the elements
+  static constexpr int BUF_D = (ELEM0 + EI * MARCH_THREADS * 4) / 8;  // doubles per buffer
+  // loads of the LDS_DEPTH - 1 younger bundles (the per-step centre loads
+  // are not counted, so the wait holds however many a step issues)
+  static constexpr int WAIT = (LDS_DEPTH - 1) * INSTR;
+  static_assert(WAIT < 64, "vmcnt holds 6 bits");
+};
 
 typedef __attribute__((address_space(3))) void* lds_void_ptr;
 typedef __attribute__((address_space(1))) void* glb_void_ptr;
 typedef const __attribute__((address_space(1))) char* glb_char_ptr;
 
+template <int N>
 MSMG_DEV void wait_vm(void) {
-  // s_waitcnt with vmcnt = LDS_WAIT, expcnt and lgkmcnt left open
-  __builtin_amdgcn_s_waitcnt((LDS_WAIT & 0xF) | ((LDS_WAIT >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+  // s_waitcnt with vmcnt = N, expcnt and lgkmcnt left open
+  __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
 }
 MSMG_DEV void wait_vm0(void) { __builtin_amdgcn_s_waitcnt(0 | (0x7 << 4) | (0xF << 8)); }
 // barrier without a memory fence (the fence would drain every LDS load in
@@ -335,12 +347,15 @@ MSMG_DEV void for_each_step(F&& f, std::integer_sequence<int, J...>) {
   (f(StepIdx<J>{}), ...);
 }
 
+// Staged nodes are FP64 (x), elements KT (kc, converted to FP64 when read).
 // loadc(b, o) -> per-node data of node b + o (register queue, LDS_NB slots);
-// emit as in march().  bufs: the LDS_NB buffers of LDS_BUF_D doubles, each a
-// separate LDS array.
-template <bool CUBIC, typename LoadC, typename Emit>
+// emit as in march().  bufs: the LDS_NB buffers of LdsLayout<KT>::BUF_D
+// doubles, each a separate LDS array.
+template <bool CUBIC, typename KT, typename LoadC, typename Emit>
 MSMG_DEV void march_lds(const Geo& g, const Stencil& st, const March& mg, long long tile, double* const* bufs,
-                        const double* __restrict__ x, const double* __restrict__ kc, LoadC loadc, Emit emit) {
+                        const double* __restrict__ x, const KT* __restrict__ kc, LoadC loadc, Emit emit) {
+  using LY = LdsLayout<KT>;
+  constexpr int NI = LY::NI, INSTR = LY::INSTR, KL = LY::KL, KB = LY::KB, ELEM0 = LY::ELEM0;
   using CD = decltype(loadc(0LL, 0u));
   const int tx = int(tile % mg.ntx), ty = int((tile / mg.ntx) % mg.nty), tz = int(tile / ((long long)mg.ntx * mg.nty));
   const int za = tz * mg.zc;
@@ -356,18 +371,23 @@ MSMG_DEV void march_lds(const Geo& g, const Stencil& st, const March& mg, long l
 
   // byte offset inside its plane of this lane's dword of each load
   // instruction (padding lanes re-read the plane's first dword)
-  unsigned inpl[LDS_INSTR];
+  unsigned inpl[INSTR];
 #pragma unroll
-  for (int i = 0; i < LDS_INSTR; ++i) {
-    const int dw = ((i < LDS_NI ? i : i - LDS_NI) * (MARCH_THREADS / 64) + wave) * 64 + lane;
-    const int q = dw >> 1;
+  for (int i = 0; i < INSTR; ++i) {
+    const int dw = ((i < NI ? i : i - NI) * (MARCH_THREADS / 64) + wave) * 64 + lane;
     unsigned off = 0;
-    if (i < LDS_NI && q < LPW * LPH) {
-      const int gx = min(max(xa - 1 + q % LPW, 0), g.nnx - 1), gy = min(max(ya - 1 + q / LPW, 0), g.nny - 1);
-      off = unsigned(gy * g.nnx + gx) * 8u + unsigned(dw & 1) * 4u;
-    } else if (i >= LDS_NI && q < LEW * LEH) {
-      const int ex = min(max(xa - 1 + q % LEW, 0), g.nx - 1), ey = min(max(ya - 1 + q / LEW, 0), g.ny - 1);
-      off = unsigned(ey * g.nx + ex) * 8u + unsigned(dw & 1) * 4u;
+    if (i < NI) {
+      const int q = dw >> 1;
+      if (q < LPW * LPH) {
+        const int gx = min(max(xa - 1 + q % LPW, 0), g.nnx - 1), gy = min(max(ya - 1 + q / LPW, 0), g.nny - 1);
+        off = unsigned(gy * g.nnx + gx) * 8u + unsigned(dw & 1) * 4u;
+      }
+    } else {
+      const int q = dw / KL;
+      if (q < LEW * LEH) {
+        const int ex = min(max(xa - 1 + q % LEW, 0), g.nx - 1), ey = min(max(ya - 1 + q / LEW, 0), g.ny - 1);
+        off = unsigned(ey * g.nx + ex) * unsigned(sizeof(KT)) + unsigned(dw % KL) * unsigned(KB);
+      }
     }
     inpl[i] = off;
   }
@@ -383,12 +403,29 @@ MSMG_DEV void march_lds(const Geo& g, const Stencil& st, const March& mg, long l
   const glb_char_ptr xg = (glb_char_ptr)x, kg = (glb_char_ptr)kc;
   auto issue = [&](double* buf, int z) {
     const glb_char_ptr nb = xg + (long long)min(max(z + 1, 0), g.nnz - 1) * nplane * 8;
-    const glb_char_ptr eb = kg + (long long)min(max(z, 0), g.nz - 1) * eplane * 8;
+    const glb_char_ptr eb = kg + (long long)min(max(z, 0), g.nz - 1) * eplane * (long long)sizeof(KT);
     char* dst = reinterpret_cast<char*>(buf) + wave * 256;
 #pragma unroll
-    for (int i = 0; i < LDS_INSTR; ++i) {
-      const glb_char_ptr src = (i < LDS_NI ? nb : eb) + inpl[i];
-      __builtin_amdgcn_global_load_lds((glb_void_ptr)src, (lds_void_ptr)(dst + i * MARCH_THREADS * 4), 4, 0, 0);
+    for (int i = 0; i < INSTR; ++i) {
+      if (i < NI)
+        __builtin_amdgcn_global_load_lds((glb_void_ptr)(nb + inpl[i]), (lds_void_ptr)(dst + i * MARCH_THREADS * 4), 4,
+                                         0, 0);
+      else
+        __builtin_amdgcn_global_load_lds((glb_void_ptr)(eb + inpl[i]), (lds_void_ptr)(dst + i * MARCH_THREADS * 4), LdsLayout<KT>::KB,
+                                         0, 0);
+    }
+  };
+  // conductivity of element slot e of a buffer's element region
+  auto kval = [&](const double* buf, int e) -> double {
+    const char* p = reinterpret_cast<const char*>(buf) + ELEM0;
+    if constexpr (sizeof(KT) == 8) {
+      return *reinterpret_cast<const double*>(p + 8 * e);
+    } else if constexpr (sizeof(KT) == 4) {
+      return cvt<double, KT>(*reinterpret_cast<const KT*>(p + 4 * e));
+    } else {
+      KT v;
+      __builtin_memcpy(&v, p + 4 * e, sizeof(KT));
+      return cvt<double, KT>(v);
     }
   };
   auto read_plane = [&](const double* src, double* dst) {
@@ -397,12 +434,12 @@ MSMG_DEV void march_lds(const Geo& g, const Stencil& st, const March& mg, long l
 #pragma unroll
       for (int dx = 0; dx < 3; ++dx) dst[dy * 3 + dx] = src[(ly + dy) * LPW + (lx + dx)];
   };
-  auto read_k = [&](const double* src, bool zin, double* kq) {
+  auto read_k = [&](const double* buf, bool zin, double* kq) {
 #pragma unroll
     for (int cy = 0; cy < 2; ++cy)
 #pragma unroll
       for (int cx = 0; cx < 2; ++cx) {
-        const double v = src[(ly + cy) * LEW + (lx + cx)];
+        const double v = kval(buf, (ly + cy) * LEW + (lx + cx));
         kq[cy * 2 + cx] = (zin && ev[cy * 2 + cx]) ? v : 0.0;
       }
   };
@@ -432,16 +469,20 @@ MSMG_DEV void march_lds(const Geo& g, const Stencil& st, const March& mg, long l
       const int ez = za - 1;
       const bool zin = ez >= 0 && ez < g.nz;
       const long long base = (long long)min(max(ez, 0), g.nz - 1) * eplane;
+      char* pe = reinterpret_cast<char*>(pb) + ELEM0;
       for (int q = tid; q < LEW * LEH; q += MARCH_THREADS) {
         const int ex = xa - 1 + q % LEW, ey = ya - 1 + q / LEW;
         const bool ok = zin && ex >= 0 && ex < g.nx && ey >= 0 && ey < g.ny;
-        pb[LDS_ELEM0 + q] = ok ? kc[base + (long long)ey * g.nx + ex] : 0.0;
+        KT v;
+        __builtin_memset(&v, 0, sizeof(KT));
+        if (ok) v = kc[base + (long long)ey * g.nx + ex];
+        __builtin_memcpy(pe + (sizeof(KT) == 8 ? 8 : 4) * q, &v, sizeof(KT));
       }
     }
     __syncthreads();
     double P[9], kq[4];
     read_plane(pb, P);
-    read_k(pb + LDS_ELEM0, true, kq);
+    read_k(pb, true, kq);
     __syncthreads();
     stage_nodes(za);
     __syncthreads();
@@ -452,7 +493,7 @@ MSMG_DEV void march_lds(const Geo& g, const Stencil& st, const March& mg, long l
   auto step = [&](auto jc, int z) {
     constexpr int j = decltype(jc)::value;
     constexpr int jn = (j + LDS_DEPTH) % LDS_NB;
-    wait_vm();
+    wait_vm<LY::WAIT>();
     lds_barrier();
     // refill the buffer read in the previous step
     issue(bufs[jn], z + LDS_DEPTH);
@@ -460,7 +501,7 @@ MSMG_DEV void march_lds(const Geo& g, const Stencil& st, const March& mg, long l
     const double* buf = bufs[j];
     double B[9], kq[4];
     read_plane(buf, B);
-    read_k(buf + LDS_ELEM0, z < g.nz, kq);
+    read_k(buf, z < g.nz, kq);
     const double ax = carry + layer_apply<double, CUBIC>(st, kq, A, B);
     if (inside && z < zb) emit((long long)z * nplane, cxy, ax, A[4], pc[j]);
     carry = layer_apply<double, CUBIC>(st, kq, B, A);

@@ -22,18 +22,66 @@ MSMG_DEV long long nb_cell(const Hier& h, int cx, int cy, int cz, int b, bool& o
 // (colours 0..7) is S_c^-1 = (D + L)^-1, the backward sweep (7..0) its
 // transpose.
 // LP * 8 lanes per cell (LP = power of two >= Lc): lane = (row l, slot q); slot q
-// sums the neighbour blocks b = q, q + 8, q + 16 of row l; the 8 slots of a row
-// are then combined by shuffles (fixed order), so the 27-block products of a
-// cell run in parallel.
+// sums the neighbour blocks b = q, q + 8, q + 16, q + 24 of row l; the 8 slots
+// of a row are then combined by shuffles (fixed order), so the 27-block
+// products of a cell run in parallel.  L is a compile-time constant so that
+// every load of a lane (its row of up to four blocks, the matching entries of
+// x, b_i and the row of D_i^-1) is issued before the first product.
 constexpr int ROW_SLOTS = 8;
+constexpr int SLOT_BLOCKS = (27 + ROW_SLOTS - 1) / ROW_SLOTS;
 
-template <typename VT, typename AT>
-__global__ void k_gs_colour(Hier h, int colour, int forward, int LP, const AT* __restrict__ Ac,
+template <int L>
+constexpr int lanes_pow2() {
+  return L <= 1 ? 1 : L <= 2 ? 2 : L <= 4 ? 4 : 8;
+}
+
+// Row l, slot q of one cell: the blocks b = q + 8 k it uses (use[k]) with
+// their neighbour cells, loaded with the matching entries of x; part = the
+// sum of A_ib x_b over them in the order of b then m (unused blocks add 0).
+template <typename VT, typename AT, int L, typename Use>
+MSMG_DEV VT row_products(const Hier& h, const AT* __restrict__ A, const VT* __restrict__ x, int cx, int cy, int cz,
+                         int l, int q, bool row, Use use_block) {
+  bool use[SLOT_BLOCKS];
+  long long nc[SLOT_BLOCKS];
+#pragma unroll
+  for (int k = 0; k < SLOT_BLOCKS; ++k) {
+    const int bb = q + ROW_SLOTS * k;
+    bool ok = false;
+    nc[k] = 0;
+    if (row && bb < 27) nc[k] = nb_cell(h, cx, cy, cz, bb, ok);
+    use[k] = ok && use_block(bb);
+  }
+  VT part = VT(0);
+  if constexpr (L <= 4) {
+    VT av[SLOT_BLOCKS][L], xv[SLOT_BLOCKS][L];
+#pragma unroll
+    for (int k = 0; k < SLOT_BLOCKS; ++k)
+#pragma unroll
+      for (int m = 0; m < L; ++m) {
+        av[k][m] = use[k] ? ld<VT, AT>(A, ((q + ROW_SLOTS * k) * L + l) * L + m) : VT(0);
+        xv[k][m] = use[k] ? x[nc[k] * L + m] : VT(0);
+      }
+#pragma unroll
+    for (int k = 0; k < SLOT_BLOCKS; ++k)
+#pragma unroll
+      for (int m = 0; m < L; ++m) part += av[k][m] * xv[k][m];
+  } else {
+    // larger rows: the staged copies would spill; products as the loads land
+#pragma unroll
+    for (int k = 0; k < SLOT_BLOCKS; ++k)
+      if (use[k])
+#pragma unroll
+        for (int m = 0; m < L; ++m) part += ld<VT, AT>(A, ((q + ROW_SLOTS * k) * L + l) * L + m) * x[nc[k] * L + m];
+  }
+  return part;
+}
+
+template <typename VT, typename AT, int L>
+__global__ void k_gs_colour(Hier h, int colour, int forward, const AT* __restrict__ Ac,
                             const AT* __restrict__ Dinv, const VT* __restrict__ b, VT* __restrict__ x,
                             const Scalars* sc) {
   if (sc && sc->done) return;
-  const int L = h.Lc;
-  const int CL = LP * ROW_SLOTS;
+  constexpr int CL = lanes_pow2<L>() * ROW_SLOTS;
   const long long gtid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   const int lane = int(gtid % CL);
   const int l = lane / ROW_SLOTS, q = lane % ROW_SLOTS;
@@ -41,66 +89,62 @@ __global__ void k_gs_colour(Hier h, int colour, int forward, int LP, const AT* _
   const int px = colour & 1, py = (colour >> 1) & 1, pz = (colour >> 2) & 1;
   const int nx = (h.ncx - px + 1) / 2, ny = (h.ncy - py + 1) / 2, nz = (h.ncz - pz + 1) / 2;
   const bool valid = ci < (long long)nx * ny * nz;
+  const bool row = valid && l < L;
   long long cell = 0;
-  VT part = VT(0);
+  int cx = 0, cy = 0, cz = 0;
   if (valid) {
-    const int cx = 2 * int(ci % nx) + px;
-    const int cy = 2 * int((ci / nx) % ny) + py;
-    const int cz = 2 * int(ci / ((long long)nx * ny)) + pz;
+    cx = 2 * int(ci % nx) + px;
+    cy = 2 * int((ci / nx) % ny) + py;
+    cz = 2 * int(ci / ((long long)nx * ny)) + pz;
     cell = ((long long)cz * h.ncy + cy) * h.ncx + cx;
-    if (l < L) {
-      const AT* A = Ac + cell * 27 * L * L;
-      for (int bb = q; bb < 27; bb += ROW_SLOTS) {
-        const int ox = bb % 3 - 1, oy = (bb / 3) % 3 - 1, oz = bb / 9 - 1;
-        const int ncol = ((px + ox) & 1) + 2 * ((py + oy) & 1) + 4 * ((pz + oz) & 1);
-        if (forward ? (ncol >= colour) : (ncol <= colour)) continue;
-        bool ok;
-        const long long nc = nb_cell(h, cx, cy, cz, bb, ok);
-        if (!ok) continue;
-        for (int m = 0; m < L; ++m) part += ld<VT, AT>(A, (bb * L + l) * L + m) * x[nc * L + m];
-      }
-    }
   }
+  const VT bi = row ? b[cell * L + l] : VT(0);
+  VT dv[L];
+#pragma unroll
+  for (int m = 0; m < L; ++m) dv[m] = row ? ld<VT, AT>(Dinv, (cell * L + l) * L + m) : VT(0);
+  VT part = row_products<VT, AT, L>(h, Ac + cell * 27 * L * L, x, cx, cy, cz, l, q, row, [&](int bb) {
+    const int ox = bb % 3 - 1, oy = (bb / 3) % 3 - 1, oz = bb / 9 - 1;
+    const int ncol = ((px + ox) & 1) + 2 * ((py + oy) & 1) + 4 * ((pz + oz) & 1);
+    return forward ? (ncol < colour) : (ncol > colour);
+  });
   // row sums over the 8 slots (xor within aligned groups of 8 lanes)
 #pragma unroll
   for (int off = 1; off < ROW_SLOTS; off <<= 1) part += __shfl_xor(part, off, 64);
-  const VT t = (valid && l < L) ? b[cell * L + l] - part : VT(0);
+  const VT t = row ? bi - part : VT(0);
   // x_i = D_i^-1 t: lane (l, 0) of each row computes row l
   const int base = (threadIdx.x / CL) * CL;
   VT upd = VT(0);
+#pragma unroll
   for (int m = 0; m < L; ++m) {
     const VT tm = __shfl(t, base + m * ROW_SLOTS, 64);
-    if (valid && l < L) upd += ld<VT, AT>(Dinv, (cell * L + l) * L + m) * tm;
+    if (row) upd += dv[m] * tm;
   }
-  if (valid && l < L && q == 0) x[cell * L + l] = upd;
+  if (row && q == 0) x[cell * L + l] = upd;
 }
 
-// t = b - A_c x on every cell (CELL_LANES lanes per cell as in the sweep).
-template <typename VT, typename AT>
-__global__ void k_ac_residual(Hier h, int LP, const AT* __restrict__ Ac, const VT* __restrict__ b,
+// t = b - A_c x on every cell (lanes per cell as in the sweep).
+template <typename VT, typename AT, int L>
+__global__ void k_ac_residual(Hier h, const AT* __restrict__ Ac, const VT* __restrict__ b,
                               const VT* __restrict__ x, VT* __restrict__ t, const Scalars* sc) {
   if (sc && sc->done) return;
-  const int L = h.Lc;
-  const int CL = LP * ROW_SLOTS;
+  constexpr int CL = lanes_pow2<L>() * ROW_SLOTS;
   const long long gtid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   const int lane = int(gtid % CL);
   const int l = lane / ROW_SLOTS, q = lane % ROW_SLOTS;
   const long long cell = gtid / CL;
-  const bool valid = cell < h.ncells && l < L;
-  VT part = VT(0);
-  if (valid) {
-    const int cx = int(cell % h.ncx), cy = int((cell / h.ncx) % h.ncy), cz = int(cell / ((long long)h.ncx * h.ncy));
-    const AT* A = Ac + cell * 27 * L * L;
-    for (int bb = q; bb < 27; bb += ROW_SLOTS) {
-      bool ok;
-      const long long nc = nb_cell(h, cx, cy, cz, bb, ok);
-      if (!ok) continue;
-      for (int m = 0; m < L; ++m) part += ld<VT, AT>(A, (bb * L + l) * L + m) * x[nc * L + m];
-    }
+  const bool row = cell < h.ncells && l < L;
+  int cx = 0, cy = 0, cz = 0;
+  if (row) {
+    cx = int(cell % h.ncx);
+    cy = int((cell / h.ncx) % h.ncy);
+    cz = int(cell / ((long long)h.ncx * h.ncy));
   }
+  const VT bi = row ? b[cell * L + l] : VT(0);
+  VT part = row_products<VT, AT, L>(h, Ac + (row ? cell : 0) * 27 * L * L, x, cx, cy, cz, l, q, row,
+                                    [](int) { return true; });
 #pragma unroll
   for (int off = 1; off < ROW_SLOTS; off <<= 1) part += __shfl_xor(part, off, 64);
-  if (valid && q == 0) t[cell * L + l] = b[cell * L + l] - part;
+  if (row && q == 0) t[cell * L + l] = bi - part;
 }
 
 // r_cc[J*Lcc + b] = sum_d R_cc[J][b][d] t[cc_dofs[d]]: one wave per output entry.
@@ -153,6 +197,22 @@ __global__ void k_cc_prolong(Hier h, int n_c, const VT* __restrict__ Rcc, const 
 }
 
 // ---------------------------------------------------------------------------
+// dispatch over the number of basis vectors per cell (1 .. LC_MAX)
+#define COARSE_L_DISPATCH(Lrt, ...)                          \
+  do {                                                       \
+    switch (Lrt) {                                           \
+      case 1: { constexpr int LL = 1; __VA_ARGS__; } break;  \
+      case 2: { constexpr int LL = 2; __VA_ARGS__; } break;  \
+      case 3: { constexpr int LL = 3; __VA_ARGS__; } break;  \
+      case 4: { constexpr int LL = 4; __VA_ARGS__; } break;  \
+      case 5: { constexpr int LL = 5; __VA_ARGS__; } break;  \
+      case 6: { constexpr int LL = 6; __VA_ARGS__; } break;  \
+      case 7: { constexpr int LL = 7; __VA_ARGS__; } break;  \
+      default: { constexpr int LL = 8; __VA_ARGS__; } break; \
+    }                                                        \
+  } while (0)
+static_assert(LC_MAX == 8, "COARSE_L_DISPATCH covers 1 .. 8");
+
 static inline int lanes_per_cell(int L) {
   int lp = 1;
   while (lp < L) lp <<= 1;
@@ -169,7 +229,7 @@ void launch_gs_sweep(const Ctx& c, const void* b, void* x, bool forward, hipStre
     if (ncol == 0) continue;
     const long long nthreads = ncol * LP * ROW_SLOTS;
     const dim3 gr((unsigned)((nthreads + 255) / 256)), bl(256);
-#define GS(VT, AT) hipLaunchKernelGGL((k_gs_colour<VT, AT>), gr, bl, 0, s, h, colour, forward ? 1 : 0, LP, (const AT*)c.cc.Ac, (const AT*)c.cc.AcDinv, (const VT*)b, (VT*)x, c.sc)
+#define GS(VT, AT) COARSE_L_DISPATCH(h.Lc, hipLaunchKernelGGL((k_gs_colour<VT, AT, LL>), gr, bl, 0, s, h, colour, forward ? 1 : 0, (const AT*)c.cc.Ac, (const AT*)c.cc.AcDinv, (const VT*)b, (VT*)x, c.sc))
     if (c.cc.a_dt == DT_F64) GS(double, double);
     else GS(double, float);
 #undef GS
@@ -180,7 +240,7 @@ void launch_ac_residual(const Ctx& c, const void* b, const void* x, void* t, hip
   const int LP = lanes_per_cell(c.h.Lc);
   const long long n = (long long)c.h.ncells * LP * ROW_SLOTS;
   const dim3 gr((unsigned)((n + 255) / 256)), bl(256);
-#define AR(VT, AT) hipLaunchKernelGGL((k_ac_residual<VT, AT>), gr, bl, 0, s, c.h, LP, (const AT*)c.cc.Ac, (const VT*)b, (const VT*)x, (VT*)t, c.sc)
+#define AR(VT, AT) COARSE_L_DISPATCH(c.h.Lc, hipLaunchKernelGGL((k_ac_residual<VT, AT, LL>), gr, bl, 0, s, c.h, (const AT*)c.cc.Ac, (const VT*)b, (const VT*)x, (VT*)t, c.sc))
   if (c.cc.a_dt == DT_F64) AR(double, double);
   else AR(double, float);
 #undef AR

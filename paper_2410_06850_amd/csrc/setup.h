@@ -13,7 +13,7 @@ namespace msmg {
 // Pivot block of the batched symmetric Gauss-Jordan (sweep) inverse and its
 // workspace: per matrix the inverted pivot block (GJ_NB^2) and the pivot row
 // panel (GJ_NB x n).
-constexpr int GJ_NB = 64;
+constexpr int GJ_NB = 128;  // pivot columns per sweep step (64-deep halves per tile)
 inline size_t gj_workspace_doubles(int n, int batch) {
   return (size_t)batch * ((size_t)GJ_NB * GJ_NB + (size_t)GJ_NB * n);
 }

@@ -639,10 +639,13 @@ __global__ void k_acc_pad(Hier h, const int* __restrict__ cc_ptr, int n_cc, doub
 //
 // Pivot block: invert the current A_KK (SPD, read from the lower triangle) in
 // LDS by unblocked Gauss-Jordan, keep P, store -P; 1024 threads, each owning
-// the entries tid + 1024 q of the nb x nb block.
+// the entries tid + 1024 q of the nb x nb block (dynamic LDS, GJ_PIVOT_LDS).
+constexpr int GJ_PLD = GJ_NB + 1;
+constexpr size_t GJ_PIVOT_LDS = sizeof(double) * (GJ_NB * GJ_PLD + 2 * GJ_NB);
 __global__ __launch_bounds__(1024) void k_gj_pivot(int n, double* __restrict__ Ab, int k0, int nb,
                                                    double* __restrict__ Pb) {
-  __shared__ double a[GJ_NB][GJ_NB + 1];
+  extern __shared__ double gjp_lds[];
+  auto a = [&](int r, int c) -> double& { return gjp_lds[r * GJ_PLD + c]; };
   constexpr int NQ = (GJ_NB * GJ_NB + 1023) / 1024;
   double* A = Ab + (long long)blockIdx.z * n * n;
   double* P = Pb + (long long)blockIdx.z * GJ_NB * GJ_NB;
@@ -653,32 +656,29 @@ __global__ __launch_bounds__(1024) void k_gj_pivot(int n, double* __restrict__ A
     const int e = tid + 1024 * q;
     if (e < ne) {
       const int r = e / nb, c = e % nb;
-      a[r][c] = A[(long long)(k0 + max(r, c)) * n + (k0 + min(r, c))];
+      a(r, c) = A[(long long)(k0 + max(r, c)) * n + (k0 + min(r, c))];
     }
   }
   __syncthreads();
+  // pivot row and column of the current step, copied before the update
+  double* rowk = gjp_lds + GJ_NB * GJ_PLD;
+  double* colk = rowk + GJ_NB;
   for (int k = 0; k < nb; ++k) {
-    const double piv = 1.0 / a[k][k];
-    double akc[NQ], ark[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int e = tid + 1024 * q;
-      akc[q] = ark[q] = 0.0;
-      if (e < ne) {
-        akc[q] = a[k][e % nb];
-        ark[q] = a[e / nb][k];
-      }
+    if (tid < nb) {
+      rowk[tid] = a(k, tid);
+      colk[tid] = a(tid, k);
     }
     __syncthreads();
-#pragma unroll
+    const double piv = 1.0 / rowk[k];
+#pragma unroll 4
     for (int q = 0; q < NQ; ++q) {
       const int e = tid + 1024 * q;
       if (e >= ne) continue;
       const int r = e / nb, c = e % nb;
-      if (r == k && c == k) a[r][c] = piv;
-      else if (r == k) a[r][c] = akc[q] * piv;
-      else if (c == k) a[r][c] = -ark[q] * piv;
-      else a[r][c] = a[r][c] - ark[q] * akc[q] * piv;
+      if (r == k && c == k) a(r, c) = piv;
+      else if (r == k) a(r, c) = rowk[c] * piv;
+      else if (c == k) a(r, c) = -colk[r] * piv;
+      else a(r, c) = a(r, c) - colk[r] * rowk[c] * piv;
     }
     __syncthreads();
   }
@@ -687,14 +687,14 @@ __global__ __launch_bounds__(1024) void k_gj_pivot(int n, double* __restrict__ A
     const int e = tid + 1024 * q;
     if (e >= ne) continue;
     const int r = e / nb, c = e % nb;
-    P[r * nb + c] = a[r][c];
-    A[(long long)(k0 + r) * n + (k0 + c)] = -a[r][c];
+    P[r * nb + c] = a(r, c);
+    A[(long long)(k0 + r) * n + (k0 + c)] = -a(r, c);
   }
 }
 
 // The two products of a sweep step on 64 x 64 output tiles, computed by FP64
-// matrix cores (inner dimension: the nb pivot columns), reading A through its
-// lower triangle (A_xy = A[max][min]):
+// matrix cores (inner dimension: the nb <= GJ_NB pivot columns, staged in
+// 64-deep halves), reading A through its lower triangle (A_xy = A[max][min]):
 //   GJ_ROW:    Rb[r][j]  =  sum_t P[r][t] A[k0+t][j]     (j outside the pivot block)
 //   GJ_UPDATE: A[i][j]  -=  sum_t A[i][k0+t] Rb[t][j]    (i >= j tiles, both outside it)
 // Each wave owns a 32 x 32 quarter of the tile as 2 x 2 blocks of
@@ -702,26 +702,30 @@ __global__ __launch_bounds__(1024) void k_gj_pivot(int n, double* __restrict__ A
 // operand: column lane % 16, k lane / 16; result register v: column
 // lane % 16, row lane / 16 + 4 v, as measured on gfx950).  Both operands are
 // staged in LDS with row strides chosen so that the operand reads of 32 lanes
-// hit distinct banks; every thread issues all its global loads (and, for the
-// update, its part of the output tile) before the first LDS store, so the
-// loads of a tile are in flight together.  Operand entries beyond nb are zero.
+// hit distinct banks; every thread issues all its global loads of a half (and,
+// for the update, its part of the output tile) before the first LDS store, so
+// the loads of a tile are in flight together.  Operand entries beyond nb are
+// zero.  A pass over the lower triangle per step is what bounds the update, so
+// the wider pivot block halves the passes for the same arithmetic.
 typedef double gj_v4d __attribute__((ext_vector_type(4)));
 constexpr int GJ_LDA = 66, GJ_LDB = 80;
-constexpr size_t GJ_TILE_LDS = sizeof(double) * (64 * GJ_LDA + GJ_NB * GJ_LDB);
+constexpr int GJ_HALVES = GJ_NB / 64;
+static_assert(GJ_NB % 64 == 0, "pivot blocks of whole 64-deep halves");
+constexpr size_t GJ_TILE_LDS = sizeof(double) * (64 * GJ_LDA + 64 * GJ_LDB);
 constexpr long long GJ_WORKGROUPS = 2048;  // persistent tile loops: a few rounds of resident workgroups
 enum { GJ_ROW = 0, GJ_UPDATE = 2 };
 
 template <int MODE>
 __global__ __launch_bounds__(256) void k_gj_tile(int n, double* __restrict__ Ab, int k0, int nb,
                                                  const double* __restrict__ Pb, double* __restrict__ Rbb, int batch) {
-  static_assert(GJ_NB == 64, "tiles assume 64 pivot columns");
   extern __shared__ double gj_lds[];
   double* As = gj_lds;                 // As[r][t], 64 x GJ_LDA
-  double* Bs = gj_lds + 64 * GJ_LDA;   // Bs[t][c], GJ_NB x GJ_LDB
-  // tiles per matrix: the row panel's nt tiles, or the nt (nt + 1) / 2 tiles of the
-  // lower triangle; workgroups loop over (matrix, tile) pairs
+  double* Bs = gj_lds + 64 * GJ_LDA;   // Bs[t][c], 64 x GJ_LDB
+  // tiles per matrix: the row panel's GJ_HALVES x nt tiles (tile row = 64
+  // pivot rows), or the nt (nt + 1) / 2 tiles of the lower triangle;
+  // workgroups loop over (matrix, tile) pairs
   const int nt = (n + 63) / 64;
-  const long long per = MODE == GJ_ROW ? nt : (long long)nt * (nt + 1) / 2;
+  const long long per = MODE == GJ_ROW ? (long long)GJ_HALVES * nt : (long long)nt * (nt + 1) / 2;
   const long long total = per * batch;
   for (long long wk = blockIdx.x; wk < total; wk += gridDim.x) {
     const long long z = wk / per, tl = wk % per;
@@ -732,11 +736,14 @@ __global__ __launch_bounds__(256) void k_gj_tile(int n, double* __restrict__ Ab,
       while ((long long)(ti + 1) * (ti + 2) / 2 <= tl) ++ti;
       while ((long long)ti * (ti + 1) / 2 > tl) --ti;
       tj = int(tl - (long long)ti * (ti + 1) / 2);
+    } else {
+      ti = int(tl / nt);  // tile row of the panel: pivot rows 64 ti ..
+      tj = int(tl % nt);
     }
     const int i0 = ti * 64, j0 = tj * 64;
     const bool ipiv_tile = i0 >= k0 && i0 + 64 <= k0 + nb, jpiv_tile = j0 >= k0 && j0 + 64 <= k0 + nb;
     if (MODE == GJ_UPDATE && (ipiv_tile || jpiv_tile)) continue;  // pivot rows/columns: write-back
-    if (MODE == GJ_ROW && jpiv_tile) continue;
+    if (MODE == GJ_ROW && (jpiv_tile || i0 >= nb)) continue;
     double* A = Ab + z * n * n;
     const double* P = Pb + z * GJ_NB * GJ_NB;
     double* Rb = Rbb + z * GJ_NB * n;
@@ -745,9 +752,9 @@ __global__ __launch_bounds__(256) void k_gj_tile(int n, double* __restrict__ Ab,
     const int l16 = lane & 15, lk = lane >> 4;
     // entry (i, j) of the symmetric matrix from its lower triangle
     auto sym = [&](int i, int j) { return A[(long long)max(i, j) * n + min(i, j)]; };
-    auto a_elem = [&](int r, int t) -> double {  // A operand [r][t]
+    auto a_elem = [&](int r, int t) -> double {  // A operand [r][t] (t: pivot column)
       if (t >= nb) return 0.0;
-      if (MODE == GJ_ROW) return r < nb ? P[r * nb + t] : 0.0;
+      if (MODE == GJ_ROW) return i0 + r < nb ? P[(i0 + r) * nb + t] : 0.0;
       const int i = i0 + r;
       return i < n ? sym(i, k0 + t) : 0.0;
     };
@@ -760,7 +767,7 @@ __global__ __launch_bounds__(256) void k_gj_tile(int n, double* __restrict__ Ab,
     auto out_ok = [&](int i, int j) {
       const bool iok = i < n && !(i >= k0 && i < k0 + nb), jok = j < n && !(j >= k0 && j < k0 + nb);
       if (MODE == GJ_UPDATE) return iok && jok;
-      return i - i0 < nb && jok;
+      return i < nb && jok;
     };
     // panels read through the upper triangle's mirror (rows above or columns
     // right of the pivot block) are contiguous along the other index: let
@@ -776,15 +783,17 @@ __global__ __launch_bounds__(256) void k_gj_tile(int n, double* __restrict__ Ab,
       c = b_tr ? (e >> 6) : (e & 63);
     };
     double ra[16], rb[16];
+    auto load_half = [&](int t0) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int e = tid + 256 * q;
-      int r, t, c;
-      a_rt(e, r, t);
-      ra[q] = a_elem(r, t);
-      b_tc(e, t, c);
-      rb[q] = b_elem(t, c);
-    }
+      for (int q = 0; q < 16; ++q) {
+        const int e = tid + 256 * q;
+        int r, t, c;
+        a_rt(e, r, t);
+        ra[q] = a_elem(r, t0 + t);
+        b_tc(e, t, c);
+        rb[q] = b_elem(t0 + t, c);
+      }
+    };
     gj_v4d cv[2][2];
     if (MODE == GJ_UPDATE) {
 #pragma unroll
@@ -797,33 +806,40 @@ __global__ __launch_bounds__(256) void k_gj_tile(int n, double* __restrict__ Ab,
             cv[bi][bj][v] = out_ok(i, j) ? A[(long long)i * n + j] : 0.0;
           }
     }
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int e = tid + 256 * q;
-      int r, t, c;
-      a_rt(e, r, t);
-      As[r * GJ_LDA + t] = ra[q];
-      b_tc(e, t, c);
-      Bs[t * GJ_LDB + c] = rb[q];
-    }
-    __syncthreads();
     gj_v4d acc[2][2];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
       for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = gj_v4d{0.0, 0.0, 0.0, 0.0};
-    const int ksteps = (nb + 3) / 4;
+#pragma unroll 1
+    for (int hf = 0; hf < GJ_HALVES; ++hf) {
+      const int t0 = hf * 64;
+      if (t0 >= nb) break;  // uniform over the workgroup
+      load_half(t0);
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int e = tid + 256 * q;
+        int r, t, c;
+        a_rt(e, r, t);
+        As[r * GJ_LDA + t] = ra[q];
+        b_tc(e, t, c);
+        Bs[t * GJ_LDB + c] = rb[q];
+      }
+      __syncthreads();
+      const int ksteps = (min(64, nb - t0) + 3) / 4;
 #pragma unroll 4
-    for (int ks = 0; ks < ksteps; ++ks) {
-      const int kk = ks * 4 + lk;
-      const double a0 = As[(wr + l16) * GJ_LDA + kk];
-      const double a1 = As[(wr + 16 + l16) * GJ_LDA + kk];
-      const double b0 = Bs[kk * GJ_LDB + wc + l16];
-      const double b1 = Bs[kk * GJ_LDB + wc + 16 + l16];
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+      for (int ks = 0; ks < ksteps; ++ks) {
+        const int kk = ks * 4 + lk;
+        const double a0 = As[(wr + l16) * GJ_LDA + kk];
+        const double a1 = As[(wr + 16 + l16) * GJ_LDA + kk];
+        const double b0 = Bs[kk * GJ_LDB + wc + l16];
+        const double b1 = Bs[kk * GJ_LDB + wc + 16 + l16];
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+      }
+      __syncthreads();  // the next half (or tile) overwrites the staged operands
     }
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
@@ -834,9 +850,8 @@ __global__ __launch_bounds__(256) void k_gj_tile(int n, double* __restrict__ Ab,
           const int i = i0 + wr + bi * 16 + lk + 4 * v, j = j0 + wc + bj * 16 + l16;
           if (!out_ok(i, j)) continue;
           if (MODE == GJ_UPDATE) A[(long long)i * n + j] = cv[bi][bj][v] - acc[bi][bj][v];
-          else Rb[(long long)(i - i0) * n + j] = acc[bi][bj][v];
+          else Rb[(long long)i * n + j] = acc[bi][bj][v];
         }
-    __syncthreads();  // the next tile overwrites the staged panels
   }
 }
 
@@ -1180,14 +1195,17 @@ int gj_inverse(int n, int batch, double* A, double* work, hipStream_t s) {
   for (const void* f : {(const void*)k_gj_tile<GJ_ROW>, (const void*)k_gj_tile<GJ_UPDATE>})
     if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(GJ_TILE_LDS)) != hipSuccess)
       return MSMG_EHIP;
+  if (hipFuncSetAttribute((const void*)k_gj_pivot, hipFuncAttributeMaxDynamicSharedMemorySize, int(GJ_PIVOT_LDS)) !=
+      hipSuccess)
+    return MSMG_EHIP;
   const unsigned nt = unsigned((n + 63) / 64);
   for (int k0 = 0; k0 < n; k0 += GJ_NB) {
     const int nb = std::min(GJ_NB, n - k0);
-    hipLaunchKernelGGL(k_gj_pivot, dim3(1, 1, batch), dim3(1024), 0, s, n, A, k0, nb, P);
-    // the row panel tiles run along j (one tile row at i0 = 0); the update covers
+    hipLaunchKernelGGL(k_gj_pivot, dim3(1, 1, batch), dim3(1024), GJ_PIVOT_LDS, s, n, A, k0, nb, P);
+    // the row panel tiles run along j (GJ_NB / 64 tile rows); the update covers
     // the lower triangle; both loop over (matrix, tile) pairs on at most
     // GJ_WORKGROUPS workgroups
-    const long long nrow = (long long)nt * batch, nupd = (long long)nt * (nt + 1) / 2 * batch;
+    const long long nrow = (long long)GJ_HALVES * nt * batch, nupd = (long long)nt * (nt + 1) / 2 * batch;
     hipLaunchKernelGGL(k_gj_tile<GJ_ROW>, dim3((unsigned)std::min<long long>(nrow, GJ_WORKGROUPS)), dim3(256),
                        GJ_TILE_LDS, s, n, A, k0, nb, P, Rb, batch);
     hipLaunchKernelGGL(k_gj_tile<GJ_UPDATE>, dim3((unsigned)std::min<long long>(nupd, GJ_WORKGROUPS)), dim3(256),

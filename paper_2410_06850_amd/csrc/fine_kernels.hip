@@ -104,7 +104,7 @@ MSMG_DEV void dd_add(double& hi, double& lo, double a, double ae) {
   lo = t - (hi - s);
 }
 
-__global__ void k_update_xr(double* __restrict__ x, double* __restrict__ xlo, double* __restrict__ r,
+__global__ void k_update_xr(double* __restrict__ x, float* __restrict__ xlo, double* __restrict__ r,
                             const double* __restrict__ p, const double* __restrict__ q, long long nn, Scalars* sc,
                             double* partials, unsigned* counter) {
   if (sc->done) return;
@@ -116,10 +116,10 @@ __global__ void k_update_xr(double* __restrict__ x, double* __restrict__ xlo, do
     const double pn = p[n];
     const double prod = a * pn;
     const double perr = fma(a, pn, -prod);
-    double hi = x[n], lo = xlo[n];
+    double hi = x[n], lo = double(xlo[n]);
     dd_add(hi, lo, prod, perr);
     x[n] = hi;
-    xlo[n] = lo;
+    xlo[n] = float(lo);  // |lo| <= ulp(hi) / 2: FP32 keeps about 77 bits of the sum
     const double rn = r[n] - a * q[n];
     r[n] = rn;
     s[0] += rn * rn;
@@ -142,16 +142,16 @@ __global__ void k_update_xr(double* __restrict__ x, double* __restrict__ xlo, do
 
 // T = xhi + xlo rounded (or xlo copied out when tlo is given) on free nodes;
 // fixed values (or 0) on fixed nodes.
-__global__ void k_finish_solution_dd(double* __restrict__ T, const double* __restrict__ xlo, double* __restrict__ tlo,
+__global__ void k_finish_solution_dd(double* __restrict__ T, const float* __restrict__ xlo, double* __restrict__ tlo,
                                      const double* __restrict__ tfix, const uint32_t* __restrict__ bits, long long nn) {
   for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < nn; n += (long long)gridDim.x * blockDim.x) {
     if (mask_bit(bits, n)) {
       T[n] = tfix ? tfix[n] : 0.0;
       if (tlo) tlo[n] = 0.0;
     } else if (tlo) {
-      tlo[n] = xlo[n];
+      tlo[n] = double(xlo[n]);
     } else {
-      T[n] = T[n] + xlo[n];
+      T[n] = T[n] + double(xlo[n]);
     }
   }
 }
@@ -229,7 +229,7 @@ MSMG_MARCH_KERNEL void k_apply(
 template <typename RT, bool CUBIC>
 __global__ void k_residual(Geo g, Stencil st, Hier h, int CX, const RT* __restrict__ rho, Material m,
                            const uint32_t* __restrict__ bits, const double* __restrict__ b,
-                           const double* __restrict__ x, const double* __restrict__ xlo, double* __restrict__ y,
+                           const double* __restrict__ x, const float* __restrict__ xlo, double* __restrict__ y,
                            Scalars* sc, double* partials, unsigned* counter) {
   __shared__ double red[16];
   TILE_PROLOGUE
@@ -248,7 +248,7 @@ __global__ void k_residual(Geo g, Stencil st, Hier h, int CX, const RT* __restri
                                                      [&](int a, int bb, int c) { return x[node_id(g, a, bb, c)]; });
             if (xlo)
               out -= gather_apply<double, CUBIC>(g, st, kk, i, j, k,
-                                                 [&](int a, int bb, int c) { return xlo[node_id(g, a, bb, c)]; });
+                                                 [&](int a, int bb, int c) { return double(xlo[node_id(g, a, bb, c)]); });
           }
           y[n] = out;
           s[0] += out * out;
@@ -815,12 +815,12 @@ void launch_norm2(const Ctx& c, const double* v, int what, double rtol2, hipStre
   hipLaunchKernelGGL(k_norm2, dim3(nb), dim3(256), 0, s, v, c.g.nn, what, rtol2, c.sc, c.partials, c.counter);
 }
 
-void launch_update_xr(const Ctx& c, double* x, double* xlo, double* r, const double* p, const double* q, hipStream_t s) {
+void launch_update_xr(const Ctx& c, double* x, float* xlo, double* r, const double* p, const double* q, hipStream_t s) {
   const int nb = grid1d(c.g.nn, 256, c.red_blocks);
   hipLaunchKernelGGL(k_update_xr, dim3(nb), dim3(256), 0, s, x, xlo, r, p, q, c.g.nn, c.sc, c.partials, c.counter);
 }
 
-void launch_finish_solution_dd(const Ctx& c, double* T, const double* xlo, double* tlo, const double* tfix, hipStream_t s) {
+void launch_finish_solution_dd(const Ctx& c, double* T, const float* xlo, double* tlo, const double* tfix, hipStream_t s) {
   hipLaunchKernelGGL(k_finish_solution_dd, dim3(grid1d(c.g.nn, 256, 8192)), dim3(256), 0, s, T, xlo, tlo, tfix, c.bits, c.g.nn);
 }
 
@@ -864,7 +864,7 @@ void launch_apply(const Ctx& c, const double* x, double* y, int mode, hipStream_
 #undef APL
 }
 
-void launch_residual(const Ctx& c, const double* b, const double* x, const double* xlo, double* y, bool reduce,
+void launch_residual(const Ctx& c, const double* b, const double* x, const float* xlo, double* y, bool reduce,
                      hipStream_t s) {
   const dim3 gr = tile_grid(c), bl = tile_block(c);
   Scalars* sc = reduce ? c.sc : nullptr;

@@ -86,13 +86,13 @@ void launch_diag_inv(const Ctx& c, const void* rho, int rdt, void* dinv, int vdt
 void launch_zero_fixed_copy(const Ctx& c, const double* in, double* out, hipStream_t s);
 void launch_finish_solution(const Ctx& c, double* T, const double* tfix, hipStream_t s);
 void launch_norm2(const Ctx& c, const double* v, int what, double rtol2, hipStream_t s);
-void launch_update_xr(const Ctx& c, double* x, double* xlo, double* r, const double* p, const double* q, hipStream_t s);
-void launch_finish_solution_dd(const Ctx& c, double* T, const double* xlo, double* tlo, const double* tfix, hipStream_t s);
+void launch_update_xr(const Ctx& c, double* x, float* xlo, double* r, const double* p, const double* q, hipStream_t s);
+void launch_finish_solution_dd(const Ctx& c, double* T, const float* xlo, double* tlo, const double* tfix, hipStream_t s);
 void launch_update_p(const Ctx& c, double* p, const double* z, hipStream_t s);
 // y = A x (mode 0), with p^T A p -> alpha (mode 1), or P A P xraw + (I - P) xraw
 // (mode 2, x = xraw with zero fixed entries).  x is zero on fixed nodes.
 void launch_apply(const Ctx& c, const double* x, double* y, int mode, hipStream_t s, const double* xraw = nullptr);
-void launch_residual(const Ctx& c, const double* b, const double* x, const double* xlo, double* y, bool reduce,
+void launch_residual(const Ctx& c, const double* b, const double* x, const float* xlo, double* y, bool reduce,
                      hipStream_t s);
 void launch_smooth(const Ctx& c, const void* in, bool in_is_f64, void* out, hipStream_t s);
 void launch_restrict(const Ctx& c, const void* r, void* rc, hipStream_t s);

@@ -82,7 +82,7 @@ struct msmg_handle {
 
   // PCG vectors (FP64)
   double *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr, *b = nullptr;
-  double* xlo = nullptr;  // low part of the double-double iterate
+  float* xlo = nullptr;   // low part of the double-double iterate (|lo| <= ulp(hi) / 2, FP32)
   // V-cycle vectors (v_dt) and coarse vectors
   void *v_r1 = nullptr, *v_r2 = nullptr, *v_res = nullptr, *v_t0 = nullptr, *v_t1 = nullptr;
   void *c_rc = nullptr, *c_x0 = nullptr, *c_t = nullptr, *c_x1 = nullptr, *c_d = nullptr;
@@ -409,7 +409,7 @@ static int alloc_arrays(msmg_handle* h, bool dry, size_t* total) {
     A(&h->r, nn * 8); A(&h->p, nn * 8); A(&h->q, nn * 8); A(&h->z, nn * 8);
   }
   A(&h->b, nn * 8);
-  A(&h->xlo, nn * 8);
+  A(&h->xlo, nn * 4);
   A(&h->v_r1, nn * vs); A(&h->v_res, nn * vs);
   if (o.cheb_degree > 2) { A(&h->v_t0, nn * vs); A(&h->v_t1, nn * vs); }
   // one slot per workgroup of any reducing launch (tiles, march, 1-D grids)
@@ -787,7 +787,7 @@ static int solve_impl(msmg_handle* h, const double* f, double* T, double* T_lo, 
   launch_fill(c, h->p, 0.0, s);
   launch_sc_reset(c, 1, maxit, s);
   launch_norm2(c, h->b, 0, rtol * rtol, s);  // bb, tol2
-  launch_fill(c, h->xlo, 0.0, s);
+  HIP_TRY(hipMemsetAsync(h->xlo, 0, sizeof(float) * size_t(c.g.nn), s));
   if (use_x0) launch_residual(c, h->b, x, nullptr, h->r, false, s);
   else launch_copy(c, h->b, h->r, s);
   launch_norm2(c, h->r, 1, 0.0, s);  // rr

@@ -9,8 +9,10 @@ from ``synth`` (seeded generators without solver arithmetic).
 
 Modules
   q1      discretisation: element matrix, assembly, load, Dirichlet lifting,
-          compliance, adjoint sensitivity (paper section 2 and its
-          ``material``, ``new linear system`` and ``adjoint`` equations).
+          compliance, adjoint sensitivity, the design-dependent heat source
+          and the mean-temperature objective (paper section 2 and its
+          ``material``, ``new linear system``, ``cost function`` and
+          ``adjoint`` equations).
   msmg    three-grid multiscale preconditioner and PCG (paper section 3,
           Algorithm 1, equations ``spepb`` and ``spectral cc``).
   interp  grid-to-grid interpolation of temperatures and densities (the

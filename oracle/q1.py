@@ -10,7 +10,9 @@ Paper anchors
     trilinear (Q1) hexahedral elements instead of the paper's two-point flux
     finite volumes (the nodal reading is the one this project solves);
   * adjoint sensitivity, section 2.3, eq. (adjoint): A u = dc/dt and
-    dc/dx = u^T (df/dx - dA/dx t), with df/dx = 0 for a fixed source.
+    dc/dx = u^T (df/dx - dA/dx t), with df/dx = 0 for a fixed source and
+    df/dx from eq. (material) for the design-dependent heat source f0 (1 - x^p);
+  * mean-temperature objective, section 2.3 eq. (cost function).
 
 Layouts: nodes n = (k (ny+1) + j)(nx+1) + i, elements e = (k ny + j) nx + i
 (x fastest); element-local node a = ax + 2 ay + 4 az.
@@ -219,6 +221,48 @@ def sensitivity(grid, rho, T, lam, kmin, kmax, p):
     le = np.asarray(lam).ravel()[en]
     q = np.einsum("ea,ab,eb->e", le, K0, Te)
     return -dk * q
+
+
+def heat_source(rho, f0, p):
+    """Section 2.1 eq. (material), second line: element heat generation
+    f_e = f0 (1 - rho_e^p), rho^p by repeated products."""
+    rho = np.asarray(rho, dtype=np.float64)
+    rp = rho.copy()
+    for _ in range(int(p) - 1):
+        rp = rp * rho
+    return f0 * (1.0 - rp)
+
+
+def heat_source_load(grid, rho, f0, p):
+    """Nodal load of the design-dependent source: f_n = sum_{e ni n} f0 (1 - rho_e^p) V / 8."""
+    return element_load(grid, heat_source(np.asarray(rho).ravel(), f0, p))
+
+
+def mean_temperature_weights(grid):
+    """Section 2.3 eq. (cost function) on Q1 nodes: c = (1/|Omega|) int T dx = w^T T.
+
+    The paper averages its cell temperatures; for the nodal Q1 field the same
+    mean is the integral of T over the box divided by the box volume, whose
+    weights are the consistent load of the constant source 1/|Omega|.
+    """
+    return element_load(grid, 1.0 / (grid.nelem * grid.vol))
+
+
+def sensitivity_heat_source(grid, rho, T, lam, kmin, kmax, p, f0):
+    """dc/drho_e = lam^T (df/drho_e - dA/drho_e T)  (section 2.3, with the
+    design-dependent source of eq. (material)).
+
+    df/drho_e puts -f0 p rho_e^(p-1) V / 8 on each node of e, so
+    dc/drho_e = -(dk/drho)_e lam_e^T K0 T_e - f0 p rho_e^(p-1) (V / 8) sum_a lam_a.
+    lam is the adjoint (zero on fixed nodes); T carries the fixed values.
+    """
+    rho = np.asarray(rho, dtype=np.float64).ravel()
+    rp = np.ones_like(rho)
+    for _ in range(int(p) - 1):
+        rp = rp * rho
+    en = grid.element_nodes()
+    lsum = np.asarray(lam, dtype=np.float64).ravel()[en].sum(axis=1)
+    return sensitivity(grid, rho, T, lam, kmin, kmax, p) - f0 * p * rp * (grid.vol / 8.0) * lsum
 
 
 def apply_elementwise(grid, kelem, x, mask=None, zslab=16):

@@ -215,6 +215,76 @@ def test_general_adjoint_fd():
     assert abs(fd - dL @ d) <= 1e-6 * abs(dL @ d)
 
 
+def test_heat_source_load_invariants():
+    """eq. (material), second line: the design-dependent source and its load."""
+    g = q1.Grid(4, 3, 5)
+    rho = np.random.default_rng(3).uniform(0.0, 1.0, g.nelem)
+    f0, p = 2.5, 3
+    fs = q1.heat_source_load(g, rho, f0, p)
+    # total heat is the integral of f0 (1 - rho^p) over the box
+    assert abs(fs.sum() - f0 * np.sum(1.0 - rho ** 3) * g.vol) <= 1e-14 * abs(fs.sum())
+    # void generates f0 everywhere, solid nothing
+    assert np.allclose(q1.heat_source_load(g, np.zeros(g.nelem), f0, p), q1.element_load(g, f0), rtol=0, atol=1e-16)
+    assert np.abs(q1.heat_source_load(g, np.ones(g.nelem), f0, p)).max() == 0.0
+    # p = 1 at rho = 1/2: half the void source
+    assert np.allclose(q1.heat_source_load(g, np.full(g.nelem, 0.5), f0, 1), q1.element_load(g, f0 / 2), rtol=1e-15)
+    # a single hot element loads exactly its 8 nodes with V/8 each
+    r1 = np.ones(g.nelem)
+    r1[g.element_index(1, 2, 3)] = 0.0
+    f1 = q1.heat_source_load(g, r1, f0, p)
+    assert np.count_nonzero(f1) == 8 and np.allclose(f1[f1 != 0], f0 * g.vol / 8)
+
+
+def test_mean_temperature_weights():
+    """eq. (cost function): w^T T is the mean of the Q1 field over the box."""
+    g = q1.Grid(6, 4, 5, 2.0, 1.0, 0.5)
+    w = q1.mean_temperature_weights(g)
+    assert abs(w.sum() - 1.0) < 1e-14
+    ix, jy, kz = g.node_coords()
+    x, y, z = ix * g.hx, jy * g.hy, kz * g.hz
+    # trilinear fields are exact in Q1: mean of x y z over [0,2]x[0,1]x[0,.5] is 1 * 1/2 * 1/4
+    assert abs(w @ (x * y * z).ravel() - 0.125) < 1e-14
+    # x^2 is integrated by the Q1 interpolant, i.e. the trapezoid rule: (L^2/3 + h^2/6)
+    hx = 2.0 / 6
+    assert abs(w @ (x ** 2).ravel() - (4.0 / 3 + hx ** 2 / 6)) < 1e-13
+
+
+def _mean_temperature_of(g, rho, mask, kmin, kmax, p, f0, td):
+    A = q1.assemble(g, q1.conductivity(rho, kmin, kmax, p))
+    f = q1.heat_source_load(g, rho, f0, p)
+    T = q1.solve_direct(A, f, mask, td)
+    return q1.mean_temperature_weights(g) @ T, T, A
+
+
+@pytest.mark.parametrize("kmin,kmax,f0", [(1e-2, 1.0, 1.0), (0.3, 0.3, 1.0), (1e-2, 1.0, 0.0)])
+def test_paper_state_adjoint_fd(kmin, kmax, f0):
+    """Section 2.3 with the paper's pair: source f0 (1 - rho^p), T_D = 100 on the
+    patch, mean-temperature objective.  The adjoint gradient matches central
+    finite differences; the three cases pin the full gradient, the source term
+    alone (k independent of rho) and the stiffness term alone (f0 = 0: no
+    source, so the fixed values vary along the patch, 100 + 50 x, to keep T
+    non-constant)."""
+    n, p = 5, 3
+    g = q1.Grid(n)
+    rho = np.random.default_rng(11).uniform(0.2, 0.9, g.nelem)
+    mask = synth.dirichlet_patch_mask(n, n, n).ravel()
+    ix = g.node_coords()[0]
+    td = np.where(mask != 0, 100.0 + (50.0 * ix * g.hx if f0 == 0.0 else 0.0), 0.0)
+    c, T, A = _mean_temperature_of(g, rho, mask, kmin, kmax, p, f0, td)
+    lam = q1.adjoint_solve(A, q1.mean_temperature_weights(g), mask)
+    assert np.abs(lam[mask != 0]).max() == 0.0
+    dc = q1.sensitivity_heat_source(g, rho, T, lam, kmin, kmax, p, f0)
+    d = np.random.default_rng(12).standard_normal(g.nelem)
+    eps = 1e-6
+    fd = (_mean_temperature_of(g, rho + eps * d, mask, kmin, kmax, p, f0, td)[0]
+          - _mean_temperature_of(g, rho - eps * d, mask, kmin, kmax, p, f0, td)[0]) / (2 * eps)
+    assert abs(fd - dc @ d) <= 1e-6 * abs(dc @ d)
+    if f0 == 0.0:
+        assert np.array_equal(dc, q1.sensitivity(g, rho, T, lam, kmin, kmax, p))
+    if kmin == kmax:
+        assert np.abs(q1.sensitivity(g, rho, T, lam, kmin, kmax, p)).max() == 0.0
+
+
 def test_elementwise_apply_matches_assembly():
     rng = np.random.default_rng(11)
     g = q1.Grid(7, 5, 9, 1.0, 0.5, 2.0)

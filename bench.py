@@ -159,6 +159,48 @@ def run_workload(name, args):
         for kmin in (1e-2, 1e-4, 1e-6):
             out["runs"].append(solve_case(256, rho, kmin, fp64, tag="fp64"))
             out["runs"].append(solve_case(256, rho, kmin, mixed, tag="mixed"))
+    elif name == "cube256_grf16_paper_pair":
+        # the paper's own state and adjoint pair: source f0 (1 - rho^p) with
+        # f0 = 1, T_D = 100 on the patch (LS1), mean-temperature adjoint (LS2)
+        # sharing the set-up, then the sensitivity with its df/drho term
+        n = 256
+        rho_np = synth.grf_rho(n, 16, seed=0).ravel()
+        mask_np = synth.dirichlet_patch_mask(n, n, n).ravel()
+        free = int((n + 1) ** 3 - int(mask_np.sum()))
+        rho = torch.tensor(rho_np, device=dev)
+        mask = torch.tensor(mask_np, device=dev)
+        td = torch.where(mask != 0, 100.0, 0.0).to(torch.float64)
+        for kmin in (1e-2, 1e-4, 1e-6):
+            for tag, opts in (("fp64", fp64), ("mixed", mixed)):
+                s = pkg.Solver(n, tune_cache=tune, **opts)
+                rec = {}
+                for rep in range(2):  # the second repetition is reported
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    s.setup(rho, kmin, 1.0, 3, mask, td)
+                    f = s.heat_source_load(1.0)
+                    w = s.mean_temperature_weights()
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    T, i1 = s.solve(f, rtol=RTOL, maxit=2000)
+                    torch.cuda.synchronize()
+                    t2 = time.perf_counter()
+                    u, i2 = s.solve_adjoint(w, rtol=RTOL, maxit=2000)
+                    torch.cuda.synchronize()
+                    t3 = time.perf_counter()
+                    dc = s.sensitivity_heat_source(T, u, 1.0)
+                    torch.cuda.synchronize()
+                    t4 = time.perf_counter()
+                    rec = dict(tag=tag, n=n, k_min=kmin, mean_T=float(torch.dot(w, T)),
+                               setup_ms=1e3 * (t1 - t0), ls1_iterations=i1.iterations, ls1_ms=1e3 * (t2 - t1),
+                               ls1_rel_res=i1.rel_res, ls2_iterations=i2.iterations, ls2_ms=1e3 * (t3 - t2),
+                               ls2_rel_res=i2.rel_res, sensitivity_ms=1e3 * (t4 - t3),
+                               codes=[i1.code, i2.code], dofs_per_s=2 * free / (t3 - t1),
+                               dc_min=float(dc.min()), dc_max=float(dc.max()))
+                _log(json.dumps(rec))
+                out["runs"].append(rec)
+                del s, T, u, dc
+                torch.cuda.empty_cache()
     elif name == "cube512_topopt":
         n = 512
         s = pkg.Solver(n, tune_cache=tune, eig_warm_start=1, **mixed)
@@ -170,6 +212,45 @@ def run_workload(name, args):
         out["runs"] = hist
         out["config"] = dict(n=n, iterations=args.iterations, volume_fraction=0.3, radius=1.5, move=0.2, eta=0.5,
                              k_min=1e-6, precision="mixed", eig_warm_start=1)
+    elif name == "cube128_to_512_continuation":
+        # the interpolation technique at the design level (section 4): the
+        # paper's mean-temperature problem (source f0 (1 - rho^p), T_D = 100,
+        # contrast 1e6, volume fraction 0.05) optimised 40 / 20 / 10 iterations
+        # on 128^3 / 256^3 / 512^3, each level started from the injected
+        # design of the previous one; then 10 iterations directly on 512^3
+        # from the uniform design for comparison (OC update instead of MMA)
+        vf = 0.05
+
+        def make_mask(n):
+            return torch.tensor(synth.dirichlet_patch_mask(n, n, n).ravel(), device=dev)
+
+        def make_solver(n):
+            return pkg.Solver(n, tune_cache=tune, eig_warm_start=1, **mixed)
+
+        def make_fixed(n):
+            return torch.where(make_mask(n) != 0, 100.0, 0.0).to(torch.float64)
+
+        def summary(lv):
+            h = lv["history"]
+            return dict(n=lv["n"], iterations=lv["iterations"], seconds=lv["seconds"], first=h[0]["objective"],
+                        last=h[-1]["objective"], volume=h[-1]["volume"], pcg=[r["pcg_iterations"] for r in h],
+                        adjoint=[r["adjoint_iterations"] for r in h])
+
+        common = dict(kmin=1e-6, objective="mean_temperature", f0=1.0, maxit=4000,
+                      log=lambda r: _log(json.dumps(r)))
+        t_all = time.perf_counter()
+        x, levels = pkg.topopt.continuation(make_solver, make_mask, 128, (40, 20, 10), vf, make_fixed=make_fixed,
+                                            **common)
+        total_cont = time.perf_counter() - t_all
+        del x
+        torch.cuda.empty_cache()
+        _, direct = pkg.topopt.continuation(make_solver, make_mask, 512, (10,), vf, make_fixed=make_fixed, **common)
+        levels = [summary(lv) for lv in levels]
+        direct = summary(direct[0])
+        out["runs"] = [dict(kind="continuation", total_s=total_cont, levels=levels),
+                       dict(kind="direct512", **direct)]
+        out["config"] = dict(schedule=[40, 20, 10], volume_fraction=vf, k_min=1e-6, T_D=100.0, f0=1.0, radius=1.5,
+                             move=0.2, eta=0.5, update="OC", precision="mixed")
     elif name == "cube512_grf32_warmstart":
         # the interpolation step: solve the 256^3 companion (2^3 block average of
         # the same unthresholded field, thresholded at its own 60th percentile),
@@ -281,6 +362,7 @@ def main():
                     help="run one plain 1 GiB device copy first (reference for the HBM counters)")
     ap.add_argument("--workload", default=None,
                     help="run a companion workload instead of the benchmark: cube128_grf8_c1e6, "
+                         "cube256_grf16_paper_pair, cube128_to_512_continuation, "
                          "cube256_grf16_contrast_sweep, cube512_topopt, cube512_grf32_warmstart, "
                          "cube1024_grf32_c1e6")
     ap.add_argument("--iterations", type=int, default=20, help="optimisation iterations (cube512_topopt)")

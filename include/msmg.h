@@ -173,6 +173,26 @@ int msmg_solve_adjoint(msmg_handle* h, const double* g, double* lambda, double* 
  * valid for zero fixed values).  dc: element FP64 output. */
 int msmg_sensitivity(msmg_handle* h, const double* T, const double* lambda, double* dc, hipStream_t stream);
 
+/* Element sensitivities of an objective with the design-dependent heat source of
+ * section 2.1 eq. (material), f_e = f0 (1 - rho_e^p) (section 2.3):
+ *   dc/drho_e = lambda^T (df/drho_e - dA/drho_e T)
+ *             = -p rho_e^(p-1) [ (k_max - k_min) lambda_e^T K0 T_e + f0 (V/8) sum_{a in e} lambda_a ],
+ * rho, p, k_min, k_max from the last msmg_setup.  T: nodal FP64 state including its
+ * fixed values; lambda: nodal FP64 adjoint with zero fixed entries (required, the
+ * source term makes the problem non-self-adjoint); dc: element FP64 output.  f0 = 0
+ * gives msmg_sensitivity's value.  MSMG_EINVAL for NULL pointers or a non-finite
+ * f0, MSMG_ESTATE before the first msmg_setup. */
+int msmg_sensitivity_heat_source(msmg_handle* h, const double* T, const double* lambda, double f0, double* dc,
+                                 hipStream_t stream);
+
+/* Nodal load of the design-dependent heat source of section 2.1 eq. (material):
+ * f_n = sum_{e ni n} f0 (1 - rho_e^p) V/8 with rho and p of the last msmg_setup.
+ * f: nodal FP64 output, written on every node (the solves ignore fixed entries).
+ * MSMG_EINVAL for a NULL pointer or a non-finite f0, MSMG_ESTATE before the first
+ * msmg_setup.  The mean-temperature objective of section 2.3 eq. (cost function),
+ * (1/|Omega|) int T, has the weights msmg_element_load(src = NULL, 1/|Omega|). */
+int msmg_heat_source_load(msmg_handle* h, double f0, double* f, hipStream_t stream);
+
 /* y = P A P x + (I - P) x with P the projection on free nodes (FP64, nodal). */
 int msmg_apply(msmg_handle* h, const double* x, double* y, hipStream_t stream);
 

@@ -94,6 +94,8 @@ SIGNATURES = [
     ("msmg_apply", _I, [_VP, _VP, _VP, _VP]),
     ("msmg_precondition", _I, [_VP, _VP, _VP, _VP]),
     ("msmg_element_load", _I, [_VP, _VP, _D, _VP, _VP]),
+    ("msmg_sensitivity_heat_source", _I, [_VP, _VP, _VP, _D, _VP, _VP]),
+    ("msmg_heat_source_load", _I, [_VP, _D, _VP, _VP]),
     ("msmg_prolong_nodal", _I, [_I, _I, _I, _VP, _VP, _VP]),
     ("msmg_prolong_element", _I, [_I, _I, _I, _VP, _VP, _I, _VP]),
     ("msmg_density_filter", _I, [_I, _I, _I, _D, _VP, _VP, _I, _VP]),

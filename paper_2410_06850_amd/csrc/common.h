@@ -309,6 +309,7 @@ struct Scalars {
   double zr, zq;   // partial products of the last V-cycle
   double true_rr;  // ||b - A x||^2
   int done;        // 1: stop issuing work (converged / failed)
+  int xpend;       // 1: x still lacks alpha p of the current step (the next direction update adds it)
   int status;      // see SolveStatus
   int iters;
   int maxit;

@@ -104,22 +104,17 @@ MSMG_DEV void dd_add(double& hi, double& lo, double a, double ae) {
   lo = t - (hi - s);
 }
 
-__global__ void k_update_xr(double* __restrict__ x, float* __restrict__ xlo, double* __restrict__ r,
-                            const double* __restrict__ p, const double* __restrict__ q, long long nn, Scalars* sc,
-                            double* partials, unsigned* counter) {
+// r -= alpha q and ||r||^2 with the stop tests.  The iterate is not touched
+// here: its update x += alpha p is deferred to the direction update, which
+// reads p anyway (xpend marks it outstanding).
+__global__ void k_update_r(double* __restrict__ r, const double* __restrict__ q, long long nn, Scalars* sc,
+                           double* partials, unsigned* counter) {
   if (sc->done) return;
   __shared__ double red[16];
   const double a = sc->alpha;
   double s[1] = {0.0};
 #pragma unroll 4
   for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < nn; n += (long long)gridDim.x * blockDim.x) {
-    const double pn = p[n];
-    const double prod = a * pn;
-    const double perr = fma(a, pn, -prod);
-    double hi = x[n], lo = double(xlo[n]);
-    dd_add(hi, lo, prod, perr);
-    x[n] = hi;
-    xlo[n] = float(lo);  // |lo| <= ulp(hi) / 2: FP32 keeps about 77 bits of the sum
     const double rn = r[n] - a * q[n];
     r[n] = rn;
     s[0] += rn * rn;
@@ -127,6 +122,7 @@ __global__ void k_update_xr(double* __restrict__ x, float* __restrict__ xlo, dou
   grid_reduce<1>(s, red, partials, counter, gridDim.x, blockIdx.x, [&](double* t) {
     sc->rr = t[0];
     sc->iters += 1;
+    sc->xpend = 1;
     if (!(t[0] == t[0]) || t[0] > 1.7e308) {
       sc->status = ST_NONFINITE;
       sc->done = 1;
@@ -138,6 +134,25 @@ __global__ void k_update_xr(double* __restrict__ x, float* __restrict__ xlo, dou
       sc->done = 1;
     }
   });
+}
+
+// x += alpha p in double-double: (x, xlo) + the exact product a p as a pair.
+MSMG_DEV void dd_axpy(double* __restrict__ x, float* __restrict__ xlo, long long n, double a, double pn) {
+  const double prod = a * pn;
+  const double perr = fma(a, pn, -prod);
+  double hi = x[n], lo = double(xlo[n]);
+  dd_add(hi, lo, prod, perr);
+  x[n] = hi;
+  xlo[n] = float(lo);  // |lo| <= ulp(hi) / 2: FP32 keeps about 77 bits of the sum
+}
+
+// The outstanding x += alpha p once the iteration has stopped (ignores `done`).
+__global__ void k_update_x_pending(double* __restrict__ x, float* __restrict__ xlo, const double* __restrict__ p,
+                                   long long nn, const Scalars* sc) {
+  if (!sc->xpend) return;
+  const double a = sc->alpha;
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < nn; n += (long long)gridDim.x * blockDim.x)
+    dd_axpy(x, xlo, n, a, p[n]);
 }
 
 // T = xhi + xlo rounded (or xlo copied out when tlo is given) on free nodes;
@@ -156,12 +171,21 @@ __global__ void k_finish_solution_dd(double* __restrict__ T, const float* __rest
   }
 }
 
-// p = z + beta p
-__global__ void k_update_p(double* __restrict__ p, const double* __restrict__ z, long long nn, const Scalars* sc) {
+// x += alpha p (when outstanding), then p = z + beta p: one read of the old p.
+__global__ void k_update_px(double* __restrict__ x, float* __restrict__ xlo, double* __restrict__ p,
+                            const double* __restrict__ z, long long nn, const Scalars* sc) {
   if (sc->done) return;
-  const double b = sc->beta;
-  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < nn; n += (long long)gridDim.x * blockDim.x)
-    p[n] = z[n] + b * p[n];
+  const double a = sc->alpha, b = sc->beta;
+  if (sc->xpend) {
+    for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < nn; n += (long long)gridDim.x * blockDim.x) {
+      const double pn = p[n];
+      dd_axpy(x, xlo, n, a, pn);
+      p[n] = z[n] + b * pn;
+    }
+  } else {
+    for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < nn; n += (long long)gridDim.x * blockDim.x)
+      p[n] = z[n] + b * p[n];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -215,6 +239,7 @@ MSMG_MARCH_KERNEL void k_apply(
   if (MODE != 1) return;
   grid_reduce<1>(s, red, partials, counter, gridDim.x, blockIdx.x, [&](double* tt) {
     sc->pq = tt[0];
+    sc->xpend = 0;  // every block of the preceding direction update has read it
     if (!(tt[0] > 0.0) || !(sc->rz > 0.0)) {
       sc->status = (tt[0] == tt[0] && sc->rz == sc->rz) ? ST_BREAKDOWN : ST_NONFINITE;
       sc->done = 1;
@@ -617,11 +642,14 @@ MSMG_MARCH_KERNEL void k_cheb2_out(Geo g, Stencil st, March mg, const KT* __rest
 }
 
 // ---------------------------------------------------------------------------
-// Sensitivity: dc/drho_e = -p rho^(p-1) (kmax - kmin) lam_e^T K0 T_e   (section 2.3)
-template <typename RT>
+// Sensitivity (section 2.3): dc/drho_e = lam^T (df/drho_e - dA/drho_e T)
+//   = -p rho^(p-1) [ (kmax - kmin) lam_e^T K0 T_e + f0 (V/8) sum_a lam_a ],
+// the second term only for the design-dependent source f0 (1 - rho^p) of
+// eq. (material) (SRC = true).
+template <typename RT, bool SRC>
 __global__ void k_sensitivity(Geo g, Stencil st, const RT* __restrict__ rho, Material m,
                               const double* __restrict__ T, const double* __restrict__ lam,
-                              const uint32_t* __restrict__ bits, double* __restrict__ dc) {
+                              const uint32_t* __restrict__ bits, double f0, double* __restrict__ dc) {
   const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (e >= g.ne) return;
   const int i = int(e % g.nx), j = int((e / g.nx) % g.ny), k = int(e / ((long long)g.nx * g.ny));
@@ -652,7 +680,36 @@ __global__ void k_sensitivity(Geo g, Stencil st, const RT* __restrict__ rho, Mat
   const double r = to_f64<RT>(rho[e]);
   double rp = 1.0;
   for (int t = 1; t < m.p; ++t) rp *= r;
-  dc[e] = -double(m.p) * rp * (m.kmax - m.kmin) * q;
+  if (SRC) {
+    double ls = 0.0;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) ls += lv[a];
+    // the stiffness term rounds exactly as in the source-free case, so f0 = 0 gives its value
+    dc[e] = -double(m.p) * rp * (m.kmax - m.kmin) * q - double(m.p) * rp * (f0 * (g.vol / 8.0) * ls);
+  } else {
+    dc[e] = -double(m.p) * rp * (m.kmax - m.kmin) * q;
+  }
+}
+
+// Nodal load of the design-dependent heat source of eq. (material):
+// f_n = sum_{e ni n} f0 (1 - rho_e^p) V / 8.
+template <typename RT>
+__global__ void k_heat_source_load(Geo g, const RT* __restrict__ rho, int p, double f0, double* __restrict__ f) {
+  const long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (n >= g.nn) return;
+  const int i = int(n % g.nnx), j = int((n / g.nnx) % g.nny), k = int(n / ((long long)g.nnx * g.nny));
+  double s = 0.0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int ei = i - 1 + (c & 1), ej = j - 1 + ((c >> 1) & 1), ek = k - 1 + ((c >> 2) & 1);
+    if (ei >= 0 && ei < g.nx && ej >= 0 && ej < g.ny && ek >= 0 && ek < g.nz) {
+      const double r = to_f64<RT>(rho[elem_id(g, ei, ej, ek)]);
+      double rp = r;
+      for (int t = 1; t < p; ++t) rp *= r;
+      s += f0 * (1.0 - rp);
+    }
+  }
+  f[n] = s * (g.vol / 8.0);
 }
 
 // Consistent load of an element-wise constant source: f_n = sum_{e ni n} s_e V / 8.
@@ -720,6 +777,7 @@ __global__ void k_sc_reset(Scalars* sc, int full, int maxit) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   sc->done = 0;
   sc->status = ST_RUNNING;
+  sc->xpend = 0;
   if (full) {
     sc->iters = 0;
     sc->maxit = maxit;
@@ -815,17 +873,21 @@ void launch_norm2(const Ctx& c, const double* v, int what, double rtol2, hipStre
   hipLaunchKernelGGL(k_norm2, dim3(nb), dim3(256), 0, s, v, c.g.nn, what, rtol2, c.sc, c.partials, c.counter);
 }
 
-void launch_update_xr(const Ctx& c, double* x, float* xlo, double* r, const double* p, const double* q, hipStream_t s) {
+void launch_update_r(const Ctx& c, double* r, const double* q, hipStream_t s) {
   const int nb = grid1d(c.g.nn, 256, c.red_blocks);
-  hipLaunchKernelGGL(k_update_xr, dim3(nb), dim3(256), 0, s, x, xlo, r, p, q, c.g.nn, c.sc, c.partials, c.counter);
+  hipLaunchKernelGGL(k_update_r, dim3(nb), dim3(256), 0, s, r, q, c.g.nn, c.sc, c.partials, c.counter);
+}
+
+void launch_update_x_pending(const Ctx& c, double* x, float* xlo, const double* p, hipStream_t s) {
+  hipLaunchKernelGGL(k_update_x_pending, dim3(grid1d(c.g.nn, 256, 8192)), dim3(256), 0, s, x, xlo, p, c.g.nn, c.sc);
 }
 
 void launch_finish_solution_dd(const Ctx& c, double* T, const float* xlo, double* tlo, const double* tfix, hipStream_t s) {
   hipLaunchKernelGGL(k_finish_solution_dd, dim3(grid1d(c.g.nn, 256, 8192)), dim3(256), 0, s, T, xlo, tlo, tfix, c.bits, c.g.nn);
 }
 
-void launch_update_p(const Ctx& c, double* p, const double* z, hipStream_t s) {
-  hipLaunchKernelGGL(k_update_p, dim3(grid1d(c.g.nn, 256, 8192)), dim3(256), 0, s, p, z, c.g.nn, c.sc);
+void launch_update_px(const Ctx& c, double* x, float* xlo, double* p, const double* z, hipStream_t s) {
+  hipLaunchKernelGGL(k_update_px, dim3(grid1d(c.g.nn, 256, 8192)), dim3(256), 0, s, x, xlo, p, z, c.g.nn, c.sc);
 }
 
 static inline dim3 tile_block(const Ctx& c) { return dim3(c.CX * c.h.H, c.h.H); }
@@ -1024,9 +1086,30 @@ void launch_smooth_output(const Ctx& c, const void* in, bool in_is_f64, const do
 void launch_sensitivity(const Ctx& c, const double* T, const double* lam, double* dc, hipStream_t s) {
   const dim3 gr((unsigned)((c.g.ne + 255) / 256)), bl(256);
   if (c.rho_dt == DT_F64)
-    hipLaunchKernelGGL((k_sensitivity<double>), gr, bl, 0, s, c.g, c.st, (const double*)c.rho, c.mat, T, lam, c.bits, dc);
+    hipLaunchKernelGGL((k_sensitivity<double, false>), gr, bl, 0, s, c.g, c.st, (const double*)c.rho, c.mat, T, lam,
+                       c.bits, 0.0, dc);
   else
-    hipLaunchKernelGGL((k_sensitivity<float>), gr, bl, 0, s, c.g, c.st, (const float*)c.rho, c.mat, T, lam, c.bits, dc);
+    hipLaunchKernelGGL((k_sensitivity<float, false>), gr, bl, 0, s, c.g, c.st, (const float*)c.rho, c.mat, T, lam,
+                       c.bits, 0.0, dc);
+}
+
+void launch_sensitivity_heat_source(const Ctx& c, const double* T, const double* lam, double f0, double* dc,
+                                    hipStream_t s) {
+  const dim3 gr((unsigned)((c.g.ne + 255) / 256)), bl(256);
+  if (c.rho_dt == DT_F64)
+    hipLaunchKernelGGL((k_sensitivity<double, true>), gr, bl, 0, s, c.g, c.st, (const double*)c.rho, c.mat, T, lam,
+                       c.bits, f0, dc);
+  else
+    hipLaunchKernelGGL((k_sensitivity<float, true>), gr, bl, 0, s, c.g, c.st, (const float*)c.rho, c.mat, T, lam,
+                       c.bits, f0, dc);
+}
+
+void launch_heat_source_load(const Ctx& c, double f0, double* f, hipStream_t s) {
+  const dim3 gr((unsigned)((c.g.nn + 255) / 256)), bl(256);
+  if (c.rho_dt == DT_F64)
+    hipLaunchKernelGGL((k_heat_source_load<double>), gr, bl, 0, s, c.g, (const double*)c.rho, c.mat.p, f0, f);
+  else
+    hipLaunchKernelGGL((k_heat_source_load<float>), gr, bl, 0, s, c.g, (const float*)c.rho, c.mat.p, f0, f);
 }
 
 void launch_element_load(const Geo& g, const double* src, double sconst, double* f, hipStream_t s) {

@@ -86,9 +86,10 @@ void launch_diag_inv(const Ctx& c, const void* rho, int rdt, void* dinv, int vdt
 void launch_zero_fixed_copy(const Ctx& c, const double* in, double* out, hipStream_t s);
 void launch_finish_solution(const Ctx& c, double* T, const double* tfix, hipStream_t s);
 void launch_norm2(const Ctx& c, const double* v, int what, double rtol2, hipStream_t s);
-void launch_update_xr(const Ctx& c, double* x, float* xlo, double* r, const double* p, const double* q, hipStream_t s);
+void launch_update_r(const Ctx& c, double* r, const double* q, hipStream_t s);
+void launch_update_x_pending(const Ctx& c, double* x, float* xlo, const double* p, hipStream_t s);
 void launch_finish_solution_dd(const Ctx& c, double* T, const float* xlo, double* tlo, const double* tfix, hipStream_t s);
-void launch_update_p(const Ctx& c, double* p, const double* z, hipStream_t s);
+void launch_update_px(const Ctx& c, double* x, float* xlo, double* p, const double* z, hipStream_t s);
 // y = A x (mode 0), with p^T A p -> alpha (mode 1), or P A P xraw + (I - P) xraw
 // (mode 2, x = xraw with zero fixed entries).  x is zero on fixed nodes.
 void launch_apply(const Ctx& c, const double* x, double* y, int mode, hipStream_t s, const double* xraw = nullptr);
@@ -107,6 +108,9 @@ bool smooth_output_fused(const Ctx& c);
 void launch_smooth_output(const Ctx& c, const void* in, bool in_is_f64, const double* base, double* z,
                           const double* r, const double* q, int mode, hipStream_t s);
 void launch_sensitivity(const Ctx& c, const double* T, const double* lam, double* dc, hipStream_t s);
+void launch_sensitivity_heat_source(const Ctx& c, const double* T, const double* lam, double f0, double* dc,
+                                    hipStream_t s);
+void launch_heat_source_load(const Ctx& c, double f0, double* f, hipStream_t s);
 void launch_element_load(const Geo& g, const double* src, double sconst, double* f, hipStream_t s);
 void launch_prolong_nodal(int nx, int ny, int nz, const double* tc, double* tf, hipStream_t s);
 void launch_prolong_element(int nx, int ny, int nz, const void* rc, void* rf, int dt, hipStream_t s);

@@ -744,6 +744,27 @@ extern "C" int msmg_sensitivity(msmg_handle* h, const double* T, const double* l
   return MSMG_OK;
 }
 
+extern "C" int msmg_sensitivity_heat_source(msmg_handle* h, const double* T, const double* lam, double f0, double* dc,
+                                            hipStream_t s) {
+  if (!h || !T || !lam || !dc) return fail(MSMG_EINVAL, "NULL argument");
+  if (!std::isfinite(f0)) return fail(MSMG_EINVAL, "f0 must be finite");
+  if (!h->setup_done) return fail(MSMG_ESTATE, "msmg_setup has not completed");
+  Ctx c = make_ctx(h);
+  launch_sensitivity_heat_source(c, T, lam, f0, dc, s);
+  HIP_TRY(hipGetLastError());
+  return MSMG_OK;
+}
+
+extern "C" int msmg_heat_source_load(msmg_handle* h, double f0, double* f, hipStream_t s) {
+  if (!h || !f) return fail(MSMG_EINVAL, "NULL argument");
+  if (!std::isfinite(f0)) return fail(MSMG_EINVAL, "f0 must be finite");
+  if (!h->setup_done) return fail(MSMG_ESTATE, "msmg_setup has not completed");
+  Ctx c = make_ctx(h);
+  launch_heat_source_load(c, f0, f, s);
+  HIP_TRY(hipGetLastError());
+  return MSMG_OK;
+}
+
 extern "C" int msmg_element_load(msmg_handle* h, const double* src, double sconst, double* f, hipStream_t s) {
   if (!h || !f) return fail(MSMG_EINVAL, "NULL argument");
   launch_element_load(h->g, src, sconst, f, s);
@@ -817,7 +838,7 @@ static int solve_impl(msmg_handle* h, const double* f, double* T, double* T_lo, 
   int timed_total = 0;
   if (!converged && maxit > 0) {
     precondition(h, c, h->r, h->z, nullptr, 0, s);
-    launch_update_p(c, h->p, h->z, s);
+    launch_update_px(c, x, h->xlo, h->p, h->z, s);
     const int batch = h->opt.check_interval;
     const int max_timed = 512;
     if (h->opt.timing && h->events.empty()) {
@@ -831,17 +852,20 @@ static int solve_impl(msmg_handle* h, const double* f, double* T, double* T_lo, 
         if (tm) HIP_TRY(hipEventRecord(h->events[4 * launched + 0], s));
         launch_apply(c, h->p, h->q, 1, s);
         if (tm) HIP_TRY(hipEventRecord(h->events[4 * launched + 1], s));
-        launch_update_xr(c, x, h->xlo, h->r, h->p, h->q, s);
+        launch_update_r(c, h->r, h->q, s);
         if (tm) HIP_TRY(hipEventRecord(h->events[4 * launched + 2], s));
         precondition(h, c, h->r, h->z, h->q, 1, s);
         if (tm) HIP_TRY(hipEventRecord(h->events[4 * launched + 3], s));
-        launch_update_p(c, h->p, h->z, s);
+        launch_update_px(c, x, h->xlo, h->p, h->z, s);  // also x += alpha p of this step
         ++launched;
       }
       timed_total = std::min(launched, max_timed);
       TRY(read_scalars(h, s));
       const Scalars& S = *h->sc_host;
       if (!S.done) continue;
+      // the step that stopped the iteration skipped the direction update:
+      // add its alpha p to the iterate before x is read
+      launch_update_x_pending(c, x, h->xlo, h->p, s);
       iters = S.iters;
       if (S.status == ST_CONV_RECURSIVE) {
         // confirm with the true residual
@@ -864,7 +888,7 @@ static int solve_impl(msmg_handle* h, const double* f, double* T, double* T_lo, 
         launch_sc_reset(c, 0, 0, s);
         launch_fill(c, h->p, 0.0, s);
         precondition(h, c, h->r, h->z, nullptr, 0, s);
-        launch_update_p(c, h->p, h->z, s);
+        launch_update_px(c, x, h->xlo, h->p, h->z, s);
         continue;
       }
       status = (S.status == ST_MAXIT) ? MSMG_MAXIT : (S.status == ST_BREAKDOWN ? MSMG_BREAKDOWN : MSMG_NONFINITE);

@@ -55,6 +55,7 @@ class Solver:
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self.nnodes = (self.nx + 1) * (self.ny + 1) * (self.nz + 1)
         self.nelem = self.nx * self.ny * self.nz
+        self.volume = float(lx) * float(ly) * float(lz)
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         self.opts = L.default_options(**options)
         self._tune_cache = self.opts.tune_cache  # keep the bytes alive
@@ -162,6 +163,25 @@ class Solver:
         L.check(L.lib().msmg_sensitivity(self._h, _ptr(T), _ptr(lam) if lam is not None else None, _ptr(out),
                                          _stream()), "msmg_sensitivity")
         return out
+
+    def sensitivity_heat_source(self, T, lam, f0, out=None):
+        """dc/drho with the design-dependent source f0 (1 - rho^p) (lam: the adjoint)."""
+        T = _need(T, "T", torch.float64, self.nnodes, self.device)
+        lam = _need(lam, "lam", torch.float64, self.nnodes, self.device)
+        out = torch.empty(self.nelem, dtype=torch.float64, device=self.device) if out is None else out
+        L.check(L.lib().msmg_sensitivity_heat_source(self._h, _ptr(T), _ptr(lam), float(f0), _ptr(out), _stream()),
+                "msmg_sensitivity_heat_source")
+        return out
+
+    def heat_source_load(self, f0=1.0):
+        """Nodal load of the source f0 (1 - rho^p) for the set-up density."""
+        f = torch.empty(self.nnodes, dtype=torch.float64, device=self.device)
+        L.check(L.lib().msmg_heat_source_load(self._h, float(f0), _ptr(f), _stream()), "msmg_heat_source_load")
+        return f
+
+    def mean_temperature_weights(self):
+        """Nodal weights w with w^T T = (1/|Omega|) int T (the mean-temperature objective)."""
+        return self.element_load(None, 1.0 / self.volume)
 
     def element_load(self, src=None, const=1.0):
         f = torch.empty(self.nnodes, dtype=torch.float64, device=self.device)

@@ -131,7 +131,7 @@ def test_topopt_loop_runs_and_decreases_compliance(pkg):
     print("case topopt-loop cube16", flush=True)
     s = pkg.Solver(16, H=8, sd=2)
     x, hist = pkg.topopt.optimize(s, to_dev(patch_mask(16), torch.uint8), iterations=6, kmin=1e-6)
-    cs = [h["compliance"] for h in hist]
+    cs = [h["objective"] for h in hist]
     assert all(np.isfinite(cs))
     assert cs[-1] < cs[0]
     assert abs(hist[-1]["volume"] - 0.3) <= 1e-6

@@ -156,6 +156,28 @@ def test_solve_matches_oracle(pkg, name):
     assert abs(info8.iterations - res8.iterations) <= slack, (info8.iterations, res8.iterations)
 
 
+@pytest.mark.parametrize("k", [1, 2, 7])
+def test_iteration_limit_returns_kth_iterate(pkg, k):
+    """A solve stopped by maxit = k returns the k-th PCG iterate (its last
+    alpha p included) and the true residual of that iterate."""
+    print(f"case maxit={k} cube16_noise_H8", flush=True)
+    name = "cube16_noise_H8"
+    g, h, s, rho, mask, kmin = _pair(pkg, name)
+    f = q1.element_load(g, 1.0)
+    A = q1.assemble(g, h.k)
+    Tlo = torch.empty(g.nnodes, dtype=torch.float64, device="cuda")
+    T, info = s.solve(to_dev(f), rtol=1e-15, maxit=k, T_lo=Tlo)
+    assert info.code == 1 and info.iterations == k, info
+    T, Tlo = T.cpu().numpy(), Tlo.cpu().numpy()
+    To, res, _ = omsmg.solve(g, rho, f, mask, kmin, KMAX, P, hier=h, rtol=1e-15, maxit=k)
+    assert res.status == "maxit" and res.iterations == k
+    err = rel(T + Tlo, To + res.x_lo)
+    rr = q1.relative_residual_diff(A, T, f, mask, T_lo=Tlo)
+    print(f"  rel.err={err:.3e} res gpu={info.rel_res:.6e} oracle-of-gpu={rr:.6e} oracle={res.rel_res:.6e}")
+    assert err <= 1e-10
+    assert abs(info.rel_res - rr) <= 1e-6 * rr
+
+
 MIXED = {
     # FP64 cycle arithmetic with BF16 copies of rho and R_c (a fixed linear
     # preconditioner): iterations stay within 10% of the all-FP64 path

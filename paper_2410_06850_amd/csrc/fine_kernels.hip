@@ -115,7 +115,7 @@ __global__ void k_update_r(double* __restrict__ r, const double* __restrict__ q,
   double s[1] = {0.0};
 #pragma unroll 4
   for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < nn; n += (long long)gridDim.x * blockDim.x) {
-    const double rn = r[n] - a * q[n];
+    const double rn = r[n] - a * __builtin_nontemporal_load(q + n);
     r[n] = rn;
     s[0] += rn * rn;
   }
@@ -137,13 +137,16 @@ __global__ void k_update_r(double* __restrict__ r, const double* __restrict__ q,
 }
 
 // x += alpha p in double-double: (x, xlo) + the exact product a p as a pair.
+// The iterate is streamed with non-temporal accesses: it is not read again
+// until the next step, and caching it would evict the direction p that the
+// operator apply reads next.
 MSMG_DEV void dd_axpy(double* __restrict__ x, float* __restrict__ xlo, long long n, double a, double pn) {
   const double prod = a * pn;
   const double perr = fma(a, pn, -prod);
-  double hi = x[n], lo = double(xlo[n]);
+  double hi = __builtin_nontemporal_load(x + n), lo = double(__builtin_nontemporal_load(xlo + n));
   dd_add(hi, lo, prod, perr);
-  x[n] = hi;
-  xlo[n] = float(lo);  // |lo| <= ulp(hi) / 2: FP32 keeps about 77 bits of the sum
+  __builtin_nontemporal_store(hi, x + n);
+  __builtin_nontemporal_store(float(lo), xlo + n);  // |lo| <= ulp(hi) / 2: FP32 keeps about 77 bits of the sum
 }
 
 // The outstanding x += alpha p once the iteration has stopped (ignores `done`).
@@ -180,7 +183,7 @@ __global__ void k_update_px(double* __restrict__ x, float* __restrict__ xlo, dou
     for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < nn; n += (long long)gridDim.x * blockDim.x) {
       const double pn = p[n];
       dd_axpy(x, xlo, n, a, pn);
-      p[n] = z[n] + b * pn;
+      p[n] = __builtin_nontemporal_load(z + n) + b * pn;
     }
   } else {
     for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < nn; n += (long long)gridDim.x * blockDim.x)

@@ -104,9 +104,12 @@ def measured_traffic():
 
 
 PATHS = {
-    # FP64 cycle arithmetic with BF16 copies of k and R_c, FP32 Jacobi diagonal
-    "mixed": dict(vcycle_dtype=0, rho_v_dtype=2, basis_dtype=2),
+    # FP64 cycle arithmetic with FP32 copies of k and R_c, FP32 Jacobi diagonal
+    "mixed": dict(vcycle_dtype=0, rho_v_dtype=1, basis_dtype=1),
     "fp64": dict(),
+    # the same with BF16 copies: less traffic, but the rounded coarse basis
+    # costs iterations on fields with large high-conductivity regions
+    "bf16": dict(vcycle_dtype=0, rho_v_dtype=2, basis_dtype=2),
     # FP32 cycle vectors and arithmetic (BF16 copies)
     "f32cycle": dict(vcycle_dtype=1, rho_v_dtype=2, basis_dtype=2),
 }
@@ -148,17 +151,19 @@ def run_workload(name, args):
         torch.cuda.empty_cache()
         return rec
 
-    mixed, fp64 = PATHS["mixed"], PATHS["fp64"]
+    mixed, fp64, bf16 = PATHS["mixed"], PATHS["fp64"], PATHS["bf16"]
     if name == "cube128_grf8_c1e6":
         for seed in (0, 1, 2):
             rho = synth.grf_rho(128, 8, seed=seed).ravel()
             out["runs"].append(solve_case(128, rho, 1e-6, fp64, seed=seed, tag="fp64"))
             out["runs"].append(solve_case(128, rho, 1e-6, mixed, seed=seed, tag="mixed"))
+            out["runs"].append(solve_case(128, rho, 1e-6, bf16, seed=seed, tag="bf16"))
     elif name == "cube256_grf16_contrast_sweep":
         rho = synth.grf_rho(256, 16, seed=0).ravel()
         for kmin in (1e-2, 1e-4, 1e-6):
             out["runs"].append(solve_case(256, rho, kmin, fp64, tag="fp64"))
             out["runs"].append(solve_case(256, rho, kmin, mixed, tag="mixed"))
+            out["runs"].append(solve_case(256, rho, kmin, bf16, tag="bf16"))
     elif name == "cube256_grf16_paper_pair":
         # the paper's own state and adjoint pair: source f0 (1 - rho^p) with
         # f0 = 1, T_D = 100 on the patch (LS1), mean-temperature adjoint (LS2)
@@ -171,7 +176,7 @@ def run_workload(name, args):
         mask = torch.tensor(mask_np, device=dev)
         td = torch.where(mask != 0, 100.0, 0.0).to(torch.float64)
         for kmin in (1e-2, 1e-4, 1e-6):
-            for tag, opts in (("fp64", fp64), ("mixed", mixed)):
+            for tag, opts in (("fp64", fp64), ("mixed", mixed), ("bf16", bf16)):
                 s = pkg.Solver(n, tune_cache=tune, **opts)
                 rec = {}
                 for rep in range(2):  # the second repetition is reported
@@ -201,9 +206,47 @@ def run_workload(name, args):
                 out["runs"].append(rec)
                 del s, T, u, dc
                 torch.cuda.empty_cache()
+    elif name == "cube512_paper_contrasts":
+        # the paper's solver-comparison setting at its size and tolerance:
+        # 512^3, contrast 10^cr for cr = 1..6, source f0 (1 - rho^p), T_D = 100,
+        # LS1 (state) and LS2 (mean-temperature adjoint) to rtol 1e-6 with one
+        # set-up; the paper's fields come from its optimisation runs and are
+        # replaced by a thresholded GRF (ell 32, volume fraction 0.4)
+        n = 512
+        rho = torch.tensor(synth.grf_rho(n, 32, seed=0).ravel(), device=dev)
+        mask = torch.tensor(synth.dirichlet_patch_mask(n, n, n).ravel(), device=dev)
+        free = int((n + 1) ** 3 - int(mask.sum()))
+        td = torch.where(mask != 0, 100.0, 0.0).to(torch.float64)
+        for tag, opts in (("mixed", mixed), ("bf16", bf16), ("fp64", fp64)):
+            s = pkg.Solver(n, tune_cache=tune, **opts)
+            s.setup(rho, 1e-1, 1.0, 3, mask, td)  # launch-shape tuning, not timed
+            for cr in range(1, 7):
+                kmin = 10.0 ** (-cr)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                s.setup(rho, kmin, 1.0, 3, mask, td)
+                f = s.heat_source_load(1.0)
+                w = s.mean_temperature_weights()
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                T, i1 = s.solve(f, rtol=1e-6, maxit=4000)
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                u, i2 = s.solve_adjoint(w, rtol=1e-6, maxit=4000)
+                torch.cuda.synchronize()
+                t3 = time.perf_counter()
+                rec = dict(tag=tag, n=n, cr=cr, setup_s=t1 - t0, ls1_s=t2 - t1, ls1_iterations=i1.iterations,
+                           ls2_s=t3 - t2, ls2_iterations=i2.iterations, codes=[i1.code, i2.code],
+                           ls1_rel_res=i1.rel_res, ls2_rel_res=i2.rel_res, free_dofs=free)
+                _log(json.dumps(rec))
+                out["runs"].append(rec)
+                del T, u
+            s.close()
+            del s
+            torch.cuda.empty_cache()
     elif name == "cube512_topopt":
         n = 512
-        s = pkg.Solver(n, tune_cache=tune, eig_warm_start=1, **mixed)
+        s = pkg.Solver(n, tune_cache=tune, eig_warm_start=1, **bf16)
         mask = torch.tensor(synth.dirichlet_patch_mask(n, n, n).ravel(), device=dev)
         t0 = time.perf_counter()
         _, hist = pkg.topopt.optimize(s, mask, iterations=args.iterations, volume_fraction=0.3, x0=0.3,
@@ -211,7 +254,7 @@ def run_workload(name, args):
         out["total_s"] = time.perf_counter() - t0
         out["runs"] = hist
         out["config"] = dict(n=n, iterations=args.iterations, volume_fraction=0.3, radius=1.5, move=0.2, eta=0.5,
-                             k_min=1e-6, precision="mixed", eig_warm_start=1)
+                             k_min=1e-6, precision="mixed, BF16 copies", eig_warm_start=1)
     elif name == "cube128_to_512_continuation":
         # the interpolation technique at the design level (section 4): the
         # paper's mean-temperature problem (source f0 (1 - rho^p), T_D = 100,
@@ -225,7 +268,7 @@ def run_workload(name, args):
             return torch.tensor(synth.dirichlet_patch_mask(n, n, n).ravel(), device=dev)
 
         def make_solver(n):
-            return pkg.Solver(n, tune_cache=tune, eig_warm_start=1, **mixed)
+            return pkg.Solver(n, tune_cache=tune, eig_warm_start=1, **bf16)
 
         def make_fixed(n):
             return torch.where(make_mask(n) != 0, 100.0, 0.0).to(torch.float64)
@@ -250,7 +293,7 @@ def run_workload(name, args):
         out["runs"] = [dict(kind="continuation", total_s=total_cont, levels=levels),
                        dict(kind="direct512", **direct)]
         out["config"] = dict(schedule=[40, 20, 10], volume_fraction=vf, k_min=1e-6, T_D=100.0, f0=1.0, radius=1.5,
-                             move=0.2, eta=0.5, update="OC", precision="mixed")
+                             move=0.2, eta=0.5, update="OC", precision="mixed, BF16 copies")
     elif name == "cube512_grf32_warmstart":
         # the interpolation step: solve the 256^3 companion (2^3 block average of
         # the same unthresholded field, thresholded at its own 60th percentile),
@@ -262,7 +305,7 @@ def run_workload(name, args):
         res = {}
         for n, rho_np in ((256, rho_c), (512, rho_f)):
             mask_np = synth.dirichlet_patch_mask(n, n, n).ravel()
-            s = pkg.Solver(n, tune_cache=tune, **mixed)
+            s = pkg.Solver(n, tune_cache=tune, **bf16)
             s.setup(torch.tensor(rho_np, device=dev), 1e-6, 1.0, 3, torch.tensor(mask_np, device=dev))
             f = s.element_load(const=1.0)
             if n == 256:
@@ -301,7 +344,7 @@ def run_workload(name, args):
         res = {}
         n = 512
         mask_np = synth.dirichlet_patch_mask(n, n, n).ravel()
-        s = pkg.Solver(n, tune_cache=tune, **mixed)
+        s = pkg.Solver(n, tune_cache=tune, **bf16)
         s.setup(torch.tensor(rho_c, device=dev), 1e-6, 1.0, 3, torch.tensor(mask_np, device=dev))
         f = s.element_load(const=1.0)
         T, info = s.solve(f, rtol=RTOL, maxit=2000)
@@ -312,7 +355,7 @@ def run_workload(name, args):
         del T, f, s, rho_c
         torch.cuda.empty_cache()
         n = 1024
-        opts = dict(mixed, rho_storage=1, lean_memory=1)
+        opts = dict(bf16, rho_storage=1, lean_memory=1)  # BF16 copies: the memory-lean layout
         mask_np = synth.dirichlet_patch_mask(n, n, n).ravel()
         free = int((n + 1) ** 3 - int(mask_np.sum()))
         s = pkg.Solver(n, tune_cache=tune, **opts)
@@ -342,7 +385,7 @@ def run_workload(name, args):
         res["free_dofs"] = free
         res["eig_unconverged"], res["cc_unconverged"] = warm.eig_unconverged, warm.cc_unconverged
         out["runs"] = [res]
-        out["config"] = dict(n=n, ell=32, k_min=1e-6, precision="mixed", rho_storage="f32", lean_memory=1,
+        out["config"] = dict(n=n, ell=32, k_min=1e-6, precision="mixed, BF16 copies", rho_storage="f32", lean_memory=1,
                              H=8, sd=8, Lc=4, Lcc=17)
     else:
         raise SystemExit(f"unknown workload {name}")
@@ -358,11 +401,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison path")
     ap.add_argument("--no-f32", action="store_true", help="skip the FP32-cycle comparison path")
+    ap.add_argument("--no-bf16", action="store_true", help="skip the BF16-copies comparison path")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (reference for the HBM counters)")
     ap.add_argument("--workload", default=None,
                     help="run a companion workload instead of the benchmark: cube128_grf8_c1e6, "
-                         "cube256_grf16_paper_pair, cube128_to_512_continuation, "
+                         "cube256_grf16_paper_pair, cube128_to_512_continuation, cube512_paper_contrasts, "
                          "cube256_grf16_contrast_sweep, cube512_topopt, cube512_grf32_warmstart, "
                          "cube1024_grf32_c1e6")
     ap.add_argument("--iterations", type=int, default=20, help="optimisation iterations (cube512_topopt)")
@@ -454,6 +498,9 @@ def main():
     if not args.no_fp64:
         _log("FP64 path")
         others["fp64"] = summary(run_path(PATHS["fp64"], 1, 0, "fp64"))
+    if not args.no_bf16:
+        _log("BF16-copies path")
+        others["bf16"] = summary(run_path(PATHS["bf16"], 1, 0, "bf16"))
     if not args.no_f32:
         _log("FP32-cycle path")
         others["f32cycle"] = summary(run_path(PATHS["f32cycle"], 1, 0, "f32cycle"))
@@ -483,7 +530,7 @@ def main():
             "field": f"thresholded Gaussian random field, ell={ELL * n / N:g} elements, volume fraction 0.4, seed 0",
             "k_min": KMIN, "k_max": 1.0, "p": 3, "rtol": RTOL,
             "hierarchy": {"H": 8, "sd": 8, "Lc": 4, "Lcc": 17, "cheb_degree": 2},
-            "precision": ("FP64 PCG (double-double iterate) and FP64 cycle arithmetic; BF16 copies of k and R_c, "
+            "precision": ("FP64 PCG (double-double iterate) and FP64 cycle arithmetic; FP32 copies of k and R_c, "
                           "FP32 Jacobi diagonal in the cycle; FP64 coarse levels"),
             "step": "set-up + PCG solve from zero + compliance sensitivity; value counts the solve only",
         },

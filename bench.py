@@ -152,6 +152,9 @@ def run_workload(name, args):
         return rec
 
     mixed, fp64, bf16 = PATHS["mixed"], PATHS["fp64"], PATHS["bf16"]
+    # coefficient copies of the single-path workloads (interpolation,
+    # optimisation, continuation, 1024^3): BF16 unless --copies f32
+    lean = mixed if args.copies == "f32" else bf16
     if name == "cube128_grf8_c1e6":
         for seed in (0, 1, 2):
             rho = synth.grf_rho(128, 8, seed=seed).ravel()
@@ -246,7 +249,7 @@ def run_workload(name, args):
             torch.cuda.empty_cache()
     elif name == "cube512_topopt":
         n = 512
-        s = pkg.Solver(n, tune_cache=tune, eig_warm_start=1, **bf16)
+        s = pkg.Solver(n, tune_cache=tune, eig_warm_start=1, **lean)
         mask = torch.tensor(synth.dirichlet_patch_mask(n, n, n).ravel(), device=dev)
         t0 = time.perf_counter()
         _, hist = pkg.topopt.optimize(s, mask, iterations=args.iterations, volume_fraction=0.3, x0=0.3,
@@ -254,7 +257,7 @@ def run_workload(name, args):
         out["total_s"] = time.perf_counter() - t0
         out["runs"] = hist
         out["config"] = dict(n=n, iterations=args.iterations, volume_fraction=0.3, radius=1.5, move=0.2, eta=0.5,
-                             k_min=1e-6, precision="mixed, BF16 copies", eig_warm_start=1)
+                             k_min=1e-6, precision=f"mixed, {args.copies} copies", eig_warm_start=1)
     elif name == "cube128_to_512_continuation":
         # the interpolation technique at the design level (section 4): the
         # paper's mean-temperature problem (source f0 (1 - rho^p), T_D = 100,
@@ -268,7 +271,7 @@ def run_workload(name, args):
             return torch.tensor(synth.dirichlet_patch_mask(n, n, n).ravel(), device=dev)
 
         def make_solver(n):
-            return pkg.Solver(n, tune_cache=tune, eig_warm_start=1, **bf16)
+            return pkg.Solver(n, tune_cache=tune, eig_warm_start=1, **lean)
 
         def make_fixed(n):
             return torch.where(make_mask(n) != 0, 100.0, 0.0).to(torch.float64)
@@ -293,7 +296,7 @@ def run_workload(name, args):
         out["runs"] = [dict(kind="continuation", total_s=total_cont, levels=levels),
                        dict(kind="direct512", **direct)]
         out["config"] = dict(schedule=[40, 20, 10], volume_fraction=vf, k_min=1e-6, T_D=100.0, f0=1.0, radius=1.5,
-                             move=0.2, eta=0.5, update="OC", precision="mixed, BF16 copies")
+                             move=0.2, eta=0.5, update="OC", precision=f"mixed, {args.copies} copies")
     elif name == "cube512_grf32_warmstart":
         # the interpolation step: solve the 256^3 companion (2^3 block average of
         # the same unthresholded field, thresholded at its own 60th percentile),
@@ -305,7 +308,7 @@ def run_workload(name, args):
         res = {}
         for n, rho_np in ((256, rho_c), (512, rho_f)):
             mask_np = synth.dirichlet_patch_mask(n, n, n).ravel()
-            s = pkg.Solver(n, tune_cache=tune, **bf16)
+            s = pkg.Solver(n, tune_cache=tune, **lean)
             s.setup(torch.tensor(rho_np, device=dev), 1e-6, 1.0, 3, torch.tensor(mask_np, device=dev))
             f = s.element_load(const=1.0)
             if n == 256:
@@ -344,7 +347,7 @@ def run_workload(name, args):
         res = {}
         n = 512
         mask_np = synth.dirichlet_patch_mask(n, n, n).ravel()
-        s = pkg.Solver(n, tune_cache=tune, **bf16)
+        s = pkg.Solver(n, tune_cache=tune, **lean)
         s.setup(torch.tensor(rho_c, device=dev), 1e-6, 1.0, 3, torch.tensor(mask_np, device=dev))
         f = s.element_load(const=1.0)
         T, info = s.solve(f, rtol=RTOL, maxit=2000)
@@ -355,7 +358,7 @@ def run_workload(name, args):
         del T, f, s, rho_c
         torch.cuda.empty_cache()
         n = 1024
-        opts = dict(bf16, rho_storage=1, lean_memory=1)  # BF16 copies: the memory-lean layout
+        opts = dict(lean, rho_storage=1, lean_memory=1)
         mask_np = synth.dirichlet_patch_mask(n, n, n).ravel()
         free = int((n + 1) ** 3 - int(mask_np.sum()))
         s = pkg.Solver(n, tune_cache=tune, **opts)
@@ -385,7 +388,7 @@ def run_workload(name, args):
         res["free_dofs"] = free
         res["eig_unconverged"], res["cc_unconverged"] = warm.eig_unconverged, warm.cc_unconverged
         out["runs"] = [res]
-        out["config"] = dict(n=n, ell=32, k_min=1e-6, precision="mixed, BF16 copies", rho_storage="f32", lean_memory=1,
+        out["config"] = dict(n=n, ell=32, k_min=1e-6, precision=f"mixed, {args.copies} copies", rho_storage="f32", lean_memory=1,
                              H=8, sd=8, Lc=4, Lcc=17)
     else:
         raise SystemExit(f"unknown workload {name}")
@@ -402,6 +405,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison path")
     ap.add_argument("--no-f32", action="store_true", help="skip the FP32-cycle comparison path")
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16-copies comparison path")
+    ap.add_argument("--copies", choices=("bf16", "f32"), default="bf16",
+                    help="coefficient copies of the single-path workloads (interpolation, optimisation, 1024^3)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (reference for the HBM counters)")
     ap.add_argument("--workload", default=None,

@@ -104,12 +104,15 @@ def measured_traffic():
 
 
 PATHS = {
-    # FP64 cycle arithmetic with FP32 copies of k and R_c, FP32 Jacobi diagonal
-    "mixed": dict(vcycle_dtype=0, rho_v_dtype=1, basis_dtype=1),
+    # FP64 cycle arithmetic with a BF16 copy of k, an FP32 copy of R_c and an
+    # FP32 Jacobi diagonal
+    "mixed": dict(vcycle_dtype=0, rho_v_dtype=2, basis_dtype=1),
     "fp64": dict(),
-    # the same with BF16 copies: less traffic, but the rounded coarse basis
-    # costs iterations on fields with large high-conductivity regions
+    # the same with a BF16 basis as well: less traffic, but the rounded coarse
+    # basis costs iterations on fields with large high-conductivity regions
     "bf16": dict(vcycle_dtype=0, rho_v_dtype=2, basis_dtype=2),
+    # FP32 copies of both
+    "f32": dict(vcycle_dtype=0, rho_v_dtype=1, basis_dtype=1),
     # FP32 cycle vectors and arithmetic (BF16 copies)
     "f32cycle": dict(vcycle_dtype=1, rho_v_dtype=2, basis_dtype=2),
 }
@@ -153,8 +156,9 @@ def run_workload(name, args):
 
     mixed, fp64, bf16 = PATHS["mixed"], PATHS["fp64"], PATHS["bf16"]
     # coefficient copies of the single-path workloads (interpolation,
-    # optimisation, continuation, 1024^3): BF16 unless --copies f32
-    lean = mixed if args.copies == "f32" else bf16
+    # optimisation, continuation, 1024^3): BF16 k and R_c unless --copies
+    # f32 (FP32 both) or mixed (BF16 k, FP32 R_c)
+    lean = {"bf16": bf16, "f32": PATHS["f32"], "mixed": mixed}[args.copies]
     if name == "cube128_grf8_c1e6":
         for seed in (0, 1, 2):
             rho = synth.grf_rho(128, 8, seed=seed).ravel()
@@ -405,7 +409,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison path")
     ap.add_argument("--no-f32", action="store_true", help="skip the FP32-cycle comparison path")
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16-copies comparison path")
-    ap.add_argument("--copies", choices=("bf16", "f32"), default="bf16",
+    ap.add_argument("--copies", choices=("bf16", "f32", "mixed"), default="bf16",
                     help="coefficient copies of the single-path workloads (interpolation, optimisation, 1024^3)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (reference for the HBM counters)")
@@ -535,7 +539,7 @@ def main():
             "field": f"thresholded Gaussian random field, ell={ELL * n / N:g} elements, volume fraction 0.4, seed 0",
             "k_min": KMIN, "k_max": 1.0, "p": 3, "rtol": RTOL,
             "hierarchy": {"H": 8, "sd": 8, "Lc": 4, "Lcc": 17, "cheb_degree": 2},
-            "precision": ("FP64 PCG (double-double iterate) and FP64 cycle arithmetic; FP32 copies of k and R_c, "
+            "precision": ("FP64 PCG (double-double iterate) and FP64 cycle arithmetic; BF16 copy of k, FP32 copy of R_c, "
                           "FP32 Jacobi diagonal in the cycle; FP64 coarse levels"),
             "step": "set-up + PCG solve from zero + compliance sensitivity; value counts the solve only",
         },

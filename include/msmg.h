@@ -67,6 +67,7 @@ typedef struct msmg_options {
   int vcycle_dtype;    /* MSMG_F64 or MSMG_F32 vectors inside the cycle         [F64]  */
   int rho_v_dtype;     /* density copy read by the cycle: F64/F32/BF16          [F64]  */
   int basis_dtype;     /* storage of R_c: F64/F32/BF16                          [F64]  */
+                       /* (an FP64 cycle takes equal copy types, or BF16 + F32)        */
   int pc_kind;         /* MSMG_PC_MULTIGRID or MSMG_PC_SMOOTHER (level 0 only)  [MG]   */
   int check_interval;  /* PCG iterations between host convergence polls        [8]    */
   int eig_block;       /* level-1 subspace block size (0 = tuned)               [0]    */

@@ -962,6 +962,7 @@ void launch_residual(const Ctx& c, const double* b, const double* x, const float
     if (c.v_dt == DT_F64) {                                                                    \
       if (c.b_dt == DT_F64) VC_CASE(double, double, double, double, __VA_ARGS__)               \
       else if (c.b_dt == DT_BF16) VC_CASE(double, bf16, bf16, float, __VA_ARGS__)              \
+      else if (c.kv_dt == DT_BF16) VC_CASE(double, bf16, float, float, __VA_ARGS__)            \
       else VC_CASE(double, float, float, float, __VA_ARGS__)                                   \
     } else {                                                                                   \
       if (c.kv_dt == DT_BF16 && c.b_dt == DT_BF16) VC_CASE(float, bf16, bf16, float, __VA_ARGS__) \

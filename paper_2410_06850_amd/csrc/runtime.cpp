@@ -355,8 +355,11 @@ static int check_options(const msmg_options& o) {
   if (o.vcycle_dtype != MSMG_F64 && o.vcycle_dtype != MSMG_F32) return fail(MSMG_EINVAL, "vcycle_dtype must be F64 or F32");
   if (o.rho_v_dtype < 0 || o.rho_v_dtype > 2 || o.basis_dtype < 0 || o.basis_dtype > 2)
     return fail(MSMG_EINVAL, "bad storage dtype");
-  if (o.vcycle_dtype == MSMG_F64 && o.rho_v_dtype != o.basis_dtype)
-    return fail(MSMG_EINVAL, "an FP64 cycle takes density and basis copies of one type (F64, F32 or BF16)");
+  if (o.vcycle_dtype == MSMG_F64 && o.rho_v_dtype != o.basis_dtype &&
+      !(o.rho_v_dtype == MSMG_BF16 && o.basis_dtype == MSMG_F32))
+    return fail(MSMG_EINVAL,
+                "an FP64 cycle takes density and basis copies of one type (F64, F32 or BF16), or a BF16 density "
+                "copy with an F32 basis");
   if (o.vcycle_dtype == MSMG_F32 && (o.rho_v_dtype == MSMG_F64 || o.basis_dtype == MSMG_F64))
     return fail(MSMG_EINVAL, "an FP32 cycle takes F32 or BF16 density and basis copies");
   if (o.pc_kind != MSMG_PC_MULTIGRID && o.pc_kind != MSMG_PC_SMOOTHER) return fail(MSMG_EINVAL, "bad pc_kind");

@@ -3,7 +3,7 @@ relative residual of the GPU solution T + T_lo with its own element-by-element
 operator (difference form, slab by slab) and requires <= rtol (1 + 1e-3).
 
 256^3 is the benchmark configuration (GRF ell 16, seed 0, contrast 1e6, H 8,
-sd 8, the mixed (FP32 copies), FP64 and BF16-copies paths as bench.py runs
+sd 8, the mixed (BF16 k, FP32 R_c), FP64 and BF16-copies paths as bench.py runs
 them); 512^3 uses the interpolation workload's field (GRF ell 32).  The four
 cases take about 60 s.
 """
@@ -16,7 +16,7 @@ from oracle import q1
 pytestmark = pytest.mark.gpu
 
 RTOL, KMIN, KMAX, P = 1e-8, 1e-6, 1.0, 3
-PATHS = {"mixed": dict(vcycle_dtype=0, rho_v_dtype=1, basis_dtype=1), "fp64": {},
+PATHS = {"mixed": dict(vcycle_dtype=0, rho_v_dtype=2, basis_dtype=1), "fp64": {},
          "bf16": dict(vcycle_dtype=0, rho_v_dtype=2, basis_dtype=2)}
 
 

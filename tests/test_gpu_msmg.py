@@ -180,10 +180,12 @@ def test_iteration_limit_returns_kth_iterate(pkg, k):
 
 MIXED = {
     # FP64 cycle arithmetic with FP32 copies of rho and R_c (a fixed linear
-    # preconditioner, the default mixed path): iterations within 10% of FP64
+    # preconditioner): iterations within 10% of FP64
     "f32-coefficients": (dict(vcycle_dtype=0, rho_v_dtype=1, basis_dtype=1), 1.1),
     # the same with BF16 copies
     "bf16-coefficients": (dict(vcycle_dtype=0, rho_v_dtype=2, basis_dtype=2), 1.1),
+    # BF16 conductivity copy with an FP32 basis (the default mixed path)
+    "bf16k-f32basis": (dict(vcycle_dtype=0, rho_v_dtype=2, basis_dtype=1), 1.1),
     # FP32 cycle vectors: rounding noise makes the preconditioner vary from one
     # application to the next, which costs iterations at high contrast
     "f32-cycle": (dict(vcycle_dtype=1, rho_v_dtype=2, basis_dtype=2), 1.6),
@@ -227,7 +229,7 @@ def test_deterministic(pkg):
     assert torch.equal(T1, T2)
 
 
-@pytest.mark.parametrize("mode", ["fp64", "f32-coefficients", "bf16-coefficients"])
+@pytest.mark.parametrize("mode", ["fp64", "bf16k-f32basis", "bf16-coefficients"])
 def test_certificate_cube128_grf8_c1e6(pkg, mode):
     """P2 at 128^3 (GRF ell 8, contrast 1e6, H 8, sd 8): the oracle's own residual
     of the GPU solution T + T_lo is <= rtol (1 + 1e-3)."""

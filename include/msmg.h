@@ -236,6 +236,22 @@ int msmg_density_filter(int nx, int ny, int nz, double radius, const double* in,
 int msmg_oc_update(msmg_handle* h, const double* x, const double* dc, const double* dv, double volume_fraction,
                    double move, double eta, double x_min, double* x_new, double* lambda, hipStream_t stream);
 
+/* msmg_oc_update without a handle and without any allocation, for callers
+ * that cannot allocate device memory (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc).  Same update, same kernels and the
+ * same result as msmg_oc_update on an nx*ny*nz design; x, dc, dv, x_new:
+ * element FP64 device arrays (x_new must not alias the inputs), lambda
+ * nullable.  The scratch (block partials of the volume sweeps, a counter and
+ * the multiplier bracket, about 66 KB) is a fixed array that each device holds
+ * from the first call until the process ends; its size does not depend on the
+ * design.  Designs above 2^40 elements are rejected with MSMG_EINVAL.  Every
+ * call on one device uses that device's array, so calls that overlap on one
+ * device (other streams, other threads) race; serialise them.  The counter is
+ * cleared by a kernel at the start of every call (no memset). */
+int msmg_oc_update_noalloc(int nx, int ny, int nz, const double* x, const double* dc, const double* dv,
+                           double volume_fraction, double move, double eta, double x_min, double* x_new,
+                           double* lambda, hipStream_t stream);
+
 /* Diagnostics of the last set-up, copied to host memory (blocking):
  *   what = 0: level-1 eigenvalues, ncells*Lc doubles (padded entries 0)
  *   what = 1: R_c in FP64, nodes*Lc doubles, node-major

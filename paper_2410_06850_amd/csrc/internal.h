@@ -75,6 +75,12 @@ void launch_density_filter(int nx, int ny, int nz, double r, const double* in, d
 void launch_oc_update(long long ne, const double* x, const double* dc, const double* dv, double volume, double move,
                       double eta, double xmin, double* xnew, double* lam_out, void* state, double* partials,
                       unsigned* counter, int passes, hipStream_t s);
+// the same with the scratch in a fixed per-device array (no allocation)
+hipError_t oc_scratch_device_ptr(void** out);
+size_t oc_scratch_bytes();
+void launch_oc_update_scratch(long long ne, const double* x, const double* dc, const double* dv, double volume,
+                              double move, double eta, double xmin, double* xnew, double* lam_out, void* scratch_ptr,
+                              int passes, hipStream_t s);
 
 // fine level
 long long march_resident_blocks();  // marching workgroups the device runs at once

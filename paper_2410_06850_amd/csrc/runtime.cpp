@@ -1004,3 +1004,27 @@ extern "C" int msmg_oc_update(msmg_handle* h, const double* x, const double* dc,
   HIP_TRY(hipGetLastError());
   return MSMG_OK;
 }
+
+// Largest design the allocation-free update takes (its scratch does not grow
+// with the design; the bound keeps element indices and volumes exact).
+static constexpr long long OC_NOALLOC_MAX_ELEMENTS = 1LL << 40;
+
+extern "C" int msmg_oc_update_noalloc(int nx, int ny, int nz, const double* x, const double* dc, const double* dv,
+                                      double volume_fraction, double move, double eta, double x_min, double* x_new,
+                                      double* lambda, hipStream_t s) {
+  if (nx < 1 || ny < 1 || nz < 1) return fail(MSMG_EINVAL, "mesh sizes must be >= 1");
+  const long long ne = (long long)nx * ny * nz;
+  if (ne > OC_NOALLOC_MAX_ELEMENTS)
+    return fail(MSMG_EINVAL, "design has " + std::to_string(ne) + " elements; the allocation-free update takes at most " +
+                                 std::to_string(OC_NOALLOC_MAX_ELEMENTS));
+  if (!x || !dc || !dv || !x_new) return fail(MSMG_EINVAL, "NULL argument");
+  if (x_new == x || x_new == dc || x_new == dv) return fail(MSMG_EINVAL, "x_new must not alias the inputs");
+  if (!(volume_fraction > 0.0 && volume_fraction <= 1.0)) return fail(MSMG_EINVAL, "volume fraction in (0, 1]");
+  if (!(move > 0.0) || !(eta > 0.0) || !(x_min >= 0.0 && x_min < 1.0))
+    return fail(MSMG_EINVAL, "need move > 0, eta > 0, 0 <= x_min < 1");
+  void* scratch = nullptr;
+  HIP_TRY(oc_scratch_device_ptr(&scratch));
+  launch_oc_update_scratch(ne, x, dc, dv, volume_fraction * double(ne), move, eta, x_min, x_new, lambda, scratch, 8, s);
+  HIP_TRY(hipGetLastError());
+  return MSMG_OK;
+}

@@ -1,6 +1,7 @@
 // Design-update kernels around the solve: the density filter and the
 // optimality-criteria (OC) update used by the topology-optimisation loop.
 #include <cmath>
+#include <mutex>
 
 #include "common.h"
 #include "internal.h"
@@ -88,9 +89,10 @@ MSMG_DEV double oc_new(double x, double dc, double dv, double lam, double move, 
   return v;
 }
 
-__global__ void k_oc_init(OCState* st, double log_lo, double log_hi) {
+__global__ void k_oc_init(OCState* st, double log_lo, double log_hi, unsigned* counter) {
   st->log_lo = log_lo;
   st->log_hi = log_hi;
+  if (counter) *counter = 0u;
 }
 
 __global__ void k_oc_volumes(long long ne, const double* __restrict__ x, const double* __restrict__ dc,
@@ -133,7 +135,61 @@ void launch_oc_update(long long ne, const double* x, const double* dc, const dou
                       double eta, double xmin, double* xnew, double* lam_out, void* state, double* partials,
                       unsigned* counter, int passes, hipStream_t s) {
   OCState* st = (OCState*)state;
-  hipLaunchKernelGGL(k_oc_init, dim3(1), dim3(1), 0, s, st, std::log(1e-40), std::log(1e40));
+  hipLaunchKernelGGL(k_oc_init, dim3(1), dim3(1), 0, s, st, std::log(1e-40), std::log(1e40), (unsigned*)nullptr);
+  for (int it = 0; it < passes; ++it)
+    hipLaunchKernelGGL(k_oc_volumes, dim3(OC_BLOCKS), dim3(256), 0, s, ne, x, dc, dv, move, eta, xmin, volume, st,
+                       partials, counter);
+  hipLaunchKernelGGL(k_oc_apply, dim3(grid1d(ne, 256, 65536)), dim3(256), 0, s, ne, x, dc, dv, move, eta, xmin, st,
+                     xnew, lam_out);
+}
+
+// ---------------------------------------------------------------------------
+// The same update with its scratch (block partials of the volume sweeps, the
+// reduction counter, the multiplier bracket) in a fixed device array instead
+// of a handle: nothing is allocated, so callers that may not allocate (graph
+// capture, serving loops) can use it.  The array's size does not depend on the
+// design size: the volume sweeps always run OC_BLOCKS workgroups.  Each device
+// holds its own copy; calls on one device share it.
+constexpr size_t OC_SCRATCH_COUNTER = 0, OC_SCRATCH_STATE = 256, OC_SCRATCH_PARTIALS = 512;
+constexpr size_t OC_SCRATCH_BYTES = OC_SCRATCH_PARTIALS + sizeof(double) * OC_NL * OC_BLOCKS;
+static __device__ __align__(256) unsigned char scratch[OC_SCRATCH_BYTES];
+
+static_assert(sizeof(OCState) <= OC_SCRATCH_PARTIALS - OC_SCRATCH_STATE, "state slot");
+
+// Device address of this device's scratch array, looked up once per device
+// (the array's name is only a host-side stand-in).
+constexpr int OC_MAX_DEVICES = 64;
+static std::mutex oc_scratch_mutex;
+static void* oc_scratch_addr[OC_MAX_DEVICES] = {};
+
+hipError_t oc_scratch_device_ptr(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= OC_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(oc_scratch_mutex);
+  if (!oc_scratch_addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    oc_scratch_addr[dev] = p;
+  }
+  *out = oc_scratch_addr[dev];
+  return hipSuccess;
+}
+
+size_t oc_scratch_bytes() { return OC_SCRATCH_BYTES; }
+
+void launch_oc_update_scratch(long long ne, const double* x, const double* dc, const double* dv, double volume,
+                              double move, double eta, double xmin, double* xnew, double* lam_out, void* scratch_ptr,
+                              int passes, hipStream_t s) {
+  char* base = static_cast<char*>(scratch_ptr);
+  unsigned* counter = reinterpret_cast<unsigned*>(base + OC_SCRATCH_COUNTER);
+  OCState* st = reinterpret_cast<OCState*>(base + OC_SCRATCH_STATE);
+  double* partials = reinterpret_cast<double*>(base + OC_SCRATCH_PARTIALS);
+  // the counter is cleared by a kernel (not a memset), so the sequence can be
+  // captured in a graph
+  hipLaunchKernelGGL(k_oc_init, dim3(1), dim3(1), 0, s, st, std::log(1e-40), std::log(1e40), counter);
   for (int it = 0; it < passes; ++it)
     hipLaunchKernelGGL(k_oc_volumes, dim3(OC_BLOCKS), dim3(256), 0, s, ne, x, dc, dv, move, eta, xmin, volume, st,
                        partials, counter);

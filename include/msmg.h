@@ -65,7 +65,10 @@ typedef struct msmg_options {
   double cheb_lo;      /* smoothing interval on D^-1 A                          [0.15] */
   double cheb_hi;      /*                                                        [1.5]  */
   int vcycle_dtype;    /* MSMG_F64 or MSMG_F32 vectors inside the cycle         [F64]  */
-  int rho_v_dtype;     /* density copy read by the cycle: F64/F32/BF16          [F64]  */
+  int rho_v_dtype;     /* conductivity copy read by the cycle: F64/F32/BF16     [F64]
+                          (the FP64 k = k_min + rho^p (k_max - k_min) of each
+                          element, rounded once per set-up; rho itself is kept
+                          at its canonical precision)                             */
   int basis_dtype;     /* storage of R_c: F64/F32/BF16                          [F64]  */
                        /* (an FP64 cycle takes equal copy types, or BF16 + F32)        */
   int pc_kind;         /* MSMG_PC_MULTIGRID or MSMG_PC_SMOOTHER (level 0 only)  [MG]   */

@@ -69,7 +69,21 @@ template <> MSMG_HD float cvt<float, bf16>(bf16 v) { return bf16_to_float(v); }
 template <typename T> MSMG_HD T from_f64(double v);
 template <> MSMG_HD double from_f64<double>(double v) { return v; }
 template <> MSMG_HD float from_f64<float>(double v) { return float(v); }
-template <> MSMG_HD bf16 from_f64<bf16>(double v) { return float_to_bf16(float(v)); }
+// One rounding from binary64 to bf16 (round to nearest even): the value is first
+// rounded to binary32 *to odd* (truncate, then set the last bit when anything
+// was cut off), which keeps the information the second rounding needs; binary32
+// carries 16 more significand bits than bf16, so the second, nearest-even,
+// rounding then equals a direct one.
+template <> MSMG_HD bf16 from_f64<bf16>(double v) {
+  union { uint32_t u; float f; } c;
+  c.f = float(v);
+  const double back = double(c.f);
+  if (back != v && v == v) {
+    if ((back < 0.0 ? -back : back) > (v < 0.0 ? -v : v)) c.u -= 1u;  // toward zero
+    c.u |= 1u;
+  }
+  return float_to_bf16(c.f);
+}
 
 // ---------------------------------------------------------------------------
 // Mesh geometry and the unit-conductivity Q1 stencil coefficients.

@@ -542,6 +542,18 @@ extern "C" int msmg_create(msmg_handle** out, int nx, int ny, int nz, double lx,
   if (!h->Rccv) h->Rccv = h->Rcc64;
   HIP_TRY(hipMemset(h->counter, 0, 64));
   HIP_TRY(hipMemset(h->sc, 0, sizeof(Scalars)));
+  if (o.timing) {
+    // events of the per-iteration timing (created here, outside any solve)
+    h->events.resize(4 * 512);
+    for (auto& e : h->events) {
+      hipError_t err = hipEventCreate(&e);
+      if (err != hipSuccess) {
+        e = nullptr;
+        msmg_destroy(h);
+        return fail(MSMG_EHIP, std::string("hipEventCreate: ") + hipGetErrorString(err));
+      }
+    }
+  }
   if (h->mg) {
     // coarse-coarse dof maps (host-built, uploaded once)
     const Hier& hh = h->hier;
@@ -843,11 +855,7 @@ static int solve_impl(msmg_handle* h, const double* f, double* T, double* T_lo, 
     precondition(h, c, h->r, h->z, nullptr, 0, s);
     launch_update_px(c, x, h->xlo, h->p, h->z, s);
     const int batch = h->opt.check_interval;
-    const int max_timed = 512;
-    if (h->opt.timing && h->events.empty()) {
-      h->events.resize(4 * max_timed);
-      for (auto& e : h->events) HIP_TRY(hipEventCreate(&e));
-    }
+    const int max_timed = int(h->events.size() / 4);
     int launched = 0;
     while (true) {
       for (int it = 0; it < batch; ++it) {

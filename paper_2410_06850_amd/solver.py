@@ -145,13 +145,13 @@ class Solver:
 
     def apply(self, x, y=None):
         x = _need(x, "x", torch.float64, self.nnodes, self.device)
-        y = torch.empty_like(x) if y is None else y
+        y = torch.empty_like(x) if y is None else _need(y, "y", torch.float64, self.nnodes, self.device)
         L.check(L.lib().msmg_apply(self._h, _ptr(x), _ptr(y), _stream()), "msmg_apply")
         return y
 
     def precondition(self, r, z=None):
         r = _need(r, "r", torch.float64, self.nnodes, self.device)
-        z = torch.empty_like(r) if z is None else z
+        z = torch.empty_like(r) if z is None else _need(z, "z", torch.float64, self.nnodes, self.device)
         L.check(L.lib().msmg_precondition(self._h, _ptr(r), _ptr(z), _stream()), "msmg_precondition")
         return z
 
@@ -159,7 +159,8 @@ class Solver:
         T = _need(T, "T", torch.float64, self.nnodes, self.device)
         if lam is not None:
             _need(lam, "lam", torch.float64, self.nnodes, self.device)
-        out = torch.empty(self.nelem, dtype=torch.float64, device=self.device) if out is None else out
+        out = (torch.empty(self.nelem, dtype=torch.float64, device=self.device) if out is None
+               else _need(out, "out", torch.float64, self.nelem, self.device))
         L.check(L.lib().msmg_sensitivity(self._h, _ptr(T), _ptr(lam) if lam is not None else None, _ptr(out),
                                          _stream()), "msmg_sensitivity")
         return out
@@ -168,7 +169,8 @@ class Solver:
         """dc/drho with the design-dependent source f0 (1 - rho^p) (lam: the adjoint)."""
         T = _need(T, "T", torch.float64, self.nnodes, self.device)
         lam = _need(lam, "lam", torch.float64, self.nnodes, self.device)
-        out = torch.empty(self.nelem, dtype=torch.float64, device=self.device) if out is None else out
+        out = (torch.empty(self.nelem, dtype=torch.float64, device=self.device) if out is None
+               else _need(out, "out", torch.float64, self.nelem, self.device))
         L.check(L.lib().msmg_sensitivity_heat_source(self._h, _ptr(T), _ptr(lam), float(f0), _ptr(out), _stream()),
                 "msmg_sensitivity_heat_source")
         return out
@@ -205,7 +207,7 @@ def density_filter(x, n, radius=1.5, transpose=False, out=None):
     """Hat-weight density filter on an (nx,ny,nz) element mesh (or its adjoint)."""
     nx, ny, nz = n
     _need(x, "x", torch.float64, nx * ny * nz, x.device)
-    out = torch.empty_like(x) if out is None else out
+    out = torch.empty_like(x) if out is None else _need(out, "out", torch.float64, nx * ny * nz, x.device)
     L.check(L.lib().msmg_density_filter(nx, ny, nz, float(radius), _ptr(x), _ptr(out), int(bool(transpose)),
                                         _stream()), "msmg_density_filter")
     return out

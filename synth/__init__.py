@@ -1,8 +1,7 @@
 """Seeded synthetic inputs shared by the oracle-side tests and the HIP-side bench.
 
 This package holds no arithmetic of the solver method: it only draws design
-fields, builds the Dirichlet node mask of the model problem and lists the
-workload configurations.  Both the oracle (``oracle/``) and the product
+fields and builds the Dirichlet node mask of the model problem.  Both the oracle (``oracle/``) and the product
 package consume it; neither imports the other.
 """
 from .fields import (  # noqa: F401
@@ -14,4 +13,3 @@ from .fields import (  # noqa: F401
     dirichlet_patch_mask,
     field_sha256,
 )
-from .configs import WORKLOADS, workload  # noqa: F401

@@ -135,3 +135,40 @@ def test_topopt_loop_runs_and_decreases_compliance(pkg):
     assert all(np.isfinite(cs))
     assert cs[-1] < cs[0]
     assert abs(hist[-1]["volume"] - 0.3) <= 1e-6
+
+
+def test_compliance_gradient_fd_cube32(pkg):
+    """The optimisation workload's gradient check: compliance c = f^T T on a
+    32^3 instance (near-uniform density, default hierarchy H 8, sd 8), autograd
+    gradient against the oracle's adjoint sensitivity (1e-8) and against a
+    central finite difference with FP64 perturbations of 1e-6 along a random
+    direction (1e-6; section 2.3)."""
+    n = 32
+    print("case autograd-compliance FD cube32_noise, delta 1e-6", flush=True)
+    g = q1.Grid(n)
+    rho = field(n, "noise", 4)
+    mask = patch_mask(n)
+    f = q1.element_load(g, 1.0)
+    s = pkg.Solver(n, H=8, sd=8)
+    m = to_dev(mask, torch.uint8)
+    r = to_dev(rho).requires_grad_(True)
+    c = pkg.autograd.compliance(r, to_dev(f), s, KMIN, KMAX, P, m, rtol=1e-12, maxit=500)
+    c.backward()
+    grad = r.grad.cpu().numpy()
+    A = q1.assemble(g, q1.conductivity(rho, KMIN, KMAX, P))
+    To = q1.solve_direct(A, f, mask)
+    want = q1.sensitivity(g, rho, To, To, KMIN, KMAX, P)
+    e_or = rel(grad, want)
+    d = np.random.default_rng(8).uniform(-1, 1, rho.size)
+    delta = 1e-6
+    vals = []
+    for sgn in (1, -1):
+        with torch.no_grad():
+            cv = pkg.autograd.compliance(to_dev(rho + sgn * delta * d), to_dev(f), s, KMIN, KMAX, P, m,
+                                         rtol=1e-12, maxit=500)
+        vals.append(float(cv))
+    fdv = (vals[0] - vals[1]) / (2 * delta)
+    e_fd = abs(fdv - float(grad @ d)) / abs(fdv)
+    print(f"  oracle gradient rel.err {e_or:.2e}, FD relative error {e_fd:.2e}")
+    assert e_or <= 1e-8
+    assert e_fd <= 1e-6

@@ -5,6 +5,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
+import synth  # noqa: E402
 from gpu_common import KMAX, P, field, max_sin_angle, oracle_hier, patch_mask, rel, to_dev  # noqa: E402
 from oracle import msmg as omsmg  # noqa: E402
 from oracle import q1  # noqa: E402
@@ -152,8 +153,7 @@ def test_solve_matches_oracle(pkg, name):
     _, info8 = s.solve(to_dev(f), rtol=1e-8, maxit=500)
     _, res8, _ = omsmg.solve(g, rho, f, mask, kmin, KMAX, P, hier=h, rtol=1e-8)
     print(f"  rtol 1e-8: gpu it={info8.iterations} oracle it={res8.iterations}")
-    slack = 1 if kind == "noise" else max(1, int(0.1 * res8.iterations))
-    assert abs(info8.iterations - res8.iterations) <= slack, (info8.iterations, res8.iterations)
+    assert abs(info8.iterations - res8.iterations) <= 1, (info8.iterations, res8.iterations)
 
 
 @pytest.mark.parametrize("k", [1, 2, 7])
@@ -252,14 +252,29 @@ def test_certificate_cube128_grf8_c1e6(pkg, mode):
     assert cert <= 1e-8 * (1 + 1e-3)
 
 
-def test_warm_started_setup_matches_cold(pkg):
+@pytest.mark.parametrize("change", ["grown", "flipped"])
+def test_warm_started_setup_matches_cold(pkg, change):
     """A set-up started from the previous design's basis converges to the same
-    local spectra and preconditioner as a cold one."""
+    local spectra and preconditioner as a cold one.
+
+    "grown": the next design grows the conducting phase (the same GRF
+    thresholded at volume fraction 0.45 instead of 0.40; 205 of 4096 elements
+    change), as an optimisation step does.  Its PCG count is stable (the oracle
+    takes 19 iterations with or without a relative 1e-12 perturbation of its
+    preconditioner output), so warm, cold and oracle counts agree to +-1.
+    "flipped": 5% of the elements flipped at random between void and solid,
+    which leaves isolated conductors and ~200 iterations; there a relative
+    1e-12 perturbation of the oracle's own preconditioner moves its count from
+    207 to 208-221, so only the preconditioner output (unique up to rounding and
+    the subspace error) and convergence are compared."""
     name = "cube16_grf_c1e6_H4"
-    print(f"case warm-start {name}", flush=True)
+    print(f"case warm-start {name} {change}", flush=True)
     n, kind, seed, kmin, H, sd = CASES[name]
     rho1 = field(n, kind, seed)
-    rho2 = np.where(np.random.default_rng(11).random(rho1.size) < 0.05, 1.0 - rho1 + 1e-3, rho1)
+    if change == "grown":
+        rho2 = synth.threshold_field(synth.grf_raw(n, 4, seed=seed), vf=0.45).ravel()
+    else:
+        rho2 = np.where(np.random.default_rng(11).random(rho1.size) < 0.05, 1.0 - rho1 + 1e-3, rho1)
     mask = to_dev(patch_mask(n), torch.uint8)
     warm = pkg.Solver(n, H=H, sd=sd, eig_warm_start=1)
     warm.setup(to_dev(rho1), kmin, KMAX, P, mask)
@@ -281,8 +296,8 @@ def test_warm_started_setup_matches_cold(pkg):
     _, iw = warm.solve(f, rtol=1e-8)
     _, ic = cold.solve(f, rtol=1e-8)
     print(f"  iterations warm {iw.iterations} cold {ic.iterations}")
-    # the two bases agree to the eigensolver tolerance, not bitwise; this
-    # field (5% of the elements flipped at contrast 1e6) needs ~200
-    # iterations, where rounding-level basis differences move the count by a
-    # few percent: the same 10% slack as for the other high-contrast fields
-    assert iw.code == 0 and abs(iw.iterations - ic.iterations) <= max(1, int(0.1 * ic.iterations))
+    assert iw.code == 0 and ic.code == 0
+    if change == "grown":
+        _, res, _ = omsmg.solve(g, rho2, q1.element_load(g, 1.0), patch_mask(n), kmin, KMAX, P, hier=h, rtol=1e-8)
+        print(f"  oracle {res.iterations}")
+        assert abs(iw.iterations - ic.iterations) <= 1 and abs(ic.iterations - res.iterations) <= 1

@@ -5,10 +5,9 @@ runs.  The oracle cannot assemble this operator, so it checks sampled rows:
 its node-by-node residual rows of the GPU solution against the GPU's own
 operator rows, and the load rows against the GPU's load.
 
-Opt-in (MSMG_FULL_SIZE=1): about three minutes and 220 GB of device memory.
+Part of the default GPU suite: about three minutes and 220 GB of device
+memory (the file name sorts it after the faster GPU tests).
 """
-import os
-
 import numpy as np
 import pytest
 import torch
@@ -16,9 +15,7 @@ import torch
 import synth
 from oracle import q1
 
-pytestmark = [pytest.mark.gpu,
-              pytest.mark.skipif(os.environ.get("MSMG_FULL_SIZE") != "1",
-                                 reason="full-size 1024^3 case runs only with MSMG_FULL_SIZE=1")]
+pytestmark = pytest.mark.gpu
 
 N, KMIN, KMAX, P, RTOL = 1024, 1e-6, 1.0, 3, 1e-8
 

@@ -541,6 +541,33 @@ def main():
     achieved = apply_bytes / (apply_ms * 1e-3) / 1e9
     traffic = measured_traffic() if n == N else None
 
+    # practical ceiling of the apply's access mix on this device: the same
+    # bytes streamed once each without the stencil (msmg_stream_ceiling)
+    ceiling = None
+    try:
+        import ctypes
+
+        from paper_2410_06850_amd import _lib as L
+
+        nn_e = (n + 1) ** 3 // 2 * 2
+        xa = torch.ones(nn_e, dtype=torch.float64, device=dev)
+        ka = torch.ones(n ** 3, dtype=torch.float64, device=dev)
+        ya = torch.empty_like(xa)
+        ms = ctypes.c_double()
+        L.check(L.lib().msmg_stream_ceiling(ctypes.c_void_p(xa.data_ptr()), ctypes.c_void_p(ka.data_ptr()),
+                                            ctypes.c_void_p(ya.data_ptr()), nn_e, n ** 3, 20, ctypes.byref(ms),
+                                            ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)),
+                "msmg_stream_ceiling")
+        cbytes = 8.0 * (2 * nn_e + n ** 3)
+        cgbs = cbytes / (ms.value * 1e-3) / 1e9
+        ceiling = {"kernel": "k_stream_ceiling (one coalesced read of x and k, one write of y)", "us": ms.value * 1e3,
+                   "bytes": cbytes, "achieved": cgbs, "frac_of_peak": cgbs / HBM_PEAK_GBS,
+                   "apply_frac_of_ceiling": achieved / cgbs}
+        del xa, ka, ya
+        torch.cuda.empty_cache()
+    except Exception as e:  # the measurement aid is optional; the bench line stands without it
+        _log(f"stream ceiling not measured: {e}")
+
     others = {}
     if not args.no_fp64:
         _log("FP64 path")
@@ -612,6 +639,7 @@ def main():
             "traffic": traffic,
             "apply_us": apply_ms * 1e3,
             "bytes_per_launch": apply_bytes,
+            "ceiling": ceiling,
         },
         "cpu_baseline": cpu,
     }

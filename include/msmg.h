@@ -51,7 +51,9 @@ enum {
   MSMG_EHIP = -3,       /* HIP runtime error                              */
   MSMG_ESETUP = -4,     /* coarse-space construction failed               */
   MSMG_ESINGULAR = -5,  /* no fixed-temperature node: A is singular       */
-  MSMG_ESTATE = -6      /* call order violated (e.g. solve before setup)  */
+  MSMG_ESTATE = -6,     /* call order violated (e.g. solve before setup)  */
+  MSMG_ETIMEOUT = -7    /* a bounded device-side wait gave up (the
+                           coarse-level kernel's grid-wide barrier)       */
 };
 
 /* Solver options (section 4 of the paper fixes sd, L_c, L_cc as tunables;
@@ -98,6 +100,12 @@ typedef struct msmg_options {
                           grids (1024^3 on one GPU).                             */
   int cc_group;        /* coarse-coarse cells whose dense shifted matrices the   [0]
                           set-up holds at once (0 = as many as fit in 24 GB)     */
+  int coarse_fused;    /* bit 0: levels 1 and 2 of each cycle in one launch      [3]
+                          (one workgroup per compute unit, grid-wide barriers
+                          between the steps); bit 1: the restriction fused into the cycle's
+                          first residual (H = 2, 4, 8 or 16).  Cleared bits run
+                          one launch per step.  The same arithmetic up to the
+                          order of the sums.                                     */
 } msmg_options;
 
 /* Solve report. */
@@ -201,12 +209,25 @@ int msmg_heat_source_load(msmg_handle* h, double f0, double* f, hipStream_t stre
 int msmg_apply(msmg_handle* h, const double* x, double* y, hipStream_t stream);
 
 /* z = M^-1 r: one preconditioner application (Algorithm 1 for the multigrid
- * kind).  Entries of r on fixed nodes are ignored; z is zero there. */
+ * kind).  Entries of r on fixed nodes are ignored; z is zero there.  With the
+ * one-launch coarse levels (options.coarse_fused bit 0) the call waits for the
+ * result and returns MSMG_ETIMEOUT if a barrier wait of that kernel gave up. */
 int msmg_precondition(msmg_handle* h, const double* r, double* z, hipStream_t stream);
 
 /* Consistent nodal load of an element-wise constant source: f_n = sum_{e ni n} s_e V/8,
  * with s_e = src[e], or s_e = src_const when src is NULL. */
 int msmg_element_load(msmg_handle* h, const double* src, double src_const, double* f, hipStream_t stream);
+
+/* Measurement aid: the memory traffic of the operator apply (msmg_apply reads
+ * x on nn nodes and k on ne elements and writes y on nn nodes) without its
+ * stencil.  Runs y = x (+ k on the first ne entries) reps times, coalesced,
+ * one read or write per value, and returns the mean kernel time in *ms (host
+ * pointer); 8 (2 nn + ne) bytes over that time is the bandwidth this access mix
+ * reaches, the practical ceiling of the apply.  x, k, y: FP64 device arrays
+ * (y must not alias x or k), nn and ne even, 2 <= ne <= nn.  Blocks until
+ * done. */
+int msmg_stream_ceiling(const double* x, const double* k, double* y, long long nn, long long ne, int reps, double* ms,
+                        hipStream_t stream);
 
 /* Interpolation step between resolutions (section 3, interpolation technique):
  * Tc on the (nx,ny,nz) mesh -> Tf on the (2nx,2ny,2nz) mesh, the coarse trilinear

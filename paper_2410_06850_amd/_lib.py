@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libmsmg.so")
 MSMG_F64, MSMG_F32, MSMG_BF16 = 0, 1, 2
 MSMG_PC_MULTIGRID, MSMG_PC_SMOOTHER = 0, 1
 MSMG_OK, MSMG_MAXIT, MSMG_BREAKDOWN, MSMG_NONFINITE = 0, 1, 2, 3
-MSMG_EINVAL, MSMG_ENOMEM, MSMG_EHIP, MSMG_ESETUP, MSMG_ESINGULAR, MSMG_ESTATE = -1, -2, -3, -4, -5, -6
+MSMG_EINVAL, MSMG_ENOMEM, MSMG_EHIP, MSMG_ESETUP, MSMG_ESINGULAR, MSMG_ESTATE, MSMG_ETIMEOUT = -1, -2, -3, -4, -5, -6, -7
 
 EXPORT_LOCAL_EVALS, EXPORT_RC, EXPORT_AC, EXPORT_CC_EVALS, EXPORT_ACC, EXPORT_CELL_STATUS = range(6)
 
@@ -48,6 +48,7 @@ class Options(ctypes.Structure):
         ("rho_storage", ctypes.c_int),
         ("lean_memory", ctypes.c_int),
         ("cc_group", ctypes.c_int),
+        ("coarse_fused", ctypes.c_int),
     ]
 
 
@@ -96,6 +97,7 @@ SIGNATURES = [
     ("msmg_element_load", _I, [_VP, _VP, _D, _VP, _VP]),
     ("msmg_sensitivity_heat_source", _I, [_VP, _VP, _VP, _D, _VP, _VP]),
     ("msmg_heat_source_load", _I, [_VP, _D, _VP, _VP]),
+    ("msmg_stream_ceiling", _I, [_VP, _VP, _VP, ctypes.c_longlong, ctypes.c_longlong, _I, ctypes.POINTER(_D), _VP]),
     ("msmg_prolong_nodal", _I, [_I, _I, _I, _VP, _VP, _VP]),
     ("msmg_prolong_element", _I, [_I, _I, _I, _VP, _VP, _I, _VP]),
     ("msmg_density_filter", _I, [_I, _I, _I, _D, _VP, _VP, _I, _VP]),

@@ -197,6 +197,292 @@ __global__ void k_cc_prolong(Hier h, int n_c, const VT* __restrict__ Rcc, const 
 }
 
 // ---------------------------------------------------------------------------
+// Levels 1 and 2 of Algorithm 1 in one grid-synchronised launch.
+//
+// The coarse work between the restriction and the prolongation is about twenty
+// dependent steps (eight colours of the forward sweep, the residual, the
+// coarse-coarse restriction, the direct solve with its prolongation, eight
+// colours of the backward sweep), each far too small to fill the GPU; as
+// separate launches they cost more in launch gaps than in work.  Here one
+// workgroup per compute unit runs every step, with a grid-wide barrier
+// between steps.  The grid never exceeds the number of workgroups the device
+// keeps resident at once, so all of them run together; each barrier wait is
+// bounded (spin_limit polls): a workgroup that exceeds it stops waiting, and
+// the solve reports MSMG_ETIMEOUT instead of hanging.
+//
+// Values one step writes and a later step reads on another workgroup (the
+// coarse iterate, the residual, r_cc) go through agent-scope atomic exchanges
+// and loads, which are performed at the device's coherence point: the compute
+// units of different XCDs do not share an L2.  A workgroup waits for the
+// results of its exchanges before it arrives at a barrier, so its values are in
+// place when the last arrival releases the others.  Read-only data (A_c, the
+// block inverses, R_cc, A_cc^-1, the restricted residual written by the
+// previous kernel) use ordinary loads.
+//
+// Backward sweep: Algorithm 1 sets e_c = x1 + S_c^-T (r_c - A_c x1).  One
+// Gauss-Seidel sweep over the colours 7..0 on A_c e = r_c started from x1,
+// updating x in place from all 27 neighbour blocks, computes exactly this
+// (the update of a cell sees x1 on colours not yet swept and the new values on
+// the swept ones, which is the transposed sweep applied to the residual), so
+// the residual step before it and the separate correction vector disappear.
+struct Level1Args {
+  Hier h;
+  const double* Ac;      // [ncells][27][L][L]
+  const double* Dinv;    // [ncells][L][L] inverses of the diagonal blocks
+  const double* rc;      // R_c (r0 - A r1), from the previous kernel
+  double* x;             // coarse iterate: x0, then x1, then e_c
+  double* t;             // r_c - A_c x0
+  double* rcc;           // R_cc t
+  const double* Rcc;     // per cc cell J: [Lcc][nd_J]
+  const int* cc_ptr;
+  const int* cc_dofs;
+  const double* AccInv;  // [n_cc][n_cc]
+  int n_cc;
+  unsigned* bar;         // barrier words (level1_barrier_words(), zero between launches)
+  Scalars* sc;
+  unsigned spin_limit;
+};
+
+MSMG_DEV double coh_load(const double* p) {
+  return __longlong_as_double((long long)__hip_atomic_load(reinterpret_cast<unsigned long long*>(const_cast<double*>(p)),
+                                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+MSMG_DEV unsigned long long coh_store(double* p, double v) {
+  return __hip_atomic_exchange(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Barrier words (each on its own 128-byte line): arrivals of the 8 workgroup
+// groups (workgroup b belongs to group b % 8, the XCD the hardware deals it
+// to), arrivals of the groups, the release word each group polls, the exits.
+constexpr int L1B_GROUPS = 8, L1B_LINE = 32;
+constexpr int L1B_GLOBAL = L1B_GROUPS * L1B_LINE, L1B_RELEASE = L1B_GLOBAL + L1B_LINE;
+constexpr int L1B_EXIT = L1B_RELEASE + L1B_GROUPS * L1B_LINE;
+constexpr int L1B_WORDS = L1B_EXIT + 1;
+
+// Grid-wide barrier number `k` (1, 2, ...), two-level so that no counter
+// serialises more than a few dozen atomics: a workgroup counts itself in its
+// group; the group's last arrival counts the group globally; the last group
+// publishes k in every group's release word, which the group polls.  Counters
+// only grow within a launch (each workgroup arrives once per barrier), so
+// arrival number k * size - 1 is the last one of barrier k.  Returns false
+// (and stops waiting at later barriers) when a wait exceeded the spin limit.
+MSMG_DEV bool l1_barrier(const Level1Args& a, unsigned k, unsigned long long seen, int* ok_sh) {
+  asm volatile("" ::"v"(seen) : "memory");  // this thread's exchanges have completed
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = *ok_sh;
+    const unsigned ng = gridDim.x < L1B_GROUPS ? gridDim.x : L1B_GROUPS;
+    const unsigned g = blockIdx.x % L1B_GROUPS;
+    const unsigned gsize = (gridDim.x - g + L1B_GROUPS - 1) / L1B_GROUPS;
+    unsigned* rel = a.bar + L1B_RELEASE + g * L1B_LINE;
+    const unsigned t = __hip_atomic_fetch_add(a.bar + g * L1B_LINE, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (t == k * gsize - 1) {
+      const unsigned tg = __hip_atomic_fetch_add(a.bar + L1B_GLOBAL, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (tg == k * ng - 1)
+        for (unsigned q = 0; q < ng; ++q)
+          __hip_atomic_store(a.bar + L1B_RELEASE + q * L1B_LINE, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (ok) {
+      unsigned n = 0;
+      while (__hip_atomic_load(rel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < k) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++n >= a.spin_limit) {
+          ok = 0;
+          break;
+        }
+      }
+    }
+    *ok_sh = ok;
+  }
+  __syncthreads();
+  return *ok_sh != 0;
+}
+
+// One Gauss-Seidel colour of the grid-synchronised sweep.  forward: x_i =
+// D_i^-1 (b_i - sum_{j of earlier colours} A_ij x_j) (zero start, colour 0
+// first).  !forward: x_i += D_i^-1 (b_i - sum_{all 27 j} A_ij x_j) (in place).
+template <int L>
+MSMG_DEV unsigned long long l1_colour(const Level1Args& a, int colour, bool forward) {
+  constexpr int CL = lanes_pow2<L>() * ROW_SLOTS;
+  const Hier& h = a.h;
+  const int px = colour & 1, py = (colour >> 1) & 1, pz = (colour >> 2) & 1;
+  const int nx = (h.ncx - px + 1) / 2, ny = (h.ncy - py + 1) / 2, nz = (h.ncz - pz + 1) / 2;
+  const long long total = (long long)nx * ny * nz * CL;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  unsigned long long seen = 0;
+  // the loop bound is uniform over a wave (base differs per wave by multiples of 64)
+  for (long long base = (long long)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < total; base += stride) {
+    const long long gtid = base + (threadIdx.x & 63);
+    const int lane = int(gtid % CL);
+    const int l = lane / ROW_SLOTS, q = lane % ROW_SLOTS;
+    const long long ci = gtid / CL;
+    const bool valid = gtid < total;
+    const bool row = valid && l < L;
+    long long cell = 0;
+    int cx = 0, cy = 0, cz = 0;
+    if (valid) {
+      cx = 2 * int(ci % nx) + px;
+      cy = 2 * int((ci / nx) % ny) + py;
+      cz = 2 * int(ci / ((long long)nx * ny)) + pz;
+      cell = ((long long)cz * h.ncy + cy) * h.ncx + cx;
+    }
+    const double bi = row ? a.rc[cell * L + l] : 0.0;
+    const double xi = (row && !forward) ? coh_load(a.x + cell * L + l) : 0.0;
+    double dv[L];
+#pragma unroll
+    for (int m = 0; m < L; ++m) dv[m] = row ? a.Dinv[(cell * L + l) * L + m] : 0.0;
+    // row_products with coherent loads of x
+    double part = 0.0;
+    {
+      const double* A = a.Ac + cell * 27 * L * L;
+#pragma unroll
+      for (int k = 0; k < SLOT_BLOCKS; ++k) {
+        const int bb = q + ROW_SLOTS * k;
+        bool ok = false;
+        long long nc = 0;
+        if (row && bb < 27) nc = nb_cell(h, cx, cy, cz, bb, ok);
+        if (ok && forward) {
+          const int ox = bb % 3 - 1, oy = (bb / 3) % 3 - 1, oz = bb / 9 - 1;
+          const int ncol = ((px + ox) & 1) + 2 * ((py + oy) & 1) + 4 * ((pz + oz) & 1);
+          ok = ncol < colour;
+        }
+        if (ok) {
+#pragma unroll
+          for (int m = 0; m < L; ++m) part += A[(bb * L + l) * L + m] * coh_load(a.x + nc * L + m);
+        }
+      }
+    }
+#pragma unroll
+    for (int off = 1; off < ROW_SLOTS; off <<= 1) part += __shfl_xor(part, off, 64);
+    const double tv = row ? bi - part : 0.0;
+    const int gbase = (threadIdx.x & 63) / CL * CL;
+    double upd = 0.0;
+#pragma unroll
+    for (int m = 0; m < L; ++m) {
+      const double tm = __shfl(tv, gbase + m * ROW_SLOTS, 64);
+      if (row) upd += dv[m] * tm;
+    }
+    if (row && q == 0) seen |= coh_store(a.x + cell * L + l, xi + upd);
+  }
+  return seen;
+}
+
+template <int L>
+__global__ __launch_bounds__(512) void k_level1(Level1Args a) {
+  if (a.sc->done) return;  // uniform: set by an earlier kernel
+  __shared__ int ok_sh;
+  __shared__ double ecc_sh[64];
+  if (threadIdx.x == 0) ok_sh = 1;
+  __syncthreads();
+  const Hier& h = a.h;
+  constexpr int CL = lanes_pow2<L>() * ROW_SLOTS;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  unsigned k = 0;
+  bool ok = true;
+  // forward sweep from zero: x0 = S_c^-1 r_c
+  for (int colour = 0; colour < 8; ++colour) {
+    const unsigned long long seen = l1_colour<L>(a, colour, true);
+    ok = l1_barrier(a, ++k, seen, &ok_sh);
+  }
+  // t = r_c - A_c x0
+  {
+    unsigned long long seen = 0;
+    const long long total = (long long)h.ncells * CL;
+    for (long long base = (long long)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < total; base += stride) {
+      const long long gtid = base + (threadIdx.x & 63);
+      const int lane = int(gtid % CL);
+      const int l = lane / ROW_SLOTS, q = lane % ROW_SLOTS;
+      const long long cell = gtid / CL;
+      const bool row = gtid < total && l < L;
+      int cx = 0, cy = 0, cz = 0;
+      if (row) {
+        cx = int(cell % h.ncx);
+        cy = int((cell / h.ncx) % h.ncy);
+        cz = int(cell / ((long long)h.ncx * h.ncy));
+      }
+      double part = 0.0;
+      const double* A = a.Ac + (row ? cell : 0) * 27 * L * L;
+#pragma unroll
+      for (int kk = 0; kk < SLOT_BLOCKS; ++kk) {
+        const int bb = q + ROW_SLOTS * kk;
+        bool okb = false;
+        long long nc = 0;
+        if (row && bb < 27) nc = nb_cell(h, cx, cy, cz, bb, okb);
+        if (okb) {
+#pragma unroll
+          for (int m = 0; m < L; ++m) part += A[(bb * L + l) * L + m] * coh_load(a.x + nc * L + m);
+        }
+      }
+#pragma unroll
+      for (int off = 1; off < ROW_SLOTS; off <<= 1) part += __shfl_xor(part, off, 64);
+      if (row && q == 0) seen |= coh_store(a.t + cell * L + l, a.rc[cell * L + l] - part);
+    }
+    ok = l1_barrier(a, ++k, seen, &ok_sh);
+  }
+  // r_cc = R_cc t: one wave per entry (J, b)
+  {
+    unsigned long long seen = 0;
+    const long long nw = (long long)h.ncc * h.Lcc;
+    const int lane = threadIdx.x & 63;
+    for (long long w = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w < nw; w += stride >> 6) {
+      const int J = int(w / h.Lcc), bidx = int(w % h.Lcc);
+      const int d0 = a.cc_ptr[J], nd = a.cc_ptr[J + 1] - d0;
+      const double* R = a.Rcc + (long long)h.Lcc * d0 + (long long)bidx * nd;
+      double sum = 0.0;
+      for (int d = lane; d < nd; d += 64) sum += R[d] * coh_load(a.t + a.cc_dofs[d0 + d]);
+      sum = wave_sum(sum);
+      if (lane == 0) seen |= coh_store(a.rcc + w, sum);
+    }
+    ok = l1_barrier(a, ++k, seen, &ok_sh);
+  }
+  // per coarse-coarse cell J (one workgroup at a time): e_J = rows J of
+  // A_cc^-1 r_cc (direct solve), then x1 = x0 + R_cc^T e_J on J's dofs
+  {
+    unsigned long long seen = 0;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nwaves = blockDim.x >> 6;
+    for (int J = blockIdx.x; J < h.ncc; J += gridDim.x) {
+      for (int b = wave; b < h.Lcc; b += nwaves) {
+        const double* arow = a.AccInv + (long long)(J * h.Lcc + b) * a.n_cc;
+        double sum = 0.0;
+        for (int j = lane; j < a.n_cc; j += 64) sum += arow[j] * coh_load(a.rcc + j);
+        sum = wave_sum(sum);
+        if (lane == 0) ecc_sh[b] = sum;
+      }
+      __syncthreads();
+      const int d0 = a.cc_ptr[J], nd = a.cc_ptr[J + 1] - d0;
+      const double* R = a.Rcc + (long long)h.Lcc * d0;
+      for (int d = threadIdx.x; d < nd; d += blockDim.x) {
+        const int gd = a.cc_dofs[d0 + d];
+        double v = coh_load(a.x + gd);
+        for (int b = 0; b < h.Lcc; ++b) v += R[(long long)b * nd + d] * ecc_sh[b];
+        seen |= coh_store(a.x + gd, v);
+      }
+      __syncthreads();
+    }
+    ok = l1_barrier(a, ++k, seen, &ok_sh);
+  }
+  // backward sweep from x1 on r_c: x = x1 + S_c^-T (r_c - A_c x1) = e_c
+  for (int colour = 7; colour >= 0; --colour) {
+    const unsigned long long seen = l1_colour<L>(a, colour, false);
+    if (colour > 0) ok = l1_barrier(a, ++k, seen, &ok_sh);
+    else asm volatile("" ::"v"(seen) : "memory");
+  }
+  // the last workgroup to leave resets the counters; a failed wait is reported
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (!ok) {
+      a.sc->status = ST_SYNC_TIMEOUT;
+      a.sc->done = 1;
+    }
+    const unsigned ticket = __hip_atomic_fetch_add(a.bar + L1B_EXIT, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (ticket == gridDim.x - 1)
+      for (int w = 0; w < L1B_WORDS; w += (w < L1B_EXIT ? L1B_LINE : 1))
+        __hip_atomic_store(a.bar + w, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // dispatch over the number of basis vectors per cell (1 .. LC_MAX)
 #define COARSE_L_DISPATCH(Lrt, ...)                          \
   do {                                                       \
@@ -256,6 +542,50 @@ void launch_acc_solve(const Ctx& c, const double* rcc, double* ecc, hipStream_t 
   const long long n = c.cc.n_cc;
   const dim3 gr((unsigned)((n * 64 + 255) / 256)), bl(256);
   hipLaunchKernelGGL(k_acc_solve, gr, bl, 0, s, c.cc.n_cc, c.cc.AccInv, rcc, ecc, c.sc);
+}
+
+int level1_barrier_words() { return L1B_WORDS; }
+
+int level1_blocks() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) return 0;
+  int per = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(&k_level1<4>), 512, 0) !=
+          hipSuccess ||
+      per < 1)
+    return 0;
+  return cus;  // one workgroup per compute unit (co-resident: per >= 1)
+}
+
+hipError_t launch_level1(const Ctx& c, int blocks, const double* rc, double* x, double* t, double* rcc,
+                         unsigned* bar, unsigned spin_limit, hipStream_t s) {
+  if (c.cc.a_dt != DT_F64 || c.h.Lcc > 64 || blocks < 1) return hipErrorInvalidValue;
+  Level1Args a{};
+  a.h = c.h;
+  a.Ac = (const double*)c.cc.Ac;
+  a.Dinv = (const double*)c.cc.AcDinv;
+  a.rc = rc;
+  a.x = x;
+  a.t = t;
+  a.rcc = rcc;
+  a.Rcc = (const double*)c.cc.Rcc;
+  a.cc_ptr = c.cc.cc_ptr;
+  a.cc_dofs = c.cc.cc_dofs;
+  a.AccInv = c.cc.AccInv;
+  a.n_cc = c.cc.n_cc;
+  a.bar = bar;
+  a.sc = c.sc;
+  a.spin_limit = spin_limit;
+  // An ordinary launch: `blocks` is at most the device's co-resident capacity
+  // for this kernel (level1_blocks), and the kernels before it on the stream
+  // finish without waiting for it, so every workgroup becomes resident; the
+  // cooperative launch API gives the same guarantee but delays the start of
+  // the kernel (about 20 us per launch measured at 256^3), and the bounded
+  // waits turn any failure of the assumption into MSMG_ETIMEOUT instead of a
+  // hang.
+  COARSE_L_DISPATCH(c.h.Lc, hipLaunchKernelGGL((k_level1<LL>), dim3(blocks), dim3(512), 0, s, a));
+  return hipGetLastError();
 }
 
 void launch_cc_prolong(const Ctx& c, const void* base, const double* ecc, void* out, hipStream_t s) {

@@ -329,7 +329,14 @@ struct Scalars {
   int maxit;
 };
 
-enum SolveStatus { ST_RUNNING = 0, ST_CONV_RECURSIVE = 1, ST_MAXIT = 2, ST_BREAKDOWN = 3, ST_NONFINITE = 4 };
+enum SolveStatus {
+  ST_RUNNING = 0,
+  ST_CONV_RECURSIVE = 1,
+  ST_MAXIT = 2,
+  ST_BREAKDOWN = 3,
+  ST_NONFINITE = 4,
+  ST_SYNC_TIMEOUT = 5  // a bounded device-side wait gave up (grid-synchronised coarse-level kernel)
+};
 
 // Cross-block deterministic reduction: each block publishes its partials, the
 // last block to finish sums all partials in block order and runs `fin`.

@@ -6,6 +6,8 @@
 // Paper anchors: material law eq. (material); the system A t = f of section
 // 2.2 (here with Q1 elements); Algorithm 1 (three-grid cycle) lines for the
 // fine level; adjoint sensitivity of section 2.3.
+#include <algorithm>
+
 #include "internal.h"
 #include "setup.h"
 
@@ -544,6 +546,138 @@ MSMG_MARCH_KERNEL void k_vresidual(Geo g, Stencil st, March mg, const KT* __rest
       });
 }
 
+// ---------------------------------------------------------------------------
+// Residual fused with the restriction of Algorithm 1: rc = R_c (r - A x).  The
+// march computes the residual of each node (rounded to the cycle's vector type
+// VT, as the stored residual would be) and accumulates R_c[n][l] times it for
+// the node's coarse cell; the residual itself is never stored.  At the end of
+// every coarse z-cell of its chunk a workgroup reduces the sums per coarse
+// cell it meets (lanes of one cell row by shuffles, then rows) and writes them
+// to its own slots of rpart; k_restrict_finish adds the slots of each cell in
+// a fixed order, so the result is bitwise reproducible.
+template <typename IT, typename BT, int L>
+struct RWB {
+  IT r;
+  uint32_t w;
+  BT row[L];
+};
+
+template <typename BT, int L>
+MSMG_DEV void load_row_raw(const BT* __restrict__ Rc, long long n, BT out[L]) {
+  constexpr int B = L * int(sizeof(BT));
+  if constexpr (B == 32) {
+    const uint4* p = reinterpret_cast<const uint4*>(Rc + n * L);
+    const uint4 w0 = p[0], w1 = p[1];
+    __builtin_memcpy(out, &w0, 16);
+    __builtin_memcpy(reinterpret_cast<char*>(out) + 16, &w1, 16);
+  } else if constexpr (B == 16) {
+    const uint4 w = *reinterpret_cast<const uint4*>(Rc + n * L);
+    __builtin_memcpy(out, &w, 16);
+  } else if constexpr (B == 8) {
+    const uint2 w = *reinterpret_cast<const uint2*>(Rc + n * L);
+    __builtin_memcpy(out, &w, 8);
+  } else if constexpr (B == 4) {
+    const uint32_t w = *reinterpret_cast<const uint32_t*>(Rc + n * L);
+    __builtin_memcpy(out, &w, 4);
+  } else {
+#pragma unroll
+    for (int l = 0; l < L; ++l) out[l] = Rc[n * L + l];
+  }
+}
+
+template <typename VT, typename KT, typename XT, typename BT, int L, bool CUBIC>
+MSMG_MARCH_KERNEL void k_vresidual_restrict(Geo g, Stencil st, Hier h, RestrictGeo rg, const KT* __restrict__ kv,
+                                            const uint32_t* __restrict__ bits, const double* __restrict__ r,
+                                            const XT* __restrict__ x, const BT* __restrict__ Rc,
+                                            double* __restrict__ rpart, const Scalars* sc) {
+  if (sc && sc->done) return;
+  __shared__ XT sx[2 * PW * PH];
+  __shared__ XT sk[2 * EW * EH];
+  __shared__ double red[MY * (MX / 2) * L];  // [row][cell of the row][l], at most MX / 2 cells per row
+  const long long tile = xcd_tile(blockIdx.x, gridDim.x);
+  const March& mg = rg.m;
+  const int tx = int(tile % mg.ntx), ty = int((tile / mg.ntx) % mg.nty);
+  const int xa = tx * MX, ya = ty * MY;
+  const int lx = threadIdx.x, ly = threadIdx.y, tid = lx + MX * ly;
+  const int H = h.H;
+  const int cx0 = owner_axis(xa, H, h.ncx), cy0 = owner_axis(ya, H, h.ncy);
+  double acc[L];
+#pragma unroll
+  for (int l = 0; l < L; ++l) acc[l] = 0.0;
+  march_ex<XT, CUBIC>(
+      g, st, mg, tile, sx, sk, [&](long long b, unsigned o) { return plane_ld(x, b, o); }, [&](XT v) { return v; },
+      [&](long long b, unsigned o) { return plane_ld(kv, b, o); }, [&](KT v) { return cvt<XT, KT>(v); },
+      [&](long long b, unsigned o) {
+        RWB<double, BT, L> c;
+        c.r = plane_ld(r, b, o);
+        c.w = bits[(b + o) >> 5];
+        load_row_raw<BT, L>(Rc, b + o, c.row);
+        return c;
+      },
+      [&](long long b, unsigned o, XT ax, XT, const RWB<double, BT, L>& c) {
+        if ((c.w >> ((b + o) & 31)) & 1u) return;  // fixed node: residual and basis vanish
+        const double res = double(VT(cvt<XT, double>(c.r) - ax));
+#pragma unroll
+        for (int l = 0; l < L; ++l) acc[l] += to_f64(c.row[l]) * res;
+      },
+      [&](int z, int za, int zb) {
+        if (z >= zb) return;
+        const int czl = owner_axis(z, H, h.ncz);
+        if (z + 1 < zb && owner_axis(z + 1, H, h.ncz) == czl) return;  // uniform over the workgroup
+        // cell sums of this row: groups of H lanes (a row is one wave, MX = 64)
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+          double v = acc[l];
+          for (int off = 1; off < H; off <<= 1) v += __shfl_xor(v, off, 64);
+          if (lx % H == 0) red[(ly * (MX / 2) + lx / H) * L + l] = v;
+          acc[l] = 0.0;
+        }
+        __syncthreads();
+        // the last cell of an axis keeps the remainder nodes, so it may hold
+        // several lane groups (and rows): add the groups by owner cell
+        const int lcz = czl - owner_axis(za, H, h.ncz);
+        const int ngrp = MX / H;
+        for (int q = tid; q < rg.nlx * rg.nly * L; q += MARCH_THREADS) {
+          const int l = q % L, lc = q / L, lcx = lc % rg.nlx, lcy = lc / rg.nlx;
+          double sum = 0.0;
+          for (int row = 0; row < MY; ++row) {
+            if (owner_axis(ya + row, H, h.ncy) - cy0 != lcy) continue;
+            for (int grp = 0; grp < ngrp; ++grp)
+              if (owner_axis(xa + grp * H, H, h.ncx) - cx0 == lcx) sum += red[(row * (MX / 2) + grp) * L + l];
+          }
+          rpart[(((tile * rg.nlz + lcz) * rg.nly + lcy) * rg.nlx + lcx) * L + l] = sum;
+        }
+        __syncthreads();
+      });
+}
+
+// rc[cell][l] = sum of the cell's slots, over the workgroups whose column
+// blocks meet the cell (y, then x), in its one z chunk.
+template <int L>
+__global__ void k_restrict_finish(Geo g, Hier h, RestrictGeo rg, const double* __restrict__ rpart,
+                                  double* __restrict__ rc, const Scalars* sc) {
+  if (sc && sc->done) return;
+  const long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (q >= (long long)h.ncells * L) return;
+  const int l = int(q % L);
+  const long long cell = q / L;
+  const int cx = int(cell % h.ncx), cy = int((cell / h.ncx) % h.ncy), cz = int(cell / ((long long)h.ncx * h.ncy));
+  const int H = h.H;
+  const int tx0 = (cx * H) / MX, tx1 = (cell_end(cx, H, h.ncx, g.nnx) - 1) / MX;
+  const int ty0 = (cy * H) / MY, ty1 = (cell_end(cy, H, h.ncy, g.nny) - 1) / MY;
+  const int tz = cz / rg.czc, lcz = cz - tz * rg.czc;
+  double sum = 0.0;
+  for (int ty = ty0; ty <= ty1; ++ty) {
+    const int lcy = cy - owner_axis(ty * MY, H, h.ncy);
+    for (int tx = tx0; tx <= tx1; ++tx) {
+      const int lcx = cx - owner_axis(tx * MX, H, h.ncx);
+      const long long tile = tx + (long long)rg.m.ntx * (ty + (long long)rg.m.nty * tz);
+      sum += rpart[(((tile * rg.nlz + lcz) * rg.nly + lcy) * rg.nlx + lcx) * L + l];
+    }
+  }
+  rc[cell * L + l] = sum;
+}
+
 // PCG scalars after a preconditioner application: tt = (z^T r, z^T q).
 MSMG_DEV void vc_finish(Scalars* sc, const double* tt, int mode) {
   sc->zr = tt[0];
@@ -747,6 +881,21 @@ __global__ void k_prolong_nodal(int nx, int ny, int nz, const double* __restrict
 }
 
 // Element injection (nx,ny,nz) -> (2nx,2ny,2nz): each child takes its parent's value.
+// Streaming reference of the operator apply's memory traffic: y = x + k over
+// the first ne entries, y = x beyond, i.e. exactly one read of every x and k
+// value and one write of every y value (8 B per node twice, 8 B per element),
+// coalesced, with no stencil and no halo.  Its rate is the bandwidth this
+// access mix reaches on the device, the practical ceiling of k_apply.
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+__global__ void k_stream_ceiling(const dvec2* __restrict__ x, const dvec2* __restrict__ k, dvec2* __restrict__ y,
+                                 long long nn2, long long ne2) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nn2; i += (long long)gridDim.x * blockDim.x) {
+    dvec2 v = __builtin_nontemporal_load(x + i);
+    if (i < ne2) v += __builtin_nontemporal_load(k + i);
+    __builtin_nontemporal_store(v, y + i);
+  }
+}
+
 template <typename T>
 __global__ void k_prolong_element(int nx, int ny, int nz, const T* __restrict__ rc, T* __restrict__ rf) {
   const long long fnx = 2LL * nx, fny = 2LL * ny, fnz = 2LL * nz;
@@ -809,7 +958,7 @@ void launch_sc_reset(const Ctx& c, int full, int maxit, hipStream_t s) {
   hipLaunchKernelGGL(k_sc_reset, dim3(1), dim3(64), 0, s, c.sc, full, maxit);
 }
 int count_fixed(const Ctx& c, int* nfixed, hipStream_t s) {
-  unsigned* d = reinterpret_cast<unsigned*>(c.counter) + 8;  // spare slot of the counter block
+  unsigned* d = c.counter + CTR_FIXED;
   if (hipMemsetAsync(d, 0, 4, s) != hipSuccess) return MSMG_EHIP;
   const long long nw = (c.g.nn + 31) >> 5;
   hipLaunchKernelGGL(k_count_bits, dim3(512), dim3(256), 0, s, c.bits, nw, d);
@@ -1060,6 +1209,46 @@ void launch_vresidual(const Ctx& c, const void* r, bool r_is_f64, const void* x,
   });
 }
 
+RestrictGeo make_restrict_geo(const Geo& g, const Hier& h, long long resident) {
+  RestrictGeo rg{};
+  rg.m.ntx = (g.nnx + MX - 1) / MX;
+  rg.m.nty = (g.nny + MY - 1) / MY;
+  const long long txy = (long long)rg.m.ntx * rg.m.nty;
+  if (resident < 1) resident = 1;
+  // coarse z-cells per chunk: the fewest rounds of resident workgroups times
+  // planes staged per workgroup (as make_march)
+  long long best_cost = -1;
+  int best = 1;
+  for (int czc = 1; czc <= h.ncz; ++czc) {
+    const int nzc = (h.ncz + czc - 1) / czc;
+    const long long rounds = (txy * nzc + resident - 1) / resident;
+    const long long cost = rounds * (czc * h.H + 2);
+    if (best_cost < 0 || cost < best_cost) {
+      best_cost = cost;
+      best = czc;
+    }
+  }
+  rg.czc = best;
+  rg.m.zc = best * h.H;
+  rg.m.nzc = (h.ncz + best - 1) / best;
+  rg.m.blocks = ((txy * rg.m.nzc + 7) / 8) * 8;
+  rg.nlx = MX / h.H > 0 ? MX / h.H : 1;
+  rg.nly = MY / h.H > 0 ? MY / h.H : 1;
+  rg.nlz = best;
+  rg.slots = txy * rg.m.nzc * rg.nlx * rg.nly * rg.nlz;
+  return rg;
+}
+
+void launch_vresidual_restrict(const Ctx& c, const double* r, const void* x, double* rc, hipStream_t s) {
+  const dim3 gr((unsigned)c.rg.m.blocks), bl = march_block();
+  VC_DISPATCH({
+    (void)sizeof(DVT);
+    L_DISPATCH(c.h.Lc, hipLaunchKernelGGL((k_vresidual_restrict<VT, KVT, VT, BT, LL, CU>), gr, bl, 0, s, c.g, c.st, c.h, c.rg, (const KVT*)c.kv, c.bits, r, (const VT*)x, (const BT*)c.Rc, c.rpart, c.sc));
+  });
+  const long long n = (long long)c.h.ncells * c.h.Lc;
+  L_DISPATCH(c.h.Lc, hipLaunchKernelGGL((k_restrict_finish<LL>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, c.g, c.h, c.rg, (const double*)c.rpart, rc, c.sc));
+}
+
 void launch_vc_output(const Ctx& c, const void* a, bool a_is_f64, const void* b, double* z, const double* r,
                       const double* q, int mode, hipStream_t s) {
   const int nb = grid1d(c.g.nn, 256, c.red_blocks);
@@ -1123,6 +1312,15 @@ void launch_element_load(const Geo& g, const double* src, double sconst, double*
 void launch_prolong_nodal(int nx, int ny, int nz, const double* tc, double* tf, hipStream_t s) {
   const long long n = (2LL * nx + 1) * (2LL * ny + 1) * (2LL * nz + 1);
   hipLaunchKernelGGL(k_prolong_nodal, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, nx, ny, nz, tc, tf);
+}
+
+void launch_stream_ceiling(const double* x, const double* k, double* y, long long nn, long long ne, hipStream_t s) {
+  const long long nn2 = nn / 2, ne2 = ne / 2;
+  int dev = 0, cus = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const dim3 gr((unsigned)std::max<long long>(1, std::min<long long>((nn2 + 255) / 256, 16LL * cus))), bl(256);
+  hipLaunchKernelGGL(k_stream_ceiling, gr, bl, 0, s, (const dvec2*)x, (const dvec2*)k, (dvec2*)y, nn2, ne2);
 }
 
 void launch_prolong_element(int nx, int ny, int nz, const void* rc, void* rf, int dt, hipStream_t s) {

@@ -32,6 +32,22 @@ struct CoarseCtx {
   int n_c, n_cc;
 };
 
+// Partial sums of the restriction fused into the cycle's first residual: the
+// march runs on z chunks of whole coarse cells (czc of them, the last chunk
+// also takes the remainder planes of the last cell); a workgroup's MX x MY
+// column block meets at most nlx x nly coarse cells per z-cell, so each
+// workgroup owns nlx * nly * nlz slots of L_c sums.
+struct RestrictGeo {
+  March m;            // cell-aligned march: zc = czc * H, nzc = ceil(ncz / czc)
+  int czc;
+  int nlx, nly, nlz;  // local coarse cells per workgroup along x, y, z
+  long long slots;    // workgroups x local cells (each slot holds L_c doubles)
+};
+RestrictGeo make_restrict_geo(const Geo& g, const Hier& h, long long resident);
+// The fused residual + restriction covers cell sizes that divide the march's
+// tile rows into whole lane groups: H in {2, 4, 8, 16}.
+inline bool restrict_fusable(const Hier& h) { return h.H == 2 || h.H == 4 || h.H == 8 || h.H == 16; }
+
 struct Ctx {
   Geo g;
   Stencil st;
@@ -58,8 +74,15 @@ struct Ctx {
   int red_blocks;
   void* vc_t0;        // V-cycle scratch vectors (v_dt)
   void* vc_t1;
+  RestrictGeo rg;     // fused residual + restriction (when restrict_fusable)
+  double* rpart;      // its per-workgroup partial sums, rg.slots * Lc doubles
   CoarseCtx cc;
 };
+
+// Slots of the handle's 16-word counter block (zero between kernels unless
+// noted): the ticket of grid_reduce, the fixed-node count of a set-up (left
+// holding the count).
+constexpr int CTR_REDUCE = 0, CTR_FIXED = 8;
 
 // 1-D launch size: one thread per item, at most `cap` workgroups (grid-stride loops)
 inline int grid1d(long long n, int bs, int cap = 4096) {
@@ -106,6 +129,10 @@ void launch_restrict(const Ctx& c, const void* r, void* rc, hipStream_t s);
 void launch_prolong(const Ctx& c, const void* base, const void* e1, const void* e2, void* out, hipStream_t s);
 void launch_vresidual(const Ctx& c, const void* r, bool r_is_f64, const void* x, bool x_is_f64, void* out,
                       hipStream_t s);
+// rc = R_c (r - A x) without storing the residual (r FP64, x of the cycle's
+// vector type): the fused march writes per-workgroup partials, a second kernel
+// adds them per coarse cell in a fixed order.  Only when restrict_fusable.
+void launch_vresidual_restrict(const Ctx& c, const double* r, const void* x, double* rc, hipStream_t s);
 void launch_vc_output(const Ctx& c, const void* a, bool a_is_f64, const void* b, double* z, const double* r,
                       const double* q, int mode, hipStream_t s);
 // Degree-2 post-smoother fused with the output: z = base + S^-1 in (base may be
@@ -120,6 +147,9 @@ void launch_heat_source_load(const Ctx& c, double f0, double* f, hipStream_t s);
 void launch_element_load(const Geo& g, const double* src, double sconst, double* f, hipStream_t s);
 void launch_prolong_nodal(int nx, int ny, int nz, const double* tc, double* tf, hipStream_t s);
 void launch_prolong_element(int nx, int ny, int nz, const void* rc, void* rf, int dt, hipStream_t s);
+// one read of x (nn) and k (ne <= nn) and one write of y (nn), coalesced: the
+// operator apply's traffic without its stencil (nn, ne even)
+void launch_stream_ceiling(const double* x, const double* k, double* y, long long nn, long long ne, hipStream_t s);
 
 // coarse levels (V-cycle)
 void launch_gs_sweep(const Ctx& c, const void* b, void* x, bool forward, hipStream_t s);
@@ -127,5 +157,15 @@ void launch_ac_residual(const Ctx& c, const void* b, const void* x, void* t, hip
 void launch_cc_restrict(const Ctx& c, const void* t, double* rcc, hipStream_t s);
 void launch_acc_solve(const Ctx& c, const double* rcc, double* ecc, hipStream_t s);
 void launch_cc_prolong(const Ctx& c, const void* base, const double* ecc, void* out, hipStream_t s);
+// Levels 1 and 2 of Algorithm 1 (coarse sweeps, coarse-coarse restriction,
+// direct solve, prolongation) in one launch of `blocks` workgroups with
+// grid-wide barriers between the steps (level1_blocks(): one per compute unit,
+// within the device's co-resident capacity; 0 when that cannot be had).
+// Input rc; output x = e_c, the coarse correction; t and rcc are its scratch;
+// bar: level1_barrier_words() zeroed words.  FP64 A_c only.
+int level1_blocks();
+int level1_barrier_words();  // size of its barrier buffer (unsigned words)
+hipError_t launch_level1(const Ctx& c, int blocks, const double* rc, double* x, double* t, double* rcc,
+                         unsigned* bar, unsigned spin_limit, hipStream_t s);
 
 }  // namespace msmg

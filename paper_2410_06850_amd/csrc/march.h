@@ -133,10 +133,16 @@ constexpr int march_depth() {
 // outside the mesh stage 0 when written to LDS) and the step loop has a fixed
 // shape, so the compiler can count the loads in flight exactly and waits only
 // for the queue slot a step consumes.
+//
+// after(z, za, zb) runs at the end of every step, in every thread of the
+// workgroup (also for the padding steps past zb), after the step's emits: the
+// place for work that needs the whole workgroup, such as a block reduction.
+// The z chunk of workgroup tz is [tz * zc, tz * zc + zc), the last one up to
+// the last plane (it may be longer than zc).
 template <typename W, bool CUBIC, typename LoadN, typename ConvN, typename LoadK, typename ConvK, typename LoadC,
-          typename Emit>
-MSMG_DEV void march(const Geo& g, const Stencil& st, const March& mg, long long tile, W* sx, W* sk, LoadN loadn,
-                    ConvN convn, LoadK loadk, ConvK convk, LoadC loadc, Emit emit) {
+          typename Emit, typename After>
+MSMG_DEV void march_ex(const Geo& g, const Stencil& st, const March& mg, long long tile, W* sx, W* sk, LoadN loadn,
+                       ConvN convn, LoadK loadk, ConvK convk, LoadC loadc, Emit emit, After after) {
   using RN = decltype(loadn(0LL, 0u));
   using RK = decltype(loadk(0LL, 0u));
   using CD = decltype(loadc(0LL, 0u));
@@ -144,7 +150,7 @@ MSMG_DEV void march(const Geo& g, const Stencil& st, const March& mg, long long 
   const int tx = int(tile % mg.ntx), ty = int((tile / mg.ntx) % mg.nty), tz = int(tile / ((long long)mg.ntx * mg.nty));
   const int za = tz * mg.zc;
   if (tz >= mg.nzc || za >= g.nnz) return;  // uniform over the block
-  const int zb = min(za + mg.zc, g.nnz);
+  const int zb = (tz == mg.nzc - 1) ? g.nnz : min(za + mg.zc, g.nnz);
   const int xa = tx * MX, ya = ty * MY;
   const int lx = threadIdx.x, ly = threadIdx.y, tid = lx + MX * ly;
   const int x = xa + lx, y = ya + ly;
@@ -266,8 +272,16 @@ MSMG_DEV void march(const Geo& g, const Stencil& st, const March& mg, long long 
       carry = layer_apply<W, CUBIC>(st, kq, B, A);
 #pragma unroll
       for (int q = 0; q < 9; ++q) A[q] = B[q];
+      after(z, za, zb);
     }
   }
+}
+
+template <typename W, bool CUBIC, typename LoadN, typename ConvN, typename LoadK, typename ConvK, typename LoadC,
+          typename Emit>
+MSMG_DEV void march(const Geo& g, const Stencil& st, const March& mg, long long tile, W* sx, W* sk, LoadN loadn,
+                    ConvN convn, LoadK loadk, ConvK convk, LoadC loadc, Emit emit) {
+  march_ex<W, CUBIC>(g, st, mg, tile, sx, sk, loadn, convn, loadk, convk, loadc, emit, [](int, int, int) {});
 }
 
 
@@ -360,7 +374,7 @@ MSMG_DEV void march_lds(const Geo& g, const Stencil& st, const March& mg, long l
   const int tx = int(tile % mg.ntx), ty = int((tile / mg.ntx) % mg.nty), tz = int(tile / ((long long)mg.ntx * mg.nty));
   const int za = tz * mg.zc;
   if (tz >= mg.nzc || za >= g.nnz) return;  // uniform over the block
-  const int zb = min(za + mg.zc, g.nnz);
+  const int zb = (tz == mg.nzc - 1) ? g.nnz : min(za + mg.zc, g.nnz);
   const int xa = tx * LMX, ya = ty * LMY;
   const int lx = threadIdx.x, ly = threadIdx.y, tid = lx + LMX * ly;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;

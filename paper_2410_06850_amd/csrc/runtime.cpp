@@ -87,6 +87,10 @@ struct msmg_handle {
   void *v_r1 = nullptr, *v_r2 = nullptr, *v_res = nullptr, *v_t0 = nullptr, *v_t1 = nullptr;
   void *c_rc = nullptr, *c_x0 = nullptr, *c_t = nullptr, *c_x1 = nullptr, *c_d = nullptr;
   double *rcc = nullptr, *ecc = nullptr;
+  int l1_blocks = 0;         // workgroups of the grid-synchronised coarse-level kernel (0: separate launches)
+  unsigned* l1_bar = nullptr;  // its barrier words
+  RestrictGeo rg{};          // fused residual + restriction of the cycle
+  double* rpart = nullptr;   // its per-workgroup partial sums
 
   Scalars* sc = nullptr;
   Scalars* sc_host = nullptr;  // pinned
@@ -272,6 +276,8 @@ static Ctx make_ctx(msmg_handle* h) {
   c.red_blocks = h->red_blocks;
   c.vc_t0 = h->v_t0;
   c.vc_t1 = h->v_t1;
+  c.rg = h->rg;
+  c.rpart = h->rpart;
   c.cc.Ac = h->Acv;
   c.cc.AcDinv = h->AcDinvv;
   c.cc.a_dt = h->a_dt;
@@ -347,6 +353,7 @@ extern "C" void msmg_default_options(msmg_options* o) {
   o->rho_storage = MSMG_F64;
   o->lean_memory = 0;
   o->cc_group = 0;
+  o->coarse_fused = 3;
 }
 
 extern "C" const char* msmg_last_error(void) { return g_last_error.c_str(); }
@@ -451,6 +458,11 @@ static int alloc_arrays(msmg_handle* h, bool dry, size_t* total) {
     A(&h->c_rc, (size_t)h->n_c * 8); A(&h->c_x0, (size_t)h->n_c * 8); A(&h->c_t, (size_t)h->n_c * 8);
     A(&h->c_x1, (size_t)h->n_c * 8); A(&h->c_d, (size_t)h->n_c * 8);
     A(&h->rcc, (size_t)h->n_cc * 8); A(&h->ecc, (size_t)h->n_cc * 8);
+    if (o.coarse_fused & 1) A(&h->l1_bar, (size_t)level1_barrier_words() * 4);
+    if ((o.coarse_fused & 2) && restrict_fusable(h->hier)) {
+      h->rg = make_restrict_geo(h->g, h->hier, h->march_resident);
+      A(&h->rpart, (size_t)h->rg.slots * h->hier.Lc * 8);
+    }
     if (rc == MSMG_OK)
       rc = setup_scratch_alloc(h->g, h->hier, h->max_cc_dofs, h->n_cc, o, &h->scratch, [&](void** p, size_t bytes) {
         sum += bytes;
@@ -526,6 +538,7 @@ extern "C" int msmg_create(msmg_handle** out, int nx, int ny, int nz, double lx,
   h->march_resident = march_resident_blocks();
   h->apply_resident = apply_resident_blocks();
   int rc = alloc_arrays(h, false, nullptr);
+  if (rc == MSMG_OK && h->mg && h->l1_bar && h->a_dt == DT_F64 && h->hier.Lcc <= 64) h->l1_blocks = level1_blocks();
   if (rc == MSMG_OK) {
     hipError_t e = hipHostMalloc((void**)&h->sc_host, sizeof(Scalars), hipHostMallocDefault);
     if (e != hipSuccess) rc = fail(MSMG_ENOMEM, "pinned host allocation failed");
@@ -541,6 +554,7 @@ extern "C" int msmg_create(msmg_handle** out, int nx, int ny, int nz, double lx,
   if (!h->AcDinvv) h->AcDinvv = h->AcDinv64;
   if (!h->Rccv) h->Rccv = h->Rcc64;
   HIP_TRY(hipMemset(h->counter, 0, 64));
+  if (h->l1_bar) HIP_TRY(hipMemset(h->l1_bar, 0, (size_t)level1_barrier_words() * 4));
   HIP_TRY(hipMemset(h->sc, 0, sizeof(Scalars)));
   if (o.timing) {
     // events of the per-iteration timing (created here, outside any solve)
@@ -683,6 +697,35 @@ extern "C" int msmg_setup(msmg_handle* h, const void* rho, msmg_dtype rho_dtype,
   return MSMG_OK;
 }
 
+// Polls of one bounded barrier wait in the grid-synchronised coarse-level kernel
+// (each poll sleeps ~60 ns): about a quarter of a second, far beyond any
+// legitimate wait, after which the solve reports MSMG_ETIMEOUT.
+static constexpr unsigned LEVEL1_SPIN_LIMIT = 1u << 22;
+
+// Levels 1 and 2 of Algorithm 1 and the prolongation to level 0:
+// v_r2 = r1 + R_c^T e_c from the restricted residual c_rc.
+static void coarse_correction(msmg_handle* h, const Ctx& c, hipStream_t s) {
+  if (h->l1_blocks > 0) {
+    // every coarse step in one grid-synchronised launch; c_x0 ends as e_c
+    if (launch_level1(c, h->l1_blocks, (const double*)h->c_rc, (double*)h->c_x0, (double*)h->c_t, h->rcc,
+                      h->l1_bar, LEVEL1_SPIN_LIMIT, s) == hipSuccess) {
+      launch_prolong(c, h->v_r1, h->c_x0, nullptr, h->v_r2, s);
+      return;
+    }
+    // the launch failed: one launch per step from now on
+    (void)hipGetLastError();
+    h->l1_blocks = 0;
+  }
+  launch_gs_sweep(c, h->c_rc, h->c_x0, true, s);                    // rc0 = S_c^-1 rc
+  launch_ac_residual(c, h->c_rc, h->c_x0, h->c_t, s);               // rc - A_c rc0
+  launch_cc_restrict(c, h->c_t, h->rcc, s);                         // rcc = R_cc (...)
+  launch_acc_solve(c, h->rcc, h->ecc, s);                           // ecc = A_cc^-1 rcc
+  launch_cc_prolong(c, h->c_x0, h->ecc, h->c_x1, s);                // rc1 = rc0 + R_cc^T ecc
+  launch_ac_residual(c, h->c_rc, h->c_x1, h->c_t, s);               // rc - A_c rc1
+  launch_gs_sweep(c, h->c_t, h->c_d, false, s);                     // S_c^-T (...)
+  launch_prolong(c, h->v_r1, h->c_x1, h->c_d, h->v_r2, s);          // r2 = r1 + R_c^T ec (FP64)
+}
+
 // One preconditioner application r (FP64) -> z (FP64) with the PCG reduction
 // mode (0 init, 1 iteration, 2 none).
 static void precondition(msmg_handle* h, const Ctx& c, const double* r, double* z, const double* q, int mode,
@@ -699,16 +742,13 @@ static void precondition(msmg_handle* h, const Ctx& c, const double* r, double* 
     return;
   }
   launch_smooth(c, r, true, h->v_r1, s);                            // r1 = S^-1 r0
-  launch_vresidual(c, r, true, h->v_r1, v64, h->v_res, s);          // r0 - A r1
-  launch_restrict(c, h->v_res, h->c_rc, s);                         // rc = R_c (r0 - A r1)
-  launch_gs_sweep(c, h->c_rc, h->c_x0, true, s);                    // rc0 = S_c^-1 rc
-  launch_ac_residual(c, h->c_rc, h->c_x0, h->c_t, s);               // rc - A_c rc0
-  launch_cc_restrict(c, h->c_t, h->rcc, s);                         // rcc = R_cc (...)
-  launch_acc_solve(c, h->rcc, h->ecc, s);                           // ecc = A_cc^-1 rcc
-  launch_cc_prolong(c, h->c_x0, h->ecc, h->c_x1, s);                // rc1 = rc0 + R_cc^T ecc
-  launch_ac_residual(c, h->c_rc, h->c_x1, h->c_t, s);               // rc - A_c rc1
-  launch_gs_sweep(c, h->c_t, h->c_d, false, s);                     // S_c^-T (...)
-  launch_prolong(c, h->v_r1, h->c_x1, h->c_d, h->v_r2, s);          // r2 = r1 + R_c^T ec (FP64)
+  if (h->rpart) {
+    launch_vresidual_restrict(c, r, h->v_r1, (double*)h->c_rc, s);  // rc = R_c (r0 - A r1)
+  } else {
+    launch_vresidual(c, r, true, h->v_r1, v64, h->v_res, s);        // r0 - A r1
+    launch_restrict(c, h->v_res, h->c_rc, s);                       // rc = R_c (r0 - A r1)
+  }
+  coarse_correction(h, c, s);                                       // r2 = r1 + R_c^T e_c
   launch_vresidual(c, r, true, h->v_r2, true, h->v_res, s);         // r0 - A r2
   if (fused) {
     launch_smooth_output(c, h->v_res, false, (const double*)h->v_r2, z, r, q, mode, s);  // y = r2 + S^-T (...)
@@ -733,6 +773,12 @@ extern "C" int msmg_precondition(msmg_handle* h, const double* r, double* z, hip
   launch_zero_fixed_copy(c, r, h->r, s);
   precondition(h, c, h->r, z, nullptr, 2, s);
   HIP_TRY(hipGetLastError());
+  if (h->l1_blocks > 0) {
+    // the grid-synchronised coarse-level kernel reports a failed wait in the scalars
+    TRY(read_scalars(h, s));
+    if (h->sc_host->status == ST_SYNC_TIMEOUT)
+      return fail(MSMG_ETIMEOUT, "a grid-wide wait of the coarse-level kernel exceeded its limit");
+  }
   return MSMG_OK;
 }
 
@@ -784,6 +830,33 @@ extern "C" int msmg_element_load(msmg_handle* h, const double* src, double scons
   if (!h || !f) return fail(MSMG_EINVAL, "NULL argument");
   launch_element_load(h->g, src, sconst, f, s);
   HIP_TRY(hipGetLastError());
+  return MSMG_OK;
+}
+
+extern "C" int msmg_stream_ceiling(const double* x, const double* k, double* y, long long nn, long long ne, int reps,
+                                   double* ms, hipStream_t s) {
+  if (!x || !k || !y || !ms) return fail(MSMG_EINVAL, "NULL argument");
+  if (nn < 2 || ne < 2 || ne > nn || (nn & 1) || (ne & 1) || reps < 1)
+    return fail(MSMG_EINVAL, "need even sizes 2 <= ne <= nn and reps >= 1");
+  if (x == y || k == y) return fail(MSMG_EINVAL, "y must not alias x or k");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  hipError_t err = hipEventCreate(&e1);
+  if (err != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(MSMG_EHIP, std::string("hipEventCreate: ") + hipGetErrorString(err));
+  }
+  launch_stream_ceiling(x, k, y, nn, ne, s);  // warm-up
+  err = hipEventRecord(e0, s);
+  for (int r = 0; r < reps && err == hipSuccess; ++r) launch_stream_ceiling(x, k, y, nn, ne, s);
+  if (err == hipSuccess) err = hipEventRecord(e1, s);
+  if (err == hipSuccess) err = hipEventSynchronize(e1);
+  float t = 0.f;
+  if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess) return fail(MSMG_EHIP, std::string("stream ceiling: ") + hipGetErrorString(err));
+  *ms = double(t) / reps;
   return MSMG_OK;
 }
 
@@ -902,6 +975,8 @@ static int solve_impl(msmg_handle* h, const double* f, double* T, double* T_lo, 
         launch_update_px(c, x, h->xlo, h->p, h->z, s);
         continue;
       }
+      if (S.status == ST_SYNC_TIMEOUT)
+        return fail(MSMG_ETIMEOUT, "a grid-wide wait of the coarse-level kernel exceeded its limit");
       status = (S.status == ST_MAXIT) ? MSMG_MAXIT : (S.status == ST_BREAKDOWN ? MSMG_BREAKDOWN : MSMG_NONFINITE);
       launch_residual(c, h->b, x, h->xlo, h->q, true, s);
       TRY(read_scalars(h, s));

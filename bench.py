@@ -285,18 +285,21 @@ def run_workload(name, args):
         mask = torch.tensor(synth.dirichlet_patch_mask(n, n, n).ravel(), device=dev)
         t0 = time.perf_counter()
         _, hist = pkg.topopt.optimize(s, mask, iterations=args.iterations, volume_fraction=0.3, x0=0.3,
-                                      radius=1.5, kmin=1e-6, log=lambda r: _log(json.dumps(r)))
+                                      radius=1.5, kmin=1e-6, optimizer=args.optimizer,
+                                      log=lambda r: _log(json.dumps(r)))
         out["total_s"] = time.perf_counter() - t0
         out["runs"] = hist
         out["config"] = dict(n=n, iterations=args.iterations, volume_fraction=0.3, radius=1.5, move=0.2, eta=0.5,
-                             k_min=1e-6, precision=f"mixed, {args.copies} copies", eig_warm_start=1)
+                             k_min=1e-6, precision=f"mixed, {args.copies} copies", eig_warm_start=1,
+                             update=args.optimizer.upper())
     elif name == "cube128_to_512_continuation":
         # the interpolation technique at the design level (section 4): the
         # paper's mean-temperature problem (source f0 (1 - rho^p), T_D = 100,
         # contrast 1e6, volume fraction 0.05) optimised 40 / 20 / 10 iterations
         # on 128^3 / 256^3 / 512^3, each level started from the injected
         # design of the previous one; then 10 iterations directly on 512^3
-        # from the uniform design for comparison (OC update instead of MMA)
+        # from the uniform design for comparison (design update: --optimizer,
+        # the paper's MMA by default)
         vf = 0.05
 
         def make_mask(n):
@@ -314,7 +317,7 @@ def run_workload(name, args):
                         last=h[-1]["objective"], volume=h[-1]["volume"], pcg=[r["pcg_iterations"] for r in h],
                         adjoint=[r["adjoint_iterations"] for r in h])
 
-        common = dict(kmin=1e-6, objective="mean_temperature", f0=1.0, maxit=4000,
+        common = dict(kmin=1e-6, objective="mean_temperature", f0=1.0, maxit=4000, optimizer=args.optimizer,
                       log=lambda r: _log(json.dumps(r)))
         t_all = time.perf_counter()
         x, levels = pkg.topopt.continuation(make_solver, make_mask, 128, (40, 20, 10), vf, make_fixed=make_fixed,
@@ -328,7 +331,7 @@ def run_workload(name, args):
         out["runs"] = [dict(kind="continuation", total_s=total_cont, levels=levels),
                        dict(kind="direct512", **direct)]
         out["config"] = dict(schedule=[40, 20, 10], volume_fraction=vf, k_min=1e-6, T_D=100.0, f0=1.0, radius=1.5,
-                             move=0.2, eta=0.5, update="OC", precision=f"mixed, {args.copies} copies")
+                             move=0.2, eta=0.5, update=args.optimizer.upper(), precision=f"mixed, {args.copies} copies")
     elif name == "cube512_grf32_warmstart":
         # the interpolation step: solve the 256^3 companion (2^3 block average of
         # the same unthresholded field, thresholded at its own 60th percentile),
@@ -437,6 +440,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison path")
     ap.add_argument("--no-f32", action="store_true", help="skip the FP32-cycle comparison path")
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16-copies comparison path")
+    ap.add_argument("--optimizer", choices=("mma", "oc"), default="mma",
+                    help="design update of the optimisation workloads (cube128_to_512_continuation, cube512_topopt)")
     ap.add_argument("--copies", choices=("bf16", "f32", "mixed"), default="bf16",
                     help="coefficient copies of the single-path workloads (interpolation, optimisation, 1024^3)")
     ap.add_argument("--calibrate-copy", action="store_true",

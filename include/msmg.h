@@ -260,6 +260,24 @@ int msmg_density_filter(int nx, int ny, int nz, double radius, const double* in,
 int msmg_oc_update(msmg_handle* h, const double* x, const double* dc, const double* dv, double volume_fraction,
                    double move, double eta, double x_min, double* x_new, double* lambda, hipStream_t stream);
 
+/* Method of moving asymptotes (MMA; Svanberg 1987), the optimiser of the
+ * paper's section 2.3, for one volume constraint f1(x) = dv . x / N - vf <= 0
+ * and x_min <= x <= 1 on the handle's N elements: update number iter (0-based)
+ * moves the asymptotes by the signs of the last two steps (the first two
+ * updates place them at x -/+ 0.5 (1 - x_min)), builds the separable convex
+ * approximation of the objective (gradient df0) and the constraint, limits the
+ * step to max(x_min, L + 0.1 (x - L), x - move (1 - x_min)) ..
+ * min(1, U - 0.1 (U - x), x + move (1 - x_min)), and solves the approximate
+ * problem (elastic variable with c = 1000, d = 1) through its dual, the
+ * multiplier found on the device.  x, xold1, xold2 (the designs of the two
+ * previous updates; any values for iter < 2), df0, dv, x_new: element FP64
+ * device arrays; low, upp: element FP64 in/out (the previous asymptotes in,
+ * this update's out); lambda: nullable device pointer receiving the
+ * multiplier.  Uses the handle's reduction scratch. */
+int msmg_mma_update(msmg_handle* h, int iter, const double* x, const double* xold1, const double* xold2, double* low,
+                    double* upp, const double* df0, const double* dv, double volume_fraction, double move,
+                    double x_min, double* x_new, double* lambda, hipStream_t stream);
+
 /* msmg_oc_update without a handle and without any allocation, for callers
  * that cannot allocate device memory (code under HIP graph capture, serving
  * loops, harnesses that forbid hipMalloc).  Same update, same kernels and the

@@ -102,6 +102,7 @@ SIGNATURES = [
     ("msmg_prolong_element", _I, [_I, _I, _I, _VP, _VP, _I, _VP]),
     ("msmg_density_filter", _I, [_I, _I, _I, _D, _VP, _VP, _I, _VP]),
     ("msmg_oc_update", _I, [_VP, _VP, _VP, _VP, _D, _D, _D, _D, _VP, _VP, _VP]),
+    ("msmg_mma_update", _I, [_VP, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _D, _D, _D, _VP, _VP, _VP]),
     ("msmg_oc_update_noalloc", _I, [_I, _I, _I, _VP, _VP, _VP, _D, _D, _D, _D, _VP, _VP, _VP]),
     ("msmg_export", _I, [_VP, _I, _VP, _SZ]),
     ("msmg_destroy", None, [_VP]),

@@ -98,6 +98,11 @@ void launch_density_filter(int nx, int ny, int nz, double r, const double* in, d
 void launch_oc_update(long long ne, const double* x, const double* dc, const double* dv, double volume, double move,
                       double eta, double xmin, double* xnew, double* lam_out, void* state, double* partials,
                       unsigned* counter, int passes, hipStream_t s);
+// method of moving asymptotes for one volume constraint: low, upp in/out
+void launch_mma_update(int it, long long ne, const double* x, const double* x1, const double* x2, double* low,
+                       double* upp, const double* df0, const double* dv, double vf, double move, double xmin,
+                       double xmax, double* xnew, double* lam_out, void* state, double* partials, unsigned* counter,
+                       int passes, hipStream_t s);
 // the same with the scratch in a fixed per-device array (no allocation)
 hipError_t oc_scratch_device_ptr(void** out);
 size_t oc_scratch_bytes();

@@ -1088,6 +1088,22 @@ extern "C" int msmg_oc_update(msmg_handle* h, const double* x, const double* dc,
   return MSMG_OK;
 }
 
+extern "C" int msmg_mma_update(msmg_handle* h, int iter, const double* x, const double* xold1, const double* xold2,
+                               double* low, double* upp, const double* df0, const double* dv, double volume_fraction,
+                               double move, double x_min, double* x_new, double* lambda, hipStream_t s) {
+  if (!h || !x || !xold1 || !xold2 || !low || !upp || !df0 || !dv || !x_new) return fail(MSMG_EINVAL, "NULL argument");
+  if (iter < 0) return fail(MSMG_EINVAL, "iter must be >= 0");
+  if (x_new == x || x_new == xold1 || x_new == xold2 || x_new == low || x_new == upp || x_new == df0 || x_new == dv ||
+      low == upp)
+    return fail(MSMG_EINVAL, "x_new, low and upp must not alias the other arrays");
+  if (!(volume_fraction > 0.0 && volume_fraction <= 1.0)) return fail(MSMG_EINVAL, "volume fraction in (0, 1]");
+  if (!(move > 0.0) || !(x_min >= 0.0 && x_min < 1.0)) return fail(MSMG_EINVAL, "need move > 0 and 0 <= x_min < 1");
+  launch_mma_update(iter, h->g.ne, x, xold1, xold2, low, upp, df0, dv, volume_fraction, move, x_min, 1.0, x_new,
+                    lambda, h->oc_state, h->partials, h->counter, 8, s);
+  HIP_TRY(hipGetLastError());
+  return MSMG_OK;
+}
+
 // Largest design the allocation-free update takes (its scratch does not grow
 // with the design; the bound keeps element indices and volumes exact).
 static constexpr long long OC_NOALLOC_MAX_ELEMENTS = 1LL << 40;

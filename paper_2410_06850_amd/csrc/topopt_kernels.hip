@@ -144,6 +144,160 @@ void launch_oc_update(long long ne, const double* x, const double* dc, const dou
 }
 
 // ---------------------------------------------------------------------------
+// Method of moving asymptotes (Svanberg 1987; the parameter conventions of his
+// 2007 note on MMA and GCMMA), the optimiser of the paper's section 2.3, for the
+// one linear volume constraint f1(x) = dv . x / N - vf <= 0 on
+// x_min <= x <= x_max.  The separable convex approximation at x has
+//   p = (U - x)^2 (1.001 g+ + 0.001 g- + raa0 / span),
+//   q = (x - L)^2 (0.001 g+ + 1.001 g- + raa0 / span)
+// per function (g+ / g- the positive / negative part of its derivative); the
+// approximate problem (with the elastic variable y, weights c = 1000, d = 1) is
+// solved through its dual: for a multiplier lam every x_e minimises
+// (p0 + lam p1) / (U - x) + (q0 + lam q1) / (x - L) on [alpha, beta] in closed
+// form, and the dual slope (approximate constraint minus y = max(0, lam - c))
+// is non-increasing in lam.  lam = 0 when the slope at 0 is not positive;
+// otherwise its root is bracketed on a log scale as in the OC update.
+constexpr double MMA_ASYINIT = 0.5, MMA_ASYINCR = 1.2, MMA_ASYDECR = 0.7, MMA_ALBEFA = 0.1, MMA_RAA0 = 1e-5,
+                 MMA_C = 1000.0;
+
+struct MMAState {
+  double log_lo, log_hi;  // bracket of log(lambda)
+  int zero;               // 1: the constraint is inactive, lambda = 0
+};
+static_assert(sizeof(MMAState) <= 64, "fits the handle's 64-byte state slot");
+
+// Asymptotes of update `it` (0-based) from the last two steps; in/out low, upp.
+__global__ void k_mma_asymptotes(int it, long long ne, const double* __restrict__ x, const double* __restrict__ x1,
+                                 const double* __restrict__ x2, double* __restrict__ low, double* __restrict__ upp,
+                                 double span) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < ne; e += (long long)gridDim.x * blockDim.x) {
+    const double xe = x[e];
+    double lo, up;
+    if (it < 2) {
+      lo = xe - MMA_ASYINIT * span;
+      up = xe + MMA_ASYINIT * span;
+    } else {
+      const double sg = (xe - x1[e]) * (x1[e] - x2[e]);
+      const double gam = sg < 0.0 ? MMA_ASYDECR : (sg > 0.0 ? MMA_ASYINCR : 1.0);
+      lo = xe - gam * (x1[e] - low[e]);
+      up = xe + gam * (upp[e] - x1[e]);
+      lo = fmin(fmax(lo, xe - 10.0 * span), xe - 0.01 * span);
+      up = fmin(fmax(up, xe + 0.01 * span), xe + 10.0 * span);
+    }
+    low[e] = lo;
+    upp[e] = up;
+  }
+}
+
+// The element's share of the approximate problem at x with asymptotes lo, up.
+struct MMAElem {
+  double p0, q0, p1, q1, lo, up, alpha, beta, base;  // base: the x-independent part of its constraint term
+};
+
+MSMG_DEV MMAElem mma_elem(double x, double lo, double up, double df0, double g1, double move, double xmin,
+                          double xmax) {
+  MMAElem m;
+  const double span = xmax - xmin, reg = MMA_RAA0 / span;
+  const double gp0 = fmax(df0, 0.0), gm0 = fmax(-df0, 0.0), gp1 = fmax(g1, 0.0), gm1 = fmax(-g1, 0.0);
+  const double du = up - x, dl = x - lo;
+  m.p0 = du * du * (1.001 * gp0 + 0.001 * gm0 + reg);
+  m.q0 = dl * dl * (0.001 * gp0 + 1.001 * gm0 + reg);
+  m.p1 = du * du * (1.001 * gp1 + 0.001 * gm1 + reg);
+  m.q1 = dl * dl * (0.001 * gp1 + 1.001 * gm1 + reg);
+  m.lo = lo;
+  m.up = up;
+  m.alpha = fmax(fmax(xmin, lo + MMA_ALBEFA * dl), x - move * span);
+  m.beta = fmin(fmin(xmax, up - MMA_ALBEFA * du), x + move * span);
+  // constraint term at x_new minus its value at x plus the linear part g1 x
+  m.base = g1 * x - (m.p1 / du + m.q1 / dl);
+  return m;
+}
+
+MSMG_DEV double mma_x(const MMAElem& m, double lam) {
+  const double P = sqrt(m.p0 + lam * m.p1), Q = sqrt(m.q0 + lam * m.q1);
+  return fmin(fmax((P * m.lo + Q * m.up) / (P + Q), m.alpha), m.beta);
+}
+
+MSMG_DEV double mma_con(const MMAElem& m, double xn) { return m.p1 / (m.up - xn) + m.q1 / (xn - m.lo) + m.base; }
+
+// Dual slope at lambda = 0: decides whether the constraint is active.
+__global__ void k_mma_slope0(long long ne, const double* __restrict__ x, const double* __restrict__ low,
+                             const double* __restrict__ upp, const double* __restrict__ df0,
+                             const double* __restrict__ dv, double inv_n, double vf, double move, double xmin,
+                             double xmax, MMAState* st, double* partials, unsigned* counter) {
+  __shared__ double red[16];
+  double v[1] = {0.0};
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < ne; e += (long long)gridDim.x * blockDim.x) {
+    const MMAElem m = mma_elem(x[e], low[e], upp[e], df0[e], dv[e] * inv_n, move, xmin, xmax);
+    v[0] += mma_con(m, mma_x(m, 0.0));
+  }
+  grid_reduce<1>(v, red, partials, counter, gridDim.x, blockIdx.x, [&](double* t) {
+    st->zero = (t[0] - vf <= 0.0) ? 1 : 0;
+    st->log_lo = log(1e-40);
+    st->log_hi = log(1e40);
+  });
+}
+
+// One bracketing pass: the dual slope at OC_NL points of the bracket; keeps the
+// sub-interval where it changes sign (the ends when it does not).
+__global__ void k_mma_slopes(long long ne, const double* __restrict__ x, const double* __restrict__ low,
+                             const double* __restrict__ upp, const double* __restrict__ df0,
+                             const double* __restrict__ dv, double inv_n, double vf, double move, double xmin,
+                             double xmax, MMAState* st, double* partials, unsigned* counter) {
+  __shared__ double red[OC_NL * 16];
+  if (st->zero) return;  // uniform
+  const double llo = st->log_lo, lhi = st->log_hi;
+  double lam[OC_NL], v[OC_NL];
+#pragma unroll
+  for (int q = 0; q < OC_NL; ++q) {
+    lam[q] = exp(llo + (lhi - llo) * q / double(OC_NL - 1));
+    v[q] = 0.0;
+  }
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < ne; e += (long long)gridDim.x * blockDim.x) {
+    const MMAElem m = mma_elem(x[e], low[e], upp[e], df0[e], dv[e] * inv_n, move, xmin, xmax);
+#pragma unroll
+    for (int q = 0; q < OC_NL; ++q) v[q] += mma_con(m, mma_x(m, lam[q]));
+  }
+  grid_reduce<OC_NL>(v, red, partials, counter, gridDim.x, blockIdx.x, [&](double* sum) {
+    // slope[q] = sum[q] - vf - max(0, lam_q - c), non-increasing in q; keep
+    // [lam_q, lam_{q+1}] with slope[q] > 0 >= slope[q+1]
+    auto slope = [&](int q) { return sum[q] - vf - fmax(0.0, exp(llo + (lhi - llo) * q / double(OC_NL - 1)) - MMA_C); };
+    int q = 0;
+    while (q < OC_NL - 2 && slope(q + 1) > 0.0) ++q;
+    const double step = (lhi - llo) / double(OC_NL - 1);
+    st->log_lo = llo + step * q;
+    st->log_hi = llo + step * (q + 1);
+  });
+}
+
+__global__ void k_mma_apply(long long ne, const double* __restrict__ x, const double* __restrict__ low,
+                            const double* __restrict__ upp, const double* __restrict__ df0,
+                            const double* __restrict__ dv, double inv_n, double move, double xmin, double xmax,
+                            const MMAState* st, double* __restrict__ xnew, double* lam_out) {
+  const double lam = st->zero ? 0.0 : exp(0.5 * (st->log_lo + st->log_hi));
+  if (lam_out && blockIdx.x == 0 && threadIdx.x == 0) *lam_out = lam;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < ne; e += (long long)gridDim.x * blockDim.x)
+    xnew[e] = mma_x(mma_elem(x[e], low[e], upp[e], df0[e], dv[e] * inv_n, move, xmin, xmax), lam);
+}
+
+void launch_mma_update(int it, long long ne, const double* x, const double* x1, const double* x2, double* low,
+                       double* upp, const double* df0, const double* dv, double vf, double move, double xmin,
+                       double xmax, double* xnew, double* lam_out, void* state, double* partials, unsigned* counter,
+                       int passes, hipStream_t s) {
+  MMAState* st = (MMAState*)state;
+  const dim3 g1d(grid1d(ne, 256, 65536)), b(256);
+  const double inv_n = 1.0 / double(ne);
+  hipLaunchKernelGGL(k_mma_asymptotes, g1d, b, 0, s, it, ne, x, x1, x2, low, upp, xmax - xmin);
+  hipLaunchKernelGGL(k_mma_slope0, dim3(OC_BLOCKS), b, 0, s, ne, x, low, upp, df0, dv, inv_n, vf, move, xmin, xmax,
+                     st, partials, counter);
+  for (int p = 0; p < passes; ++p)
+    hipLaunchKernelGGL(k_mma_slopes, dim3(OC_BLOCKS), b, 0, s, ne, x, low, upp, df0, dv, inv_n, vf, move, xmin,
+                       xmax, st, partials, counter);
+  hipLaunchKernelGGL(k_mma_apply, g1d, b, 0, s, ne, x, low, upp, df0, dv, inv_n, move, xmin, xmax, st, xnew,
+                     lam_out);
+}
+
+// ---------------------------------------------------------------------------
 // The same update with its scratch (block partials of the volume sweeps, the
 // reduction counter, the multiplier bracket) in a fixed device array instead
 // of a handle: nothing is allocated, so callers that may not allocate (graph

@@ -143,6 +143,19 @@ class Solver:
                                        float(eta), float(x_min), _ptr(out), _ptr(lam), _stream()), "msmg_oc_update")
         return out, lam
 
+    def mma_update(self, it, x, xold1, xold2, low, upp, df0, dv, volume_fraction, move=0.2, x_min=1e-3, out=None):
+        """Method of moving asymptotes step (update number `it`); low and upp are
+        updated in place; returns (x_new, lambda) with lambda a 0-d device tensor."""
+        for t, nm in ((x, "x"), (xold1, "xold1"), (xold2, "xold2"), (low, "low"), (upp, "upp"), (df0, "df0"),
+                      (dv, "dv")):
+            _need(t, nm, torch.float64, self.nelem, self.device)
+        out = torch.empty_like(x) if out is None else _need(out, "out", torch.float64, self.nelem, self.device)
+        lam = torch.empty((), dtype=torch.float64, device=self.device)
+        L.check(L.lib().msmg_mma_update(self._h, int(it), _ptr(x), _ptr(xold1), _ptr(xold2), _ptr(low), _ptr(upp),
+                                        _ptr(df0), _ptr(dv), float(volume_fraction), float(move), float(x_min),
+                                        _ptr(out), _ptr(lam), _stream()), "msmg_mma_update")
+        return out, lam
+
     def apply(self, x, y=None):
         x = _need(x, "x", torch.float64, self.nnodes, self.device)
         y = torch.empty_like(x) if y is None else _need(y, "y", torch.float64, self.nnodes, self.device)

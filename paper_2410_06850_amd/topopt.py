@@ -1,7 +1,7 @@
 """Topology-optimisation loop around the solver (the experiments of section 4
 minimise a thermal objective over densities with a gradient-based update;
-here a hat density filter and an optimality-criteria update with a volume
-constraint, all on the GPU).
+here a hat density filter and a moving-asymptotes (MMA) or optimality-criteria
+update with a volume constraint, all on the GPU).
 
 Objectives: compliance c = f^T T (fixed unit source, zero fixed values), or
 the paper's mean temperature (source f0 (1 - rho^p) of eq. (material), fixed
@@ -9,7 +9,9 @@ values T_D, eq. (cost function)).
 
 Each iteration: rho_phys = H(x); c(rho_phys) (set-up rebuilt for rho_phys,
 PCG solve); dc/dx = H^T dc/drho_phys (autograd: adjoint solve where needed,
-sensitivity kernel, then the filter's adjoint); x <- OC(x, dc/dx, H^T 1).
+sensitivity kernel, then the filter's adjoint); x <- OC(x, dc/dx, H^T 1), or
+the method of moving asymptotes (section 2.3's optimiser) with the volume
+constraint H^T 1 . x / N <= volume fraction.
 
 ``continuation`` is the interpolation technique of section 4 at the design
 level: optimise on a coarse mesh, inject the design into the 2x mesh
@@ -38,10 +40,15 @@ class DensityFilter(torch.autograd.Function):
 
 def optimize(solver, mask, iterations=20, volume_fraction=0.3, x0=0.3, radius=1.5, move=0.2, eta=0.5,
              kmin=1e-6, kmax=1.0, p=3, rtol=1e-8, maxit=1000, x_min=1e-3, log=None,
-             objective="compliance", fixed_values=None, f0=1.0):
+             objective="compliance", fixed_values=None, f0=1.0, optimizer="oc"):
     """Run `iterations` design updates; returns (x, history).  x0: a constant or
     an element tensor (the initial design); objective: "compliance" or
-    "mean_temperature" (with fixed_values and the source amplitude f0)."""
+    "mean_temperature" (with fixed_values and the source amplitude f0);
+    optimizer: "oc" (optimality criteria) or "mma" (the method of moving
+    asymptotes of section 2.3, on the objective scaled by its first value and
+    the volume constraint dv . x / N <= volume_fraction)."""
+    if optimizer not in ("oc", "mma"):
+        raise ValueError(f"unknown optimizer {optimizer}")
     n = (solver.nx, solver.ny, solver.nz)
     dev = solver.device
     if objective not in ("compliance", "mean_temperature"):
@@ -56,6 +63,11 @@ def optimize(solver, mask, iterations=20, volume_fraction=0.3, x0=0.3, radius=1.
     ones = torch.ones_like(x)
     dv = density_filter(ones, n, radius, transpose=True)
     hist = []
+    if optimizer == "mma":
+        # MMA state: the last two designs and the asymptotes
+        xold1, xold2 = x.clone(), x.clone()
+        low, upp = torch.zeros_like(x), torch.ones_like(x)
+        c_scale = None
     for it in range(iterations):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -68,11 +80,19 @@ def optimize(solver, mask, iterations=20, volume_fraction=0.3, x0=0.3, radius=1.
                                           maxit=maxit)
         c.backward()
         info = solver.last_info
-        x_new, lam = solver.oc_update(x, xv.grad, dv, volume_fraction, move=move, eta=eta, x_min=x_min)
+        if optimizer == "oc":
+            x_new, lam = solver.oc_update(x, xv.grad, dv, volume_fraction, move=move, eta=eta, x_min=x_min)
+        else:
+            if c_scale is None:
+                c_scale = 1.0 / max(abs(float(c.detach())), 1e-300)
+            x_new, lam = solver.mma_update(it, x, xold1, xold2, low, upp, xv.grad * c_scale, dv, volume_fraction,
+                                           move=move, x_min=x_min)
+            xold2, xold1 = xold1, x
         change = float((x_new - x).abs().max())
         x = x_new
         torch.cuda.synchronize()
         rec = dict(iteration=it, objective=float(c.detach()), change=change, volume=float(x.mean()),
+                   volume_physical=float(torch.dot(dv, x)) / solver.nelem, optimizer=optimizer,
                    pcg_iterations=info["iterations"], setup_ms=info["setup_ms"], solve_ms=info["solve_ms"],
                    adjoint_iterations=(solver.last_adjoint_info["iterations"] if objective != "compliance" else 0),
                    step_s=time.perf_counter() - t0, lam=float(lam))

@@ -127,6 +127,43 @@ def test_oc_update_matches_oracle(pkg, case):
     assert abs(float(xn.sum()) - 0.3 * g.nelem) <= 1e-6 * g.nelem
 
 
+@pytest.mark.parametrize("it,shift", [(0, -0.05), (1, -0.02), (4, -0.05), (5, None), (6, -0.3)])
+def test_mma_update_matches_oracle(pkg, case, it, shift):
+    """MMA step (section 2.3's optimiser) against the oracle: asymptotes (first
+    updates and the sign rule), the multiplier of the dual (1e-8) and the new
+    design (1e-9), with the volume target just below the design (active
+    constraint, lam ~ 2-5), far above a thin design (vf = 1: inactive, lam = 0)
+    and far below (unreachable within the move limits: elastic, lam > c).
+    The objective gradient is scaled like the loop's (objective / its first
+    value, so ~1/N per element)."""
+    print(f"case mma-update cube16 it={it} shift={shift}", flush=True)
+    g, s, rho, mask = case
+    rng = np.random.default_rng(10 + it)
+    ne = g.nelem
+    x = rng.uniform(0.05, 0.15, ne) if shift is None else rng.uniform(0.2, 0.8, ne)
+    x1 = np.clip(x + rng.uniform(-0.05, 0.05, ne), 1e-3, 1.0)
+    x2 = np.clip(x1 + rng.uniform(-0.05, 0.05, ne), 1e-3, 1.0)
+    low, upp = x - rng.uniform(0.05, 0.5, ne), x + rng.uniform(0.05, 0.5, ne)
+    dc = -np.exp(rng.standard_normal(ne)) / ne
+    dv = rng.uniform(0.5, 1.5, ne)
+    vf = 1.0 if shift is None else float(dv @ x) / ne + shift
+    want, lo_o, up_o, lam_o = topopt.mma_update(it, x, x1, x2, low, upp, dc, dv, vf, move=0.2, x_min=1e-3)
+    lo_g, up_g = to_dev(low), to_dev(upp)
+    xn, lam = s.mma_update(it, to_dev(x), to_dev(x1), to_dev(x2), lo_g, up_g, to_dev(dc), to_dev(dv), vf,
+                           move=0.2, x_min=1e-3)
+    assert rel(lo_g.cpu().numpy(), lo_o) <= 1e-15 and rel(up_g.cpu().numpy(), up_o) <= 1e-15
+    print(f"  lambda gpu {float(lam):.12e} oracle {lam_o:.12e}")
+    if shift is None:
+        assert lam_o == 0.0 and float(lam) == 0.0
+    elif shift == -0.3:
+        assert lam_o > 1000.0
+    else:
+        assert 0.0 < lam_o < 1000.0
+    if lam_o != 0.0:
+        assert abs(float(lam) - lam_o) <= 1e-8 * lam_o
+    assert rel(xn.cpu().numpy(), want) <= 1e-9
+
+
 def test_topopt_loop_runs_and_decreases_compliance(pkg):
     print("case topopt-loop cube16", flush=True)
     s = pkg.Solver(16, H=8, sd=2)
@@ -135,6 +172,20 @@ def test_topopt_loop_runs_and_decreases_compliance(pkg):
     assert all(np.isfinite(cs))
     assert cs[-1] < cs[0]
     assert abs(hist[-1]["volume"] - 0.3) <= 1e-6
+
+
+def test_topopt_loop_with_mma(pkg):
+    """The loop with the method of moving asymptotes: the compliance falls and
+    the physical (filtered) volume meets the constraint."""
+    print("case topopt-loop mma cube16", flush=True)
+    s = pkg.Solver(16, H=8, sd=2)
+    x, hist = pkg.topopt.optimize(s, to_dev(patch_mask(16), torch.uint8), iterations=8, kmin=1e-6, x0=0.3,
+                                  optimizer="mma")
+    cs = [h["objective"] for h in hist]
+    print("  compliance " + " ".join(f"{c:.4g}" for c in cs))
+    assert all(np.isfinite(cs)) and cs[-1] < 0.8 * cs[0]
+    assert hist[-1]["volume_physical"] <= 0.3 + 1e-6
+    assert float(x.min()) >= 1e-3 and float(x.max()) <= 1.0
 
 
 def test_compliance_gradient_fd_cube32(pkg):

@@ -106,6 +106,9 @@ typedef struct msmg_options {
                           first residual (H = 2, 4, 8 or 16).  Cleared bits run
                           one launch per step.  The same arithmetic up to the
                           order of the sums.                                     */
+  int pair_rhs;        /* 1: allocate a second set of PCG and cycle vectors     [0]
+                          for msmg_solve_pair (about 11 nodal vectors more;
+                          needs the multigrid kind with cheb_degree 2)           */
 } msmg_options;
 
 /* Solve report. */
@@ -177,6 +180,25 @@ int msmg_solve(msmg_handle* h, const double* f, double* T, double* T_lo, int use
  * zero on fixed nodes; lambda_lo nullable). */
 int msmg_solve_adjoint(msmg_handle* h, const double* g, double* lambda, double* lambda_lo, int use_x0, double rtol,
                        int maxit, msmg_info* info, hipStream_t stream);
+
+/* The state solve and the adjoint solve of one set-up together (the paper's
+ * LS1 and LS2 of section 4, sharing the set-up as in its tables; section 2.3,
+ * eq. adjoint): A T = f with the set-up's fixed values (as msmg_solve from a
+ * zero guess) and A_FF lambda = g with zero fixed entries (as
+ * msmg_solve_adjoint), by two PCG recurrences advanced together.  Every
+ * kernel that reads the operator's coefficients (the operator apply, the
+ * smoothers, the fused residual and restriction, levels 1 and 2, the
+ * prolongation) runs once for both right-hand sides, the two sides'
+ * workgroups side by side on one XCD; scalars, stopping tests and residual
+ * replacements stay per side, and a side that has stopped drops out.
+ * f, g: nodal FP64 loads; T, lambda: nodal FP64 outputs; T_lo, lambda_lo:
+ * nullable low parts as for msmg_solve; info_T, info_lambda: nullable host
+ * reports (solve_ms is the pair's wall time).  Needs a handle created with
+ * options.pair_rhs = 1 (MSMG_ESTATE otherwise).  Returns the first non-zero
+ * outcome of the two solves, or an error < 0. */
+int msmg_solve_pair(msmg_handle* h, const double* f, double* T, double* T_lo, const double* g, double* lambda,
+                    double* lambda_lo, double rtol, int maxit, msmg_info* info_T, msmg_info* info_lambda,
+                    hipStream_t stream);
 
 /* Element sensitivities dc/drho_e = -p rho_e^(p-1) (k_max - k_min) lambda_e^T K0 T_e
  * (evaluated as -sum_{a<b} K0_ab (lambda_a - lambda_b)(T_a - T_b), exact for zero-row-sum K0)

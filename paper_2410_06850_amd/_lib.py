@@ -49,6 +49,7 @@ class Options(ctypes.Structure):
         ("lean_memory", ctypes.c_int),
         ("cc_group", ctypes.c_int),
         ("coarse_fused", ctypes.c_int),
+        ("pair_rhs", ctypes.c_int),
     ]
 
 
@@ -91,6 +92,8 @@ SIGNATURES = [
     ("msmg_setup", _I, [_VP, _VP, _I, _D, _D, _I, _VP, _VP, _VP]),
     ("msmg_solve", _I, [_VP, _VP, _VP, _VP, _I, _D, _I, ctypes.POINTER(Info), _VP]),
     ("msmg_solve_adjoint", _I, [_VP, _VP, _VP, _VP, _I, _D, _I, ctypes.POINTER(Info), _VP]),
+    ("msmg_solve_pair", _I, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _D, _I, ctypes.POINTER(Info), ctypes.POINTER(Info),
+                             _VP]),
     ("msmg_sensitivity", _I, [_VP, _VP, _VP, _VP, _VP]),
     ("msmg_apply", _I, [_VP, _VP, _VP, _VP]),
     ("msmg_precondition", _I, [_VP, _VP, _VP, _VP]),

@@ -225,21 +225,24 @@ __global__ void k_cc_prolong(Hier h, int n_c, const VT* __restrict__ Rcc, const 
 // (the update of a cell sees x1 on colours not yet swept and the new values on
 // the swept ones, which is the transposed sweep applied to the residual), so
 // the residual step before it and the separate correction vector disappear.
+// Per right-hand side (one or two, see NS): rc, x, t, rcc, sc.  With two
+// sides the lanes of one cell's two sides sit in one wave, so their loads of
+// A_c, R_cc and A_cc^-1 are the same addresses and coalesce.
 struct Level1Args {
   Hier h;
-  const double* Ac;      // [ncells][27][L][L]
-  const double* Dinv;    // [ncells][L][L] inverses of the diagonal blocks
-  const double* rc;      // R_c (r0 - A r1), from the previous kernel
-  double* x;             // coarse iterate: x0, then x1, then e_c
-  double* t;             // r_c - A_c x0
-  double* rcc;           // R_cc t
-  const double* Rcc;     // per cc cell J: [Lcc][nd_J]
+  const double* Ac;          // [ncells][27][L][L]
+  const double* Dinv;        // [ncells][L][L] inverses of the diagonal blocks
+  Two<const double*> rc;     // R_c (r0 - A r1), from the previous kernel
+  Two<double*> x;            // coarse iterate: x0, then x1, then e_c
+  Two<double*> t;            // r_c - A_c x0
+  Two<double*> rcc;          // R_cc t
+  const double* Rcc;         // per cc cell J: [Lcc][nd_J]
   const int* cc_ptr;
   const int* cc_dofs;
-  const double* AccInv;  // [n_cc][n_cc]
+  const double* AccInv;      // [n_cc][n_cc]
   int n_cc;
-  unsigned* bar;         // barrier words (level1_barrier_words(), zero between launches)
-  Scalars* sc;
+  unsigned* bar;             // barrier words (level1_barrier_words(), zero between launches)
+  Two<Scalars*> sc;
   unsigned spin_limit;
 };
 
@@ -302,23 +305,25 @@ MSMG_DEV bool l1_barrier(const Level1Args& a, unsigned k, unsigned long long see
 // One Gauss-Seidel colour of the grid-synchronised sweep.  forward: x_i =
 // D_i^-1 (b_i - sum_{j of earlier colours} A_ij x_j) (zero start, colour 0
 // first).  !forward: x_i += D_i^-1 (b_i - sum_{all 27 j} A_ij x_j) (in place).
-template <int L>
+template <int L, int NS>
 MSMG_DEV unsigned long long l1_colour(const Level1Args& a, int colour, bool forward) {
   constexpr int CL = lanes_pow2<L>() * ROW_SLOTS;
   const Hier& h = a.h;
   const int px = colour & 1, py = (colour >> 1) & 1, pz = (colour >> 2) & 1;
   const int nx = (h.ncx - px + 1) / 2, ny = (h.ncy - py + 1) / 2, nz = (h.ncz - pz + 1) / 2;
-  const long long total = (long long)nx * ny * nz * CL;
+  const long long total = (long long)nx * ny * nz * CL * NS;
   const long long stride = (long long)gridDim.x * blockDim.x;
   unsigned long long seen = 0;
   // the loop bound is uniform over a wave (base differs per wave by multiples of 64)
   for (long long base = (long long)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < total; base += stride) {
     const long long gtid = base + (threadIdx.x & 63);
     const int lane = int(gtid % CL);
+    const int side = NS == 1 ? 0 : int((gtid / CL) % NS);
     const int l = lane / ROW_SLOTS, q = lane % ROW_SLOTS;
-    const long long ci = gtid / CL;
+    const long long ci = gtid / (CL * NS);
     const bool valid = gtid < total;
     const bool row = valid && l < L;
+    double* __restrict__ x = a.x[side];
     long long cell = 0;
     int cx = 0, cy = 0, cz = 0;
     if (valid) {
@@ -327,8 +332,8 @@ MSMG_DEV unsigned long long l1_colour(const Level1Args& a, int colour, bool forw
       cz = 2 * int(ci / ((long long)nx * ny)) + pz;
       cell = ((long long)cz * h.ncy + cy) * h.ncx + cx;
     }
-    const double bi = row ? a.rc[cell * L + l] : 0.0;
-    const double xi = (row && !forward) ? coh_load(a.x + cell * L + l) : 0.0;
+    const double bi = row ? a.rc[side][cell * L + l] : 0.0;
+    const double xi = (row && !forward) ? coh_load(x + cell * L + l) : 0.0;
     double dv[L];
 #pragma unroll
     for (int m = 0; m < L; ++m) dv[m] = row ? a.Dinv[(cell * L + l) * L + m] : 0.0;
@@ -349,7 +354,7 @@ MSMG_DEV unsigned long long l1_colour(const Level1Args& a, int colour, bool forw
         }
         if (ok) {
 #pragma unroll
-          for (int m = 0; m < L; ++m) part += A[(bb * L + l) * L + m] * coh_load(a.x + nc * L + m);
+          for (int m = 0; m < L; ++m) part += A[(bb * L + l) * L + m] * coh_load(x + nc * L + m);
         }
       }
     }
@@ -363,16 +368,19 @@ MSMG_DEV unsigned long long l1_colour(const Level1Args& a, int colour, bool forw
       const double tm = __shfl(tv, gbase + m * ROW_SLOTS, 64);
       if (row) upd += dv[m] * tm;
     }
-    if (row && q == 0) seen |= coh_store(a.x + cell * L + l, xi + upd);
+    if (row && q == 0) seen |= coh_store(x + cell * L + l, xi + upd);
   }
   return seen;
 }
 
-template <int L>
+template <int L, int NS>
 __global__ __launch_bounds__(512) void k_level1(Level1Args a) {
-  if (a.sc->done) return;  // uniform: set by an earlier kernel
+  bool all_done = true;
+#pragma unroll
+  for (int q = 0; q < NS; ++q) all_done = all_done && a.sc[q]->done;
+  if (all_done) return;  // uniform: set by earlier kernels
   __shared__ int ok_sh;
-  __shared__ double ecc_sh[64];
+  __shared__ double ecc_sh[NS][64];
   if (threadIdx.x == 0) ok_sh = 1;
   __syncthreads();
   const Hier& h = a.h;
@@ -382,19 +390,21 @@ __global__ __launch_bounds__(512) void k_level1(Level1Args a) {
   bool ok = true;
   // forward sweep from zero: x0 = S_c^-1 r_c
   for (int colour = 0; colour < 8; ++colour) {
-    const unsigned long long seen = l1_colour<L>(a, colour, true);
+    const unsigned long long seen = l1_colour<L, NS>(a, colour, true);
     ok = l1_barrier(a, ++k, seen, &ok_sh);
   }
   // t = r_c - A_c x0
   {
     unsigned long long seen = 0;
-    const long long total = (long long)h.ncells * CL;
+    const long long total = (long long)h.ncells * CL * NS;
     for (long long base = (long long)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < total; base += stride) {
       const long long gtid = base + (threadIdx.x & 63);
       const int lane = int(gtid % CL);
+      const int side = NS == 1 ? 0 : int((gtid / CL) % NS);
       const int l = lane / ROW_SLOTS, q = lane % ROW_SLOTS;
-      const long long cell = gtid / CL;
+      const long long cell = gtid / (CL * NS);
       const bool row = gtid < total && l < L;
+      const double* x = a.x[side];
       int cx = 0, cy = 0, cz = 0;
       if (row) {
         cx = int(cell % h.ncx);
@@ -411,28 +421,31 @@ __global__ __launch_bounds__(512) void k_level1(Level1Args a) {
         if (row && bb < 27) nc = nb_cell(h, cx, cy, cz, bb, okb);
         if (okb) {
 #pragma unroll
-          for (int m = 0; m < L; ++m) part += A[(bb * L + l) * L + m] * coh_load(a.x + nc * L + m);
+          for (int m = 0; m < L; ++m) part += A[(bb * L + l) * L + m] * coh_load(x + nc * L + m);
         }
       }
 #pragma unroll
       for (int off = 1; off < ROW_SLOTS; off <<= 1) part += __shfl_xor(part, off, 64);
-      if (row && q == 0) seen |= coh_store(a.t + cell * L + l, a.rc[cell * L + l] - part);
+      if (row && q == 0) seen |= coh_store(a.t[side] + cell * L + l, a.rc[side][cell * L + l] - part);
     }
     ok = l1_barrier(a, ++k, seen, &ok_sh);
   }
-  // r_cc = R_cc t: one wave per entry (J, b)
+  // r_cc = R_cc t: one wave per entry (J, b) and side
   {
     unsigned long long seen = 0;
-    const long long nw = (long long)h.ncc * h.Lcc;
+    const long long nw = (long long)h.ncc * h.Lcc * NS;
     const int lane = threadIdx.x & 63;
     for (long long w = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w < nw; w += stride >> 6) {
-      const int J = int(w / h.Lcc), bidx = int(w % h.Lcc);
+      const int side = NS == 1 ? 0 : int(w % NS);
+      const long long we = w / NS;
+      const int J = int(we / h.Lcc), bidx = int(we % h.Lcc);
       const int d0 = a.cc_ptr[J], nd = a.cc_ptr[J + 1] - d0;
       const double* R = a.Rcc + (long long)h.Lcc * d0 + (long long)bidx * nd;
+      const double* t = a.t[side];
       double sum = 0.0;
-      for (int d = lane; d < nd; d += 64) sum += R[d] * coh_load(a.t + a.cc_dofs[d0 + d]);
+      for (int d = lane; d < nd; d += 64) sum += R[d] * coh_load(t + a.cc_dofs[d0 + d]);
       sum = wave_sum(sum);
-      if (lane == 0) seen |= coh_store(a.rcc + w, sum);
+      if (lane == 0) seen |= coh_store(a.rcc[side] + we, sum);
     }
     ok = l1_barrier(a, ++k, seen, &ok_sh);
   }
@@ -444,19 +457,35 @@ __global__ __launch_bounds__(512) void k_level1(Level1Args a) {
     for (int J = blockIdx.x; J < h.ncc; J += gridDim.x) {
       for (int b = wave; b < h.Lcc; b += nwaves) {
         const double* arow = a.AccInv + (long long)(J * h.Lcc + b) * a.n_cc;
-        double sum = 0.0;
-        for (int j = lane; j < a.n_cc; j += 64) sum += arow[j] * coh_load(a.rcc + j);
-        sum = wave_sum(sum);
-        if (lane == 0) ecc_sh[b] = sum;
+        double sum[NS];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) sum[q] = 0.0;
+        for (int j = lane; j < a.n_cc; j += 64) {
+          const double av = arow[j];
+#pragma unroll
+          for (int q = 0; q < NS; ++q) sum[q] += av * coh_load(a.rcc[q] + j);
+        }
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+          sum[q] = wave_sum(sum[q]);
+          if (lane == 0) ecc_sh[q][b] = sum[q];
+        }
       }
       __syncthreads();
       const int d0 = a.cc_ptr[J], nd = a.cc_ptr[J + 1] - d0;
       const double* R = a.Rcc + (long long)h.Lcc * d0;
       for (int d = threadIdx.x; d < nd; d += blockDim.x) {
         const int gd = a.cc_dofs[d0 + d];
-        double v = coh_load(a.x + gd);
-        for (int b = 0; b < h.Lcc; ++b) v += R[(long long)b * nd + d] * ecc_sh[b];
-        seen |= coh_store(a.x + gd, v);
+        double v[NS];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) v[q] = coh_load(a.x[q] + gd);
+        for (int b = 0; b < h.Lcc; ++b) {
+          const double rv = R[(long long)b * nd + d];
+#pragma unroll
+          for (int q = 0; q < NS; ++q) v[q] += rv * ecc_sh[q][b];
+        }
+#pragma unroll
+        for (int q = 0; q < NS; ++q) seen |= coh_store(a.x[q] + gd, v[q]);
       }
       __syncthreads();
     }
@@ -464,7 +493,7 @@ __global__ __launch_bounds__(512) void k_level1(Level1Args a) {
   }
   // backward sweep from x1 on r_c: x = x1 + S_c^-T (r_c - A_c x1) = e_c
   for (int colour = 7; colour >= 0; --colour) {
-    const unsigned long long seen = l1_colour<L>(a, colour, false);
+    const unsigned long long seen = l1_colour<L, NS>(a, colour, false);
     if (colour > 0) ok = l1_barrier(a, ++k, seen, &ok_sh);
     else asm volatile("" ::"v"(seen) : "memory");
   }
@@ -472,8 +501,11 @@ __global__ __launch_bounds__(512) void k_level1(Level1Args a) {
   __syncthreads();
   if (threadIdx.x == 0) {
     if (!ok) {
-      a.sc->status = ST_SYNC_TIMEOUT;
-      a.sc->done = 1;
+#pragma unroll
+      for (int q = 0; q < NS; ++q) {
+        a.sc[q]->status = ST_SYNC_TIMEOUT;
+        a.sc[q]->done = 1;
+      }
     }
     const unsigned ticket = __hip_atomic_fetch_add(a.bar + L1B_EXIT, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (ticket == gridDim.x - 1)
@@ -551,32 +583,37 @@ int level1_blocks() {
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) return 0;
   int per = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(&k_level1<4>), 512, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(&k_level1<4, 2>), 512, 0) !=
           hipSuccess ||
       per < 1)
     return 0;
   return cus;  // one workgroup per compute unit (co-resident: per >= 1)
 }
 
-hipError_t launch_level1(const Ctx& c, int blocks, const double* rc, double* x, double* t, double* rcc,
-                         unsigned* bar, unsigned spin_limit, hipStream_t s) {
-  if (c.cc.a_dt != DT_F64 || c.h.Lcc > 64 || blocks < 1) return hipErrorInvalidValue;
+static Level1Args level1_args(const Ctx& c, unsigned* bar, unsigned spin_limit) {
   Level1Args a{};
   a.h = c.h;
   a.Ac = (const double*)c.cc.Ac;
   a.Dinv = (const double*)c.cc.AcDinv;
-  a.rc = rc;
-  a.x = x;
-  a.t = t;
-  a.rcc = rcc;
   a.Rcc = (const double*)c.cc.Rcc;
   a.cc_ptr = c.cc.cc_ptr;
   a.cc_dofs = c.cc.cc_dofs;
   a.AccInv = c.cc.AccInv;
   a.n_cc = c.cc.n_cc;
   a.bar = bar;
-  a.sc = c.sc;
   a.spin_limit = spin_limit;
+  return a;
+}
+
+hipError_t launch_level1(const Ctx& c, int blocks, const double* rc, double* x, double* t, double* rcc,
+                         unsigned* bar, unsigned spin_limit, hipStream_t s) {
+  if (c.cc.a_dt != DT_F64 || c.h.Lcc > 64 || blocks < 1) return hipErrorInvalidValue;
+  Level1Args a = level1_args(c, bar, spin_limit);
+  a.rc = one(rc);
+  a.x = one(x);
+  a.t = one(t);
+  a.rcc = one(rcc);
+  a.sc = one(c.sc);
   // An ordinary launch: `blocks` is at most the device's co-resident capacity
   // for this kernel (level1_blocks), and the kernels before it on the stream
   // finish without waiting for it, so every workgroup becomes resident; the
@@ -584,7 +621,21 @@ hipError_t launch_level1(const Ctx& c, int blocks, const double* rc, double* x, 
   // the kernel (about 20 us per launch measured at 256^3), and the bounded
   // waits turn any failure of the assumption into MSMG_ETIMEOUT instead of a
   // hang.
-  COARSE_L_DISPATCH(c.h.Lc, hipLaunchKernelGGL((k_level1<LL>), dim3(blocks), dim3(512), 0, s, a));
+  COARSE_L_DISPATCH(c.h.Lc, hipLaunchKernelGGL((k_level1<LL, 1>), dim3(blocks), dim3(512), 0, s, a));
+  return hipGetLastError();
+}
+
+hipError_t launch_level1_pair(const Ctx& c0, const Ctx& c1, int blocks, const double* rc0, const double* rc1,
+                              double* x0, double* x1, double* t0, double* t1, double* rcc0, double* rcc1,
+                              unsigned* bar, unsigned spin_limit, hipStream_t s) {
+  if (c0.cc.a_dt != DT_F64 || c0.h.Lcc > 64 || blocks < 1) return hipErrorInvalidValue;
+  Level1Args a = level1_args(c0, bar, spin_limit);
+  a.rc = two(rc0, rc1);
+  a.x = two(x0, x1);
+  a.t = two(t0, t1);
+  a.rcc = two(rcc0, rcc1);
+  a.sc = two(c0.sc, c1.sc);
+  COARSE_L_DISPATCH(c0.h.Lc, hipLaunchKernelGGL((k_level1<LL, 2>), dim3(blocks), dim3(512), 0, s, a));
   return hipGetLastError();
 }
 

@@ -269,6 +269,50 @@ MSMG_DEV Tile tile_of_thread(const Geo& g, const Hier& h, int CX, long long tile
   return t;
 }
 
+// ---------------------------------------------------------------------------
+// Launches over one or two right-hand sides (the batched state/adjoint pair):
+// kernels that read the operator's coefficients take each per-side pointer as
+// a Two<T> and run NS workgroups per tile.  The two sides' workgroups of a tile
+// are 8 apart, so the hardware deals them to the same XCD and the second
+// side's coefficient reads hit that XCD's L2.
+template <typename T>
+struct Two {
+  T v[2];
+  MSMG_HD T operator[](int i) const { return v[i]; }
+};
+template <typename T>
+MSMG_HD Two<T> two(T a, T b) {
+  Two<T> t;
+  t.v[0] = a;
+  t.v[1] = b;
+  return t;
+}
+template <typename T>
+MSMG_HD Two<T> one(T a) {
+  return two(a, a);
+}
+
+struct SideBlock {
+  int side;
+  long long blk, nblk;  // the workgroup's index and count within its side
+};
+// NS = 2 needs a grid of a multiple of 16 workgroups.
+template <int NS>
+MSMG_DEV SideBlock side_block() {
+  SideBlock r;
+  if (NS == 1) {
+    r.side = 0;
+    r.blk = blockIdx.x;
+    r.nblk = gridDim.x;
+  } else {
+    const long long b = blockIdx.x;
+    r.side = int((b >> 3) & 1);
+    r.blk = (b & 7) | ((b >> 4) << 3);
+    r.nblk = gridDim.x / 2;
+  }
+  return r;
+}
+
 // XCD-aware remap: workgroups are dealt round-robin to the 8 XCDs; give each
 // XCD a contiguous run of tiles so neighbouring tiles share one L2.  nblocks
 // must be a multiple of 8 (then the map is a bijection of [0, nblocks)).

@@ -217,15 +217,20 @@ struct ApplyCentre {
 // y = A x on free rows (MODE 0: 0 on fixed rows; MODE 1: also p^T (A p) ->
 // alpha; MODE 2: xr, the caller's raw input, on fixed rows), on the march
 // whose prefetch queue sits in LDS.  The staged input x is zero on fixed nodes.
-template <bool CUBIC, int MODE>
+template <bool CUBIC, int MODE, int NS>
 MSMG_MARCH_KERNEL void k_apply(
     Geo g, Stencil st, March mg, const double* __restrict__ kc, const uint32_t* __restrict__ bits,
-    const double* __restrict__ x, const double* __restrict__ xr, double* __restrict__ y, Scalars* sc,
-    double* partials, unsigned* counter) {
+    Two<const double*> xs, Two<const double*> xrs, Two<double*> ys, Two<Scalars*> scs, Two<double*> partials,
+    Two<unsigned*> counters) {
+  const SideBlock sb = side_block<NS>();
+  Scalars* sc = scs[sb.side];
   if (MODE == 1 && sc->done) return;
+  const double* __restrict__ x = xs[sb.side];
+  const double* __restrict__ xr = xrs[sb.side];
+  double* __restrict__ y = ys[sb.side];
   MSMG_LDS_BUFFERS(double)
   __shared__ double red[16];
-  const long long tile = xcd_tile(blockIdx.x, gridDim.x);
+  const long long tile = xcd_tile(sb.blk, sb.nblk);
   double s[1] = {0.0};
   march_lds<CUBIC>(
       g, st, mg, tile, bufs, x, kc,
@@ -242,7 +247,7 @@ MSMG_MARCH_KERNEL void k_apply(
         if (MODE == 1) s[0] += xc * out;
       });
   if (MODE != 1) return;
-  grid_reduce<1>(s, red, partials, counter, gridDim.x, blockIdx.x, [&](double* tt) {
+  grid_reduce<1>(s, red, partials[sb.side], counters[sb.side], int(sb.nblk), int(sb.blk), [&](double* tt) {
     sc->pq = tt[0];
     sc->xpend = 0;  // every block of the preceding direction update has read it
     if (!(tt[0] > 0.0) || !(sc->rz > 0.0)) {
@@ -314,15 +319,18 @@ struct RD {
   DT di;
 };
 
-template <typename VT, typename KT, typename IT, typename DT, bool CUBIC>
-MSMG_MARCH_KERNEL void k_cheb2(Geo g, Stencil st, March mg, const KT* __restrict__ kv,
-                                                         const IT* __restrict__ r,
-                                                         const DT* __restrict__ dinv, VT* __restrict__ out,
-                                                         VT* __restrict__ dout, ChebCoef cc, const Scalars* sc) {
+template <typename VT, typename KT, typename IT, typename DT, bool CUBIC, int NS>
+MSMG_MARCH_KERNEL void k_cheb2(Geo g, Stencil st, March mg, const KT* __restrict__ kv, Two<const IT*> rs,
+                               const DT* __restrict__ dinv, Two<VT*> outs, VT* __restrict__ dout, ChebCoef cc,
+                               Two<const Scalars*> scs) {
+  const SideBlock sb = side_block<NS>();
+  const Scalars* sc = scs[sb.side];
   if (sc && sc->done) return;
+  const IT* __restrict__ r = rs[sb.side];
+  VT* __restrict__ out = outs[sb.side];
   __shared__ VT sx[2 * PW * PH];
   __shared__ VT sk[2 * EW * EH];
-  const long long tile = xcd_tile(blockIdx.x, gridDim.x);
+  const long long tile = xcd_tile(sb.blk, sb.nblk);
   const VT it = VT(cc.inv_theta), c0 = VT(cc.c0), c1 = VT(cc.c1);
   auto loadrd = [&](long long b, unsigned o) {
     RD<DT, IT> v;
@@ -487,17 +495,28 @@ __global__ void k_restrict(Geo g, Hier h, int CX, const VT* __restrict__ r, cons
 
 // Prolongation of Algorithm 1: out = base + sum_l R_c[n][l] (e1 + e2)[owner(n)][l]
 // (e2 optional).  Fixed nodes stay 0 (R_c vanishes there).
-template <typename VT, typename BT, int L>
-__global__ void k_prolong(Geo g, Hier h, int CX, const VT* __restrict__ base, const BT* __restrict__ Rc,
-                          const double* __restrict__ e1, const double* __restrict__ e2, double* __restrict__ out,
-                          const Scalars* sc) {
-  if (sc && sc->done) return;
+// With NS = 2 each thread prolongs both sides' corrections with one read of
+// the basis row (a side whose solve has stopped is skipped).
+template <typename VT, typename BT, int L, int NS>
+__global__ void k_prolong(Geo g, Hier h, int CX, Two<const VT*> bases, const BT* __restrict__ Rc,
+                          Two<const double*> e1s, Two<const double*> e2s, Two<double*> outs,
+                          Two<const Scalars*> scs) {
+  bool live[NS];
+  bool any = false;
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {
+    live[q] = !(scs[q] && scs[q]->done);
+    any = any || live[q];
+  }
+  if (!any) return;
   TILE_PROLOGUE
   if (!t.active) return;
   const long long cell = ((long long)t.cz * h.ncy + t.cy) * h.ncx + t.cx;
-  double e[L];
+  double e[NS][L];
 #pragma unroll
-  for (int l = 0; l < L; ++l) e[l] = e1[cell * L + l] + (e2 ? e2[cell * L + l] : 0.0);
+  for (int q = 0; q < NS; ++q)
+#pragma unroll
+    for (int l = 0; l < L; ++l) e[q][l] = live[q] ? e1s[q][cell * L + l] + (e2s[q] ? e2s[q][cell * L + l] : 0.0) : 0.0;
   for (int j = t.ys; j < t.ye; ++j)
     for (int i = t.xs; i < t.xe; ++i) {
       const long long n0 = node_id(g, i, j, t.zs), pl = (long long)g.nnx * g.nny;
@@ -506,10 +525,14 @@ __global__ void k_prolong(Geo g, Hier h, int CX, const VT* __restrict__ base, co
         const long long n = n0 + k * pl;
         double row[L];
         load_row<BT, L>(Rc, n, row);
-        double v = base ? double(base[n]) : 0.0;
 #pragma unroll
-        for (int l = 0; l < L; ++l) v += row[l] * e[l];
-        out[n] = v;
+        for (int q = 0; q < NS; ++q) {
+          if (!live[q]) continue;
+          double v = bases[q] ? double(bases[q][n]) : 0.0;
+#pragma unroll
+          for (int l = 0; l < L; ++l) v += row[l] * e[q][l];
+          outs[q][n] = v;
+        }
       }
     }
 }
@@ -523,15 +546,19 @@ struct RW {
   uint32_t w;
 };
 
-template <typename VT, typename KT, typename IT, typename XT, bool CUBIC>
+template <typename VT, typename KT, typename IT, typename XT, bool CUBIC, int NS>
 MSMG_MARCH_KERNEL void k_vresidual(Geo g, Stencil st, March mg, const KT* __restrict__ kv,
-                                                             const uint32_t* __restrict__ bits,
-                                                             const IT* __restrict__ r, const XT* __restrict__ x,
-                                                             VT* __restrict__ out, const Scalars* sc) {
+                                   const uint32_t* __restrict__ bits, Two<const IT*> rs, Two<const XT*> xs,
+                                   Two<VT*> outs, Two<const Scalars*> scs) {
+  const SideBlock sb = side_block<NS>();
+  const Scalars* sc = scs[sb.side];
   if (sc && sc->done) return;
+  const IT* __restrict__ r = rs[sb.side];
+  const XT* __restrict__ x = xs[sb.side];
+  VT* __restrict__ out = outs[sb.side];
   __shared__ XT sx[2 * PW * PH];
   __shared__ XT sk[2 * EW * EH];
-  const long long tile = xcd_tile(blockIdx.x, gridDim.x);
+  const long long tile = xcd_tile(sb.blk, sb.nblk);
   march<XT, CUBIC>(
       g, st, mg, tile, sx, sk, [&](long long b, unsigned o) { return plane_ld(x, b, o); }, [&](XT v) { return v; },
       [&](long long b, unsigned o) { return plane_ld(kv, b, o); }, [&](KT v) { return cvt<XT, KT>(v); },
@@ -585,16 +612,21 @@ MSMG_DEV void load_row_raw(const BT* __restrict__ Rc, long long n, BT out[L]) {
   }
 }
 
-template <typename VT, typename KT, typename XT, typename BT, int L, bool CUBIC>
+template <typename VT, typename KT, typename XT, typename BT, int L, bool CUBIC, int NS>
 MSMG_MARCH_KERNEL void k_vresidual_restrict(Geo g, Stencil st, Hier h, RestrictGeo rg, const KT* __restrict__ kv,
-                                            const uint32_t* __restrict__ bits, const double* __restrict__ r,
-                                            const XT* __restrict__ x, const BT* __restrict__ Rc,
-                                            double* __restrict__ rpart, const Scalars* sc) {
+                                            const uint32_t* __restrict__ bits, Two<const double*> rs,
+                                            Two<const XT*> xs, const BT* __restrict__ Rc, Two<double*> rparts,
+                                            Two<const Scalars*> scs) {
+  const SideBlock sb = side_block<NS>();
+  const Scalars* sc = scs[sb.side];
   if (sc && sc->done) return;
+  const double* __restrict__ r = rs[sb.side];
+  const XT* __restrict__ x = xs[sb.side];
+  double* __restrict__ rpart = rparts[sb.side];
   __shared__ XT sx[2 * PW * PH];
   __shared__ XT sk[2 * EW * EH];
   __shared__ double red[MY * (MX / 2) * L];  // [row][cell of the row][l], at most MX / 2 cells per row
-  const long long tile = xcd_tile(blockIdx.x, gridDim.x);
+  const long long tile = xcd_tile(sb.blk, sb.nblk);
   const March& mg = rg.m;
   const int tx = int(tile % mg.ntx), ty = int((tile / mg.ntx) % mg.nty);
   const int xa = tx * MX, ya = ty * MY;
@@ -731,17 +763,23 @@ struct RDZ {
   double b, rr, q;
 };
 
-template <typename VT, typename KT, typename IT, typename DT, bool CUBIC, int MODE>
-MSMG_MARCH_KERNEL void k_cheb2_out(Geo g, Stencil st, March mg, const KT* __restrict__ kv,
-                                   const IT* __restrict__ res, const DT* __restrict__ dinv, ChebCoef cc,
-                                   const double* __restrict__ base, double* __restrict__ z,
-                                   const double* __restrict__ r, const double* __restrict__ q, Scalars* sc,
-                                   double* partials, unsigned* counter) {
+template <typename VT, typename KT, typename IT, typename DT, bool CUBIC, int MODE, int NS>
+MSMG_MARCH_KERNEL void k_cheb2_out(Geo g, Stencil st, March mg, const KT* __restrict__ kv, Two<const IT*> ress,
+                                   const DT* __restrict__ dinv, ChebCoef cc, Two<const double*> bases,
+                                   Two<double*> zs, Two<const double*> rs, Two<const double*> qs, Two<Scalars*> scs,
+                                   Two<double*> partials, Two<unsigned*> counters) {
+  const SideBlock sb = side_block<NS>();
+  Scalars* sc = scs[sb.side];
   if (sc->done) return;
+  const IT* __restrict__ res = ress[sb.side];
+  const double* __restrict__ base = bases[sb.side];
+  double* __restrict__ z = zs[sb.side];
+  const double* __restrict__ r = rs[sb.side];
+  const double* __restrict__ q = qs[sb.side];
   __shared__ VT sx[2 * PW * PH];
   __shared__ VT sk[2 * EW * EH];
   __shared__ double red[32];
-  const long long tile = xcd_tile(blockIdx.x, gridDim.x);
+  const long long tile = xcd_tile(sb.blk, sb.nblk);
   const VT it = VT(cc.inv_theta), c0 = VT(cc.c0), c1 = VT(cc.c1);
   double s[2] = {0.0, 0.0};
   march<VT, CUBIC>(
@@ -775,7 +813,8 @@ MSMG_MARCH_KERNEL void k_cheb2_out(Geo g, Stencil st, March mg, const KT* __rest
         if (MODE == 1) s[1] += zz * c.q;
       });
   if (MODE == 2) return;
-  grid_reduce<2>(s, red, partials, counter, gridDim.x, blockIdx.x, [&](double* tt) { vc_finish(sc, tt, MODE); });
+  grid_reduce<2>(s, red, partials[sb.side], counters[sb.side], int(sb.nblk), int(sb.blk),
+                 [&](double* tt) { vc_finish(sc, tt, MODE); });
 }
 
 // ---------------------------------------------------------------------------
@@ -1052,7 +1091,7 @@ long long march_resident_blocks() {
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 2048;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 2048;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(&k_vresidual<double, bf16, double, double, true>),
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(&k_vresidual<double, bf16, double, double, true, 1>),
                                                    MARCH_THREADS, 0) != hipSuccess)
     return 2048;
   return (long long)(per > 0 ? per : 1) * (cus > 0 ? cus : 1);
@@ -1063,7 +1102,7 @@ long long apply_resident_blocks() {
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 2048;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 2048;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(&k_apply<true, 1>),
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(&k_apply<true, 1, 1>),
                                                    MARCH_THREADS, 0) != hipSuccess)
     return 2048;
   return (long long)(per > 0 ? per : 1) * (cus > 0 ? cus : 1);
@@ -1071,10 +1110,18 @@ long long apply_resident_blocks() {
 
 void launch_apply(const Ctx& c, const double* x, double* y, int mode, hipStream_t s, const double* xraw) {
   const dim3 gr((unsigned)c.mgl.blocks), bl(LMX, LMY);
-#define APL(CU, MD) hipLaunchKernelGGL((k_apply<CU, MD>), gr, bl, 0, s, c.g, c.st, c.mgl, c.kc, c.bits, x, xraw, y, c.sc, c.partials, c.counter)
+#define APL(CU, MD) hipLaunchKernelGGL((k_apply<CU, MD, 1>), gr, bl, 0, s, c.g, c.st, c.mgl, c.kc, c.bits, one(x), one(xraw), one(y), one(c.sc), one(c.partials), one(c.counter))
 #define AP_M(CU) do { if (mode == 0) APL(CU, 0); else if (mode == 1) APL(CU, 1); else APL(CU, 2); } while (0)
   if (c.st.cubic) AP_M(true); else AP_M(false);
 #undef AP_M
+#undef APL
+}
+
+void launch_apply_pair(const Ctx& a, const Ctx& b, const double* xa, const double* xb, double* ya, double* yb,
+                       hipStream_t s) {
+  const dim3 gr((unsigned)(2 * a.mgl.blocks)), bl(LMX, LMY);
+#define APL(CU) hipLaunchKernelGGL((k_apply<CU, 1, 2>), gr, bl, 0, s, a.g, a.st, a.mgl, a.kc, a.bits, two(xa, xb), two((const double*)nullptr, (const double*)nullptr), two(ya, yb), two(a.sc, b.sc), two(a.partials, b.partials), two(a.counter, b.counter))
+  if (a.st.cubic) APL(true); else APL(false);
 #undef APL
 }
 
@@ -1141,9 +1188,9 @@ void launch_smooth(const Ctx& c, const void* in, bool in_is_f64, void* out, hipS
       VT* xa = (deg % 2 == 0) ? o : (VT*)c.vc_t1;  // so that the last step lands in `out`
       VT* xb = (xa == o) ? (VT*)c.vc_t1 : o;
       if (in_is_f64)
-        hipLaunchKernelGGL((k_cheb2<VT, KVT, double, DVT, CU>), gr, bl, 0, s, c.g, c.st, c.mg, (const KVT*)c.kv, (const double*)in, dinv, xa, d, c.cheb, c.sc);
+        hipLaunchKernelGGL((k_cheb2<VT, KVT, double, DVT, CU, 1>), gr, bl, 0, s, c.g, c.st, c.mg, (const KVT*)c.kv, one((const double*)in), dinv, one(xa), d, c.cheb, one((const Scalars*)c.sc));
       else
-        hipLaunchKernelGGL((k_cheb2<VT, KVT, VT, DVT, CU>), gr, bl, 0, s, c.g, c.st, c.mg, (const KVT*)c.kv, (const VT*)in, dinv, xa, d, c.cheb, c.sc);
+        hipLaunchKernelGGL((k_cheb2<VT, KVT, VT, DVT, CU, 1>), gr, bl, 0, s, c.g, c.st, c.mg, (const KVT*)c.kv, one((const VT*)in), dinv, one(xa), d, c.cheb, one((const Scalars*)c.sc));
       for (int step = 2; step < deg; ++step) {
         const double ca = c.cheb.step_a[step], cb = c.cheb.step_b[step];
         if (in_is_f64)
@@ -1153,6 +1200,19 @@ void launch_smooth(const Ctx& c, const void* in, bool in_is_f64, void* out, hipS
         VT* tmp = xa; xa = xb; xb = tmp;
       }
     }
+  });
+}
+
+// The degree-2 smoother S^-1 applied to two FP64 residuals at once.
+void launch_smooth_pair(const Ctx& a, const Ctx& b, const double* ina, const double* inb, void* outa, void* outb,
+                        hipStream_t s) {
+  const Ctx& c = a;
+  const dim3 gr((unsigned)(2 * c.mg.blocks)), bl = march_block();
+  VC_DISPATCH({
+    (void)sizeof(BT);
+    hipLaunchKernelGGL((k_cheb2<VT, KVT, double, DVT, CU, 2>), gr, bl, 0, s, c.g, c.st, c.mg, (const KVT*)c.kv,
+                       two(ina, inb), (const DVT*)c.dinv, two((VT*)outa, (VT*)outb), (VT*)nullptr, c.cheb,
+                       two((const Scalars*)a.sc, (const Scalars*)b.sc));
   });
 }
 
@@ -1190,7 +1250,19 @@ void launch_prolong(const Ctx& c, const void* base, const void* e1, const void* 
     (void)sizeof(KVT);
     (void)sizeof(DVT);
     (void)CU;
-    L_DISPATCH(c.h.Lc, hipLaunchKernelGGL((k_prolong<VT, BT, LL>), gr, bl, 0, s, c.g, c.h, c.CX, (const VT*)base, (const BT*)c.Rc, (const double*)e1, (const double*)e2, (double*)out, c.sc));
+    L_DISPATCH(c.h.Lc, hipLaunchKernelGGL((k_prolong<VT, BT, LL, 1>), gr, bl, 0, s, c.g, c.h, c.CX, one((const VT*)base), (const BT*)c.Rc, one((const double*)e1), one((const double*)e2), one((double*)out), one((const Scalars*)c.sc)));
+  });
+}
+
+void launch_prolong_pair(const Ctx& a, const Ctx& b, const void* basea, const void* baseb, const void* ea,
+                         const void* eb, void* outa, void* outb, hipStream_t s) {
+  const Ctx& c = a;
+  const dim3 gr = tile_grid(c), bl = tile_block(c);
+  VC_DISPATCH({
+    (void)sizeof(KVT);
+    (void)sizeof(DVT);
+    (void)CU;
+    L_DISPATCH(c.h.Lc, hipLaunchKernelGGL((k_prolong<VT, BT, LL, 2>), gr, bl, 0, s, c.g, c.h, c.CX, two((const VT*)basea, (const VT*)baseb), (const BT*)c.Rc, two((const double*)ea, (const double*)eb), two((const double*)nullptr, (const double*)nullptr), two((double*)outa, (double*)outb), two((const Scalars*)a.sc, (const Scalars*)b.sc)));
   });
 }
 
@@ -1201,11 +1273,25 @@ void launch_vresidual(const Ctx& c, const void* r, bool r_is_f64, const void* x,
     (void)sizeof(BT);
     (void)sizeof(DVT);
     if (x_is_f64) {
-      hipLaunchKernelGGL((k_vresidual<VT, KVT, double, double, CU>), gr, bl, 0, s, c.g, c.st, c.mg, (const KVT*)c.kv, c.bits, (const double*)r, (const double*)x, (VT*)out, c.sc);
+      hipLaunchKernelGGL((k_vresidual<VT, KVT, double, double, CU, 1>), gr, bl, 0, s, c.g, c.st, c.mg, (const KVT*)c.kv, c.bits, one((const double*)r), one((const double*)x), one((VT*)out), one((const Scalars*)c.sc));
     } else {
-      hipLaunchKernelGGL((k_vresidual<VT, KVT, double, VT, CU>), gr, bl, 0, s, c.g, c.st, c.mg, (const KVT*)c.kv, c.bits, (const double*)r, (const VT*)x, (VT*)out, c.sc);
+      hipLaunchKernelGGL((k_vresidual<VT, KVT, double, VT, CU, 1>), gr, bl, 0, s, c.g, c.st, c.mg, (const KVT*)c.kv, c.bits, one((const double*)r), one((const VT*)x), one((VT*)out), one((const Scalars*)c.sc));
     }
     (void)r_is_f64;
+  });
+}
+
+// out = r - A x for two sides at once (FP64 r and x, the prolonged iterates)
+void launch_vresidual_pair(const Ctx& a, const Ctx& b, const double* ra, const double* rb, const double* xa,
+                           const double* xb, void* outa, void* outb, hipStream_t s) {
+  const Ctx& c = a;
+  const dim3 gr((unsigned)(2 * c.mg.blocks)), bl = march_block();
+  VC_DISPATCH({
+    (void)sizeof(BT);
+    (void)sizeof(DVT);
+    hipLaunchKernelGGL((k_vresidual<VT, KVT, double, double, CU, 2>), gr, bl, 0, s, c.g, c.st, c.mg, (const KVT*)c.kv,
+                       c.bits, two(ra, rb), two(xa, xb), two((VT*)outa, (VT*)outb),
+                       two((const Scalars*)a.sc, (const Scalars*)b.sc));
   });
 }
 
@@ -1243,10 +1329,23 @@ void launch_vresidual_restrict(const Ctx& c, const double* r, const void* x, dou
   const dim3 gr((unsigned)c.rg.m.blocks), bl = march_block();
   VC_DISPATCH({
     (void)sizeof(DVT);
-    L_DISPATCH(c.h.Lc, hipLaunchKernelGGL((k_vresidual_restrict<VT, KVT, VT, BT, LL, CU>), gr, bl, 0, s, c.g, c.st, c.h, c.rg, (const KVT*)c.kv, c.bits, r, (const VT*)x, (const BT*)c.Rc, c.rpart, c.sc));
+    L_DISPATCH(c.h.Lc, hipLaunchKernelGGL((k_vresidual_restrict<VT, KVT, VT, BT, LL, CU, 1>), gr, bl, 0, s, c.g, c.st, c.h, c.rg, (const KVT*)c.kv, c.bits, one(r), one((const VT*)x), (const BT*)c.Rc, one(c.rpart), one((const Scalars*)c.sc)));
   });
   const long long n = (long long)c.h.ncells * c.h.Lc;
   L_DISPATCH(c.h.Lc, hipLaunchKernelGGL((k_restrict_finish<LL>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, c.g, c.h, c.rg, (const double*)c.rpart, rc, c.sc));
+}
+
+void launch_vresidual_restrict_pair(const Ctx& a, const Ctx& b, const double* ra, const double* rb, const void* xa,
+                                    const void* xb, double* rca, double* rcb, hipStream_t s) {
+  const Ctx& c = a;
+  const dim3 gr((unsigned)(2 * c.rg.m.blocks)), bl = march_block();
+  VC_DISPATCH({
+    (void)sizeof(DVT);
+    L_DISPATCH(c.h.Lc, hipLaunchKernelGGL((k_vresidual_restrict<VT, KVT, VT, BT, LL, CU, 2>), gr, bl, 0, s, c.g, c.st, c.h, c.rg, (const KVT*)c.kv, c.bits, two(ra, rb), two((const VT*)xa, (const VT*)xb), (const BT*)c.Rc, two(a.rpart, b.rpart), two((const Scalars*)a.sc, (const Scalars*)b.sc)));
+  });
+  const long long n = (long long)c.h.ncells * c.h.Lc;
+  L_DISPATCH(c.h.Lc, hipLaunchKernelGGL((k_restrict_finish<LL>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a.g, a.h, a.rg, (const double*)a.rpart, rca, a.sc));
+  L_DISPATCH(c.h.Lc, hipLaunchKernelGGL((k_restrict_finish<LL>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, b.g, b.h, b.rg, (const double*)b.rpart, rcb, b.sc));
 }
 
 void launch_vc_output(const Ctx& c, const void* a, bool a_is_f64, const void* b, double* z, const double* r,
@@ -1266,7 +1365,7 @@ bool smooth_output_fused(const Ctx& c) { return c.cheb.degree == 2; }
 void launch_smooth_output(const Ctx& c, const void* in, bool in_is_f64, const double* base, double* z,
                           const double* r, const double* q, int mode, hipStream_t s) {
   const dim3 gr = march_grid(c), bl = march_block();
-#define SO(IT_, MD) hipLaunchKernelGGL((k_cheb2_out<VT, KVT, IT_, DVT, CU, MD>), gr, bl, 0, s, c.g, c.st, c.mg, (const KVT*)c.kv, (const IT_*)in, (const DVT*)c.dinv, c.cheb, base, z, r, q, c.sc, c.partials, c.counter)
+#define SO(IT_, MD) hipLaunchKernelGGL((k_cheb2_out<VT, KVT, IT_, DVT, CU, MD, 1>), gr, bl, 0, s, c.g, c.st, c.mg, (const KVT*)c.kv, one((const IT_*)in), (const DVT*)c.dinv, c.cheb, one(base), one(z), one(r), one(q), one(c.sc), one(c.partials), one(c.counter))
 #define SO_M(IT_) do { if (mode == 0) SO(IT_, 0); else if (mode == 1) SO(IT_, 1); else SO(IT_, 2); } while (0)
   VC_DISPATCH({
     (void)sizeof(BT);
@@ -1274,6 +1373,21 @@ void launch_smooth_output(const Ctx& c, const void* in, bool in_is_f64, const do
   });
 #undef SO_M
 #undef SO
+}
+
+// The fused post-smoother and output for two sides (V-cycle vectors in, PCG
+// reductions of `mode` 0 or 1 per side).
+void launch_smooth_output_pair(const Ctx& a, const Ctx& b, const void* ina, const void* inb, const double* basea,
+                               const double* baseb, double* za, double* zb, const double* ra, const double* rb,
+                               const double* qa, const double* qb, int mode, hipStream_t s) {
+  const Ctx& c = a;
+  const dim3 gr((unsigned)(2 * c.mg.blocks)), bl = march_block();
+#define SOP(MD) hipLaunchKernelGGL((k_cheb2_out<VT, KVT, VT, DVT, CU, MD, 2>), gr, bl, 0, s, c.g, c.st, c.mg, (const KVT*)c.kv, two((const VT*)ina, (const VT*)inb), (const DVT*)c.dinv, c.cheb, two(basea, baseb), two(za, zb), two(ra, rb), two(qa, qb), two(a.sc, b.sc), two(a.partials, b.partials), two(a.counter, b.counter))
+  VC_DISPATCH({
+    (void)sizeof(BT);
+    if (mode == 0) SOP(0); else SOP(1);
+  });
+#undef SOP
 }
 
 void launch_sensitivity(const Ctx& c, const double* T, const double* lam, double* dc, hipStream_t s) {

@@ -145,6 +145,23 @@ void launch_vc_output(const Ctx& c, const void* a, bool a_is_f64, const void* b,
 bool smooth_output_fused(const Ctx& c);
 void launch_smooth_output(const Ctx& c, const void* in, bool in_is_f64, const double* base, double* z,
                           const double* r, const double* q, int mode, hipStream_t s);
+// The same kernels for the two right-hand sides of a batched pair (a and b:
+// contexts of the two sides; the coefficients are a's, shared).  The
+// smoother, the residual after the coarse correction and the fused output are
+// the degree-2 forms; inputs and outputs as in the single-side launchers.
+void launch_apply_pair(const Ctx& a, const Ctx& b, const double* xa, const double* xb, double* ya, double* yb,
+                       hipStream_t s);
+void launch_smooth_pair(const Ctx& a, const Ctx& b, const double* ina, const double* inb, void* outa, void* outb,
+                        hipStream_t s);
+void launch_vresidual_restrict_pair(const Ctx& a, const Ctx& b, const double* ra, const double* rb, const void* xa,
+                                    const void* xb, double* rca, double* rcb, hipStream_t s);
+void launch_prolong_pair(const Ctx& a, const Ctx& b, const void* basea, const void* baseb, const void* ea,
+                         const void* eb, void* outa, void* outb, hipStream_t s);
+void launch_vresidual_pair(const Ctx& a, const Ctx& b, const double* ra, const double* rb, const double* xa,
+                           const double* xb, void* outa, void* outb, hipStream_t s);
+void launch_smooth_output_pair(const Ctx& a, const Ctx& b, const void* ina, const void* inb, const double* basea,
+                               const double* baseb, double* za, double* zb, const double* ra, const double* rb,
+                               const double* qa, const double* qb, int mode, hipStream_t s);
 void launch_sensitivity(const Ctx& c, const double* T, const double* lam, double* dc, hipStream_t s);
 void launch_sensitivity_heat_source(const Ctx& c, const double* T, const double* lam, double f0, double* dc,
                                     hipStream_t s);
@@ -168,6 +185,9 @@ void launch_cc_prolong(const Ctx& c, const void* base, const double* ecc, void* 
 // within the device's co-resident capacity; 0 when that cannot be had).
 // Input rc; output x = e_c, the coarse correction; t and rcc are its scratch;
 // bar: level1_barrier_words() zeroed words.  FP64 A_c only.
+hipError_t launch_level1_pair(const Ctx& c0, const Ctx& c1, int blocks, const double* rc0, const double* rc1,
+                              double* x0, double* x1, double* t0, double* t1, double* rcc0, double* rcc1,
+                              unsigned* bar, unsigned spin_limit, hipStream_t s);
 int level1_blocks();
 int level1_barrier_words();  // size of its barrier buffer (unsigned words)
 hipError_t launch_level1(const Ctx& c, int blocks, const double* rc, double* x, double* t, double* rcc,

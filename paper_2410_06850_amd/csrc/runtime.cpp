@@ -35,6 +35,21 @@ static int fail(int code, const std::string& msg) {
       return fail(MSMG_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e));             \
   } while (0)
 
+// The vectors, scalars and reduction scratch of one right-hand side's PCG.
+struct VecSet {
+  double *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr, *b = nullptr;
+  float* xlo = nullptr;  // low part of the double-double iterate (|lo| <= ulp(hi) / 2, FP32)
+  // V-cycle vectors (v_dt; v_r2 FP64) and coarse vectors
+  void *v_r1 = nullptr, *v_r2 = nullptr, *v_res = nullptr;
+  void *c_rc = nullptr, *c_x0 = nullptr, *c_t = nullptr, *c_x1 = nullptr, *c_d = nullptr;
+  double *rcc = nullptr, *ecc = nullptr;
+  double* rpart = nullptr;  // partial sums of the fused residual + restriction
+  Scalars* sc = nullptr;
+  Scalars* sc_host = nullptr;  // pinned
+  double* partials = nullptr;
+  unsigned* counter = nullptr;
+};
+
 struct msmg_handle {
   int device = 0;
   msmg_options opt{};
@@ -80,22 +95,13 @@ struct msmg_handle {
   int n_c = 0, n_cc = 0, max_cc_dofs = 0, max_cell_nodes = 0;
   std::vector<int> h_cc_ptr;
 
-  // PCG vectors (FP64)
-  double *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr, *b = nullptr;
-  float* xlo = nullptr;   // low part of the double-double iterate (|lo| <= ulp(hi) / 2, FP32)
-  // V-cycle vectors (v_dt) and coarse vectors
-  void *v_r1 = nullptr, *v_r2 = nullptr, *v_res = nullptr, *v_t0 = nullptr, *v_t1 = nullptr;
-  void *c_rc = nullptr, *c_x0 = nullptr, *c_t = nullptr, *c_x1 = nullptr, *c_d = nullptr;
-  double *rcc = nullptr, *ecc = nullptr;
+  // per right-hand side: vs[0] for every solve, vs[1] for the second side of
+  // a batched pair (allocated with options.pair_rhs)
+  VecSet vs[2];
+  void *v_t0 = nullptr, *v_t1 = nullptr;  // Chebyshev scratch for degrees > 2 (side 0)
   int l1_blocks = 0;         // workgroups of the grid-synchronised coarse-level kernel (0: separate launches)
   unsigned* l1_bar = nullptr;  // its barrier words
   RestrictGeo rg{};          // fused residual + restriction of the cycle
-  double* rpart = nullptr;   // its per-workgroup partial sums
-
-  Scalars* sc = nullptr;
-  Scalars* sc_host = nullptr;  // pinned
-  double* partials = nullptr;
-  unsigned* counter = nullptr;
   int red_blocks = 4096;
   long long march_resident = 2048;  // marching workgroups resident at once (queried at create)
   long long apply_resident = 768;   // the same for the LDS-queue apply
@@ -249,7 +255,7 @@ static ChebCoef make_cheb(const msmg_options& o) {
   return c;
 }
 
-static Ctx make_ctx(msmg_handle* h) {
+static Ctx make_ctx(msmg_handle* h, int side = 0) {
   Ctx c{};
   c.g = h->g;
   c.st = h->st;
@@ -270,14 +276,14 @@ static Ctx make_ctx(msmg_handle* h) {
   c.Rc = h->Rcs;
   c.b_dt = h->b_dt;
   c.cheb = make_cheb(h->opt);
-  c.sc = h->sc;
-  c.partials = h->partials;
-  c.counter = h->counter;
+  c.sc = h->vs[side].sc;
+  c.partials = h->vs[side].partials;
+  c.counter = h->vs[side].counter;
   c.red_blocks = h->red_blocks;
   c.vc_t0 = h->v_t0;
   c.vc_t1 = h->v_t1;
   c.rg = h->rg;
-  c.rpart = h->rpart;
+  c.rpart = h->vs[side].rpart;
   c.cc.Ac = h->Acv;
   c.cc.AcDinv = h->AcDinvv;
   c.cc.a_dt = h->a_dt;
@@ -311,8 +317,10 @@ static void free_all(msmg_handle* h) {
   h->events.clear();
   for (void* p : h->allocs) (void)hipFree(p);
   h->allocs.clear();
-  if (h->sc_host) (void)hipHostFree(h->sc_host);
-  h->sc_host = nullptr;
+  for (VecSet& V : h->vs) {
+    if (V.sc_host) (void)hipHostFree(V.sc_host);
+    V.sc_host = nullptr;
+  }
 }
 
 #define TRY(expr)                 \
@@ -354,6 +362,7 @@ extern "C" void msmg_default_options(msmg_options* o) {
   o->lean_memory = 0;
   o->cc_group = 0;
   o->coarse_fused = 3;
+  o->pair_rhs = 0;
 }
 
 extern "C" const char* msmg_last_error(void) { return g_last_error.c_str(); }
@@ -377,6 +386,8 @@ static int check_options(const msmg_options& o) {
     return fail(MSMG_EINVAL, "bad coarse-coarse eigensolver options");
   if (o.rho_storage != MSMG_F64 && o.rho_storage != MSMG_F32) return fail(MSMG_EINVAL, "rho_storage must be F64 or F32");
   if (o.cc_group < 0) return fail(MSMG_EINVAL, "cc_group must be >= 0");
+  if (o.pair_rhs && (o.pc_kind != MSMG_PC_MULTIGRID || o.cheb_degree != 2))
+    return fail(MSMG_EINVAL, "pair_rhs needs the multigrid preconditioner with the degree-2 smoother");
   if (o.lean_memory && o.eig_warm_start)
     return fail(MSMG_EINVAL, "lean_memory keeps no basis between set-ups: eig_warm_start is not available");
   return MSMG_OK;
@@ -412,33 +423,33 @@ static int alloc_arrays(msmg_handle* h, bool dry, size_t* total) {
     double* blk = nullptr;
     A(&blk, (size_t)nv * nn * 8);
     if (blk) {
-      h->r = blk; h->p = blk + nn; h->q = blk + 2 * nn; h->z = blk + 3 * nn;
+      h->vs[0].r = blk; h->vs[0].p = blk + nn; h->vs[0].q = blk + 2 * nn; h->vs[0].z = blk + 3 * nn;
       h->Rc64 = blk;
     }
   } else {
-    A(&h->r, nn * 8); A(&h->p, nn * 8); A(&h->q, nn * 8); A(&h->z, nn * 8);
+    A(&h->vs[0].r, nn * 8); A(&h->vs[0].p, nn * 8); A(&h->vs[0].q, nn * 8); A(&h->vs[0].z, nn * 8);
   }
-  A(&h->b, nn * 8);
-  A(&h->xlo, nn * 4);
-  A(&h->v_r1, nn * vs); A(&h->v_res, nn * vs);
+  A(&h->vs[0].b, nn * 8);
+  A(&h->vs[0].xlo, nn * 4);
+  A(&h->vs[0].v_r1, nn * vs); A(&h->vs[0].v_res, nn * vs);
   if (o.cheb_degree > 2) { A(&h->v_t0, nn * vs); A(&h->v_t1, nn * vs); }
   // one slot per workgroup of any reducing launch (tiles, march, 1-D grids)
   h->partial_slots = std::max<long long>({h->ntiles + 8, 8192LL, make_march(h->g, h->march_resident).blocks,
                                           make_march(h->g, h->apply_resident, 8, LMX, LMY).blocks,
                                           (long long)h->red_blocks});
-  A(&h->partials, h->partial_slots * 2 * 8);
-  A(&h->counter, 64);
+  A(&h->vs[0].partials, h->partial_slots * 2 * 8);
+  A(&h->vs[0].counter, 64);
   A(&h->oc_state, 64);
-  A(&h->sc, sizeof(Scalars));
+  A(&h->vs[0].sc, sizeof(Scalars));
   if (h->mg) {
-    A(&h->v_r2, nn * 8);  // prolongated iterate: FP64 on every path
+    A(&h->vs[0].v_r2, nn * 8);  // prolongated iterate: FP64 on every path
     if (!lean) A(&h->Rc64, nn * h->hier.Lc * 8);
     // the cycle's copy of the basis; the lean layout needs its own even in FP64,
     // since the master there is overwritten by the first solve
     if (h->b_dt != DT_F64 || lean) A(&h->Rcs, nn * h->hier.Lc * dt_size(h->b_dt));
     const size_t nblk = (size_t)h->hier.ncells * 27 * h->hier.Lc * h->hier.Lc;
     A(&h->Ac64, nblk * 8);
-    if (lean && nblk <= (size_t)nn) h->G64 = (double*)h->v_r2;
+    if (lean && nblk <= (size_t)nn) h->G64 = (double*)h->vs[0].v_r2;
     else A(&h->G64, nblk * 8);
     A(&h->AcDinv64, (size_t)h->n_c * h->hier.Lc * 8);
     if (h->a_dt != DT_F64) {
@@ -455,13 +466,28 @@ static int alloc_arrays(msmg_handle* h, bool dry, size_t* total) {
     A(&h->cell_status, (size_t)h->hier.ncells * 4);
     A(&h->cc_evals, (size_t)h->n_cc * 8);
     A(&h->cc_status, (size_t)h->hier.ncc * 4);
-    A(&h->c_rc, (size_t)h->n_c * 8); A(&h->c_x0, (size_t)h->n_c * 8); A(&h->c_t, (size_t)h->n_c * 8);
-    A(&h->c_x1, (size_t)h->n_c * 8); A(&h->c_d, (size_t)h->n_c * 8);
-    A(&h->rcc, (size_t)h->n_cc * 8); A(&h->ecc, (size_t)h->n_cc * 8);
+    A(&h->vs[0].c_rc, (size_t)h->n_c * 8); A(&h->vs[0].c_x0, (size_t)h->n_c * 8); A(&h->vs[0].c_t, (size_t)h->n_c * 8);
+    A(&h->vs[0].c_x1, (size_t)h->n_c * 8); A(&h->vs[0].c_d, (size_t)h->n_c * 8);
+    A(&h->vs[0].rcc, (size_t)h->n_cc * 8); A(&h->vs[0].ecc, (size_t)h->n_cc * 8);
     if (o.coarse_fused & 1) A(&h->l1_bar, (size_t)level1_barrier_words() * 4);
     if ((o.coarse_fused & 2) && restrict_fusable(h->hier)) {
       h->rg = make_restrict_geo(h->g, h->hier, h->march_resident);
-      A(&h->rpart, (size_t)h->rg.slots * h->hier.Lc * 8);
+      A(&h->vs[0].rpart, (size_t)h->rg.slots * h->hier.Lc * 8);
+    }
+    if (o.pair_rhs) {
+      // the second side of a batched pair: its own PCG and cycle vectors
+      VecSet& V = h->vs[1];
+      A(&V.r, nn * 8); A(&V.p, nn * 8); A(&V.q, nn * 8); A(&V.z, nn * 8); A(&V.b, nn * 8);
+      A(&V.xlo, nn * 4);
+      A(&V.v_r1, nn * vs); A(&V.v_res, nn * vs); A(&V.v_r2, nn * 8);
+      A(&V.partials, h->partial_slots * 2 * 8);
+      A(&V.counter, 64);
+      A(&V.sc, sizeof(Scalars));
+      A(&V.c_rc, (size_t)h->n_c * 8); A(&V.c_x0, (size_t)h->n_c * 8); A(&V.c_t, (size_t)h->n_c * 8);
+      A(&V.c_x1, (size_t)h->n_c * 8); A(&V.c_d, (size_t)h->n_c * 8);
+      A(&V.rcc, (size_t)h->n_cc * 8); A(&V.ecc, (size_t)h->n_cc * 8);
+      if (h->vs[0].rpart || (dry && (o.coarse_fused & 2) && restrict_fusable(h->hier)))
+        A(&V.rpart, (size_t)h->rg.slots * h->hier.Lc * 8);
     }
     if (rc == MSMG_OK)
       rc = setup_scratch_alloc(h->g, h->hier, h->max_cc_dofs, h->n_cc, o, &h->scratch, [&](void** p, size_t bytes) {
@@ -540,8 +566,11 @@ extern "C" int msmg_create(msmg_handle** out, int nx, int ny, int nz, double lx,
   int rc = alloc_arrays(h, false, nullptr);
   if (rc == MSMG_OK && h->mg && h->l1_bar && h->a_dt == DT_F64 && h->hier.Lcc <= 64) h->l1_blocks = level1_blocks();
   if (rc == MSMG_OK) {
-    hipError_t e = hipHostMalloc((void**)&h->sc_host, sizeof(Scalars), hipHostMallocDefault);
-    if (e != hipSuccess) rc = fail(MSMG_ENOMEM, "pinned host allocation failed");
+    for (VecSet& V : h->vs) {
+      if (!V.sc || rc != MSMG_OK) continue;
+      hipError_t e = hipHostMalloc((void**)&V.sc_host, sizeof(Scalars), hipHostMallocDefault);
+      if (e != hipSuccess) rc = fail(MSMG_ENOMEM, "pinned host allocation failed");
+    }
   }
   if (rc != MSMG_OK) {
     free_all(h);
@@ -553,9 +582,11 @@ extern "C" int msmg_create(msmg_handle** out, int nx, int ny, int nz, double lx,
   if (!h->Acv) h->Acv = h->Ac64;
   if (!h->AcDinvv) h->AcDinvv = h->AcDinv64;
   if (!h->Rccv) h->Rccv = h->Rcc64;
-  HIP_TRY(hipMemset(h->counter, 0, 64));
+  for (VecSet& V : h->vs)
+    if (V.counter) HIP_TRY(hipMemset(V.counter, 0, 64));
   if (h->l1_bar) HIP_TRY(hipMemset(h->l1_bar, 0, (size_t)level1_barrier_words() * 4));
-  HIP_TRY(hipMemset(h->sc, 0, sizeof(Scalars)));
+  for (VecSet& V : h->vs)
+    if (V.sc) HIP_TRY(hipMemset(V.sc, 0, sizeof(Scalars)));
   if (o.timing) {
     // events of the per-iteration timing (created here, outside any solve)
     h->events.resize(4 * 512);
@@ -704,32 +735,32 @@ static constexpr unsigned LEVEL1_SPIN_LIMIT = 1u << 22;
 
 // Levels 1 and 2 of Algorithm 1 and the prolongation to level 0:
 // v_r2 = r1 + R_c^T e_c from the restricted residual c_rc.
-static void coarse_correction(msmg_handle* h, const Ctx& c, hipStream_t s) {
+static void coarse_correction(msmg_handle* h, const Ctx& c, VecSet& V, hipStream_t s) {
   if (h->l1_blocks > 0) {
     // every coarse step in one grid-synchronised launch; c_x0 ends as e_c
-    if (launch_level1(c, h->l1_blocks, (const double*)h->c_rc, (double*)h->c_x0, (double*)h->c_t, h->rcc,
+    if (launch_level1(c, h->l1_blocks, (const double*)V.c_rc, (double*)V.c_x0, (double*)V.c_t, V.rcc,
                       h->l1_bar, LEVEL1_SPIN_LIMIT, s) == hipSuccess) {
-      launch_prolong(c, h->v_r1, h->c_x0, nullptr, h->v_r2, s);
+      launch_prolong(c, V.v_r1, V.c_x0, nullptr, V.v_r2, s);
       return;
     }
     // the launch failed: one launch per step from now on
     (void)hipGetLastError();
     h->l1_blocks = 0;
   }
-  launch_gs_sweep(c, h->c_rc, h->c_x0, true, s);                    // rc0 = S_c^-1 rc
-  launch_ac_residual(c, h->c_rc, h->c_x0, h->c_t, s);               // rc - A_c rc0
-  launch_cc_restrict(c, h->c_t, h->rcc, s);                         // rcc = R_cc (...)
-  launch_acc_solve(c, h->rcc, h->ecc, s);                           // ecc = A_cc^-1 rcc
-  launch_cc_prolong(c, h->c_x0, h->ecc, h->c_x1, s);                // rc1 = rc0 + R_cc^T ecc
-  launch_ac_residual(c, h->c_rc, h->c_x1, h->c_t, s);               // rc - A_c rc1
-  launch_gs_sweep(c, h->c_t, h->c_d, false, s);                     // S_c^-T (...)
-  launch_prolong(c, h->v_r1, h->c_x1, h->c_d, h->v_r2, s);          // r2 = r1 + R_c^T ec (FP64)
+  launch_gs_sweep(c, V.c_rc, V.c_x0, true, s);                    // rc0 = S_c^-1 rc
+  launch_ac_residual(c, V.c_rc, V.c_x0, V.c_t, s);               // rc - A_c rc0
+  launch_cc_restrict(c, V.c_t, V.rcc, s);                         // rcc = R_cc (...)
+  launch_acc_solve(c, V.rcc, V.ecc, s);                           // ecc = A_cc^-1 rcc
+  launch_cc_prolong(c, V.c_x0, V.ecc, V.c_x1, s);                // rc1 = rc0 + R_cc^T ecc
+  launch_ac_residual(c, V.c_rc, V.c_x1, V.c_t, s);               // rc - A_c rc1
+  launch_gs_sweep(c, V.c_t, V.c_d, false, s);                     // S_c^-T (...)
+  launch_prolong(c, V.v_r1, V.c_x1, V.c_d, V.v_r2, s);          // r2 = r1 + R_c^T ec (FP64)
 }
 
 // One preconditioner application r (FP64) -> z (FP64) with the PCG reduction
 // mode (0 init, 1 iteration, 2 none).
-static void precondition(msmg_handle* h, const Ctx& c, const double* r, double* z, const double* q, int mode,
-                         hipStream_t s) {
+static void precondition(msmg_handle* h, const Ctx& c, VecSet& V, const double* r, double* z, const double* q,
+                         int mode, hipStream_t s) {
   const bool v64 = (h->v_dt == DT_F64);
   const bool fused = smooth_output_fused(c);
   if (!h->mg) {
@@ -737,29 +768,29 @@ static void precondition(msmg_handle* h, const Ctx& c, const double* r, double* 
       launch_smooth_output(c, r, true, nullptr, z, r, q, mode, s);
       return;
     }
-    launch_smooth(c, r, true, h->v_r1, s);
-    launch_vc_output(c, h->v_r1, v64, nullptr, z, r, q, mode, s);
+    launch_smooth(c, r, true, V.v_r1, s);
+    launch_vc_output(c, V.v_r1, v64, nullptr, z, r, q, mode, s);
     return;
   }
-  launch_smooth(c, r, true, h->v_r1, s);                            // r1 = S^-1 r0
-  if (h->rpart) {
-    launch_vresidual_restrict(c, r, h->v_r1, (double*)h->c_rc, s);  // rc = R_c (r0 - A r1)
+  launch_smooth(c, r, true, V.v_r1, s);                            // r1 = S^-1 r0
+  if (V.rpart) {
+    launch_vresidual_restrict(c, r, V.v_r1, (double*)V.c_rc, s);  // rc = R_c (r0 - A r1)
   } else {
-    launch_vresidual(c, r, true, h->v_r1, v64, h->v_res, s);        // r0 - A r1
-    launch_restrict(c, h->v_res, h->c_rc, s);                       // rc = R_c (r0 - A r1)
+    launch_vresidual(c, r, true, V.v_r1, v64, V.v_res, s);        // r0 - A r1
+    launch_restrict(c, V.v_res, V.c_rc, s);                       // rc = R_c (r0 - A r1)
   }
-  coarse_correction(h, c, s);                                       // r2 = r1 + R_c^T e_c
-  launch_vresidual(c, r, true, h->v_r2, true, h->v_res, s);         // r0 - A r2
+  coarse_correction(h, c, V, s);                                       // r2 = r1 + R_c^T e_c
+  launch_vresidual(c, r, true, V.v_r2, true, V.v_res, s);         // r0 - A r2
   if (fused) {
-    launch_smooth_output(c, h->v_res, false, (const double*)h->v_r2, z, r, q, mode, s);  // y = r2 + S^-T (...)
+    launch_smooth_output(c, V.v_res, false, (const double*)V.v_r2, z, r, q, mode, s);  // y = r2 + S^-T (...)
     return;
   }
-  launch_smooth(c, h->v_res, false, h->v_r1, s);                    // S^-T (...)
-  launch_vc_output(c, h->v_r2, true, h->v_r1, z, r, q, mode, s);    // y = r2 + ...
+  launch_smooth(c, V.v_res, false, V.v_r1, s);                    // S^-T (...)
+  launch_vc_output(c, V.v_r2, true, V.v_r1, z, r, q, mode, s);    // y = r2 + ...
 }
 
-static int read_scalars(msmg_handle* h, hipStream_t s) {
-  HIP_TRY(hipMemcpyAsync(h->sc_host, h->sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+static int read_scalars(VecSet& V, hipStream_t s) {
+  HIP_TRY(hipMemcpyAsync(V.sc_host, V.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   return MSMG_OK;
 }
@@ -770,13 +801,13 @@ extern "C" int msmg_precondition(msmg_handle* h, const double* r, double* z, hip
   Ctx c = make_ctx(h);
   if (h->opt.lean_memory) h->basis_live = false;
   launch_sc_reset(c, 0, 0, s);
-  launch_zero_fixed_copy(c, r, h->r, s);
-  precondition(h, c, h->r, z, nullptr, 2, s);
+  launch_zero_fixed_copy(c, r, h->vs[0].r, s);
+  precondition(h, c, h->vs[0], h->vs[0].r, z, nullptr, 2, s);
   HIP_TRY(hipGetLastError());
   if (h->l1_blocks > 0) {
     // the grid-synchronised coarse-level kernel reports a failed wait in the scalars
-    TRY(read_scalars(h, s));
-    if (h->sc_host->status == ST_SYNC_TIMEOUT)
+    TRY(read_scalars(h->vs[0], s));
+    if (h->vs[0].sc_host->status == ST_SYNC_TIMEOUT)
       return fail(MSMG_ETIMEOUT, "a grid-wide wait of the coarse-level kernel exceeded its limit");
   }
   return MSMG_OK;
@@ -790,8 +821,8 @@ extern "C" int msmg_apply(msmg_handle* h, const double* x, double* y, hipStream_
   // the march stages x with zero fixed entries (handle scratch q, which the
   // lean layout shares with the exported basis)
   if (h->opt.lean_memory) h->basis_live = false;
-  launch_zero_fixed_copy(c, x, h->q, s);
-  launch_apply(c, h->q, y, 2, s, x);
+  launch_zero_fixed_copy(c, x, h->vs[0].q, s);
+  launch_apply(c, h->vs[0].q, y, 2, s, x);
   HIP_TRY(hipGetLastError());
   return MSMG_OK;
 }
@@ -884,31 +915,32 @@ static int solve_impl(msmg_handle* h, const double* f, double* T, double* T_lo, 
   if (f == T || (T_lo && (T_lo == T || T_lo == f))) return fail(MSMG_EINVAL, "f, T and T_lo must not alias");
   const double t0 = now_ms();
   Ctx c = make_ctx(h);
+  VecSet& V = h->vs[0];
   if (h->opt.lean_memory) h->basis_live = false;
   const double* lift = (h->has_tfix && !homogeneous) ? h->tfix : nullptr;
   double* x = T;
   // b = f - A t_fix on free rows (0 on fixed rows)
-  if (lift) launch_residual(c, f, lift, nullptr, h->b, false, s);
-  else launch_zero_fixed_copy(c, f, h->b, s);
+  if (lift) launch_residual(c, f, lift, nullptr, V.b, false, s);
+  else launch_zero_fixed_copy(c, f, V.b, s);
   // x: free entries of the guess (or 0), fixed entries 0 during the iteration
   if (use_x0) launch_zero_fixed_copy(c, T, x, s);
   else launch_fill(c, x, 0.0, s);
-  launch_fill(c, h->p, 0.0, s);
+  launch_fill(c, V.p, 0.0, s);
   launch_sc_reset(c, 1, maxit, s);
-  launch_norm2(c, h->b, 0, rtol * rtol, s);  // bb, tol2
-  HIP_TRY(hipMemsetAsync(h->xlo, 0, sizeof(float) * size_t(c.g.nn), s));
-  if (use_x0) launch_residual(c, h->b, x, nullptr, h->r, false, s);
-  else launch_copy(c, h->b, h->r, s);
-  launch_norm2(c, h->r, 1, 0.0, s);  // rr
-  TRY(read_scalars(h, s));
+  launch_norm2(c, V.b, 0, rtol * rtol, s);  // bb, tol2
+  HIP_TRY(hipMemsetAsync(V.xlo, 0, sizeof(float) * size_t(c.g.nn), s));
+  if (use_x0) launch_residual(c, V.b, x, nullptr, V.r, false, s);
+  else launch_copy(c, V.b, V.r, s);
+  launch_norm2(c, V.r, 1, 0.0, s);  // rr
+  TRY(read_scalars(V, s));
   int restarts = 0;
   int status = MSMG_OK;
   double rel = 0.0;
-  const double bb = h->sc_host->bb;
+  const double bb = V.sc_host->bb;
   if (!(bb > 0.0)) {
     // zero right-hand side: the solution is the lift alone
     launch_fill(c, x, 0.0, s);
-    launch_finish_solution_dd(c, T, h->xlo, T_lo, lift, s);
+    launch_finish_solution_dd(c, T, V.xlo, T_lo, lift, s);
     HIP_TRY(hipStreamSynchronize(s));
     if (info) {
       std::memset(info, 0, sizeof(*info));
@@ -920,13 +952,13 @@ static int solve_impl(msmg_handle* h, const double* f, double* T, double* T_lo, 
     }
     return MSMG_OK;
   }
-  bool converged = h->sc_host->rr <= h->sc_host->tol2;
-  if (converged) rel = std::sqrt(h->sc_host->rr / bb);
+  bool converged = V.sc_host->rr <= V.sc_host->tol2;
+  if (converged) rel = std::sqrt(V.sc_host->rr / bb);
   int iters = 0;
   int timed_total = 0;
   if (!converged && maxit > 0) {
-    precondition(h, c, h->r, h->z, nullptr, 0, s);
-    launch_update_px(c, x, h->xlo, h->p, h->z, s);
+    precondition(h, c, V, V.r, V.z, nullptr, 0, s);
+    launch_update_px(c, x, V.xlo, V.p, V.z, s);
     const int batch = h->opt.check_interval;
     const int max_timed = int(h->events.size() / 4);
     int launched = 0;
@@ -934,60 +966,60 @@ static int solve_impl(msmg_handle* h, const double* f, double* T, double* T_lo, 
       for (int it = 0; it < batch; ++it) {
         const bool tm = h->opt.timing && launched < max_timed;
         if (tm) HIP_TRY(hipEventRecord(h->events[4 * launched + 0], s));
-        launch_apply(c, h->p, h->q, 1, s);
+        launch_apply(c, V.p, V.q, 1, s);
         if (tm) HIP_TRY(hipEventRecord(h->events[4 * launched + 1], s));
-        launch_update_r(c, h->r, h->q, s);
+        launch_update_r(c, V.r, V.q, s);
         if (tm) HIP_TRY(hipEventRecord(h->events[4 * launched + 2], s));
-        precondition(h, c, h->r, h->z, h->q, 1, s);
+        precondition(h, c, V, V.r, V.z, V.q, 1, s);
         if (tm) HIP_TRY(hipEventRecord(h->events[4 * launched + 3], s));
-        launch_update_px(c, x, h->xlo, h->p, h->z, s);  // also x += alpha p of this step
+        launch_update_px(c, x, V.xlo, V.p, V.z, s);  // also x += alpha p of this step
         ++launched;
       }
       timed_total = std::min(launched, max_timed);
-      TRY(read_scalars(h, s));
-      const Scalars& S = *h->sc_host;
+      TRY(read_scalars(V, s));
+      const Scalars& S = *V.sc_host;
       if (!S.done) continue;
       // the step that stopped the iteration skipped the direction update:
       // add its alpha p to the iterate before x is read
-      launch_update_x_pending(c, x, h->xlo, h->p, s);
+      launch_update_x_pending(c, x, V.xlo, V.p, s);
       iters = S.iters;
       if (S.status == ST_CONV_RECURSIVE) {
         // confirm with the true residual
-        launch_residual(c, h->b, x, h->xlo, h->q, true, s);
-        TRY(read_scalars(h, s));
-        const double trr = h->sc_host->true_rr;
-        if (trr <= h->sc_host->tol2) {
+        launch_residual(c, V.b, x, V.xlo, V.q, true, s);
+        TRY(read_scalars(V, s));
+        const double trr = V.sc_host->true_rr;
+        if (trr <= V.sc_host->tol2) {
           converged = true;
           rel = std::sqrt(trr / bb);
           break;
         }
-        if (h->sc_host->iters >= maxit || restarts >= 16) {
+        if (V.sc_host->iters >= maxit || restarts >= 16) {
           status = MSMG_MAXIT;
           rel = std::sqrt(trr / bb);
           break;
         }
         // residual replacement and restart of the search direction
         ++restarts;
-        launch_copy(c, h->q, h->r, s);
+        launch_copy(c, V.q, V.r, s);
         launch_sc_reset(c, 0, 0, s);
-        launch_fill(c, h->p, 0.0, s);
-        precondition(h, c, h->r, h->z, nullptr, 0, s);
-        launch_update_px(c, x, h->xlo, h->p, h->z, s);
+        launch_fill(c, V.p, 0.0, s);
+        precondition(h, c, V, V.r, V.z, nullptr, 0, s);
+        launch_update_px(c, x, V.xlo, V.p, V.z, s);
         continue;
       }
       if (S.status == ST_SYNC_TIMEOUT)
         return fail(MSMG_ETIMEOUT, "a grid-wide wait of the coarse-level kernel exceeded its limit");
       status = (S.status == ST_MAXIT) ? MSMG_MAXIT : (S.status == ST_BREAKDOWN ? MSMG_BREAKDOWN : MSMG_NONFINITE);
-      launch_residual(c, h->b, x, h->xlo, h->q, true, s);
-      TRY(read_scalars(h, s));
-      rel = std::sqrt(h->sc_host->true_rr / bb);
+      launch_residual(c, V.b, x, V.xlo, V.q, true, s);
+      TRY(read_scalars(V, s));
+      rel = std::sqrt(V.sc_host->true_rr / bb);
       break;
     }
   } else if (!converged) {
     status = MSMG_MAXIT;
-    rel = std::sqrt(h->sc_host->rr / bb);
+    rel = std::sqrt(V.sc_host->rr / bb);
   }
-  launch_finish_solution_dd(c, T, h->xlo, T_lo, lift, s);
+  launch_finish_solution_dd(c, T, V.xlo, T_lo, lift, s);
   HIP_TRY(hipStreamSynchronize(s));
   HIP_TRY(hipGetLastError());
   if (info) {
@@ -1021,6 +1053,212 @@ static int solve_impl(msmg_handle* h, const double* f, double* T, double* T_lo, 
   }
   if (status != MSMG_OK) g_last_error = "solve stopped before convergence";
   return status;
+}
+
+// Levels 0-2 of Algorithm 1 for the two right-hand sides of a batched pair:
+// every kernel that reads the operator's coefficients (the conductivity copy,
+// the Jacobi diagonal, the basis R_c, A_c, R_cc, A_cc^-1) runs once for both
+// sides; a side whose solve has stopped skips its share.
+static void precondition_pair(msmg_handle* h, const Ctx& c0, const Ctx& c1, VecSet& V0, VecSet& V1,
+                              const double* q0, const double* q1, int mode, hipStream_t s) {
+  launch_smooth_pair(c0, c1, V0.r, V1.r, V0.v_r1, V1.v_r1, s);                         // r1 = S^-1 r0
+  if (V0.rpart && V1.rpart) {
+    launch_vresidual_restrict_pair(c0, c1, V0.r, V1.r, V0.v_r1, V1.v_r1, (double*)V0.c_rc, (double*)V1.c_rc, s);
+  } else {
+    const bool v64 = (h->v_dt == DT_F64);
+    launch_vresidual(c0, V0.r, true, V0.v_r1, v64, V0.v_res, s);
+    launch_restrict(c0, V0.v_res, V0.c_rc, s);
+    launch_vresidual(c1, V1.r, true, V1.v_r1, v64, V1.v_res, s);
+    launch_restrict(c1, V1.v_res, V1.c_rc, s);
+  }
+  bool coarse_done = false;
+  if (h->l1_blocks > 0) {
+    if (launch_level1_pair(c0, c1, h->l1_blocks, (const double*)V0.c_rc, (const double*)V1.c_rc, (double*)V0.c_x0,
+                           (double*)V1.c_x0, (double*)V0.c_t, (double*)V1.c_t, V0.rcc, V1.rcc, h->l1_bar,
+                           LEVEL1_SPIN_LIMIT, s) == hipSuccess) {
+      launch_prolong_pair(c0, c1, V0.v_r1, V1.v_r1, V0.c_x0, V1.c_x0, V0.v_r2, V1.v_r2, s);
+      coarse_done = true;
+    } else {
+      (void)hipGetLastError();
+      h->l1_blocks = 0;
+    }
+  }
+  if (!coarse_done) {
+    coarse_correction(h, c0, V0, s);
+    coarse_correction(h, c1, V1, s);
+  }
+  launch_vresidual_pair(c0, c1, V0.r, V1.r, (const double*)V0.v_r2, (const double*)V1.v_r2, V0.v_res, V1.v_res, s);
+  launch_smooth_output_pair(c0, c1, V0.v_res, V1.v_res, (const double*)V0.v_r2, (const double*)V1.v_r2, V0.z, V1.z,
+                            V0.r, V1.r, q0, q1, mode, s);
+}
+
+// One side of a batched pair: its system, iterate and outcome.
+struct PairSide {
+  VecSet* V;
+  Ctx c;
+  const double* f;
+  double* x;
+  double* x_lo;
+  const double* lift;
+  double bb = 0.0;
+  bool finished = false;
+  int status = MSMG_OK, iters = 0, restarts = 0;
+  double rel = 0.0;
+};
+
+// The state solve A T = f (with the set-up's fixed values) and the adjoint
+// solve A_FF lambda = g (zero fixed values) of one set-up, as two PCG
+// recurrences advanced together: each iteration's operator apply and
+// preconditioner run once for both (precondition_pair); the vector updates,
+// scalars, stopping tests and residual replacements stay per side.
+static int solve_pair_impl(msmg_handle* h, const double* f, double* T, double* T_lo, const double* g, double* lam,
+                           double* lam_lo, double rtol, int maxit, msmg_info* info_T, msmg_info* info_lam,
+                           hipStream_t s) {
+  if (!h || !f || !T || !g || !lam) return fail(MSMG_EINVAL, "NULL argument");
+  if (!h->setup_done) return fail(MSMG_ESTATE, "msmg_setup has not completed");
+  if (!h->vs[1].sc) return fail(MSMG_ESTATE, "the handle was created without options.pair_rhs");
+  if (!(rtol >= 0.0) || maxit < 1) return fail(MSMG_EINVAL, "need rtol >= 0 and maxit >= 1");
+  {
+    const void* ps[] = {f, T, T_lo, g, lam, lam_lo};
+    for (int i = 0; i < 6; ++i)
+      for (int j = i + 1; j < 6; ++j)
+        if (ps[i] && ps[i] == ps[j]) return fail(MSMG_EINVAL, "f, T, T_lo, g, lambda and lambda_lo must not alias");
+  }
+  const double t0 = now_ms();
+  if (h->opt.lean_memory) h->basis_live = false;
+  PairSide S[2];
+  S[0].V = &h->vs[0];
+  S[0].c = make_ctx(h, 0);
+  S[0].f = f;
+  S[0].x = T;
+  S[0].x_lo = T_lo;
+  S[0].lift = h->has_tfix ? h->tfix : nullptr;
+  S[1].V = &h->vs[1];
+  S[1].c = make_ctx(h, 1);
+  S[1].f = g;
+  S[1].x = lam;
+  S[1].x_lo = lam_lo;
+  S[1].lift = nullptr;
+  bool trivial = false;
+  for (PairSide& P : S) {
+    VecSet& V = *P.V;
+    const Ctx& c = P.c;
+    if (P.lift) launch_residual(c, P.f, P.lift, nullptr, V.b, false, s);
+    else launch_zero_fixed_copy(c, P.f, V.b, s);
+    launch_fill(c, P.x, 0.0, s);
+    launch_fill(c, V.p, 0.0, s);
+    launch_sc_reset(c, 1, maxit, s);
+    launch_norm2(c, V.b, 0, rtol * rtol, s);
+    HIP_TRY(hipMemsetAsync(V.xlo, 0, sizeof(float) * size_t(c.g.nn), s));
+    launch_copy(c, V.b, V.r, s);
+    launch_norm2(c, V.r, 1, 0.0, s);
+    TRY(read_scalars(V, s));
+    P.bb = V.sc_host->bb;
+    if (!(P.bb > 0.0) || V.sc_host->rr <= V.sc_host->tol2) trivial = true;
+  }
+  if (trivial) {
+    // a zero or already converged right-hand side: two ordinary solves
+    int r0 = solve_impl(h, f, T, T_lo, 0, rtol, maxit, info_T, s, false);
+    if (r0 < 0) return r0;
+    int r1 = solve_impl(h, g, lam, lam_lo, 0, rtol, maxit, info_lam, s, true);
+    if (r1 < 0) return r1;
+    return r0 != MSMG_OK ? r0 : r1;
+  }
+  precondition_pair(h, S[0].c, S[1].c, *S[0].V, *S[1].V, nullptr, nullptr, 0, s);
+  for (PairSide& P : S) launch_update_px(P.c, P.x, P.V->xlo, P.V->p, P.V->z, s);
+  const int batch = h->opt.check_interval;
+  while (!(S[0].finished && S[1].finished)) {
+    // once one side has stopped, the other runs the single-side kernels (the
+    // pair kernels would still stage the stopped side's share in places)
+    PairSide* alone = S[0].finished ? &S[1] : (S[1].finished ? &S[0] : nullptr);
+    for (int it = 0; it < batch; ++it) {
+      if (alone) {
+        VecSet& V = *alone->V;
+        launch_apply(alone->c, V.p, V.q, 1, s);
+        launch_update_r(alone->c, V.r, V.q, s);
+        precondition(h, alone->c, V, V.r, V.z, V.q, 1, s);
+        launch_update_px(alone->c, alone->x, V.xlo, V.p, V.z, s);
+        continue;
+      }
+      launch_apply_pair(S[0].c, S[1].c, S[0].V->p, S[1].V->p, S[0].V->q, S[1].V->q, s);
+      for (PairSide& P : S) launch_update_r(P.c, P.V->r, P.V->q, s);
+      precondition_pair(h, S[0].c, S[1].c, *S[0].V, *S[1].V, S[0].V->q, S[1].V->q, 1, s);
+      for (PairSide& P : S) launch_update_px(P.c, P.x, P.V->xlo, P.V->p, P.V->z, s);
+    }
+    for (PairSide& P : S) {
+      if (P.finished) continue;
+      VecSet& V = *P.V;
+      const Ctx& c = P.c;
+      TRY(read_scalars(V, s));
+      const Scalars Sc = *V.sc_host;
+      if (!Sc.done) continue;
+      launch_update_x_pending(c, P.x, V.xlo, V.p, s);
+      P.iters = Sc.iters;
+      if (Sc.status == ST_SYNC_TIMEOUT)
+        return fail(MSMG_ETIMEOUT, "a grid-wide wait of the coarse-level kernel exceeded its limit");
+      if (Sc.status == ST_CONV_RECURSIVE) {
+        launch_residual(c, V.b, P.x, V.xlo, V.q, true, s);
+        TRY(read_scalars(V, s));
+        const double trr = V.sc_host->true_rr;
+        if (trr <= V.sc_host->tol2) {
+          P.finished = true;
+          P.rel = std::sqrt(trr / P.bb);
+          continue;
+        }
+        if (V.sc_host->iters >= maxit || P.restarts >= 16) {
+          P.finished = true;
+          P.status = MSMG_MAXIT;
+          P.rel = std::sqrt(trr / P.bb);
+          continue;
+        }
+        // residual replacement and restart of this side's direction (its
+        // first preconditioner application runs alone); the next batch
+        // takes it up again with the other side
+        ++P.restarts;
+        launch_copy(c, V.q, V.r, s);
+        launch_sc_reset(c, 0, 0, s);
+        launch_fill(c, V.p, 0.0, s);
+        precondition(h, c, V, V.r, V.z, nullptr, 0, s);
+        launch_update_px(c, P.x, V.xlo, V.p, V.z, s);
+        continue;
+      }
+      P.finished = true;
+      P.status = (Sc.status == ST_MAXIT) ? MSMG_MAXIT : (Sc.status == ST_BREAKDOWN ? MSMG_BREAKDOWN : MSMG_NONFINITE);
+      launch_residual(c, V.b, P.x, V.xlo, V.q, true, s);
+      TRY(read_scalars(V, s));
+      P.rel = std::sqrt(V.sc_host->true_rr / P.bb);
+    }
+  }
+  for (PairSide& P : S) launch_finish_solution_dd(P.c, P.x, P.V->xlo, P.x_lo, P.lift, s);
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipGetLastError());
+  const double ms = now_ms() - t0;
+  msmg_info* infos[2] = {info_T, info_lam};
+  for (int k = 0; k < 2; ++k) {
+    if (!infos[k]) continue;
+    msmg_info* in = infos[k];
+    std::memset(in, 0, sizeof(*in));
+    in->status = S[k].status;
+    in->iterations = S[k].iters;
+    in->restarts = S[k].restarts;
+    in->rel_res = S[k].rel;
+    in->solve_ms = ms;
+    in->setup_ms = h->setup_ms;
+    in->n_c = h->n_c;
+    in->n_cc = h->n_cc;
+    in->eig_unconverged = h->eig_unconverged;
+    in->cc_unconverged = h->cc_unconverged;
+    in->eig_ties = h->eig_ties;
+  }
+  const int st = S[0].status != MSMG_OK ? S[0].status : S[1].status;
+  if (st != MSMG_OK) g_last_error = "a solve of the pair stopped before convergence";
+  return st;
+}
+
+extern "C" int msmg_solve_pair(msmg_handle* h, const double* f, double* T, double* T_lo, const double* g,
+                               double* lambda, double* lambda_lo, double rtol, int maxit, msmg_info* info_T,
+                               msmg_info* info_lambda, hipStream_t s) {
+  return solve_pair_impl(h, f, T, T_lo, g, lambda, lambda_lo, rtol, maxit, info_T, info_lambda, s);
 }
 
 extern "C" int msmg_solve(msmg_handle* h, const double* f, double* T, double* T_lo, int use_x0, double rtol,
@@ -1083,7 +1321,7 @@ extern "C" int msmg_oc_update(msmg_handle* h, const double* x, const double* dc,
     return fail(MSMG_EINVAL, "need move > 0, eta > 0, 0 <= x_min < 1");
   const long long ne = h->g.ne;
   launch_oc_update(ne, x, dc, dv, volume_fraction * double(ne), move, eta, x_min, x_new, lambda, h->oc_state,
-                   h->partials, h->counter, 8, s);
+                   h->vs[0].partials, h->vs[0].counter, 8, s);
   HIP_TRY(hipGetLastError());
   return MSMG_OK;
 }
@@ -1099,7 +1337,7 @@ extern "C" int msmg_mma_update(msmg_handle* h, int iter, const double* x, const 
   if (!(volume_fraction > 0.0 && volume_fraction <= 1.0)) return fail(MSMG_EINVAL, "volume fraction in (0, 1]");
   if (!(move > 0.0) || !(x_min >= 0.0 && x_min < 1.0)) return fail(MSMG_EINVAL, "need move > 0 and 0 <= x_min < 1");
   launch_mma_update(iter, h->g.ne, x, xold1, xold2, low, upp, df0, dv, volume_fraction, move, x_min, 1.0, x_new,
-                    lambda, h->oc_state, h->partials, h->counter, 8, s);
+                    lambda, h->oc_state, h->vs[0].partials, h->vs[0].counter, 8, s);
   HIP_TRY(hipGetLastError());
   return MSMG_OK;
 }

@@ -132,6 +132,29 @@ class Solver:
         out["code"] = code
         return lam, out
 
+    def solve_pair(self, f, g, rtol=1e-8, maxit=1000, T=None, lam=None, T_lo=None, lam_lo=None):
+        """State solve A T = f and adjoint solve A_FF lambda = g together (one
+        set-up, shared coefficient reads); needs Solver(..., pair_rhs=1).
+        Returns (T, lambda, info_T, info_lambda)."""
+        f = _need(f, "f", torch.float64, self.nnodes, self.device)
+        g = _need(g, "g", torch.float64, self.nnodes, self.device)
+        T = torch.empty_like(f) if T is None else _need(T, "T", torch.float64, self.nnodes, self.device)
+        lam = torch.empty_like(g) if lam is None else _need(lam, "lam", torch.float64, self.nnodes, self.device)
+        for t, nm in ((T_lo, "T_lo"), (lam_lo, "lam_lo")):
+            if t is not None:
+                _need(t, nm, torch.float64, self.nnodes, self.device)
+        i1, i2 = L.Info(), L.Info()
+        code = L.check(L.lib().msmg_solve_pair(self._h, _ptr(f), _ptr(T), _ptr(T_lo) if T_lo is not None else None,
+                                               _ptr(g), _ptr(lam), _ptr(lam_lo) if lam_lo is not None else None,
+                                               float(rtol), int(maxit), ctypes.byref(i1), ctypes.byref(i2),
+                                               _stream()), "msmg_solve_pair")
+        outs = []
+        for inf in (i1, i2):
+            o = SolveInfo({k: getattr(inf, k) for k, _ in L.Info._fields_})
+            o["code"] = code
+            outs.append(o)
+        return T, lam, outs[0], outs[1]
+
     def oc_update(self, x, dc, dv, volume_fraction, move=0.2, eta=0.5, x_min=1e-3, out=None):
         """Optimality-criteria update with the volume multiplier found on the GPU;
         returns (x_new, lambda) with lambda a 0-d device tensor."""

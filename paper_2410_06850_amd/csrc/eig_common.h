@@ -127,7 +127,7 @@ MSMG_DEV void wave_jacobi8(const double* A, double* Vs, double* ev, int max_swee
     s = t * c;
   };
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    for (int r = 0; r < 7; ++r) {
+      for (int r = 0; r < 7; ++r) {
       // the round's four disjoint rotations: lane e computes the one of its
       // column pair; the row pass takes the rotation of its row pair from lane i
       // (row 0, column i), whose column pair is that row pair
@@ -201,15 +201,26 @@ MSMG_DEV bool wave_cholinv8(const double* G, double* C) {
 // ev[k] are the eigenvalues in ascending order and column k of Vs holds the
 // matching eigenvector (Vs = V with permuted columns).  Uses threads
 // tid < m*m for element work; all threads of the block must call.
-// LDS: A, V, B, Vs: m*m; ev: m; perm: m ints; red: >= 2 * nwaves doubles.
+// LDS: A, V, B, Vs: m*m; ev: m; perm: m ints; red: >= 2 * nwaves doubles;
+// cs: 2 m doubles (the round's rotations, computed once per index).
 MSMG_DEV void block_jacobi(double* A, double* V, double* B, double* Vs, double* ev, int* perm, int m,
-                           double* red, int max_sweeps = 16) {
+                           double* red, double* cs, int max_sweeps = 16) {
   const int tid = block_tid(), nthr = block_nthr();
   const int mm = m + (m & 1);
   for (int e = tid; e < m * m; e += nthr) V[e] = (e / m == e % m) ? 1.0 : 0.0;
   __syncthreads();
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     for (int r = 0; r < mm - 1; ++r) {
+      // the rotation of each index's pair (identity for the odd-size dummy);
+      // both members of a pair evaluate it from the same entries
+      for (int j = tid; j < m; j += nthr) {
+        const int jp = rr_partner(r, j, mm);
+        double c = 1.0, s = 0.0;
+        if (jp < m) jacobi_rot(A, m, min(j, jp), max(j, jp), c, s);
+        cs[2 * j] = c;
+        cs[2 * j + 1] = s;
+      }
+      __syncthreads();
       double vnew[4];
       int cnt = 0;
       for (int e = tid; e < m * m; e += nthr, ++cnt) {
@@ -220,9 +231,8 @@ MSMG_DEV void block_jacobi(double* A, double* V, double* B, double* Vs, double* 
           bv = A[e];
           vv = V[e];
         } else {
-          double c, s;
+          const double c = cs[2 * j], s = cs[2 * j + 1];
           const int p = min(j, jp), q = max(j, jp);
-          jacobi_rot(A, m, p, q, c, s);
           if (j == p) {
             bv = c * A[i * m + p] - s * A[i * m + q];
             vv = c * V[i * m + p] - s * V[i * m + q];
@@ -244,9 +254,8 @@ MSMG_DEV void block_jacobi(double* A, double* V, double* B, double* Vs, double* 
         if (ip >= m) {
           av = B[e];
         } else {
-          double c, s;
+          const double c = cs[2 * i], s = cs[2 * i + 1];
           const int p = min(i, ip), q = max(i, ip);
-          jacobi_rot(A, m, p, q, c, s);
           av = (i == p) ? (c * B[p * m + j] - s * B[q * m + j]) : (s * B[p * m + j] + c * B[q * m + j]);
         }
         vnew[cnt < 4 ? cnt : 3] = av;

@@ -114,7 +114,7 @@ struct msmg_handle {
   bool setup_done = false;
   double setup_ms = 0.0;
   int eig_unconverged = 0, cc_unconverged = 0, eig_ties = 0;
-  TuneChoice tune{};
+  TuneChoice tune[2]{};  // level-1 launch shapes per cell class
   std::vector<void*> allocs;
   std::vector<hipEvent_t> events;  // timing mode: 4 per timed iteration
 };
@@ -711,7 +711,7 @@ extern "C" int msmg_setup(msmg_handle* h, const void* rho, msmg_dtype rho_dtype,
     a.opt = &h->opt;
     a.warm = (h->opt.eig_warm_start && h->has_basis) ? 1 : 0;
     h->has_basis = false;
-    a.tune = &h->tune;
+    a.tune = h->tune;
     SetupReport rep{};
     const int r = run_setup(c, a, &h->scratch, &rep, s);
     if (r != MSMG_OK) return fail(r, std::string("set-up failed: ") + rep.msg);

@@ -20,6 +20,7 @@ inline size_t gj_workspace_doubles(int n, int batch) {
 // Device memory for the dense shifted coarse-coarse matrices: the cc cells are
 // solved in groups whose matrices fit in this many bytes.
 constexpr size_t CC_GROUP_BYTES = size_t(24) << 30;
+constexpr int CC_GRAM_SLICES = 8;  // workgroups per cc cell of the Gram products
 int gj_inverse(int n, int batch, double* A, double* work, hipStream_t s);
 
 // Launch shape of the level-1 eigensolver chosen by the tuner.
@@ -38,12 +39,15 @@ struct SetupScratch {
   double* Yp = nullptr;  // previous block (filter recurrence)
   double* Z = nullptr;   // operator image / next block
   double* small = nullptr;  // per cc cell: 3 matrices of mcc x mcc
+  double* gpart = nullptr;  // per cc cell of a group: CC_GRAM_SLICES partial Gram matrices
   double* ccpar = nullptr;  // per cc cell filter parameters
-  int* ccflag = nullptr;    // per cc cell: converged iteration or -1
+  int* ccflag = nullptr;    // per cc cell: converged iteration or -1; then per cc cell: Cholesky failed
   double* acc_copy = nullptr;  // A_cc before inversion (diagnostics)
   double* gj = nullptr;        // Gauss-Jordan panels (batched)
   double* Gd = nullptr;        // dense shifted coarse-coarse matrices, then their inverses
   unsigned* work = nullptr;    // work-queue counter
+  int* cells = nullptr;        // level-1 cells by shape class: the regular (H^3-node) cells, then the rest
+  int n_regular = -1;          // regular cells in `cells` (-1: list not built yet)
   int mcc = 0;
   int cc_group = 0;            // cc cells whose dense shifted matrices are held at once
 };
@@ -76,7 +80,7 @@ struct SetupArgs {
   const int* dof_loc;
   const msmg_options* opt;
   int warm;  // level-1 solver starts from the basis left in Rc64 by the previous set-up
-  TuneChoice* tune;
+  TuneChoice* tune;  // per level-1 cell class: [0] regular cells, [1] the rest
 };
 
 struct SetupReport {
@@ -91,9 +95,11 @@ int setup_scratch_alloc(const Geo& g, const Hier& h, int max_cc_dofs, int n_cc, 
 
 int run_setup(const Ctx& c, const SetupArgs& a, SetupScratch* s, SetupReport* rep, hipStream_t st);
 
-// level-1 eigensolver launch (used by the tuner and the set-up)
+// level-1 eigensolver launch over cells[first .. first + count) of the class
+// list, with LDS for cells of up to nl nodes (used by the tuner and the set-up)
 int launch_local_eigen(const Ctx& c, const SetupArgs& a, SetupScratch* s, int bs, int m, int degree,
-                       int blocks, hipStream_t st, int ncells = 0);
+                       int blocks, hipStream_t st, int first, int count, int nl);
+size_t local_lds_bytes(int M, int nl);
 
 // utilities implemented with the fine kernels
 void launch_fill(const Ctx& c, double* x, double v, hipStream_t s);

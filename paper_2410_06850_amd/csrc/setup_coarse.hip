@@ -56,6 +56,22 @@ __global__ void k_galerkin(Geo g, Stencil st, Hier h, int CX, const void* rho, i
       if (oy < 0) ye = min(ye, cell_begin(t.cy, H) + 1);
       if (oz > 0) zs = max(zs, cell_end(t.cz, H, h.ncz, g.nnz) - 1);
       if (oz < 0) ze = min(ze, cell_begin(t.cz, H) + 1);
+      // node ranges of the neighbour cell (its nodes are the stencil partners
+      // counted), and the cc-cell boundaries an element of this cell's
+      // neighbourhood can straddle: the first node of this cell and of the
+      // next one along each axis, where that node starts a new cc cell
+      const int nbx0 = cell_begin(icx, H), nbx1 = cell_end(icx, H, h.ncx, g.nnx);
+      const int nby0 = cell_begin(icy, H), nby1 = cell_end(icy, H, h.ncy, g.nny);
+      const int nbz0 = cell_begin(icz, H), nbz1 = cell_end(icz, H, h.ncz, g.nnz);
+      auto starts_cc = [&](int c, int nc, int ng) {
+        return c >= 1 && c <= nc - 1 && c % h.sd == 0 && c / h.sd <= ng - 1;
+      };
+      const int sbx0 = starts_cc(t.cx, h.ncx, h.nccx) ? cell_begin(t.cx, H) : -1;
+      const int sbx1 = starts_cc(t.cx + 1, h.ncx, h.nccx) ? cell_begin(t.cx + 1, H) : -1;
+      const int sby0 = starts_cc(t.cy, h.ncy, h.nccy) ? cell_begin(t.cy, H) : -1;
+      const int sby1 = starts_cc(t.cy + 1, h.ncy, h.nccy) ? cell_begin(t.cy + 1, H) : -1;
+      const int sbz0 = starts_cc(t.cz, h.ncz, h.nccz) ? cell_begin(t.cz, H) : -1;
+      const int sbz1 = starts_cc(t.cz + 1, h.ncz, h.nccz) ? cell_begin(t.cz + 1, H) : -1;
       for (int k = zs; k < ze; ++k)
         for (int j = ys; j < ye; ++j)
           for (int i = xs; i < xe; ++i) {
@@ -66,10 +82,11 @@ __global__ void k_galerkin(Geo g, Stencil st, Hier h, int CX, const void* rho, i
               const int ei = i - 1 + (c & 1), ej = j - 1 + ((c >> 1) & 1), ek = k - 1 + ((c >> 2) & 1);
               bool in = ei >= 0 && ei < g.nx && ej >= 0 && ej < g.ny && ek >= 0 && ek < g.nz;
               if (in && drop_cc) {
-                const int gx0 = group_axis(owner_axis(ei, H, h.ncx), h.sd, h.nccx), gx1 = group_axis(owner_axis(ei + 1, H, h.ncx), h.sd, h.nccx);
-                const int gy0 = group_axis(owner_axis(ej, H, h.ncy), h.sd, h.nccy), gy1 = group_axis(owner_axis(ej + 1, H, h.ncy), h.sd, h.nccy);
-                const int gz0 = group_axis(owner_axis(ek, H, h.ncz), h.sd, h.nccz), gz1 = group_axis(owner_axis(ek + 1, H, h.ncz), h.sd, h.nccz);
-                in = (gx0 == gx1) && (gy0 == gy1) && (gz0 == gz1);
+                // the element's upper node starts a new cc cell on some axis
+                const bool sx = (ei + 1 == sbx0) || (ei + 1 == sbx1);
+                const bool sy = (ej + 1 == sby0) || (ej + 1 == sby1);
+                const bool sz = (ek + 1 == sbz0) || (ek + 1 == sbz1);
+                in = !(sx || sy || sz);
               }
               if (in) {
                 const long long e = elem_id(g, ei, ej, ek);
@@ -88,7 +105,7 @@ __global__ void k_galerkin(Geo g, Stencil st, Hier h, int CX, const void* rho, i
             for (int o = 0; o < 27; ++o) {
               const int mx = i + o % 3 - 1, my = j + (o / 3) % 3 - 1, mz = k + o / 9 - 1;
               if (mx < 0 || mx >= g.nnx || my < 0 || my >= g.nny || mz < 0 || mz >= g.nnz) continue;
-              if (owner_axis(mx, H, h.ncx) != icx || owner_axis(my, H, h.ncy) != icy || owner_axis(mz, H, h.ncz) != icz) continue;
+              if (mx < nbx0 || mx >= nbx1 || my < nby0 || my >= nby1 || mz < nbz0 || mz >= nbz1) continue;
               const long long m = node_id(g, mx, my, mz);
 #pragma unroll
               for (int b = 0; b < LT; ++b) wb[b] += w[o] * ld<double, BT>(R, m * LT + b);
@@ -292,13 +309,16 @@ __global__ __launch_bounds__(64) void k_cc_spmm(CCArgs a, const double* __restri
   }
 }
 
-// S_J = P_J^T Q_J (m x m per cc cell, m <= 32) -> small[J][which], symmetrised
-// from the upper triangle.  One workgroup per cc cell; chunks of 64 dofs of
-// both blocks are staged in LDS and each thread accumulates a 2 x 2 patch.
+// S_J = P_J^T Q_J (m x m per cc cell, m <= 32), in CC_KS slices of the dofs:
+// workgroup (J, ks) sums the 64-dof chunks ks, ks + CC_KS, ... of cell J into
+// part[(J - J0) * CC_KS + ks] (upper triangle mirrored); k_cc_gram_sum adds
+// the slices in a fixed order into small[J][which].  Chunks of both blocks
+// are staged in LDS and each thread accumulates a 2 x 2 patch.
+constexpr int CC_KS = CC_GRAM_SLICES;
 __global__ __launch_bounds__(256) void k_cc_gram(CCArgs a, const double* __restrict__ P, const double* __restrict__ Q,
-                                                 double* __restrict__ small, int which, const int* __restrict__ flag) {
+                                                 double* __restrict__ part, const int* __restrict__ flag) {
   __shared__ double Ps[32 * 65], Qs[32 * 65];
-  const int J = a.J0 + blockIdx.x;
+  const int J = a.J0 + blockIdx.x, ks = blockIdx.y;
   if (flag && flag[J] >= 0) return;
   const int m = a.m;
   const int d0 = a.cc_ptr[J], nd = a.cc_ptr[J + 1] - d0;
@@ -307,7 +327,7 @@ __global__ __launch_bounds__(256) void k_cc_gram(CCArgs a, const double* __restr
   const int tid = threadIdx.x;
   const int ti = (tid >> 4) * 2, tj = (tid & 15) * 2;
   double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-  for (int k0 = 0; k0 < nd; k0 += 64) {
+  for (int k0 = ks * 64; k0 < nd; k0 += 64 * CC_KS) {
     __syncthreads();
     for (int e = tid; e < 32 * 64; e += 256) {
       const int i = e >> 6, kk = e & 63;
@@ -326,7 +346,7 @@ __global__ __launch_bounds__(256) void k_cc_gram(CCArgs a, const double* __restr
       acc[1][1] += p1 * q1;
     }
   }
-  double* S = small + ((long long)J * 4 + which) * m * m;
+  double* S = part + ((long long)(J - a.J0) * CC_KS + ks) * m * m;
 #pragma unroll
   for (int u = 0; u < 2; ++u)
 #pragma unroll
@@ -339,14 +359,33 @@ __global__ __launch_bounds__(256) void k_cc_gram(CCArgs a, const double* __restr
     }
 }
 
+__global__ __launch_bounds__(256) void k_cc_gram_sum(CCArgs a, const double* __restrict__ part,
+                                                     double* __restrict__ small, int which,
+                                                     const int* __restrict__ flag) {
+  const int J = a.J0 + blockIdx.x;
+  if (flag && flag[J] >= 0) return;
+  const int m = a.m;
+  const double* Pt = part + (long long)(J - a.J0) * CC_KS * m * m;
+  double* S = small + ((long long)J * 4 + which) * m * m;
+  for (int e = threadIdx.x; e < m * m; e += 256) {
+    double v = 0.0;
+#pragma unroll
+    for (int ks = 0; ks < CC_KS; ++ks) v += Pt[(long long)ks * m * m + e];
+    S[e] = v;
+  }
+}
+
 // Per cc cell: eigen-decomposition of small[J][which] (m x m).
 //   kind 0 (orthonormalise): C = U S^-1/2 -> small[J][2]
 //   kind 1 (Rayleigh-Ritz):  C = U (ascending) -> small[J][2], Ritz values -> ritz[J][:]
+//   only (kind 0): when not null, only the cells whose Cholesky factorisation
+//   failed (only[J] != 0)
 __global__ void k_cc_small_eig(CCArgs a, double* __restrict__ small, int which, int kind, double* __restrict__ ritz,
-                               const int* __restrict__ flag) {
+                               const int* __restrict__ flag, const int* __restrict__ only) {
   extern __shared__ double sm[];
   const int J = a.J0 + blockIdx.x;
   if (flag && flag[J] >= 0) return;
+  if (only && !only[J]) return;
   const int m = a.m;
   double* A = sm;
   double* V = A + m * m;
@@ -354,11 +393,12 @@ __global__ void k_cc_small_eig(CCArgs a, double* __restrict__ small, int which, 
   double* Vs = B + m * m;
   double* ev = Vs + m * m;
   double* red = ev + m;
-  int* perm = reinterpret_cast<int*>(red + 64);
+  double* cs = red + 64;
+  int* perm = reinterpret_cast<int*>(cs + 2 * m);
   const double* S = small + ((long long)J * 4 + which) * m * m;
   for (int e = threadIdx.x; e < m * m; e += blockDim.x) A[e] = S[e];
   __syncthreads();
-  block_jacobi(A, V, B, Vs, ev, perm, m, red);
+  block_jacobi(A, V, B, Vs, ev, perm, m, red, cs);
   double* C = small + ((long long)J * 4 + 2) * m * m;
   for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
     const int k = e % m;
@@ -367,6 +407,66 @@ __global__ void k_cc_small_eig(CCArgs a, double* __restrict__ small, int which, 
   }
   if (kind == 1)
     for (int k = threadIdx.x; k < m; k += blockDim.x) ritz[(long long)J * m + k] = ev[k];
+}
+
+// Orthonormalising transform of a cc cell's block from its Gram matrix
+// S = small[J][which] (m x m, m <= 32) by one wave: the Cholesky factor
+// S = L L^T and C = L^-T (upper triangular) -> small[J][2], so that P C has
+// orthonormal columns (the block orthonormalised in column order, as
+// Gram-Schmidt would).  A pivot below 1e-14 of its diagonal entry (a block
+// of condition above ~1e7) or not positive sets failed[J] = 1 and leaves C
+// unwritten; the eigen-decomposition then takes that cell.
+__global__ __launch_bounds__(64) void k_cc_cholinv(CCArgs a, double* __restrict__ small, int which,
+                                                   const int* __restrict__ flag, int* __restrict__ failed) {
+  __shared__ double Ls[32 * 33];
+  __shared__ double Xs[32 * 33];
+  const int J = a.J0 + blockIdx.x;
+  if (flag && flag[J] >= 0) return;
+  const int m = a.m;
+  const int lane = threadIdx.x;
+  const double* S = small + ((long long)J * 4 + which) * m * m;
+  for (int e = lane; e < m * m; e += 64) Ls[(e / m) * 33 + e % m] = S[e];
+  __syncthreads();
+  bool ok = true;
+  for (int k = 0; k < m && ok; ++k) {
+    const double d = Ls[k * 33 + k];
+    const double s0 = S[k * m + k];
+    ok = (d > 1e-14 * s0) && (d > 1e-300);
+    if (!ok) break;
+    const double rd = 1.0 / sqrt(d);
+    __syncthreads();
+    // column k of L (rows k .. m-1)
+    for (int i = k + lane; i < m; i += 64) Ls[i * 33 + k] *= rd;
+    __syncthreads();
+    // trailing lower triangle: S_ij -= L_ik L_jk for k < j <= i
+    const int t = m - k - 1;
+    for (int e = lane; e < t * t; e += 64) {
+      const int i = k + 1 + e / t, j = k + 1 + e % t;
+      if (j <= i) Ls[i * 33 + j] -= Ls[i * 33 + k] * Ls[j * 33 + k];
+    }
+    __syncthreads();
+  }
+  if (!ok) {
+    if (lane == 0) failed[J] = 1;
+    return;
+  }
+  // X = L^-1 by forward substitution, column j in lane j
+  if (lane < m) {
+    const int j = lane;
+    for (int i = 0; i < m; ++i) {
+      double acc = (i == j) ? 1.0 : 0.0;
+      for (int k = j; k < i; ++k) acc -= Ls[i * 33 + k] * Xs[k * 33 + j];
+      Xs[i * 33 + j] = (i >= j) ? acc / Ls[i * 33 + i] : 0.0;
+    }
+  }
+  __syncthreads();
+  // C = X^T
+  double* C = small + ((long long)J * 4 + 2) * m * m;
+  for (int e = lane; e < m * m; e += 64) {
+    const int i = e / m, j = e % m;
+    C[e] = Xs[j * 33 + i];
+  }
+  if (lane == 0) failed[J] = 0;
 }
 
 // Q = P C per cc cell (C = small[J][2], m <= 32).  Grid (ceil(nd / 256), ncc):
@@ -514,7 +614,8 @@ __global__ void k_cc_dense(CCArgs a, double* __restrict__ X, double* __restrict_
   double* Vs = B + nd * nd;
   double* ev = Vs + nd * nd;
   double* red = ev + nd;
-  int* perm = reinterpret_cast<int*>(red + 64);
+  double* cs = red + 64;
+  int* perm = reinterpret_cast<int*>(cs + 2 * nd);
   for (int e = threadIdx.x; e < nd * nd; e += blockDim.x) {
     const int p = e / nd, q = e % nd;
     const long long dp = a.cc_dofs[d0 + p], dq = a.cc_dofs[d0 + q];
@@ -549,7 +650,7 @@ __global__ void k_cc_dense(CCArgs a, double* __restrict__ X, double* __restrict_
     else if (p > q) A[e] = B[q * nd + p];
   }
   __syncthreads();
-  block_jacobi(A, V, B, Vs, ev, perm, nd, red);
+  block_jacobi(A, V, B, Vs, ev, perm, nd, red, cs);
   const int m = a.m;
   for (int e = threadIdx.x; e < m * nd; e += blockDim.x) {
     const int k = e / nd, d = e % nd;
@@ -564,17 +665,23 @@ __global__ void k_cc_dense(CCArgs a, double* __restrict__ X, double* __restrict_
 // vector b, u = A_c v with v = sum over cc cells J of class Q of R_cc[J][b],
 // then A_cc[(I, a), (J(Q, I), b)] = R_cc[I][a] . u.
 
-template <typename VT, typename AT>
-__global__ void k_acc_apply(Hier h, const AT* __restrict__ Ac, const VT* __restrict__ Rcc, const int* __restrict__ cc_ptr,
-                            const int* __restrict__ dof_cc, const int* __restrict__ dof_loc, int qx, int qy, int qz, int b,
-                            double* __restrict__ u) {
+// One launch pair per class Q takes the columns b0 .. b0 + 31 at once: u
+// holds column b at u + (b - b0) * ustride, each thread one coarse dof.
+constexpr int ACC_B = 32;
+template <typename AT, typename VT, int L>
+__global__ __launch_bounds__(256) void k_acc_apply_cols(Hier h, const AT* __restrict__ Ac, const VT* __restrict__ Rcc,
+                                                        const int* __restrict__ cc_ptr, const int* __restrict__ dof_cc,
+                                                        const int* __restrict__ dof_loc, int qx, int qy, int qz, int b0,
+                                                        double* __restrict__ u, long long ustride) {
   const long long d = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  const int L = h.Lc;
   if (d >= (long long)h.ncells * L) return;
+  const int nb = min(ACC_B, h.Lcc - b0);
   const int cell = int(d / L), l = int(d % L);
   const int cx = cell % h.ncx, cy = (cell / h.ncx) % h.ncy, cz = cell / (h.ncx * h.ncy);
   const AT* A = Ac + (long long)cell * 27 * L * L;
-  double s = 0.0;
+  double s[ACC_B];
+#pragma unroll
+  for (int b = 0; b < ACC_B; ++b) s[b] = 0.0;
   for (int bb = 0; bb < 27; ++bb) {
     const int x = cx + bb % 3 - 1, y = cy + (bb / 3) % 3 - 1, z = cz + bb / 9 - 1;
     if (x < 0 || x >= h.ncx || y < 0 || y >= h.ncy || z < 0 || z >= h.ncz) continue;
@@ -583,21 +690,35 @@ __global__ void k_acc_apply(Hier h, const AT* __restrict__ Ac, const VT* __restr
     const int jx = J % h.nccx, jy = (J / h.nccx) % h.nccy, jz = J / (h.nccx * h.nccy);
     if (jx % 3 != qx || jy % 3 != qy || jz % 3 != qz) continue;
     const int d0 = cc_ptr[J], nd = cc_ptr[J + 1] - d0;
-    if (b >= min(h.Lcc, nd)) continue;
-    const VT* R = Rcc + (long long)h.Lcc * d0 + (long long)b * nd;
+    const int bend = min(min(h.Lcc, nd) - b0, nb);
     const int loc0 = dof_loc[nc * L];
-    for (int m = 0; m < L; ++m) s += double(ld<double, AT>(A, (bb * L + l) * L + m)) * double(R[loc0 + m]);
+    double a[L];
+#pragma unroll
+    for (int m = 0; m < L; ++m) a[m] = double(ld<double, AT>(A, (bb * L + l) * L + m));
+    const VT* R = Rcc + (long long)h.Lcc * d0 + (long long)b0 * nd + loc0;
+#pragma unroll
+    for (int b = 0; b < ACC_B; ++b) {
+      if (b < bend) {
+#pragma unroll
+        for (int m = 0; m < L; ++m) s[b] += a[m] * double(R[(long long)b * nd + m]);
+      }
+    }
   }
-  u[d] = s;
+#pragma unroll
+  for (int b = 0; b < ACC_B; ++b)
+    if (b < nb) u[(long long)b * ustride + d] = s[b];
 }
 
 template <typename VT>
-__global__ void k_acc_dot(Hier h, const VT* __restrict__ Rcc, const int* __restrict__ cc_ptr, const int* __restrict__ cc_dofs,
-                          const double* __restrict__ u, int qx, int qy, int qz, int b, int n_cc, double* __restrict__ Acc) {
+__global__ void k_acc_dot_cols(Hier h, const VT* __restrict__ Rcc, const int* __restrict__ cc_ptr,
+                               const int* __restrict__ cc_dofs, const double* __restrict__ u, long long ustride, int qx,
+                               int qy, int qz, int b0, int n_cc, double* __restrict__ Acc) {
   const long long w = (blockIdx.x * (long long)blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
-  if (w >= (long long)h.ncc * h.Lcc) return;
-  const int I = int(w / h.Lcc), a = int(w % h.Lcc);
+  const int nb = min(ACC_B, h.Lcc - b0);
+  if (w >= (long long)h.ncc * h.Lcc * nb) return;
+  const int bl = int(w % nb), a = int((w / nb) % h.Lcc), I = int(w / ((long long)nb * h.Lcc));
+  const int b = b0 + bl;
   const int ix = I % h.nccx, iy = (I / h.nccx) % h.nccy, iz = I / (h.nccx * h.nccy);
   auto off3 = [](int c, int q) {
     const int dd = ((q - c) % 3 + 3) % 3;
@@ -610,8 +731,9 @@ __global__ void k_acc_dot(Hier h, const VT* __restrict__ Rcc, const int* __restr
   const int ndJ = cc_ptr[J + 1] - cc_ptr[J];
   if (a >= min(h.Lcc, nd) || b >= min(h.Lcc, ndJ)) return;
   const VT* R = Rcc + (long long)h.Lcc * d0 + (long long)a * nd;
+  const double* ub = u + (long long)bl * ustride;
   double s = 0.0;
-  for (int d = lane; d < nd; d += 64) s += double(R[d]) * u[cc_dofs[d0 + d]];
+  for (int d = lane; d < nd; d += 64) s += double(R[d]) * ub[cc_dofs[d0 + d]];
   s = wave_sum(s);
   if (lane == 0) Acc[(long long)(I * h.Lcc + a) * n_cc + (J * h.Lcc + b)] = s;
 }
@@ -637,32 +759,78 @@ __global__ void k_acc_pad(Hier h, const int* __restrict__ cc_ptr, int n_cc, doub
 // lower triangle (i >= j) is read and kept up to date, halving the trailing
 // updates; a last pass negates and mirrors it into the full inverse.
 //
-// Pivot block: invert the current A_KK (SPD, read from the lower triangle) in
-// LDS by unblocked Gauss-Jordan, keep P, store -P; 1024 threads, each owning
-// the entries tid + 1024 q of the nb x nb block (dynamic LDS, GJ_PIVOT_LDS).
+// Pivot block: invert the current A_KK (SPD, read from the lower triangle) by
+// unblocked Gauss-Jordan, keep P, store -P; 1024 threads, each holding the
+// entries of a full block in registers (a partial last block in LDS); the
+// pivot row and column of each step pass through LDS (dynamic LDS,
+// GJ_PIVOT_LDS).
 constexpr int GJ_PLD = GJ_NB + 1;
-constexpr size_t GJ_PIVOT_LDS = sizeof(double) * (GJ_NB * GJ_PLD + 2 * GJ_NB);
+constexpr size_t GJ_PIVOT_LDS = sizeof(double) * (2 * GJ_NB + GJ_NB * GJ_PLD);
 __global__ __launch_bounds__(1024) void k_gj_pivot(int n, double* __restrict__ Ab, int k0, int nb,
                                                    double* __restrict__ Pb) {
   extern __shared__ double gjp_lds[];
-  auto a = [&](int r, int c) -> double& { return gjp_lds[r * GJ_PLD + c]; };
   constexpr int NQ = (GJ_NB * GJ_NB + 1023) / 1024;
   double* A = Ab + (long long)blockIdx.z * n * n;
   double* P = Pb + (long long)blockIdx.z * GJ_NB * GJ_NB;
   const int tid = threadIdx.x;
   const int ne = nb * nb;
+  double* rowk = gjp_lds;
+  double* colk = rowk + GJ_NB;
+  if (nb == GJ_NB) {
+    // full block: the thread holds column c = tid % nb of rows r0 + 8 q in
+    // registers; each step the owners publish the pivot row and column
+    static_assert(GJ_NB * 8 == 1024, "a full pivot block is 8 rows per pass of 1024 threads");
+    const int c = tid & (GJ_NB - 1), r0 = tid >> 7;
+    double v[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int r = r0 + 8 * q;
+      v[q] = A[(long long)(k0 + max(r, c)) * n + (k0 + min(r, c))];
+    }
+    for (int k = 0; k < nb; ++k) {
+      if (r0 == (k & 7)) {
+        double w = 0.0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) w = (q == (k >> 3)) ? v[q] : w;
+        rowk[c] = w;
+      }
+      if (c == k) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) colk[r0 + 8 * q] = v[q];
+      }
+      __syncthreads();
+      const double piv = 1.0 / rowk[k];
+      const double rc = rowk[c];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int r = r0 + 8 * q;
+        if (r == k && c == k) v[q] = piv;
+        else if (r == k) v[q] = rc * piv;
+        else if (c == k) v[q] = -colk[r] * piv;
+        else v[q] = v[q] - colk[r] * rc * piv;
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int r = r0 + 8 * q;
+      P[r * nb + c] = v[q];
+      A[(long long)(k0 + r) * n + (k0 + c)] = -v[q];
+    }
+    return;
+  }
+  // the last, partial block: the entries tid + 1024 q in LDS
+  double* blk = colk + GJ_NB;
+  auto a = [&](int r, int c) -> double& { return blk[r * GJ_PLD + c]; };
+  int rq[NQ], cq[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     const int e = tid + 1024 * q;
-    if (e < ne) {
-      const int r = e / nb, c = e % nb;
-      a(r, c) = A[(long long)(k0 + max(r, c)) * n + (k0 + min(r, c))];
-    }
+    rq[q] = e < ne ? e / nb : -1;
+    cq[q] = e < ne ? e % nb : 0;
+    if (rq[q] >= 0) a(rq[q], cq[q]) = A[(long long)(k0 + max(rq[q], cq[q])) * n + (k0 + min(rq[q], cq[q]))];
   }
   __syncthreads();
-  // pivot row and column of the current step, copied before the update
-  double* rowk = gjp_lds + GJ_NB * GJ_PLD;
-  double* colk = rowk + GJ_NB;
   for (int k = 0; k < nb; ++k) {
     if (tid < nb) {
       rowk[tid] = a(k, tid);
@@ -670,11 +838,10 @@ __global__ __launch_bounds__(1024) void k_gj_pivot(int n, double* __restrict__ A
     }
     __syncthreads();
     const double piv = 1.0 / rowk[k];
-#pragma unroll 4
+#pragma unroll
     for (int q = 0; q < NQ; ++q) {
-      const int e = tid + 1024 * q;
-      if (e >= ne) continue;
-      const int r = e / nb, c = e % nb;
+      const int r = rq[q], c = cq[q];
+      if (r < 0) continue;
       if (r == k && c == k) a(r, c) = piv;
       else if (r == k) a(r, c) = rowk[c] * piv;
       else if (c == k) a(r, c) = -colk[r] * piv;
@@ -684,9 +851,8 @@ __global__ __launch_bounds__(1024) void k_gj_pivot(int n, double* __restrict__ A
   }
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
-    const int e = tid + 1024 * q;
-    if (e >= ne) continue;
-    const int r = e / nb, c = e % nb;
+    const int r = rq[q], c = cq[q];
+    if (r < 0) continue;
     P[r * nb + c] = a(r, c);
     A[(long long)(k0 + r) * n + (k0 + c)] = -a(r, c);
   }
@@ -1072,17 +1238,21 @@ static int run_cc_group(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, CCA
   double* bound = ritz + (size_t)h.ncc * m;
   int* flag = sc->ccflag;
   const int small_threads = std::min(1024, std::max(64, ((m * m + 63) / 64) * 64));
-  const size_t small_lds = sizeof(double) * (5 * m * m + m + 64) + sizeof(int) * m;
+  const size_t small_lds = sizeof(double) * (4 * m * m + 3 * m + 64) + sizeof(int) * m;
+  int* chol_failed = sc->ccflag + h.ncc;
   hipLaunchKernelGGL(k_cc_bound, dim3(nJ), dim3(256), 0, s, a, bound);
   hipLaunchKernelGGL(k_cc_start, dim3((unsigned)((ndof + 255) / 256)), dim3(256), 0, s, a, Y);
   if (hipMemsetAsync(flag + J0, 0xff, sizeof(int) * nJ, s) != hipSuccess) return MSMG_EHIP;  // -1: active
   {
-    const size_t lds = sizeof(double) * (4 * CC_DENSE * CC_DENSE + CC_DENSE + 64) + sizeof(int) * CC_DENSE;
+    const size_t lds = sizeof(double) * (4 * CC_DENSE * CC_DENSE + 3 * CC_DENSE + 64) + sizeof(int) * CC_DENSE;
     hipLaunchKernelGGL(k_cc_dense, dim3(nJ), dim3(1024), lds, s, a, Xp, ritz, flag);
   }
   auto orth = [&](double* P, double* tmp) {
-    hipLaunchKernelGGL(k_cc_gram, dim3(nJ), dim3(256), 0, s, a, P, P, small, 0, flag);
-    hipLaunchKernelGGL(k_cc_small_eig, dim3(nJ), dim3(small_threads), small_lds, s, a, small, 0, 0, ritz, flag);
+    hipLaunchKernelGGL(k_cc_gram, dim3(nJ, CC_KS), dim3(256), 0, s, a, P, P, sc->gpart, flag);
+    hipLaunchKernelGGL(k_cc_gram_sum, dim3(nJ), dim3(256), 0, s, a, sc->gpart, small, 0, flag);
+    hipLaunchKernelGGL(k_cc_cholinv, dim3(nJ), dim3(64), 0, s, a, small, 0, flag, chol_failed);
+    hipLaunchKernelGGL(k_cc_small_eig, dim3(nJ), dim3(small_threads), small_lds, s, a, small, 0, 0, ritz, flag,
+                       (const int*)chol_failed);
     hipLaunchKernelGGL(k_cc_transform, gt, bt, 0, s, a, P, tmp, small, flag);
   };
   auto spmm = [&](const double* P, double* Q) {
@@ -1097,8 +1267,10 @@ static int run_cc_group(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, CCA
     orth(Y, Xp);
     orth(Xp, Y);
     spmm(Y, Z);
-    hipLaunchKernelGGL(k_cc_gram, dim3(nJ), dim3(256), 0, s, a, Y, Z, small, 0, flag);
-    hipLaunchKernelGGL(k_cc_small_eig, dim3(nJ), dim3(small_threads), small_lds, s, a, small, 0, 1, ritz, flag);
+    hipLaunchKernelGGL(k_cc_gram, dim3(nJ, CC_KS), dim3(256), 0, s, a, Y, Z, sc->gpart, flag);
+    hipLaunchKernelGGL(k_cc_gram_sum, dim3(nJ), dim3(256), 0, s, a, sc->gpart, small, 0, flag);
+    hipLaunchKernelGGL(k_cc_small_eig, dim3(nJ), dim3(small_threads), small_lds, s, a, small, 0, 1, ritz, flag,
+                       (const int*)nullptr);
     hipLaunchKernelGGL(k_cc_transform, gt, bt, 0, s, a, Y, Xp, small, flag);  // Xp = Ritz vectors
     hipLaunchKernelGGL(k_cc_transform, gt, bt, 0, s, a, Z, Y, small, flag);   // Y = G * Ritz vectors
     std::swap(Y, Z);                                                            // Z = G X, Y free
@@ -1177,12 +1349,19 @@ int build_acc(const Ctx& c, const SetupArgs& sa, double* u, hipStream_t s) {
   const dim3 gu((unsigned)((ndof + 255) / 256)), bu(256);
   const long long nw = (long long)h.ncc * h.Lcc;
   const dim3 gd((unsigned)((nw * 64 + 255) / 256)), bd(256);
+  // u holds up to ACC_B columns of ndof values (the scratch block has m > Lcc)
   for (int q = 0; q < 27; ++q) {
     const int qx = q % 3, qy = (q / 3) % 3, qz = q / 9;
     if (qx >= h.nccx || qy >= h.nccy || qz >= h.nccz) continue;
-    for (int b = 0; b < h.Lcc; ++b) {
-      hipLaunchKernelGGL((k_acc_apply<double, double>), gu, bu, 0, s, h, (const double*)sa.Ac64, (const double*)sa.Rccv, sa.cc_ptr, sa.dof_cc, sa.dof_loc, qx, qy, qz, b, u);
-      hipLaunchKernelGGL((k_acc_dot<double>), gd, bd, 0, s, h, (const double*)sa.Rccv, sa.cc_ptr, sa.cc_dofs, u, qx, qy, qz, b, n, sa.Acc);
+    for (int b0 = 0; b0 < h.Lcc; b0 += ACC_B) {
+      const int nb = std::min(ACC_B, h.Lcc - b0);
+      switch (h.Lc) {
+#define ACA(L_) case L_: hipLaunchKernelGGL((k_acc_apply_cols<double, double, L_>), gu, bu, 0, s, h, (const double*)sa.Ac64, (const double*)sa.Rccv, sa.cc_ptr, sa.dof_cc, sa.dof_loc, qx, qy, qz, b0, u, ndof); break;
+        ACA(1) ACA(2) ACA(3) ACA(4) ACA(5) ACA(6) ACA(7) ACA(8)
+#undef ACA
+      }
+      const dim3 gdc((unsigned)((nw * nb * 64 + 255) / 256));
+      hipLaunchKernelGGL((k_acc_dot_cols<double>), gdc, bd, 0, s, h, (const double*)sa.Rccv, sa.cc_ptr, sa.cc_dofs, u, ndof, qx, qy, qz, b0, n, sa.Acc);
     }
   }
   hipLaunchKernelGGL(k_acc_pad, dim3((n + 255) / 256), dim3(256), 0, s, h, sa.cc_ptr, n, sa.Acc);

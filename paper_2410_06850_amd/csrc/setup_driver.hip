@@ -33,7 +33,7 @@ int setup_scratch_alloc(const Geo& g, const Hier& h, int max_cc_dofs, int n_cc, 
   if ((r = alloc((void**)&s->Z, nvec * 8))) return r;
   if ((r = alloc((void**)&s->small, (size_t)h.ncc * 4 * m * m * 8))) return r;
   if ((r = alloc((void**)&s->ccpar, (size_t)h.ncc * (8 + m + 1) * 8))) return r;
-  if ((r = alloc((void**)&s->ccflag, (size_t)h.ncc * 4))) return r;
+  if ((r = alloc((void**)&s->ccflag, (size_t)h.ncc * 2 * 4))) return r;  // convergence flags, Cholesky failures
   if (!o.lean_memory && (r = alloc((void**)&s->acc_copy, (size_t)n_cc * n_cc * 8))) return r;
   const size_t ndm = (size_t)std::max(max_cc_dofs, 1);
   s->cc_group = (int)std::max<size_t>(1, std::min<size_t>(h.ncc, CC_GROUP_BYTES / (ndm * ndm * 8)));
@@ -42,7 +42,10 @@ int setup_scratch_alloc(const Geo& g, const Hier& h, int max_cc_dofs, int n_cc, 
   const size_t gj_batch = gj_workspace_doubles(int(ndm), s->cc_group);
   if ((r = alloc((void**)&s->gj, std::max(gj_single, gj_batch) * 8))) return r;
   if ((r = alloc((void**)&s->Gd, (size_t)s->cc_group * ndm * ndm * 8))) return r;
+  if ((r = alloc((void**)&s->gpart, (size_t)s->cc_group * CC_GRAM_SLICES * m * m * 8))) return r;
   if ((r = alloc((void**)&s->work, 64))) return r;
+  if ((r = alloc((void**)&s->cells, (size_t)h.ncells * 4))) return r;
+  s->n_regular = -1;
   return MSMG_OK;
 }
 
@@ -110,31 +113,34 @@ static int count_unconverged(const SetupArgs& sa, int ncells, int* unconv, int* 
 }
 
 // Time the level-1 eigensolver over a few launch shapes on the first cells of
-// the real problem and keep the fastest one with the fewest unconverged cells.
-static int tune_local(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, int cus, hipStream_t s, TuneChoice* best) {
+// one class (cells[first .. first + count), LDS for nl nodes) and keep the
+// fastest one with the fewest unconverged cells.  Two workgroups per CU are
+// tried where their LDS fits (regular cells of H = 8: 512 nodes, 76 KB).
+static int tune_local(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, int cus, int first, int count, int nl,
+                      hipStream_t s, TuneChoice* best) {
   struct Cand { int bs, m, degree, bpc; };
-  // both subspace blocks sit in LDS (about 94 KB for the 9^3-node cells of
-  // H = 8), so one workgroup per CU; the shapes differ in threads per cell
   std::vector<Cand> cands = {{256, 8, 12, 1}, {512, 8, 12, 1}, {768, 8, 8, 1}, {768, 8, 12, 1},
-                             {768, 8, 20, 1}, {1024, 8, 12, 1}};
+                             {768, 8, 20, 1}, {1024, 8, 12, 1}, {256, 8, 12, 2}, {512, 8, 12, 2},
+                             {512, 8, 8, 2}, {512, 8, 20, 2}};
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MSMG_EHIP;
   best->valid = 0;
   int best_unconv = 1 << 30;
   // candidates are timed on the first cells only (a few rounds of workgroups)
-  const int lim = std::min(c.h.ncells, 64 * cus);
+  const int lim = std::min(count, 64 * cus);
   for (const Cand& cd : cands) {
     if (cd.m < c.h.Lc + 1) continue;
+    if (cd.bpc > 1 && size_t(cd.bpc) * local_lds_bytes(cd.m, nl) > 160 * 1024) continue;
     const int blocks = std::max(1, std::min(lim, cd.bpc * cus));
     (void)hipEventRecord(e0, s);
-    const int r = launch_local_eigen(c, sa, sc, cd.bs, cd.m, cd.degree, blocks, s, lim);
+    const int r = launch_local_eigen(c, sa, sc, cd.bs, cd.m, cd.degree, blocks, s, first, lim, nl);
     (void)hipEventRecord(e1, s);
     if (r != MSMG_OK) continue;
     if (hipEventSynchronize(e1) != hipSuccess) return MSMG_EHIP;
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, e0, e1);
     int un = 0, ti = 0;
-    if (count_unconverged(sa, lim, &un, &ti, s) != MSMG_OK) return MSMG_EHIP;
+    if (count_unconverged(sa, c.h.ncells, &un, &ti, s) != MSMG_OK) return MSMG_EHIP;
     const bool better = (un < best_unconv) || (un == best_unconv && ms < best->ms);
     if (!best->valid || better) {
       best->valid = 1;
@@ -151,6 +157,29 @@ static int tune_local(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, int c
   return best->valid ? MSMG_OK : MSMG_ESETUP;
 }
 
+// The level-1 cells in two shape classes: the regular cells (H nodes along
+// every axis) first, then the cells that keep a remainder, with their count.
+static int build_cell_classes(const Hier& h, const Geo& g, SetupScratch* sc, hipStream_t s) {
+  std::vector<int> reg, rest;
+  reg.reserve(h.ncells);
+  for (int cz = 0; cz < h.ncz; ++cz)
+    for (int cy = 0; cy < h.ncy; ++cy)
+      for (int cx = 0; cx < h.ncx; ++cx) {
+        const int cell = (cz * h.ncy + cy) * h.ncx + cx;
+        const bool regular = cell_end(cx, h.H, h.ncx, g.nnx) - cell_begin(cx, h.H) == h.H &&
+                             cell_end(cy, h.H, h.ncy, g.nny) - cell_begin(cy, h.H) == h.H &&
+                             cell_end(cz, h.H, h.ncz, g.nnz) - cell_begin(cz, h.H) == h.H;
+        (regular ? reg : rest).push_back(cell);
+      }
+  const int n0 = int(reg.size());
+  reg.insert(reg.end(), rest.begin(), rest.end());
+  if (hipMemcpyAsync(sc->cells, reg.data(), sizeof(int) * reg.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+    return MSMG_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return MSMG_EHIP;
+  sc->n_regular = n0;
+  return MSMG_OK;
+}
+
 int run_setup(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, SetupReport* rep, hipStream_t s) {
   std::memset(rep, 0, sizeof(*rep));
   const Hier& h = c.h;
@@ -159,31 +188,39 @@ int run_setup(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, SetupReport* 
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
 
-  // 1. local spectral problems eq. (spepb) -> R_c (FP64)
-  TuneChoice& tc = *sa.tune;
+  // 1. local spectral problems eq. (spepb) -> R_c (FP64), one launch per cell
+  // shape class, each with its own tuned shape and LDS size
   int r;
-  if (o.eig_block > 0 || o.eig_degree > 0 || !o.autotune) {
-    tc.valid = 1;
-    tc.bs = sa.max_cell_nodes <= 256 ? 256 : 768;
-    tc.blocks_per_cu = 1;
-    tc.m = o.eig_block > 0 ? o.eig_block : 8;
-    tc.degree = o.eig_degree > 0 ? o.eig_degree : 12;
-  } else if (!tc.valid) {
-    const std::string key = tune_key(c, sa.max_cell_nodes);
-    if (!cache_lookup(o.tune_cache, key, &tc)) {
-      r = tune_local(c, sa, sc, cus, s, &tc);
-      if (r != MSMG_OK) {
-        std::snprintf(rep->msg, sizeof(rep->msg), "level-1 eigensolver tuning failed");
-        return r;
+  if (sc->n_regular < 0 && (r = build_cell_classes(h, c.g, sc, s))) return hip_ok(hipGetLastError(), rep, "cell classes");
+  const int nclass[2] = {sc->n_regular, h.ncells - sc->n_regular};
+  const int first[2] = {0, sc->n_regular};
+  const int nlc[2] = {h.H * h.H * h.H, sa.max_cell_nodes};
+  for (int k = 0; k < 2; ++k) {
+    if (nclass[k] == 0) continue;
+    TuneChoice& tc = sa.tune[k];
+    if (o.eig_block > 0 || o.eig_degree > 0 || !o.autotune) {
+      tc.valid = 1;
+      tc.bs = nlc[k] <= 256 ? 256 : 768;
+      tc.blocks_per_cu = 1;
+      tc.m = o.eig_block > 0 ? o.eig_block : 8;
+      tc.degree = o.eig_degree > 0 ? o.eig_degree : 12;
+    } else if (!tc.valid) {
+      const std::string key = tune_key(c, nlc[k]);
+      if (!cache_lookup(o.tune_cache, key, &tc)) {
+        r = tune_local(c, sa, sc, cus, first[k], nclass[k], nlc[k], s, &tc);
+        if (r != MSMG_OK) {
+          std::snprintf(rep->msg, sizeof(rep->msg), "level-1 eigensolver tuning failed");
+          return r;
+        }
+        cache_store(o.tune_cache, key, tc);
       }
-      cache_store(o.tune_cache, key, tc);
     }
-  }
-  const int blocks = std::max(1, std::min(h.ncells, tc.blocks_per_cu * cus));
-  r = launch_local_eigen(c, sa, sc, tc.bs, tc.m, tc.degree, blocks, s);
-  if (r != MSMG_OK) {
-    std::snprintf(rep->msg, sizeof(rep->msg), "level-1 eigensolver launch failed (block %d)", tc.m);
-    return r;
+    const int blocks = std::max(1, std::min(nclass[k], tc.blocks_per_cu * cus));
+    r = launch_local_eigen(c, sa, sc, tc.bs, tc.m, tc.degree, blocks, s, first[k], nclass[k], nlc[k]);
+    if (r != MSMG_OK) {
+      std::snprintf(rep->msg, sizeof(rep->msg), "level-1 eigensolver launch failed (block %d)", tc.m);
+      return r;
+    }
   }
   if ((r = count_unconverged(sa, h.ncells, &rep->eig_unconverged, &rep->eig_ties, s))) return r;
 

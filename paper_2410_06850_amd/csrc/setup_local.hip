@@ -25,7 +25,14 @@ constexpr int DENSE_MAX = 16;
 #ifndef MSMG_LOCAL_CHOLQR
 #define MSMG_LOCAL_CHOLQR 1  // orthonormalise by Cholesky-QR (else always by the eigen-decomposition)
 #endif
-constexpr int RED_SLOTS = 640;  // block reductions of up to 40 values over 16 waves
+constexpr int RED_SLOTS = 256;  // block reductions of up to 16 values over 16 waves
+// doubles of the second subspace block: it also holds the dense path's four
+// DENSE_MAX^2 matrices and its node index lists
+MSMG_HD constexpr size_t local_blk1_words(int M, int nl) {
+  return (size_t(M) * nl > 4 * DENSE_MAX * DENSE_MAX + (size_t(nl) + DENSE_MAX + 1) / 2 + 1)
+             ? size_t(M) * nl
+             : 4 * DENSE_MAX * DENSE_MAX + (size_t(nl) + DENSE_MAX + 1) / 2 + 1;
+}
 
 struct LocalArgs {
   Geo g;
@@ -39,9 +46,10 @@ struct LocalArgs {
   int degree;
   int maxit;
   double tol;
-  int nl_max;   // LDS capacity in nodes
+  int nl_max;   // LDS capacity in nodes (the largest cell of the class)
   int warm;     // start from the basis in Rc64 (previous set-up)
-  int ncells;   // cells to solve: all, or the first ones when the tuner times a shape
+  const int* cells;  // the class's cells: cells[0 .. ncells)
+  int ncells;   // cells to solve
   double* Rc64;
   double* evals;
   int* status;
@@ -69,25 +77,34 @@ MSMG_DEV double hash01(unsigned x) {
   return double(x) * (1.0 / 4294967296.0) - 0.5;
 }
 
-template <int M, int BS>
-__global__ __launch_bounds__(BS) void k_local_eigen(LocalArgs A) {
+// NLC: the LDS capacity per vector as a compile-time constant (the common
+// cell sizes), so that the vector strides become immediate offsets; 0 takes
+// it from the arguments.
+template <int M, int BS, int NLC>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BS <= 512 ? 2 * BS / 256 : 1)))
+void k_local_eigen(LocalArgs A) {
   extern __shared__ double lds[];
-  const int NL = A.nl_max;
+  const int NL = NLC > 0 ? NLC : A.nl_max;
   // Both subspace blocks live in LDS (node-contiguous per vector); registers
   // only hold per-node temporaries, so the kernel runs without spilling.
   double* blk0 = lds;               // M * NL : block buffer
-  double* blk1 = blk0 + M * NL;     // M * NL : block buffer
-  double* kl = blk1 + M * NL;       // NL : conductivities of internal elements
+  double* blk1 = blk0 + M * NL;     // local_blk1_words : block buffer
+  double* kl = blk1 + local_blk1_words(M, NL);  // NL : conductivities of internal elements
   double* isq = kl + NL;            // NL : 1/sqrt(m) on free nodes, 0 on fixed
-  double* Gm = isq + NL;            // small matrices (16*16 each)
-  double* Vm = Gm + 256;
-  double* Bm = Vm + 256;
-  double* Vs = Bm + 256;
-  double* ev = Vs + 256;            // 16
+  double* Gm = isq + NL;            // small matrices (M*M each)
+  double* Vm = Gm + M * M;
+  double* Bm = Vm + M * M;
+  double* Vs = Bm + M * M;
+  double* ev = Vs + M * M;          // 16
   double* red = ev + 16;            // RED_SLOTS
   int* perm = reinterpret_cast<int*>(red + RED_SLOTS);   // 16
   int* ired = perm + 16;                          // 16
-  int* fidx = ired + 16;                          // NL (dense path: free index of a node)
+  // the dense path (at most DENSE_MAX free nodes) works in the second block
+  double* Gd = blk1;                              // DENSE_MAX^2 each
+  double* Vd = Gd + DENSE_MAX * DENSE_MAX;
+  double* Bd = Vd + DENSE_MAX * DENSE_MAX;
+  double* Vsd = Bd + DENSE_MAX * DENSE_MAX;
+  int* fidx = reinterpret_cast<int*>(Vsd + DENSE_MAX * DENSE_MAX);  // NL: free index of a node
   int* flist = fidx + NL;                         // DENSE_MAX
   __shared__ int s_cell;
 
@@ -105,9 +122,10 @@ __global__ __launch_bounds__(BS) void k_local_eigen(LocalArgs A) {
   while (true) {
     if (tid == 0) s_cell = int(atomicAdd(A.work, 1u));
     __syncthreads();
-    const int cell = s_cell;
+    const int wi = s_cell;
     __syncthreads();
-    if (cell >= A.ncells) break;
+    if (wi >= A.ncells) break;
+    const int cell = A.cells[wi];
     const int cx = cell % h.ncx, cy = (cell / h.ncx) % h.ncy, cz = cell / (h.ncx * h.ncy);
     const int x0 = cell_begin(cx, h.H), x1 = cell_end(cx, h.H, h.ncx, g.nnx);
     const int y0 = cell_begin(cy, h.H), y1 = cell_end(cy, h.H, h.ncy, g.nny);
@@ -189,12 +207,17 @@ __global__ __launch_bounds__(BS) void k_local_eigen(LocalArgs A) {
           const bool okz = (oz == 0) || (oz > 0 && ccz == 1) || (oz < 0 && ccz == 0);
           if (okx && oky && okz) ks += kk[c];
         }
-        const int nx_ = lx + ox, ny_ = ly + oy, nz_ = lz + oz;
-        if (nx_ < 0 || nx_ >= nlx || ny_ < 0 || ny_ >= nly || nz_ < 0 || nz_ >= nlz) continue;
-        const int nb = ln + (oz * nly + oy) * nlx + ox;
+        // a neighbour outside the cell box shares only absent elements with
+        // the node (ks = 0): its clamped index reads some local node's finite
+        // values, weighted by zero.  No branch, so the loads of consecutive
+        // neighbours can be in flight together.
+        const int nb = min(max(ln + (oz * nly + oy) * nlx + ox, 0), nloc - 1);
         const double wo = pat * ks, sb = isq[nb];
+        double pv[M];
 #pragma unroll
-        for (int j = 0; j < M; ++j) out[j] += wo * (sb * P[j * NL + nb] - v0[j]);
+        for (int j = 0; j < M; ++j) pv[j] = P[j * NL + nb];
+#pragma unroll
+        for (int j = 0; j < M; ++j) out[j] += wo * (sb * pv[j] - v0[j]);
       }
 #pragma unroll
       for (int j = 0; j < M; ++j) out[j] *= s0;
@@ -245,7 +268,7 @@ __global__ __launch_bounds__(BS) void k_local_eigen(LocalArgs A) {
         if (wid == 0) wave_jacobi8(Gm, Vs, ev);
         __syncthreads();
       } else {
-        block_jacobi(Gm, Vm, Bm, Vs, ev, perm, M, red);
+        block_jacobi(Gm, Vm, Bm, Vs, ev, perm, M, red, red + 32);
       }
     };
     // orthonormalise a block from G = P^T P: P <- P R^-1 with the Cholesky
@@ -326,14 +349,14 @@ __global__ __launch_bounds__(BS) void k_local_eigen(LocalArgs A) {
           stencil27(A.st, kk, w);
           kab = w[(dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)];
         }
-        Gm[e] = isq[ia] * kab * isq[ib];
+        Gd[e] = isq[ia] * kab * isq[ib];
       }
       __syncthreads();
-      block_jacobi(Gm, Vm, Bm, Vs, ev, perm, nf, red);
+      block_jacobi(Gd, Vd, Bd, Vsd, ev, perm, nf, red, red + 32);
       for (int e = tid; e < M * NL; e += BS) {
         const int j = e / NL, ln = e % NL;
         double v = 0.0;
-        if (ln < nloc && isq[ln] > 0.0 && j < nf) v = Vs[fidx[ln] * nf + j];
+        if (ln < nloc && isq[ln] > 0.0 && j < nf) v = Vsd[fidx[ln] * nf + j];
         X[e] = v;
       }
       if (L < nf && ev[L] - ev[L - 1] < 1e-8 * b_hi) tie = true;
@@ -498,19 +521,22 @@ __global__ __launch_bounds__(BS) void k_local_eigen(LocalArgs A) {
 }
 
 // LDS bytes of one workgroup
-static size_t local_lds_bytes(int M, int nl) {
-  return sizeof(double) * (2 * size_t(M) * nl + 2 * size_t(nl) + 4 * 256 + 16 + RED_SLOTS) + sizeof(int) * (16 + 16 + size_t(nl) + DENSE_MAX);
+size_t local_lds_bytes(int M, int nl) {
+  return sizeof(double) * (size_t(M) * nl + local_blk1_words(M, nl) + 2 * size_t(nl) + 4 * size_t(M) * M + 16 +
+                           RED_SLOTS) +
+         sizeof(int) * (16 + 16);
 }
 
-template <int M, int BS>
+template <int M, int BS, int NLC>
 static void launch_local_t(const LocalArgs& a, int blocks, hipStream_t s) {
   const size_t lds = local_lds_bytes(M, a.nl_max);
-  (void)hipFuncSetAttribute((const void*)k_local_eigen<M, BS>, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-  hipLaunchKernelGGL((k_local_eigen<M, BS>), dim3(blocks), dim3(BS), lds, s, a);
+  (void)hipFuncSetAttribute((const void*)k_local_eigen<M, BS, NLC>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            int(lds));
+  hipLaunchKernelGGL((k_local_eigen<M, BS, NLC>), dim3(blocks), dim3(BS), lds, s, a);
 }
 
 int launch_local_eigen(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, int bs, int m, int degree, int blocks,
-                       hipStream_t s, int ncells) {
+                       hipStream_t s, int first, int count, int nl) {
   LocalArgs a;
   a.g = c.g;
   a.st = c.st;
@@ -523,9 +549,12 @@ int launch_local_eigen(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, int 
   a.degree = degree;
   a.maxit = sa.opt->eig_maxit;
   a.tol = sa.opt->eig_tol;
-  a.nl_max = sa.max_cell_nodes;
+  a.nl_max = nl;
   a.warm = sa.warm;
-  a.ncells = (ncells > 0 && ncells < c.h.ncells) ? ncells : c.h.ncells;
+  if (first < 0 || count < 0 || first + count > c.h.ncells || nl < 1 || nl > sa.max_cell_nodes) return MSMG_EINVAL;
+  a.cells = sc->cells + first;
+  a.ncells = count;
+  if (count == 0) return MSMG_OK;
   a.Rc64 = sa.Rc64;
   a.evals = sa.evals;
   a.status = sa.cell_status;
@@ -533,15 +562,22 @@ int launch_local_eigen(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, int 
   if (m < c.h.Lc + 1) return MSMG_EINVAL;
   if (local_lds_bytes(m, a.nl_max) > 160 * 1024) return MSMG_EINVAL;
   if (hipMemsetAsync(sc->work, 0, sizeof(unsigned), s) != hipSuccess) return MSMG_EHIP;
-#define LL(M_, BS_)                                      \
-  if (m == M_ && bs == BS_) {                            \
-    launch_local_t<M_, BS_>(a, blocks, s);               \
-    return hipGetLastError() == hipSuccess ? MSMG_OK : MSMG_EHIP; \
+  // compile-time capacities: 8^3-node cells (H = 8) and 9^3 (the last cells
+  // of a mesh of 8 k elements per axis)
+#define LL(M_, BS_, NLC_)                                              \
+  if (m == M_ && bs == BS_ && (NLC_ == 0 || a.nl_max == NLC_)) {       \
+    launch_local_t<M_, BS_, NLC_>(a, blocks, s);                       \
+    return hipGetLastError() == hipSuccess ? MSMG_OK : MSMG_EHIP;      \
   }
-  LL(8, 256)
-  LL(8, 512)
-  LL(8, 768)
-  LL(8, 1024)
+  LL(8, 256, 512)
+  LL(8, 512, 512)
+  LL(8, 512, 729)
+  LL(8, 768, 729)
+  LL(8, 1024, 729)
+  LL(8, 256, 0)
+  LL(8, 512, 0)
+  LL(8, 768, 0)
+  LL(8, 1024, 0)
 #undef LL
   return MSMG_EINVAL;
 }

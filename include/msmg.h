@@ -100,12 +100,13 @@ typedef struct msmg_options {
                           grids (1024^3 on one GPU).                             */
   int cc_group;        /* coarse-coarse cells whose dense shifted matrices the   [0]
                           set-up holds at once (0 = as many as fit in 24 GB)     */
-  int coarse_fused;    /* bit 0: levels 1 and 2 of each cycle in one launch      [3]
+  int coarse_fused;    /* bit 0: levels 1 and 2 of each cycle in one launch      [7]
                           (one workgroup per compute unit, grid-wide barriers
                           between the steps); bit 1: the restriction fused into the cycle's
-                          first residual (H = 2, 4, 8 or 16).  Cleared bits run
-                          one launch per step.  The same arithmetic up to the
-                          order of the sums.                                     */
+                          first residual (H = 2, 4, 8 or 16); bit 2: the
+                          prolongation fused into the residual after the coarse
+                          correction.  Cleared bits run one launch per step.
+                          The same arithmetic up to the order of the sums.       */
   int pair_rhs;        /* 1: allocate a second set of PCG and cycle vectors     [0]
                           for msmg_solve_pair (about 11 nodal vectors more;
                           needs the multigrid kind with cheb_degree 2)           */

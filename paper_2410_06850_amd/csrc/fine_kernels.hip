@@ -539,7 +539,7 @@ __global__ void k_prolong(Geo g, Hier h, int CX, Two<const VT*> bases, const BT*
 
 // V-cycle residual on level 0:  out = r - A x (free rows).  The stencil runs in
 // the type of x: after the coarse correction x carries the large, nearly flat
-// values of the low-energy modes and is kept (and differenced) in FP64.
+// values of the low-energy modes and is kept in FP64.
 template <typename IT>
 struct RW {
   IT r;
@@ -610,6 +610,77 @@ MSMG_DEV void load_row_raw(const BT* __restrict__ Rc, long long n, BT out[L]) {
 #pragma unroll
     for (int l = 0; l < L; ++l) out[l] = Rc[n * L + l];
   }
+}
+
+// The residual after the coarse correction with the prolongation fused in:
+// x = base + R_c^T e (e = e1 + e2 per coarse cell) is formed for every node
+// the march stages, halo included, in the order k_prolong uses, so that
+// out = r - A x and the prolonged vector x2 (written for the owned nodes) are
+// those of the two separate kernels to the bit.  Each staging slot keeps the
+// e of its current coarse cell in registers and reloads it when the march
+// enters the next coarse z-cell.
+template <typename VT, typename BT, int L>
+struct PRN {
+  VT base;
+  BT row[L];
+};
+
+template <typename VT, typename KT, typename BT, int L, bool CUBIC>
+MSMG_MARCH_KERNEL void k_vresidual_prolong(Geo g, Stencil st, March mg, Hier h, const KT* __restrict__ kv,
+                                           const uint32_t* __restrict__ bits, const double* __restrict__ r,
+                                           const VT* __restrict__ base, const BT* __restrict__ Rc,
+                                           const double* __restrict__ e1, const double* __restrict__ e2,
+                                           VT* __restrict__ out, double* __restrict__ x2, const Scalars* sc) {
+  if (sc && sc->done) return;
+  static_assert(march_depth<double>() == 1, "the e registers assume a one-step queue");
+  static_assert(MARCH_NODE_SLOTS == 2, "two node slots per thread");
+  __shared__ double sx[2 * PW * PH];
+  __shared__ double sk[2 * EW * EH];
+  const long long tile = xcd_tile(blockIdx.x, gridDim.x);
+  // coarse cell column (x, y) of each staging slot, and its current e
+  int ccx[2], ccy[2], ecz[2] = {-1, -1};
+  double ev[2][L];
+  {
+    int gx, gy;
+    march_slot_xy<0>(g, mg, tile, gx, gy);
+    ccx[0] = owner_axis(gx, h.H, h.ncx);
+    ccy[0] = owner_axis(gy, h.H, h.ncy);
+    march_slot_xy<1>(g, mg, tile, gx, gy);
+    ccx[1] = owner_axis(gx, h.H, h.ncx);
+    ccy[1] = owner_axis(gy, h.H, h.ncy);
+  }
+  march<double, CUBIC>(
+      g, st, mg, tile, sx, sk,
+      [&](long long b, unsigned o, int slot, int zz) {
+        const int cz = owner_axis(zz, h.H, h.ncz);
+        if (cz != ecz[slot]) {
+          const long long cell = ((long long)cz * h.ncy + ccy[slot]) * h.ncx + ccx[slot];
+#pragma unroll
+          for (int l = 0; l < L; ++l) ev[slot][l] = e1[cell * L + l] + (e2 ? e2[cell * L + l] : 0.0);
+          ecz[slot] = cz;
+        }
+        PRN<VT, BT, L> v;
+        v.base = plane_ld(base, b, o);
+        load_row_raw<BT, L>(Rc, b + o, v.row);
+        return v;
+      },
+      [&](const PRN<VT, BT, L>& v, int slot) {
+        double x = double(v.base);
+#pragma unroll
+        for (int l = 0; l < L; ++l) x += to_f64(v.row[l]) * ev[slot][l];
+        return x;
+      },
+      [&](long long b, unsigned o) { return plane_ld(kv, b, o); }, [&](KT v) { return cvt<double, KT>(v); },
+      [&](long long b, unsigned o) {
+        RW<double> c;
+        c.r = plane_ld(r, b, o);
+        c.w = bits[(b + o) >> 5];
+        return c;
+      },
+      [&](long long b, unsigned o, double ax, double xc, const RW<double>& c) {
+        plane_st(out, b, o, ((c.w >> ((b + o) & 31)) & 1u) ? VT(0) : VT(c.r - ax));
+        plane_st(x2, b, o, xc);
+      });
 }
 
 template <typename VT, typename KT, typename XT, typename BT, int L, bool CUBIC, int NS>
@@ -1292,6 +1363,17 @@ void launch_vresidual_pair(const Ctx& a, const Ctx& b, const double* ra, const d
     hipLaunchKernelGGL((k_vresidual<VT, KVT, double, double, CU, 2>), gr, bl, 0, s, c.g, c.st, c.mg, (const KVT*)c.kv,
                        c.bits, two(ra, rb), two(xa, xb), two((VT*)outa, (VT*)outb),
                        two((const Scalars*)a.sc, (const Scalars*)b.sc));
+  });
+}
+
+void launch_vresidual_prolong(const Ctx& c, const double* r, const void* base, const double* e1, const double* e2,
+                              void* out, double* x2, hipStream_t s) {
+  const dim3 gr = march_grid(c), bl = march_block();
+  VC_DISPATCH({
+    (void)sizeof(DVT);
+    L_DISPATCH(c.h.Lc, hipLaunchKernelGGL((k_vresidual_prolong<VT, KVT, BT, LL, CU>), gr, bl, 0, s, c.g, c.st, c.mg,
+                                          c.h, (const KVT*)c.kv, c.bits, r, (const VT*)base, (const BT*)c.Rc, e1, e2,
+                                          (VT*)out, x2, (const Scalars*)c.sc));
   });
 }
 

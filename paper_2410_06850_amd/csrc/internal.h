@@ -134,6 +134,11 @@ void launch_restrict(const Ctx& c, const void* r, void* rc, hipStream_t s);
 void launch_prolong(const Ctx& c, const void* base, const void* e1, const void* e2, void* out, hipStream_t s);
 void launch_vresidual(const Ctx& c, const void* r, bool r_is_f64, const void* x, bool x_is_f64, void* out,
                       hipStream_t s);
+// out = r - A x2 with x2 = base + R_c^T (e1 + e2) formed in the march (e2 may
+// be null); x2 is written too.  The prolongation and the residual of the two
+// separate launches, bit for bit.
+void launch_vresidual_prolong(const Ctx& c, const double* r, const void* base, const double* e1, const double* e2,
+                              void* out, double* x2, hipStream_t s);
 // rc = R_c (r - A x) without storing the residual (r FP64, x of the cycle's
 // vector type): the fused march writes per-workgroup partials, a second kernel
 // adds them per coarse cell in a fixed order.  Only when restrict_fusable.

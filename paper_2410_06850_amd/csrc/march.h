@@ -16,6 +16,7 @@
 // is prefetched the same way.
 #pragma once
 
+#include <type_traits>
 #include <utility>
 
 #include "common.h"
@@ -105,6 +106,43 @@ MSMG_DEV W layer_apply(const Stencil& st, const W kq[4], const W s[9], const W o
   return acc;
 }
 
+// The same contribution as a plain sum sum_j a_nj x_j - (sum_j a_nj) x_n: the
+// coefficient sum of a layer is (sum of its pattern weights) x (sum of kq), so
+// about half the FP64 operations of the difference form.  Exact for the same
+// linear operator; it differs from the difference form only by rounding (no
+// cancellation of x_n inside each term), which the cycle, a preconditioner,
+// does not need.
+template <typename W, bool CUBIC>
+MSMG_DEV W layer_apply_sum(const Stencil& st, const W kq[4], const W s[9], const W o[9]) {
+  const W k02 = kq[0] + kq[2], k13 = kq[1] + kq[3], k01 = kq[0] + kq[1], k23 = kq[2] + kq[3];
+  const W ksum = k01 + k23;
+  W wsum = W(st.fd[2]) + W(st.fd[1]) + W(st.fd[0]) + W(st.bd);
+  W acc = W(st.fd[2]) * (kq[0] * s[0] + kq[1] * s[2] + kq[2] * s[6] + kq[3] * s[8]);
+  acc += W(st.fd[1]) * (k02 * o[3] + k13 * o[5]);
+  acc += W(st.fd[0]) * (k01 * o[1] + k23 * o[7]);
+  acc += W(st.bd) * (kq[0] * o[0] + kq[1] * o[2] + kq[2] * o[6] + kq[3] * o[8]);
+  if (!CUBIC) {
+    acc += W(st.ax[0]) * (k02 * s[3] + k13 * s[5]);
+    acc += W(st.ax[1]) * (k01 * s[1] + k23 * s[7]);
+    acc += W(st.ax[2]) * (ksum * o[4]);
+    wsum += W(st.ax[0]) + W(st.ax[1]) + W(st.ax[2]);
+  }
+  return acc - (wsum * ksum) * s[4];
+}
+
+// The layer product of the cycle's marching kernels: the plain sum in FP64
+// (MSMG_CYCLE_DIFFERENCE_FORM selects the difference form instead), the
+// difference form for narrower types, whose rounding the cancellation would
+// otherwise expose.
+#ifndef MSMG_CYCLE_DIFFERENCE_FORM
+#define MSMG_CYCLE_DIFFERENCE_FORM 0
+#endif
+template <typename W, bool CUBIC>
+MSMG_DEV W cycle_layer(const Stencil& st, const W kq[4], const W s[9], const W o[9]) {
+  if constexpr (MSMG_CYCLE_DIFFERENCE_FORM || sizeof(W) < 8) return layer_apply<W, CUBIC>(st, kq, s, o);
+  else return layer_apply_sum<W, CUBIC>(st, kq, s, o);
+}
+
 // Element base + ofs of an array, with the plane base kept apart from the
 // 32-bit in-plane offset.
 template <typename T>
@@ -139,11 +177,39 @@ constexpr int march_depth() {
 // place for work that needs the whole workgroup, such as a block reduction.
 // The z chunk of workgroup tz is [tz * zc, tz * zc + zc), the last one up to
 // the last plane (it may be longer than zc).
+//
+// loadn may also take (b, o, s, zz): the thread's staging slot s (node
+// (x, y) = march_slot_xy(tile, s), clamped into the mesh) and the plane zz
+// (clamped), for node data that depends on where the node lies; convn may
+// take (raw, s).  Slot s of plane zz is converted before slot s of the next
+// plane is loaded when the queue is one step deep.
+template <int S>
+MSMG_DEV void march_slot_xy(const Geo& g, const March& mg, long long tile, int& gx, int& gy) {
+  const int tx = int(tile % mg.ntx), ty = int((tile / mg.ntx) % mg.nty);
+  const int tid = threadIdx.x + MX * threadIdx.y;
+  const int q = tid + S * MARCH_THREADS;
+  gx = min(max(tx * MX - 1 + q % PW, 0), g.nnx - 1);
+  gy = min(max(ty * MY - 1 + q / PW, 0), g.nny - 1);
+}
+constexpr int MARCH_NODE_SLOTS = (PW * PH + MARCH_THREADS - 1) / MARCH_THREADS;
+
+template <typename LoadN>
+MSMG_DEV auto march_loadn(LoadN& loadn, long long base, unsigned ofs, int s, int zz) {
+  if constexpr (std::is_invocable_v<LoadN&, long long, unsigned, int, int>) return loadn(base, ofs, s, zz);
+  else return loadn(base, ofs);
+}
+// convn may likewise take (raw, s)
+template <typename ConvN, typename RN>
+MSMG_DEV auto march_convn(ConvN& convn, const RN& raw, int s) {
+  if constexpr (std::is_invocable_v<ConvN&, const RN&, int>) return convn(raw, s);
+  else return convn(raw);
+}
+
 template <typename W, bool CUBIC, typename LoadN, typename ConvN, typename LoadK, typename ConvK, typename LoadC,
           typename Emit, typename After>
 MSMG_DEV void march_ex(const Geo& g, const Stencil& st, const March& mg, long long tile, W* sx, W* sk, LoadN loadn,
                        ConvN convn, LoadK loadk, ConvK convk, LoadC loadc, Emit emit, After after) {
-  using RN = decltype(loadn(0LL, 0u));
+  using RN = decltype(march_loadn(loadn, 0LL, 0u, 0, 0));
   using RK = decltype(loadk(0LL, 0u));
   using CD = decltype(loadc(0LL, 0u));
   constexpr int DEPTH = march_depth<W>();
@@ -182,9 +248,10 @@ MSMG_DEV void march_ex(const Geo& g, const Stencil& st, const March& mg, long lo
   RK pk[DEPTH][ES];
   CD pc[DEPTH];
   auto load_nodes = [&](int d, int zz) {
-    const long long base = (long long)min(max(zz, 0), g.nnz - 1) * nplane;
+    const int zc = min(max(zz, 0), g.nnz - 1);
+    const long long base = (long long)zc * nplane;
 #pragma unroll
-    for (int s = 0; s < NS; ++s) pn[d][s] = loadn(base, nofs[s]);
+    for (int s = 0; s < NS; ++s) pn[d][s] = march_loadn(loadn, base, nofs[s], s, zc);
   };
   auto load_elems = [&](int d, int ez) {
     const long long base = (long long)min(max(ez, 0), g.nz - 1) * eplane;
@@ -197,7 +264,7 @@ MSMG_DEV void march_ex(const Geo& g, const Stencil& st, const March& mg, long lo
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const int q = tid + s * MARCH_THREADS;
-      const W v = convn(pn[d][s]);
+      const W v = march_convn(convn, pn[d][s], s);
       if (q < PW * PH) sx[buf * PW * PH + q] = (zin && ((nvalid >> s) & 1u)) ? v : W(0);
     }
   };
@@ -240,7 +307,7 @@ MSMG_DEV void march_ex(const Geo& g, const Stencil& st, const March& mg, long lo
     read_plane(0, P);
     read_plane(1, A);
     read_k(0, kq);
-    carry = layer_apply<W, CUBIC>(st, kq, A, P);
+    carry = cycle_layer<W, CUBIC>(st, kq, A, P);
     __syncthreads();
   }
 #pragma unroll
@@ -267,9 +334,9 @@ MSMG_DEV void march_ex(const Geo& g, const Stencil& st, const March& mg, long lo
       W B[9], kq[4];
       read_plane(buf, B);
       read_k(buf, kq);
-      const W ax = carry + layer_apply<W, CUBIC>(st, kq, A, B);
+      const W ax = carry + cycle_layer<W, CUBIC>(st, kq, A, B);
       if (inside && z < zb) emit((long long)z * nplane, cxy, ax, A[4], cur);
-      carry = layer_apply<W, CUBIC>(st, kq, B, A);
+      carry = cycle_layer<W, CUBIC>(st, kq, B, A);
 #pragma unroll
       for (int q = 0; q < 9; ++q) A[q] = B[q];
       after(z, za, zb);

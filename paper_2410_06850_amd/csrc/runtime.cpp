@@ -361,7 +361,7 @@ extern "C" void msmg_default_options(msmg_options* o) {
   o->rho_storage = MSMG_F64;
   o->lean_memory = 0;
   o->cc_group = 0;
-  o->coarse_fused = 3;
+  o->coarse_fused = 7;
   o->pair_rhs = 0;
 }
 
@@ -735,11 +735,20 @@ static constexpr unsigned LEVEL1_SPIN_LIMIT = 1u << 22;
 
 // Levels 1 and 2 of Algorithm 1 and the prolongation to level 0:
 // v_r2 = r1 + R_c^T e_c from the restricted residual c_rc.
-static void coarse_correction(msmg_handle* h, const Ctx& c, VecSet& V, hipStream_t s) {
+// Levels 1 and 2 of Algorithm 1 and the prolongation r2 = r1 + R_c^T e_c.
+// With e1 given, the prolongation is left to the caller: e_c = *e1 + *e2
+// (*e2 may be null).
+static void coarse_correction(msmg_handle* h, const Ctx& c, VecSet& V, hipStream_t s, const double** e1 = nullptr,
+                              const double** e2 = nullptr) {
   if (h->l1_blocks > 0) {
     // every coarse step in one grid-synchronised launch; c_x0 ends as e_c
     if (launch_level1(c, h->l1_blocks, (const double*)V.c_rc, (double*)V.c_x0, (double*)V.c_t, V.rcc,
                       h->l1_bar, LEVEL1_SPIN_LIMIT, s) == hipSuccess) {
+      if (e1) {
+        *e1 = (const double*)V.c_x0;
+        *e2 = nullptr;
+        return;
+      }
       launch_prolong(c, V.v_r1, V.c_x0, nullptr, V.v_r2, s);
       return;
     }
@@ -754,6 +763,11 @@ static void coarse_correction(msmg_handle* h, const Ctx& c, VecSet& V, hipStream
   launch_cc_prolong(c, V.c_x0, V.ecc, V.c_x1, s);                // rc1 = rc0 + R_cc^T ecc
   launch_ac_residual(c, V.c_rc, V.c_x1, V.c_t, s);               // rc - A_c rc1
   launch_gs_sweep(c, V.c_t, V.c_d, false, s);                     // S_c^-T (...)
+  if (e1) {
+    *e1 = (const double*)V.c_x1;
+    *e2 = (const double*)V.c_d;
+    return;
+  }
   launch_prolong(c, V.v_r1, V.c_x1, V.c_d, V.v_r2, s);          // r2 = r1 + R_c^T ec (FP64)
 }
 
@@ -779,8 +793,14 @@ static void precondition(msmg_handle* h, const Ctx& c, VecSet& V, const double* 
     launch_vresidual(c, r, true, V.v_r1, v64, V.v_res, s);        // r0 - A r1
     launch_restrict(c, V.v_res, V.c_rc, s);                       // rc = R_c (r0 - A r1)
   }
-  coarse_correction(h, c, V, s);                                       // r2 = r1 + R_c^T e_c
-  launch_vresidual(c, r, true, V.v_r2, true, V.v_res, s);         // r0 - A r2
+  if (h->opt.coarse_fused & 4) {
+    const double *e1 = nullptr, *e2 = nullptr;
+    coarse_correction(h, c, V, s, &e1, &e2);                           // e_c
+    launch_vresidual_prolong(c, r, V.v_r1, e1, e2, V.v_res, (double*)V.v_r2, s);  // r2 = r1 + R_c^T e_c, r0 - A r2
+  } else {
+    coarse_correction(h, c, V, s);                                     // r2 = r1 + R_c^T e_c
+    launch_vresidual(c, r, true, V.v_r2, true, V.v_res, s);       // r0 - A r2
+  }
   if (fused) {
     launch_smooth_output(c, V.v_res, false, (const double*)V.v_r2, z, r, q, mode, s);  // y = r2 + S^-T (...)
     return;

@@ -1,0 +1,54 @@
+"""The fused launches of the cycle against the one-launch-per-step cycle
+(Algorithm 1): options.coarse_fused bit 0 (levels 1 and 2 in one
+grid-synchronised launch), bit 1 (the restriction in the first residual) and
+bit 2 (the prolongation in the residual after the coarse correction).
+
+Bit 2 repeats the separate kernels' arithmetic node by node, so it must leave
+z = M^-1 r unchanged to the bit; bits 0 and 1 change the order of sums and
+are held to 1e-13 of |z|.  The default (all fused) cycle is the one the
+oracle parity tests check."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from gpu_common import KMAX, P, field, patch_mask, to_dev  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+MIXED = dict(vcycle_dtype=0, rho_v_dtype=2, basis_dtype=1)
+
+
+def _z(n, rho, mask, kmin, H, sd, r, **opts):
+    import paper_2410_06850_amd as pkg
+
+    s = pkg.Solver(n, H=H, sd=sd, **opts)
+    s.setup(to_dev(rho), kmin, KMAX, P, to_dev(mask, torch.uint8))
+    z = s.precondition(to_dev(r))
+    f = s.element_load(const=1.0)
+    T, info = s.solve(f, rtol=1e-10, maxit=500)
+    return z, T, info
+
+
+@pytest.mark.parametrize("n,kind,kmin,H,sd,opts", [
+    (16, "noise", 1e-3, 8, 2, {}),
+    (24, "grf", 1e-4, 4, 3, {}),
+    (24, "grf", 1e-6, 4, 3, MIXED),
+    (20, "grf", 1e-4, 4, 2, {}),  # 5 coarse cells per axis with a remainder-free split
+])
+def test_fused_cycles_match(n, kind, kmin, H, sd, opts):
+    print(f"case fusion cube{n}_{kind} kmin={kmin} H={H} sd={sd} opts={opts}", flush=True)
+    rho = field(n, kind, 5)
+    mask = patch_mask(n)
+    r = np.random.default_rng(7).standard_normal((n + 1) ** 3)
+    r[mask.astype(bool)] = 0.0
+    out = {b: _z(n, rho, mask, kmin, H, sd, r, coarse_fused=b, **opts) for b in (0, 4, 3, 7)}
+    # bit 2 alone is exact, with and without the other fusions
+    assert torch.equal(out[0][0], out[4][0]) and torch.equal(out[3][0], out[7][0])
+    assert torch.equal(out[0][1], out[4][1]) and torch.equal(out[3][1], out[7][1])
+    assert out[0][2].iterations == out[4][2].iterations and out[3][2].iterations == out[7][2].iterations
+    z0, z7 = out[0][0].cpu().numpy(), out[7][0].cpu().numpy()
+    err = np.abs(z7 - z0).max() / np.abs(z0).max()
+    print(f"  fused vs separate launches: max |dz| / max |z| = {err:.2e}; iterations "
+          f"{out[0][2].iterations} / {out[7][2].iterations}", flush=True)
+    assert err <= 1e-13

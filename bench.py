@@ -37,6 +37,7 @@ ELL = 16
 KMIN = 1e-6
 RTOL = 1e-8
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6  # dense FP64 (matrix cores)
 
 
 def _log(msg):
@@ -607,6 +608,24 @@ def main():
         errors["reference"] = sols["ref_info"]
     del sols
 
+    def setup_report(recs, n):
+        # set-up phases from HIP events inside the timed set-ups (options.timing);
+        # the dense inversions (shifted coarse-coarse matrices, A_cc) with their
+        # n^3 flops against the FP64 peak
+        ph = np.mean([r["info"]["setup_phase_ms"] for r in recs], axis=0)
+        dms = float(np.mean([r["info"]["setup_dense_ms"] for r in recs]))
+        dgf = float(recs[-1]["info"]["setup_dense_gflop"])
+        ncells = (n // 8) ** 3
+        return {
+            "ms": 1e3 * float(np.mean([r["setup"] for r in recs])),
+            "phases_ms": {"local_spectral_problems": float(ph[0]), "galerkin_Ac": float(ph[1]),
+                          "coarse_coarse_problems": float(ph[2]), "Acc_and_inverse": float(ph[3])},
+            "local_problems_per_s": ncells / (float(ph[0]) * 1e-3) if ph[0] > 0 else None,
+            "dense_inverses": {"ms": dms, "gflop": dgf, "tflops": dgf / dms if dms > 0 else None,
+                               "peak_tflops": FP64_PEAK_TFLOPS,
+                               "frac": dgf / dms / FP64_PEAK_TFLOPS if dms > 0 else None},
+        }
+
     cpu = None
     if not args.no_cpu_baseline:
         _log("CPU oracle baseline")
@@ -641,6 +660,7 @@ def main():
         "solve_ms": 1e3 * t_solve,
         "setup_ms": 1e3 * float(np.mean([r["setup"] for r in mix])),
         "precond_us": 1e3 * float(np.mean([r["info"]["precond_ms"] for r in mix])),
+        "setup": setup_report(mix, n),
         "paths": others,
         "solution_errors": errors,
         "roofline": {

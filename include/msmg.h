@@ -127,6 +127,11 @@ typedef struct msmg_info {
   int timed;               /* iterations timed (options.timing)                  */
   double apply_ms;         /* mean duration of the PCG operator apply kernel     */
   double precond_ms;       /* mean duration of one preconditioner application    */
+  double setup_phase_ms[4]; /* timing: the last set-up's phases (HIP events):    */
+                            /* local spectral problems, Galerkin A_c, the        */
+                            /* coarse-coarse problems, A_cc and its inverse      */
+  double setup_dense_ms;    /* timing: of these, the dense Gauss-Jordan inverses */
+  double setup_dense_gflop; /* their flop count, n^3 per n x n inverse           */
 } msmg_info;
 
 /* Hierarchy sizes for a mesh and options; host only, no GPU needed. */

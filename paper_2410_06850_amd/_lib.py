@@ -69,6 +69,9 @@ class Info(ctypes.Structure):
         ("timed", ctypes.c_int),
         ("apply_ms", ctypes.c_double),
         ("precond_ms", ctypes.c_double),
+        ("setup_phase_ms", ctypes.c_double * 4),
+        ("setup_dense_ms", ctypes.c_double),
+        ("setup_dense_gflop", ctypes.c_double),
     ]
 
 

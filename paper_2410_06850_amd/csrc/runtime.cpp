@@ -117,6 +117,9 @@ struct msmg_handle {
   TuneChoice tune[2]{};  // level-1 launch shapes per cell class
   std::vector<void*> allocs;
   std::vector<hipEvent_t> events;  // timing mode: 4 per timed iteration
+  std::vector<hipEvent_t> setup_events;  // timing mode: set-up phases (SETUP_EVENTS)
+  double setup_phase_ms[4] = {0, 0, 0, 0};
+  double setup_dense_ms = 0.0, setup_dense_gflop = 0.0;
 };
 
 static size_t dt_size(int dt) { return dt == DT_F64 ? 8 : (dt == DT_F32 ? 4 : 2); }
@@ -315,6 +318,8 @@ static int dev_alloc(msmg_handle* h, T** p, size_t bytes) {
 static void free_all(msmg_handle* h) {
   for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
   h->events.clear();
+  for (hipEvent_t e : h->setup_events) (void)hipEventDestroy(e);
+  h->setup_events.clear();
   for (void* p : h->allocs) (void)hipFree(p);
   h->allocs.clear();
   for (VecSet& V : h->vs) {
@@ -588,8 +593,17 @@ extern "C" int msmg_create(msmg_handle** out, int nx, int ny, int nz, double lx,
   for (VecSet& V : h->vs)
     if (V.sc) HIP_TRY(hipMemset(V.sc, 0, sizeof(Scalars)));
   if (o.timing) {
-    // events of the per-iteration timing (created here, outside any solve)
+    // events of the per-iteration and set-up timing (created here, outside any solve)
     h->events.resize(4 * 512);
+    h->setup_events.resize(SETUP_EVENTS);
+    for (auto& e : h->setup_events) {
+      hipError_t err = hipEventCreate(&e);
+      if (err != hipSuccess) {
+        e = nullptr;
+        msmg_destroy(h);
+        return fail(MSMG_EHIP, std::string("hipEventCreate: ") + hipGetErrorString(err));
+      }
+    }
     for (auto& e : h->events) {
       hipError_t err = hipEventCreate(&e);
       if (err != hipSuccess) {
@@ -712,12 +726,23 @@ extern "C" int msmg_setup(msmg_handle* h, const void* rho, msmg_dtype rho_dtype,
     a.warm = (h->opt.eig_warm_start && h->has_basis) ? 1 : 0;
     h->has_basis = false;
     a.tune = h->tune;
+    a.ev = h->setup_events.empty() ? nullptr : h->setup_events.data();
     SetupReport rep{};
     const int r = run_setup(c, a, &h->scratch, &rep, s);
     if (r != MSMG_OK) return fail(r, std::string("set-up failed: ") + rep.msg);
     h->eig_unconverged = rep.eig_unconverged;
     h->cc_unconverged = rep.cc_unconverged;
     h->eig_ties = rep.eig_ties;
+    if (a.ev) {
+      HIP_TRY(hipEventSynchronize(a.ev[4]));
+      for (int k = 0; k < 4; ++k) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, a.ev[k], a.ev[k + 1]));
+        h->setup_phase_ms[k] = ms;
+      }
+      h->setup_dense_ms = rep.dense_ms;
+      h->setup_dense_gflop = rep.dense_gflop;
+    }
   }
   HIP_TRY(hipStreamSynchronize(s));
   HIP_TRY(hipGetLastError());
@@ -925,6 +950,12 @@ extern "C" int msmg_prolong_element(int nx, int ny, int nz, const void* rc, void
   return MSMG_OK;
 }
 
+static void fill_setup_timing(const msmg_handle* h, msmg_info* info) {
+  for (int k = 0; k < 4; ++k) info->setup_phase_ms[k] = h->setup_phase_ms[k];
+  info->setup_dense_ms = h->setup_dense_ms;
+  info->setup_dense_gflop = h->setup_dense_gflop;
+}
+
 // PCG driver shared by the state and adjoint solves.  `homogeneous` solves
 // with zero fixed values (the adjoint system), ignoring the set-up's values.
 static int solve_impl(msmg_handle* h, const double* f, double* T, double* T_lo, int use_x0, double rtol, int maxit,
@@ -1050,6 +1081,7 @@ static int solve_impl(msmg_handle* h, const double* f, double* T, double* T_lo, 
     info->rel_res = rel;
     info->solve_ms = now_ms() - t0;
     info->setup_ms = h->setup_ms;
+    fill_setup_timing(h, info);
     info->n_c = h->n_c;
     info->n_cc = h->n_cc;
     info->eig_unconverged = h->eig_unconverged;
@@ -1264,6 +1296,7 @@ static int solve_pair_impl(msmg_handle* h, const double* f, double* T, double* T
     in->rel_res = S[k].rel;
     in->solve_ms = ms;
     in->setup_ms = h->setup_ms;
+    fill_setup_timing(h, in);
     in->n_c = h->n_c;
     in->n_cc = h->n_cc;
     in->eig_unconverged = h->eig_unconverged;

@@ -81,14 +81,23 @@ struct SetupArgs {
   const msmg_options* opt;
   int warm;  // level-1 solver starts from the basis left in Rc64 by the previous set-up
   TuneChoice* tune;  // per level-1 cell class: [0] regular cells, [1] the rest
+  // timing (null: none): SETUP_EVENTS events; the phase boundaries are
+  // recorded in ev[0 .. 4], ev[5], ev[6] bracket each dense inversion
+  hipEvent_t* ev;
 };
+constexpr int SETUP_EVENTS = 7;
 
 struct SetupReport {
   int eig_unconverged;
   int cc_unconverged;
   int eig_ties;
+  double dense_ms;     // with timing: the dense Gauss-Jordan inversions
+  double dense_gflop;  // and their flop count (n^3 per n x n sweep inverse)
   char msg[256];
 };
+// time one dense batched inversion (n x n, batch of them) into rep when the
+// set-up is timed
+int timed_gj_inverse(const SetupArgs& sa, SetupReport* rep, int n, int batch, double* A, double* work, hipStream_t s);
 
 int setup_scratch_alloc(const Geo& g, const Hier& h, int max_cc_dofs, int n_cc, const msmg_options& o, SetupScratch* s,
                         const std::function<int(void**, size_t)>& alloc);

@@ -1223,7 +1223,8 @@ void launch_block_inverse(const Ctx& c, double* Ac, double* Dinv, hipStream_t s)
 
 // One group of cc cells (J0 .. J0 + nJ - 1): start block, dense path for small
 // cells, shift-invert subspace iteration with Rayleigh-Ritz on G, R_cc rows.
-static int run_cc_group(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, CCArgs a, hipStream_t s) {
+static int run_cc_group(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, CCArgs a, SetupReport* rep,
+                        hipStream_t s) {
   const Hier& h = c.h;
   const int m = a.m, nJ = a.nJ, J0 = a.J0;
   const long long ndof = (long long)h.ncells * h.Lc;
@@ -1284,7 +1285,7 @@ static int run_cc_group(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, CCA
   hipLaunchKernelGGL(k_ccd_assemble, dim3((unsigned)(((long long)ndm * ndm + 255) / 256), nJ), dim3(256), 0, s, a,
                      ndm, par, sc->Gd);
   {
-    const int r = gj_inverse(ndm, nJ, sc->Gd, sc->gj, s);
+    const int r = timed_gj_inverse(sa, rep, ndm, nJ, sc->Gd, sc->gj, s);
     if (r != MSMG_OK) return r;
   }
   const dim3 ga((ndm + CCD_ROWS - 1) / CCD_ROWS, nJ), ba(256);
@@ -1310,7 +1311,8 @@ static int run_cc_group(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, CCA
   return hipGetLastError() == hipSuccess ? MSMG_OK : MSMG_EHIP;
 }
 
-int run_cc_eigen(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, const double* G, int* n_unconv, hipStream_t s) {
+int run_cc_eigen(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, const double* G, int* n_unconv, SetupReport* rep,
+                 hipStream_t s) {
   const Hier& h = c.h;
   CCArgs a;
   a.h = h;
@@ -1326,7 +1328,7 @@ int run_cc_eigen(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, const doub
   for (int J0 = 0; J0 < h.ncc; J0 += sc->cc_group) {
     a.J0 = J0;
     a.nJ = std::min(sc->cc_group, h.ncc - J0);
-    const int r = run_cc_group(c, sa, sc, a, s);
+    const int r = run_cc_group(c, sa, sc, a, rep, s);
     if (r != MSMG_OK) return r;
   }
   int* flag = sc->ccflag;

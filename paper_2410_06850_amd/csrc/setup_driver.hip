@@ -16,7 +16,8 @@ namespace msmg {
 
 int launch_galerkin(const Ctx& c, const void* R, int b_dt, int drop_cc, double* out, hipStream_t s);
 void launch_block_inverse(const Ctx& c, double* Ac, double* Dinv, hipStream_t s);
-int run_cc_eigen(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, const double* G, int* n_unconv, hipStream_t s);
+int run_cc_eigen(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, const double* G, int* n_unconv, SetupReport* rep,
+                 hipStream_t s);
 int build_acc(const Ctx& c, const SetupArgs& sa, double* u, hipStream_t s);
 void launch_convert(const void* in, int din, void* out, int dout, long long n, hipStream_t s);
 
@@ -180,8 +181,27 @@ static int build_cell_classes(const Hier& h, const Geo& g, SetupScratch* sc, hip
   return MSMG_OK;
 }
 
+int timed_gj_inverse(const SetupArgs& sa, SetupReport* rep, int n, int batch, double* A, double* work, hipStream_t s) {
+  if (sa.ev && hipEventRecord(sa.ev[5], s) != hipSuccess) return MSMG_EHIP;
+  const int r = gj_inverse(n, batch, A, work, s);
+  if (r != MSMG_OK || !sa.ev) return r;
+  float ms = 0.f;
+  if (hipEventRecord(sa.ev[6], s) != hipSuccess || hipEventSynchronize(sa.ev[6]) != hipSuccess ||
+      hipEventElapsedTime(&ms, sa.ev[5], sa.ev[6]) != hipSuccess)
+    return MSMG_EHIP;
+  rep->dense_ms += ms;
+  rep->dense_gflop += double(batch) * double(n) * double(n) * double(n) * 1e-9;
+  return MSMG_OK;
+}
+
 int run_setup(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, SetupReport* rep, hipStream_t s) {
   std::memset(rep, 0, sizeof(*rep));
+  // phase boundaries for the timing mode: 0 start, 1 after the local problems,
+  // 2 after A_c, 3 after the coarse-coarse problems, 4 after A_cc^-1
+  auto mark = [&](int k) {
+    if (sa.ev) (void)hipEventRecord(sa.ev[k], s);
+  };
+  mark(0);
   const Hier& h = c.h;
   const msmg_options& o = *sa.opt;
   int dev = 0, cus = 256;
@@ -224,6 +244,7 @@ int run_setup(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, SetupReport* 
   }
   if ((r = count_unconverged(sa, h.ncells, &rep->eig_unconverged, &rep->eig_ties, s))) return r;
 
+  mark(1);
   // 2. stored copy of R_c, Galerkin A_c from the stored values
   const long long nb = c.g.nn * h.Lc;
   if (sa.Rcs != (void*)sa.Rc64) launch_convert(sa.Rc64, DT_F64, sa.Rcs, sa.b_dt, nb, s);
@@ -235,21 +256,24 @@ int run_setup(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, SetupReport* 
     launch_convert(sa.AcDinv64, DT_F64, sa.AcDinvv, sa.a_dt, (long long)sa.n_c * h.Lc, s);
   }
 
+  mark(2);
   // 3. coarse-coarse spectral problems eq. (spectral cc) on the FP64 basis
   if ((r = launch_galerkin(c, sa.Rc64, DT_F64, 1, sa.G64, s))) return hip_ok(hipGetLastError(), rep, "Galerkin G");
-  if ((r = run_cc_eigen(c, sa, sc, sa.G64, &rep->cc_unconverged, s))) {
+  if ((r = run_cc_eigen(c, sa, sc, sa.G64, &rep->cc_unconverged, rep, s))) {
     std::snprintf(rep->msg, sizeof(rep->msg), "coarse-coarse eigensolver failed");
     return r;
   }
   if (sa.Rccv != sa.Rcc64) launch_convert(sa.Rcc64, DT_F64, sa.Rccv, DT_F32, (long long)h.Lcc * sa.n_c, s);
 
+  mark(3);
   // 4. A_cc = R_cc A_c R_cc^T from the cycle's copies, then its inverse
   if ((r = build_acc(c, sa, sc->Y, s))) return hip_ok(hipGetLastError(), rep, "A_cc");
   const size_t nn2 = (size_t)sa.n_cc * sa.n_cc * 8;
   if (sc->acc_copy &&
       (r = hip_ok(hipMemcpyAsync(sc->acc_copy, sa.Acc, nn2, hipMemcpyDeviceToDevice, s), rep, "A_cc copy")))
     return r;
-  if ((r = gj_inverse(sa.n_cc, 1, sa.Acc, sc->gj, s))) return hip_ok(hipGetLastError(), rep, "A_cc inverse");
+  if ((r = timed_gj_inverse(sa, rep, sa.n_cc, 1, sa.Acc, sc->gj, s))) return hip_ok(hipGetLastError(), rep, "A_cc inverse");
+  mark(4);
   return hip_ok(hipGetLastError(), rep, "set-up");
 }
 

@@ -40,6 +40,14 @@ def _need(t, name, dtype, numel, device):
 _DT = {torch.float64: L.MSMG_F64, torch.float32: L.MSMG_F32}
 
 
+def _info(info):
+    d = {}
+    for k, _ in L.Info._fields_:
+        v = getattr(info, k)
+        d[k] = list(v) if isinstance(v, ctypes.Array) else v
+    return SolveInfo(d)
+
+
 class SolveInfo(dict):
     __getattr__ = dict.__getitem__
 
@@ -109,7 +117,7 @@ class Solver:
         code = L.check(L.lib().msmg_solve(self._h, _ptr(f), _ptr(T), _ptr(T_lo) if T_lo is not None else None,
                                           int(bool(use_x0)), float(rtol), int(maxit), ctypes.byref(info), _stream()),
                        "msmg_solve")
-        out = SolveInfo({k: getattr(info, k) for k, _ in L.Info._fields_})
+        out = _info(info)
         out["code"] = code
         return T, out
 
@@ -128,7 +136,7 @@ class Solver:
                                                   _ptr(lam_lo) if lam_lo is not None else None, int(bool(use_x0)),
                                                   float(rtol), int(maxit), ctypes.byref(info), _stream()),
                        "msmg_solve_adjoint")
-        out = SolveInfo({k: getattr(info, k) for k, _ in L.Info._fields_})
+        out = _info(info)
         out["code"] = code
         return lam, out
 
@@ -150,7 +158,7 @@ class Solver:
                                                _stream()), "msmg_solve_pair")
         outs = []
         for inf in (i1, i2):
-            o = SolveInfo({k: getattr(inf, k) for k, _ in L.Info._fields_})
+            o = _info(inf)
             o["code"] = code
             outs.append(o)
         return T, lam, outs[0], outs[1]

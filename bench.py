@@ -403,7 +403,7 @@ def run_workload(name, args):
         del T, f, s, rho_c
         torch.cuda.empty_cache()
         n = 1024
-        opts = dict(lean, rho_storage=1, lean_memory=1)
+        opts = dict(lean, rho_storage=1, lean_memory=1, timing=1)
         mask_np = synth.dirichlet_patch_mask(n, n, n).ravel()
         free = int((n + 1) ** 3 - int(mask_np.sum()))
         s = pkg.Solver(n, tune_cache=tune, **opts)
@@ -420,7 +420,9 @@ def run_workload(name, args):
         f = s.element_load(const=1.0)
         T, cold = s.solve(f, rtol=RTOL, maxit=2000)
         res["fine_cold"] = dict(n=n, iterations=cold.iterations, solve_ms=cold.solve_ms, code=cold.code,
-                                rel_res=cold.rel_res, dofs_per_s=free / (1e-3 * cold.solve_ms))
+                                rel_res=cold.rel_res, dofs_per_s=free / (1e-3 * cold.solve_ms),
+                                apply_us=1e3 * cold.apply_ms, precond_us=1e3 * cold.precond_ms,
+                                setup_phase_ms=cold.setup_phase_ms)
         _log(json.dumps(res["fine_cold"]))
         T, warm = s.solve(f, x0, rtol=RTOL, maxit=2000, use_x0=True)
         res["fine_warm"] = dict(n=n, iterations=warm.iterations, solve_ms=warm.solve_ms, code=warm.code,
@@ -552,7 +554,7 @@ def main():
     # with HIP events on the solve stream inside the timed steps
     apply_ms = float(np.mean([r["info"]["apply_ms"] for r in mix]))
     nn, ne = (n + 1) ** 3, n ** 3
-    apply_bytes = 16 * nn + 8 * ne + nn / 8  # p read, q written, k read, mask bits
+    apply_bytes = 16 * nn + 8 * ne + nn / 8  # p read, q written, the FP64 density read, mask bits
     achieved = apply_bytes / (apply_ms * 1e-3) / 1e9
     traffic = measured_traffic() if n == N else None
 

@@ -36,12 +36,13 @@ __global__ void k_convert(const Tin* __restrict__ in, Tout* __restrict__ out, lo
 }
 
 // Element conductivities k_e = k_min + rho_e^p (k_max - k_min) in FP64 (the
-// material law), computed once per density field for the solve kernels.
-template <typename RT>
-__global__ void k_conductivity(const RT* __restrict__ rho, double* __restrict__ kc, long long ne, Material m) {
+// material law), computed once per density field for the cycle's kernels.
+// OT: the stored type (FP64, or the cycle's copy rounded as k_convert rounds).
+template <typename RT, typename OT>
+__global__ void k_conductivity(const RT* __restrict__ rho, OT* __restrict__ kc, long long ne, Material m) {
   const double dk = m.kmax - m.kmin;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < ne; e += (long long)gridDim.x * blockDim.x)
-    kc[e] = conductivity<double>(to_f64<RT>(rho[e]), m.kmin, dk, m.p);
+    kc[e] = from_f64<OT>(conductivity<double>(to_f64<RT>(rho[e]), m.kmin, dk, m.p));
 }
 
 // Jacobi diagonal inverse: D_n = self * sum of the 8 k_e around n; 0 on fixed nodes.
@@ -217,9 +218,12 @@ struct ApplyCentre {
 // y = A x on free rows (MODE 0: 0 on fixed rows; MODE 1: also p^T (A p) ->
 // alpha; MODE 2: xr, the caller's raw input, on fixed rows), on the march
 // whose prefetch queue sits in LDS.  The staged input x is zero on fixed nodes.
-template <bool CUBIC, int MODE, int NS>
+// KT double: the stored FP64 conductivities; KT float: the FP32 canonical
+// density, taken through the material law as the element layers are read (the
+// value k_conductivity stores), so the apply streams 4 B per element.
+template <bool CUBIC, int MODE, int NS, typename KT>
 MSMG_MARCH_KERNEL void k_apply(
-    Geo g, Stencil st, March mg, const double* __restrict__ kc, const uint32_t* __restrict__ bits,
+    Geo g, Stencil st, March mg, const KT* __restrict__ kin, Material mat, const uint32_t* __restrict__ bits,
     Two<const double*> xs, Two<const double*> xrs, Two<double*> ys, Two<Scalars*> scs, Two<double*> partials,
     Two<unsigned*> counters) {
   const SideBlock sb = side_block<NS>();
@@ -228,12 +232,17 @@ MSMG_MARCH_KERNEL void k_apply(
   const double* __restrict__ x = xs[sb.side];
   const double* __restrict__ xr = xrs[sb.side];
   double* __restrict__ y = ys[sb.side];
-  MSMG_LDS_BUFFERS(double)
+  MSMG_LDS_BUFFERS(KT)
   __shared__ double red[16];
   const long long tile = xcd_tile(sb.blk, sb.nblk);
   double s[1] = {0.0};
+  const double dk = mat.kmax - mat.kmin;
   march_lds<CUBIC>(
-      g, st, mg, tile, bufs, x, kc,
+      g, st, mg, tile, bufs, x, kin,
+      [&](KT v) {
+        if constexpr (sizeof(KT) == 8) return double(v);
+        else return conductivity<double>(to_f64<KT>(v), mat.kmin, dk, mat.p);
+      },
       [&](long long b, unsigned o) {
         ApplyCentre c;
         c.w = bits[(b + o) >> 5];
@@ -1104,12 +1113,15 @@ void launch_convert(const void* in, int din, void* out, int dout, long long n, h
 #undef CONV
 }
 
-void launch_conductivity(const Ctx& c, const void* rho, int rdt, double* kc, hipStream_t s) {
+void launch_conductivity(const Ctx& c, const void* rho, int rdt, void* kc, int kdt, hipStream_t s) {
   const dim3 gr(grid1d(c.g.ne, 256, 8192)), bl(256);
-  if (rdt == DT_F64)
-    hipLaunchKernelGGL((k_conductivity<double>), gr, bl, 0, s, (const double*)rho, kc, c.g.ne, c.mat);
-  else
-    hipLaunchKernelGGL((k_conductivity<float>), gr, bl, 0, s, (const float*)rho, kc, c.g.ne, c.mat);
+#define KCD(RT, OT) hipLaunchKernelGGL((k_conductivity<RT, OT>), gr, bl, 0, s, (const RT*)rho, (OT*)kc, c.g.ne, c.mat)
+  if (rdt == DT_F64) {
+    if (kdt == DT_F64) KCD(double, double); else if (kdt == DT_F32) KCD(double, float); else KCD(double, bf16);
+  } else {
+    if (kdt == DT_F64) KCD(float, double); else if (kdt == DT_F32) KCD(float, float); else KCD(float, bf16);
+  }
+#undef KCD
 }
 
 void launch_diag_inv(const Ctx& c, const void* rho, int rdt, void* dinv, int vdt, hipStream_t s) {
@@ -1173,7 +1185,7 @@ long long apply_resident_blocks() {
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 2048;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 2048;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(&k_apply<true, 1, 1>),
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(&k_apply<true, 1, 1, double>),
                                                    MARCH_THREADS, 0) != hipSuccess)
     return 2048;
   return (long long)(per > 0 ? per : 1) * (cus > 0 ? cus : 1);
@@ -1181,9 +1193,11 @@ long long apply_resident_blocks() {
 
 void launch_apply(const Ctx& c, const double* x, double* y, int mode, hipStream_t s, const double* xraw) {
   const dim3 gr((unsigned)c.mgl.blocks), bl(LMX, LMY);
-#define APL(CU, MD) hipLaunchKernelGGL((k_apply<CU, MD, 1>), gr, bl, 0, s, c.g, c.st, c.mgl, c.kc, c.bits, one(x), one(xraw), one(y), one(c.sc), one(c.partials), one(c.counter))
-#define AP_M(CU) do { if (mode == 0) APL(CU, 0); else if (mode == 1) APL(CU, 1); else APL(CU, 2); } while (0)
-  if (c.st.cubic) AP_M(true); else AP_M(false);
+#define APL(CU, MD, KT, P) hipLaunchKernelGGL((k_apply<CU, MD, 1, KT>), gr, bl, 0, s, c.g, c.st, c.mgl, (const KT*)(P), c.mat, c.bits, one(x), one(xraw), one(y), one(c.sc), one(c.partials), one(c.counter))
+#define AP_M(CU, KT, P) do { if (mode == 0) APL(CU, 0, KT, P); else if (mode == 1) APL(CU, 1, KT, P); else APL(CU, 2, KT, P); } while (0)
+  // FP64 density: the stored FP64 conductivities; FP32: the density itself
+  if (c.kc) { if (c.st.cubic) AP_M(true, double, c.kc); else AP_M(false, double, c.kc); }
+  else { if (c.st.cubic) AP_M(true, float, c.rho); else AP_M(false, float, c.rho); }
 #undef AP_M
 #undef APL
 }
@@ -1191,8 +1205,9 @@ void launch_apply(const Ctx& c, const double* x, double* y, int mode, hipStream_
 void launch_apply_pair(const Ctx& a, const Ctx& b, const double* xa, const double* xb, double* ya, double* yb,
                        hipStream_t s) {
   const dim3 gr((unsigned)(2 * a.mgl.blocks)), bl(LMX, LMY);
-#define APL(CU) hipLaunchKernelGGL((k_apply<CU, 1, 2>), gr, bl, 0, s, a.g, a.st, a.mgl, a.kc, a.bits, two(xa, xb), two((const double*)nullptr, (const double*)nullptr), two(ya, yb), two(a.sc, b.sc), two(a.partials, b.partials), two(a.counter, b.counter))
-  if (a.st.cubic) APL(true); else APL(false);
+#define APL(CU, KT, P) hipLaunchKernelGGL((k_apply<CU, 1, 2, KT>), gr, bl, 0, s, a.g, a.st, a.mgl, (const KT*)(P), a.mat, a.bits, two(xa, xb), two((const double*)nullptr, (const double*)nullptr), two(ya, yb), two(a.sc, b.sc), two(a.partials, b.partials), two(a.counter, b.counter))
+  if (a.kc) { if (a.st.cubic) APL(true, double, a.kc); else APL(false, double, a.kc); }
+  else { if (a.st.cubic) APL(true, float, a.rho); else APL(false, float, a.rho); }
 #undef APL
 }
 

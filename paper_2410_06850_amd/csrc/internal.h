@@ -59,8 +59,9 @@ struct Ctx {
   March mgl;          // the same for the LDS-queue apply (its own tile shape)
   const void* rho;    // canonical density (rho_dt)
   int rho_dt;
-  const double* kc;   // element conductivities, FP64
-  const void* kv;     // conductivity copy read by the cycle (kv_dt; aliases kc for FP64)
+  const double* kc;   // FP64 element conductivities for an FP64 density (null for FP32:
+                      // the apply forms them from rho)
+  const void* kv;     // element conductivities read by the cycle (kv_dt; may alias kc)
   int kv_dt;
   const uint32_t* bits;
   void* dinv;         // Jacobi D^-1, V-cycle type
@@ -115,7 +116,7 @@ long long march_resident_blocks();  // marching workgroups the device runs at on
 long long apply_resident_blocks();  // the same for the LDS-queue apply
 void launch_pack_mask(const uint8_t* mask, uint32_t* bits, long long nn, hipStream_t s);
 void launch_convert(const void* in, int din, void* out, int dout, long long n, hipStream_t s);
-void launch_conductivity(const Ctx& c, const void* rho, int rdt, double* kc, hipStream_t s);
+void launch_conductivity(const Ctx& c, const void* rho, int rdt, void* kc, int kdt, hipStream_t s);
 void launch_diag_inv(const Ctx& c, const void* rho, int rdt, void* dinv, int vdt, hipStream_t s);
 void launch_zero_fixed_copy(const Ctx& c, const double* in, double* out, hipStream_t s);
 void launch_finish_solution(const Ctx& c, double* T, const double* tfix, hipStream_t s);

@@ -428,13 +428,15 @@ MSMG_DEV void for_each_step(F&& f, std::integer_sequence<int, J...>) {
   (f(StepIdx<J>{}), ...);
 }
 
-// Staged nodes are FP64 (x), elements KT (kc, converted to FP64 when read).
-// loadc(b, o) -> per-node data of node b + o (register queue, LDS_NB slots);
-// emit as in march().  bufs: the LDS_NB buffers of LdsLayout<KT>::BUF_D
-// doubles, each a separate LDS array.
-template <bool CUBIC, typename KT, typename LoadC, typename Emit>
+// Staged nodes are FP64 (x), elements KT (an element array, turned into the
+// FP64 conductivity by convk when read: a stored conductivity or the density
+// through the material law).  loadc(b, o) -> per-node data of node b + o
+// (register queue, LDS_NB slots); emit as in march().  bufs: the LDS_NB
+// buffers of LdsLayout<KT>::BUF_D doubles, each a separate LDS array.
+template <bool CUBIC, typename KT, typename ConvK, typename LoadC, typename Emit>
 MSMG_DEV void march_lds(const Geo& g, const Stencil& st, const March& mg, long long tile, double* const* bufs,
-                        const double* __restrict__ x, const KT* __restrict__ kc, LoadC loadc, Emit emit) {
+                        const double* __restrict__ x, const KT* __restrict__ kc, ConvK convk, LoadC loadc,
+                        Emit emit) {
   using LY = LdsLayout<KT>;
   constexpr int NI = LY::NI, INSTR = LY::INSTR, KL = LY::KL, KB = LY::KB, ELEM0 = LY::ELEM0;
   using CD = decltype(loadc(0LL, 0u));
@@ -500,13 +502,13 @@ MSMG_DEV void march_lds(const Geo& g, const Stencil& st, const March& mg, long l
   auto kval = [&](const double* buf, int e) -> double {
     const char* p = reinterpret_cast<const char*>(buf) + ELEM0;
     if constexpr (sizeof(KT) == 8) {
-      return *reinterpret_cast<const double*>(p + 8 * e);
+      return convk(*reinterpret_cast<const KT*>(p + 8 * e));
     } else if constexpr (sizeof(KT) == 4) {
-      return cvt<double, KT>(*reinterpret_cast<const KT*>(p + 4 * e));
+      return convk(*reinterpret_cast<const KT*>(p + 4 * e));
     } else {
       KT v;
       __builtin_memcpy(&v, p + 4 * e, sizeof(KT));
-      return cvt<double, KT>(v);
+      return convk(v);
     }
   };
   auto read_plane = [&](const double* src, double* dst) {
@@ -563,7 +565,7 @@ MSMG_DEV void march_lds(const Geo& g, const Stencil& st, const March& mg, long l
     __syncthreads();
     double P[9], kq[4];
     read_plane(pb, P);
-    read_k(pb, true, kq);
+    read_k(pb, za - 1 >= 0, kq);  // the layer below the mesh has no elements
     __syncthreads();
     stage_nodes(za);
     __syncthreads();

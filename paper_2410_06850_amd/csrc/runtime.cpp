@@ -66,8 +66,8 @@ struct msmg_handle {
 
   // density, mask, fixed values
   void* rho = nullptr;
-  double* kc = nullptr;   // element conductivities (FP64)
-  void* kv = nullptr;     // conductivity copy read by the cycle; may alias kc
+  double* kc = nullptr;   // FP64 element conductivities (FP64 density only)
+  void* kv = nullptr;     // element conductivities read by the cycle (kv_dt; may alias kc)
   uint32_t* bits = nullptr;
   double* tfix = nullptr;
   bool has_tfix = false;
@@ -416,8 +416,11 @@ static int alloc_arrays(msmg_handle* h, bool dry, size_t* total) {
     if (!dry && rc == MSMG_OK) rc = dev_alloc(h, p, bytes);
   };
   A(&h->rho, ne * dt_size(h->rho_store_dt));
-  A(&h->kc, ne * 8);
-  if (h->kv_dt != DT_F64) A(&h->kv, ne * dt_size(h->kv_dt));
+  // FP64 conductivities for the PCG apply when the density is FP64 (with an
+  // FP32 density the apply forms them from it); the cycle's copy
+  const bool kc64 = h->rho_store_dt == DT_F64;
+  if (kc64) A(&h->kc, ne * 8);
+  if (!(kc64 && h->kv_dt == DT_F64)) A(&h->kv, ne * dt_size(h->kv_dt));
   A(&h->bits, ((nn + 31) / 32) * 4);
   // Jacobi diagonal: FP64 only on the all-FP64 path (a fixed coefficient like rho)
   h->dv_dt = (h->v_dt == DT_F64 && h->b_dt == DT_F64) ? DT_F64 : DT_F32;
@@ -690,8 +693,8 @@ extern "C" int msmg_setup(msmg_handle* h, const void* rho, msmg_dtype rho_dtype,
     if (nfixed == 0) return fail(MSMG_ESINGULAR, "the Dirichlet mask is empty: the operator is singular");
   }
   Ctx c = make_ctx(h);
-  launch_conductivity(c, h->rho, h->rho_dt, h->kc, s);
-  if (h->kv != h->kc) launch_convert(h->kc, DT_F64, h->kv, h->kv_dt, ne, s);
+  if (h->kc) launch_conductivity(c, h->rho, h->rho_dt, h->kc, DT_F64, s);
+  if (h->kv != h->kc) launch_conductivity(c, h->rho, h->rho_dt, h->kv, h->kv_dt, s);
   launch_diag_inv(c, h->rho, h->rho_dt, h->dinv, h->dv_dt, s);
   HIP_TRY(hipGetLastError());
   if (h->mg) {

@@ -103,6 +103,7 @@ class Hierarchy:
         self.g = grid
         self.o = opts or Options()
         self.kmin, self.kmax, self.p = kmin, kmax, p
+        self.n_unknowns = grid.nnodes
         self.mask = np.asarray(mask).ravel().astype(bool)
         self.k = q1.conductivity(np.asarray(rho).ravel(), kmin, kmax, p)
         A = q1.assemble(grid, self.k)
@@ -114,9 +115,19 @@ class Hierarchy:
         self._level2()
 
     # -- partition ---------------------------------------------------------
+    def _axis_runs(self, axis):
+        """Runs of unknowns along one axis (nodes here)."""
+        return axis_runs((self.g.nx, self.g.ny, self.g.nz)[axis], self.o.H)
+
+    def _axis_unknowns(self):
+        return (self.g.nnx, self.g.nny, self.g.nnz)
+
+    def unknown_index(self, i, j, k):
+        return self.g.node_index(i, j, k)
+
     def _partition(self):
         g, o = self.g, self.o
-        self.runs = [axis_runs(g.nx, o.H), axis_runs(g.ny, o.H), axis_runs(g.nz, o.H)]
+        self.runs = [self._axis_runs(0), self._axis_runs(1), self._axis_runs(2)]
         self.nc = [len(r) for r in self.runs]
         self.groups = [axis_groups(n, o.sd) for n in self.nc]
         self.ncc = [len(gr) for gr in self.groups]
@@ -128,7 +139,7 @@ class Hierarchy:
                     self.cells.append((cx, cy, cz))
         # owner coarse cell of every node, per axis
         self.own_axis = []
-        for ax, n in enumerate((g.nnx, g.nny, g.nnz)):
+        for ax, n in enumerate(self._axis_unknowns()):
             o_ax = np.empty(n, dtype=np.int64)
             for c, (s, e) in enumerate(self.runs[ax]):
                 o_ax[s:e] = c
@@ -151,7 +162,7 @@ class Hierarchy:
         (sx, ex), (sy, ey), (sz, ez) = self.runs[0][cx], self.runs[1][cy], self.runs[2][cz]
         kk, jj, ii = np.meshgrid(np.arange(sz, ez), np.arange(sy, ey), np.arange(sx, ex),
                                  indexing="ij")
-        return self.g.node_index(ii.ravel(), jj.ravel(), kk.ravel())
+        return self.unknown_index(ii.ravel(), jj.ravel(), kk.ravel())
 
     def _box_elements(self, xr, yr, zr):
         """Elements whose 8 nodes lie in the node box xr * yr * zr (half-open ranges)."""
@@ -224,7 +235,7 @@ class Hierarchy:
             r += nl
         self.n_c = r
         self.Rc = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
-                                shape=(self.n_c, self.g.nnodes)).tocsr()
+                                shape=(self.n_c, self.n_unknowns)).tocsr()
         self.level1_operators()
 
     def level1_operators(self):
@@ -267,10 +278,14 @@ class Hierarchy:
             ok &= ga == gb
         return ok
 
-    def _level2(self):
-        o, g = self.o, self.g
+    def cc_stiffness(self):
+        """Stiffness of the elements inside one coarse-coarse cell, masked."""
         elems = np.flatnonzero(self.cc_elements_mask())
-        Kcc = q1.masked_operator(q1.assemble(g, self.k, elems), self.mask)
+        return q1.masked_operator(q1.assemble(self.g, self.k, elems), self.mask)
+
+    def _level2(self):
+        o = self.o
+        Kcc = self.cc_stiffness()
         # the identity part of the masked form never meets R_c (zero on fixed nodes)
         KR = (self.Rc @ Kcc @ self.Rc.T).tocsr()
         ncx, ncy, ncz = self.ncc

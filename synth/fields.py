@@ -91,6 +91,22 @@ def dirichlet_patch_mask(nx, ny, nz, frac=(1, 5)):
     return mask
 
 
+def dirichlet_patch_faces(nx, ny, nz, frac=(1, 5)):
+    """Cell face flags (uint8 per cell, (nz, ny, nx)) of the same centred bottom
+    patch for cell-centred unknowns: bit 4 (the -z face) is set on the bottom
+    cells whose face centre lies in the patch, ``den * |2 i + 1 - nx| <= num * nx``
+    and the same along y.  Bits 0..5 name the -x, +x, -y, +y, -z, +z faces.
+    """
+    num, den = frac
+    flags = np.zeros((nz, ny, nx), dtype=np.uint8)
+    i = np.arange(nx)
+    j = np.arange(ny)
+    inx = den * np.abs(2 * i + 1 - nx) <= num * nx
+    iny = den * np.abs(2 * j + 1 - ny) <= num * ny
+    flags[0] = np.where(iny[:, None] & inx[None, :], np.uint8(1 << 4), np.uint8(0))
+    return flags
+
+
 def field_sha256(a):
     """SHA-256 of the raw bytes of a C-contiguous array."""
     return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()

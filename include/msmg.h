@@ -41,6 +41,17 @@ typedef enum { MSMG_F64 = 0, MSMG_F32 = 1, MSMG_BF16 = 2 } msmg_dtype;
 
 typedef enum { MSMG_PC_MULTIGRID = 0, MSMG_PC_SMOOTHER = 1 } msmg_pc_kind;
 
+/* Discretisation of the heat equation.
+ *   MSMG_Q1:   trilinear (Q1) elements; unknowns are the (nx+1)(ny+1)(nz+1)
+ *              mesh nodes, Dirichlet data live on fixed nodes.
+ *   MSMG_TPFA: the paper's cell-centred two-point flux finite volumes
+ *              (section 2.2, eq. flux and eq. new linear system); unknowns
+ *              are the nx*ny*nz cells (numbered like the elements), the face
+ *              conductivity is the harmonic mean of the two cells', and
+ *              Dirichlet data live on flagged boundary faces, each closing
+ *              its cell's balance over half a cell (2 k_K |F| / h_d). */
+typedef enum { MSMG_Q1 = 0, MSMG_TPFA = 1 } msmg_discretisation;
+
 enum {
   MSMG_OK = 0,
   MSMG_MAXIT = 1,       /* iteration limit reached                      */
@@ -110,6 +121,15 @@ typedef struct msmg_options {
   int pair_rhs;        /* 1: allocate a second set of PCG and cycle vectors     [0]
                           for msmg_solve_pair (about 11 nodal vectors more;
                           needs the multigrid kind with cheb_degree 2)           */
+  int discretisation;  /* MSMG_Q1 or MSMG_TPFA                                  [Q1]
+                          TPFA: FP64 cycle vectors, density copy and basis
+                          (the dtype options at F64), no pair_rhs, no
+                          lean_memory, and cheb_hi >= 2 (the Jacobi-scaled
+                          TPFA matrix reaches close to 2; [0.2, 2] suits it).
+                          Vectors ("nodal" below) then hold one value per
+                          cell; coarse cells group H^3 cells (remainders join
+                          the last); the coarse-level fusions of coarse_fused
+                          bits 1 and 2 do not apply.                            */
 } msmg_options;
 
 /* Solve report. */
@@ -163,7 +183,13 @@ int msmg_create(msmg_handle** h, int nx, int ny, int nz, double lx, double ly, d
  * MSMG_F32 (copied; this copy defines the operator).  k_min > 0,
  * k_max >= k_min, p >= 1.  mask: nodal uint8, nonzero = fixed temperature
  * (must contain at least one node).  fixed_values: nodal FP64 temperatures
- * read on fixed nodes, or NULL for zero.  Call again whenever rho changes. */
+ * read on fixed nodes, or NULL for zero.  Call again whenever rho changes.
+ * TPFA: mask holds one byte per cell, its Dirichlet faces (bit 0 the -x
+ * face, 1 +x, 2 -y, 3 +y, 4 -z, 5 +z); only faces on the domain boundary may
+ * be flagged (MSMG_EINVAL otherwise) and at least one must be
+ * (MSMG_ESINGULAR otherwise).  fixed_values: one FP64 temperature per cell,
+ * imposed on every flagged face of that cell, or NULL for zero.  All device
+ * pointers. */
 int msmg_setup(msmg_handle* h, const void* rho, msmg_dtype rho_dtype, double k_min, double k_max, int p,
                const uint8_t* mask, const double* fixed_values, hipStream_t stream);
 
@@ -206,14 +232,16 @@ int msmg_solve_pair(msmg_handle* h, const double* f, double* T, double* T_lo, co
                     double* lambda_lo, double rtol, int maxit, msmg_info* info_T, msmg_info* info_lambda,
                     hipStream_t stream);
 
-/* Element sensitivities dc/drho_e = -p rho_e^(p-1) (k_max - k_min) lambda_e^T K0 T_e
+/* (Q1 only: MSMG_EINVAL for a TPFA handle.)
+ * Element sensitivities dc/drho_e = -p rho_e^(p-1) (k_max - k_min) lambda_e^T K0 T_e
  * (evaluated as -sum_{a<b} K0_ab (lambda_a - lambda_b)(T_a - T_b), exact for zero-row-sum K0)
  * (section 2.3 with a design-independent load).  lambda: nodal adjoint with zero
  * fixed entries, or NULL for the compliance case lambda = T (free entries of T;
  * valid for zero fixed values).  dc: element FP64 output. */
 int msmg_sensitivity(msmg_handle* h, const double* T, const double* lambda, double* dc, hipStream_t stream);
 
-/* Element sensitivities of an objective with the design-dependent heat source of
+/* (Q1 only: MSMG_EINVAL for a TPFA handle.)
+ * Element sensitivities of an objective with the design-dependent heat source of
  * section 2.1 eq. (material), f_e = f0 (1 - rho_e^p) (section 2.3):
  *   dc/drho_e = lambda^T (df/drho_e - dA/drho_e T)
  *             = -p rho_e^(p-1) [ (k_max - k_min) lambda_e^T K0 T_e + f0 (V/8) sum_{a in e} lambda_a ],
@@ -226,14 +254,16 @@ int msmg_sensitivity_heat_source(msmg_handle* h, const double* T, const double* 
                                  hipStream_t stream);
 
 /* Nodal load of the design-dependent heat source of section 2.1 eq. (material):
- * f_n = sum_{e ni n} f0 (1 - rho_e^p) V/8 with rho and p of the last msmg_setup.
+ * f_n = sum_{e ni n} f0 (1 - rho_e^p) V/8 with rho and p of the last msmg_setup
+ * (TPFA: the cell integral f_K = f0 (1 - rho_K^p) |K|).
  * f: nodal FP64 output, written on every node (the solves ignore fixed entries).
  * MSMG_EINVAL for a NULL pointer or a non-finite f0, MSMG_ESTATE before the first
  * msmg_setup.  The mean-temperature objective of section 2.3 eq. (cost function),
  * (1/|Omega|) int T, has the weights msmg_element_load(src = NULL, 1/|Omega|). */
 int msmg_heat_source_load(msmg_handle* h, double f0, double* f, hipStream_t stream);
 
-/* y = P A P x + (I - P) x with P the projection on free nodes (FP64, nodal). */
+/* y = P A P x + (I - P) x with P the projection on free nodes (FP64, nodal).
+ * TPFA: y = A x over the cells (no unknown is fixed). */
 int msmg_apply(msmg_handle* h, const double* x, double* y, hipStream_t stream);
 
 /* z = M^-1 r: one preconditioner application (Algorithm 1 for the multigrid
@@ -243,7 +273,8 @@ int msmg_apply(msmg_handle* h, const double* x, double* y, hipStream_t stream);
 int msmg_precondition(msmg_handle* h, const double* r, double* z, hipStream_t stream);
 
 /* Consistent nodal load of an element-wise constant source: f_n = sum_{e ni n} s_e V/8,
- * with s_e = src[e], or s_e = src_const when src is NULL. */
+ * with s_e = src[e], or s_e = src_const when src is NULL (TPFA: the cell
+ * integral f_K = s_K |K|). */
 int msmg_element_load(msmg_handle* h, const double* src, double src_const, double* f, hipStream_t stream);
 
 /* Measurement aid: the memory traffic of the operator apply (msmg_apply reads

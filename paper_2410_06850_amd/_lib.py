@@ -17,6 +17,7 @@ MSMG_PC_MULTIGRID, MSMG_PC_SMOOTHER = 0, 1
 MSMG_OK, MSMG_MAXIT, MSMG_BREAKDOWN, MSMG_NONFINITE = 0, 1, 2, 3
 MSMG_EINVAL, MSMG_ENOMEM, MSMG_EHIP, MSMG_ESETUP, MSMG_ESINGULAR, MSMG_ESTATE, MSMG_ETIMEOUT = -1, -2, -3, -4, -5, -6, -7
 
+MSMG_Q1, MSMG_TPFA = 0, 1
 EXPORT_LOCAL_EVALS, EXPORT_RC, EXPORT_AC, EXPORT_CC_EVALS, EXPORT_ACC, EXPORT_CELL_STATUS = range(6)
 
 
@@ -50,6 +51,7 @@ class Options(ctypes.Structure):
         ("cc_group", ctypes.c_int),
         ("coarse_fused", ctypes.c_int),
         ("pair_rhs", ctypes.c_int),
+        ("discretisation", ctypes.c_int),
     ]
 
 

@@ -25,6 +25,7 @@ SOURCES = [
     "setup_coarse.hip",
     "setup_driver.hip",
     "topopt_kernels.hip",
+    "tpfa_kernels.hip",
     "runtime.cpp",
 ]
 

@@ -1,6 +1,8 @@
 // Internal declarations shared by the kernel files and the runtime.
 #pragma once
 
+#include <algorithm>
+
 #include "common.h"
 #include "march.h"
 
@@ -78,6 +80,11 @@ struct Ctx {
   RestrictGeo rg;     // fused residual + restriction (when restrict_fusable)
   double* rpart;      // its per-workgroup partial sums, rg.slots * Lc doubles
   CoarseCtx cc;
+  // cell-centred two-point flux discretisation: unknowns are the cells (g.nn =
+  // g.ne, g.nnx = g.nx, ...), kc holds the FP64 cell conductivities, dface the
+  // Dirichlet face flags of each cell (bit 0 -x, 1 +x, 2 -y, 3 +y, 4 -z, 5 +z)
+  int tpfa;
+  const uint8_t* dface;
 };
 
 // Slots of the handle's 16-word counter block (zero between kernels unless
@@ -178,6 +185,23 @@ void launch_prolong_element(int nx, int ny, int nz, const void* rc, void* rf, in
 // one read of x (nn) and k (ne <= nn) and one write of y (nn), coalesced: the
 // operator apply's traffic without its stencil (nn, ne even)
 void launch_stream_ceiling(const double* x, const double* k, double* y, long long nn, long long ne, hipStream_t s);
+
+// cell-centred two-point flux operator (Ctx.tpfa): FP64 vectors, FP64 basis
+bool tpfa_grid_fits(const Ctx& c);  // the stencil grid fits the reduction's block budget
+void launch_tpfa_apply(const Ctx& c, const double* x, double* y, bool reduce, hipStream_t s);
+void launch_tpfa_residual(const Ctx& c, const double* b, const double* x, const float* xlo, double* y, bool reduce,
+                          hipStream_t s);
+void launch_tpfa_vresidual(const Ctx& c, const double* r, const double* x, double* out, hipStream_t s);
+void launch_tpfa_smooth(const Ctx& c, const double* in, double* out, hipStream_t s);
+void launch_tpfa_restrict(const Ctx& c, const double* v, double* rc, hipStream_t s);
+void launch_tpfa_prolong(const Ctx& c, const double* base, const double* e1, const double* e2, double* out,
+                         hipStream_t s);
+void launch_tpfa_diag_inv(const Ctx& c, double* dinv, hipStream_t s);
+void launch_tpfa_lift(const Ctx& c, const double* f, const double* td, double* b, hipStream_t s);
+void launch_tpfa_flags(const Ctx& c, const uint8_t* in, uint8_t* out, unsigned long long* counts, hipStream_t s);
+void launch_tpfa_cell_load(const Ctx& c, const double* src, double sconst, double* f, hipStream_t s);
+void launch_tpfa_heat_source_load(const Ctx& c, double f0, double* f, hipStream_t s);
+int launch_tpfa_galerkin(const Ctx& c, const void* R, int b_dt, int drop_cc, double* out, hipStream_t s);
 
 // coarse levels (V-cycle)
 void launch_gs_sweep(const Ctx& c, const void* b, void* x, bool forward, hipStream_t s);

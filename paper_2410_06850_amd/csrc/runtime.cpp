@@ -63,6 +63,9 @@ struct msmg_handle {
   int rho_dt = DT_F64, kv_dt = DT_F64, v_dt = DT_F64, b_dt = DT_F64, a_dt = DT_F64, dv_dt = DT_F64;
   int rho_store_dt = DT_F64;  // storage of the canonical density copy
   bool mg = true;
+  bool tpfa = false;                     // cell-centred two-point flux discretisation
+  uint8_t* dface = nullptr;              // its Dirichlet face flags (one byte per cell)
+  unsigned long long* fcount = nullptr;  // flag counts of the last set-up: valid, misplaced
 
   // density, mask, fixed values
   void* rho = nullptr;
@@ -135,11 +138,12 @@ struct Plan {
   std::vector<int> cc_ptr;  // host, ncc+1
 };
 
-static int make_plan(int nx, int ny, int nz, const msmg_options& o, Plan& P) {
+// extra = 1: unknowns are the nodes (n + 1 per axis); 0: the cells (TPFA)
+static int make_plan(int nx, int ny, int nz, const msmg_options& o, Plan& P, int extra = 1) {
   if (nx < 1 || ny < 1 || nz < 1) return fail(MSMG_EINVAL, "mesh sizes must be positive");
   if (o.H < 2) return fail(MSMG_EINVAL, "H must be >= 2");
   if (o.H > 16) return fail(MSMG_EINVAL, "H must be <= 16");
-  if (nx < o.H || ny < o.H || nz < o.H) return fail(MSMG_EINVAL, "each axis needs at least H elements");
+  if (nx < o.H || ny < o.H || nz < o.H) return fail(MSMG_EINVAL, "each axis needs at least H elements (cells)");
   if (o.sd < 1) return fail(MSMG_EINVAL, "sd must be >= 1");
   if (o.Lc < 1 || o.Lc > LC_MAX) return fail(MSMG_EINVAL, "Lc must be in 1..8");
   if (o.Lcc < 1) return fail(MSMG_EINVAL, "Lcc must be >= 1");
@@ -159,7 +163,8 @@ static int make_plan(int nx, int ny, int nz, const msmg_options& o, Plan& P) {
   h.ncc = h.nccx * h.nccy * h.nccz;
   h.Lcc = o.Lcc;
   auto ext = [&](int c, int nc, int nn) { return cell_end(c, o.H, nc, nn) - cell_begin(c, o.H); };
-  const int mx = ext(h.ncx - 1, h.ncx, nx + 1), my = ext(h.ncy - 1, h.ncy, ny + 1), mz = ext(h.ncz - 1, h.ncz, nz + 1);
+  const int mx = ext(h.ncx - 1, h.ncx, nx + extra), my = ext(h.ncy - 1, h.ncy, ny + extra),
+            mz = ext(h.ncz - 1, h.ncz, nz + extra);
   P.max_cell_nodes = mx * my * mz;
   if (mx > 16 || my > 16 || mz > 16) return fail(MSMG_EINVAL, "a coarse cell exceeds 16 nodes per axis");
   P.CX = std::max(1, 64 / o.H);
@@ -192,10 +197,12 @@ static int make_plan(int nx, int ny, int nz, const msmg_options& o, Plan& P) {
   return MSMG_OK;
 }
 
-static Geo make_geo(int nx, int ny, int nz, double lx, double ly, double lz) {
+static Geo make_geo(int nx, int ny, int nz, double lx, double ly, double lz, bool cells = false) {
   Geo g;
   g.nx = nx; g.ny = ny; g.nz = nz;
-  g.nnx = nx + 1; g.nny = ny + 1; g.nnz = nz + 1;
+  // cell unknowns (TPFA): the "node" grid is the cell grid
+  const int e = cells ? 0 : 1;
+  g.nnx = nx + e; g.nny = ny + e; g.nnz = nz + e;
   g.nn = (long long)g.nnx * g.nny * g.nnz;
   g.ne = (long long)nx * ny * nz;
   g.hx = lx / nx; g.hy = ly / ny; g.hz = lz / nz;
@@ -298,6 +305,8 @@ static Ctx make_ctx(msmg_handle* h, int side = 0) {
   c.cc.AccInv = h->Acc;
   c.cc.n_c = h->n_c;
   c.cc.n_cc = h->n_cc;
+  c.tpfa = h->tpfa ? 1 : 0;
+  c.dface = h->dface;
   return c;
 }
 
@@ -368,6 +377,7 @@ extern "C" void msmg_default_options(msmg_options* o) {
   o->cc_group = 0;
   o->coarse_fused = 7;
   o->pair_rhs = 0;
+  o->discretisation = MSMG_Q1;
 }
 
 extern "C" const char* msmg_last_error(void) { return g_last_error.c_str(); }
@@ -395,6 +405,14 @@ static int check_options(const msmg_options& o) {
     return fail(MSMG_EINVAL, "pair_rhs needs the multigrid preconditioner with the degree-2 smoother");
   if (o.lean_memory && o.eig_warm_start)
     return fail(MSMG_EINVAL, "lean_memory keeps no basis between set-ups: eig_warm_start is not available");
+  if (o.discretisation != MSMG_Q1 && o.discretisation != MSMG_TPFA) return fail(MSMG_EINVAL, "bad discretisation");
+  if (o.discretisation == MSMG_TPFA) {
+    if (o.vcycle_dtype != MSMG_F64 || o.rho_v_dtype != MSMG_F64 || o.basis_dtype != MSMG_F64)
+      return fail(MSMG_EINVAL, "the TPFA discretisation runs FP64 cycle vectors, density copy and basis");
+    if (o.pair_rhs || o.lean_memory) return fail(MSMG_EINVAL, "the TPFA discretisation has no pair_rhs or lean_memory");
+    if (!(o.cheb_hi >= 2.0))
+      return fail(MSMG_EINVAL, "TPFA needs cheb_hi >= 2: the Jacobi-scaled TPFA matrix reaches close to 2");
+  }
   return MSMG_OK;
 }
 
@@ -418,8 +436,12 @@ static int alloc_arrays(msmg_handle* h, bool dry, size_t* total) {
   A(&h->rho, ne * dt_size(h->rho_store_dt));
   // FP64 conductivities for the PCG apply when the density is FP64 (with an
   // FP32 density the apply forms them from it); the cycle's copy
-  const bool kc64 = h->rho_store_dt == DT_F64;
+  const bool kc64 = h->rho_store_dt == DT_F64 || h->tpfa;
   if (kc64) A(&h->kc, ne * 8);
+  if (h->tpfa) {
+    A(&h->dface, ne);
+    A(&h->fcount, 16);
+  }
   if (!(kc64 && h->kv_dt == DT_F64)) A(&h->kv, ne * dt_size(h->kv_dt));
   A(&h->bits, ((nn + 31) / 32) * 4);
   // Jacobi diagonal: FP64 only on the all-FP64 path (a fixed coefficient like rho)
@@ -478,7 +500,7 @@ static int alloc_arrays(msmg_handle* h, bool dry, size_t* total) {
     A(&h->vs[0].c_x1, (size_t)h->n_c * 8); A(&h->vs[0].c_d, (size_t)h->n_c * 8);
     A(&h->vs[0].rcc, (size_t)h->n_cc * 8); A(&h->vs[0].ecc, (size_t)h->n_cc * 8);
     if (o.coarse_fused & 1) A(&h->l1_bar, (size_t)level1_barrier_words() * 4);
-    if ((o.coarse_fused & 2) && restrict_fusable(h->hier)) {
+    if ((o.coarse_fused & 2) && restrict_fusable(h->hier) && !h->tpfa) {
       h->rg = make_restrict_geo(h->g, h->hier, h->march_resident);
       A(&h->vs[0].rpart, (size_t)h->rg.slots * h->hier.Lc * 8);
     }
@@ -511,10 +533,21 @@ static int alloc_arrays(msmg_handle* h, bool dry, size_t* total) {
 static void init_handle(msmg_handle* h, const msmg_options& o, const Plan& P, int nx, int ny, int nz, double lx,
                         double ly, double lz) {
   h->opt = o;
-  h->g = make_geo(nx, ny, nz, lx, ly, lz);
+  h->tpfa = o.discretisation == MSMG_TPFA;
+  h->g = make_geo(nx, ny, nz, lx, ly, lz, h->tpfa);
   double lmk0 = 0.0;
   h->st = make_stencil(h->g, &lmk0);
   h->lam_bound = 8.0 * lmk0 / h->g.vol;
+  if (h->tpfa) {
+    // Gershgorin bound of M^-1/2 K M^-1/2 for the TPFA local problems: per
+    // face, T/m_K + T/sqrt(m_K m_L) <= (1 + sqrt 2) / h_d^2, two faces per axis
+    const double s2 = 1.0 / (h->g.hx * h->g.hx) + 1.0 / (h->g.hy * h->g.hy) + 1.0 / (h->g.hz * h->g.hz);
+    h->lam_bound = 2.0 * (1.0 + std::sqrt(2.0)) * s2;
+    // the stencil launches reduce over one workgroup per 64 x 4 column tile
+    // and z chunk: enough reduction slots for one chunk per column
+    const long long cols = (long long)((nx + 63) / 64) * ((ny + 3) / 4);
+    h->red_blocks = int(std::max<long long>(4096, ((cols + 8 + 7) / 8) * 8));
+  }
   h->hier = P.h;
   h->CX = P.CX;
   h->ntiles = P.ntiles;
@@ -539,14 +572,15 @@ extern "C" int msmg_query_plan(int nx, int ny, int nz, const msmg_options* opt, 
   if (!out) return fail(MSMG_EINVAL, "out is NULL");
   TRY(check_options(o));
   Plan P;
-  TRY(make_plan(nx, ny, nz, o, P));
+  TRY(make_plan(nx, ny, nz, o, P, o.discretisation == MSMG_TPFA ? 0 : 1));
   out->ncx = P.h.ncx; out->ncy = P.h.ncy; out->ncz = P.h.ncz; out->ncells = P.h.ncells;
   out->nccx = P.h.nccx; out->nccy = P.h.nccy; out->nccz = P.h.nccz; out->ncc = P.h.ncc;
   out->n_c = P.n_c;
   out->n_cc = P.n_cc;
   out->max_cell_nodes = P.max_cell_nodes;
   out->max_cc_dofs = P.max_cc_dofs;
-  out->nodes = (long long)(nx + 1) * (ny + 1) * (nz + 1);
+  const int e = o.discretisation == MSMG_TPFA ? 0 : 1;
+  out->nodes = (long long)(nx + e) * (ny + e) * (nz + e);
   out->elements = (long long)nx * ny * nz;
   msmg_handle tmp;
   init_handle(&tmp, o, P, nx, ny, nz, 1.0, 1.0, 1.0);
@@ -565,7 +599,7 @@ extern "C" int msmg_create(msmg_handle** out, int nx, int ny, int nz, double lx,
   if (opt) o = *opt; else msmg_default_options(&o);
   TRY(check_options(o));
   Plan P;
-  TRY(make_plan(nx, ny, nz, o, P));
+  TRY(make_plan(nx, ny, nz, o, P, o.discretisation == MSMG_TPFA ? 0 : 1));
   msmg_handle* h = new msmg_handle();
   init_handle(h, o, P, nx, ny, nz, lx, ly, lz);
   HIP_TRY(hipGetDevice(&h->device));
@@ -674,6 +708,25 @@ extern "C" int msmg_setup(msmg_handle* h, const void* rho, msmg_dtype rho_dtype,
   h->rho_dt = h->rho_store_dt;
   const long long nn = h->g.nn, ne = h->g.ne;
   launch_convert(rho, rho_dtype, h->rho, h->rho_store_dt, ne, s);
+  if (h->tpfa) {
+    // Dirichlet face flags: copied and checked; no unknown is fixed
+    Ctx c0 = make_ctx(h);
+    unsigned long long cnt[2] = {0, 0};
+    HIP_TRY(hipMemsetAsync(h->fcount, 0, 16, s));
+    launch_tpfa_flags(c0, mask, h->dface, h->fcount, s);
+    HIP_TRY(hipMemsetAsync(h->bits, 0, ((nn + 31) / 32) * 4, s));
+    HIP_TRY(hipMemcpyAsync(cnt, h->fcount, 16, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (cnt[1]) return fail(MSMG_EINVAL, "a Dirichlet face flag sits on an internal face (or outside bits 0..5)");
+    if (cnt[0] == 0) return fail(MSMG_ESINGULAR, "no Dirichlet face: the operator is singular");
+    if (fixed_values) {
+      if (!h->tfix) TRY(dev_alloc(h, &h->tfix, nn * 8));
+      launch_convert(fixed_values, DT_F64, h->tfix, DT_F64, nn, s);
+      h->has_tfix = true;
+    } else {
+      h->has_tfix = false;
+    }
+  } else {
   launch_pack_mask(mask, h->bits, nn, s);
   if (fixed_values) {
     if (!h->tfix) TRY(dev_alloc(h, &h->tfix, nn * 8));
@@ -692,10 +745,12 @@ extern "C" int msmg_setup(msmg_handle* h, const void* rho, msmg_dtype rho_dtype,
     TRY(count_fixed(c, &nfixed, s));
     if (nfixed == 0) return fail(MSMG_ESINGULAR, "the Dirichlet mask is empty: the operator is singular");
   }
+  }
   Ctx c = make_ctx(h);
   if (h->kc) launch_conductivity(c, h->rho, h->rho_dt, h->kc, DT_F64, s);
   if (h->kv != h->kc) launch_conductivity(c, h->rho, h->rho_dt, h->kv, h->kv_dt, s);
-  launch_diag_inv(c, h->rho, h->rho_dt, h->dinv, h->dv_dt, s);
+  if (h->tpfa) launch_tpfa_diag_inv(c, (double*)h->dinv, s);
+  else launch_diag_inv(c, h->rho, h->rho_dt, h->dinv, h->dv_dt, s);
   HIP_TRY(hipGetLastError());
   if (h->mg) {
     SetupArgs a{};
@@ -799,10 +854,35 @@ static void coarse_correction(msmg_handle* h, const Ctx& c, VecSet& V, hipStream
   launch_prolong(c, V.v_r1, V.c_x1, V.c_d, V.v_r2, s);          // r2 = r1 + R_c^T ec (FP64)
 }
 
+// Algorithm 1 on the cell unknowns of the two-point flux discretisation:
+// the level-0 steps as separate launches, levels 1 and 2 shared with Q1.
+static void precondition_tpfa(msmg_handle* h, const Ctx& c, VecSet& V, const double* r, double* z, const double* q,
+                              int mode, hipStream_t s) {
+  double* r1 = (double*)V.v_r1;
+  double* res = (double*)V.v_res;
+  launch_tpfa_smooth(c, r, r1, s);  // r1 = S^-1 r0
+  if (!h->mg) {
+    launch_vc_output(c, r1, true, nullptr, z, r, q, mode, s);
+    return;
+  }
+  launch_tpfa_vresidual(c, r, r1, res, s);           // r0 - A r1
+  launch_tpfa_restrict(c, res, (double*)V.c_rc, s);  // rc = R_c (r0 - A r1)
+  const double *e1 = nullptr, *e2 = nullptr;
+  coarse_correction(h, c, V, s, &e1, &e2);                  // e_c
+  launch_tpfa_prolong(c, r1, e1, e2, (double*)V.v_r2, s);  // r2 = r1 + R_c^T e_c
+  launch_tpfa_vresidual(c, r, (const double*)V.v_r2, res, s);  // r0 - A r2
+  launch_tpfa_smooth(c, res, r1, s);                           // S^-T (...)
+  launch_vc_output(c, V.v_r2, true, r1, z, r, q, mode, s);     // y = r2 + ...
+}
+
 // One preconditioner application r (FP64) -> z (FP64) with the PCG reduction
 // mode (0 init, 1 iteration, 2 none).
 static void precondition(msmg_handle* h, const Ctx& c, VecSet& V, const double* r, double* z, const double* q,
                          int mode, hipStream_t s) {
+  if (c.tpfa) {
+    precondition_tpfa(h, c, V, r, z, q, mode, s);
+    return;
+  }
   const bool v64 = (h->v_dt == DT_F64);
   const bool fused = smooth_output_fused(c);
   if (!h->mg) {
@@ -866,6 +946,11 @@ extern "C" int msmg_apply(msmg_handle* h, const double* x, double* y, hipStream_
   if (!h->setup_done) return fail(MSMG_ESTATE, "msmg_setup has not completed");
   if (x == y) return fail(MSMG_EINVAL, "x and y must not alias");
   Ctx c = make_ctx(h);
+  if (h->tpfa) {
+    launch_tpfa_apply(c, x, y, false, s);
+    HIP_TRY(hipGetLastError());
+    return MSMG_OK;
+  }
   // the march stages x with zero fixed entries (handle scratch q, which the
   // lean layout shares with the exported basis)
   if (h->opt.lean_memory) h->basis_live = false;
@@ -877,6 +962,7 @@ extern "C" int msmg_apply(msmg_handle* h, const double* x, double* y, hipStream_
 
 extern "C" int msmg_sensitivity(msmg_handle* h, const double* T, const double* lam, double* dc, hipStream_t s) {
   if (!h || !T || !dc) return fail(MSMG_EINVAL, "NULL argument");
+  if (h->tpfa) return fail(MSMG_EINVAL, "sensitivities are provided for the Q1 discretisation only");
   if (!h->setup_done) return fail(MSMG_ESTATE, "msmg_setup has not completed");
   Ctx c = make_ctx(h);
   launch_sensitivity(c, T, lam, dc, s);
@@ -888,6 +974,7 @@ extern "C" int msmg_sensitivity_heat_source(msmg_handle* h, const double* T, con
                                             hipStream_t s) {
   if (!h || !T || !lam || !dc) return fail(MSMG_EINVAL, "NULL argument");
   if (!std::isfinite(f0)) return fail(MSMG_EINVAL, "f0 must be finite");
+  if (h->tpfa) return fail(MSMG_EINVAL, "sensitivities are provided for the Q1 discretisation only");
   if (!h->setup_done) return fail(MSMG_ESTATE, "msmg_setup has not completed");
   Ctx c = make_ctx(h);
   launch_sensitivity_heat_source(c, T, lam, f0, dc, s);
@@ -900,14 +987,16 @@ extern "C" int msmg_heat_source_load(msmg_handle* h, double f0, double* f, hipSt
   if (!std::isfinite(f0)) return fail(MSMG_EINVAL, "f0 must be finite");
   if (!h->setup_done) return fail(MSMG_ESTATE, "msmg_setup has not completed");
   Ctx c = make_ctx(h);
-  launch_heat_source_load(c, f0, f, s);
+  if (h->tpfa) launch_tpfa_heat_source_load(c, f0, f, s);
+  else launch_heat_source_load(c, f0, f, s);
   HIP_TRY(hipGetLastError());
   return MSMG_OK;
 }
 
 extern "C" int msmg_element_load(msmg_handle* h, const double* src, double sconst, double* f, hipStream_t s) {
   if (!h || !f) return fail(MSMG_EINVAL, "NULL argument");
-  launch_element_load(h->g, src, sconst, f, s);
+  if (h->tpfa) launch_tpfa_cell_load(make_ctx(h), src, sconst, f, s);
+  else launch_element_load(h->g, src, sconst, f, s);
   HIP_TRY(hipGetLastError());
   return MSMG_OK;
 }
@@ -959,6 +1048,18 @@ static void fill_setup_timing(const msmg_handle* h, msmg_info* info) {
   info->setup_dense_gflop = h->setup_dense_gflop;
 }
 
+// The PCG's products with A on either discretisation: q = A p with the step
+// length reduction, and b - A x (x + xlo) with the true-residual reduction.
+static void op_apply_pcg(const Ctx& c, const double* p, double* q, hipStream_t s) {
+  if (c.tpfa) launch_tpfa_apply(c, p, q, true, s);
+  else launch_apply(c, p, q, 1, s);
+}
+static void op_residual(const Ctx& c, const double* b, const double* x, const float* xlo, double* y, bool reduce,
+                        hipStream_t s) {
+  if (c.tpfa) launch_tpfa_residual(c, b, x, xlo, y, reduce, s);
+  else launch_residual(c, b, x, xlo, y, reduce, s);
+}
+
 // PCG driver shared by the state and adjoint solves.  `homogeneous` solves
 // with zero fixed values (the adjoint system), ignoring the set-up's values.
 static int solve_impl(msmg_handle* h, const double* f, double* T, double* T_lo, int use_x0, double rtol, int maxit,
@@ -973,8 +1074,10 @@ static int solve_impl(msmg_handle* h, const double* f, double* T, double* T_lo, 
   if (h->opt.lean_memory) h->basis_live = false;
   const double* lift = (h->has_tfix && !homogeneous) ? h->tfix : nullptr;
   double* x = T;
-  // b = f - A t_fix on free rows (0 on fixed rows)
-  if (lift) launch_residual(c, f, lift, nullptr, V.b, false, s);
+  // b = f - A t_fix on free rows (0 on fixed rows); TPFA: b = f plus the
+  // Dirichlet faces' 2 k_K |F| / h_d T_D
+  if (c.tpfa) launch_tpfa_lift(c, f, lift, V.b, s);
+  else if (lift) launch_residual(c, f, lift, nullptr, V.b, false, s);
   else launch_zero_fixed_copy(c, f, V.b, s);
   // x: free entries of the guess (or 0), fixed entries 0 during the iteration
   if (use_x0) launch_zero_fixed_copy(c, T, x, s);
@@ -983,7 +1086,7 @@ static int solve_impl(msmg_handle* h, const double* f, double* T, double* T_lo, 
   launch_sc_reset(c, 1, maxit, s);
   launch_norm2(c, V.b, 0, rtol * rtol, s);  // bb, tol2
   HIP_TRY(hipMemsetAsync(V.xlo, 0, sizeof(float) * size_t(c.g.nn), s));
-  if (use_x0) launch_residual(c, V.b, x, nullptr, V.r, false, s);
+  if (use_x0) op_residual(c, V.b, x, nullptr, V.r, false, s);
   else launch_copy(c, V.b, V.r, s);
   launch_norm2(c, V.r, 1, 0.0, s);  // rr
   TRY(read_scalars(V, s));
@@ -1020,7 +1123,7 @@ static int solve_impl(msmg_handle* h, const double* f, double* T, double* T_lo, 
       for (int it = 0; it < batch; ++it) {
         const bool tm = h->opt.timing && launched < max_timed;
         if (tm) HIP_TRY(hipEventRecord(h->events[4 * launched + 0], s));
-        launch_apply(c, V.p, V.q, 1, s);
+        op_apply_pcg(c, V.p, V.q, s);
         if (tm) HIP_TRY(hipEventRecord(h->events[4 * launched + 1], s));
         launch_update_r(c, V.r, V.q, s);
         if (tm) HIP_TRY(hipEventRecord(h->events[4 * launched + 2], s));
@@ -1039,7 +1142,7 @@ static int solve_impl(msmg_handle* h, const double* f, double* T, double* T_lo, 
       iters = S.iters;
       if (S.status == ST_CONV_RECURSIVE) {
         // confirm with the true residual
-        launch_residual(c, V.b, x, V.xlo, V.q, true, s);
+        op_residual(c, V.b, x, V.xlo, V.q, true, s);
         TRY(read_scalars(V, s));
         const double trr = V.sc_host->true_rr;
         if (trr <= V.sc_host->tol2) {
@@ -1064,7 +1167,7 @@ static int solve_impl(msmg_handle* h, const double* f, double* T, double* T_lo, 
       if (S.status == ST_SYNC_TIMEOUT)
         return fail(MSMG_ETIMEOUT, "a grid-wide wait of the coarse-level kernel exceeded its limit");
       status = (S.status == ST_MAXIT) ? MSMG_MAXIT : (S.status == ST_BREAKDOWN ? MSMG_BREAKDOWN : MSMG_NONFINITE);
-      launch_residual(c, V.b, x, V.xlo, V.q, true, s);
+      op_residual(c, V.b, x, V.xlo, V.q, true, s);
       TRY(read_scalars(V, s));
       rel = std::sqrt(V.sc_host->true_rr / bb);
       break;

@@ -63,8 +63,8 @@ static std::string tune_key(const Ctx& c, int nl) {
   (void)hipGetDevice(&dev);
   (void)hipGetDeviceProperties(&p, dev);
   char buf[256];
-  std::snprintf(buf, sizeof(buf), "%s H%d L%d nl%d rho%d cells%d", p.gcnArchName, c.h.H, c.h.Lc, nl, c.rho_dt,
-                c.h.ncells);
+  std::snprintf(buf, sizeof(buf), "%s H%d L%d nl%d rho%d cells%d%s", p.gcnArchName, c.h.H, c.h.Lc, nl, c.rho_dt,
+                c.h.ncells, c.tpfa ? " tpfa" : "");
   return buf;
 }
 
@@ -248,7 +248,10 @@ int run_setup(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, SetupReport* 
   // 2. stored copy of R_c, Galerkin A_c from the stored values
   const long long nb = c.g.nn * h.Lc;
   if (sa.Rcs != (void*)sa.Rc64) launch_convert(sa.Rc64, DT_F64, sa.Rcs, sa.b_dt, nb, s);
-  if ((r = launch_galerkin(c, sa.Rcs, sa.b_dt, 0, sa.Ac64, s))) return hip_ok(hipGetLastError(), rep, "Galerkin A_c");
+  auto galerkin = [&](const void* R, int bdt, int drop_cc, double* out) {
+    return c.tpfa ? launch_tpfa_galerkin(c, R, bdt, drop_cc, out, s) : launch_galerkin(c, R, bdt, drop_cc, out, s);
+  };
+  if ((r = galerkin(sa.Rcs, sa.b_dt, 0, sa.Ac64))) return hip_ok(hipGetLastError(), rep, "Galerkin A_c");
   launch_block_inverse(c, sa.Ac64, sa.AcDinv64, s);
   const long long nblk = (long long)h.ncells * 27 * h.Lc * h.Lc;
   if (sa.a_dt != DT_F64) {
@@ -258,7 +261,7 @@ int run_setup(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, SetupReport* 
 
   mark(2);
   // 3. coarse-coarse spectral problems eq. (spectral cc) on the FP64 basis
-  if ((r = launch_galerkin(c, sa.Rc64, DT_F64, 1, sa.G64, s))) return hip_ok(hipGetLastError(), rep, "Galerkin G");
+  if ((r = galerkin(sa.Rc64, DT_F64, 1, sa.G64))) return hip_ok(hipGetLastError(), rep, "Galerkin G");
   if ((r = run_cc_eigen(c, sa, sc, sa.G64, &rep->cc_unconverged, rep, s))) {
     std::snprintf(rep->msg, sizeof(rep->msg), "coarse-coarse eigensolver failed");
     return r;

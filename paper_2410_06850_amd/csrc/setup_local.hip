@@ -79,8 +79,10 @@ MSMG_DEV double hash01(unsigned x) {
 
 // NLC: the LDS capacity per vector as a compile-time constant (the common
 // cell sizes), so that the vector strides become immediate offsets; 0 takes
-// it from the arguments.
-template <int M, int BS, int NLC>
+// it from the arguments.  TP: the cell-centred two-point flux problem of the
+// same equation (unknowns are the cells of the coarse cell, K_i the TPFA form
+// of its internal faces, M_i = diag(k_K |K|)).
+template <int M, int BS, int NLC, bool TP>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(BS <= 512 ? 2 * BS / 256 : 1)))
 void k_local_eigen(LocalArgs A) {
   extern __shared__ double lds[];
@@ -118,6 +120,8 @@ void k_local_eigen(LocalArgs A) {
   const double pat_ax[3] = {A.st.ax[0], A.st.ax[1], A.st.ax[2]};
   const double pat_fd[3] = {A.st.fd[0], A.st.fd[1], A.st.fd[2]};
   const double pat_bd = A.st.bd;
+  // TP: face weights |F| / h_d
+  const double tw[3] = {g.hy * g.hz / g.hx, g.hx * g.hz / g.hy, g.hx * g.hy / g.hz};
 
   while (true) {
     if (tid == 0) s_cell = int(atomicAdd(A.work, 1u));
@@ -133,9 +137,16 @@ void k_local_eigen(LocalArgs A) {
     const int nlx = x1 - x0, nly = y1 - y0, nlz = z1 - z0;
     const int nloc = nlx * nly * nlz;
     const int nex = nlx - 1, ney = nly - 1, nez = nlz - 1;
-    const int nel = nex * ney * nez;
-    // conductivities of the internal elements
-    for (int e = tid; e < nel; e += BS) {
+    const int nel = TP ? nloc : nex * ney * nez;
+    // conductivities of the internal elements (of the cells for TP)
+    if (TP) {
+      for (int e = tid; e < nloc; e += BS) {
+        const int ex = e % nlx, ey = (e / nlx) % nly, ez = e / (nlx * nly);
+        const long long gc = node_id(g, x0 + ex, y0 + ey, z0 + ez);
+        const double r = (A.rho_dt == DT_F64) ? ((const double*)A.rho)[gc] : double(((const float*)A.rho)[gc]);
+        kl[e] = conductivity<double>(r, A.mat.kmin, dk, A.mat.p);
+      }
+    } else for (int e = tid; e < nel; e += BS) {
       const int ex = e % nex, ey = (e / nex) % ney, ez = e / (nex * ney);
       const long long ge = elem_id(g, x0 + ex, y0 + ey, z0 + ez);
       const double r = (A.rho_dt == DT_F64) ? ((const double*)A.rho)[ge] : double(((const float*)A.rho)[ge]);
@@ -148,6 +159,15 @@ void k_local_eigen(LocalArgs A) {
       const int lx = ln % nlx, ly = (ln / nlx) % nly, lz = ln / (nlx * nly);
       const long long gn = node_id(g, x0 + lx, y0 + ly, z0 + lz);
       double m = 0.0;
+      if (TP) {
+        m = kl[ln] * g.vol;
+        isq[ln] = m > 0.0 ? 1.0 / sqrt(m) : 0.0;
+        if (m > 0.0) {
+          nfree_d += 1.0;
+          msum += m;
+        }
+        continue;
+      }
       for (int c = 0; c < 8; ++c) {
         const int ex = lx - 1 + (c & 1), ey = ly - 1 + ((c >> 1) & 1), ez = lz - 1 + ((c >> 2) & 1);
         if (ex >= 0 && ex < nex && ey >= 0 && ey < ney && ez >= 0 && ez < nez) m += kl[(ez * ney + ey) * nex + ex];
@@ -175,6 +195,35 @@ void k_local_eigen(LocalArgs A) {
     // B = M^-1/2 K M^-1/2, K in difference form with per-offset weights)
     auto apply_node = [&](const double* P, int ln, double* out) {
       const int lx = ln % nlx, ly = (ln / nlx) % nly, lz = ln / (nlx * nly);
+      if constexpr (TP) {
+        // faces to the six neighbours inside the coarse cell: T = w_d 2 k k' / (k + k')
+        const double s0 = isq[ln], k0 = kl[ln];
+        double v0[M];
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+          v0[j] = s0 * P[j * NL + ln];
+          out[j] = 0.0;
+        }
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+          const int a = f / 2, sd = (f & 1) ? 1 : -1;
+          const int p = (a == 0 ? lx : (a == 1 ? ly : lz)) + sd;
+          const int na = a == 0 ? nlx : (a == 1 ? nly : nlz);
+          const bool in = p >= 0 && p < na;
+          const int step = a == 0 ? 1 : (a == 1 ? nlx : nlx * nly);
+          const int nb = in ? ln + sd * step : ln;
+          const double kn = kl[nb], sb = isq[nb];
+          const double T = in ? tw[a] * (2.0 * k0 * kn / (k0 + kn)) : 0.0;
+          double pv[M];
+#pragma unroll
+          for (int j = 0; j < M; ++j) pv[j] = P[j * NL + nb];
+#pragma unroll
+          for (int j = 0; j < M; ++j) out[j] += T * (v0[j] - sb * pv[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < M; ++j) out[j] *= s0;
+        return;
+      }
       double kk[8];
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
@@ -339,7 +388,23 @@ void k_local_eigen(LocalArgs A) {
         const int bx = ib % nlx, by = (ib / nlx) % nly, bz = ib / (nlx * nly);
         const int dx = bx - ax, dy = by - ay, dz = bz - az;
         double kab = 0.0;
-        if (abs(dx) <= 1 && abs(dy) <= 1 && abs(dz) <= 1) {
+        if (TP) {
+          const int ad = abs(dx) + abs(dy) + abs(dz);
+          if (ad == 0) {
+            // diagonal: the sum of the cell's internal face transmissibilities
+            for (int f = 0; f < 6; ++f) {
+              const int a = f / 2, sd = (f & 1) ? 1 : -1;
+              const int p = (a == 0 ? ax : (a == 1 ? ay : az)) + sd;
+              const int na = a == 0 ? nlx : (a == 1 ? nly : nlz);
+              if (p < 0 || p >= na) continue;
+              const int nb = ia + sd * (a == 0 ? 1 : (a == 1 ? nlx : nlx * nly));
+              kab += tw[a] * (2.0 * kl[ia] * kl[nb] / (kl[ia] + kl[nb]));
+            }
+          } else if (ad == 1) {
+            const int a = dx != 0 ? 0 : (dy != 0 ? 1 : 2);
+            kab = -tw[a] * (2.0 * kl[ia] * kl[ib] / (kl[ia] + kl[ib]));
+          }
+        } else if (abs(dx) <= 1 && abs(dy) <= 1 && abs(dz) <= 1) {
           double kk[8];
           for (int c = 0; c < 8; ++c) {
             const int ex = ax - 1 + (c & 1), ey = ay - 1 + ((c >> 1) & 1), ez = az - 1 + ((c >> 2) & 1);
@@ -527,12 +592,12 @@ size_t local_lds_bytes(int M, int nl) {
          sizeof(int) * (16 + 16);
 }
 
-template <int M, int BS, int NLC>
+template <int M, int BS, int NLC, bool TP>
 static void launch_local_t(const LocalArgs& a, int blocks, hipStream_t s) {
   const size_t lds = local_lds_bytes(M, a.nl_max);
-  (void)hipFuncSetAttribute((const void*)k_local_eigen<M, BS, NLC>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  (void)hipFuncSetAttribute((const void*)k_local_eigen<M, BS, NLC, TP>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             int(lds));
-  hipLaunchKernelGGL((k_local_eigen<M, BS, NLC>), dim3(blocks), dim3(BS), lds, s, a);
+  hipLaunchKernelGGL((k_local_eigen<M, BS, NLC, TP>), dim3(blocks), dim3(BS), lds, s, a);
 }
 
 int launch_local_eigen(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, int bs, int m, int degree, int blocks,
@@ -565,10 +630,21 @@ int launch_local_eigen(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, int 
   // compile-time capacities: 8^3-node cells (H = 8) and 9^3 (the last cells
   // of a mesh of 8 k elements per axis)
 #define LL(M_, BS_, NLC_)                                              \
-  if (m == M_ && bs == BS_ && (NLC_ == 0 || a.nl_max == NLC_)) {       \
-    launch_local_t<M_, BS_, NLC_>(a, blocks, s);                       \
+  if (!c.tpfa && m == M_ && bs == BS_ && (NLC_ == 0 || a.nl_max == NLC_)) { \
+    launch_local_t<M_, BS_, NLC_, false>(a, blocks, s);                \
     return hipGetLastError() == hipSuccess ? MSMG_OK : MSMG_EHIP;      \
   }
+#define LT(M_, BS_, NLC_)                                              \
+  if (c.tpfa && m == M_ && bs == BS_ && (NLC_ == 0 || a.nl_max == NLC_)) { \
+    launch_local_t<M_, BS_, NLC_, true>(a, blocks, s);                 \
+    return hipGetLastError() == hipSuccess ? MSMG_OK : MSMG_EHIP;      \
+  }
+  LT(8, 256, 512)
+  LT(8, 512, 512)
+  LT(8, 256, 0)
+  LT(8, 512, 0)
+  LT(8, 768, 0)
+  LT(8, 1024, 0)
   LL(8, 256, 512)
   LL(8, 512, 512)
   LL(8, 512, 729)
@@ -579,6 +655,7 @@ int launch_local_eigen(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, int 
   LL(8, 768, 0)
   LL(8, 1024, 0)
 #undef LL
+#undef LT
   return MSMG_EINVAL;
 }
 

@@ -53,18 +53,33 @@ class SolveInfo(dict):
 
 
 class Solver:
-    """PCG with the three-grid multiscale preconditioner on an nx*ny*nz Q1 mesh."""
+    """PCG with the three-grid multiscale preconditioner on an nx*ny*nz mesh.
 
-    def __init__(self, nx, ny=None, nz=None, lx=1.0, ly=1.0, lz=1.0, device=None, **options):
+    discretisation="q1" (default): trilinear elements, unknowns on the
+    (nx+1)(ny+1)(nz+1) nodes, a nodal Dirichlet mask.  discretisation="tpfa":
+    the paper's cell-centred two-point flux finite volumes, unknowns on the
+    nx*ny*nz cells, the "mask" of set-up holds each cell's Dirichlet face bits
+    and the smoothing interval defaults to [0.2, 2].  ``nnodes`` is the
+    number of unknowns either way."""
+
+    def __init__(self, nx, ny=None, nz=None, lx=1.0, ly=1.0, lz=1.0, device=None, discretisation="q1", **options):
         if not torch.cuda.is_available():
             raise RuntimeError("the MsMG solver needs a HIP GPU")
         ny = nx if ny is None else ny
         nz = nx if nz is None else nz
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
-        self.nnodes = (self.nx + 1) * (self.ny + 1) * (self.nz + 1)
+        if discretisation not in ("q1", "tpfa"):
+            raise ValueError("discretisation must be 'q1' or 'tpfa'")
+        self.tpfa = discretisation == "tpfa"
+        e = 0 if self.tpfa else 1
+        self.nnodes = (self.nx + e) * (self.ny + e) * (self.nz + e)
         self.nelem = self.nx * self.ny * self.nz
         self.volume = float(lx) * float(ly) * float(lz)
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        if self.tpfa:
+            options = dict(options, discretisation=L.MSMG_TPFA)
+            options.setdefault("cheb_lo", 0.2)
+            options.setdefault("cheb_hi", 2.0)
         self.opts = L.default_options(**options)
         self._tune_cache = self.opts.tune_cache  # keep the bytes alive
         h = ctypes.c_void_p()

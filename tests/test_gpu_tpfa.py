@@ -1,0 +1,271 @@
+"""GPU parity of the cell-centred two-point flux (TPFA) path against the oracle
+(through the C ABI): the operator, the set-up's spectra, the preconditioner
+and PCG, plus the argument checks of the TPFA handle."""
+import ctypes
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import synth  # noqa: E402
+from gpu_common import KMAX, P, max_sin_angle, rel, to_dev  # noqa: E402
+from oracle import q1, tpfa  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    # name: (shape (nz, ny, nx), kind, seed, kmin, H, sd)
+    "cube16_noise_H8": ((16, 16, 16), "noise", 0, 1e-3, 8, 2),
+    "cube16_grf_c1e6_H4": ((16, 16, 16), "grf", 2, 1e-6, 4, 2),
+    "box20x12x9_grf_c1e4_H4": ((9, 12, 20), "grf", 3, 1e-4, 4, 3),
+    "cube12_noise_H2": ((12, 12, 12), "noise", 5, 1e-3, 2, 3),
+}
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    import paper_2410_06850_amd as p
+    return p
+
+
+def _field(shape, kind, seed):
+    if kind == "noise":
+        return synth.uniform_noise_rho(shape[2], seed, shape=shape).ravel()
+    return synth.grf_rho(shape[2], 4, seed=seed, shape=shape).ravel()
+
+
+def _flags(shape):
+    return synth.dirichlet_patch_faces(shape[2], shape[1], shape[0]).ravel()
+
+
+_cache = {}
+
+
+def _pair(pkg, name, **opts):
+    key = (name, tuple(sorted(opts.items())))
+    if key in _cache:
+        return _cache[key]
+    shape, kind, seed, kmin, H, sd = CASES[name]
+    rho = _field(shape, kind, seed)
+    flags = _flags(shape)
+    g = q1.Grid(shape[2], shape[1], shape[0])
+    deg = opts.get("cheb_degree", 2)
+    h = tpfa.Hierarchy(g, rho, kmin, KMAX, P, flags, tpfa.default_options(H=H, sd=sd, cheb_degree=deg))
+    s = pkg.Solver(shape[2], shape[1], shape[0], discretisation="tpfa", H=H, sd=sd, **opts)
+    s.setup(to_dev(rho), kmin, KMAX, P, to_dev(flags, torch.uint8))
+    _cache[key] = (g, h, s, rho, flags, kmin)
+    return _cache[key]
+
+
+APPLY_SHAPES = [
+    # (nz, ny, nx), box lengths: several 64 x 4 column tiles with ragged edges
+    ((16, 16, 16), (1.0, 1.0, 1.0)),
+    ((9, 12, 20), (2.0, 0.5, 0.3)),
+    ((5, 9, 70), (1.0, 1.0, 1.0)),
+    ((33, 7, 65), (0.7, 1.3, 2.1)),
+]
+
+
+@pytest.mark.parametrize("shape,lengths", APPLY_SHAPES)
+def test_apply_matches_oracle(pkg, shape, lengths):
+    print(f"case tpfa-apply {shape} {lengths}", flush=True)
+    nz, ny, nx = shape
+    g = q1.Grid(nx, ny, nz, lx=lengths[0], ly=lengths[1], lz=lengths[2])
+    rho = synth.grf_rho(nx, 3, seed=1, shape=shape).ravel()
+    kmin = 1e-6
+    # Dirichlet faces on the bottom patch and on the whole +x face
+    flags = _flags(shape).astype(np.uint8)
+    ex, ey, ez = g.element_coords()
+    flags[ex == nx - 1] |= np.uint8(1 << 1)
+    s = pkg.Solver(nx, ny, nz, lx=lengths[0], ly=lengths[1], lz=lengths[2], discretisation="tpfa", H=4, sd=2)
+    s.setup(to_dev(rho), kmin, KMAX, P, to_dev(flags, torch.uint8))
+    k = q1.conductivity(rho, kmin, KMAX, P)
+    A = tpfa.assemble(g, k, flags)
+    x = np.random.default_rng(0).standard_normal(g.nelem) * 100.0
+    y = s.apply(to_dev(x)).cpu().numpy()
+    want = A @ x
+    err = np.abs(y - want).max() / np.abs(want).max()
+    print(f"  max rel err {err:.3e}")
+    assert err <= 1e-13
+    s.close()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_local_eigenpairs_match_oracle(pkg, name):
+    print(f"case tpfa-local-eigen {name}", flush=True)
+    g, h, s, rho, flags, kmin = _pair(pkg, name)
+    Lc = h.o.Lc
+    ev = s.export(0, h.n_c).numpy().reshape(-1, Lc)
+    st = s.export(5, len(h.cells), torch.int32).numpy()
+    Rc = s.export(1, g.nelem * Lc).numpy().reshape(g.nelem, Lc)
+    bound = 4.0 * (1 / g.hx ** 2 + 1 / g.hy ** 2 + 1 / g.hz ** 2)
+    checked = 0
+    for ci in range(len(h.cells)):
+        want = h.cell_evals[ci]
+        nl = len(want)
+        assert ((st[ci] >> 20) & 0xFF) == nl
+        assert not (st[ci] >> 28) & 1, f"cell {ci} did not converge"
+        got = ev[ci, :nl]
+        assert np.all(np.abs(got - want) <= 1e-9 * np.maximum(np.abs(want), 1e-3 * bound)), (ci, got, want)
+        nodes, phi = h.cell_basis[ci]
+        K, m, _ = h.local_problem(*h.cells[ci])
+        lam_all = np.linalg.eigvalsh(K / np.sqrt(m)[:, None] / np.sqrt(m)[None, :])
+        gap = lam_all[nl] - lam_all[nl - 1] if nl < len(lam_all) else np.inf
+        if gap < 1e-6 * bound:
+            continue
+        sa = max_sin_angle(phi, Rc[nodes, :nl], m)
+        assert sa <= 1e-6, (ci, sa)
+        checked += 1
+    assert checked > 0
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_coarse_spectra_match_oracle(pkg, name):
+    """Basis-invariant checks of A_c, the cc eigenvalues and A_cc."""
+    print(f"case tpfa-coarse-spectra {name}", flush=True)
+    g, h, s, rho, flags, kmin = _pair(pkg, name)
+    Lc = h.o.Lc
+    ncells = len(h.cells)
+    Ac = s.export(2, ncells * 27 * Lc * Lc).numpy().reshape(ncells, 27, Lc, Lc)
+    n_c = ncells * Lc
+    D = np.zeros((n_c, n_c))
+    for ci, (cx, cy, cz) in enumerate(h.cells):
+        for b in range(27):
+            ox, oy, oz = b % 3 - 1, (b // 3) % 3 - 1, b // 9 - 1
+            x, y, z = cx + ox, cy + oy, cz + oz
+            if 0 <= x < h.nc[0] and 0 <= y < h.nc[1] and 0 <= z < h.nc[2]:
+                cj = h.cell_id(x, y, z)
+                D[ci * Lc:(ci + 1) * Lc, cj * Lc:(cj + 1) * Lc] = Ac[ci, b]
+            elif (abs(ox) + abs(oy) + abs(oz)) > 0:
+                assert not Ac[ci, b].any()
+            if abs(ox) + abs(oy) + abs(oz) > 1:
+                assert not Ac[ci, b].any(), "TPFA couples face neighbours only"
+    valid = np.concatenate([np.arange(len(h.cell_rows[ci])) + ci * Lc for ci in range(ncells)])
+    Dg = D[np.ix_(valid, valid)]
+    assert np.abs(Dg - Dg.T).max() <= 1e-11 * np.abs(Dg).max()
+    eg = np.linalg.eigvalsh(0.5 * (Dg + Dg.T))
+    eo = np.linalg.eigvalsh(h.Ac.toarray())
+    assert np.abs(eg - eo).max() <= 1e-9 * np.abs(eo).max()
+    cc = s.export(3, h.n_cc).numpy()
+    want = np.concatenate(h.cc_evals)
+    assert np.abs(cc - want).max() <= 1e-8 * np.abs(want).max() + 1e-12
+    Acc = s.export(4, h.n_cc * h.n_cc).numpy().reshape(h.n_cc, h.n_cc)
+    e1 = np.linalg.eigvalsh(0.5 * (Acc + Acc.T))
+    e2 = np.linalg.eigvalsh(h.Acc)
+    assert np.abs(e1 - e2).max() <= 1e-8 * np.abs(e2).max()
+
+
+def _predicted_subspace_error(g, h, tol=1e-12):
+    b1 = 2 * (1 + np.sqrt(2)) * (1 / g.hx ** 2 + 1 / g.hy ** 2 + 1 / g.hz ** 2)
+    e1 = max([tol * b1 / gp for gp in h.cell_gaps if gp > 0] + [0.0])
+    e2 = max([tol * nrm / gp for gp, nrm in zip(h.cc_gaps, h.cc_norms) if gp > 0] + [0.0])
+    return max(e1, e2)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_preconditioner_apply_matches_oracle(pkg, name):
+    """z = M^-1 r matches to the accuracy of the computed coarse spaces."""
+    print(f"case tpfa-precondition {name}", flush=True)
+    g, h, s, rho, flags, kmin = _pair(pkg, name)
+    r = np.random.default_rng(4).standard_normal(g.nelem)
+    want = h.precondition(r)
+    got = s.precondition(to_dev(r)).cpu().numpy()
+    bound = max(1e-10, 100 * _predicted_subspace_error(g, h))
+    print(f"  rel={rel(got, want):.3e} bound={bound:.3e}")
+    assert rel(got, want) <= bound
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_solve_matches_oracle(pkg, name):
+    print(f"case tpfa-solve {name}", flush=True)
+    g, h, s, rho, flags, kmin = _pair(pkg, name)
+    kind = CASES[name][1]
+    f = tpfa.cell_load(g, 1.0 - rho ** 3)
+    td = np.full(g.nelem, 100.0)
+    s.setup(to_dev(rho), kmin, KMAX, P, to_dev(flags, torch.uint8), to_dev(td))
+    rtol = 1e-12 if kind == "noise" else 1e-10
+    Tlo = torch.empty(g.nelem, dtype=torch.float64, device="cuda")
+    T, info = s.solve(to_dev(f), rtol=rtol, maxit=500, T_lo=Tlo)
+    assert info.code == 0, info
+    T, Tlo = T.cpu().numpy(), Tlo.cpu().numpy()
+    # the oracle's own residual of the GPU iterate (difference form, both parts)
+    b = tpfa.rhs(g, h.k, flags, f, td)
+    op = h.A
+    r = b - op.free_product(T.astype(np.longdouble) + Tlo.astype(np.longdouble))
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= rtol * (1 + 1e-2)
+    To, res, _ = tpfa.solve(g, rho, f, flags, kmin, KMAX, P, hier=h, rtol=rtol, maxit=500, td=td)
+    assert res.status == "converged"
+    err = rel(T + Tlo, To + res.x_lo)
+    print(f"  gpu it={info.iterations} oracle it={res.iterations} rel.err={err:.3e}")
+    assert err <= (1e-10 if kind == "noise" else 1e-4)
+    _, info8 = s.solve(to_dev(f), rtol=1e-8, maxit=500)
+    _, res8, _ = tpfa.solve(g, rho, f, flags, kmin, KMAX, P, hier=h, rtol=1e-8, td=td)
+    print(f"  rtol 1e-8: gpu it={info8.iterations} oracle it={res8.iterations}")
+    assert abs(info8.iterations - res8.iterations) <= 1, (info8.iterations, res8.iterations)
+    # the adjoint solve: zero Dirichlet values, the same operator
+    lam, ia = s.solve_adjoint(to_dev(f), rtol=1e-10, maxit=500)
+    la = tpfa.solve_direct(g, h.k, flags, f, None)
+    assert ia.code == 0 and rel(lam.cpu().numpy(), la) <= (1e-8 if kind == "noise" else 1e-4)
+
+
+@pytest.mark.parametrize("opts", [dict(cheb_degree=3), dict(cheb_degree=1), dict(pc_kind=1)])
+def test_other_smoothers_match_oracle(pkg, opts):
+    """Chebyshev degrees other than 2 and the smoother-only preconditioner."""
+    name = "cube16_noise_H8"
+    print(f"case tpfa-smoothers {opts}", flush=True)
+    g, h, s, rho, flags, kmin = _pair(pkg, name, **opts)
+    r = np.random.default_rng(9).standard_normal(g.nelem)
+    if opts.get("pc_kind") == 1:
+        want = h.chebyshev(r)
+    else:
+        want = h.precondition(r)
+    got = s.precondition(to_dev(r)).cpu().numpy()
+    print(f"  rel={rel(got, want):.3e}")
+    assert rel(got, want) <= 1e-10
+
+
+def test_shipped_hierarchy_iterations(pkg):
+    """H = 8 with a full coarse-coarse cell of 4^3 coarse cells (dimension 256)
+    at contrast 1e6: PCG iterations within one of the oracle's."""
+    shape = (32, 32, 32)
+    print("case tpfa-shipped cube32 grf c1e6 H8 sd4", flush=True)
+    rho = synth.grf_rho(32, 4, seed=11, shape=shape).ravel()
+    flags = _flags(shape)
+    g = q1.Grid(32)
+    kmin = 1e-6
+    h = tpfa.Hierarchy(g, rho, kmin, KMAX, P, flags, tpfa.default_options(H=8, sd=4))
+    s = pkg.Solver(32, discretisation="tpfa", H=8, sd=4)
+    td = np.full(g.nelem, 100.0)
+    s.setup(to_dev(rho), kmin, KMAX, P, to_dev(flags, torch.uint8), to_dev(td))
+    f = tpfa.cell_load(g, 1.0 - rho ** 3)
+    _, info = s.solve(to_dev(f), rtol=1e-8, maxit=500)
+    _, res, _ = tpfa.solve(g, rho, f, flags, kmin, KMAX, P, hier=h, rtol=1e-8, td=td)
+    print(f"  gpu it={info.iterations} oracle it={res.iterations}")
+    assert info.code == 0 and res.status == "converged"
+    assert abs(info.iterations - res.iterations) <= 1
+    r = np.random.default_rng(2).standard_normal(g.nelem)
+    got = s.precondition(to_dev(r)).cpu().numpy()
+    want = h.precondition(r)
+    assert rel(got, want) <= max(1e-10, 100 * _predicted_subspace_error(g, h))
+    s.close()
+
+
+def test_tpfa_argument_checks(pkg):
+    from paper_2410_06850_amd import _lib as L
+    shape = (8, 8, 8)
+    rho = to_dev(np.full(512, 0.5))
+    s = pkg.Solver(8, discretisation="tpfa", H=4, sd=2)
+    bad = np.zeros(512, dtype=np.uint8)
+    bad[(3 * 8 + 3) * 8 + 3] = 1  # a -x face inside the mesh
+    with pytest.raises(RuntimeError):
+        s.setup(rho, 1e-3, KMAX, P, to_dev(bad, torch.uint8))
+    with pytest.raises(RuntimeError):
+        s.setup(rho, 1e-3, KMAX, P, to_dev(np.zeros(512, dtype=np.uint8), torch.uint8))
+    s.setup(rho, 1e-3, KMAX, P, to_dev(_flags(shape), torch.uint8))
+    with pytest.raises(RuntimeError):
+        s.sensitivity(torch.zeros(512, dtype=torch.float64, device="cuda"))
+    s.close()
+    o = L.default_options(discretisation=L.MSMG_TPFA, H=4, sd=2)  # Q1 smoothing interval: rejected
+    hnd = ctypes.c_void_p()
+    assert L.lib().msmg_create(ctypes.byref(hnd), 8, 8, 8, 1.0, 1.0, 1.0, ctypes.byref(o)) == L.MSMG_EINVAL

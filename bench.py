@@ -442,6 +442,72 @@ def run_workload(name, args):
     print(json.dumps(out), flush=True)
 
 
+def run_tpfa(pkg, rho, n, steps, warmup, rtol=RTOL):
+    """The paper's own discretisation, cell-centred TPFA, on the same design
+    field: the bottom patch as Dirichlet faces at T_D = 100 and the
+    design-dependent heat source f0 (1 - rho^p), f0 = 1 (the state problem of
+    the paper's section 4); FP64 throughout.  One step = set-up + solve from
+    zero; value counts the solve."""
+    import torch
+
+    dev = rho.device
+    flags = torch.tensor(synth.dirichlet_patch_faces(n, n, n).ravel(), device=dev)
+    td = torch.full((n ** 3,), 100.0, dtype=torch.float64, device=dev)
+    s = pkg.Solver(n, discretisation="tpfa", timing=1, tune_cache=TUNE_CACHE)
+    T = T_lo = None
+    recs = []
+    for k in range(warmup + steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.setup(rho, KMIN, 1.0, 3, flags, td)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        f = s.heat_source_load(1.0)
+        if T is None:
+            T, T_lo = torch.empty_like(f), torch.empty_like(f)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        T, info = s.solve(f, T, rtol=rtol, maxit=2000, T_lo=T_lo)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        _log(f"tpfa step {k}: setup {1e3 * (t1 - t0):.1f} ms, solve {1e3 * (t3 - t2):.1f} ms "
+             f"({info.iterations} it, rel.res {info.rel_res:.2e}, code {info.code}), apply {info.apply_ms * 1e3:.1f} us")
+        if info.code != 0:
+            raise RuntimeError(f"tpfa: solve did not converge: {dict(info)}")
+        if k >= warmup:
+            recs.append(dict(setup=t1 - t0, solve=t3 - t2, info=dict(info)))
+    apply_ms = s.time_apply(T, 50)
+    _, i6 = s.solve(f, rtol=1e-6, maxit=2000)
+    t = float(np.mean([r["solve"] for r in recs]))
+    apply_in_solve_ms = float(np.mean([r["info"]["apply_ms"] for r in recs]))
+    apply_bytes = 25.0 * n ** 3  # x and k read (8 B each), the face flags (1 B), y written (8 B)
+    ach = apply_bytes / (apply_ms * 1e-3) / 1e9
+    ph = np.mean([r["info"]["setup_phase_ms"] for r in recs], axis=0)
+    del s
+    torch.cuda.empty_cache()
+    return {
+        "workload": f"cube{n}_tpfa_grf{ELL * n // N}_c1e6",
+        "discretisation": "cell-centred two-point flux finite volumes (harmonic face conductivities), FP64",
+        "problem": "T_D = 100 on the bottom-patch faces, heat source f0 (1 - rho^3), f0 = 1",
+        "cells": n ** 3,
+        "value": n ** 3 / t,
+        "unit": "DOFs/s",
+        "iterations": recs[-1]["info"]["iterations"],
+        "rel_res": recs[-1]["info"]["rel_res"],
+        "iterations_rtol_1e-6": i6.iterations,
+        "solve_ms": 1e3 * t,
+        "setup_ms": 1e3 * float(np.mean([r["setup"] for r in recs])),
+        "setup_phases_ms": {"local_spectral_problems": float(ph[0]), "galerkin_Ac": float(ph[1]),
+                            "coarse_coarse_problems": float(ph[2]), "Acc_and_inverse": float(ph[3])},
+        "precond_us": 1e3 * float(np.mean([r["info"]["precond_ms"] for r in recs])),
+        "roofline": {"kernel": "k_tpfa_apply (PCG operator apply q = A p, FP64, difference form)", "bound": "hbm",
+                     "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                     "apply_us": apply_ms * 1e3, "apply_us_in_solve": apply_in_solve_ms * 1e3,
+                     "timing": "HIP events around 50 back-to-back launches of the PCG apply kernel",
+                     "bytes_per_launch": apply_bytes},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -452,6 +518,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 comparison path")
     ap.add_argument("--no-f32", action="store_true", help="skip the FP32-cycle comparison path")
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16-copies comparison path")
+    ap.add_argument("--no-tpfa", action="store_true", help="skip the cell-centred TPFA companion line")
     ap.add_argument("--optimizer", choices=("mma", "oc"), default="mma",
                     help="design update of the optimisation workloads (cube128_to_512_continuation, cube512_topopt)")
     ap.add_argument("--copies", choices=("bf16", "f32", "mixed"), default="bf16",
@@ -518,6 +585,9 @@ def main():
                 raise RuntimeError(f"{tag}: solve did not converge: {dict(info)}")
             if k >= warmup:
                 recs.append(dict(setup=t1 - t0, solve=t2 - t1, sens=t3 - t2, step=t3 - t0, info=dict(info)))
+        # the apply kernel alone, launched back to back on this set-up (the
+        # in-solve events above also count each launch's dispatch gap)
+        recs[-1]["apply_b2b_ms"] = s.time_apply(T, 50)
         if keep is not None:
             keep[tag] = (T + T_lo).cpu()
             if tag == "fp64":
@@ -551,8 +621,12 @@ def main():
     t_step = float(np.mean([r["step"] for r in mix]))
     info = mix[-1]["info"]
     # dominant kernel: the PCG operator apply (one launch per iteration), timed
-    # with HIP events on the solve stream inside the timed steps
-    apply_ms = float(np.mean([r["info"]["apply_ms"] for r in mix]))
+    # with HIP events on the solve stream: 50 back-to-back launches of the
+    # PCG's apply kernel on the last set-up (msmg_time_apply), and, for
+    # reference, per launch inside the timed solves (which adds each launch's
+    # dispatch gap)
+    apply_ms = float(mix[-1]["apply_b2b_ms"])
+    apply_in_solve_ms = float(np.mean([r["info"]["apply_ms"] for r in mix]))
     nn, ne = (n + 1) ** 3, n ** 3
     apply_bytes = 16 * nn + 8 * ne + nn / 8  # p read, q written, the FP64 density read, mask bits
     achieved = apply_bytes / (apply_ms * 1e-3) / 1e9
@@ -628,6 +702,11 @@ def main():
                                "frac": dgf / dms / FP64_PEAK_TFLOPS if dms > 0 else None},
         }
 
+    tpfa_line = None
+    if not args.no_tpfa:
+        _log("TPFA (cell-centred) path")
+        tpfa_line = run_tpfa(pkg, rho, n, args.steps, args.warmup)
+
     cpu = None
     if not args.no_cpu_baseline:
         _log("CPU oracle baseline")
@@ -674,9 +753,12 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
             "apply_us": apply_ms * 1e3,
+            "apply_us_in_solve": apply_in_solve_ms * 1e3,
+            "timing": "HIP events around 50 back-to-back launches of the PCG apply kernel on the solve stream",
             "bytes_per_launch": apply_bytes,
             "ceiling": ceiling,
         },
+        "tpfa": tpfa_line,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -288,6 +288,16 @@ int msmg_element_load(msmg_handle* h, const double* src, double src_const, doubl
 int msmg_stream_ceiling(const double* x, const double* k, double* y, long long nn, long long ne, int reps, double* ms,
                         hipStream_t stream);
 
+/* Measurement aid: the PCG's operator-apply kernel (q = A p with its step
+ * reduction, the kernel of every PCG iteration) launched reps times back to
+ * back on p = x after the last msmg_setup; *ms (host pointer) receives the
+ * mean time per launch from HIP events around the batch, so per-launch
+ * dispatch gaps are amortised rather than counted once each.  x: nodal FP64
+ * device array (cells for TPFA), not zero on free entries.  Uses the
+ * handle's PCG work vectors and scalars (do not overlap with a solve on the
+ * handle).  Blocks until done. */
+int msmg_time_apply(msmg_handle* h, const double* x, int reps, double* ms, hipStream_t stream);
+
 /* Interpolation step between resolutions (section 3, interpolation technique):
  * Tc on the (nx,ny,nz) mesh -> Tf on the (2nx,2ny,2nz) mesh, the coarse trilinear
  * function evaluated at the fine nodes (no handle needed). */

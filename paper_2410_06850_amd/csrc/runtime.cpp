@@ -543,10 +543,6 @@ static void init_handle(msmg_handle* h, const msmg_options& o, const Plan& P, in
     // face, T/m_K + T/sqrt(m_K m_L) <= (1 + sqrt 2) / h_d^2, two faces per axis
     const double s2 = 1.0 / (h->g.hx * h->g.hx) + 1.0 / (h->g.hy * h->g.hy) + 1.0 / (h->g.hz * h->g.hz);
     h->lam_bound = 2.0 * (1.0 + std::sqrt(2.0)) * s2;
-    // the stencil launches reduce over one workgroup per 64 x 4 column tile
-    // and z chunk: enough reduction slots for one chunk per column
-    const long long cols = (long long)((nx + 63) / 64) * ((ny + 3) / 4);
-    h->red_blocks = int(std::max<long long>(4096, ((cols + 8 + 7) / 8) * 8));
   }
   h->hier = P.h;
   h->CX = P.CX;
@@ -603,6 +599,10 @@ extern "C" int msmg_create(msmg_handle** out, int nx, int ny, int nz, double lx,
   msmg_handle* h = new msmg_handle();
   init_handle(h, o, P, nx, ny, nz, lx, ly, lz);
   HIP_TRY(hipGetDevice(&h->device));
+  if (h->tpfa && !tpfa_grid_fits(make_ctx(h))) {
+    delete h;
+    return fail(MSMG_EINVAL, "the TPFA stencil grid exceeds its workgroup budget (nx * ny too large)");
+  }
   h->march_resident = march_resident_blocks();
   h->apply_resident = apply_resident_blocks();
   int rc = alloc_arrays(h, false, nullptr);
@@ -917,6 +917,18 @@ static void precondition(msmg_handle* h, const Ctx& c, VecSet& V, const double* 
   launch_vc_output(c, V.v_r2, true, V.v_r1, z, r, q, mode, s);    // y = r2 + ...
 }
 
+// The PCG's products with A on either discretisation: q = A p with the step
+// length reduction, and b - A x (x + xlo) with the true-residual reduction.
+static void op_apply_pcg(const Ctx& c, const double* p, double* q, hipStream_t s) {
+  if (c.tpfa) launch_tpfa_apply(c, p, q, true, s);
+  else launch_apply(c, p, q, 1, s);
+}
+static void op_residual(const Ctx& c, const double* b, const double* x, const float* xlo, double* y, bool reduce,
+                        hipStream_t s) {
+  if (c.tpfa) launch_tpfa_residual(c, b, x, xlo, y, reduce, s);
+  else launch_residual(c, b, x, xlo, y, reduce, s);
+}
+
 static int read_scalars(VecSet& V, hipStream_t s) {
   HIP_TRY(hipMemcpyAsync(V.sc_host, V.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -1001,6 +1013,37 @@ extern "C" int msmg_element_load(msmg_handle* h, const double* src, double scons
   return MSMG_OK;
 }
 
+extern "C" int msmg_time_apply(msmg_handle* h, const double* x, int reps, double* ms, hipStream_t s) {
+  if (!h || !x || !ms) return fail(MSMG_EINVAL, "NULL argument");
+  if (reps < 1) return fail(MSMG_EINVAL, "reps must be >= 1");
+  if (!h->setup_done) return fail(MSMG_ESTATE, "msmg_setup has not completed");
+  Ctx c = make_ctx(h);
+  VecSet& V = h->vs[0];
+  if (h->opt.lean_memory) h->basis_live = false;
+  // p = x (zero fixed entries), r^T z = p^T p > 0, so that every launch of the
+  // PCG's apply runs its step reduction and leaves the iteration undone
+  launch_sc_reset(c, 1, 1 << 30, s);
+  launch_zero_fixed_copy(c, x, V.p, s);
+  launch_vc_output(c, V.p, true, nullptr, V.z, V.p, nullptr, 0, s);
+  op_apply_pcg(c, V.p, V.q, s);  // warm-up
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  hipError_t err = hipEventCreate(&e1);
+  if (err == hipSuccess) err = hipEventRecord(e0, s);
+  for (int r = 0; r < reps && err == hipSuccess; ++r) op_apply_pcg(c, V.p, V.q, s);
+  if (err == hipSuccess) err = hipEventRecord(e1, s);
+  if (err == hipSuccess) err = hipEventSynchronize(e1);
+  float t = 0.f;
+  if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+  (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (err != hipSuccess) return fail(MSMG_EHIP, std::string("apply timing: ") + hipGetErrorString(err));
+  TRY(read_scalars(V, s));
+  if (V.sc_host->done) return fail(MSMG_EINVAL, "x gives p^T A p <= 0 (zero or non-finite input)");
+  *ms = double(t) / reps;
+  return MSMG_OK;
+}
+
 extern "C" int msmg_stream_ceiling(const double* x, const double* k, double* y, long long nn, long long ne, int reps,
                                    double* ms, hipStream_t s) {
   if (!x || !k || !y || !ms) return fail(MSMG_EINVAL, "NULL argument");
@@ -1046,18 +1089,6 @@ static void fill_setup_timing(const msmg_handle* h, msmg_info* info) {
   for (int k = 0; k < 4; ++k) info->setup_phase_ms[k] = h->setup_phase_ms[k];
   info->setup_dense_ms = h->setup_dense_ms;
   info->setup_dense_gflop = h->setup_dense_gflop;
-}
-
-// The PCG's products with A on either discretisation: q = A p with the step
-// length reduction, and b - A x (x + xlo) with the true-residual reduction.
-static void op_apply_pcg(const Ctx& c, const double* p, double* q, hipStream_t s) {
-  if (c.tpfa) launch_tpfa_apply(c, p, q, true, s);
-  else launch_apply(c, p, q, 1, s);
-}
-static void op_residual(const Ctx& c, const double* b, const double* x, const float* xlo, double* y, bool reduce,
-                        hipStream_t s) {
-  if (c.tpfa) launch_tpfa_residual(c, b, x, xlo, y, reduce, s);
-  else launch_residual(c, b, x, xlo, y, reduce, s);
 }
 
 // PCG driver shared by the state and adjoint solves.  `homogeneous` solves

@@ -15,7 +15,8 @@
 // The stencil kernels march a 64 x 4 column tile of threads through a z range
 // of cells, each thread one (x, y) column; the x and k values of the cells
 // below, at and above the current one stay in registers, the four in-plane
-// neighbours come through the caches.
+// neighbours come through the caches (staging the planes in LDS measured
+// slower: the barrier per plane exposes the load latency).
 #include "internal.h"
 #include "setup.h"
 
@@ -24,6 +25,9 @@ namespace msmg {
 namespace {
 
 constexpr int TX = 64, TY = 4;
+// workgroups of one stencil launch at most (the reducing launches publish one
+// partial per workgroup; the handle keeps at least this many slots)
+constexpr long long TILE_BUDGET = 8192;
 
 struct TGeo {
   int nx, ny, nz;
@@ -44,10 +48,11 @@ TGeo tgeo(const Ctx& c) {
   t.w[2] = c.g.hx * c.g.hy / c.g.hz;
   t.ntx = (t.nx + TX - 1) / TX;
   t.nty = (t.ny + TY - 1) / TY;
-  // z chunks: as many as the reduction's block budget allows (grids are
-  // padded to multiples of 8 for the XCD remap)
+  // z chunks of about 8 cells, as many as the workgroup budget allows
+  // (grids are padded to multiples of 8 for the XCD remap)
   const long long cols = (long long)t.ntx * t.nty;
-  long long nzt = std::max<long long>(1, std::min<long long>(t.nz, (c.red_blocks - 8) / std::max<long long>(cols, 1)));
+  const long long want = (t.nz + 7) / 8;
+  long long nzt = std::max<long long>(1, std::min<long long>(want, (TILE_BUDGET - 8) / std::max<long long>(cols, 1)));
   t.zc = int((t.nz + nzt - 1) / nzt);
   t.ntz = (t.nz + t.zc - 1) / t.zc;
   t.tiles = cols * t.ntz;
@@ -88,36 +93,61 @@ MSMG_DEV ColumnTile column_tile(const TGeo& t) {
 // Marches the thread's column and calls body(n, kc, vc, acc) with
 // acc = (A v)_n, where v_m = V(m) is any per-cell value (a vector, or a
 // product of vectors formed on the fly).  Absent neighbours take the cell's
-// own k and value, so their terms vanish without a branch.
+// own k and value, so their terms vanish without a branch.  The loads of the
+// next z step (its four in-plane neighbours, its flags and the cell two
+// planes up) are issued before the current step's arithmetic, so that two
+// steps' loads are in flight per thread.
 template <typename VF, typename Body>
 MSMG_DEV void tpfa_march(const TGeo& t, const ColumnTile& c, const double* __restrict__ k,
                          const uint8_t* __restrict__ df, VF V, Body body) {
   if (!c.active) return;
   const long long sx = 1, sy = t.nx, sz = (long long)t.nx * t.ny;
-  const long long base = (long long)c.j * sy + c.i;
-  long long n = base + (long long)c.z0 * sz;
+  const bool xm = c.i > 0, xp = c.i + 1 < t.nx, ym = c.j > 0, yp = c.j + 1 < t.ny;
+  const long long oxm = xm ? -sx : 0, oxp = xp ? sx : 0, oym = ym ? -sy : 0, oyp = yp ? sy : 0;
+  struct Ring {
+    double kxm, kxp, kym, kyp, vxm, vxp, vym, vyp;
+    unsigned f;
+  };
+  auto ring = [&](long long m) {
+    Ring r;
+    r.kxm = k[m + oxm];
+    r.kxp = k[m + oxp];
+    r.kym = k[m + oym];
+    r.kyp = k[m + oyp];
+    r.vxm = V(m + oxm);
+    r.vxp = V(m + oxp);
+    r.vym = V(m + oym);
+    r.vyp = V(m + oyp);
+    r.f = df[m];
+    return r;
+  };
+  long long n = (long long)c.j * sy + c.i + (long long)c.z0 * sz;
   double kc = k[n], vc = V(n);
-  double km = kc, vm = vc;
+  double km = kc, vm = vc, kp = kc, vp = vc;
   if (c.z0 > 0) {
     km = k[n - sz];
     vm = V(n - sz);
   }
+  if (c.z0 + 1 < t.nz) {
+    kp = k[n + sz];
+    vp = V(n + sz);
+  }
+  Ring cur = ring(n);
   for (int z = c.z0; z < c.z1; ++z, n += sz) {
-    double kp = kc, vp = vc;
-    if (z + 1 < t.nz) {
-      kp = k[n + sz];
-      vp = V(n + sz);
+    Ring nxt = cur;
+    double kpp = kp, vpp = vp;
+    if (z + 1 < c.z1) {
+      nxt = ring(n + sz);
+      if (z + 2 < t.nz) {
+        kpp = k[n + 2 * sz];
+        vpp = V(n + 2 * sz);
+      }
     }
-    const bool xm = c.i > 0, xp = c.i + 1 < t.nx, ym = c.j > 0, yp = c.j + 1 < t.ny;
-    const long long nxm = xm ? n - sx : n, nxp = xp ? n + sx : n, nym = ym ? n - sy : n, nyp = yp ? n + sy : n;
-    const double kxm = k[nxm], kxp = k[nxp], kym = k[nym], kyp = k[nyp];
-    const double vxm = V(nxm), vxp = V(nxp), vym = V(nym), vyp = V(nyp);
-    const unsigned f = df[n];
-    double acc = dir_w(t, f, kc) * vc;
-    acc += face_T(t.w[0], kc, kxm) * (vc - vxm);
-    acc += face_T(t.w[0], kc, kxp) * (vc - vxp);
-    acc += face_T(t.w[1], kc, kym) * (vc - vym);
-    acc += face_T(t.w[1], kc, kyp) * (vc - vyp);
+    double acc = dir_w(t, cur.f, kc) * vc;
+    acc += face_T(t.w[0], kc, cur.kxm) * (vc - cur.vxm);
+    acc += face_T(t.w[0], kc, cur.kxp) * (vc - cur.vxp);
+    acc += face_T(t.w[1], kc, cur.kym) * (vc - cur.vym);
+    acc += face_T(t.w[1], kc, cur.kyp) * (vc - cur.vyp);
     acc += face_T(t.w[2], kc, km) * (vc - vm);
     acc += face_T(t.w[2], kc, kp) * (vc - vp);
     body(n, kc, vc, acc);
@@ -125,6 +155,9 @@ MSMG_DEV void tpfa_march(const TGeo& t, const ColumnTile& c, const double* __res
     vm = vc;
     kc = kp;
     vc = vp;
+    kp = kpp;
+    vp = vpp;
+    cur = nxt;
   }
 }
 
@@ -521,7 +554,7 @@ static_assert(LC_MAX == 8, "TL_DISPATCH covers 1 .. 8");
 
 bool tpfa_grid_fits(const Ctx& c) {
   const TGeo t = tgeo(c);
-  return tgrid(t) <= unsigned(c.red_blocks);
+  return (long long)tgrid(t) <= TILE_BUDGET;
 }
 
 void launch_tpfa_apply(const Ctx& c, const double* x, double* y, bool reduce, hipStream_t s) {

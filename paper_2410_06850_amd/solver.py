@@ -208,6 +208,13 @@ class Solver:
         L.check(L.lib().msmg_apply(self._h, _ptr(x), _ptr(y), _stream()), "msmg_apply")
         return y
 
+    def time_apply(self, x, reps=50):
+        """Mean time (ms) of the PCG's operator-apply kernel over reps back-to-back launches on p = x."""
+        x = _need(x, "x", torch.float64, self.nnodes, self.device)
+        ms = ctypes.c_double()
+        L.check(L.lib().msmg_time_apply(self._h, _ptr(x), int(reps), ctypes.byref(ms), _stream()), "msmg_time_apply")
+        return ms.value
+
     def precondition(self, r, z=None):
         r = _need(r, "r", torch.float64, self.nnodes, self.device)
         z = torch.empty_like(r) if z is None else _need(z, "z", torch.float64, self.nnodes, self.device)

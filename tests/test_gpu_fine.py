@@ -147,3 +147,29 @@ def test_error_paths(msmg):
     s.setup(rho, 1e-3, 1.0, 3, to_dev(patch_mask(n), torch.uint8))
     T, info = s.solve(f)
     assert info.code == 0 and float(T.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("tpfa", [False, True])
+def test_time_apply_leaves_the_solver_usable(msmg, tpfa):
+    """msmg_time_apply runs the PCG apply kernel on p = x and reports a time;
+    x with p^T A p = 0 is refused; a solve afterwards is unchanged."""
+    import paper_2410_06850_amd._lib as L
+    print(f"case time-apply tpfa={tpfa}", flush=True)
+    n = 16
+    rho = to_dev(field(n))
+    if tpfa:
+        import synth
+        s = msmg.Solver(n, discretisation="tpfa", H=8, sd=2)
+        s.setup(rho, 1e-3, KMAX, P, to_dev(synth.dirichlet_patch_faces(n, n, n).ravel(), torch.uint8))
+    else:
+        s = msmg.Solver(n, H=8, sd=2)
+        s.setup(rho, 1e-3, KMAX, P, to_dev(patch_mask(n), torch.uint8))
+    f = s.element_load(const=1.0)
+    T0, i0 = s.solve(f, rtol=1e-10)
+    ms = s.time_apply(T0, 5)
+    assert ms > 0.0
+    with pytest.raises(L.MsmgError) as e:
+        s.time_apply(torch.zeros_like(f), 2)
+    assert e.value.code == L.MSMG_EINVAL
+    T1, i1 = s.solve(f, rtol=1e-10)
+    assert i1.iterations == i0.iterations and torch.equal(T0, T1)

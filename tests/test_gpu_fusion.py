@@ -22,7 +22,10 @@ MIXED = dict(vcycle_dtype=0, rho_v_dtype=2, basis_dtype=1)
 def _z(n, rho, mask, kmin, H, sd, r, **opts):
     import paper_2410_06850_amd as pkg
 
-    s = pkg.Solver(n, H=H, sd=sd, **opts)
+    # a fixed level-1 launch shape: the tuner picks it by timing, and two
+    # handles that picked different shapes hold bases that differ in the last
+    # bits, which the bitwise checks below would see
+    s = pkg.Solver(n, H=H, sd=sd, autotune=0, **opts)
     s.setup(to_dev(rho), kmin, KMAX, P, to_dev(mask, torch.uint8))
     z = s.precondition(to_dev(r))
     f = s.element_load(const=1.0)

@@ -363,6 +363,19 @@ int msmg_oc_update_noalloc(int nx, int ny, int nz, const double* x, const double
                            double volume_fraction, double move, double eta, double x_min, double* x_new,
                            double* lambda, hipStream_t stream);
 
+/* Objective values of the optimisation loop (section 2.3: the compliance
+ * c = f^T T, the mean temperature of eq. cost function c = w^T T): *out = a^T b
+ * over n <= the handle's unknowns, summed in a fixed order (bitwise
+ * reproducible).  a, b: FP64 device arrays; out: one FP64 device value.  Uses
+ * the handle's reduction scratch (do not overlap with other calls on the
+ * handle). */
+int msmg_dot(msmg_handle* h, const double* a, const double* b, long long n, double* out, hipStream_t stream);
+
+/* Chain-rule scaling of a gradient (section 2.3): y = c * s * x over n entries,
+ * with s = *s_dev read on the device (an upstream gradient; s_dev NULL: s = 1).
+ * x, y: FP64 device arrays (y may alias x). */
+int msmg_scale(const double* x, long long n, double c, const double* s_dev, double* y, hipStream_t stream);
+
 /* Diagnostics of the last set-up, copied to host memory (blocking):
  *   what = 0: level-1 eigenvalues, ncells*Lc doubles (padded entries 0)
  *   what = 1: R_c in FP64, nodes*Lc doubles, node-major

@@ -107,6 +107,8 @@ SIGNATURES = [
     ("msmg_heat_source_load", _I, [_VP, _D, _VP, _VP]),
     ("msmg_stream_ceiling", _I, [_VP, _VP, _VP, ctypes.c_longlong, ctypes.c_longlong, _I, ctypes.POINTER(_D), _VP]),
     ("msmg_time_apply", _I, [_VP, _VP, _I, ctypes.POINTER(_D), _VP]),
+    ("msmg_dot", _I, [_VP, _VP, _VP, ctypes.c_longlong, _VP, _VP]),
+    ("msmg_scale", _I, [_VP, ctypes.c_longlong, _D, _VP, _VP, _VP]),
     ("msmg_prolong_nodal", _I, [_I, _I, _I, _VP, _VP, _VP]),
     ("msmg_prolong_element", _I, [_I, _I, _I, _VP, _VP, _I, _VP]),
     ("msmg_density_filter", _I, [_I, _I, _I, _D, _VP, _VP, _I, _VP]),

@@ -12,6 +12,8 @@ f0 (1 - rho^p) of eq. (material), fixed values T_D, and the mean temperature
 c = (1/|Omega|) int T of eq. (cost function).  Its backward solves the adjoint
 A_FF u_F = w_F (w: the mean weights) and adds the df/drho term:
     dc/drho_e = u^T (df/drho_e - dA/drho_e T).
+The objective values and the chain-rule scalings by the upstream gradient run
+in the library too (msmg_dot, msmg_scale); this module only wires the calls.
 """
 from __future__ import annotations
 
@@ -54,7 +56,7 @@ class _Compliance(torch.autograd.Function):
         ctx.solver, ctx.version = solver, solver.version
         ctx.save_for_backward(T)
         solver.last_info = info
-        return torch.dot(f.detach(), T)
+        return solver.dot(f.detach().contiguous(), T)
 
     @staticmethod
     def backward(ctx, gc):
@@ -63,8 +65,8 @@ class _Compliance(torch.autograd.Function):
             raise RuntimeError("the solver was set up again before backward; the adjoint needs the forward set-up")
         (T,) = ctx.saved_tensors
         # zero fixed values: the adjoint of c = f^T T is u = T
-        g_rho = solver.sensitivity(T) * gc if ctx.needs_input_grad[0] else None
-        g_f = 2.0 * T * gc if ctx.needs_input_grad[1] else None  # c = f^T A^-1 f
+        g_rho = solver.scale(solver.sensitivity(T), 1.0, gc) if ctx.needs_input_grad[0] else None
+        g_f = solver.scale(T, 2.0, gc) if ctx.needs_input_grad[1] else None  # c = f^T A^-1 f
         return g_rho, g_f, None, None, None, None, None, None, None
 
 
@@ -80,7 +82,7 @@ class _MeanTemperature(torch.autograd.Function):
         ctx.solver, ctx.version, ctx.f0, ctx.rtol, ctx.maxit = solver, solver.version, f0, rtol, maxit
         ctx.save_for_backward(T, w)
         solver.last_info = info
-        return torch.dot(w, T)
+        return solver.dot(w, T)
 
     @staticmethod
     def backward(ctx, gc):
@@ -92,7 +94,7 @@ class _MeanTemperature(torch.autograd.Function):
         if info.code != 0:
             raise RuntimeError(f"adjoint solve did not converge: {dict(info)}")
         solver.last_adjoint_info = info
-        g_rho = solver.sensitivity_heat_source(T, u, ctx.f0) * gc
+        g_rho = solver.scale(solver.sensitivity_heat_source(T, u, ctx.f0), 1.0, gc)
         return g_rho, None, None, None, None, None, None, None, None, None
 
 

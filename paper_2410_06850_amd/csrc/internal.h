@@ -118,6 +118,12 @@ void launch_oc_update_scratch(long long ne, const double* x, const double* dc, c
                               double move, double eta, double xmin, double* xnew, double* lam_out, void* scratch_ptr,
                               int passes, hipStream_t s);
 
+// objective values and chain-rule scalings: *out = a^T b (fixed order, the
+// handle's reduction scratch), y = c * (*sdev) * x (sdev may be null: y = c x)
+void launch_dot(const double* a, const double* b, long long n, double* out, double* partials, unsigned* counter,
+                int max_blocks, hipStream_t s);
+void launch_scale(const double* x, long long n, double c, const double* sdev, double* y, hipStream_t s);
+
 // fine level
 long long march_resident_blocks();  // marching workgroups the device runs at once
 long long apply_resident_blocks();  // the same for the LDS-queue apply

@@ -1516,6 +1516,21 @@ extern "C" int msmg_oc_update(msmg_handle* h, const double* x, const double* dc,
   return MSMG_OK;
 }
 
+extern "C" int msmg_dot(msmg_handle* h, const double* a, const double* b, long long n, double* out, hipStream_t s) {
+  if (!h || !a || !b || !out) return fail(MSMG_EINVAL, "NULL argument");
+  if (n < 0 || n > h->g.nn) return fail(MSMG_EINVAL, "need 0 <= n <= the handle's unknowns");
+  launch_dot(a, b, n, out, h->vs[0].partials, h->vs[0].counter, h->red_blocks, s);
+  HIP_TRY(hipGetLastError());
+  return MSMG_OK;
+}
+
+extern "C" int msmg_scale(const double* x, long long n, double c, const double* s_dev, double* y, hipStream_t s) {
+  if (!x || !y || n < 0) return fail(MSMG_EINVAL, "bad arguments");
+  launch_scale(x, n, c, s_dev, y, s);
+  HIP_TRY(hipGetLastError());
+  return MSMG_OK;
+}
+
 extern "C" int msmg_mma_update(msmg_handle* h, int iter, const double* x, const double* xold1, const double* xold2,
                                double* low, double* upp, const double* df0, const double* dv, double volume_fraction,
                                double move, double x_min, double* x_new, double* lambda, hipStream_t s) {

@@ -144,6 +144,36 @@ void launch_oc_update(long long ne, const double* x, const double* dc, const dou
 }
 
 // ---------------------------------------------------------------------------
+// Objective values and chain-rule scalings of the optimisation loop: a^T b in
+// a fixed order (the compliance f^T T, the mean temperature w^T T), and
+// y = c s x with s a device scalar (an upstream gradient).
+
+__global__ void k_dot(const double* __restrict__ a, const double* __restrict__ b, long long n, double* out,
+                      double* partials, unsigned* counter) {
+  __shared__ double red[16];
+  double s[1] = {0.0};
+  for (long long m = blockIdx.x * (long long)blockDim.x + threadIdx.x; m < n; m += (long long)gridDim.x * blockDim.x)
+    s[0] += a[m] * b[m];
+  grid_reduce<1>(s, red, partials, counter, gridDim.x, blockIdx.x, [&](double* t) { *out = t[0]; });
+}
+
+__global__ void k_scale(const double* __restrict__ x, long long n, double c, const double* __restrict__ sdev,
+                        double* __restrict__ y) {
+  const double f = sdev ? c * sdev[0] : c;
+  for (long long m = blockIdx.x * (long long)blockDim.x + threadIdx.x; m < n; m += (long long)gridDim.x * blockDim.x)
+    y[m] = f * x[m];
+}
+
+void launch_dot(const double* a, const double* b, long long n, double* out, double* partials, unsigned* counter,
+                int max_blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot, dim3(grid1d(n, 256, max_blocks)), dim3(256), 0, s, a, b, n, out, partials, counter);
+}
+
+void launch_scale(const double* x, long long n, double c, const double* sdev, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale, dim3(grid1d(n, 256, 8192)), dim3(256), 0, s, x, n, c, sdev, y);
+}
+
+// ---------------------------------------------------------------------------
 // Method of moving asymptotes (Svanberg 1987; the parameter conventions of his
 // 2007 note on MMA and GCMMA), the optimiser of the paper's section 2.3, for the
 // one linear volume constraint f1(x) = dv . x / N - vf <= 0 on

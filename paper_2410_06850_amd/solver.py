@@ -208,6 +208,26 @@ class Solver:
         L.check(L.lib().msmg_apply(self._h, _ptr(x), _ptr(y), _stream()), "msmg_apply")
         return y
 
+    def dot(self, a, b):
+        """a^T b as a 0-d device tensor (fixed summation order, msmg_dot)."""
+        if a.numel() != b.numel():
+            raise ValueError("a and b must have the same length")
+        _need(a, "a", torch.float64, a.numel(), self.device)
+        _need(b, "b", torch.float64, a.numel(), self.device)
+        out = torch.empty((), dtype=torch.float64, device=self.device)
+        L.check(L.lib().msmg_dot(self._h, _ptr(a), _ptr(b), a.numel(), _ptr(out), _stream()), "msmg_dot")
+        return out
+
+    def scale(self, x, c=1.0, s=None, out=None):
+        """c * s * x with s a 0-d device tensor (or None), msmg_scale."""
+        _need(x, "x", torch.float64, x.numel(), self.device)
+        if s is not None:
+            s = _need(s.reshape(()).to(torch.float64).contiguous(), "s", torch.float64, 1, self.device)
+        out = torch.empty_like(x) if out is None else _need(out, "out", torch.float64, x.numel(), self.device)
+        L.check(L.lib().msmg_scale(_ptr(x), x.numel(), float(c), _ptr(s) if s is not None else None, _ptr(out),
+                                   _stream()), "msmg_scale")
+        return out
+
     def time_apply(self, x, reps=50):
         """Mean time (ms) of the PCG's operator-apply kernel over reps back-to-back launches on p = x."""
         x = _need(x, "x", torch.float64, self.nnodes, self.device)

@@ -173,3 +173,23 @@ def test_time_apply_leaves_the_solver_usable(msmg, tpfa):
     assert e.value.code == L.MSMG_EINVAL
     T1, i1 = s.solve(f, rtol=1e-10)
     assert i1.iterations == i0.iterations and torch.equal(T0, T1)
+
+
+def test_dot_and_scale(msmg):
+    """msmg_dot against an exact (fsum) dot product, reproducible bit for bit;
+    msmg_scale is c * s * x with s read on the device."""
+    import math
+    print("case dot/scale", flush=True)
+    n = 16
+    s = msmg.Solver(n, H=8, sd=2)
+    rng = np.random.default_rng(3)
+    a, b = rng.standard_normal((2, s.nnodes))
+    da, db = to_dev(a), to_dev(b)
+    d1, d2 = s.dot(da, db), s.dot(da, db)
+    exact = math.fsum(a * b)
+    assert abs(float(d1) - exact) <= 1e-13 * math.fsum(np.abs(a * b))
+    assert torch.equal(d1, d2)
+    g = torch.tensor(0.75, dtype=torch.float64, device=dev())
+    y = s.scale(da, 2.0, g).cpu().numpy()
+    assert np.array_equal(y, (2.0 * 0.75) * a)
+    assert np.array_equal(s.scale(da, 3.0).cpu().numpy(), 3.0 * a)

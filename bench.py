@@ -289,6 +289,43 @@ def run_workload(name, args):
             s.close()
             del s
             torch.cuda.empty_cache()
+    elif name == "cube512_tpfa_paper_contrasts":
+        # the same setting on the paper's own discretisation (cell-centred
+        # TPFA, FP64): 512^3 cells, contrast 10^cr for cr = 1..6, T_D = 100 on
+        # the bottom-patch faces, source f0 (1 - rho^p), LS1 and LS2 to rtol
+        # 1e-6 with one set-up, hierarchies (sd, L_c, L_cc) = (8, 4, 17) and
+        # (6, 4, 17) with H = 8 (the paper's best columns)
+        n = 512
+        rho = torch.tensor(synth.grf_rho(n, 32, seed=0).ravel(), device=dev)
+        flags = torch.tensor(synth.dirichlet_patch_faces(n, n, n).ravel(), device=dev)
+        td = torch.full((n ** 3,), 100.0, dtype=torch.float64, device=dev)
+        for sd in (8, 6):
+            s = pkg.Solver(n, discretisation="tpfa", sd=sd, tune_cache=tune)
+            s.setup(rho, 1e-1, 1.0, 3, flags, td)  # launch-shape tuning, not timed
+            for cr in range(1, 7):
+                kmin = 10.0 ** (-cr)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                s.setup(rho, kmin, 1.0, 3, flags, td)
+                f = s.heat_source_load(1.0)
+                w = s.mean_temperature_weights()
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                T, i1 = s.solve(f, rtol=1e-6, maxit=4000)
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                u, i2 = s.solve_adjoint(w, rtol=1e-6, maxit=4000)
+                torch.cuda.synchronize()
+                t3 = time.perf_counter()
+                rec = dict(tag=f"tpfa_sd{sd}", n=n, cr=cr, sd=sd, Lc=4, Lcc=17, setup_s=t1 - t0, ls1_s=t2 - t1,
+                           ls1_iterations=i1.iterations, ls2_s=t3 - t2, ls2_iterations=i2.iterations,
+                           codes=[i1.code, i2.code], ls1_rel_res=i1.rel_res, ls2_rel_res=i2.rel_res, cells=n ** 3)
+                _log(json.dumps(rec))
+                out["runs"].append(rec)
+                del T, u
+            s.close()
+            del s
+            torch.cuda.empty_cache()
     elif name == "cube512_topopt":
         n = 512
         s = pkg.Solver(n, tune_cache=tune, eig_warm_start=1, **lean)
@@ -528,6 +565,7 @@ def main():
     ap.add_argument("--workload", default=None,
                     help="run a companion workload instead of the benchmark: cube128_grf8_c1e6, "
                          "cube256_grf16_paper_pair, cube128_to_512_continuation, cube512_paper_contrasts, "
+                         "cube512_tpfa_paper_contrasts, "
                          "cube256_grf16_contrast_sweep, cube512_topopt, cube512_grf32_warmstart, "
                          "cube1024_grf32_c1e6")
     ap.add_argument("--iterations", type=int, default=20, help="optimisation iterations (cube512_topopt)")

@@ -213,6 +213,45 @@ def default_options(**kw):
     return msmg.Options(**o)
 
 
+def sensitivity(grid, rho, t, lam, kmin, kmax, p, dface, td=None, f0=0.0):
+    """dc/drho_K = lam^T (db/drho_K - dA/drho_K t) for A(rho) t = b(rho) and an
+    objective c with adjoint A lam = dc/dt (section 2.3), on TPFA:
+
+      * internal face F = (K, L): T_F = w_d 2 k_K k_L / (k_K + k_L), so
+        dT_F/dk_K = w_d 2 k_L^2 / (k_K + k_L)^2 and the face adds
+        -dT_F/dk_K (lam_K - lam_L)(t_K - t_L);
+      * Dirichlet face of K: 2 w_d k_K on the diagonal and in the right-hand
+        side (times T_D), adding 2 w_d lam_K (T_D - t_K);
+      * both times dk/drho = p rho^(p-1) (k_max - k_min);
+      * the heat source f0 (1 - rho^p) |K| adds lam_K (-f0 p rho^(p-1)) |K|.
+    td: per-cell Dirichlet values (None = 0)."""
+    rho = np.asarray(rho, dtype=np.float64).ravel()
+    t = np.asarray(t, dtype=np.float64).ravel()
+    lam = np.asarray(lam, dtype=np.float64).ravel()
+    k = q1.conductivity(rho, kmin, kmax, p)
+    g = np.zeros(grid.nelem)
+    for axis in range(3):
+        K, L = internal_faces(grid, axis)
+        w = face_weight(grid, axis)
+        s2 = (k[K] + k[L]) ** 2
+        prod = (lam[K] - lam[L]) * (t[K] - t[L])
+        np.add.at(g, K, -w * 2.0 * k[L] ** 2 / s2 * prod)
+        np.add.at(g, L, -w * 2.0 * k[K] ** 2 / s2 * prod)
+    dface = check_face_flags(grid, dface)
+    tdv = np.zeros(grid.nelem) if td is None else np.broadcast_to(np.asarray(td, dtype=np.float64),
+                                                                 (grid.nelem,)).copy()
+    for axis, side, bit in FACE_BITS:
+        on = ((dface >> bit) & 1).astype(np.float64)
+        g += on * 2.0 * face_weight(grid, axis) * lam * (tdv - t)
+    rp1 = np.ones_like(rho)
+    for _ in range(int(p) - 1):
+        rp1 = rp1 * rho
+    g *= p * rp1 * (kmax - kmin)
+    if f0:
+        g += lam * (-f0 * p * rp1) * grid.vol
+    return g
+
+
 def cell_runs(n_cells, H):
     """Cell runs along one axis: [(start, end_exclusive)] over cells 0..n_cells-1."""
     nc = n_cells // H

@@ -246,3 +246,34 @@ def test_smoother_interval_and_positive_preconditioner():
 def tpfa_source(rho, f0=1.0, p=3):
     """eq. (material) heat source f0 (1 - x^p) per cell."""
     return f0 * (1.0 - np.asarray(rho) ** p)
+
+
+@pytest.mark.parametrize("f0", [0.0, 1.0])
+def test_sensitivity_matches_finite_differences(f0):
+    """dc/drho of c = w^T t with A(rho) t = b(rho) (heat source f0 (1 - rho^3),
+    T_D on the patch faces) against central differences of direct solves."""
+    shape = (5, 6, 7)
+    g = q1.Grid(7, 6, 5, lx=1.0, ly=0.8, lz=1.2)
+    rho = synth.uniform_noise_rho(7, 3, base=0.5, amp=0.3, shape=shape).ravel()
+    flags = synth.dirichlet_patch_faces(7, 6, 5, frac=(1, 2)).ravel().astype(np.uint8)
+    flags[g.element_index(6, 2, 3)] |= np.uint8(2)   # and one +x face
+    kmin, kmax, p, td = 1e-2, 1.0, 3, 100.0
+    wgt = np.random.default_rng(1).uniform(0.5, 1.5, g.nelem)
+    src = np.random.default_rng(2).uniform(0.5, 1.5, g.nelem)
+
+    def objective(r):
+        k = q1.conductivity(r, kmin, kmax, p)
+        f = tpfa.cell_load(g, src + f0 * (1.0 - r ** 3))
+        t = tpfa.solve_direct(g, k, flags, f, td)
+        return wgt @ t, t, k
+
+    c0, t, k = objective(rho)
+    lam = tpfa.solve_direct(g, k, flags, wgt, None)
+    grad = tpfa.sensitivity(g, rho, t, lam, kmin, kmax, p, flags, td, f0)
+    eps = 1e-4   # central differences: O(eps^2) truncation, far above the rounding of c ~ 1e4
+    for K in (0, g.element_index(3, 3, 0), g.element_index(6, 2, 3), g.element_index(2, 4, 4), g.nelem - 1):
+        rp, rm = rho.copy(), rho.copy()
+        rp[K] += eps
+        rm[K] -= eps
+        fd = (objective(rp)[0] - objective(rm)[0]) / (2 * eps)
+        assert abs(fd - grad[K]) <= 1e-6 * max(abs(fd), 1e-3 * abs(c0)), (K, fd, grad[K])

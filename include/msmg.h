@@ -232,16 +232,18 @@ int msmg_solve_pair(msmg_handle* h, const double* f, double* T, double* T_lo, co
                     double* lambda_lo, double rtol, int maxit, msmg_info* info_T, msmg_info* info_lambda,
                     hipStream_t stream);
 
-/* (Q1 only: MSMG_EINVAL for a TPFA handle.)
- * Element sensitivities dc/drho_e = -p rho_e^(p-1) (k_max - k_min) lambda_e^T K0 T_e
+/* Element sensitivities dc/drho_e = -p rho_e^(p-1) (k_max - k_min) lambda_e^T K0 T_e
  * (evaluated as -sum_{a<b} K0_ab (lambda_a - lambda_b)(T_a - T_b), exact for zero-row-sum K0)
  * (section 2.3 with a design-independent load).  lambda: nodal adjoint with zero
  * fixed entries, or NULL for the compliance case lambda = T (free entries of T;
- * valid for zero fixed values).  dc: element FP64 output. */
+ * valid for zero fixed values).  dc: element FP64 output.
+ * TPFA: per cell, dc/drho_K = lambda^T (db/drho_K - dA/drho_K T) with the
+ * harmonic faces' dT_F/dk_K = w_d 2 k_L^2 / (k_K + k_L)^2 and the Dirichlet
+ * faces' 2 w_d k_K (diagonal and T_D lift, T_D from the set-up), times
+ * dk/drho. */
 int msmg_sensitivity(msmg_handle* h, const double* T, const double* lambda, double* dc, hipStream_t stream);
 
-/* (Q1 only: MSMG_EINVAL for a TPFA handle.)
- * Element sensitivities of an objective with the design-dependent heat source of
+/* Element sensitivities of an objective with the design-dependent heat source of
  * section 2.1 eq. (material), f_e = f0 (1 - rho_e^p) (section 2.3):
  *   dc/drho_e = lambda^T (df/drho_e - dA/drho_e T)
  *             = -p rho_e^(p-1) [ (k_max - k_min) lambda_e^T K0 T_e + f0 (V/8) sum_{a in e} lambda_a ],
@@ -249,7 +251,8 @@ int msmg_sensitivity(msmg_handle* h, const double* T, const double* lambda, doub
  * fixed values; lambda: nodal FP64 adjoint with zero fixed entries (required, the
  * source term makes the problem non-self-adjoint); dc: element FP64 output.  f0 = 0
  * gives msmg_sensitivity's value.  MSMG_EINVAL for NULL pointers or a non-finite
- * f0, MSMG_ESTATE before the first msmg_setup. */
+ * f0, MSMG_ESTATE before the first msmg_setup.  TPFA: msmg_sensitivity's cell
+ * value plus lambda_K (-f0 p rho_K^(p-1)) |K|. */
 int msmg_sensitivity_heat_source(msmg_handle* h, const double* T, const double* lambda, double f0, double* dc,
                                  hipStream_t stream);
 

@@ -208,6 +208,10 @@ void launch_tpfa_flags(const Ctx& c, const uint8_t* in, uint8_t* out, unsigned l
 void launch_tpfa_cell_load(const Ctx& c, const double* src, double sconst, double* f, hipStream_t s);
 void launch_tpfa_heat_source_load(const Ctx& c, double f0, double* f, hipStream_t s);
 int launch_tpfa_galerkin(const Ctx& c, const void* R, int b_dt, int drop_cc, double* out, hipStream_t s);
+// design sensitivities: lam null = the compliance (lam = T), td null = zero
+// Dirichlet values, source: the heat source's term with f0
+void launch_tpfa_sensitivity(const Ctx& c, const double* T, const double* lam, const double* td, double f0,
+                             bool source, double* dc, hipStream_t s);
 
 // coarse levels (V-cycle)
 void launch_gs_sweep(const Ctx& c, const void* b, void* x, bool forward, hipStream_t s);

@@ -974,10 +974,10 @@ extern "C" int msmg_apply(msmg_handle* h, const double* x, double* y, hipStream_
 
 extern "C" int msmg_sensitivity(msmg_handle* h, const double* T, const double* lam, double* dc, hipStream_t s) {
   if (!h || !T || !dc) return fail(MSMG_EINVAL, "NULL argument");
-  if (h->tpfa) return fail(MSMG_EINVAL, "sensitivities are provided for the Q1 discretisation only");
   if (!h->setup_done) return fail(MSMG_ESTATE, "msmg_setup has not completed");
   Ctx c = make_ctx(h);
-  launch_sensitivity(c, T, lam, dc, s);
+  if (h->tpfa) launch_tpfa_sensitivity(c, T, lam, h->has_tfix ? h->tfix : nullptr, 0.0, false, dc, s);
+  else launch_sensitivity(c, T, lam, dc, s);
   HIP_TRY(hipGetLastError());
   return MSMG_OK;
 }
@@ -986,10 +986,10 @@ extern "C" int msmg_sensitivity_heat_source(msmg_handle* h, const double* T, con
                                             hipStream_t s) {
   if (!h || !T || !lam || !dc) return fail(MSMG_EINVAL, "NULL argument");
   if (!std::isfinite(f0)) return fail(MSMG_EINVAL, "f0 must be finite");
-  if (h->tpfa) return fail(MSMG_EINVAL, "sensitivities are provided for the Q1 discretisation only");
   if (!h->setup_done) return fail(MSMG_ESTATE, "msmg_setup has not completed");
   Ctx c = make_ctx(h);
-  launch_sensitivity_heat_source(c, T, lam, f0, dc, s);
+  if (h->tpfa) launch_tpfa_sensitivity(c, T, lam, h->has_tfix ? h->tfix : nullptr, f0, true, dc, s);
+  else launch_sensitivity_heat_source(c, T, lam, f0, dc, s);
   HIP_TRY(hipGetLastError());
   return MSMG_OK;
 }

@@ -369,6 +369,52 @@ __global__ void k_tpfa_heat_source_load(long long n, const RT* __restrict__ rho,
   }
 }
 
+// Design sensitivities (section 2.3) on the TPFA operator:
+//   dc/drho_K = lam^T (db/drho_K - dA/drho_K t)
+// with, per internal face F = (K, L), dT_F/dk_K = w_d 2 k_L^2 / (k_K + k_L)^2
+// times -(lam_K - lam_L)(t_K - t_L), per Dirichlet face 2 w_d lam_K (T_D - t_K),
+// all times dk/drho = p rho^(p-1) (k_max - k_min); SOURCE adds the heat
+// source's lam_K (-f0 p rho^(p-1)) |K|.  lam null: lam = t (the compliance
+// with zero Dirichlet values); td null: T_D = 0.
+template <typename RT, bool SOURCE>
+__global__ void k_tpfa_sensitivity(TGeo t, const RT* __restrict__ rho, Material mat, const double* __restrict__ T,
+                                   const double* __restrict__ lam, const uint8_t* __restrict__ df,
+                                   const double* __restrict__ td, double f0, double vol, double* __restrict__ dc) {
+  const double dk = mat.kmax - mat.kmin;
+  const long long sy = t.nx, sz = (long long)t.nx * t.ny;
+  for (long long m = blockIdx.x * (long long)blockDim.x + threadIdx.x; m < t.n; m += (long long)gridDim.x * blockDim.x) {
+    const int i = int(m % t.nx), j = int((m / t.nx) % t.ny), z = int(m / sz);
+    const double r = double(rho[m]);
+    const double kc = conductivity<double>(r, mat.kmin, dk, mat.p);
+    const double tc = T[m], lc = lam ? lam[m] : tc;
+    const bool in[6] = {i > 0, i + 1 < t.nx, j > 0, j + 1 < t.ny, z > 0, z + 1 < t.nz};
+    const long long st[6] = {-1, 1, -sy, sy, -sz, sz};
+    double g = 0.0;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      if (!in[f]) continue;
+      const long long q = m + st[f];
+      const double kn = conductivity<double>(double(rho[q]), mat.kmin, dk, mat.p);
+      const double s = kc + kn;
+      const double dT = t.w[f / 2] * (2.0 * kn * kn / (s * s));
+      const double ln = lam ? lam[q] : T[q];
+      g -= dT * ((lc - ln) * (tc - T[q]));
+    }
+    const unsigned fl = df[m];
+    if (fl) {
+      const double tdv = td ? td[m] : 0.0;
+#pragma unroll
+      for (int f = 0; f < 6; ++f)
+        if ((fl >> f) & 1u) g += 2.0 * t.w[f / 2] * lc * (tdv - tc);
+    }
+    double rp1 = 1.0;
+    for (int q = 1; q < mat.p; ++q) rp1 *= r;
+    g *= double(mat.p) * rp1 * dk;
+    if (SOURCE) g += lc * (-f0 * double(mat.p) * rp1) * vol;
+    dc[m] = g;
+  }
+}
+
 // rc = R_c v: one workgroup per coarse cell sums its cells in a fixed order
 template <int L>
 __global__ __launch_bounds__(256) void k_tpfa_restrict(TGeo t, Hier h, const double* __restrict__ v,
@@ -647,6 +693,16 @@ void launch_tpfa_heat_source_load(const Ctx& c, double f0, double* f, hipStream_
   else
     hipLaunchKernelGGL((k_tpfa_heat_source_load<float>), gr, bl, 0, s, c.g.ne, (const float*)c.rho, c.mat.p, f0,
                        c.g.vol, f);
+}
+
+void launch_tpfa_sensitivity(const Ctx& c, const double* T, const double* lam, const double* td, double f0,
+                             bool source, double* dc, hipStream_t s) {
+  const TGeo t = tgeo(c);
+  const dim3 gr(grid1d(t.n, 256, 8192)), bl(256);
+#define TS(RT, SRC) hipLaunchKernelGGL((k_tpfa_sensitivity<RT, SRC>), gr, bl, 0, s, t, (const RT*)c.rho, c.mat, T, lam, c.dface, td, f0, c.g.vol, dc)
+  if (c.rho_dt == DT_F64) { if (source) TS(double, true); else TS(double, false); }
+  else { if (source) TS(float, true); else TS(float, false); }
+#undef TS
 }
 
 int launch_tpfa_galerkin(const Ctx& c, const void* R, int b_dt, int drop_cc, double* out, hipStream_t s) {

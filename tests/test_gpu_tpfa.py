@@ -263,9 +263,69 @@ def test_tpfa_argument_checks(pkg):
     with pytest.raises(RuntimeError):
         s.setup(rho, 1e-3, KMAX, P, to_dev(np.zeros(512, dtype=np.uint8), torch.uint8))
     s.setup(rho, 1e-3, KMAX, P, to_dev(_flags(shape), torch.uint8))
-    with pytest.raises(RuntimeError):
-        s.sensitivity(torch.zeros(512, dtype=torch.float64, device="cuda"))
     s.close()
     o = L.default_options(discretisation=L.MSMG_TPFA, H=4, sd=2)  # Q1 smoothing interval: rejected
     hnd = ctypes.c_void_p()
     assert L.lib().msmg_create(ctypes.byref(hnd), 8, 8, 8, 1.0, 1.0, 1.0, ctypes.byref(o)) == L.MSMG_EINVAL
+
+
+@pytest.mark.parametrize("rho_dt", ["f64", "f32"])
+def test_sensitivities_match_oracle(pkg, rho_dt):
+    """msmg_sensitivity (given adjoint, and lam = T) and the heat-source form on
+    TPFA against the oracle's formula, on a non-cubic box with Dirichlet values."""
+    print(f"case tpfa-sensitivity {rho_dt}", flush=True)
+    shape = (9, 12, 20)
+    nz, ny, nx = shape
+    g = q1.Grid(nx, ny, nz, lx=2.0, ly=0.5, lz=0.3)
+    rho = synth.grf_rho(nx, 3, seed=4, shape=shape).ravel()
+    if rho_dt == "f32":
+        rho = rho.astype(np.float32).astype(np.float64)
+    flags = _flags(shape).astype(np.uint8)
+    ex, ey, ez = g.element_coords()
+    flags[ex == nx - 1] |= np.uint8(1 << 1)
+    td = np.random.default_rng(5).uniform(50, 150, g.nelem)
+    kmin = 1e-4
+    s = pkg.Solver(nx, ny, nz, lx=2.0, ly=0.5, lz=0.3, discretisation="tpfa", H=4, sd=2)
+    rdev = to_dev(rho, torch.float32 if rho_dt == "f32" else torch.float64)
+    s.setup(rdev, kmin, KMAX, P, to_dev(flags, torch.uint8), to_dev(td))
+    rng = np.random.default_rng(6)
+    T = 100 + rng.standard_normal(g.nelem)
+    lam = rng.standard_normal(g.nelem)
+    for lam_in, f0 in ((lam, 0.0), (None, 0.0), (lam, 1.0)):
+        if f0:
+            got = s.sensitivity_heat_source(to_dev(T), to_dev(lam_in), f0).cpu().numpy()
+        else:
+            got = s.sensitivity(to_dev(T), to_dev(lam_in) if lam_in is not None else None).cpu().numpy()
+        want = tpfa.sensitivity(g, rho, T, T if lam_in is None else lam_in, kmin, KMAX, P, flags, td, f0)
+        err = np.abs(got - want).max() / np.abs(want).max()
+        print(f"  f0={f0} lam={'T' if lam_in is None else 'given'}: {err:.2e}")
+        assert err <= 1e-12
+    s.close()
+
+
+def test_mean_temperature_gradient_matches_oracle(pkg):
+    """The paper's objective on TPFA through autograd (state solve, adjoint
+    solve, sensitivity with the source term) against the oracle's gradient."""
+    print("case tpfa-mean-temperature autograd 16^3", flush=True)
+    from paper_2410_06850_amd import autograd
+    n = 16
+    g = q1.Grid(n)
+    rho_np = synth.grf_rho(n, 4, seed=8).ravel()
+    flags = _flags((n, n, n))
+    kmin = 1e-3
+    s = pkg.Solver(n, discretisation="tpfa", H=8, sd=2)
+    rho = to_dev(rho_np).requires_grad_(True)
+    td = to_dev(np.full(g.nelem, 100.0))
+    c = autograd.mean_temperature(rho, s, kmin, KMAX, P, to_dev(flags, torch.uint8), td, f0=1.0, rtol=1e-12)
+    c.backward()
+    k = q1.conductivity(rho_np, kmin, KMAX, P)
+    f = tpfa.cell_load(g, 1.0 - rho_np ** 3)
+    t = tpfa.solve_direct(g, k, flags, f, 100.0)
+    w = np.full(g.nelem, g.vol / 1.0)
+    lam = tpfa.solve_direct(g, k, flags, w, None)
+    want = tpfa.sensitivity(g, rho_np, t, lam, kmin, KMAX, P, flags, 100.0, 1.0)
+    got = rho.grad.cpu().numpy()
+    err = np.abs(got - want).max() / np.abs(want).max()
+    print(f"  c={float(c):.6f} oracle={w @ t:.6f} grad err {err:.2e}")
+    assert abs(float(c) - w @ t) <= 1e-9 * abs(w @ t)
+    assert err <= 1e-8

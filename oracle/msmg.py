@@ -58,6 +58,11 @@ class Options:
     cheb_degree: int = 2  # level-0 Chebyshev degree (number of smoothing steps)
     cheb_lo: float = 0.15
     cheb_hi: float = 1.5
+    # adaptive local basis (section 3 allows a count l_c^i per coarse cell):
+    # when > 0, cell i keeps its eigenpairs with lambda <= lc_threshold *
+    # lambda_ref (at least one, at most Lc), lambda_ref = (pi / (H h_max))^2
+    # the first Neumann eigenvalue of a homogeneous cube of the cell's size
+    lc_threshold: float = 0.0
 
 
 def axis_runs(n_elems, H):
@@ -207,9 +212,14 @@ class Hierarchy:
         self.cell_basis = []     # (node ids, Phi) per cell when keep_local
         self.cell_mass = []
         r = 0
+        theta = o.lc_threshold * self.lambda_ref() if o.lc_threshold > 0 else None
         for (cx, cy, cz) in self.cells:
             K, m, nodes = self.local_problem(cx, cy, cz)
             nl = min(o.Lc, len(nodes))
+            if theta is not None and nl > 1:
+                # the count of eigenvalues at or below the threshold (at least one)
+                lam_all = sla.eigh(K, np.diag(m), eigvals_only=True, subset_by_index=[0, nl - 1], driver="gvx")
+                nl = max(1, int(np.count_nonzero(lam_all <= theta)))
             ids = list(range(r, r + nl))
             self.cell_rows.append(np.array(ids, dtype=np.int64))
             if nl == 0:
@@ -237,6 +247,13 @@ class Hierarchy:
         self.Rc = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                                 shape=(self.n_c, self.n_unknowns)).tocsr()
         self.level1_operators()
+
+    def lambda_ref(self):
+        """(pi / (H h_max))^2: the first nonzero Neumann eigenvalue of a
+        homogeneous cube with the coarse cell's nominal side, the scale of the
+        adaptive threshold."""
+        hmax = max(self.g.hx, self.g.hy, self.g.hz)
+        return (np.pi / (self.o.H * hmax)) ** 2
 
     def level1_operators(self):
         """A_c = R_c A R_c^T, its diagonal-block inverses and the colour classes."""

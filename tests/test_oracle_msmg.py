@@ -288,3 +288,37 @@ def test_extended_iterate_beats_binary64_floor():
     T, res, h = msmg.solve(g, rho, f, mask, 1e-6, 1.0, 3, msmg.Options(H=4, sd=2), rtol=1e-10, maxit=300)
     assert res.status == "converged"
     assert q1.relative_residual_diff(A, T, f, mask, T_lo=res.x_lo) <= 1e-10 * (1 + 1e-3)
+
+
+@pytest.mark.parametrize("thr", [1.0, 2.5])
+def test_adaptive_local_counts_match_brute_force(thr):
+    """With lc_threshold each cell keeps its eigenpairs at or below
+    thr * (pi / (H h))^2 (at least one, at most Lc): checked against the full
+    dense spectrum of every local problem; the cycle stays SPD and PCG
+    reaches the direct solution."""
+    n = 16
+    rho = synth.grf_rho(n, 3, seed=4).ravel()
+    g, h = _setup(n, 4, 2, Lc=6, rho=rho, kmin=1e-6)
+    mask = synth.dirichlet_patch_mask(n, n, n).ravel()
+    ha = msmg.Hierarchy(g, rho, 1e-6, 1.0, 3, mask, msmg.Options(H=4, sd=2, Lc=6, lc_threshold=thr))
+    theta = thr * (np.pi / (4 * g.hx)) ** 2
+    counts = []
+    for ci, (cx, cy, cz) in enumerate(ha.cells):
+        K, m, _ = ha.local_problem(cx, cy, cz)
+        lam = sla.eigh(K, np.diag(m), eigvals_only=True)
+        want = min(6, max(1, int(np.count_nonzero(lam <= theta))))
+        assert len(ha.cell_rows[ci]) == want, (ci, lam[:8], theta)
+        assert np.allclose(ha.cell_evals[ci], h.cell_evals[ci][:want], rtol=1e-10, atol=1e-10 * lam[-1])
+        counts.append(want)
+    assert min(counts) < max(counts)  # the field makes the counts differ between cells
+    assert ha.n_c == sum(counts) < h.n_c
+    x, y = np.random.default_rng(0).standard_normal((2, g.nnodes))
+    x[ha.mask] = 0
+    y[ha.mask] = 0
+    mx, my = ha.precondition(x), ha.precondition(y)
+    assert abs(mx @ y - x @ my) <= 1e-11 * abs(mx @ y)
+    assert mx @ x > 0
+    f = q1.element_load(g, 1.0)
+    T, res, _ = msmg.solve(g, rho, f, mask, 1e-6, 1.0, 3, hier=ha, rtol=1e-10)
+    Td = q1.solve_direct(q1.assemble(g, ha.k), f, mask)
+    assert res.status == "converged" and np.linalg.norm(T - Td) / np.linalg.norm(Td) <= 1e-6

@@ -277,3 +277,27 @@ def test_sensitivity_matches_finite_differences(f0):
         rm[K] -= eps
         fd = (objective(rp)[0] - objective(rm)[0]) / (2 * eps)
         assert abs(fd - grad[K]) <= 1e-6 * max(abs(fd), 1e-3 * abs(c0)), (K, fd, grad[K])
+
+
+def test_adaptive_local_counts_match_brute_force():
+    """The adaptive count l_c^i on TPFA cells: eigenvalues at or below
+    thr * (pi / (H h))^2 of the full local spectrum, at least one, at most Lc."""
+    n = 16
+    rho = synth.grf_rho(n, 3, seed=4).ravel()
+    g = q1.Grid(n)
+    flags = synth.dirichlet_patch_faces(n, n, n).ravel()
+    thr = 1.5
+    h = tpfa.Hierarchy(g, rho, 1e-6, 1.0, 3, flags, tpfa.default_options(H=4, sd=2, Lc=6, lc_threshold=thr))
+    theta = thr * (np.pi / (4 * g.hx)) ** 2
+    counts = []
+    for ci, (cx, cy, cz) in enumerate(h.cells):
+        K, m, _ = h.local_problem(cx, cy, cz)
+        lam = sla.eigh(K, np.diag(m), eigvals_only=True)
+        want = min(6, max(1, int(np.count_nonzero(lam <= theta))))
+        assert len(h.cell_rows[ci]) == want
+        counts.append(want)
+    assert min(counts) < max(counts) and h.n_c == sum(counts)
+    f = tpfa.cell_load(g, 1.0 - rho ** 3)
+    t, res, _ = tpfa.solve(g, rho, f, flags, 1e-6, 1.0, 3, hier=h, rtol=1e-10, td=100.0)
+    td = tpfa.solve_direct(g, h.k, flags, f, 100.0)
+    assert res.status == "converged" and np.linalg.norm(t - td) / np.linalg.norm(td) <= 1e-6

@@ -326,6 +326,44 @@ def run_workload(name, args):
             s.close()
             del s
             torch.cuda.empty_cache()
+    elif name == "cube256_adaptive_basis":
+        # the adaptive local basis size (options.lc_threshold) against fixed
+        # L_c on the benchmark's field, Q1 (mixed path) and TPFA (FP64,
+        # T_D = 0, source f0 (1 - rho^3)): effective coarse dimension,
+        # iterations to 1e-8, set-up and solve time
+        n = 256
+        rho = torch.tensor(synth.grf_rho(n, 16, seed=0).ravel(), device=dev)
+        for disc in ("q1", "tpfa"):
+            if disc == "q1":
+                mask = torch.tensor(synth.dirichlet_patch_mask(n, n, n).ravel(), device=dev)
+                base = dict(mixed)
+            else:
+                mask = torch.tensor(synth.dirichlet_patch_faces(n, n, n).ravel(), device=dev)
+                base = dict(discretisation="tpfa")
+            for cfg in (dict(Lc=4), dict(Lc=7, lc_threshold=0.5), dict(Lc=7, lc_threshold=1.0),
+                        dict(Lc=7, lc_threshold=2.0), dict(Lc=7)):
+                s = pkg.Solver(n, tune_cache=tune, **base, **cfg)
+                s.setup(rho, KMIN, 1.0, 3, mask)  # launch-shape tuning, not timed
+                f = s.element_load(const=1.0) if disc == "q1" else s.heat_source_load(1.0)
+                for rep in range(2):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    s.setup(rho, KMIN, 1.0, 3, mask)
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    T, info = s.solve(f, rtol=RTOL, maxit=2000)
+                    torch.cuda.synchronize()
+                    t2 = time.perf_counter()
+                st = s.export(5, s.plan().ncells, torch.int32).numpy()
+                cnt = (st >> 20) & 0xFF
+                rec = dict(disc=disc, cfg=cfg, n_c_effective=int(cnt.sum()), basis_sizes=np.bincount(cnt).tolist(),
+                           setup_ms=1e3 * (t1 - t0), solve_ms=1e3 * (t2 - t1), iterations=info.iterations,
+                           rel_res=info.rel_res, code=info.code)
+                _log(json.dumps(rec))
+                out["runs"].append(rec)
+                s.close()
+                del s, T
+                torch.cuda.empty_cache()
     elif name == "cube512_topopt":
         n = 512
         s = pkg.Solver(n, tune_cache=tune, eig_warm_start=1, **lean)
@@ -565,7 +603,7 @@ def main():
     ap.add_argument("--workload", default=None,
                     help="run a companion workload instead of the benchmark: cube128_grf8_c1e6, "
                          "cube256_grf16_paper_pair, cube128_to_512_continuation, cube512_paper_contrasts, "
-                         "cube512_tpfa_paper_contrasts, "
+                         "cube512_tpfa_paper_contrasts, cube256_adaptive_basis, "
                          "cube256_grf16_contrast_sweep, cube512_topopt, cube512_grf32_warmstart, "
                          "cube1024_grf32_c1e6")
     ap.add_argument("--iterations", type=int, default=20, help="optimisation iterations (cube512_topopt)")

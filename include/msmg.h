@@ -130,6 +130,12 @@ typedef struct msmg_options {
                           cell; coarse cells group H^3 cells (remainders join
                           the last); the coarse-level fusions of coarse_fused
                           bits 1 and 2 do not apply.                            */
+  double lc_threshold; /* > 0: adaptive local basis size l_c^i per coarse cell  [0]
+                          (section 3 allows one per cell): cell i keeps its
+                          eigenpairs of eq. spepb with lambda <= lc_threshold *
+                          (pi / (H h_max))^2, at least one and at most Lc (Lc
+                          is then the maximum; Lc <= 7).  The coarse levels
+                          keep Lc slots per cell, unused ones decoupled.       */
 } msmg_options;
 
 /* Solve report. */

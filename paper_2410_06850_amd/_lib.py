@@ -52,6 +52,7 @@ class Options(ctypes.Structure):
         ("coarse_fused", ctypes.c_int),
         ("pair_rhs", ctypes.c_int),
         ("discretisation", ctypes.c_int),
+        ("lc_threshold", ctypes.c_double),
     ]
 
 

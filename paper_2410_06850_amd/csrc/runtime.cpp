@@ -194,6 +194,18 @@ static int make_plan(int nx, int ny, int nz, const msmg_options& o, Plan& P, int
   if (h.Lcc > maxd) h.Lcc = maxd;
   P.n_cc = h.ncc * h.Lcc;
   if (P.n_cc > 72000) return fail(MSMG_EINVAL, "coarse-coarse dimension too large for the dense level-2 solve");
+  if (o.lc_threshold > 0.0) {
+    // an adaptive basis keeps at least one vector per coarse cell, so every
+    // coarse-coarse cell must hold as many coarse cells as its subspace block
+    // has vectors, or that block would be rank deficient
+    int m = o.cc_block ? o.cc_block : std::min(32, h.Lcc + 15);
+    if (m < h.Lcc + 1) m = std::min(32, h.Lcc + 1);
+    const long long least = (long long)std::min(h.ncx, o.sd) * std::min(h.ncy, o.sd) * std::min(h.ncz, o.sd);
+    if (least < m)
+      return fail(MSMG_EINVAL, "an adaptive basis (lc_threshold > 0) needs at least " + std::to_string(m) +
+                                   " coarse cells per coarse-coarse cell (sd >= 4 for L_cc = 17)");
+    if (o.Lc > 7) return fail(MSMG_EINVAL, "an adaptive basis takes Lc <= 7");
+  }
   return MSMG_OK;
 }
 
@@ -378,6 +390,7 @@ extern "C" void msmg_default_options(msmg_options* o) {
   o->coarse_fused = 7;
   o->pair_rhs = 0;
   o->discretisation = MSMG_Q1;
+  o->lc_threshold = 0.0;
 }
 
 extern "C" const char* msmg_last_error(void) { return g_last_error.c_str(); }
@@ -406,6 +419,7 @@ static int check_options(const msmg_options& o) {
   if (o.lean_memory && o.eig_warm_start)
     return fail(MSMG_EINVAL, "lean_memory keeps no basis between set-ups: eig_warm_start is not available");
   if (o.discretisation != MSMG_Q1 && o.discretisation != MSMG_TPFA) return fail(MSMG_EINVAL, "bad discretisation");
+  if (!(o.lc_threshold >= 0.0) || !std::isfinite(o.lc_threshold)) return fail(MSMG_EINVAL, "lc_threshold must be >= 0");
   if (o.discretisation == MSMG_TPFA) {
     if (o.vcycle_dtype != MSMG_F64 || o.rho_v_dtype != MSMG_F64 || o.basis_dtype != MSMG_F64)
       return fail(MSMG_EINVAL, "the TPFA discretisation runs FP64 cycle vectors, density copy and basis");

@@ -47,6 +47,7 @@ struct LocalArgs {
   int maxit;
   double tol;
   int nl_max;   // LDS capacity in nodes (the largest cell of the class)
+  double lc_thr;  // > 0: keep the eigenpairs with lambda <= lc_thr (at least one)
   int warm;     // start from the basis in Rc64 (previous set-up)
   const int* cells;  // the class's cells: cells[0 .. ncells)
   int ncells;   // cells to solve
@@ -539,6 +540,17 @@ void k_local_eigen(LocalArgs A) {
       if (L < M && ev[L] - ev[L - 1] < 1e-8 * b_hi) tie = true;
     }
 
+    // adaptive basis size: the pairs at or below the threshold, at least one
+    // (ev holds the computed pairs in ascending order)
+    int Lk = L;
+    if (A.lc_thr > 0.0 && L > 1) {
+      int cnt = 0;
+      for (int j = 0; j < L; ++j) cnt += ev[j] <= A.lc_thr ? 1 : 0;
+      Lk = max(1, cnt);
+      const int nev = nfree <= DENSE_MAX ? nfree : M;
+      tie = Lk < nev && ev[Lk] - ev[Lk - 1] < 1e-8 * b_hi;
+    }
+
     // ---- normalise the sign and write R_c (Phi = M^-1/2 w) and eigenvalues
     double sdot[M];
 #pragma unroll
@@ -552,7 +564,7 @@ void k_local_eigen(LocalArgs A) {
     block_allsum_vec<M>(sdot, red);
     double sgn[M];
     for (int j = 0; j < M; ++j) {
-      if (j >= L) {
+      if (j >= Lk) {
         sgn[j] = 0.0;
         continue;
       }
@@ -574,12 +586,12 @@ void k_local_eigen(LocalArgs A) {
     for (int ln = tid; ln < nloc; ln += BS) {
       const int lx = ln % nlx, ly = (ln / nlx) % nly, lz = ln / (nlx * nly);
       const long long gn = node_id(g, x0 + lx, y0 + ly, z0 + lz);
-      for (int l = 0; l < Lc; ++l) A.Rc64[gn * Lc + l] = (l < L) ? sgn[l] * X[l * NL + ln] * isq[ln] : 0.0;
+      for (int l = 0; l < Lc; ++l) A.Rc64[gn * Lc + l] = (l < Lk) ? sgn[l] * X[l * NL + ln] * isq[ln] : 0.0;
     }
     if (tid == 0) {
-      for (int l = 0; l < Lc; ++l) A.evals[(long long)cell * Lc + l] = (l < L) ? ev[l] : 0.0;
+      for (int l = 0; l < Lc; ++l) A.evals[(long long)cell * Lc + l] = (l < Lk) ? ev[l] : 0.0;
       // bits 0-19 outer iterations, 20-27 basis size, 28 not converged, 29 cutoff tie
-      A.status[cell] = status | (L << 20) | (tie ? (1 << 29) : 0);
+      A.status[cell] = status | (Lk << 20) | (tie ? (1 << 29) : 0);
     }
     __syncthreads();
   }
@@ -616,6 +628,11 @@ int launch_local_eigen(const Ctx& c, const SetupArgs& sa, SetupScratch* sc, int 
   a.tol = sa.opt->eig_tol;
   a.nl_max = nl;
   a.warm = sa.warm;
+  {
+    const double hmax = std::max(c.g.hx, std::max(c.g.hy, c.g.hz));
+    const double lref = (M_PI / (c.h.H * hmax)) * (M_PI / (c.h.H * hmax));
+    a.lc_thr = sa.opt->lc_threshold > 0.0 ? sa.opt->lc_threshold * lref : 0.0;
+  }
   if (first < 0 || count < 0 || first + count > c.h.ncells || nl < 1 || nl > sa.max_cell_nodes) return MSMG_EINVAL;
   a.cells = sc->cells + first;
   a.ncells = count;

@@ -377,23 +377,31 @@ def run_workload(name, args):
         out["config"] = dict(n=n, iterations=args.iterations, volume_fraction=0.3, radius=1.5, move=0.2, eta=0.5,
                              k_min=1e-6, precision=f"mixed, {args.copies} copies", eig_warm_start=1,
                              update=args.optimizer.upper())
-    elif name == "cube128_to_512_continuation":
+    elif name in ("cube128_to_512_continuation", "cube128_to_512_tpfa_continuation"):
         # the interpolation technique at the design level (section 4): the
         # paper's mean-temperature problem (source f0 (1 - rho^p), T_D = 100,
         # contrast 1e6, volume fraction 0.05) optimised 40 / 20 / 10 iterations
         # on 128^3 / 256^3 / 512^3, each level started from the injected
         # design of the previous one; then 10 iterations directly on 512^3
         # from the uniform design for comparison (design update: --optimizer,
-        # the paper's MMA by default)
+        # the paper's MMA by default); the _tpfa_ variant on the paper's
+        # cell-centred discretisation (FP64)
         vf = 0.05
+        use_tpfa = "tpfa" in name
 
         def make_mask(n):
+            if use_tpfa:
+                return torch.tensor(synth.dirichlet_patch_faces(n, n, n).ravel(), device=dev)
             return torch.tensor(synth.dirichlet_patch_mask(n, n, n).ravel(), device=dev)
 
         def make_solver(n):
+            if use_tpfa:
+                return pkg.Solver(n, discretisation="tpfa", tune_cache=tune, eig_warm_start=1)
             return pkg.Solver(n, tune_cache=tune, eig_warm_start=1, **lean)
 
         def make_fixed(n):
+            if use_tpfa:
+                return torch.full((n ** 3,), 100.0, dtype=torch.float64, device=dev)
             return torch.where(make_mask(n) != 0, 100.0, 0.0).to(torch.float64)
 
         def summary(lv):
@@ -416,7 +424,9 @@ def run_workload(name, args):
         out["runs"] = [dict(kind="continuation", total_s=total_cont, levels=levels),
                        dict(kind="direct512", **direct)]
         out["config"] = dict(schedule=[40, 20, 10], volume_fraction=vf, k_min=1e-6, T_D=100.0, f0=1.0, radius=1.5,
-                             move=0.2, eta=0.5, update=args.optimizer.upper(), precision=f"mixed, {args.copies} copies")
+                             move=0.2, eta=0.5, update=args.optimizer.upper(),
+                             discretisation="TPFA" if use_tpfa else "Q1",
+                             precision="FP64" if use_tpfa else f"mixed, {args.copies} copies")
     elif name == "cube512_grf32_warmstart":
         # the interpolation step: solve the 256^3 companion (2^3 block average of
         # the same unthresholded field, thresholded at its own 60th percentile),
@@ -603,7 +613,7 @@ def main():
     ap.add_argument("--workload", default=None,
                     help="run a companion workload instead of the benchmark: cube128_grf8_c1e6, "
                          "cube256_grf16_paper_pair, cube128_to_512_continuation, cube512_paper_contrasts, "
-                         "cube512_tpfa_paper_contrasts, cube256_adaptive_basis, "
+                         "cube512_tpfa_paper_contrasts, cube256_adaptive_basis, cube128_to_512_tpfa_continuation, "
                          "cube256_grf16_contrast_sweep, cube512_topopt, cube512_grf32_warmstart, "
                          "cube1024_grf32_c1e6")
     ap.add_argument("--iterations", type=int, default=20, help="optimisation iterations (cube512_topopt)")

@@ -790,24 +790,6 @@ __global__ void k_restrict_finish(Geo g, Hier h, RestrictGeo rg, const double* _
   rc[cell * L + l] = sum;
 }
 
-// PCG scalars after a preconditioner application: tt = (z^T r, z^T q).
-MSMG_DEV void vc_finish(Scalars* sc, const double* tt, int mode) {
-  sc->zr = tt[0];
-  sc->zq = tt[1];
-  if (!(tt[0] > 0.0)) {
-    sc->status = (tt[0] == tt[0]) ? ST_BREAKDOWN : ST_NONFINITE;
-    sc->done = 1;
-    return;
-  }
-  if (mode == 0) {
-    sc->beta = 0.0;
-  } else {
-    // beta = z^T (r_new - r_old) / rz_old with r_old = r_new + alpha q
-    sc->beta = -sc->alpha * tt[1] / sc->rz;
-  }
-  sc->rz = tt[0];
-}
-
 // z = a + b (V-cycle type) written as FP64, with the PCG products z^T r and
 // z^T q; fin computes beta (Polak-Ribiere) and the new r^T z.
 //   mode 0: initial (beta = 0); mode 1: iteration; mode 2: no reduction.

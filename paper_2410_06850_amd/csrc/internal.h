@@ -87,6 +87,24 @@ struct Ctx {
   const uint8_t* dface;
 };
 
+// PCG scalars after a preconditioner application: tt = (z^T r, z^T q).
+MSMG_DEV inline void vc_finish(Scalars* sc, const double* tt, int mode) {
+  sc->zr = tt[0];
+  sc->zq = tt[1];
+  if (!(tt[0] > 0.0)) {
+    sc->status = (tt[0] == tt[0]) ? ST_BREAKDOWN : ST_NONFINITE;
+    sc->done = 1;
+    return;
+  }
+  if (mode == 0) {
+    sc->beta = 0.0;
+  } else {
+    // beta = z^T (r_new - r_old) / rz_old with r_old = r_new + alpha q
+    sc->beta = -sc->alpha * tt[1] / sc->rz;
+  }
+  sc->rz = tt[0];
+}
+
 // Slots of the handle's 16-word counter block (zero between kernels unless
 // noted): the ticket of grid_reduce, the fixed-node count of a set-up (left
 // holding the count).
@@ -199,6 +217,9 @@ void launch_tpfa_residual(const Ctx& c, const double* b, const double* x, const 
                           hipStream_t s);
 void launch_tpfa_vresidual(const Ctx& c, const double* r, const double* x, double* out, hipStream_t s);
 void launch_tpfa_smooth(const Ctx& c, const double* in, double* out, hipStream_t s);
+// degree-2 post-smoother fused with the output z = base + S^-1 res (PCG reduction `mode`)
+void launch_tpfa_smooth_output(const Ctx& c, const double* res, const double* base, double* z, const double* r,
+                               const double* q, int mode, hipStream_t s);
 void launch_tpfa_restrict(const Ctx& c, const double* v, double* rc, hipStream_t s);
 void launch_tpfa_prolong(const Ctx& c, const double* base, const double* e1, const double* e2, double* out,
                          hipStream_t s);

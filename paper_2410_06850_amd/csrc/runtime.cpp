@@ -885,6 +885,10 @@ static void precondition_tpfa(msmg_handle* h, const Ctx& c, VecSet& V, const dou
   coarse_correction(h, c, V, s, &e1, &e2);                  // e_c
   launch_tpfa_prolong(c, r1, e1, e2, (double*)V.v_r2, s);  // r2 = r1 + R_c^T e_c
   launch_tpfa_vresidual(c, r, (const double*)V.v_r2, res, s);  // r0 - A r2
+  if (c.cheb.degree == 2) {
+    launch_tpfa_smooth_output(c, res, (const double*)V.v_r2, z, r, q, mode, s);  // y = r2 + S^-T (...)
+    return;
+  }
   launch_tpfa_smooth(c, res, r1, s);                           // S^-T (...)
   launch_vc_output(c, V.v_r2, true, r1, z, r, q, mode, s);     // y = r2 + ...
 }

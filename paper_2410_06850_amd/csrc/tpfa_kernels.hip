@@ -287,6 +287,36 @@ __global__ __launch_bounds__(TX* TY) void k_tpfa_cheb_step(TGeo t, const double*
   });
 }
 
+// The post-smoother fused with the cycle's output: the two Chebyshev steps of
+// k_tpfa_cheb2 applied to `res`, then z = base + s with the PCG products
+// z^T r (MODE 0, 1) and z^T q (MODE 1) reduced as the separate output kernel
+// does (MODE 2: none).  s stays in registers; z is the value the separate
+// smoother and output kernels compute.
+template <int MODE>
+__global__ __launch_bounds__(TX* TY) void k_tpfa_cheb2_out(TGeo t, const double* __restrict__ k,
+                                                          const uint8_t* __restrict__ df,
+                                                          const double* __restrict__ res,
+                                                          const double* __restrict__ dinv, double inv_theta,
+                                                          double c0, double c1, const double* __restrict__ base,
+                                                          double* __restrict__ z, const double* __restrict__ r,
+                                                          const double* __restrict__ q, Scalars* sc, double* partials,
+                                                          unsigned* counter) {
+  if (sc->done) return;
+  __shared__ double red[32];
+  double s[2] = {0.0, 0.0};
+  const ColumnTile c = column_tile(t);
+  tpfa_march(t, c, k, df, [&](long long m) { return res[m] * dinv[m] * inv_theta; },
+             [&](long long n, double, double x1, double acc) {
+               const double v = c0 * x1 + c1 * (dinv[n] * (res[n] - acc));
+               const double zn = base[n] + v;
+               z[n] = zn;
+               if (MODE != 2) s[0] += zn * r[n];
+               if (MODE == 1) s[1] += zn * q[n];
+             });
+  if (MODE == 2) return;
+  grid_reduce<2>(s, red, partials, counter, gridDim.x, blockIdx.x, [&](double* tt) { vc_finish(sc, tt, MODE); });
+}
+
 // Jacobi diagonal inverse: 1 / (sum of the face transmissibilities + the Dirichlet part)
 __global__ __launch_bounds__(TX* TY) void k_tpfa_diag_inv(TGeo t, const double* __restrict__ k,
                                                          const uint8_t* __restrict__ df, double* __restrict__ dinv) {
@@ -650,6 +680,14 @@ void launch_tpfa_smooth(const Ctx& c, const double* in, double* out, hipStream_t
     xa = xb;
     xb = tmp;
   }
+}
+
+void launch_tpfa_smooth_output(const Ctx& c, const double* res, const double* base, double* z, const double* r,
+                               const double* q, int mode, hipStream_t s) {
+  const TGeo t = tgeo(c);
+#define SO(MD) hipLaunchKernelGGL((k_tpfa_cheb2_out<MD>), dim3(tgrid(t)), dim3(TX, TY), 0, s, t, c.kc, c.dface, res, (const double*)c.dinv, c.cheb.inv_theta, c.cheb.c0, c.cheb.c1, base, z, r, q, c.sc, c.partials, c.counter)
+  if (mode == 0) SO(0); else if (mode == 1) SO(1); else SO(2);
+#undef SO
 }
 
 void launch_tpfa_restrict(const Ctx& c, const double* v, double* rc, hipStream_t s) {

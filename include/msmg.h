@@ -128,8 +128,9 @@ typedef struct msmg_options {
                           TPFA matrix reaches close to 2; [0.2, 2] suits it).
                           Vectors ("nodal" below) then hold one value per
                           cell; coarse cells group H^3 cells (remainders join
-                          the last); the coarse-level fusions of coarse_fused
-                          bits 1 and 2 do not apply.                            */
+                          the last); coarse_fused bit 1 fuses the restriction
+                          into the first residual when H is 4, 8 or 16 and
+                          divides every axis; bit 2 does not apply.             */
   double lc_threshold; /* > 0: adaptive local basis size l_c^i per coarse cell  [0]
                           (section 3 allows one per cell): cell i keeps its
                           eigenpairs of eq. spepb with lambda <= lc_threshold *

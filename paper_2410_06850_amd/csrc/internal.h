@@ -221,6 +221,13 @@ void launch_tpfa_smooth(const Ctx& c, const double* in, double* out, hipStream_t
 void launch_tpfa_smooth_output(const Ctx& c, const double* res, const double* base, double* z, const double* r,
                                const double* q, int mode, hipStream_t s);
 void launch_tpfa_restrict(const Ctx& c, const double* v, double* rc, hipStream_t s);
+// rc = R_c (r - A x) without storing the residual: per-(coarse cell, row)
+// partials in part (tpfa_restrict_slots(c) * Lc doubles), then a fixed-order
+// sum; only when tpfa_restrict_fusable(c) (H in {4, 8, 16} dividing every axis)
+bool tpfa_restrict_fusable(const Ctx& c);
+long long tpfa_restrict_slots(const Ctx& c);
+void launch_tpfa_vresidual_restrict(const Ctx& c, const double* r, const double* x, double* part, double* rc,
+                                    hipStream_t s);
 void launch_tpfa_prolong(const Ctx& c, const double* base, const double* e1, const double* e2, double* out,
                          hipStream_t s);
 void launch_tpfa_diag_inv(const Ctx& c, double* dinv, hipStream_t s);

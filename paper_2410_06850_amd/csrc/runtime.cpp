@@ -518,6 +518,10 @@ static int alloc_arrays(msmg_handle* h, bool dry, size_t* total) {
       h->rg = make_restrict_geo(h->g, h->hier, h->march_resident);
       A(&h->vs[0].rpart, (size_t)h->rg.slots * h->hier.Lc * 8);
     }
+    if ((o.coarse_fused & 2) && h->tpfa) {
+      const Ctx c0 = make_ctx(h);
+      if (tpfa_restrict_fusable(c0)) A(&h->vs[0].rpart, (size_t)tpfa_restrict_slots(c0) * h->hier.Lc * 8);
+    }
     if (o.pair_rhs) {
       // the second side of a batched pair: its own PCG and cycle vectors
       VecSet& V = h->vs[1];
@@ -879,8 +883,12 @@ static void precondition_tpfa(msmg_handle* h, const Ctx& c, VecSet& V, const dou
     launch_vc_output(c, r1, true, nullptr, z, r, q, mode, s);
     return;
   }
-  launch_tpfa_vresidual(c, r, r1, res, s);           // r0 - A r1
-  launch_tpfa_restrict(c, res, (double*)V.c_rc, s);  // rc = R_c (r0 - A r1)
+  if (V.rpart) {
+    launch_tpfa_vresidual_restrict(c, r, r1, V.rpart, (double*)V.c_rc, s);  // rc = R_c (r0 - A r1)
+  } else {
+    launch_tpfa_vresidual(c, r, r1, res, s);           // r0 - A r1
+    launch_tpfa_restrict(c, res, (double*)V.c_rc, s);  // rc = R_c (r0 - A r1)
+  }
   const double *e1 = nullptr, *e2 = nullptr;
   coarse_correction(h, c, V, s, &e1, &e2);                  // e_c
   launch_tpfa_prolong(c, r1, e1, e2, (double*)V.v_r2, s);  // r2 = r1 + R_c^T e_c

@@ -74,7 +74,8 @@ MSMG_DEV double dir_w(const TGeo& t, unsigned f, double kc) {
 
 struct ColumnTile {
   int i, j, z0, z1;
-  bool active;
+  bool active;  // the thread's column lies in the mesh (and the tile is real)
+  bool tile;    // the workgroup's tile is real (not grid padding)
 };
 
 MSMG_DEV ColumnTile column_tile(const TGeo& t) {
@@ -86,7 +87,8 @@ MSMG_DEV ColumnTile column_tile(const TGeo& t) {
   c.j = ty * TY + int(threadIdx.y);
   c.z0 = int(tz) * t.zc;
   c.z1 = min(c.z0 + t.zc, t.nz);
-  c.active = tile < t.tiles && c.i < t.nx && c.j < t.ny;
+  c.tile = tile < t.tiles;
+  c.active = c.tile && c.i < t.nx && c.j < t.ny;
   return c;
 }
 
@@ -97,12 +99,16 @@ MSMG_DEV ColumnTile column_tile(const TGeo& t) {
 // next z step (its four in-plane neighbours, its flags and the cell two
 // planes up) are issued before the current step's arithmetic, so that two
 // steps' loads are in flight per thread.
-template <typename VF, typename Body>
+// ALL: every thread of a real tile marches (columns outside the mesh on the
+// clamped last column or row) and body gets the column's `active` flag as a
+// fifth argument, so that wave-wide steps inside body see every lane.
+template <bool ALL = false, typename VF, typename Body>
 MSMG_DEV void tpfa_march(const TGeo& t, const ColumnTile& c, const double* __restrict__ k,
                          const uint8_t* __restrict__ df, VF V, Body body) {
-  if (!c.active) return;
+  if (ALL ? !c.tile : !c.active) return;
   const long long sx = 1, sy = t.nx, sz = (long long)t.nx * t.ny;
-  const bool xm = c.i > 0, xp = c.i + 1 < t.nx, ym = c.j > 0, yp = c.j + 1 < t.ny;
+  const int ci = min(c.i, t.nx - 1), cj = min(c.j, t.ny - 1);
+  const bool xm = ci > 0, xp = ci + 1 < t.nx, ym = cj > 0, yp = cj + 1 < t.ny;
   const long long oxm = xm ? -sx : 0, oxp = xp ? sx : 0, oym = ym ? -sy : 0, oyp = yp ? sy : 0;
   struct Ring {
     double kxm, kxp, kym, kyp, vxm, vxp, vym, vyp;
@@ -121,7 +127,7 @@ MSMG_DEV void tpfa_march(const TGeo& t, const ColumnTile& c, const double* __res
     r.f = df[m];
     return r;
   };
-  long long n = (long long)c.j * sy + c.i + (long long)c.z0 * sz;
+  long long n = (long long)cj * sy + ci + (long long)c.z0 * sz;
   double kc = k[n], vc = V(n);
   double km = kc, vm = vc, kp = kc, vp = vc;
   if (c.z0 > 0) {
@@ -150,7 +156,8 @@ MSMG_DEV void tpfa_march(const TGeo& t, const ColumnTile& c, const double* __res
     acc += face_T(t.w[1], kc, cur.kyp) * (vc - cur.vyp);
     acc += face_T(t.w[2], kc, km) * (vc - vm);
     acc += face_T(t.w[2], kc, kp) * (vc - vp);
-    body(n, kc, vc, acc);
+    if constexpr (ALL) body(n, kc, vc, acc, c.active);
+    else body(n, kc, vc, acc);
     km = kc;
     vm = vc;
     kc = kp;
@@ -239,6 +246,67 @@ __global__ __launch_bounds__(TX* TY) void k_tpfa_vresidual(TGeo t, const double*
   const ColumnTile c = column_tile(t);
   tpfa_march(t, c, k, df, [&](long long m) { return x[m]; },
              [&](long long n, double, double, double acc) { out[n] = r[n] - acc; });
+}
+
+// The cycle's first residual fused with the restriction: rc = R_c (r - A x)
+// without storing the residual.  Needs H | nx, ny, nz, H dividing the 64-lane
+// x-row of a wave, and z chunks of whole coarse cells (tgeo_restrict).  Each
+// thread sums R_c(n) (r - A x)_n over its column within a coarse cell; at
+// the cell's last plane the H lanes of each coarse x-cell add their sums
+// (xor shuffles) and the first writes one partial per (coarse cell, row j):
+// part[((cz ny + j) ncx + cx) L + l].  k_tpfa_restrict_finish adds the H rows.
+template <int L, int HH>
+__global__ __launch_bounds__(TX* TY) void k_tpfa_vresidual_restrict(TGeo t, Hier h, const double* __restrict__ k,
+                                                                   const uint8_t* __restrict__ df,
+                                                                   const double* __restrict__ r,
+                                                                   const double* __restrict__ x,
+                                                                   const double* __restrict__ R,
+                                                                   double* __restrict__ part, const Scalars* sc) {
+  static_assert(TX == 64 && 64 % HH == 0, "a wave's x-row holds whole coarse cells");
+  if (sc && sc->done) return;
+  const ColumnTile c = column_tile(t);
+  const long long sz = (long long)t.nx * t.ny;
+  double a[L];
+#pragma unroll
+  for (int l = 0; l < L; ++l) a[l] = 0.0;
+  tpfa_march<true>(t, c, k, df, [&](long long m) { return x[m]; },
+                   [&](long long n, double, double, double acc, bool act) {
+                     const int z = int(n / sz);
+                     if (act) {
+                       const double v = r[n] - acc;
+#pragma unroll
+                       for (int l = 0; l < L; ++l) a[l] += R[n * L + l] * v;
+                     }
+                     if ((z + 1) % HH == 0 || z + 1 == c.z1) {
+#pragma unroll
+                       for (int l = 0; l < L; ++l) {
+                         double sum = a[l];
+#pragma unroll
+                         for (int off = 1; off < HH; off <<= 1) sum += __shfl_xor(sum, off, 64);
+                         a[l] = sum;
+                       }
+                       if (act && c.i % HH == 0) {
+                         const long long o = (((long long)(z / HH) * t.ny + c.j) * h.ncx + c.i / HH) * L;
+#pragma unroll
+                         for (int l = 0; l < L; ++l) part[o + l] = a[l];
+                       }
+#pragma unroll
+                       for (int l = 0; l < L; ++l) a[l] = 0.0;
+                     }
+                   });
+}
+
+template <int L>
+__global__ void k_tpfa_restrict_finish(TGeo t, Hier h, const double* __restrict__ part, double* __restrict__ rc,
+                                       const Scalars* sc) {
+  if (sc && sc->done) return;
+  const long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (q >= (long long)h.ncells * L) return;
+  const int cell = int(q / L), l = int(q % L);
+  const int cx = cell % h.ncx, cy = (cell / h.ncx) % h.ncy, cz = cell / (h.ncx * h.ncy);
+  double s = 0.0;
+  for (int j = cy * h.H; j < (cy + 1) * h.H; ++j) s += part[(((long long)cz * t.ny + j) * h.ncx + cx) * L + l];
+  rc[q] = s;
 }
 
 // Chebyshev-Jacobi smoother on D^-1 A from a zero guess (the three-term
@@ -654,6 +722,29 @@ void launch_tpfa_vresidual(const Ctx& c, const double* r, const double* x, doubl
   const TGeo t = tgeo(c);
   hipLaunchKernelGGL(k_tpfa_vresidual, dim3(tgrid(t)), dim3(TX, TY), 0, s, t, c.kc, c.dface, r, x, out,
                      (const Scalars*)c.sc);
+}
+
+bool tpfa_restrict_fusable(const Ctx& c) {
+  const int H = c.h.H;
+  return (H == 4 || H == 8 || H == 16) && c.g.nx % H == 0 && c.g.ny % H == 0 && c.g.nz % H == 0;
+}
+
+long long tpfa_restrict_slots(const Ctx& c) { return (long long)c.g.nz / c.h.H * c.g.ny * c.h.ncx; }
+
+void launch_tpfa_vresidual_restrict(const Ctx& c, const double* r, const double* x, double* part, double* rc,
+                                    hipStream_t s) {
+  TGeo t = tgeo(c);
+  // z chunks of whole coarse cells
+  const int H = c.h.H;
+  t.zc = ((t.zc + H - 1) / H) * H;
+  t.ntz = (t.nz + t.zc - 1) / t.zc;
+  t.tiles = (long long)t.ntx * t.nty * t.ntz;
+  const long long n = (long long)c.h.ncells * c.h.Lc;
+#define VRR(HH) TL_DISPATCH(c.h.Lc, hipLaunchKernelGGL((k_tpfa_vresidual_restrict<LL, HH>), dim3(tgrid(t)), dim3(TX, TY), 0, s, t, c.h, c.kc, c.dface, r, x, (const double*)c.Rc, part, (const Scalars*)c.sc))
+  if (H == 4) VRR(4); else if (H == 8) VRR(8); else VRR(16);
+#undef VRR
+  TL_DISPATCH(c.h.Lc, hipLaunchKernelGGL((k_tpfa_restrict_finish<LL>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                                         s, t, c.h, (const double*)part, rc, (const Scalars*)c.sc));
 }
 
 void launch_tpfa_smooth(const Ctx& c, const double* in, double* out, hipStream_t s) {

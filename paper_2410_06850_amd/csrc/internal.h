@@ -88,7 +88,7 @@ struct Ctx {
 };
 
 // PCG scalars after a preconditioner application: tt = (z^T r, z^T q).
-MSMG_DEV inline void vc_finish(Scalars* sc, const double* tt, int mode) {
+MSMG_DEV void vc_finish(Scalars* sc, const double* tt, int mode) {
   sc->zr = tt[0];
   sc->zq = tt[1];
   if (!(tt[0] > 0.0)) {

@@ -92,38 +92,55 @@ MSMG_DEV ColumnTile column_tile(const TGeo& t) {
   return c;
 }
 
+// A double from the neighbouring lane of the wave: lane i receives lane i - 1's
+// value (PREV) or lane i + 1's (!PREV), by two DPP whole-wave shifts of the
+// 32-bit halves; the lane at the end of the shift receives 0.
+template <bool PREV>
+MSMG_DEV double wave_shift(double v) {
+  constexpr int ctrl = PREV ? 0x138 : 0x130;  // wave_shr:1, wave_shl:1
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(b), ctrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), ctrl, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
 // Marches the thread's column and calls body(n, kc, vc, acc) with
 // acc = (A v)_n, where v_m = V(m) is any per-cell value (a vector, or a
 // product of vectors formed on the fly).  Absent neighbours take the cell's
-// own k and value, so their terms vanish without a branch.  The loads of the
-// next z step (its four in-plane neighbours, its flags and the cell two
-// planes up) are issued before the current step's arithmetic, so that two
-// steps' loads are in flight per thread.
+// own k and value, so their terms vanish without a branch.  A wave is one
+// 64-cell x-row of the tile: the x-neighbours' k and v are the adjacent
+// lanes' centre values (wave shifts), and only the two end lanes load theirs
+// (one load per quantity, the other lanes re-reading their own cell).  The
+// loads of the next z step (the two y-neighbours, the x-row ends, its flags
+// and the cell two planes up) are issued before the current step's
+// arithmetic, so that two steps' loads are in flight per thread.
 // ALL: every thread of a real tile marches (columns outside the mesh on the
 // clamped last column or row) and body gets the column's `active` flag as a
 // fifth argument, so that wave-wide steps inside body see every lane.
 template <bool ALL = false, typename VF, typename Body>
 MSMG_DEV void tpfa_march(const TGeo& t, const ColumnTile& c, const double* __restrict__ k,
                          const uint8_t* __restrict__ df, VF V, Body body) {
+  static_assert(TX == 64, "a wave is one x-row of the tile");
   if (ALL ? !c.tile : !c.active) return;
   const long long sx = 1, sy = t.nx, sz = (long long)t.nx * t.ny;
   const int ci = min(c.i, t.nx - 1), cj = min(c.j, t.ny - 1);
-  const bool xm = ci > 0, xp = ci + 1 < t.nx, ym = cj > 0, yp = cj + 1 < t.ny;
-  const long long oxm = xm ? -sx : 0, oxp = xp ? sx : 0, oym = ym ? -sy : 0, oyp = yp ? sy : 0;
+  const int lane = int(threadIdx.x);
+  const bool xp = ci + 1 < t.nx, ym = cj > 0, yp = cj + 1 < t.ny;
+  const long long oxm = ci > 0 ? -sx : 0, oxp = xp ? sx : 0, oym = ym ? -sy : 0, oyp = yp ? sy : 0;
+  // the end lanes' x-neighbour (the lane's own cell for the others)
+  const long long oe = lane == 0 ? oxm : (lane == TX - 1 ? oxp : 0);
   struct Ring {
-    double kxm, kxp, kym, kyp, vxm, vxp, vym, vyp;
+    double kym, kyp, vym, vyp, ke, ve;
     unsigned f;
   };
   auto ring = [&](long long m) {
     Ring r;
-    r.kxm = k[m + oxm];
-    r.kxp = k[m + oxp];
     r.kym = k[m + oym];
     r.kyp = k[m + oyp];
-    r.vxm = V(m + oxm);
-    r.vxp = V(m + oxp);
     r.vym = V(m + oym);
     r.vyp = V(m + oyp);
+    r.ke = k[m + oe];
+    r.ve = V(m + oe);
     r.f = df[m];
     return r;
   };
@@ -149,9 +166,14 @@ MSMG_DEV void tpfa_march(const TGeo& t, const ColumnTile& c, const double* __res
         vpp = V(n + 2 * sz);
       }
     }
+    const double kls = wave_shift<true>(kc), vls = wave_shift<true>(vc);
+    const double krs = wave_shift<false>(kc), vrs = wave_shift<false>(vc);
+    const double kxm = lane == 0 ? cur.ke : kls, vxm = lane == 0 ? cur.ve : vls;
+    const double kxp = lane == TX - 1 ? cur.ke : (xp ? krs : kc);
+    const double vxp = lane == TX - 1 ? cur.ve : (xp ? vrs : vc);
     double acc = dir_w(t, cur.f, kc) * vc;
-    acc += face_T(t.w[0], kc, cur.kxm) * (vc - cur.vxm);
-    acc += face_T(t.w[0], kc, cur.kxp) * (vc - cur.vxp);
+    acc += face_T(t.w[0], kc, kxm) * (vc - vxm);
+    acc += face_T(t.w[0], kc, kxp) * (vc - vxp);
     acc += face_T(t.w[1], kc, cur.kym) * (vc - cur.vym);
     acc += face_T(t.w[1], kc, cur.kyp) * (vc - cur.vyp);
     acc += face_T(t.w[2], kc, km) * (vc - vm);

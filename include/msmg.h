@@ -113,7 +113,8 @@ typedef struct msmg_options {
                           set-up holds at once (0 = as many as fit in 24 GB)     */
   int coarse_fused;    /* bit 0: levels 1 and 2 of each cycle in one launch      [7]
                           (one workgroup per compute unit, grid-wide barriers
-                          between the steps); bit 1: the restriction fused into the cycle's
+                          between the steps; taken while n_c <= 262,144, larger
+                          coarse levels run one launch per step); bit 1: the restriction fused into the cycle's
                           first residual (H = 2, 4, 8 or 16); bit 2: the
                           prolongation fused into the residual after the coarse
                           correction.  Cleared bits run one launch per step.

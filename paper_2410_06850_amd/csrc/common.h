@@ -412,13 +412,29 @@ MSMG_DEV void grid_reduce(double (&v)[NV], double* red, double* partials, unsign
   __syncthreads();
   if (!is_last) return;
   const int nthreads = blockDim.x * blockDim.y * blockDim.z;
+  // Each thread sums the partials b = tid, tid + nthreads, ... in that order;
+  // they are fetched RB at a time so that RB loads are in flight (one at a time,
+  // each waited for before the next, left the rest of the device idle for
+  // tens of microseconds behind the last block).
+  constexpr int RB = 16;
   double s[NV];
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
     s[q] = 0.0;
-    for (int b = tid; b < nblocks; b += nthreads)
-      s[q] += __longlong_as_double((long long)__hip_atomic_load(&P[(long long)q * nblocks + b], __ATOMIC_RELAXED,
-                                                                __HIP_MEMORY_SCOPE_AGENT));
+    const unsigned long long* Pq = P + (long long)q * nblocks;
+    for (int b0 = tid; b0 < nblocks; b0 += RB * nthreads) {
+      double t[RB];
+#pragma unroll
+      for (int u = 0; u < RB; ++u) {
+        const int b = b0 + u * nthreads;
+        t[u] = b < nblocks ? __longlong_as_double((long long)__hip_atomic_load(&Pq[b], __ATOMIC_RELAXED,
+                                                                               __HIP_MEMORY_SCOPE_AGENT))
+                           : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < RB; ++u)
+        if (b0 + u * nthreads < nblocks) s[q] += t[u];
+    }
   }
   block_sum<NV>(s, red);
   if (tid == 0) {

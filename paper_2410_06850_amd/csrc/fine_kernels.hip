@@ -116,8 +116,26 @@ __global__ void k_update_r(double* __restrict__ r, const double* __restrict__ q,
   __shared__ double red[16];
   const double a = sc->alpha;
   double s[1] = {0.0};
-#pragma unroll 4
-  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < nn; n += (long long)gridDim.x * blockDim.x) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  // four elements per pass with every load issued before the first store (the
+  // compiler cannot move a load of r[n + stride] above the store to r[n] on
+  // its own); the sum runs over n, n + stride, ... as in the plain loop
+  for (; n + 3 * stride < nn; n += 4 * stride) {
+    double rv[4], qv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      rv[u] = r[n + u * stride];
+      qv[u] = __builtin_nontemporal_load(q + n + u * stride);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double rn = rv[u] - a * qv[u];
+      r[n + u * stride] = rn;
+      s[0] += rn * rn;
+    }
+  }
+  for (; n < nn; n += stride) {
     const double rn = r[n] - a * __builtin_nontemporal_load(q + n);
     r[n] = rn;
     s[0] += rn * rn;

@@ -64,6 +64,10 @@ APPLY_SHAPES = [
     ((9, 12, 20), (2.0, 0.5, 0.3)),
     ((5, 9, 70), (1.0, 1.0, 1.0)),
     ((33, 7, 65), (0.7, 1.3, 2.1)),
+    # x-rows of two and three 64-lane waves: the end lanes' loads across tiles
+    ((4, 5, 127), (1.0, 0.6, 0.4)),
+    ((4, 6, 128), (1.0, 1.0, 1.0)),
+    ((5, 4, 129), (1.5, 1.0, 1.0)),
 ]
 
 

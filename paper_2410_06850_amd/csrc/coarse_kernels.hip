@@ -160,7 +160,23 @@ __global__ void k_cc_restrict(Hier h, const VT* __restrict__ Rcc, const int* __r
   const int d0 = cc_ptr[J], nd = cc_ptr[J + 1] - d0;
   const VT* R = Rcc + (long long)h.Lcc * d0 + (long long)bidx * nd;
   double s = 0.0;
-  for (int d = lane; d < nd; d += 64) s += double(R[d]) * double(t[cc_dofs[d0 + d]]);
+  // eight entries per lane in flight (the index loads, then the values they
+  // address), summed in the order d = lane, lane + 64, ...
+  for (int db = lane; db < nd; db += 8 * 64) {
+    int idx[8];
+    double rv[8], tv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int d = db + 64 * u < nd ? db + 64 * u : 0;
+      idx[u] = cc_dofs[d0 + d];
+      rv[u] = double(R[d]);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) tv[u] = double(t[idx[u]]);
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (db + 64 * u < nd) s += rv[u] * tv[u];
+  }
   s = wave_sum(s);
   if (lane == 0) rcc[w] = s;
 }
@@ -174,7 +190,19 @@ __global__ void k_acc_solve(int n, const double* __restrict__ Ainv, const double
   if (row >= n) return;
   const double* a = Ainv + row * (long long)n;
   double s = 0.0;
-  for (int j = lane; j < n; j += 64) s += a[j] * r[j];
+  // eight entries per lane in flight, summed in the order j = lane, lane + 64, ...
+  for (int jb = lane; jb < n; jb += 8 * 64) {
+    double av[8], rv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = jb + 64 * u < n ? jb + 64 * u : 0;
+      av[u] = a[j];
+      rv[u] = r[j];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (jb + 64 * u < n) s += av[u] * rv[u];
+  }
   s = wave_sum(s);
   if (lane == 0) e[row] = s;
 }
@@ -302,6 +330,34 @@ MSMG_DEV bool l1_barrier(const Level1Args& a, unsigned k, unsigned long long see
   return *ok_sh != 0;
 }
 
+// sum over the lane's neighbour blocks k (ok[k]) of A_{i,bb} x_{nc[k]} for row
+// l of the cell's 27 blocks A (bb = q + ROW_SLOTS k), with every load of A and
+// of x issued before the first product (the coherent loads of x would
+// otherwise go one block at a time); nc[k] of a skipped block is any valid
+// cell, its loads are not used.  Products in the order k, then m.
+template <int L>
+MSMG_DEV double l1_block_products(const double* A, const double* x, int l, int q, const bool (&ok)[SLOT_BLOCKS],
+                                  const long long (&nc)[SLOT_BLOCKS]) {
+  double av[SLOT_BLOCKS][L], xv[SLOT_BLOCKS][L];
+#pragma unroll
+  for (int k = 0; k < SLOT_BLOCKS; ++k) {
+    const int bb = ok[k] ? q + ROW_SLOTS * k : 0;
+#pragma unroll
+    for (int m = 0; m < L; ++m) {
+      av[k][m] = A[(bb * L + l) * L + m];
+      xv[k][m] = coh_load(x + nc[k] * L + m);
+    }
+  }
+  double part = 0.0;
+#pragma unroll
+  for (int k = 0; k < SLOT_BLOCKS; ++k)
+    if (ok[k]) {
+#pragma unroll
+      for (int m = 0; m < L; ++m) part += av[k][m] * xv[k][m];
+    }
+  return part;
+}
+
 // One Gauss-Seidel colour of the grid-synchronised sweep.  forward: x_i =
 // D_i^-1 (b_i - sum_{j of earlier colours} A_ij x_j) (zero start, colour 0
 // first).  !forward: x_i += D_i^-1 (b_i - sum_{all 27 j} A_ij x_j) (in place).
@@ -338,26 +394,23 @@ MSMG_DEV unsigned long long l1_colour(const Level1Args& a, int colour, bool forw
 #pragma unroll
     for (int m = 0; m < L; ++m) dv[m] = row ? a.Dinv[(cell * L + l) * L + m] : 0.0;
     // row_products with coherent loads of x
-    double part = 0.0;
-    {
-      const double* A = a.Ac + cell * 27 * L * L;
+    bool okk[SLOT_BLOCKS];
+    long long ncs[SLOT_BLOCKS];
 #pragma unroll
-      for (int k = 0; k < SLOT_BLOCKS; ++k) {
-        const int bb = q + ROW_SLOTS * k;
-        bool ok = false;
-        long long nc = 0;
-        if (row && bb < 27) nc = nb_cell(h, cx, cy, cz, bb, ok);
-        if (ok && forward) {
-          const int ox = bb % 3 - 1, oy = (bb / 3) % 3 - 1, oz = bb / 9 - 1;
-          const int ncol = ((px + ox) & 1) + 2 * ((py + oy) & 1) + 4 * ((pz + oz) & 1);
-          ok = ncol < colour;
-        }
-        if (ok) {
-#pragma unroll
-          for (int m = 0; m < L; ++m) part += A[(bb * L + l) * L + m] * coh_load(x + nc * L + m);
-        }
+    for (int k = 0; k < SLOT_BLOCKS; ++k) {
+      const int bb = q + ROW_SLOTS * k;
+      bool ok = false;
+      long long nc = 0;
+      if (row && bb < 27) nc = nb_cell(h, cx, cy, cz, bb, ok);
+      if (ok && forward) {
+        const int ox = bb % 3 - 1, oy = (bb / 3) % 3 - 1, oz = bb / 9 - 1;
+        const int ncol = ((px + ox) & 1) + 2 * ((py + oy) & 1) + 4 * ((pz + oz) & 1);
+        ok = ncol < colour;
       }
+      okk[k] = ok;
+      ncs[k] = ok ? nc : cell;
     }
+    double part = l1_block_products<L>(a.Ac + cell * 27 * L * L, x, row ? l : 0, q, okk, ncs);
 #pragma unroll
     for (int off = 1; off < ROW_SLOTS; off <<= 1) part += __shfl_xor(part, off, 64);
     const double tv = row ? bi - part : 0.0;
@@ -411,19 +464,19 @@ __global__ __launch_bounds__(512) void k_level1(Level1Args a) {
         cy = int((cell / h.ncx) % h.ncy);
         cz = int(cell / ((long long)h.ncx * h.ncy));
       }
-      double part = 0.0;
-      const double* A = a.Ac + (row ? cell : 0) * 27 * L * L;
+      const long long cs = row ? cell : 0;
+      bool okk[SLOT_BLOCKS];
+      long long ncs[SLOT_BLOCKS];
 #pragma unroll
       for (int kk = 0; kk < SLOT_BLOCKS; ++kk) {
         const int bb = q + ROW_SLOTS * kk;
         bool okb = false;
         long long nc = 0;
         if (row && bb < 27) nc = nb_cell(h, cx, cy, cz, bb, okb);
-        if (okb) {
-#pragma unroll
-          for (int m = 0; m < L; ++m) part += A[(bb * L + l) * L + m] * coh_load(x + nc * L + m);
-        }
+        okk[kk] = okb;
+        ncs[kk] = okb ? nc : cs;
       }
+      double part = l1_block_products<L>(a.Ac + cs * 27 * L * L, x, row ? l : 0, q, okk, ncs);
 #pragma unroll
       for (int off = 1; off < ROW_SLOTS; off <<= 1) part += __shfl_xor(part, off, 64);
       if (row && q == 0) seen |= coh_store(a.t[side] + cell * L + l, a.rc[side][cell * L + l] - part);
@@ -443,7 +496,23 @@ __global__ __launch_bounds__(512) void k_level1(Level1Args a) {
       const double* R = a.Rcc + (long long)h.Lcc * d0 + (long long)bidx * nd;
       const double* t = a.t[side];
       double sum = 0.0;
-      for (int d = lane; d < nd; d += 64) sum += R[d] * coh_load(t + a.cc_dofs[d0 + d]);
+      // eight entries per lane at a time: the index loads, then the coherent
+      // loads they address, then the products in the order d = lane, lane + 64, ...
+      for (int db = lane; db < nd; db += 8 * 64) {
+        int idx[8];
+        double rv[8], tv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int d = db + 64 * u < nd ? db + 64 * u : 0;
+          idx[u] = a.cc_dofs[d0 + d];
+          rv[u] = R[d];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) tv[u] = coh_load(t + idx[u]);
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (db + 64 * u < nd) sum += rv[u] * tv[u];
+      }
       sum = wave_sum(sum);
       if (lane == 0) seen |= coh_store(a.rcc[side] + we, sum);
     }
@@ -460,10 +529,22 @@ __global__ __launch_bounds__(512) void k_level1(Level1Args a) {
         double sum[NS];
 #pragma unroll
         for (int q = 0; q < NS; ++q) sum[q] = 0.0;
-        for (int j = lane; j < a.n_cc; j += 64) {
-          const double av = arow[j];
+        // eight entries per lane at a time, summed in the order j = lane, lane + 64, ...
+        for (int jb = lane; jb < a.n_cc; jb += 8 * 64) {
+          double av[8], rv[NS][8];
 #pragma unroll
-          for (int q = 0; q < NS; ++q) sum[q] += av * coh_load(a.rcc[q] + j);
+          for (int u = 0; u < 8; ++u) {
+            const int j = jb + 64 * u < a.n_cc ? jb + 64 * u : 0;
+            av[u] = arow[j];
+#pragma unroll
+            for (int q = 0; q < NS; ++q) rv[q][u] = coh_load(a.rcc[q] + j);
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (jb + 64 * u < a.n_cc) {
+#pragma unroll
+              for (int q = 0; q < NS; ++q) sum[q] += av[u] * rv[q][u];
+            }
         }
 #pragma unroll
         for (int q = 0; q < NS; ++q) {
